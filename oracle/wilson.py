@@ -1,0 +1,115 @@
+"""Fine Wilson-clover operator, Eq. (2) (oracle, FP64; test infrastructure).
+
+    M psi(x) = (4 + m0) psi(x) + A(x) psi(x)
+               - 1/2 sum_mu [ (1 - gamma_mu) (x) U_mu(x)         eta+ psi(x + mu)
+                            + (1 + gamma_mu) (x) U_mu(x - mu)^+   eta- psi(x - mu) ]
+
+eta = -1 on hops across the time boundary when time is antiperiodic.
+A(x) is the 12x12 clover term (Sheikholeslami-Wohlert form; the paper only
+names it as a first-order correction, so its normalisation is a reading):
+
+    A(x) = (i c_sw / 2) sum_{mu<nu} sigma_{mu nu} (x) Fhat_{mu nu}(x),
+    Fhat = (Q - Q^+)/8,  Q = sum of the four plaquette leaves at x in the
+    mu-nu plane, all with the same orientation.
+"""
+import numpy as np
+
+from . import lattice
+
+
+def _links_at(U, idx):
+    return U[idx]
+
+
+def clover_leaves(U, dims, mu, nu):
+    """Q_{mu nu}(x): sum of the four same-orientation plaquettes touching x."""
+    V = lattice.volume(dims)
+    f = lambda m, s: lattice.neighbour(dims, m, s)
+    x = np.arange(V)
+    Um, Un = U[mu], U[nu]
+    dag = lambda a: np.conj(np.swapaxes(a, -1, -2))
+    mm = lambda *ms: _chain(ms)
+    xpm, xpn = f(mu, 1), f(nu, 1)
+    xmm, xmn = f(mu, -1), f(nu, -1)
+    xmm_pn = lattice.neighbour(dims, nu, 1)[xmm]        # x - mu + nu
+    xmm_mn = lattice.neighbour(dims, nu, -1)[xmm]       # x - mu - nu
+    xpm_mn = lattice.neighbour(dims, nu, -1)[xpm]       # x + mu - nu
+    # leaf 1: x -> x+mu -> x+mu+nu -> x+nu -> x
+    q = mm(Um[x], Un[xpm], dag(Um[xpn]), dag(Un[x]))
+    # leaf 2: x -> x+nu -> x-mu+nu -> x-mu -> x
+    q = q + mm(Un[x], dag(Um[xmm_pn]), dag(Un[xmm]), Um[xmm])
+    # leaf 3: x -> x-mu -> x-mu-nu -> x-nu -> x
+    q = q + mm(dag(Um[xmm]), dag(Un[xmm_mn]), Um[xmm_mn], Un[xmn])
+    # leaf 4: x -> x-nu -> x+mu-nu -> x+mu -> x
+    q = q + mm(dag(Un[xmn]), Um[xmn], Un[xpm_mn], dag(Um[x]))
+    return q
+
+
+def _chain(ms):
+    out = ms[0]
+    for m in ms[1:]:
+        out = np.einsum('xab,xbc->xac', out, m)
+    return out
+
+
+def clover_field(U, dims, csw):
+    """A(x) as dense 12x12 matrices [V][12][12] (row/column index 3*spin + colour)."""
+    V = lattice.volume(dims)
+    A = np.zeros((V, 4, 3, 4, 3), dtype=np.complex128)
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            Q = clover_leaves(U, dims, mu, nu)
+            F = (Q - np.conj(np.swapaxes(Q, -1, -2))) / 8.0
+            A += (0.5j * csw) * np.einsum('st,xab->xsatb', lattice.sigma(mu, nu), F)
+    return A.reshape(V, 12, 12)
+
+
+def apply_wilson_clover(psi, U, clover, m0, dims, antiperiodic_t=True):
+    """M psi for psi of shape [V][4][3] (or [V][12]); clover may be None (c_sw = 0)."""
+    V = lattice.volume(dims)
+    shape = psi.shape
+    psi = psi.reshape(V, 4, 3)
+    Pm, Pp = lattice.projectors()
+    out = (4.0 + m0) * psi
+    if clover is not None:
+        out = out + np.einsum('xij,xj->xi', clover, psi.reshape(V, 12)).reshape(V, 4, 3)
+    for mu in range(4):
+        fwd = lattice.neighbour(dims, mu, +1)
+        bwd = lattice.neighbour(dims, mu, -1)
+        eta_f = lattice.boundary_sign(dims, mu, +1, antiperiodic_t)
+        eta_b = lattice.boundary_sign(dims, mu, -1, antiperiodic_t)
+        # forward hop: (1 - gamma_mu) (x) U_mu(x) psi(x + mu)
+        h = np.einsum('st,xta->xsa', Pm[mu], np.einsum('xab,xtb->xta', U[mu], psi[fwd]))
+        out = out - 0.5 * eta_f[:, None, None] * h
+        # backward hop: (1 + gamma_mu) (x) U_mu(x - mu)^dagger psi(x - mu)
+        Ub = U[mu][bwd]
+        h = np.einsum('st,xta->xsa', Pp[mu], np.einsum('xba,xtb->xta', np.conj(Ub), psi[bwd]))
+        out = out - 0.5 * eta_b[:, None, None] * h
+    return out.reshape(shape)
+
+
+def hop_matrices(U, dims, d, antiperiodic_t=True):
+    """The 12x12 matrix H_d(x) [V][12][12] that multiplies psi(x +/- mu) in
+    Eq. (2): d = 2*mu is the forward hop, d = 2*mu + 1 the backward hop."""
+    mu, back = d // 2, d % 2
+    Pm, Pp = lattice.projectors()
+    if back == 0:
+        eta = lattice.boundary_sign(dims, mu, +1, antiperiodic_t)
+        H = np.einsum('st,xab->xsatb', Pm[mu], U[mu])
+    else:
+        eta = lattice.boundary_sign(dims, mu, -1, antiperiodic_t)
+        Ub = U[mu][lattice.neighbour(dims, mu, -1)]
+        H = np.einsum('st,xba->xsatb', Pp[mu], np.conj(Ub))
+    V = lattice.volume(dims)
+    return (-0.5 * eta[:, None, None]) * H.reshape(V, 12, 12)
+
+
+def dense_matrix(apply, n):
+    """Materialise a linear map on C^n by applying it to the unit vectors."""
+    M = np.zeros((n, n), dtype=np.complex128)
+    e = np.zeros(n, dtype=np.complex128)
+    for j in range(n):
+        e[j] = 1.0
+        M[:, j] = apply(e)
+        e[j] = 0.0
+    return M

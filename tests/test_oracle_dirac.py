@@ -1,0 +1,112 @@
+"""Pins of the oracle's fine operator (Eq. 2) and its inputs, against closed
+forms and invariants that do not reuse the oracle's own formulas."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lattice, wilson
+from oracle_helpers import (abelian_flux, free_spectrum, match_multisets, pure_gauge,
+                            unit_gauge)
+
+
+def dense_M(U, clover, m0, dims, anti=True):
+    V = lattice.volume(dims)
+    return wilson.dense_matrix(
+        lambda v: wilson.apply_wilson_clover(v.reshape(V, 4, 3), U, clover, m0, dims, anti).reshape(-1),
+        V * 12)
+
+
+def test_gauge_links_are_special_unitary():
+    U = synth.gauge_field((4, 4, 4, 8), 0.4, 0).reshape(-1, 3, 3)
+    uu = U @ np.conj(np.swapaxes(U, 1, 2))
+    assert np.abs(uu - np.eye(3)).max() < 1e-14
+    assert np.abs(np.linalg.det(U) - 1).max() < 1e-14
+    # the recipe is seeded: same seed, same field; other seed, other field
+    assert np.array_equal(synth.gauge_field((2, 2, 2, 2), 0.4, 0), synth.gauge_field((2, 2, 2, 2), 0.4, 0))
+    assert not np.allclose(synth.gauge_field((2, 2, 2, 2), 0.4, 0), synth.gauge_field((2, 2, 2, 2), 0.4, 1))
+
+
+def test_gamma_clifford_algebra_and_chiral_basis():
+    g = lattice.gammas()
+    for mu in range(4):
+        assert np.allclose(g[mu], g[mu].conj().T)
+        for nu in range(4):
+            assert np.allclose(g[mu] @ g[nu] + g[nu] @ g[mu], 2 * (mu == nu) * np.eye(4))
+    assert np.allclose(lattice.gamma5(), np.diag([1, 1, -1, -1]))
+    Pm, Pp = lattice.projectors()
+    for mu in range(4):  # (1 -/+ gamma)/2 are complementary projectors
+        assert np.allclose((Pm[mu] / 2) @ (Pm[mu] / 2), Pm[mu] / 2)
+        assert np.allclose(Pm[mu] + Pp[mu], 2 * np.eye(4))
+
+
+@pytest.mark.parametrize("anti", [True, False])
+def test_free_field_spectrum_closed_form(anti):
+    """U = 1: eigenvalues m0 + sum(1 - cos p) +/- i sqrt(sum sin^2 p), 6-fold."""
+    dims = (4, 2, 2, 4)
+    m0 = -0.2
+    ev = np.linalg.eigvals(dense_M(unit_gauge(dims), None, m0, dims, anti))
+    assert match_multisets(ev, free_spectrum(dims, m0, anti)) < 1e-12
+
+
+def test_pure_gauge_spectrum_and_vanishing_clover():
+    """U_mu(x) = g(x) g(x+mu)^+ is a gauge copy of U = 1: same spectrum, zero clover."""
+    dims = (4, 2, 2, 4)
+    U = pure_gauge(dims, 7)
+    A = wilson.clover_field(U, dims, 1.0)
+    assert np.abs(A).max() < 1e-14
+    ev = np.linalg.eigvals(dense_M(U, A, -0.2, dims))
+    assert match_multisets(ev, free_spectrum(dims, -0.2)) < 1e-12
+
+
+def test_gamma5_hermiticity_random_links():
+    """gamma5 M gamma5 = M^+, checked through <phi, g5 M g5 psi> = <M phi, psi>."""
+    dims = (4, 4, 4, 4)
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 3)
+    A = wilson.clover_field(U, dims, 1.0)
+    g5 = np.kron(lattice.gamma5(), np.eye(3))
+    phi = synth.gaussian((V, 12), 1, 2)
+    psi = synth.gaussian((V, 12), 2, 2)
+    M = lambda v: wilson.apply_wilson_clover(v, U, A, -0.2, dims)
+    lhs = np.vdot(phi, M(psi @ g5.T) @ g5.T)
+    rhs = np.vdot(M(phi), psi)
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+    # M itself is not Hermitian, so this is not a trivial identity
+    assert abs(np.vdot(phi, M(psi)) - np.vdot(M(phi), psi)) > 1e-3 * abs(rhs)
+
+
+def test_clover_structure():
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.4, 0)
+    A = wilson.clover_field(U, dims, 1.0)
+    assert np.abs(A - np.conj(np.swapaxes(A, 1, 2))).max() < 1e-14          # Hermitian
+    assert np.abs(A[:, :6, 6:]).max() < 1e-15                                 # chirality blocks
+    assert np.abs(np.trace(A, axis1=1, axis2=2)).max() < 1e-13                # traceless
+    assert np.abs(A).max() > 1e-2
+    assert np.abs(wilson.clover_field(unit_gauge(dims), dims, 1.0)).max() == 0.0
+
+
+@pytest.mark.parametrize("n", [1, 3])
+def test_clover_constant_abelian_flux_closed_form(n):
+    """Every 0-1 plaquette = exp(i q theta): A = -(c_sw/2) sigma_01 (x) diag(sin q theta)."""
+    dims = (4, 4, 2, 2)
+    U, theta, q = abelian_flux(dims, n)
+    for csw in (1.0, 1.7):
+        A = wilson.clover_field(U, dims, csw)
+        expect = -(csw / 2) * np.kron(lattice.sigma(0, 1), np.diag(np.sin(q * theta)))
+        assert np.abs(A - expect[None]).max() < 1e-14
+
+
+def test_gauge_covariance_of_M():
+    """M[gU](g psi) = g M[U](psi) for a random local rotation g."""
+    from oracle_helpers import gauge_rotate
+    dims = (4, 4, 2, 4)
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 1)
+    g = synth.gauge_rotation(dims, 2)
+    Ug = gauge_rotate(U, g, dims)
+    psi = synth.gaussian((V, 4, 3), 3, 2)
+    rot = lambda p: np.einsum('xab,xsb->xsa', g, p)
+    a = wilson.apply_wilson_clover(rot(psi), Ug, wilson.clover_field(Ug, dims, 1.0), -0.3, dims)
+    b = rot(wilson.apply_wilson_clover(psi, U, wilson.clover_field(U, dims, 1.0), -0.3, dims))
+    assert np.abs(a - b).max() < 1e-13
