@@ -1,0 +1,140 @@
+/*
+ * qmg.h -- C ABI of the MI355X (gfx950) adaptive-multigrid Wilson-clover library.
+ *
+ * The method is that of Clark et al., "Accelerating Lattice QCD Multigrid on
+ * GPUs Using Fine-Grained Parallelization" (arXiv:1612.07873): the
+ * Wilson-clover matrix of Eq. (2), the adaptive geometric setup of Sec. 3.4,
+ * the coarse operator of Eq. (3) applied with the fine-grained split of
+ * Sec. 6.1-6.4, the transfer operators of Sec. 6.6 and the K-cycle GCR
+ * solver of Sec. 7.1.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers to field data are DEVICE pointers owned by the caller, unless a
+ *    comment says "host".  The library never frees caller memory; it owns
+ *    the memory behind its handles and releases it in *_destroy.
+ *  - Complex numbers are interleaved (re, im).  complex128 = 2 x double,
+ *    complex64 = 2 x float.
+ *  - Lattice dims[4] = {L0, L1, L2, L3}; site index i = x0 + L0*(x1 + L1*(x2 +
+ *    L2*x3)); dimension 3 is time (the index decomposition of Sec. 6.1).
+ *  - Coarse fields are [V][N] (N = 2*Nvec components per site, n = chi*Nvec + k);
+ *    multi-RHS coarse fields are [V][N][nrhs] (right-hand side fastest).
+ *  - Direction d = 2*mu (forward hop, multiplies u(x+mu)) or 2*mu+1 (backward).
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *    default stream) and is asynchronous unless stated otherwise.
+ *  - Every entry point checks its arguments before enqueuing anything and
+ *    returns a qmg_status; on failure qmg_last_error() describes it.  No C++
+ *    exception crosses this boundary.  A fault inside an enqueued kernel is
+ *    reported by the next synchronising call (qmg_sync).
+ *  - Handles are not thread-safe; use one handle from one host thread.
+ */
+#ifndef QMG_H
+#define QMG_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    QMG_OK = 0,
+    QMG_ERR_ARG = 1,        /* null pointer, bad enum, bad count           */
+    QMG_ERR_SHAPE = 2,      /* lattice / block / N inconsistent             */
+    QMG_ERR_PREC = 3,       /* precision not supported by this entry point  */
+    QMG_ERR_HIP = 4,        /* a HIP runtime call failed                    */
+    QMG_ERR_NOMEM = 5,      /* device allocation failed                     */
+    QMG_ERR_NOCONV = 6,     /* solver hit its iteration limit               */
+    QMG_ERR_NONFINITE = 7,  /* NaN/Inf met in a solver                      */
+    QMG_ERR_STATE = 8       /* handle used in a state that does not allow it */
+} qmg_status;
+
+/* Storage / arithmetic precision of a field or operator. */
+typedef enum {
+    QMG_C128 = 0,   /* complex128, FP64 arithmetic                          */
+    QMG_C64 = 1,    /* complex64, FP32 arithmetic                           */
+    QMG_H16 = 2,    /* FP16 pairs + FP32 scale, FP32 arithmetic             */
+    QMG_B16 = 3     /* BF16 pairs + FP32 scale, FP32 arithmetic             */
+} qmg_prec;
+
+typedef struct qmg_coarse_op_s* qmg_coarse_op;
+typedef struct qmg_fine_op_s* qmg_fine_op;
+
+/* Message describing the most recent failure on this host thread. */
+const char* qmg_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int qmg_version(void);
+
+/* Wait for all work on `stream`; returns QMG_ERR_HIP if an enqueued kernel failed. */
+qmg_status qmg_sync(void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Coarse operator, Eq. (3) (Sec. 3.4):
+ *     y(x) = X(x) u(x) + sum_{d=0..7} Y_d(x) u(x + hop_d),   periodic wrap,
+ * with hop_{2mu} = +mu and hop_{2mu+1} = -mu.  X and the eight Y_d are dense
+ * complex N x N blocks per coarse site, in the general form the Galerkin
+ * product P^+ M P produces (the paper's printed unit diagonal and daggered
+ * backward link are special cases of it).
+ * ------------------------------------------------------------------------- */
+
+/* Create an operator on a coarse lattice `dims` (every extent >= 2) with N
+ * components per site (N even, 2 <= N <= 128) from canonical DEVICE arrays
+ *     X [V][N][N] complex128,  Y [8][V][N][N] complex128  (row-major blocks).
+ * The data is copied (and converted to `storage`, which is QMG_C128 or
+ * QMG_C64) into the library's own link layout; the caller may free X and Y
+ * once the stream has passed this call.  On success *out owns device memory
+ * of about 9*V*N*N*(bytes per complex). */
+qmg_status qmg_coarse_op_create(const int dims[4], int N, const void* X, const void* Y,
+                                qmg_prec storage, void* stream, qmg_coarse_op* out);
+
+/* Write the operator back as canonical complex128 DEVICE arrays X, Y (same
+ * shapes as in create), converting from the storage precision. */
+qmg_status qmg_coarse_op_export(qmg_coarse_op op, void* X, void* Y, void* stream);
+
+/* Apply Eq. (3): out = Mhat in, for one right-hand side.  `in` and `out` are
+ * DEVICE arrays [V][N] in precision `prec`, which must equal the operator's
+ * storage precision (QMG_C128 or QMG_C64).  in and out must not overlap. */
+qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_prec prec,
+                             void* stream);
+
+/* Launch shape of the fine-grained stencil (Sec. 6.2-6.4): each work-group
+ * covers `rows` output rows of one coarse site (rows divides N), and the
+ * 9N-long row of [X | Y_0 .. Y_7] is split `split` ways across threads, with
+ * split dividing the number of 16-byte link chunks in that row.  rows*split
+ * must not exceed 1024.  Passing 0 for both restores the built-in choice. */
+qmg_status qmg_coarse_op_set_launch(qmg_coarse_op op, int rows, int split);
+qmg_status qmg_coarse_op_get_launch(qmg_coarse_op op, int* rows, int* split);
+
+void qmg_coarse_op_destroy(qmg_coarse_op op);
+
+/* ---------------------------------------------------------------------------
+ * Fine Wilson-clover operator, Eq. (2) (Sec. 3.2):
+ *   M psi(x) = (4 + m0 + A(x)) psi(x)
+ *       - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ * Chiral gamma basis (gamma_5 = diag(1,1,-1,-1)); periodic space and, when
+ * antiperiodic_t != 0, antiperiodic time.  A(x) is the clover term
+ * (i c_sw/2) sum_{mu<nu} sigma_{mu nu} (x) (Q_{mu nu} - Q_{mu nu}^+)/8 built
+ * from the clover-leaf sum Q; c_sw = 0 gives the plain Wilson operator.
+ * ------------------------------------------------------------------------- */
+
+/* Create the operator from the canonical DEVICE gauge field
+ *     gauge [4][V][3][3] complex128  (U_mu(x), row-major colour matrices),
+ * every extent >= 2.  The clover term is computed on the device here.  The
+ * gauge array may be freed once the stream has passed this call.
+ * storage: QMG_C128 or QMG_C64. */
+qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, double m0, double csw,
+                              int antiperiodic_t, qmg_prec storage, void* stream, qmg_fine_op* out);
+
+/* out = M in for one field; in/out DEVICE [V][4][3] in the operator's storage
+ * precision; in and out must not overlap. */
+qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, qmg_prec prec,
+                                    void* stream);
+
+/* Write the clover term as dense DEVICE complex128 [V][12][12] (row/column
+ * index 3*spin + colour). */
+qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* stream);
+
+void qmg_fine_op_destroy(qmg_fine_op op);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMG_H */

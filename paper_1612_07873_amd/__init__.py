@@ -1,0 +1,128 @@
+"""MI355X-native adaptive-multigrid Wilson-clover kernels (gfx950 HIP).
+
+Python side of the qmg C ABI: thin wrappers that pass torch device tensors'
+data pointers and the current HIP stream to libqmg.so.  Every step runs in
+the library's kernels; if the library is missing, these calls raise.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import PREC, QmgError, lib
+
+__all__ = ['CoarseOp', 'FineOp', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+
+_CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
+
+
+def stream_ptr(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, shape, what):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError('%s must be a device tensor' % what)
+    if t.dtype != dtype:
+        raise TypeError('%s must be %s, got %s' % (what, dtype, t.dtype))
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError('%s must have shape %s, got %s' % (what, tuple(shape), tuple(t.shape)))
+    if not t.is_contiguous():
+        raise ValueError('%s must be contiguous' % what)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _vol(dims):
+    v = 1
+    for d in dims:
+        v *= int(d)
+    return v
+
+
+class CoarseOp:
+    """Coarse operator of Eq. (3) held by the library (see qmg_coarse_op_create)."""
+
+    def __init__(self, dims, X, Y, storage='c128'):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = _vol(self.dims)
+        self.N = int(X.shape[-1])
+        self.storage = storage
+        self.dtype = _CDTYPE[storage]
+        h = ctypes.c_void_p()
+        _lib.call('qmg_coarse_op_create', _lib.c_dims(*self.dims), self.N,
+                  _dev_ptr(X, torch.complex128, (self.V, self.N, self.N), 'X'),
+                  _dev_ptr(Y, torch.complex128, (8, self.V, self.N, self.N), 'Y'),
+                  PREC[storage], stream_ptr(), ctypes.byref(h))
+        self._h = h
+
+    def apply(self, u, out=None):
+        if out is None:
+            out = torch.empty_like(u)
+        _lib.call('qmg_coarse_dslash', self._h,
+                  _dev_ptr(u, self.dtype, (self.V, self.N), 'in'),
+                  _dev_ptr(out, self.dtype, (self.V, self.N), 'out'),
+                  PREC[self.storage], stream_ptr())
+        return out
+
+    def export(self):
+        dev = torch.device('cuda')
+        X = torch.empty((self.V, self.N, self.N), dtype=torch.complex128, device=dev)
+        Y = torch.empty((8, self.V, self.N, self.N), dtype=torch.complex128, device=dev)
+        _lib.call('qmg_coarse_op_export', self._h, ctypes.c_void_p(X.data_ptr()),
+                  ctypes.c_void_p(Y.data_ptr()), stream_ptr())
+        return X, Y
+
+    def set_launch(self, rows=0, split=0):
+        _lib.call('qmg_coarse_op_set_launch', self._h, int(rows), int(split))
+
+    def launch(self):
+        r, s = ctypes.c_int(), ctypes.c_int()
+        _lib.call('qmg_coarse_op_get_launch', self._h, ctypes.byref(r), ctypes.byref(s))
+        return r.value, s.value
+
+    @property
+    def chunks_per_row(self):
+        return 9 * self.N // (1 if self.storage == 'c128' else 2)
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.qmg_coarse_op_destroy(h)
+            self._h = None
+
+
+class FineOp:
+    """Wilson-clover operator of Eq. (2) held by the library (qmg_fine_op_create)."""
+
+    def __init__(self, dims, gauge, m0, csw=1.0, antiperiodic_t=True, storage='c128'):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = _vol(self.dims)
+        self.storage = storage
+        self.dtype = _CDTYPE[storage]
+        self.m0, self.csw = float(m0), float(csw)
+        h = ctypes.c_void_p()
+        _lib.call('qmg_fine_op_create', _lib.c_dims(*self.dims),
+                  _dev_ptr(gauge, torch.complex128, (4, self.V, 3, 3), 'gauge'),
+                  self.m0, self.csw, int(bool(antiperiodic_t)), PREC[storage], stream_ptr(),
+                  ctypes.byref(h))
+        self._h = h
+
+    def apply(self, psi, out=None):
+        if out is None:
+            out = torch.empty_like(psi)
+        _lib.call('qmg_wilson_clover_dslash', self._h,
+                  _dev_ptr(psi, self.dtype, (self.V, 4, 3), 'in'),
+                  _dev_ptr(out, self.dtype, (self.V, 4, 3), 'out'), PREC[self.storage], stream_ptr())
+        return out
+
+    def clover(self):
+        A = torch.empty((self.V, 12, 12), dtype=torch.complex128, device='cuda')
+        _lib.call('qmg_fine_op_export_clover', self._h, ctypes.c_void_p(A.data_ptr()), stream_ptr())
+        return A
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.qmg_fine_op_destroy(h)
+            self._h = None

@@ -1,0 +1,69 @@
+"""ctypes declarations of the qmg C ABI (include/qmg.h).  Marshalling only."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, 'libqmg.so')
+
+c_int, c_double, c_void_p, c_char_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_char_p
+c_int_p = ctypes.POINTER(ctypes.c_int)
+c_dims = ctypes.c_int * 4
+
+QMG_C128, QMG_C64, QMG_H16, QMG_B16 = 0, 1, 2, 3
+PREC = {'c128': QMG_C128, 'c64': QMG_C64, 'h16': QMG_H16, 'b16': QMG_B16}
+STATUS = {0: 'QMG_OK', 1: 'QMG_ERR_ARG', 2: 'QMG_ERR_SHAPE', 3: 'QMG_ERR_PREC', 4: 'QMG_ERR_HIP',
+          5: 'QMG_ERR_NOMEM', 6: 'QMG_ERR_NOCONV', 7: 'QMG_ERR_NONFINITE', 8: 'QMG_ERR_STATE'}
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    'qmg_last_error': (c_char_p, []),
+    'qmg_version': (c_int, []),
+    'qmg_sync': (c_int, [c_void_p]),
+    'qmg_coarse_op_create': (c_int, [c_dims, c_int, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_coarse_op_export': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_coarse_op_set_launch': (c_int, [c_void_p, c_int, c_int]),
+    'qmg_coarse_op_get_launch': (c_int, [c_void_p, c_int_p, c_int_p]),
+    'qmg_coarse_op_destroy': (None, [c_void_p]),
+    'qmg_fine_op_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, c_void_p,
+                                   ctypes.POINTER(c_void_p)]),
+    'qmg_wilson_clover_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_fine_op_export_clover': (c_int, [c_void_p, c_void_p, c_void_p]),
+    'qmg_fine_op_destroy': (None, [c_void_p]),
+}
+
+_lib = None
+
+
+class QmgError(RuntimeError):
+    def __init__(self, status, where, msg):
+        super().__init__('%s: %s (%s)' % (where, msg, STATUS.get(status, status)))
+        self.status = status
+
+
+def lib():
+    """Load libqmg.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError('libqmg.so is not built (%s); run python -m paper_1612_07873_amd.build'
+                               % LIB_PATH)
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def check(status, where):
+    if status != 0:
+        msg = lib().qmg_last_error()
+        raise QmgError(status, where, msg.decode() if msg else '')
+
+
+def call(name, *args):
+    st = getattr(lib(), name)(*args)
+    check(st, name)
+    return st

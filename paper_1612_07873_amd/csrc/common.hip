@@ -1,0 +1,67 @@
+// Error state, argument checks and lattice helpers shared by the entry points.
+#include "qmg_internal.h"
+
+#include <vector>
+
+namespace qmg {
+
+static thread_local char g_err[1024] = "";
+
+qmg_status fail(qmg_status st, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return st;
+}
+
+void clear_error() { g_err[0] = 0; }
+
+qmg_status check_dims(const int dims[4], int min_extent, const char* what) {
+    if (!dims) return fail(QMG_ERR_ARG, "%s: dims is NULL", what);
+    for (int m = 0; m < 4; ++m)
+        if (dims[m] < min_extent || dims[m] > (1 << 12))
+            return fail(QMG_ERR_SHAPE, "%s: extent %d of dimension %d outside [%d, 4096]", what,
+                        dims[m], m, min_extent);
+    if (volume(dims) > (int64_t)1 << 30) return fail(QMG_ERR_SHAPE, "%s: volume too large", what);
+    return QMG_OK;
+}
+
+qmg_status make_neighbour_table(const int dims[4], int** dev_out, hipStream_t s) {
+    const int64_t V = volume(dims);
+    std::vector<int> h(V * 8);
+    for (int64_t i = 0; i < V; ++i) {
+        int x[4];
+        int64_t t = i;
+        for (int m = 0; m < 4; ++m) { x[m] = (int)(t % dims[m]); t /= dims[m]; }
+        for (int d = 0; d < 8; ++d) {
+            int mu = d / 2, step = (d & 1) ? -1 : 1;
+            int y[4] = {x[0], x[1], x[2], x[3]};
+            y[mu] = (y[mu] + step + dims[mu]) % dims[mu];
+            h[i * 8 + d] = y[0] + dims[0] * (y[1] + dims[1] * (y[2] + dims[2] * y[3]));
+        }
+    }
+    int* d = nullptr;
+    QMG_HIP(hipMalloc(&d, sizeof(int) * V * 8));
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(int) * V * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(QMG_ERR_HIP, "neighbour table upload: %s", hipGetErrorString(e));
+    }
+    *dev_out = d;
+    return QMG_OK;
+}
+
+const char* last_error() { return g_err; }
+
+}  // namespace qmg
+
+extern "C" const char* qmg_last_error(void) { return qmg::last_error(); }
+
+extern "C" int qmg_version(void) { return 100; }
+
+extern "C" qmg_status qmg_sync(void* stream) {
+    QMG_HIP(hipStreamSynchronize(qmg::as_stream(stream)));
+    return QMG_OK;
+}
