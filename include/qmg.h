@@ -56,6 +56,7 @@ typedef enum {
 
 typedef struct qmg_coarse_op_s* qmg_coarse_op;
 typedef struct qmg_fine_op_s* qmg_fine_op;
+typedef struct qmg_transfer_s* qmg_transfer;
 
 /* Message describing the most recent failure on this host thread. */
 const char* qmg_last_error(void);
@@ -133,6 +134,60 @@ qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, q
 qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* stream);
 
 void qmg_fine_op_destroy(qmg_fine_op op);
+
+/* ---------------------------------------------------------------------------
+ * Transfer operators (Sec. 3.4 step 3, Sec. 6.6).  The near-null vectors are
+ * cut into hypercubic aggregates of extent block[4]; within each aggregate
+ * the two chirality halves (fine level: spins {0,1} and {2,3}; coarse
+ * parent: components n < dof/2 and n >= dof/2) of every vector are
+ * orthonormalised separately by modified Gram-Schmidt in vector order (each
+ * projection done twice; R with real positive diagonal).  This gives the
+ * prolongator P, N = 2*nvec coarse components per aggregate, and the
+ * restrictor R = P^+:
+ *   (P u)(x)_f = sum_k V(x)_{f,k} u(xc(x))_{chi(f)*nvec + k}
+ *   (R psi)(xc)_{chi*nvec + k} = sum_{x in xc} sum_{f: chi(f) = chi} conj(V(x)_{f,k}) psi(x)_f
+ * ------------------------------------------------------------------------- */
+
+/* Build P from DEVICE near-null vectors nullvecs [nvec][V][fine_dof]
+ * complex128 (fine_dof = 12 on the fine lattice, the parent's N on a coarse
+ * one).  block must divide fine_dims with every coarse extent >= 2.  The
+ * orthonormalisation runs in FP64; storage (QMG_C128 or QMG_C64) is the
+ * precision prolong/restrict use for complex64 fields.  Blocks this call
+ * until the basis is built (it checks the rank on the host): returns
+ * QMG_ERR_ARG if a vector is linearly dependent (relative residual norm
+ * < 1e-10) on some aggregate. */
+qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, const int block[4], int nvec,
+                               const void* nullvecs, qmg_prec storage, void* stream,
+                               qmg_transfer* out);
+
+/* Coarse lattice extents and N = 2*nvec of the transfer (host outputs). */
+qmg_status qmg_transfer_coarse_dims(qmg_transfer t, int cdims[4], int* N);
+
+/* Write the FP64 basis V as a DEVICE complex128 array [V][fine_dof][nvec]. */
+qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* stream);
+
+/* fine_out [V][fine_dof] = P coarse_in [Vc][N]; DEVICE fields, precision p
+ * (QMG_C128, or QMG_C64 when the transfer was created with QMG_C64). */
+qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, qmg_prec p,
+                       void* stream);
+
+/* coarse_out [Vc][N] = R fine_in [V][fine_dof]; same precision rules. */
+qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, qmg_prec p,
+                        void* stream);
+
+void qmg_transfer_destroy(qmg_transfer t);
+
+/* ---------------------------------------------------------------------------
+ * Galerkin coarse operator (Sec. 3.4 step 4): Mhat = P^+ M P, assembled in
+ * FP64 by hop direction into the X / Y_d blocks of Eq. (3).  The parent is
+ * either the fine Wilson-clover operator (`fine`) or a coarse operator
+ * (`parent`) -- exactly one must be non-NULL -- defined on the transfer's
+ * fine lattice.  Requires parent dof x N <= 4096.  Blocks until the
+ * operator is built; *out is a new coarse operator in `storage`
+ * (QMG_C128 or QMG_C64).
+ * ------------------------------------------------------------------------- */
+qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_coarse_op parent,
+                               qmg_prec storage, void* stream, qmg_coarse_op* out);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['CoarseOp', 'FineOp', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 
@@ -43,12 +43,16 @@ def _vol(dims):
 class CoarseOp:
     """Coarse operator of Eq. (3) held by the library (see qmg_coarse_op_create)."""
 
-    def __init__(self, dims, X, Y, storage='c128'):
+    def __init__(self, dims, X, Y, storage='c128', _handle=None, _N=None):
         self.dims = tuple(int(d) for d in dims)
         self.V = _vol(self.dims)
-        self.N = int(X.shape[-1])
         self.storage = storage
         self.dtype = _CDTYPE[storage]
+        if _handle is not None:
+            self.N = int(_N)
+            self._h = _handle
+            return
+        self.N = int(X.shape[-1])
         h = ctypes.c_void_p()
         _lib.call('qmg_coarse_op_create', _lib.c_dims(*self.dims), self.N,
                   _dev_ptr(X, torch.complex128, (self.V, self.N, self.N), 'X'),
@@ -126,3 +130,64 @@ class FineOp:
         if h is not None and h.value and _lib._lib is not None:
             _lib._lib.qmg_fine_op_destroy(h)
             self._h = None
+
+
+class Transfer:
+    """Prolongator / restrictor built from near-null vectors (qmg_transfer_create)."""
+
+    def __init__(self, fine_dims, fine_dof, block, nullvecs, storage='c128'):
+        self.fine_dims = tuple(int(d) for d in fine_dims)
+        self.V = _vol(self.fine_dims)
+        self.dof = int(fine_dof)
+        self.block = tuple(int(b) for b in block)
+        self.nvec = int(nullvecs.shape[0])
+        self.storage = storage
+        h = ctypes.c_void_p()
+        _lib.call('qmg_transfer_create', _lib.c_dims(*self.fine_dims), self.dof, _lib.c_dims(*self.block),
+                  self.nvec, _dev_ptr(nullvecs, torch.complex128, (self.nvec, self.V, self.dof), 'nullvecs'),
+                  PREC[storage], stream_ptr(), ctypes.byref(h))
+        self._h = h
+        cd = _lib.c_dims()
+        n = ctypes.c_int()
+        _lib.call('qmg_transfer_coarse_dims', h, cd, ctypes.byref(n))
+        self.coarse_dims = tuple(cd)
+        self.Vc = _vol(self.coarse_dims)
+        self.N = n.value
+
+    def basis(self):
+        B = torch.empty((self.V, self.dof, self.nvec), dtype=torch.complex128, device='cuda')
+        _lib.call('qmg_transfer_export', self._h, ctypes.c_void_p(B.data_ptr()), stream_ptr())
+        return B
+
+    def _prec(self, t):
+        return 'c128' if t.dtype == torch.complex128 else 'c64'
+
+    def prolong(self, uc, out=None):
+        p = self._prec(uc)
+        if out is None:
+            out = torch.empty((self.V, self.dof), dtype=uc.dtype, device=uc.device)
+        _lib.call('qmg_prolong', self._h, _dev_ptr(uc, _CDTYPE[p], (self.Vc, self.N), 'coarse_in'),
+                  _dev_ptr(out, _CDTYPE[p], (self.V, self.dof), 'fine_out'), PREC[p], stream_ptr())
+        return out
+
+    def restrict(self, f, out=None):
+        p = self._prec(f)
+        if out is None:
+            out = torch.empty((self.Vc, self.N), dtype=f.dtype, device=f.device)
+        _lib.call('qmg_restrict', self._h, _dev_ptr(f, _CDTYPE[p], (self.V, self.dof), 'fine_in'),
+                  _dev_ptr(out, _CDTYPE[p], (self.Vc, self.N), 'coarse_out'), PREC[p], stream_ptr())
+        return out
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.qmg_transfer_destroy(h)
+            self._h = None
+
+
+def build_coarse_op(transfer, fine=None, parent=None, storage='c128'):
+    """Galerkin product P^+ M P as a new CoarseOp (qmg_build_coarse_op)."""
+    h = ctypes.c_void_p()
+    _lib.call('qmg_build_coarse_op', transfer._h, fine._h if fine is not None else None,
+              parent._h if parent is not None else None, PREC[storage], stream_ptr(), ctypes.byref(h))
+    return CoarseOp(transfer.coarse_dims, None, None, storage, _handle=h, _N=transfer.N)

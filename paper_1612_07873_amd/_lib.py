@@ -30,6 +30,14 @@ SIGNATURES = {
     'qmg_wilson_clover_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_fine_op_export_clover': (c_int, [c_void_p, c_void_p, c_void_p]),
     'qmg_fine_op_destroy': (None, [c_void_p]),
+    'qmg_transfer_create': (c_int, [c_dims, c_int, c_dims, c_int, c_void_p, c_int, c_void_p,
+                                    ctypes.POINTER(c_void_p)]),
+    'qmg_transfer_coarse_dims': (c_int, [c_void_p, c_int_p, c_int_p]),
+    'qmg_transfer_export': (c_int, [c_void_p, c_void_p, c_void_p]),
+    'qmg_prolong': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_restrict': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_transfer_destroy': (None, [c_void_p]),
+    'qmg_build_coarse_op': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
 }
 
 _lib = None

@@ -22,21 +22,10 @@
 // not depend on the launch shape.  The 9 input vectors of the site are staged
 // once in LDS; all lanes of a wave read the same (or two) LDS addresses per
 // step, which the LDS serves as a broadcast.
-#include "qmg_internal.h"
+#include "handles.h"
 
 #include <algorithm>
 #include <vector>
-
-struct qmg_coarse_op_s {
-    int dims[4];
-    int64_t V;
-    int N;
-    qmg_prec storage;
-    int J;        // 16-byte chunks per 9N-long row
-    void* links;  // [V][J][N] chunks
-    int* nbr;     // [V][8]
-    int rows, split;
-};
 
 namespace qmg {
 

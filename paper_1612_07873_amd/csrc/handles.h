@@ -1,0 +1,43 @@
+// Internal layout of the library's handles (not part of the public ABI).
+#pragma once
+
+#include "qmg_internal.h"
+
+struct qmg_coarse_op_s {
+    int dims[4];
+    int64_t V;
+    int N;
+    qmg_prec storage;
+    int J;        // 16-byte chunks per 9N-long row
+    void* links;  // [V][J][N] chunks (see coarse_dslash.hip)
+    int* nbr;     // [V][8]
+    int rows, split;
+};
+
+struct qmg_fine_op_s {
+    int dims[4];
+    int64_t V;
+    double m0, csw;
+    int antiperiodic_t;
+    qmg_prec storage;
+    void* U;     // [4][9][V] complex, time sign folded into U_3 on the last slice
+    void* clov;  // [2][36][V] reals: 6 diagonal, then 15 upper off-diagonal complex
+    int* nbr;    // [V][8]
+};
+
+struct qmg_transfer_s {
+    int fdims[4], block[4], cdims[4];
+    int64_t V, Vc;
+    int dof, nvec, bsites;
+    qmg_prec storage;
+    double2* basis64;  // [V][dof][nvec] FP64
+    void* basis;       // [V][dof][nvec] storage precision (== basis64 for C128)
+    int* members;      // [Vc][bsites]
+    int* owner;        // [V]
+};
+
+namespace qmg {
+// Chiral-basis Dirac matrices: gamma_mu = [[0, g_mu], [g_mu^+, 0]] with
+// g_k = -i sigma_k (k = 1..3), g_4 = 1.  gamma(mu, r, c) as (re, im).
+void gamma_matrix(int mu, double out[4][4][2]);
+}

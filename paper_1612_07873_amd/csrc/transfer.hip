@@ -1,0 +1,354 @@
+// Transfer operators (Sec. 3.4 step 3 and Sec. 6.6).
+//
+// Setup: the near-null vectors are cut into hypercubic aggregates; within
+// each aggregate the two chirality halves of every vector (fine level: spins
+// {0,1} vs {2,3}; coarse parent: components n < N/2 vs n >= N/2) are
+// orthonormalised separately by modified Gram-Schmidt in vector order, every
+// projection done twice, normalised so that R has a real positive diagonal.
+// One work-group per (aggregate, chirality), FP64, working set in global
+// memory (it is read from L2).
+//
+// Apply:
+//   prolong  (P u)(x)_f = sum_k V(x)_{f,k} u(xc(x))_{chi(f)*Nvec + k}
+//            a gather, one thread per fine degree of freedom;
+//   restrict (R psi)(xc)_{chi*Nvec + k} = sum_{x in xc, chi(f) = chi} conj(V(x)_{f,k}) psi(x)_f
+//            one work-group per aggregate, each thread owning one coarse
+//            component and a slice of the aggregate, partial sums combined in
+//            LDS in a fixed order: no atomics, bitwise repeatable.
+// The basis is kept as [V][dof][Nvec] (row f of site x holds the Nvec
+// coefficients of its chirality) in the storage precision, plus an FP64 copy
+// for the Galerkin build.
+#include "handles.h"
+
+#include <vector>
+
+namespace qmg {
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    // sum over the work-group; result returned to every thread
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) red[w] = v;
+    __syncthreads();
+    double t = 0;
+    const int nw = (blockDim.x + 63) >> 6;
+    for (int i = 0; i < nw; ++i) t += red[i];
+    return t;
+}
+
+// gather vecs [nvec][V][dof] -> W [Vc][2][nvec][Lb]  (Lb = bsites*dof/2)
+__global__ void k_gather_blocks(double2* __restrict__ W, const double2* __restrict__ vecs,
+                                const int* __restrict__ members, int64_t V, int64_t Vc, int dof,
+                                int nvec, int bsites) {
+    const int half = dof / 2;
+    const int64_t Lb = (int64_t)bsites * half;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = Vc * 2 * nvec * Lb;
+    if (g >= total) return;
+    const int64_t p = g % Lb;
+    int64_t t = g / Lb;
+    const int k = (int)(t % nvec);
+    t /= nvec;
+    const int chi = (int)(t % 2);
+    const int64_t xc = t / 2;
+    const int64_t x = members[xc * bsites + p / half];
+    const int f = chi * half + (int)(p % half);
+    W[g] = vecs[((int64_t)k * V + x) * dof + f];
+}
+
+// MGS on one (aggregate, chirality) per work-group.
+__global__ __launch_bounds__(256) void k_block_mgs(double2* __restrict__ W, int nvec, int64_t Lb,
+                                                    double rank_tol, int* __restrict__ rank_fail) {
+    __shared__ double red[8];
+    double2* Wb = W + (int64_t)blockIdx.x * nvec * Lb;
+    for (int k = 0; k < nvec; ++k) {
+        double2* wk = Wb + (int64_t)k * Lb;
+        double s = 0;
+        for (int64_t i = threadIdx.x; i < Lb; i += blockDim.x) s += wk[i].x * wk[i].x + wk[i].y * wk[i].y;
+        const double before = sqrt(block_sum(s, red));
+        for (int pass = 0; pass < 2; ++pass)
+            for (int j = 0; j < k; ++j) {
+                const double2* wj = Wb + (int64_t)j * Lb;
+                double cr = 0, cim = 0;
+                for (int64_t i = threadIdx.x; i < Lb; i += blockDim.x) {
+                    cr += wj[i].x * wk[i].x + wj[i].y * wk[i].y;    // conj(wj) * wk
+                    cim += wj[i].x * wk[i].y - wj[i].y * wk[i].x;
+                }
+                cr = block_sum(cr, red);
+                cim = block_sum(cim, red);
+                for (int64_t i = threadIdx.x; i < Lb; i += blockDim.x) {
+                    const double2 a = wj[i];
+                    wk[i].x -= cr * a.x - cim * a.y;
+                    wk[i].y -= cr * a.y + cim * a.x;
+                }
+                __syncthreads();
+            }
+        s = 0;
+        for (int64_t i = threadIdx.x; i < Lb; i += blockDim.x) s += wk[i].x * wk[i].x + wk[i].y * wk[i].y;
+        const double nrm = sqrt(block_sum(s, red));
+        if (!(nrm >= rank_tol * before) || nrm == 0.0) {
+            if (threadIdx.x == 0) rank_fail[0] = 1;
+        }
+        const double inv = nrm > 0 ? 1.0 / nrm : 0.0;
+        for (int64_t i = threadIdx.x; i < Lb; i += blockDim.x) {
+            wk[i].x *= inv;
+            wk[i].y *= inv;
+        }
+        __syncthreads();
+    }
+}
+
+// W [Vc][2][nvec][Lb] -> basis [V][dof][nvec]
+__global__ void k_scatter_basis(double2* __restrict__ B, const double2* __restrict__ W,
+                                const int* __restrict__ members, int64_t Vc, int dof, int nvec,
+                                int bsites) {
+    const int half = dof / 2;
+    const int64_t Lb = (int64_t)bsites * half;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= Vc * 2 * nvec * Lb) return;
+    const int64_t p = g % Lb;
+    int64_t t = g / Lb;
+    const int k = (int)(t % nvec);
+    t /= nvec;
+    const int chi = (int)(t % 2);
+    const int64_t xc = t / 2;
+    const int64_t x = members[xc * bsites + p / half];
+    const int f = chi * half + (int)(p % half);
+    B[(x * dof + f) * nvec + k] = W[g];
+}
+
+__global__ void k_to_c64(float2* __restrict__ o, const double2* __restrict__ i, int64_t n) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) o[g] = make_float2((float)i[g].x, (float)i[g].y);
+}
+
+template <typename R>
+__global__ void k_prolong(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
+                          const cpx<R>* __restrict__ uc, const int* __restrict__ owner, int64_t V,
+                          int dof, int nvec) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= V * dof) return;
+    const int64_t x = g / dof;
+    const int f = (int)(g - x * dof);
+    const int chi = f / (dof / 2);
+    const cpx<R>* b = B + g * nvec;
+    const cpx<R>* u = uc + (int64_t)owner[x] * 2 * nvec + chi * nvec;
+    R ar = 0, ai = 0;
+    for (int k = 0; k < nvec; ++k) cmac(ar, ai, b[k].re, b[k].im, u[k].re, u[k].im);
+    out[g] = cpx<R>{ar, ai};
+}
+
+// One work-group per aggregate; thread (chi, k, part) sums a strided slice.
+template <typename R>
+__global__ __launch_bounds__(256) void k_restrict(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
+                                                   const cpx<R>* __restrict__ in,
+                                                   const int* __restrict__ members, int dof, int nvec,
+                                                   int bsites, int parts) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    cpx<R>* red = reinterpret_cast<cpx<R>*>(smem);  // [parts][2*nvec]
+    const int64_t xc = blockIdx.x;
+    const int half = dof / 2;
+    const int nout = 2 * nvec;
+    const int t = threadIdx.x;
+    if (t < nout * parts) {
+        const int n = t % nout, part = t / nout;
+        const int chi = n / nvec, k = n - chi * nvec;
+        const int Lb = bsites * half;
+        R ar = 0, ai = 0;
+        for (int p = part; p < Lb; p += parts) {
+            const int64_t x = members[xc * bsites + p / half];
+            const int f = chi * half + p % half;
+            const cpx<R> b = B[(x * dof + f) * nvec + k];
+            const cpx<R> v = in[x * dof + f];
+            cmac_conj(ar, ai, b.re, b.im, v.re, v.im);
+        }
+        red[part * nout + n] = cpx<R>{ar, ai};
+    }
+    __syncthreads();
+    if (t < nout) {
+        R ar = 0, ai = 0;
+        for (int q = 0; q < parts; ++q) {
+            ar += red[q * nout + t].re;
+            ai += red[q * nout + t].im;
+        }
+        out[xc * nout + t] = cpx<R>{ar, ai};
+    }
+}
+
+}  // namespace qmg
+
+using namespace qmg;
+
+extern "C" void qmg_transfer_destroy(qmg_transfer t) {
+    if (!t) return;
+    if (t->basis && t->basis != (void*)t->basis64) (void)hipFree(t->basis);
+    if (t->basis64) (void)hipFree(t->basis64);
+    if (t->members) (void)hipFree(t->members);
+    if (t->owner) (void)hipFree(t->owner);
+    delete t;
+}
+
+extern "C" qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, const int block[4],
+                                          int nvec, const void* nullvecs, qmg_prec storage,
+                                          void* stream, qmg_transfer* out) {
+    if (!out) return fail(QMG_ERR_ARG, "transfer_create: out is NULL");
+    *out = nullptr;
+    QMG_TRY(check_dims(fine_dims, 2, "transfer_create"));
+    if (!block || !nullvecs) return fail(QMG_ERR_ARG, "transfer_create: NULL argument");
+    if (fine_dof < 2 || (fine_dof & 1) || fine_dof > 128)
+        return fail(QMG_ERR_SHAPE, "transfer_create: fine_dof %d must be even in [2,128]", fine_dof);
+    if (nvec < 1 || 2 * nvec > 128) return fail(QMG_ERR_SHAPE, "transfer_create: nvec %d outside [1,64]", nvec);
+    if (storage != QMG_C128 && storage != QMG_C64)
+        return fail(QMG_ERR_PREC, "transfer_create: storage %d not supported", (int)storage);
+    int cd[4];
+    int64_t bs = 1;
+    for (int m = 0; m < 4; ++m) {
+        if (block[m] < 1 || fine_dims[m] % block[m])
+            return fail(QMG_ERR_SHAPE, "transfer_create: block %d does not divide extent %d (dim %d)",
+                        block[m], fine_dims[m], m);
+        cd[m] = fine_dims[m] / block[m];
+        if (cd[m] < 2) return fail(QMG_ERR_SHAPE, "transfer_create: coarse extent %d < 2 in dim %d", cd[m], m);
+        bs *= block[m];
+    }
+    if ((int64_t)nvec > bs * (fine_dof / 2))
+        return fail(QMG_ERR_SHAPE, "transfer_create: nvec %d exceeds aggregate dimension %lld", nvec,
+                    (long long)(bs * (fine_dof / 2)));
+    hipStream_t s = as_stream(stream);
+    auto* t = new qmg_transfer_s();
+    for (int m = 0; m < 4; ++m) { t->fdims[m] = fine_dims[m]; t->block[m] = block[m]; t->cdims[m] = cd[m]; }
+    t->V = volume(fine_dims);
+    t->Vc = volume(cd);
+    t->dof = fine_dof;
+    t->nvec = nvec;
+    t->bsites = (int)bs;
+    t->storage = storage;
+
+    // aggregate tables on the host
+    std::vector<int> members(t->V), owner(t->V), fill(t->Vc, 0);
+    for (int64_t i = 0; i < t->V; ++i) {
+        int64_t r = i;
+        int x[4];
+        for (int m = 0; m < 4; ++m) { x[m] = (int)(r % fine_dims[m]); r /= fine_dims[m]; }
+        const int64_t xc = x[0] / block[0] + (int64_t)cd[0] * (x[1] / block[1] + (int64_t)cd[1] * (x[2] / block[2] + (int64_t)cd[2] * (x[3] / block[3])));
+        owner[i] = (int)xc;
+        members[xc * bs + fill[xc]++] = (int)i;
+    }
+    const size_t nb = (size_t)t->V * fine_dof * nvec;
+    const int64_t Lb = bs * (fine_dof / 2);
+    const size_t wbytes = sizeof(double2) * (size_t)t->Vc * 2 * nvec * Lb;
+    double2* W = nullptr;
+    int* flag = nullptr;
+    hipError_t e = hipMalloc(&t->members, sizeof(int) * t->V);
+    if (e == hipSuccess) e = hipMalloc(&t->owner, sizeof(int) * t->V);
+    if (e == hipSuccess) e = hipMalloc(&t->basis64, sizeof(double2) * nb);
+    if (e == hipSuccess) e = hipMalloc(&W, wbytes);
+    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int));
+    if (e == hipSuccess) e = hipMemcpyAsync(t->members, members.data(), sizeof(int) * t->V, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(t->owner, owner.data(), sizeof(int) * t->V, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int), s);
+    if (e != hipSuccess) {
+        if (W) (void)hipFree(W);
+        if (flag) (void)hipFree(flag);
+        qmg_transfer_destroy(t);
+        return fail(e == hipErrorOutOfMemory ? QMG_ERR_NOMEM : QMG_ERR_HIP, "transfer_create: %s", hipGetErrorString(e));
+    }
+    const int64_t total = t->Vc * 2 * nvec * Lb;
+    const unsigned g1 = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_gather_blocks, dim3(g1), dim3(256), 0, s, W, (const double2*)nullvecs, t->members,
+                       t->V, t->Vc, fine_dof, nvec, t->bsites);
+    hipLaunchKernelGGL(k_block_mgs, dim3((unsigned)(t->Vc * 2)), dim3(256), 0, s, W, nvec, Lb, 1e-10, flag);
+    hipLaunchKernelGGL(k_scatter_basis, dim3(g1), dim3(256), 0, s, t->basis64, W, t->members, t->Vc,
+                       fine_dof, nvec, t->bsites);
+    e = hipGetLastError();
+    int hflag = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(W);
+    (void)hipFree(flag);
+    if (e != hipSuccess) {
+        qmg_transfer_destroy(t);
+        return fail(QMG_ERR_HIP, "transfer_create: %s", hipGetErrorString(e));
+    }
+    if (hflag) {
+        qmg_transfer_destroy(t);
+        return fail(QMG_ERR_ARG, "transfer_create: near-null vectors are linearly dependent within an aggregate");
+    }
+    if (storage == QMG_C128) {
+        t->basis = t->basis64;
+    } else {
+        e = hipMalloc(&t->basis, sizeof(float2) * nb);
+        if (e != hipSuccess) {
+            qmg_transfer_destroy(t);
+            return fail(QMG_ERR_NOMEM, "transfer_create: %s", hipGetErrorString(e));
+        }
+        hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (float2*)t->basis,
+                           t->basis64, (int64_t)nb);
+        QMG_LAUNCH_CHECK();
+    }
+    *out = t;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_transfer_coarse_dims(qmg_transfer t, int cdims[4], int* N) {
+    if (!t || !cdims || !N) return fail(QMG_ERR_ARG, "transfer_coarse_dims: NULL argument");
+    for (int m = 0; m < 4; ++m) cdims[m] = t->cdims[m];
+    *N = 2 * t->nvec;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* stream) {
+    if (!t || !basis) return fail(QMG_ERR_ARG, "transfer_export: NULL argument");
+    QMG_HIP(hipMemcpyAsync(basis, t->basis64, sizeof(double2) * (size_t)t->V * t->dof * t->nvec,
+                           hipMemcpyDeviceToDevice, as_stream(stream)));
+    return QMG_OK;
+}
+
+namespace qmg {
+qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
+    const int64_t n = t->V * t->dof;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (p == QMG_C128)
+        hipLaunchKernelGGL(k_prolong<double>, dim3(nb), dim3(256), 0, s, (cpx<double>*)out,
+                           (const cpx<double>*)t->basis64, (const cpx<double>*)in, t->owner, t->V, t->dof, t->nvec);
+    else
+        hipLaunchKernelGGL(k_prolong<float>, dim3(nb), dim3(256), 0, s, (cpx<float>*)out,
+                           (const cpx<float>*)t->basis, (const cpx<float>*)in, t->owner, t->V, t->dof, t->nvec);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
+    const int nout = 2 * t->nvec;
+    const int parts = 256 / nout;
+    if (p == QMG_C128)
+        hipLaunchKernelGGL(k_restrict<double>, dim3((unsigned)t->Vc), dim3(256), sizeof(cpx<double>) * nout * parts, s,
+                           (cpx<double>*)out, (const cpx<double>*)t->basis64, (const cpx<double>*)in, t->members,
+                           t->dof, t->nvec, t->bsites, parts);
+    else
+        hipLaunchKernelGGL(k_restrict<float>, dim3((unsigned)t->Vc), dim3(256), sizeof(cpx<float>) * nout * parts, s,
+                           (cpx<float>*)out, (const cpx<float>*)t->basis, (const cpx<float>*)in, t->members,
+                           t->dof, t->nvec, t->bsites, parts);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+}  // namespace qmg
+
+static qmg_status check_transfer_prec(qmg_transfer t, qmg_prec p, const char* what) {
+    if (p != QMG_C128 && p != QMG_C64) return fail(QMG_ERR_PREC, "%s: precision %d not supported", what, (int)p);
+    if (p == QMG_C64 && t->storage != QMG_C64)
+        return fail(QMG_ERR_PREC, "%s: complex64 fields need a transfer created with complex64 storage", what);
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, qmg_prec p, void* stream) {
+    if (!t || !coarse_in || !fine_out) return fail(QMG_ERR_ARG, "prolong: NULL argument");
+    QMG_TRY(check_transfer_prec(t, p, "prolong"));
+    return transfer_prolong(t, coarse_in, fine_out, p, as_stream(stream));
+}
+
+extern "C" qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, qmg_prec p, void* stream) {
+    if (!t || !fine_in || !coarse_out) return fail(QMG_ERR_ARG, "restrict: NULL argument");
+    QMG_TRY(check_transfer_prec(t, p, "restrict"));
+    return transfer_restrict(t, fine_in, coarse_out, p, as_stream(stream));
+}

@@ -18,20 +18,9 @@
 // forward hop out of that slice and the backward hop into it); clover SoA
 // [2][36][V] reals (6 diagonal reals, then the 15 upper off-diagonal complex
 // entries row by row); spinors [V][4][3] complex (the canonical layout).
-#include "qmg_internal.h"
+#include "handles.h"
 
 #include <vector>
-
-struct qmg_fine_op_s {
-    int dims[4];
-    int64_t V;
-    double m0, csw;
-    int antiperiodic_t;
-    qmg_prec storage;
-    void* U;     // [4][9][V] complex<R>
-    void* clov;  // [2][36][V] R
-    int* nbr;    // [V][8]
-};
 
 namespace qmg {
 
@@ -314,23 +303,8 @@ __global__ void k_pack_gauge(cpx<R>* __restrict__ U, const double2* __restrict__
 
 // sigma_{mu nu} chirality blocks, from the chiral-basis gamma matrices.
 static SigmaBlocks sigma_blocks(double csw) {
-    typedef double c2[2];
-    // gamma[mu][row][col] as (re, im)
-    double g[4][4][4][2] = {};
-    // off-diagonal blocks g_mu (upper right) and g_mu^+ (lower left)
-    const double G[4][2][2][2] = {
-        {{{0, 0}, {0, -1}}, {{0, -1}, {0, 0}}},   // -i sigma_1
-        {{{0, 0}, {-1, 0}}, {{1, 0}, {0, 0}}},    // -i sigma_2
-        {{{0, -1}, {0, 0}}, {{0, 0}, {0, 1}}},    // -i sigma_3
-        {{{1, 0}, {0, 0}}, {{0, 0}, {1, 0}}}};    // 1
-    for (int mu = 0; mu < 4; ++mu)
-        for (int r = 0; r < 2; ++r)
-            for (int c = 0; c < 2; ++c) {
-                g[mu][r][2 + c][0] = G[mu][r][c][0];
-                g[mu][r][2 + c][1] = G[mu][r][c][1];
-                g[mu][2 + c][r][0] = G[mu][r][c][0];     // (g^+)_{c r} = conj(g_{r c})
-                g[mu][2 + c][r][1] = -G[mu][r][c][1];
-            }
+    double g[4][4][4][2];
+    for (int mu = 0; mu < 4; ++mu) gamma_matrix(mu, g[mu]);
     auto mm = [&](const double (*a)[4][2], const double (*b)[4][2], double (*o)[4][2]) {
         for (int r = 0; r < 4; ++r)
             for (int c = 0; c < 4; ++c) {
@@ -343,7 +317,6 @@ static SigmaBlocks sigma_blocks(double csw) {
                 o[r][c][1] = im;
             }
     };
-    (void)sizeof(c2);
     SigmaBlocks sb{};
     int plane = 0;
     for (int mu = 0; mu < 4; ++mu)
@@ -375,6 +348,24 @@ static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, void* o
 }
 
 static size_t real_bytes(qmg_prec p) { return p == QMG_C128 ? 8 : 4; }
+
+void gamma_matrix(int mu, double g[4][4][2]) {
+    // off-diagonal block g_mu (upper right); the lower-left block is g_mu^+
+    static const double G[4][2][2][2] = {
+        {{{0, 0}, {0, -1}}, {{0, -1}, {0, 0}}},   // -i sigma_1
+        {{{0, 0}, {-1, 0}}, {{1, 0}, {0, 0}}},    // -i sigma_2
+        {{{0, -1}, {0, 0}}, {{0, 0}, {0, 1}}},    // -i sigma_3
+        {{{1, 0}, {0, 0}}, {{0, 0}, {1, 0}}}};    // 1
+    for (int r = 0; r < 4; ++r)
+        for (int c = 0; c < 4; ++c) g[r][c][0] = g[r][c][1] = 0;
+    for (int r = 0; r < 2; ++r)
+        for (int c = 0; c < 2; ++c) {
+            g[r][2 + c][0] = G[mu][r][c][0];
+            g[r][2 + c][1] = G[mu][r][c][1];
+            g[2 + c][r][0] = G[mu][r][c][0];     // (g^+)_{c r} = conj(g_{r c})
+            g[2 + c][r][1] = -G[mu][r][c][1];
+        }
+}
 
 }  // namespace qmg
 
