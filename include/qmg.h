@@ -57,6 +57,7 @@ typedef enum {
 typedef struct qmg_coarse_op_s* qmg_coarse_op;
 typedef struct qmg_fine_op_s* qmg_fine_op;
 typedef struct qmg_transfer_s* qmg_transfer;
+typedef struct qmg_mg_s* qmg_mg;
 
 /* Message describing the most recent failure on this host thread. */
 const char* qmg_last_error(void);
@@ -188,6 +189,63 @@ void qmg_transfer_destroy(qmg_transfer t);
  * ------------------------------------------------------------------------- */
 qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_coarse_op parent,
                                qmg_prec storage, void* stream, qmg_coarse_op* out);
+
+/* ---------------------------------------------------------------------------
+ * Multigrid hierarchy and K-cycle GCR solver (Sec. 3.4 setup, Sec. 7.1).
+ * ------------------------------------------------------------------------- */
+
+/* Parameters of level l (the level that is coarsened), caller-owned, copied. */
+typedef struct {
+    int block[4];        /* aggregate extents (must divide the level's lattice, coarse extents >= 2) */
+    int nvec;            /* near-null vectors; the next level has N = 2*nvec (1..64) */
+    int setup_iters;     /* GCR(10) steps relaxing A x = 0 per vector (0: use the starts as given) */
+    int smoother_steps;  /* MR steps before and after the coarse correction (4) */
+    double coarse_tol;   /* relative tolerance of the GCR solve on the next level (0.25) */
+    int coarse_maxit;    /* its iteration cap (10 intermediate, 100 coarsest) */
+} qmg_level_params;
+
+typedef struct {
+    double tol;   /* stop when |b - M x| <= tol |b| (true residual, FP64) */
+    int restart;  /* 0 or 10: outer GCR Krylov space */
+    int maxit;    /* cap on outer steps */
+} qmg_solve_params;
+
+typedef struct {
+    int outer_iters;          /* outer GCR steps */
+    int level_iters[4];       /* [0] = outer steps, [l] = total GCR steps on level l */
+    int restarts;             /* true-residual restarts that did not converge */
+    int converged;
+    double true_rel_residual; /* |b - M x| / |b| from the FP64 operator */
+    double seconds;           /* host wall time of the solve */
+} qmg_solve_info;
+
+/* Build the hierarchy on DEVICE gauge [4][V][3][3] complex128 (as in
+ * qmg_fine_op_create): nlevels (1..4) levels, lp[l] for l < nlevels-1, and
+ * starts[l] = DEVICE complex128 [nvec_l][V_l][dof_l] random start vectors of
+ * the near-null relaxation on level l (dof_0 = 12, dof_l = 2*nvec_{l-1}).
+ * `inner` (QMG_C64 or QMG_C128) is the precision of the K-cycle, the
+ * relaxation and the coarse operators; the outer GCR and the true residual
+ * always use FP64.  Blocks until the setup is complete. */
+qmg_status qmg_mg_create(const int dims[4], const void* gauge, double m0, double csw, int antiperiodic_t,
+                         int nlevels, const qmg_level_params* lp, const void* const* starts,
+                         qmg_prec inner, void* stream, qmg_mg* out);
+
+/* Solve M x = b: b, x DEVICE complex128 [V][4][3] (x is overwritten, start
+ * x = 0).  Blocks; returns QMG_ERR_NOCONV if maxit is reached and
+ * QMG_ERR_NONFINITE on NaN/Inf; *info (host, may be NULL) is filled in any case. */
+qmg_status qmg_mg_gcr_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
+                            qmg_solve_info* info, void* stream);
+
+/* Borrowed views of level l: lattice dims, components per site, its coarse
+ * operator (NULL on level 0) and the transfer to level l+1 (NULL on the
+ * coarsest).  The handles stay owned by the hierarchy. */
+qmg_status qmg_mg_level(qmg_mg mg, int level, int dims[4], int* dof, qmg_coarse_op* op,
+                        qmg_transfer* to_next);
+
+/* Borrowed FP64 fine operator of the hierarchy. */
+qmg_status qmg_mg_fine_op(qmg_mg mg, qmg_fine_op* fine64);
+
+void qmg_mg_destroy(qmg_mg mg);
 
 #ifdef __cplusplus
 }

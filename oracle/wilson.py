@@ -113,3 +113,38 @@ def dense_matrix(apply, n):
         M[:, j] = apply(e)
         e[j] = 0.0
     return M
+
+
+_C = None
+
+
+def _clib():
+    global _C
+    if _C is None:
+        import ctypes
+        import os
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), '_oracle_c.so')
+        if not os.path.exists(path):
+            from . import build_c
+            build_c.build(verbose=False)
+        lib = ctypes.CDLL(path)
+        lib.oracle_wilson_clover.restype = None
+        lib.oracle_wilson_clover.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_double, ctypes.c_int] + [ctypes.c_void_p] * 3
+        _C = lib
+    return _C
+
+
+def apply_wilson_clover_c(psi, U, clover, m0, dims, antiperiodic_t=True):
+    """Same map as apply_wilson_clover, from the plain C loop in csrc/wilson_clover.c."""
+    import ctypes
+    V = lattice.volume(dims)
+    shape = psi.shape
+    psi = np.ascontiguousarray(psi, dtype=np.complex128).reshape(V, 12)
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    cl = None if clover is None else np.ascontiguousarray(clover, dtype=np.complex128)
+    g = np.ascontiguousarray(lattice.gammas(), dtype=np.complex128)
+    out = np.empty_like(psi)
+    L = (ctypes.c_int * 4)(*dims)
+    _clib().oracle_wilson_clover(L, U.ctypes.data, None if cl is None else cl.ctypes.data, float(m0),
+                                 int(bool(antiperiodic_t)), g.ctypes.data, psi.ctypes.data, out.ctypes.data)
+    return out.reshape(shape)

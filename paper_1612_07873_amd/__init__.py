@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 
@@ -91,7 +91,7 @@ class CoarseOp:
 
     def __del__(self):
         h = getattr(self, '_h', None)
-        if h is not None and h.value and _lib._lib is not None:
+        if h is not None and h.value and _lib._lib is not None and not getattr(self, '_borrowed', False):
             _lib._lib.qmg_coarse_op_destroy(h)
             self._h = None
 
@@ -180,7 +180,7 @@ class Transfer:
 
     def __del__(self):
         h = getattr(self, '_h', None)
-        if h is not None and h.value and _lib._lib is not None:
+        if h is not None and h.value and _lib._lib is not None and not getattr(self, '_borrowed', False):
             _lib._lib.qmg_transfer_destroy(h)
             self._h = None
 
@@ -191,3 +191,89 @@ def build_coarse_op(transfer, fine=None, parent=None, storage='c128'):
     _lib.call('qmg_build_coarse_op', transfer._h, fine._h if fine is not None else None,
               parent._h if parent is not None else None, PREC[storage], stream_ptr(), ctypes.byref(h))
     return CoarseOp(transfer.coarse_dims, None, None, storage, _handle=h, _N=transfer.N)
+
+
+class _BorrowedTransfer(Transfer):
+    def __init__(self, handle, fine_dims, dof, nvec, storage):
+        self._borrowed = True
+        self._h = handle
+        self.fine_dims = tuple(fine_dims)
+        self.V = _vol(self.fine_dims)
+        self.dof, self.nvec, self.storage = dof, nvec, storage
+        cd = _lib.c_dims()
+        n = ctypes.c_int()
+        _lib.call('qmg_transfer_coarse_dims', handle, cd, ctypes.byref(n))
+        self.coarse_dims = tuple(cd)
+        self.Vc = _vol(self.coarse_dims)
+        self.N = n.value
+
+
+class Multigrid:
+    """Adaptive multigrid hierarchy + K-cycle FGCR solver (qmg_mg_create / qmg_mg_gcr_solve).
+
+    levels: list of dicts with keys block, nvec, setup_iters, smoother_steps,
+    coarse_tol, coarse_maxit (one per coarsened level); starts: list of device
+    complex128 tensors [nvec_l][V_l][dof_l]."""
+
+    def __init__(self, dims, gauge, m0, csw, levels, starts, antiperiodic_t=True, inner='c64'):
+        self.dims = tuple(int(d) for d in dims)
+        self.V = _vol(self.dims)
+        self.inner = inner
+        self.nlevels = len(levels) + 1
+        lp = (_lib.LevelParams * max(1, len(levels)))()
+        for i, L in enumerate(levels):
+            lp[i].block = (ctypes.c_int * 4)(*L['block'])
+            lp[i].nvec = int(L['nvec'])
+            lp[i].setup_iters = int(L.get('setup_iters', 100))
+            lp[i].smoother_steps = int(L.get('smoother_steps', 4))
+            lp[i].coarse_tol = float(L.get('coarse_tol', 0.25))
+            lp[i].coarse_maxit = int(L.get('coarse_maxit', 10))
+        ptrs = (ctypes.c_void_p * max(1, len(starts)))()
+        for i, t in enumerate(starts):
+            if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
+                raise TypeError('starts[%d] must be a contiguous complex128 device tensor' % i)
+            ptrs[i] = t.data_ptr()
+        self._starts = starts
+        h = ctypes.c_void_p()
+        _lib.call('qmg_mg_create', _lib.c_dims(*self.dims),
+                  _dev_ptr(gauge, torch.complex128, (4, self.V, 3, 3), 'gauge'),
+                  float(m0), float(csw), int(bool(antiperiodic_t)), self.nlevels, lp, ptrs, PREC[inner],
+                  stream_ptr(), ctypes.byref(h))
+        self._h = h
+        self._levels = levels
+
+    def solve(self, b, x=None, tol=1e-10, maxit=500, check=True):
+        if x is None:
+            x = torch.empty_like(b)
+        sp = _lib.SolveParams(tol=float(tol), restart=10, maxit=int(maxit))
+        info = _lib.SolveInfo()
+        st = _lib.lib().qmg_mg_gcr_solve(self._h, _dev_ptr(b, torch.complex128, (self.V, 4, 3), 'b'),
+                                         _dev_ptr(x, torch.complex128, (self.V, 4, 3), 'x'),
+                                         ctypes.byref(sp), ctypes.byref(info), stream_ptr())
+        out = {'outer_iters': info.outer_iters, 'level_iters': list(info.level_iters)[:self.nlevels],
+               'restarts': info.restarts, 'converged': bool(info.converged),
+               'true_rel_residual': info.true_rel_residual, 'seconds': info.seconds, 'status': st}
+        if check:
+            _lib.check(st, 'qmg_mg_gcr_solve')
+        return x, out
+
+    def level(self, l):
+        d = _lib.c_dims()
+        dof = ctypes.c_int()
+        op, T = ctypes.c_void_p(), ctypes.c_void_p()
+        _lib.call('qmg_mg_level', self._h, int(l), d, ctypes.byref(dof), ctypes.byref(op), ctypes.byref(T))
+        dims = tuple(d)
+        cop = None
+        if op.value:
+            cop = CoarseOp(dims, None, None, self.inner, _handle=op, _N=dof.value)
+            cop._borrowed = True
+        tr = None
+        if T.value:
+            tr = _BorrowedTransfer(T, dims, dof.value, int(self._levels[l]['nvec']), self.inner)
+        return dims, dof.value, cop, tr
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.qmg_mg_destroy(h)
+            self._h = None

@@ -40,6 +40,32 @@ SIGNATURES = {
     'qmg_build_coarse_op': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
 }
 
+
+
+class LevelParams(ctypes.Structure):
+    _fields_ = [('block', c_int * 4), ('nvec', c_int), ('setup_iters', c_int), ('smoother_steps', c_int),
+                ('coarse_tol', c_double), ('coarse_maxit', c_int)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [('tol', c_double), ('restart', c_int), ('maxit', c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [('outer_iters', c_int), ('level_iters', c_int * 4), ('restarts', c_int), ('converged', c_int),
+                ('true_rel_residual', c_double), ('seconds', c_double)]
+
+
+SIGNATURES.update({
+    'qmg_mg_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, ctypes.POINTER(LevelParams),
+                              ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_mg_gcr_solve': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
+                                 ctypes.POINTER(SolveInfo), c_void_p]),
+    'qmg_mg_level': (c_int, [c_void_p, c_int, c_int_p, c_int_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
+    'qmg_mg_fine_op': (c_int, [c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_mg_destroy': (None, [c_void_p]),
+})
+
 _lib = None
 
 

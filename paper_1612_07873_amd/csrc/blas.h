@@ -1,0 +1,41 @@
+// BLAS-1 layer of the Krylov solvers: every scalar stays in device memory;
+// reductions are two-phase (per-block partials, then one block sums them in a
+// fixed order) so results are bitwise repeatable and need no atomics.
+#pragma once
+
+#include "qmg_internal.h"
+
+namespace qmg {
+
+struct Blas {
+    hipStream_t s = nullptr;
+    double* partials = nullptr;  // [kMaxBlocks][kMaxVals]
+    static constexpr int kMaxBlocks = 512;
+    static constexpr int kMaxVals = 40;
+
+    qmg_status init();
+    void release();
+
+    // Results are written to device doubles at `out`.
+    template <typename R> qmg_status dot(const void* a, const void* b, int64_t n, double* out);   // <a,b> (2)
+    template <typename R> qmg_status norm2(const void* a, int64_t n, double* out);                // |a|^2 (1)
+    // out = [<q,q>, <q,r>.re, <q,r>.im]
+    template <typename R> qmg_status dot_norm(const void* q, const void* r, int64_t n, double* out);
+    // out[2i..2i+1] = <Q_i, q>, i < k; Q_i = Q + i*ld
+    template <typename R> qmg_status multi_dot(const void* Q, int64_t ld, int k, const void* q, int64_t n, double* out);
+    // q -= sum_i beta_i Q_i ; z -= sum_i beta_i Z_i (z may be NULL)
+    template <typename R> qmg_status multi_axpy(const double* beta, const void* Q, const void* Z, int64_t ld, int k,
+                                                void* q, void* z, int64_t n);
+    // GCR step (no-op when s[0] = 0): nq = sqrt(s[0]); alpha = (s[1] + i s[2]) / nq; q /= nq; z /= nq; x += alpha z; r -= alpha q
+    template <typename R> qmg_status gcr_update(const double* s3, void* q, void* z, void* x, void* r, int64_t n);
+    // MR step with s = dot_norm(Ar, r) = [<Ar,Ar>, <Ar,r>.re, <Ar,r>.im]:
+    // alpha = (s1 + i s2)/s0; x = alpha r (first) or x += alpha r; r -= alpha Ar
+    template <typename R> qmg_status mr_update(const double* s3, void* r, const void* Ar, void* x, int first, int64_t n);
+    template <typename R> qmg_status axpy(double a, const void* x, void* y, int64_t n);       // y += a x
+    template <typename R> qmg_status xmy(const void* b, const void* ax, void* r, int64_t n);  // r = b - ax
+    template <typename Rs, typename Rd> qmg_status convert(const void* src, void* dst, int64_t n);
+    // x /= sqrt(nrm2[0])
+    template <typename R> qmg_status normalize(void* x, const double* nrm2, int64_t n);
+};
+
+}  // namespace qmg

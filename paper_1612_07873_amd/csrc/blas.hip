@@ -1,0 +1,319 @@
+// BLAS-1 kernels of the solvers (see blas.h).
+#include "blas.h"
+
+namespace qmg {
+
+static constexpr int kThreads = 256;
+
+static int nblocks(int64_t n) {
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b > Blas::kMaxBlocks) b = Blas::kMaxBlocks;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+// sum of v over the work-group, valid in thread 0
+__device__ __forceinline__ double wg_sum(double v, double* lds) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) lds[w] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += lds[i];
+    return t;
+}
+
+// phase 2: out[v] = sum over blocks of partials[b][v], fixed order
+__global__ void k_final(const double* __restrict__ partials, int nb, int nv, double* __restrict__ out) {
+    const int v = threadIdx.x;
+    if (v >= nv) return;
+    double t = 0;
+    for (int b = 0; b < nb; ++b) t += partials[b * Blas::kMaxVals + v];
+    out[v] = t;
+}
+
+template <typename R>
+__global__ void k_dot(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, int64_t n,
+                      double* __restrict__ part) {
+    __shared__ double lds[16];
+    double re = 0, im = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const cpx<R> x = a[i], y = b[i];
+        re += (double)x.re * y.re + (double)x.im * y.im;
+        im += (double)x.re * y.im - (double)x.im * y.re;
+    }
+    re = wg_sum(re, lds);
+    im = wg_sum(im, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x * Blas::kMaxVals + 0] = re;
+        part[blockIdx.x * Blas::kMaxVals + 1] = im;
+    }
+}
+
+template <typename R>
+__global__ void k_norm2(const cpx<R>* __restrict__ a, int64_t n, double* __restrict__ part) {
+    __shared__ double lds[16];
+    double s = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const cpx<R> x = a[i];
+        s += (double)x.re * x.re + (double)x.im * x.im;
+    }
+    s = wg_sum(s, lds);
+    if (threadIdx.x == 0) part[blockIdx.x * Blas::kMaxVals] = s;
+}
+
+template <typename R>
+__global__ void k_dot_norm(const cpx<R>* __restrict__ q, const cpx<R>* __restrict__ r, int64_t n,
+                           double* __restrict__ part) {
+    __shared__ double lds[16];
+    double qq = 0, re = 0, im = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const cpx<R> x = q[i], y = r[i];
+        qq += (double)x.re * x.re + (double)x.im * x.im;
+        re += (double)x.re * y.re + (double)x.im * y.im;
+        im += (double)x.re * y.im - (double)x.im * y.re;
+    }
+    qq = wg_sum(qq, lds);
+    re = wg_sum(re, lds);
+    im = wg_sum(im, lds);
+    if (threadIdx.x == 0) {
+        double* p = part + blockIdx.x * Blas::kMaxVals;
+        p[0] = qq;
+        p[1] = re;
+        p[2] = im;
+    }
+}
+
+template <typename R>
+__global__ void k_multi_dot(const cpx<R>* __restrict__ Q, int64_t ld, int k, const cpx<R>* __restrict__ q,
+                            int64_t n, double* __restrict__ part) {
+    __shared__ double lds[16];
+    double re[16], im[16];
+    for (int j = 0; j < 16; ++j) re[j] = im[j] = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const cpx<R> y = q[i];
+        for (int j = 0; j < k; ++j) {
+            const cpx<R> x = Q[j * ld + i];
+            re[j] += (double)x.re * y.re + (double)x.im * y.im;
+            im[j] += (double)x.re * y.im - (double)x.im * y.re;
+        }
+    }
+    for (int j = 0; j < k; ++j) {
+        const double a = wg_sum(re[j], lds);
+        const double b = wg_sum(im[j], lds);
+        if (threadIdx.x == 0) {
+            part[blockIdx.x * Blas::kMaxVals + 2 * j] = a;
+            part[blockIdx.x * Blas::kMaxVals + 2 * j + 1] = b;
+        }
+    }
+}
+
+template <typename R>
+__global__ void k_multi_axpy(const double* __restrict__ beta, const cpx<R>* __restrict__ Q,
+                             const cpx<R>* __restrict__ Z, int64_t ld, int k, cpx<R>* __restrict__ q,
+                             cpx<R>* __restrict__ z, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    R qr = q[i].re, qi = q[i].im;
+    R zr = 0, zi = 0;
+    if (z) { zr = z[i].re; zi = z[i].im; }
+    for (int j = 0; j < k; ++j) {
+        const R br = (R)beta[2 * j], bi = (R)beta[2 * j + 1];
+        const cpx<R> a = Q[j * ld + i];
+        qr -= br * a.re - bi * a.im;
+        qi -= br * a.im + bi * a.re;
+        if (z) {
+            const cpx<R> c = Z[j * ld + i];
+            zr -= br * c.re - bi * c.im;
+            zi -= br * c.im + bi * c.re;
+        }
+    }
+    q[i] = cpx<R>{qr, qi};
+    if (z) z[i] = cpx<R>{zr, zi};
+}
+
+template <typename R>
+__global__ void k_gcr_update(const double* __restrict__ s3, cpx<R>* __restrict__ q, cpx<R>* __restrict__ z,
+                             cpx<R>* __restrict__ x, cpx<R>* __restrict__ r, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !(s3[0] > 0)) return;  // q = 0: no update (breakdown is reported by the caller)
+    const double nq = sqrt(s3[0]);
+    const R inv = (R)(1.0 / nq);
+    const R ar = (R)(s3[1] / nq), ai = (R)(s3[2] / nq);
+    cpx<R> qq = q[i], zz = z[i];
+    qq.re *= inv; qq.im *= inv;
+    zz.re *= inv; zz.im *= inv;
+    q[i] = qq;
+    z[i] = zz;
+    cpx<R> xx = x[i], rr = r[i];
+    xx.re += ar * zz.re - ai * zz.im;
+    xx.im += ar * zz.im + ai * zz.re;
+    rr.re -= ar * qq.re - ai * qq.im;
+    rr.im -= ar * qq.im + ai * qq.re;
+    x[i] = xx;
+    r[i] = rr;
+}
+
+template <typename R>
+__global__ void k_mr_update(const double* __restrict__ s3, cpx<R>* __restrict__ r, const cpx<R>* __restrict__ Ar,
+                            cpx<R>* __restrict__ x, int first, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double den = s3[0];
+    const R ar = den > 0 ? (R)(s3[1] / den) : (R)0, ai = den > 0 ? (R)(s3[2] / den) : (R)0;
+    cpx<R> rr = r[i];
+    const cpx<R> a = Ar[i];
+    cpx<R> xx = first ? cpx<R>{0, 0} : x[i];
+    xx.re += ar * rr.re - ai * rr.im;
+    xx.im += ar * rr.im + ai * rr.re;
+    rr.re -= ar * a.re - ai * a.im;
+    rr.im -= ar * a.im + ai * a.re;
+    x[i] = xx;
+    r[i] = rr;
+}
+
+template <typename R>
+__global__ void k_axpy(R a, const cpx<R>* __restrict__ x, cpx<R>* __restrict__ y, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i].re += a * x[i].re;
+    y[i].im += a * x[i].im;
+}
+
+template <typename R>
+__global__ void k_xmy(const cpx<R>* __restrict__ b, const cpx<R>* __restrict__ ax, cpx<R>* __restrict__ r, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    r[i] = cpx<R>{b[i].re - ax[i].re, b[i].im - ax[i].im};
+}
+
+template <typename Rs, typename Rd>
+__global__ void k_convert(const cpx<Rs>* __restrict__ s, cpx<Rd>* __restrict__ d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    d[i] = cpx<Rd>{(Rd)s[i].re, (Rd)s[i].im};
+}
+
+template <typename R>
+__global__ void k_normalize(cpx<R>* __restrict__ x, const double* __restrict__ nrm2, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const R inv = (R)(1.0 / sqrt(nrm2[0]));
+    x[i].re *= inv;
+    x[i].im *= inv;
+}
+
+qmg_status Blas::init() {
+    if (partials) return QMG_OK;
+    QMG_HIP(hipMalloc(&partials, sizeof(double) * kMaxBlocks * kMaxVals));
+    return QMG_OK;
+}
+
+void Blas::release() {
+    if (partials) (void)hipFree(partials);
+    partials = nullptr;
+}
+
+static unsigned grid1(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+template <typename R> qmg_status Blas::dot(const void* a, const void* b, int64_t n, double* out) {
+    const int nb = nblocks(n);
+    hipLaunchKernelGGL(k_dot<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 2, out);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R> qmg_status Blas::norm2(const void* a, int64_t n, double* out) {
+    const int nb = nblocks(n);
+    hipLaunchKernelGGL(k_norm2<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)a, n, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 1, out);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R> qmg_status Blas::dot_norm(const void* q, const void* r, int64_t n, double* out) {
+    const int nb = nblocks(n);
+    hipLaunchKernelGGL(k_dot_norm<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)q, (const cpx<R>*)r, n, partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 3, out);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R>
+qmg_status Blas::multi_dot(const void* Q, int64_t ld, int k, const void* q, int64_t n, double* out) {
+    if (k <= 0) return QMG_OK;
+    if (k > 16) return fail(QMG_ERR_ARG, "multi_dot: k=%d > 16", k);
+    const int nb = nblocks(n);
+    hipLaunchKernelGGL(k_multi_dot<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)Q, ld, k, (const cpx<R>*)q, n,
+                       partials);
+    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 2 * k, out);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R>
+qmg_status Blas::multi_axpy(const double* beta, const void* Q, const void* Z, int64_t ld, int k, void* q, void* z,
+                            int64_t n) {
+    if (k <= 0) return QMG_OK;
+    hipLaunchKernelGGL(k_multi_axpy<R>, dim3(grid1(n)), dim3(kThreads), 0, s, beta, (const cpx<R>*)Q,
+                       (const cpx<R>*)Z, ld, k, (cpx<R>*)q, (cpx<R>*)z, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R>
+qmg_status Blas::gcr_update(const double* s3, void* q, void* z, void* x, void* r, int64_t n) {
+    hipLaunchKernelGGL(k_gcr_update<R>, dim3(grid1(n)), dim3(kThreads), 0, s, s3, (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x,
+                       (cpx<R>*)r, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R>
+qmg_status Blas::mr_update(const double* s3, void* r, const void* Ar, void* x, int first, int64_t n) {
+    hipLaunchKernelGGL(k_mr_update<R>, dim3(grid1(n)), dim3(kThreads), 0, s, s3, (cpx<R>*)r, (const cpx<R>*)Ar,
+                       (cpx<R>*)x, first, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R> qmg_status Blas::axpy(double a, const void* x, void* y, int64_t n) {
+    hipLaunchKernelGGL(k_axpy<R>, dim3(grid1(n)), dim3(kThreads), 0, s, (R)a, (const cpx<R>*)x, (cpx<R>*)y, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R> qmg_status Blas::xmy(const void* b, const void* ax, void* r, int64_t n) {
+    hipLaunchKernelGGL(k_xmy<R>, dim3(grid1(n)), dim3(kThreads), 0, s, (const cpx<R>*)b, (const cpx<R>*)ax,
+                       (cpx<R>*)r, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename Rs, typename Rd> qmg_status Blas::convert(const void* src, void* dst, int64_t n) {
+    hipLaunchKernelGGL((k_convert<Rs, Rd>), dim3(grid1(n)), dim3(kThreads), 0, s, (const cpx<Rs>*)src,
+                       (cpx<Rd>*)dst, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, int64_t n) {
+    hipLaunchKernelGGL(k_normalize<R>, dim3(grid1(n)), dim3(kThreads), 0, s, (cpx<R>*)x, nrm2, n);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+#define QMG_BLAS_INST(R)                                                                                   \
+    template qmg_status Blas::dot<R>(const void*, const void*, int64_t, double*);                          \
+    template qmg_status Blas::norm2<R>(const void*, int64_t, double*);                                     \
+    template qmg_status Blas::dot_norm<R>(const void*, const void*, int64_t, double*);                     \
+    template qmg_status Blas::multi_dot<R>(const void*, int64_t, int, const void*, int64_t, double*);      \
+    template qmg_status Blas::multi_axpy<R>(const double*, const void*, const void*, int64_t, int, void*, \
+                                            void*, int64_t);                                               \
+    template qmg_status Blas::gcr_update<R>(const double*, void*, void*, void*, void*, int64_t);           \
+    template qmg_status Blas::mr_update<R>(const double*, void*, const void*, void*, int, int64_t);        \
+    template qmg_status Blas::axpy<R>(double, const void*, void*, int64_t);                                \
+    template qmg_status Blas::xmy<R>(const void*, const void*, void*, int64_t);                            \
+    template qmg_status Blas::normalize<R>(void*, const double*, int64_t);
+
+QMG_BLAS_INST(double)
+QMG_BLAS_INST(float)
+template qmg_status Blas::convert<double, float>(const void*, void*, int64_t);
+template qmg_status Blas::convert<float, double>(const void*, void*, int64_t);
+template qmg_status Blas::convert<double, double>(const void*, void*, int64_t);
+template qmg_status Blas::convert<float, float>(const void*, void*, int64_t);
+
+}  // namespace qmg

@@ -24,9 +24,9 @@ void clear_error();
                                __FILE__, __LINE__);                                     \
     } while (0)
 
-#define QMG_TRY(call)                      \
+#define QMG_TRY(...)                       \
     do {                                   \
-        qmg_status s_ = (call);            \
+        qmg_status s_ = (__VA_ARGS__);     \
         if (s_ != QMG_OK) return s_;       \
     } while (0)
 

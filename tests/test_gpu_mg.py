@@ -1,0 +1,100 @@
+"""GPU multigrid: hierarchy built on the device (null-vector relaxation,
+transfers, Galerkin) and the K-cycle FGCR solve.  Judged by the oracle: the
+true residual under the oracle's FP64 M, the oracle's iteration count for the
+same hierarchy inputs, and the levels' operators against the oracle's
+Galerkin build from the same vectors."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lattice, mg as omg, solvers, transfer, wilson
+from gpu_util import dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def problem(dims, eps, seed, m0):
+    U = synth.gauge_field(dims, eps, seed)
+    A = wilson.clover_field(U, dims, 1.0)
+    return U, A, omg.FineLevel(U, A, m0, dims)
+
+
+def level_list(blocks, nvecs, setup_iters, coarse_maxit):
+    return [dict(block=b, nvec=n, setup_iters=setup_iters, smoother_steps=4, coarse_tol=0.25,
+                 coarse_maxit=c) for b, n, c in zip(blocks, nvecs, coarse_maxit)]
+
+
+def starts_for(dims, blocks, nvecs, seed):
+    out, cur, dof = [], tuple(dims), 12
+    for l, (b, n) in enumerate(zip(blocks, nvecs)):
+        out.append(synth.gaussian((n, lattice.volume(cur), dof), seed + l, 1))
+        cur = tuple(c // bb for c, bb in zip(cur, b))
+        dof = 2 * n
+    return out
+
+
+@pytest.mark.parametrize('inner', ['c128', 'c64'])
+def test_two_level_matches_oracle_iterations(inner):
+    """Setup vectors given as data (setup_iters = 0): GPU and oracle build the
+    same hierarchy; FP64 inner iteration counts must agree within 1."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (4, 4, 4, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2)], [6]
+    U, A, fine = problem(dims, 0.4, 1, m0)
+    st = starts_for(dims, blocks, nvecs, 0)
+    h = omg.Hierarchy(fine, blocks, nvecs, [s.reshape(nvecs[0], -1) for s in st], setup_iters=0)
+    b = synth.gaussian((fine.V, 4, 3), 0, 2)
+    xo, io = omg.solve(h, b.reshape(-1), tol=1e-10, coarsest_maxit=100)
+    mg = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 0, [100]), [dev(s) for s in st], inner=inner)
+    # the level-1 operator equals the oracle's Galerkin build from the same vectors
+    _, N, op1, _ = mg.level(1)
+    X, Y = op1.export()
+    tol = 1e-12 if inner == 'c128' else 1e-5
+    assert max(rel_err(host(X), h.levels[1].op.X), rel_err(host(Y), h.levels[1].op.Y)) <= tol
+    x, info = mg.solve(dev(b), tol=1e-10)
+    xh = host(x)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(xh.reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('inner', inner, 'gpu', info, 'oracle iters', io.iters, io.inner_iters, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    if inner == 'c128':
+        assert abs(info['outer_iters'] - io.iters) <= 1
+    else:
+        assert info['outer_iters'] <= io.iters + 2
+
+
+def test_three_level_with_relaxed_null_vectors():
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U, A, fine = problem(dims, 0.3, 2, m0)
+    st = starts_for(dims, blocks, nvecs, 5)
+    mg = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 30, [10, 100]), [dev(s) for s in st], inner='c64')
+    b = synth.gaussian((fine.V, 4, 3), 1, 2)
+    x, info = mg.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('3-level 8^4', info, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    assert info['level_iters'][1] > 0 and info['level_iters'][2] > 0
+    # the relaxed vectors are rich in low modes: the level-1 operator is much
+    # better conditioned for the smooth error than plain GCR on the fine level
+    x2, info2 = mg.solve(dev(b), tol=1e-10)
+    assert info2['outer_iters'] == info['outer_iters']       # repeatable
+
+
+def test_config2_shape_three_levels_to_1e10():
+    """16^3x32, eps 0.3: block 4^4 / Nvec 24 -> 4^3x8 (N 48), block 2^4 / Nvec 32 -> 2^3x4 (N 64),
+    FP32 inner, MR(4) smoothing, FP64 outer GCR(10) to 1e-10 (true residual under the oracle's M)."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (16, 16, 16, 32), -0.25
+    blocks, nvecs = [(4, 4, 4, 4), (2, 2, 2, 2)], [24, 32]
+    U = synth.gauge_field(dims, 0.3, 0)
+    A = wilson.clover_field(U, dims, 1.0)
+    st = starts_for(dims, blocks, nvecs, 0)
+    mg = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 100, [10, 100]), [dev(s) for s in st], inner='c64')
+    b = synth.gaussian((lattice.volume(dims), 4, 3), 0, 2)
+    x, info = mg.solve(dev(b), tol=1e-10)
+    r = b - wilson.apply_wilson_clover_c(host(x).reshape(b.shape), U, A, m0, dims)
+    tr = np.linalg.norm(r) / np.linalg.norm(b)
+    print('config2 shape', info, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10

@@ -9,11 +9,19 @@ from oracle_helpers import (abelian_flux, free_spectrum, match_multisets, pure_g
                             unit_gauge)
 
 
-def dense_M(U, clover, m0, dims, anti=True):
+# both restatements of Eq. (2) in the oracle are held to the same pins
+IMPLS = {'numpy': wilson.apply_wilson_clover, 'c': wilson.apply_wilson_clover_c}
+
+
+@pytest.fixture(params=sorted(IMPLS))
+def apply_M(request):
+    return IMPLS[request.param]
+
+
+def dense_M(U, clover, m0, dims, anti=True, apply=wilson.apply_wilson_clover):
     V = lattice.volume(dims)
     return wilson.dense_matrix(
-        lambda v: wilson.apply_wilson_clover(v.reshape(V, 4, 3), U, clover, m0, dims, anti).reshape(-1),
-        V * 12)
+        lambda v: apply(v.reshape(V, 4, 3), U, clover, m0, dims, anti).reshape(-1), V * 12)
 
 
 def test_gauge_links_are_special_unitary():
@@ -40,25 +48,25 @@ def test_gamma_clifford_algebra_and_chiral_basis():
 
 
 @pytest.mark.parametrize("anti", [True, False])
-def test_free_field_spectrum_closed_form(anti):
+def test_free_field_spectrum_closed_form(anti, apply_M):
     """U = 1: eigenvalues m0 + sum(1 - cos p) +/- i sqrt(sum sin^2 p), 6-fold."""
     dims = (4, 2, 2, 4)
     m0 = -0.2
-    ev = np.linalg.eigvals(dense_M(unit_gauge(dims), None, m0, dims, anti))
+    ev = np.linalg.eigvals(dense_M(unit_gauge(dims), None, m0, dims, anti, apply_M))
     assert match_multisets(ev, free_spectrum(dims, m0, anti)) < 1e-12
 
 
-def test_pure_gauge_spectrum_and_vanishing_clover():
+def test_pure_gauge_spectrum_and_vanishing_clover(apply_M):
     """U_mu(x) = g(x) g(x+mu)^+ is a gauge copy of U = 1: same spectrum, zero clover."""
     dims = (4, 2, 2, 4)
     U = pure_gauge(dims, 7)
     A = wilson.clover_field(U, dims, 1.0)
     assert np.abs(A).max() < 1e-14
-    ev = np.linalg.eigvals(dense_M(U, A, -0.2, dims))
+    ev = np.linalg.eigvals(dense_M(U, A, -0.2, dims, True, apply_M))
     assert match_multisets(ev, free_spectrum(dims, -0.2)) < 1e-12
 
 
-def test_gamma5_hermiticity_random_links():
+def test_gamma5_hermiticity_random_links(apply_M):
     """gamma5 M gamma5 = M^+, checked through <phi, g5 M g5 psi> = <M phi, psi>."""
     dims = (4, 4, 4, 4)
     V = lattice.volume(dims)
@@ -67,7 +75,7 @@ def test_gamma5_hermiticity_random_links():
     g5 = np.kron(lattice.gamma5(), np.eye(3))
     phi = synth.gaussian((V, 12), 1, 2)
     psi = synth.gaussian((V, 12), 2, 2)
-    M = lambda v: wilson.apply_wilson_clover(v, U, A, -0.2, dims)
+    M = lambda v: apply_M(v, U, A, -0.2, dims)
     lhs = np.vdot(phi, M(psi @ g5.T) @ g5.T)
     rhs = np.vdot(M(phi), psi)
     assert abs(lhs - rhs) < 1e-12 * abs(rhs)
@@ -97,7 +105,7 @@ def test_clover_constant_abelian_flux_closed_form(n):
         assert np.abs(A - expect[None]).max() < 1e-14
 
 
-def test_gauge_covariance_of_M():
+def test_gauge_covariance_of_M(apply_M):
     """M[gU](g psi) = g M[U](psi) for a random local rotation g."""
     from oracle_helpers import gauge_rotate
     dims = (4, 4, 2, 4)
@@ -107,6 +115,17 @@ def test_gauge_covariance_of_M():
     Ug = gauge_rotate(U, g, dims)
     psi = synth.gaussian((V, 4, 3), 3, 2)
     rot = lambda p: np.einsum('xab,xsb->xsa', g, p)
-    a = wilson.apply_wilson_clover(rot(psi), Ug, wilson.clover_field(Ug, dims, 1.0), -0.3, dims)
-    b = rot(wilson.apply_wilson_clover(psi, U, wilson.clover_field(U, dims, 1.0), -0.3, dims))
+    a = apply_M(rot(psi), Ug, wilson.clover_field(Ug, dims, 1.0), -0.3, dims)
+    b = rot(apply_M(psi, U, wilson.clover_field(U, dims, 1.0), -0.3, dims))
     assert np.abs(a - b).max() < 1e-13
+
+
+def test_clover_enters_the_operator_through_A(apply_M):
+    """M with clover minus M without clover is exactly A(x) psi(x) (site-local)."""
+    dims = (4, 2, 4, 2)
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.5, 9)
+    A = wilson.clover_field(U, dims, 1.3)
+    psi = synth.gaussian((V, 4, 3), 4, 2)
+    d = apply_M(psi, U, A, 0.1, dims) - apply_M(psi, U, None, 0.1, dims)
+    assert np.abs(d.reshape(V, 12) - np.einsum('xij,xj->xi', A, psi.reshape(V, 12))).max() < 1e-14
