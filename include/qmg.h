@@ -80,10 +80,16 @@ qmg_status qmg_sync(void* stream);
 /* Create an operator on a coarse lattice `dims` (every extent >= 2) with N
  * components per site (N even, 2 <= N <= 128) from canonical DEVICE arrays
  *     X [V][N][N] complex128,  Y [8][V][N][N] complex128  (row-major blocks).
- * The data is copied (and converted to `storage`, which is QMG_C128 or
- * QMG_C64) into the library's own link layout; the caller may free X and Y
- * once the stream has passed this call.  On success *out owns device memory
- * of about 9*V*N*N*(bytes per complex). */
+ * The data is copied and converted to `storage` in the library's own link
+ * layout; the caller may free X and Y once the stream has passed this call.
+ * storage:
+ *   QMG_C128, QMG_C64  complex128 / complex64 links;
+ *   QMG_H16, QMG_B16   FP16 / BF16 (re, im) pairs with one FP32 scale per
+ *                      (site, block), block = X or one Y_d, scale = largest
+ *                      |re| or |im| in the block (needs N % 4 == 0); the
+ *                      arithmetic is FP32 (the paper's 16-bit storage, which
+ *                      trades precision for bandwidth).
+ * On success *out owns device memory of about 9*V*N*N*(bytes per complex). */
 qmg_status qmg_coarse_op_create(const int dims[4], int N, const void* X, const void* Y,
                                 qmg_prec storage, void* stream, qmg_coarse_op* out);
 
@@ -92,10 +98,26 @@ qmg_status qmg_coarse_op_create(const int dims[4], int N, const void* X, const v
 qmg_status qmg_coarse_op_export(qmg_coarse_op op, void* X, void* Y, void* stream);
 
 /* Apply Eq. (3): out = Mhat in, for one right-hand side.  `in` and `out` are
- * DEVICE arrays [V][N] in precision `prec`, which must equal the operator's
- * storage precision (QMG_C128 or QMG_C64).  in and out must not overlap. */
+ * DEVICE arrays [V][N] in precision `prec`: the operator's storage precision
+ * for QMG_C128 / QMG_C64 operators, and QMG_C64 (FP32 vectors) for QMG_H16 /
+ * QMG_B16 operators.  in and out must not overlap. */
 qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_prec prec,
                              void* stream);
+
+/* Apply Eq. (3) with 16-bit vectors (QMG_H16 or QMG_B16 operator; `prec` is
+ * QMG_H16 or QMG_B16 for the vectors): in/out DEVICE [V][N] 16-bit (re, im)
+ * pairs, in_scale/out_scale DEVICE float [V]; value = scale[x] * stored.  The
+ * result is accumulated in FP32 and re-scaled per site (out_scale = largest
+ * |re| or |im| of the site's N outputs).  Buffers must not overlap. */
+qmg_status qmg_coarse_dslash_scaled(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                                    float* out_scale, qmg_prec prec, void* stream);
+
+/* Convert a DEVICE complex64 field [V][N] to 16-bit pairs `out` [V][N] with
+ * per-site scales `scale` [V] (prec QMG_H16 or QMG_B16), and back. */
+qmg_status qmg_quantize_sites(const void* in, void* out, float* scale, long long V, int N, qmg_prec prec,
+                              void* stream);
+qmg_status qmg_dequantize_sites(const void* in, const float* scale, void* out, long long V, int N,
+                                qmg_prec prec, void* stream);
 
 /* Launch shape of the fine-grained stencil (Sec. 6.2-6.4): each work-group
  * covers `rows` output rows of one coarse site (rows divides N), and the

@@ -11,9 +11,10 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
+_VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
 
 
 def stream_ptr(stream=None):
@@ -47,7 +48,7 @@ class CoarseOp:
         self.dims = tuple(int(d) for d in dims)
         self.V = _vol(self.dims)
         self.storage = storage
-        self.dtype = _CDTYPE[storage]
+        self.dtype = _VECDTYPE[storage]
         if _handle is not None:
             self.N = int(_N)
             self._h = _handle
@@ -63,11 +64,25 @@ class CoarseOp:
     def apply(self, u, out=None):
         if out is None:
             out = torch.empty_like(u)
+        vp = self.storage if self.storage in ('c128', 'c64') else 'c64'
         _lib.call('qmg_coarse_dslash', self._h,
                   _dev_ptr(u, self.dtype, (self.V, self.N), 'in'),
                   _dev_ptr(out, self.dtype, (self.V, self.N), 'out'),
-                  PREC[self.storage], stream_ptr())
+                  PREC[vp], stream_ptr())
         return out
+
+    def apply_scaled(self, u16, uscale, out16=None, oscale=None, vprec=None):
+        """16-bit vectors: u16 int32 tensor [V][N] (packed pairs), uscale float32 [V]."""
+        vprec = vprec or self.storage
+        if out16 is None:
+            out16 = torch.empty_like(u16)
+        if oscale is None:
+            oscale = torch.empty_like(uscale)
+        _lib.call('qmg_coarse_dslash_scaled', self._h, _dev_ptr(u16, torch.int32, (self.V, self.N), 'in'),
+                  _dev_ptr(uscale, torch.float32, (self.V,), 'in_scale'),
+                  _dev_ptr(out16, torch.int32, (self.V, self.N), 'out'),
+                  _dev_ptr(oscale, torch.float32, (self.V,), 'out_scale'), PREC[vprec], stream_ptr())
+        return out16, oscale
 
     def export(self):
         dev = torch.device('cuda')
@@ -277,3 +292,22 @@ class Multigrid:
         if h is not None and h.value and _lib._lib is not None:
             _lib._lib.qmg_mg_destroy(h)
             self._h = None
+
+
+def quantize_sites(v, prec='h16'):
+    """complex64 [V][N] -> (int32 [V][N] packed 16-bit pairs, float32 [V] per-site scales)."""
+    V, N = v.shape
+    q = torch.empty((V, N), dtype=torch.int32, device=v.device)
+    sc = torch.empty((V,), dtype=torch.float32, device=v.device)
+    _lib.call('qmg_quantize_sites', _dev_ptr(v, torch.complex64, (V, N), 'in'), ctypes.c_void_p(q.data_ptr()),
+              ctypes.c_void_p(sc.data_ptr()), V, N, PREC[prec], stream_ptr())
+    return q, sc
+
+
+def dequantize_sites(q, sc, prec='h16'):
+    V, N = q.shape
+    out = torch.empty((V, N), dtype=torch.complex64, device=q.device)
+    _lib.call('qmg_dequantize_sites', _dev_ptr(q, torch.int32, (V, N), 'in'),
+              _dev_ptr(sc, torch.float32, (V,), 'scale'), ctypes.c_void_p(out.data_ptr()), V, N, PREC[prec],
+              stream_ptr())
+    return out

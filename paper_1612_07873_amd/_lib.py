@@ -23,6 +23,9 @@ SIGNATURES = {
     'qmg_coarse_op_export': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_launch': (c_int, [c_void_p, c_int, c_int]),
+    'qmg_coarse_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_quantize_sites': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, c_void_p]),
+    'qmg_dequantize_sites': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, c_void_p]),
     'qmg_coarse_op_get_launch': (c_int, [c_void_p, c_int_p, c_int_p]),
     'qmg_coarse_op_destroy': (None, [c_void_p]),
     'qmg_fine_op_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, c_void_p,

@@ -6,13 +6,14 @@
 // stacked input [u(x); u(x+hop_0); ..; u(x+hop_7)].  A work-group owns one
 // site (grid parallelism, Sec. 6.1) and a tile of `rows` output rows
 // (colour-spin parallelism, Sec. 6.2).  The 9N-long row is cut into 16-byte
-// chunks (1 complex in FP64, 2 in FP32) and chunk j goes to split-lane
-// s = j mod split: this one split covers both the stencil-direction split
-// (Sec. 6.3, chunks of different d) and the dot-product split (Sec. 6.4,
-// chunks of the same d), and the partial sums meet once in LDS before the
-// single store.  The site index and its 8 neighbours come from a
-// precomputed table, so no integer division by lattice extents is done in
-// the kernel (the indexing cost Sec. 6.5 names as the Amdahl limiter).
+// chunks (1 complex in FP64, 2 in FP32, 4 in FP16/BF16) and chunk j goes to
+// split-lane s = j mod split: this one split covers both the
+// stencil-direction split (Sec. 6.3, chunks of different d) and the
+// dot-product split (Sec. 6.4, chunks of the same d), and the partial sums
+// meet once in LDS before the single store.  The site index and its 8
+// neighbours come from a precomputed table, so no integer division by
+// lattice extents is done in the kernel (the indexing cost Sec. 6.5 names as
+// the Amdahl limiter on the smallest grids).
 //
 // Link layout.  Chunks are stored [site][j][row] (row fastest).  For a fixed
 // chunk index the rows of a site are contiguous, and consecutive split-lanes
@@ -20,8 +21,19 @@
 // read one contiguous span of rows*split*16 bytes per step whatever the split:
 // every load is a fully coalesced 16-byte-per-lane load, and the layout does
 // not depend on the launch shape.  The 9 input vectors of the site are staged
-// once in LDS; all lanes of a wave read the same (or two) LDS addresses per
-// step, which the LDS serves as a broadcast.
+// once in LDS (decoded to the accumulation precision, with the 16-bit link
+// scale of each direction folded in); the first link chunks of every thread
+// are already in flight while the staging loads complete.  All lanes of a wave
+// read the same one or two LDS addresses per step (an LDS broadcast).
+//
+// Precisions (the paper's 16-bit storage exists to relieve bandwidth,
+// Sec. 4 and 7.1):
+//   C128: complex128 links and vectors, FP64 arithmetic;
+//   C64:  complex64 links and vectors, FP32 arithmetic;
+//   H16 / B16: links as FP16 / BF16 pairs with one FP32 scale per (site,
+//         direction block), value = scale * stored; FP32 arithmetic; vectors
+//         either complex64 or 16-bit pairs with one FP32 scale per site
+//         (scale = largest |re| or |im| of the site's N components).
 #include "handles.h"
 
 #include <algorithm>
@@ -29,88 +41,153 @@
 
 namespace qmg {
 
-template <typename R> struct Chunk;
-template <> struct Chunk<double> { using T = double2; static constexpr int cpc = 1; };
-template <> struct Chunk<float> { using T = float4; static constexpr int cpc = 2; };
+// ------------------------------------------------------------ 16-bit codes
+__device__ __forceinline__ uint16_t f32_to_h16(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+__device__ __forceinline__ float h16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+__device__ __forceinline__ uint16_t f32_to_b16(float f) {  // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float b16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
 
-__device__ __forceinline__ const double2* link_src(const double2* X, const double2* Y, int64_t V,
-                                                   int N, int64_t site, int r, int e) {
-    const int d = e / N, c = e - (e / N) * N;
-    return d == 0 ? X + (site * N + r) * N + c : Y + ((((int64_t)(d - 1)) * V + site) * N + r) * N + c;
+enum { FMT_F64 = 0, FMT_F32 = 1, FMT_H16 = 2, FMT_B16 = 3 };
+
+template <int F> struct Fmt;
+template <> struct Fmt<FMT_F64> { using R = double; using C = double2; static constexpr int cpc = 1; };
+template <> struct Fmt<FMT_F32> { using R = float; using C = float4; static constexpr int cpc = 2; };
+template <> struct Fmt<FMT_H16> { using R = float; using C = uint4; static constexpr int cpc = 4; };
+template <> struct Fmt<FMT_B16> { using R = float; using C = uint4; static constexpr int cpc = 4; };
+
+template <int F> __device__ __forceinline__ float dec16(uint16_t v) {
+    return F == FMT_H16 ? h16_to_f32(v) : b16_to_f32(v);
+}
+template <int F> __device__ __forceinline__ uint16_t enc16(float v) {
+    return F == FMT_H16 ? f32_to_h16(v) : f32_to_b16(v);
+}
+template <int F> __device__ __forceinline__ cpx<float> dec_pair(uint32_t w) {
+    return cpx<float>{dec16<F>((uint16_t)(w & 0xffffu)), dec16<F>((uint16_t)(w >> 16))};
+}
+template <int F> __device__ __forceinline__ uint32_t enc_pair(float re, float im) {
+    return (uint32_t)enc16<F>(re) | ((uint32_t)enc16<F>(im) << 16);
 }
 
-__device__ __forceinline__ double2* link_dst(double2* X, double2* Y, int64_t V, int N, int64_t site,
-                                             int r, int e) {
-    const int d = e / N, c = e - (e / N) * N;
-    return d == 0 ? X + (site * N + r) * N + c : Y + ((((int64_t)(d - 1)) * V + site) * N + r) * N + c;
-}
-
-// Canonical complex128 X, Y -> chunked layout.  One thread per chunk.
-__global__ void k_pack_c128(double2* __restrict__ L, const double2* __restrict__ X,
-                            const double2* __restrict__ Y, int64_t V, int N, int J) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= V * J * N) return;
-    const int r = (int)(g % N);
-    const int64_t t = g / N;
-    const int j = (int)(t % J);
-    const int64_t site = t / J;
-    L[g] = *link_src(X, Y, V, N, site, r, j);
-}
-
-__global__ void k_pack_c64(float4* __restrict__ L, const double2* __restrict__ X,
-                           const double2* __restrict__ Y, int64_t V, int N, int J) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= V * J * N) return;
-    const int r = (int)(g % N);
-    const int64_t t = g / N;
-    const int j = (int)(t % J);
-    const int64_t site = t / J;
-    const double2* p = link_src(X, Y, V, N, site, r, 2 * j);
-    L[g] = make_float4((float)p[0].x, (float)p[0].y, (float)p[1].x, (float)p[1].y);
-}
-
-__global__ void k_unpack_c128(const double2* __restrict__ L, double2* __restrict__ X,
-                              double2* __restrict__ Y, int64_t V, int N, int J) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= V * J * N) return;
-    const int r = (int)(g % N);
-    const int64_t t = g / N;
-    const int j = (int)(t % J);
-    const int64_t site = t / J;
-    *link_dst(X, Y, V, N, site, r, j) = L[g];
-}
-
-__global__ void k_unpack_c64(const float4* __restrict__ L, double2* __restrict__ X,
-                             double2* __restrict__ Y, int64_t V, int N, int J) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= V * J * N) return;
-    const int r = (int)(g % N);
-    const int64_t t = g / N;
-    const int j = (int)(t % J);
-    const int64_t site = t / J;
-    double2* p = link_dst(X, Y, V, N, site, r, 2 * j);
-    const float4 a = L[g];
-    p[0] = make_double2(a.x, a.y);
-    p[1] = make_double2(a.z, a.w);
-}
-
+// a += chunk * b[0..cpc)
 __device__ __forceinline__ void chunk_mac(const double2 a, const cpx<double>* b, double& ar, double& ai) {
     cmac(ar, ai, a.x, a.y, b[0].re, b[0].im);
 }
-
 __device__ __forceinline__ void chunk_mac(const float4 a, const cpx<float>* b, float& ar, float& ai) {
     cmac(ar, ai, a.x, a.y, b[0].re, b[0].im);
     cmac(ar, ai, a.z, a.w, b[1].re, b[1].im);
 }
+template <int F>
+__device__ __forceinline__ void chunk_mac16(const uint4 a, const cpx<float>* b, float& ar, float& ai) {
+    const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const cpx<float> v = dec_pair<F>(w[q]);
+        cmac(ar, ai, v.re, v.im, b[q].re, b[q].im);
+    }
+}
+template <int F, typename C, typename R>
+__device__ __forceinline__ void mac(const C a, const cpx<R>* b, R& ar, R& ai) {
+    if constexpr (F == FMT_H16 || F == FMT_B16) chunk_mac16<F>(a, b, ar, ai);
+    else chunk_mac(a, b, ar, ai);
+}
 
-// One work-group = (coarse site, tile of `rows` rows); rows*split threads.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Chunk<R>::T* __restrict__ L,
-                                                        const int* __restrict__ nbr,
-                                                        const cpx<R>* __restrict__ u,
-                                                        cpx<R>* __restrict__ y, int N, int J,
-                                                        int rows, int split, int ntiles) {
-    constexpr int cpc = Chunk<R>::cpc;
+__device__ __forceinline__ const double2* link_src(const double2* X, const double2* Y, int64_t V, int N,
+                                                   int64_t site, int r, int e) {
+    const int d = e / N, c = e - (e / N) * N;
+    return d == 0 ? X + (site * N + r) * N + c : Y + ((((int64_t)(d - 1)) * V + site) * N + r) * N + c;
+}
+__device__ __forceinline__ double2* link_dst(double2* X, double2* Y, int64_t V, int N, int64_t site, int r, int e) {
+    const int d = e / N, c = e - (e / N) * N;
+    return d == 0 ? X + (site * N + r) * N + c : Y + ((((int64_t)(d - 1)) * V + site) * N + r) * N + c;
+}
+
+// ---------------------------------------------------------------- packing
+// Canonical complex128 X, Y -> chunk layout [site][j][row].  One thread per chunk.
+template <int F>
+__global__ void k_pack(typename Fmt<F>::C* __restrict__ L, const float* __restrict__ lscale,
+                       const double2* __restrict__ X, const double2* __restrict__ Y, int64_t V, int N, int J) {
+    constexpr int cpc = Fmt<F>::cpc;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= V * J * N) return;
+    const int r = (int)(g % N);
+    const int64_t t = g / N;
+    const int j = (int)(t % J);
+    const int64_t site = t / J;
+    const double2* p = link_src(X, Y, V, N, site, r, j * cpc);
+    if constexpr (F == FMT_F64) {
+        L[g] = p[0];
+    } else if constexpr (F == FMT_F32) {
+        L[g] = make_float4((float)p[0].x, (float)p[0].y, (float)p[1].x, (float)p[1].y);
+    } else {
+        const float s = lscale[site * 9 + (j * cpc) / N];
+        const float inv = s > 0 ? 1.0f / s : 0.0f;
+        uint4 c;
+        c.x = enc_pair<F>((float)p[0].x * inv, (float)p[0].y * inv);
+        c.y = enc_pair<F>((float)p[1].x * inv, (float)p[1].y * inv);
+        c.z = enc_pair<F>((float)p[2].x * inv, (float)p[2].y * inv);
+        c.w = enc_pair<F>((float)p[3].x * inv, (float)p[3].y * inv);
+        L[g] = c;
+    }
+}
+
+template <int F>
+__global__ void k_unpack(const typename Fmt<F>::C* __restrict__ L, const float* __restrict__ lscale,
+                         double2* __restrict__ X, double2* __restrict__ Y, int64_t V, int N, int J) {
+    constexpr int cpc = Fmt<F>::cpc;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= V * J * N) return;
+    const int r = (int)(g % N);
+    const int64_t t = g / N;
+    const int j = (int)(t % J);
+    const int64_t site = t / J;
+    double2* p = link_dst(X, Y, V, N, site, r, j * cpc);
+    const auto a = L[g];
+    if constexpr (F == FMT_F64) {
+        p[0] = a;
+    } else if constexpr (F == FMT_F32) {
+        p[0] = make_double2(a.x, a.y);
+        p[1] = make_double2(a.z, a.w);
+    } else {
+        const double s = lscale[site * 9 + (j * cpc) / N];
+        const uint32_t w[4] = {a.x, a.y, a.z, a.w};
+        for (int q = 0; q < 4; ++q) {
+            const cpx<float> v = dec_pair<F>(w[q]);
+            p[q] = make_double2(s * v.re, s * v.im);
+        }
+    }
+}
+
+// Per (site, direction block) scale: largest |re| or |im| of the N x N block.
+__global__ __launch_bounds__(256) void k_link_scales(float* __restrict__ lscale, const double2* __restrict__ X,
+                                                     const double2* __restrict__ Y, int64_t V, int N) {
+    __shared__ double red[4];
+    const int64_t site = blockIdx.x / 9;
+    const int d = blockIdx.x % 9;
+    const double2* B = d == 0 ? X + site * N * N : Y + (((int64_t)(d - 1)) * V + site) * N * N;
+    double m = 0;
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) m = fmax(m, fmax(fabs(B[i].x), fabs(B[i].y)));
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) lscale[blockIdx.x] = (float)fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
+// ------------------------------------------------------------------ stencil
+// VF: 0 = vectors in the accumulation precision, else 16-bit pairs (format VF) + per-site scale.
+template <int F, int VF, int PRE>
+__global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C* __restrict__ L,
+                                                        const float* __restrict__ lscale,
+                                                        const int* __restrict__ nbr, const void* __restrict__ uin,
+                                                        const float* __restrict__ uscale, void* __restrict__ yout,
+                                                        float* __restrict__ yscale, int N, int J, int rows, int split,
+                                                        int ntiles) {
+    using R = typename Fmt<F>::R;
+    using C = typename Fmt<F>::C;
+    constexpr int cpc = Fmt<F>::cpc;
     extern __shared__ __align__(16) unsigned char smem[];
     cpx<R>* ul = reinterpret_cast<cpx<R>*>(smem);  // [9N] stacked inputs
     cpx<R>* red = ul + 9 * N;                       // [split][rows] partial sums
@@ -119,55 +196,127 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Chunk<R>:
     const int tile = blockIdx.x - site * ntiles;
     const int t = threadIdx.x;
     const int T = rows * split;
+    const int rl = t % rows;
+    const int s = t / rows;
+    const int r = tile * rows + rl;
+    const int K = J / split;
+    const C* Ls = L + (int64_t)site * J * N + r;
+
+    // first link chunks in flight before the staging barrier
+    C a[PRE];
+#pragma unroll
+    for (int q = 0; q < PRE; ++q)
+        if (q < K) a[q] = Ls[(int64_t)(s + split * q) * N];
 
     for (int idx = t; idx < 9 * N; idx += T) {
         const int d = idx / N;
         const int c = idx - d * N;
         const int src = d == 0 ? site : nbr[site * 8 + d - 1];
-        ul[idx] = u[(int64_t)src * N + c];
+        cpx<R> v;
+        if constexpr (VF == 0) {
+            v = reinterpret_cast<const cpx<R>*>(uin)[(int64_t)src * N + c];
+        } else {
+            v = dec_pair<VF>(reinterpret_cast<const uint32_t*>(uin)[(int64_t)src * N + c]);
+            const float su = uscale[src];
+            v.re *= su;
+            v.im *= su;
+        }
+        if constexpr (F == FMT_H16 || F == FMT_B16) {
+            const float sl = lscale[site * 9 + d];
+            v.re *= sl;
+            v.im *= sl;
+        }
+        ul[idx] = v;
     }
     __syncthreads();
 
-    const int rl = t % rows;
-    const int s = t / rows;
-    const int r = tile * rows + rl;
-    const int K = J / split;
-    const typename Chunk<R>::T* Ls = L + (int64_t)site * J * N + r;
-
     R ar[4] = {0, 0, 0, 0}, ai[4] = {0, 0, 0, 0};
-    int k = 0;
+#pragma unroll
+    for (int q = 0; q < PRE; ++q)
+        if (q < K) mac<F>(a[q], ul + (s + split * q) * cpc, ar[q & 3], ai[q & 3]);
+    int k = PRE;
     for (; k + 4 <= K; k += 4) {
-        typename Chunk<R>::T a[4];
+        C b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[q] = Ls[(int64_t)(s + split * (k + q)) * N];
+        for (int q = 0; q < 4; ++q) b[q] = Ls[(int64_t)(s + split * (k + q)) * N];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) chunk_mac(a[q], ul + (s + split * (k + q)) * cpc, ar[q], ai[q]);
+        for (int q = 0; q < 4; ++q) mac<F>(b[q], ul + (s + split * (k + q)) * cpc, ar[q], ai[q]);
     }
-    for (; k < K; ++k) {
-        const typename Chunk<R>::T a = Ls[(int64_t)(s + split * k) * N];
-        chunk_mac(a, ul + (s + split * k) * cpc, ar[0], ai[0]);
-    }
+    for (; k < K; ++k) mac<F>(Ls[(int64_t)(s + split * k) * N], ul + (s + split * k) * cpc, ar[0], ai[0]);
     R sr = (ar[0] + ar[1]) + (ar[2] + ar[3]);
     R si = (ai[0] + ai[1]) + (ai[2] + ai[3]);
     if (split > 1) {
         red[s * rows + rl] = cpx<R>{sr, si};
         __syncthreads();
-        if (s != 0) return;
-        for (int q = 1; q < split; ++q) {
-            sr += red[q * rows + rl].re;
-            si += red[q * rows + rl].im;
+        if (s == 0)
+            for (int q = 1; q < split; ++q) {
+                sr += red[q * rows + rl].re;
+                si += red[q * rows + rl].im;
+            }
+    }
+    if constexpr (VF == 0) {
+        if (s == 0) reinterpret_cast<cpx<R>*>(yout)[(int64_t)site * N + r] = cpx<R>{sr, si};
+    } else {
+        // per-site output scale: all N rows of the site are in this work-group (ntiles == 1)
+        __syncthreads();
+        float* mx = reinterpret_cast<float*>(red);
+        if (s == 0) mx[rl] = fmaxf(fabsf((float)sr), fabsf((float)si));
+        __syncthreads();
+        if (t == 0) {
+            float m = 0.f;
+            for (int i = 0; i < rows; ++i) m = fmaxf(m, mx[i]);
+            mx[rows] = m;
+            yscale[site] = m;
+        }
+        __syncthreads();
+        if (s == 0) {
+            const float m = mx[rows];
+            const float inv = m > 0 ? 1.0f / m : 0.0f;
+            reinterpret_cast<uint32_t*>(yout)[(int64_t)site * N + r] = enc_pair<VF>((float)sr * inv, (float)si * inv);
         }
     }
-    y[(int64_t)site * N + r] = cpx<R>{sr, si};
 }
 
-static int complex_per_chunk(qmg_prec p) { return p == QMG_C128 ? 1 : 2; }
-static size_t chunk_bytes() { return 16; }
+// -------------------------------------------------------- vector (de)quantise
+template <int VF>
+__global__ __launch_bounds__(64) void k_quantize(const float2* __restrict__ in, uint32_t* __restrict__ out,
+                                                 float* __restrict__ scale, int N) {
+    const int64_t site = blockIdx.x;
+    float m = 0.f;
+    for (int c = threadIdx.x; c < N; c += 64) {
+        const float2 v = in[site * N + c];
+        m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    const float inv = m > 0 ? 1.0f / m : 0.0f;
+    for (int c = threadIdx.x; c < N; c += 64) {
+        const float2 v = in[site * N + c];
+        out[site * N + c] = enc_pair<VF>(v.x * inv, v.y * inv);
+    }
+    if (threadIdx.x == 0) scale[site] = m;
+}
+
+template <int VF>
+__global__ void k_dequantize(const uint32_t* __restrict__ in, const float* __restrict__ scale,
+                             float2* __restrict__ out, int64_t V, int N) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= V * N) return;
+    const cpx<float> v = dec_pair<VF>(in[g]);
+    const float s = scale[g / N];
+    out[g] = make_float2(v.re * s, v.im * s);
+}
+
+// ----------------------------------------------------------------- host side
+static int fmt_of(qmg_prec p) {
+    return p == QMG_C128 ? FMT_F64 : p == QMG_C64 ? FMT_F32 : p == QMG_H16 ? FMT_H16 : FMT_B16;
+}
+static int complex_per_chunk(qmg_prec p) { return p == QMG_C128 ? 1 : p == QMG_C64 ? 2 : 4; }
+static bool is16(qmg_prec p) { return p == QMG_H16 || p == QMG_B16; }
 
 // Built-in launch choice: all rows of a site per work-group; the smallest
 // split (dividing J) that gives at least 2^18 threads in flight while
 // keeping at least 4 chunks per thread; row tiles only when a work-group
-// would exceed 1024 threads.
+// would exceed 1024 threads or the grid is very small.
 static void default_launch(const qmg_coarse_op_s* op, int* rows, int* split) {
     const int J = op->J, N = op->N;
     const int64_t want = (int64_t)1 << 18;
@@ -183,7 +332,7 @@ static void default_launch(const qmg_coarse_op_s* op, int* rows, int* split) {
         if (rt % 2) break;
         rt /= 2;
     }
-    while (rt * best > 1024) {  // N odd multiple: fall back to fewer split lanes
+    while (rt * best > 1024) {
         int s = best - 1;
         while (s > 1 && J % s) --s;
         best = s;
@@ -195,24 +344,50 @@ static void default_launch(const qmg_coarse_op_s* op, int* rows, int* split) {
 static qmg_status validate_launch(const qmg_coarse_op_s* op, int rows, int split) {
     if (rows <= 0 || split <= 0 || op->N % rows || op->J % split || rows * split > 1024)
         return fail(QMG_ERR_ARG,
-                    "coarse launch rows=%d split=%d invalid (need rows | N=%d, split | J=%d, "
-                    "rows*split <= 1024)",
+                    "coarse launch rows=%d split=%d invalid (need rows | N=%d, split | J=%d, rows*split <= 1024)",
                     rows, split, op->N, op->J);
     return QMG_OK;
 }
 
-template <typename R>
-static qmg_status launch_dslash(const qmg_coarse_op_s* op, const void* in, void* out, hipStream_t s) {
-    const int ntiles = op->N / op->rows;
-    const dim3 grid((unsigned)(op->V * ntiles));
-    const dim3 block((unsigned)(op->rows * op->split));
-    const size_t lds = sizeof(cpx<R>) * (9 * op->N + (op->split > 1 ? op->rows * op->split : 0));
-    hipLaunchKernelGGL(k_coarse_dslash<R>, grid, block, lds, s,
-                       reinterpret_cast<const typename Chunk<R>::T*>(op->links), op->nbr,
-                       reinterpret_cast<const cpx<R>*>(in), reinterpret_cast<cpx<R>*>(out), op->N,
-                       op->J, op->rows, op->split, ntiles);
+template <int F, int VF>
+static qmg_status launch_f(const qmg_coarse_op_s* op, int rows, int split, const void* in, const float* in_scale,
+                           void* out, float* out_scale, hipStream_t s) {
+    using R = typename Fmt<F>::R;
+    const int ntiles = op->N / rows;
+    const size_t lds = sizeof(cpx<R>) * (9 * op->N + std::max(rows * split, rows + 1));
+    const dim3 grid((unsigned)(op->V * ntiles)), block((unsigned)(rows * split));
+    const auto* L = reinterpret_cast<const typename Fmt<F>::C*>(op->links);
+    const int K = op->J / split;
+    if (K >= 16)
+        hipLaunchKernelGGL((k_coarse_dslash<F, VF, 16>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale,
+                           out, out_scale, op->N, op->J, rows, split, ntiles);
+    else
+        hipLaunchKernelGGL((k_coarse_dslash<F, VF, 4>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale,
+                           out, out_scale, op->N, op->J, rows, split, ntiles);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
+}
+
+qmg_status coarse_dslash_any(const qmg_coarse_op_s* op, const void* in, const float* in_scale, void* out,
+                             float* out_scale, qmg_prec vprec, hipStream_t s) {
+    int rows = op->rows, split = op->split;
+    const bool v16 = is16(vprec);
+    if (v16 && rows != op->N) {  // per-site output scale needs the whole site in one work-group
+        rows = op->N;
+        while (rows * split > 1024 || op->J % split) --split;
+    }
+    switch (op->storage) {
+        case QMG_C128: return launch_f<FMT_F64, 0>(op, rows, split, in, nullptr, out, nullptr, s);
+        case QMG_C64: return launch_f<FMT_F32, 0>(op, rows, split, in, nullptr, out, nullptr, s);
+        case QMG_H16:
+            if (vprec == QMG_C64) return launch_f<FMT_H16, 0>(op, rows, split, in, nullptr, out, nullptr, s);
+            if (vprec == QMG_H16) return launch_f<FMT_H16, FMT_H16>(op, rows, split, in, in_scale, out, out_scale, s);
+            return launch_f<FMT_H16, FMT_B16>(op, rows, split, in, in_scale, out, out_scale, s);
+        default:
+            if (vprec == QMG_C64) return launch_f<FMT_B16, 0>(op, rows, split, in, nullptr, out, nullptr, s);
+            if (vprec == QMG_H16) return launch_f<FMT_B16, FMT_H16>(op, rows, split, in, in_scale, out, out_scale, s);
+            return launch_f<FMT_B16, FMT_B16>(op, rows, split, in, in_scale, out, out_scale, s);
+    }
 }
 
 }  // namespace qmg
@@ -226,8 +401,10 @@ extern "C" qmg_status qmg_coarse_op_create(const int dims[4], int N, const void*
     QMG_TRY(check_dims(dims, 2, "coarse_op_create"));
     if (N < 2 || N > 128 || (N & 1)) return fail(QMG_ERR_SHAPE, "coarse_op_create: N=%d must be even in [2,128]", N);
     if (!X || !Y) return fail(QMG_ERR_ARG, "coarse_op_create: X or Y is NULL");
-    if (storage != QMG_C128 && storage != QMG_C64)
+    if (storage != QMG_C128 && storage != QMG_C64 && storage != QMG_H16 && storage != QMG_B16)
         return fail(QMG_ERR_PREC, "coarse_op_create: storage %d not supported", (int)storage);
+    if (is16(storage) && N % 4)
+        return fail(QMG_ERR_SHAPE, "coarse_op_create: 16-bit storage needs N %% 4 == 0 (N=%d)", N);
     hipStream_t s = as_stream(stream);
     auto* op = new qmg_coarse_op_s();
     for (int m = 0; m < 4; ++m) op->dims[m] = dims[m];
@@ -235,26 +412,32 @@ extern "C" qmg_status qmg_coarse_op_create(const int dims[4], int N, const void*
     op->N = N;
     op->storage = storage;
     op->J = 9 * N / complex_per_chunk(storage);
-    const size_t bytes = (size_t)op->V * op->J * N * chunk_bytes();
+    const size_t bytes = (size_t)op->V * op->J * N * 16;
     hipError_t e = hipMalloc(&op->links, bytes);
+    if (e == hipSuccess && is16(storage)) e = hipMalloc(&op->lscale, sizeof(float) * op->V * 9);
     if (e != hipSuccess) {
-        delete op;
+        qmg_coarse_op_destroy(op);
         return fail(QMG_ERR_NOMEM, "coarse_op_create: %zu bytes: %s", bytes, hipGetErrorString(e));
     }
     qmg_status st = make_neighbour_table(dims, &op->nbr, s);
     if (st != QMG_OK) {
-        (void)hipFree(op->links);
-        delete op;
+        qmg_coarse_op_destroy(op);
         return st;
     }
     const int64_t total = op->V * op->J * N;
     const unsigned nb = (unsigned)((total + 255) / 256);
-    if (storage == QMG_C128)
-        hipLaunchKernelGGL(k_pack_c128, dim3(nb), dim3(256), 0, s, (double2*)op->links,
-                           (const double2*)X, (const double2*)Y, op->V, N, op->J);
-    else
-        hipLaunchKernelGGL(k_pack_c64, dim3(nb), dim3(256), 0, s, (float4*)op->links,
-                           (const double2*)X, (const double2*)Y, op->V, N, op->J);
+    const double2 *x = (const double2*)X, *y = (const double2*)Y;
+    switch (fmt_of(storage)) {
+        case FMT_F64: hipLaunchKernelGGL(k_pack<FMT_F64>, dim3(nb), dim3(256), 0, s, (double2*)op->links, nullptr, x, y, op->V, N, op->J); break;
+        case FMT_F32: hipLaunchKernelGGL(k_pack<FMT_F32>, dim3(nb), dim3(256), 0, s, (float4*)op->links, nullptr, x, y, op->V, N, op->J); break;
+        case FMT_H16:
+            hipLaunchKernelGGL(k_link_scales, dim3((unsigned)(op->V * 9)), dim3(256), 0, s, op->lscale, x, y, op->V, N);
+            hipLaunchKernelGGL(k_pack<FMT_H16>, dim3(nb), dim3(256), 0, s, (uint4*)op->links, op->lscale, x, y, op->V, N, op->J);
+            break;
+        default:
+            hipLaunchKernelGGL(k_link_scales, dim3((unsigned)(op->V * 9)), dim3(256), 0, s, op->lscale, x, y, op->V, N);
+            hipLaunchKernelGGL(k_pack<FMT_B16>, dim3(nb), dim3(256), 0, s, (uint4*)op->links, op->lscale, x, y, op->V, N, op->J);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) {
         qmg_coarse_op_destroy(op);
@@ -270,26 +453,65 @@ extern "C" qmg_status qmg_coarse_op_export(qmg_coarse_op op, void* X, void* Y, v
     hipStream_t s = as_stream(stream);
     const int64_t total = op->V * op->J * op->N;
     const unsigned nb = (unsigned)((total + 255) / 256);
-    if (op->storage == QMG_C128)
-        hipLaunchKernelGGL(k_unpack_c128, dim3(nb), dim3(256), 0, s, (const double2*)op->links,
-                           (double2*)X, (double2*)Y, op->V, op->N, op->J);
-    else
-        hipLaunchKernelGGL(k_unpack_c64, dim3(nb), dim3(256), 0, s, (const float4*)op->links,
-                           (double2*)X, (double2*)Y, op->V, op->N, op->J);
+    double2 *x = (double2*)X, *y = (double2*)Y;
+    switch (fmt_of(op->storage)) {
+        case FMT_F64: hipLaunchKernelGGL(k_unpack<FMT_F64>, dim3(nb), dim3(256), 0, s, (const double2*)op->links, nullptr, x, y, op->V, op->N, op->J); break;
+        case FMT_F32: hipLaunchKernelGGL(k_unpack<FMT_F32>, dim3(nb), dim3(256), 0, s, (const float4*)op->links, nullptr, x, y, op->V, op->N, op->J); break;
+        case FMT_H16: hipLaunchKernelGGL(k_unpack<FMT_H16>, dim3(nb), dim3(256), 0, s, (const uint4*)op->links, op->lscale, x, y, op->V, op->N, op->J); break;
+        default: hipLaunchKernelGGL(k_unpack<FMT_B16>, dim3(nb), dim3(256), 0, s, (const uint4*)op->links, op->lscale, x, y, op->V, op->N, op->J);
+    }
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
-extern "C" qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_prec prec,
-                                        void* stream) {
+extern "C" qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_prec prec, void* stream) {
     if (!op || !in || !out) return fail(QMG_ERR_ARG, "coarse_dslash: NULL argument");
-    if (prec != op->storage)
-        return fail(QMG_ERR_PREC, "coarse_dslash: vector precision %d != operator storage %d",
-                    (int)prec, (int)op->storage);
+    const bool ok = prec == op->storage || (is16(op->storage) && prec == QMG_C64);
+    if (!ok)
+        return fail(QMG_ERR_PREC, "coarse_dslash: vector precision %d does not fit operator storage %d", (int)prec,
+                    (int)op->storage);
+    if (is16(prec)) return fail(QMG_ERR_PREC, "coarse_dslash: 16-bit vectors go through qmg_coarse_dslash_scaled");
     if (in == out) return fail(QMG_ERR_ARG, "coarse_dslash: in and out alias");
+    return coarse_dslash_any(op, in, nullptr, out, nullptr, prec, as_stream(stream));
+}
+
+extern "C" qmg_status qmg_coarse_dslash_scaled(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                                               float* out_scale, qmg_prec prec, void* stream) {
+    if (!op || !in || !in_scale || !out || !out_scale) return fail(QMG_ERR_ARG, "coarse_dslash_scaled: NULL argument");
+    if (!is16(op->storage) || !is16(prec))
+        return fail(QMG_ERR_PREC, "coarse_dslash_scaled: needs a 16-bit operator and 16-bit vectors");
+    if (in == out || (const void*)in_scale == (void*)out_scale)
+        return fail(QMG_ERR_ARG, "coarse_dslash_scaled: input and output alias");
+    return coarse_dslash_any(op, in, in_scale, out, out_scale, prec, as_stream(stream));
+}
+
+extern "C" qmg_status qmg_quantize_sites(const void* in, void* out, float* scale, long long V, int N, qmg_prec prec,
+                                         void* stream) {
+    if (!in || !out || !scale) return fail(QMG_ERR_ARG, "quantize_sites: NULL argument");
+    if (V < 1 || N < 1) return fail(QMG_ERR_SHAPE, "quantize_sites: V=%lld N=%d", V, N);
+    if (!is16(prec)) return fail(QMG_ERR_PREC, "quantize_sites: precision must be QMG_H16 or QMG_B16");
     hipStream_t s = as_stream(stream);
-    if (op->storage == QMG_C128) return launch_dslash<double>(op, in, out, s);
-    return launch_dslash<float>(op, in, out, s);
+    if (prec == QMG_H16)
+        hipLaunchKernelGGL(k_quantize<FMT_H16>, dim3((unsigned)V), dim3(64), 0, s, (const float2*)in, (uint32_t*)out, scale, N);
+    else
+        hipLaunchKernelGGL(k_quantize<FMT_B16>, dim3((unsigned)V), dim3(64), 0, s, (const float2*)in, (uint32_t*)out, scale, N);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_dequantize_sites(const void* in, const float* scale, void* out, long long V, int N,
+                                           qmg_prec prec, void* stream) {
+    if (!in || !out || !scale) return fail(QMG_ERR_ARG, "dequantize_sites: NULL argument");
+    if (V < 1 || N < 1) return fail(QMG_ERR_SHAPE, "dequantize_sites: V=%lld N=%d", V, N);
+    if (!is16(prec)) return fail(QMG_ERR_PREC, "dequantize_sites: precision must be QMG_H16 or QMG_B16");
+    hipStream_t s = as_stream(stream);
+    const unsigned nb = (unsigned)((V * N + 255) / 256);
+    if (prec == QMG_H16)
+        hipLaunchKernelGGL(k_dequantize<FMT_H16>, dim3(nb), dim3(256), 0, s, (const uint32_t*)in, scale, (float2*)out, (int64_t)V, N);
+    else
+        hipLaunchKernelGGL(k_dequantize<FMT_B16>, dim3(nb), dim3(256), 0, s, (const uint32_t*)in, scale, (float2*)out, (int64_t)V, N);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
 }
 
 extern "C" qmg_status qmg_coarse_op_set_launch(qmg_coarse_op op, int rows, int split) {
@@ -314,6 +536,7 @@ extern "C" qmg_status qmg_coarse_op_get_launch(qmg_coarse_op op, int* rows, int*
 extern "C" void qmg_coarse_op_destroy(qmg_coarse_op op) {
     if (!op) return;
     if (op->links) (void)hipFree(op->links);
+    if (op->lscale) (void)hipFree(op->lscale);
     if (op->nbr) (void)hipFree(op->nbr);
     delete op;
 }

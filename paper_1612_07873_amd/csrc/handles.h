@@ -9,8 +9,9 @@ struct qmg_coarse_op_s {
     int N;
     qmg_prec storage;
     int J;        // 16-byte chunks per 9N-long row
-    void* links;  // [V][J][N] chunks (see coarse_dslash.hip)
-    int* nbr;     // [V][8]
+    void* links;    // [V][J][N] chunks (see coarse_dslash.hip)
+    float* lscale;  // [V][9] scales of the 16-bit storages (X, then Y_0..Y_7), else NULL
+    int* nbr;       // [V][8]
     int rows, split;
 };
 

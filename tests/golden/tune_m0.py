@@ -34,6 +34,8 @@ def main():
     ap.add_argument('--seed', type=int, default=0)
     ap.add_argument('--csw', type=float, default=1.0)
     ap.add_argument('--target', type=float, default=1e-2)
+    ap.add_argument('--tol', type=float, default=1e-2, help='relative eigenvalue tolerance')
+    ap.add_argument('--steps', type=int, default=5, help='golden-section steps')
     ap.add_argument('--out', default=os.path.join(HERE, 'config2_m0.json'))
     args = ap.parse_args()
     dims = tuple(args.dims)
@@ -54,7 +56,7 @@ def main():
 
         op = sla.LinearOperator((V * 12, V * 12), matvec=mv, dtype=np.complex128)
         t = time.time()
-        w, vec = sla.eigsh(op, k=1, which='SA', tol=1e-4, ncv=48, v0=state['v0'])
+        w, vec = sla.eigsh(op, k=1, which='SA', tol=args.tol, ncv=32, v0=state['v0'])
         state['v0'] = vec[:, 0]
         s = float(np.sqrt(max(w[0], 0.0)))
         log.append({'m0': m0, 'sigma_min': s, 'matvecs': cnt[0], 'seconds': round(time.time() - t, 1)})
@@ -63,10 +65,10 @@ def main():
 
     # golden-section search for the minimum of sigma_min over m0 in [-0.6, 0]
     gr = (np.sqrt(5) - 1) / 2
-    a, b = -0.6, 0.0
+    a, b = -0.5, 0.0
     c, d = b - gr * (b - a), a + gr * (b - a)
     fc, fd = sigma_min(c), sigma_min(d)
-    for _ in range(9):
+    for _ in range(args.steps):
         if fc < fd:
             b, d, fd = d, c, fc
             c = b - gr * (b - a)

@@ -1,0 +1,98 @@
+"""The 16-bit storage form of the coarse operator (FP16 / BF16 pairs with FP32
+per-(site, block) link scales and per-site vector scales, FP32 arithmetic).
+
+Two kinds of check:
+  * arithmetic parity: the GPU result equals the FP64 oracle applied to the
+    dequantised links and vector (what the kernel actually multiplies) to FP32
+    rounding (1e-5 relative);
+  * storage error: the result against the oracle on the unrounded FP64 inputs,
+    reported and held under a bound derived from the unit roundoff u of the
+    format (u = 2^-11 FP16, 2^-8 BF16): each input entry carries a relative
+    error of at most u of its block's scale, so the norm-wise error of y stays
+    near u; the bound asserted is 4u (inputs) and 5u with a 16-bit output.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import coarse, lattice, transfer, wilson
+from gpu_util import dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+U_ROUND = {'h16': 2.0 ** -11, 'b16': 2.0 ** -8}
+
+
+def nrm_err(a, ref):
+    return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
+
+
+def galerkin_config1():
+    dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 0)
+    A = wilson.clover_field(U, dims, 1.0)
+    Vb = transfer.block_orthonormalize(synth.gaussian((24, V, 12), 0, 1), dims, block)
+    return coarse.galerkin(coarse.FineParent(U, A, -0.2, dims), Vb, block)
+
+
+def random_op(cd, N, seed):
+    V = lattice.volume(cd)
+    return coarse.CoarseOp(cd, synth.gaussian((V, N, N), seed, 2), synth.gaussian((8, V, N, N), seed + 1, 2))
+
+
+OPS = {'config1_2^4_N48': galerkin_config1, '4^3x8_N48': lambda: random_op((4, 4, 4, 8), 48, 3),
+       '2^3x4_N64': lambda: random_op((2, 2, 2, 4), 64, 5), '8^3x16_N48': lambda: random_op((8, 8, 8, 16), 48, 7)}
+
+
+@pytest.mark.parametrize('name', sorted(OPS))
+@pytest.mark.parametrize('fmt', ['h16', 'b16'])
+def test_sixteen_bit_storage(name, fmt):
+    from paper_1612_07873_amd import CoarseOp, dequantize_sites, quantize_sites
+    op = OPS[name]()
+    V, N = op.X.shape[0], op.N
+    u = synth.gaussian((V, N), 11, 2)
+    ref = op.apply(u)
+    g = CoarseOp(op.dims, dev(op.X), dev(op.Y), fmt)
+    Xq, Yq = (host(t) for t in g.export())
+    ur = U_ROUND[fmt]
+    # stored links: each entry within u of its block's scale
+    sX = np.maximum(np.abs(op.X.real), np.abs(op.X.imag)).max(axis=(1, 2))
+    assert np.all(np.abs(Xq - op.X) <= ur * sX[:, None, None] * (1 + 1e-6))
+    qop = coarse.CoarseOp(op.dims, Xq, Yq)
+
+    # FP32 vectors in and out
+    y = host(g.apply(dev(u, torch.complex64)))
+    e_arith = rel_err(y, qop.apply(u.astype(np.complex64).astype(np.complex128)))
+    e_store = nrm_err(y, ref)
+    # 16-bit vectors in and out
+    uq, us = quantize_sites(dev(u, torch.complex64), fmt)
+    ud = host(dequantize_sites(uq, us, fmt))
+    assert np.all(np.abs(ud - u) <= ur * host(us.to(torch.complex128))[:, None].real * (1 + 1e-6) + 1e-30)
+    yq, ys = g.apply_scaled(uq, us)
+    y16 = host(dequantize_sites(yq, ys, fmt))
+    yexact = qop.apply(ud)
+    e_arith16 = nrm_err(y16, yexact)
+    e_store16 = nrm_err(y16, ref)
+    print('%s %s: arithmetic %.2e / %.2e, storage error %.2e (fp32 vec) %.2e (16-bit vec), u=%.2e'
+          % (name, fmt, e_arith, e_arith16, e_store, e_store16, ur))
+    assert e_arith <= 1e-5
+    assert e_arith16 <= 1.5 * ur                    # only the output rounding remains
+    assert e_store <= 4 * ur
+    assert e_store16 <= 5 * ur
+    # per-site output scale is the largest component
+    ysh = host(ys.to(torch.complex128)).real
+    assert np.allclose(ysh, np.maximum(np.abs(yexact.real), np.abs(yexact.imag)).max(axis=1), rtol=1e-5)
+
+
+def test_zero_vector_and_errors():
+    from paper_1612_07873_amd import CoarseOp, QmgError, quantize_sites
+    op = random_op((2, 2, 2, 2), 48, 1)
+    g = CoarseOp(op.dims, dev(op.X), dev(op.Y), 'h16')
+    z = torch.zeros((16, 48), dtype=torch.complex64, device='cuda')
+    uq, us = quantize_sites(z, 'h16')
+    yq, ys = g.apply_scaled(uq, us)
+    assert float(ys.abs().max()) == 0.0 and int(yq.abs().max()) == 0
+    with pytest.raises(QmgError):
+        CoarseOp((2, 2, 2, 2), dev(op.X[:, :46, :46].copy()), dev(op.Y[:, :, :46, :46].copy()), 'h16')  # N % 4
