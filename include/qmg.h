@@ -17,7 +17,8 @@
  *  - Lattice dims[4] = {L0, L1, L2, L3}; site index i = x0 + L0*(x1 + L1*(x2 +
  *    L2*x3)); dimension 3 is time (the index decomposition of Sec. 6.1).
  *  - Coarse fields are [V][N] (N = 2*Nvec components per site, n = chi*Nvec + k);
- *    multi-RHS coarse fields are [V][N][nrhs] (right-hand side fastest).
+ *    multi-RHS coarse fields are [V][nrhs][N] (each right-hand side's N
+ *    components contiguous within a site).
  *  - Direction d = 2*mu (forward hop, multiplies u(x+mu)) or 2*mu+1 (backward).
  *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
  *    default stream) and is asynchronous unless stated otherwise.
@@ -118,6 +119,23 @@ qmg_status qmg_quantize_sites(const void* in, void* out, float* scale, long long
                               void* stream);
 qmg_status qmg_dequantize_sites(const void* in, const float* scale, void* out, long long V, int N,
                                 qmg_prec prec, void* stream);
+
+/* Apply Eq. (3) to nrhs right-hand sides at once on the matrix cores (the
+ * multi-RHS reformulation of Sec. 9): operator with QMG_H16 / QMG_B16
+ * storage and N in {16, 32, 48, 64}; nrhs in {8, 16, 32, 64}.
+ *   in        DEVICE [V][nrhs][N] 16-bit (re, im) pairs of the operator's format,
+ *   in_scale  DEVICE float [V][nrhs] (value = scale * stored; qmg_quantize_sites
+ *             with V*nrhs "sites" produces both),
+ *   out       DEVICE complex64 [V][nrhs][N].
+ * Products in FP16/BF16 on MFMA, FP32 accumulation.  The first call builds a
+ * second copy of the links in matrix-core operand order (same size as the
+ * 16-bit links). */
+qmg_status qmg_coarse_dslash_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                                  int nrhs, void* stream);
+
+/* Tile shape of the multi-RHS kernel: each wave computes 16 rows x
+ * (16 * rhs_tiles_per_wave) right-hand sides (1, 2 or 4; 0 = built-in). */
+qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, int rhs_tiles_per_wave);
 
 /* Launch shape of the fine-grained stencil (Sec. 6.2-6.4): each work-group
  * covers `rows` output rows of one coarse site (rows divides N), and the

@@ -47,6 +47,15 @@ class CoarseOp:
             y = y + np.einsum('xij,xjr->xir', self.Y[d], u[self.nbr[d]])
         return y.reshape(shp)
 
+    def apply_sites(self, u, sites):
+        """Eq. (3) at the listed coarse sites only; u [Vc][N] or [Vc][N][nrhs]."""
+        sites = np.asarray(sites)
+        u = u.reshape(self.X.shape[0], self.N, -1)
+        y = np.einsum('xij,xjr->xir', self.X[sites], u[sites])
+        for d in range(8):
+            y = y + np.einsum('xij,xjr->xir', self.Y[d][sites], u[self.nbr[d][sites]])
+        return y
+
     def dense(self):
         Vc, N = self.X.shape[0], self.N
         M = np.zeros((Vc, N, Vc, N), dtype=np.complex128)

@@ -71,6 +71,20 @@ class CoarseOp:
                   PREC[vp], stream_ptr())
         return out
 
+    def apply_mrhs(self, u16, uscale, out=None):
+        """Multi-RHS: u16 int32 [V][nrhs][N] packed 16-bit pairs, uscale float32 [V][nrhs];
+        returns complex64 [V][nrhs][N]."""
+        V, nrhs, N = u16.shape
+        if out is None:
+            out = torch.empty((V, nrhs, N), dtype=torch.complex64, device=u16.device)
+        _lib.call('qmg_coarse_dslash_mrhs', self._h, _dev_ptr(u16, torch.int32, (self.V, nrhs, self.N), 'in'),
+                  _dev_ptr(uscale, torch.float32, (self.V, nrhs), 'in_scale'),
+                  _dev_ptr(out, torch.complex64, (self.V, nrhs, self.N), 'out'), int(nrhs), stream_ptr())
+        return out
+
+    def set_mrhs_tiles(self, nrhs, tiles):
+        _lib.call('qmg_coarse_op_set_mrhs_tiles', self._h, int(nrhs), int(tiles))
+
     def apply_scaled(self, u16, uscale, out16=None, oscale=None, vprec=None):
         """16-bit vectors: u16 int32 tensor [V][N] (packed pairs), uscale float32 [V]."""
         vprec = vprec or self.storage

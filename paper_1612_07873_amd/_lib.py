@@ -23,6 +23,8 @@ SIGNATURES = {
     'qmg_coarse_op_export': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_launch': (c_int, [c_void_p, c_int, c_int]),
+    'qmg_coarse_dslash_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_coarse_op_set_mrhs_tiles': (c_int, [c_void_p, c_int, c_int]),
     'qmg_coarse_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_quantize_sites': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, c_void_p]),
     'qmg_dequantize_sites': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, c_void_p]),

@@ -537,6 +537,7 @@ extern "C" void qmg_coarse_op_destroy(qmg_coarse_op op) {
     if (!op) return;
     if (op->links) (void)hipFree(op->links);
     if (op->lscale) (void)hipFree(op->lscale);
+    if (op->mlinks) (void)hipFree(op->mlinks);
     if (op->nbr) (void)hipFree(op->nbr);
     delete op;
 }

@@ -1,0 +1,247 @@
+// Multi-right-hand-side coarse operator on the matrix cores (the multi-RHS
+// reformulation the paper proposes as future work, Sec. 9).
+//
+// Per coarse site, for nrhs right-hand sides at once,
+//     Y(N x nrhs) = sum_{d=0..8} A_d (N x N) * U_d (N x nrhs),
+// A_0 = X(x), A_{1+d} = Y_d(x), U_0 = u(x), U_{1+d} = u(x + hop_d).  With links
+// and vectors in 16-bit form, each complex product is two real products
+// sharing the same B operand: with K running over (column c, re/im),
+//     Re Y = [Ar, -Ai] [Ur; Ui],   Im Y = [Ai, Ar] [Ur; Ui],
+// and both A operands come from the stored (re, im) pairs by flipping the
+// sign bit of the imaginary half or swapping the halves.  The products run on
+// v_mfma_f32_16x16x32_{f16,bf16} with FP32 accumulation; each direction is
+// accumulated separately and then scaled by s_link(x, d) * s_u(x + hop_d, rhs)
+// (the per-(site, block) link scale and per-(site, rhs) vector scale).
+//
+// Work decomposition: one work-group per coarse site; wave w owns row tile
+// w mod (N/16) (16 output rows) and `rpw` tiles of 16 right-hand sides.  The
+// wave's link operands for all nine directions are loaded straight from HBM
+// into registers (the links are repacked once so every wave load is one
+// contiguous 1 KB: [site][d][row tile][k step][lane] x 16 bytes), while the
+// work-group stages the nine input blocks U_d ([nrhs][N] per site, contiguous)
+// and their scales in LDS.  B operands are 16-byte LDS reads.
+//
+// Field layout: u, y [V][nrhs][N] (each right-hand side's N components
+// contiguous within a site); 16-bit u with FP32 scales [V][nrhs]; y complex64.
+#include "handles.h"
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+namespace qmg {
+
+typedef _Float16 h8v __attribute__((ext_vector_type(8)));
+typedef __bf16 b8v __attribute__((ext_vector_type(8)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+enum { MF_H16 = 2, MF_B16 = 3 };
+
+template <int F> __device__ __forceinline__ f4v mfma(uint4 a, uint4 b, f4v c) {
+    if constexpr (F == MF_H16)
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8v, a), __builtin_bit_cast(h8v, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8v, a), __builtin_bit_cast(b8v, b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ uint32_t rot16(uint32_t w) { return (w >> 16) | (w << 16); }
+
+// chunked 16-bit layout [site][j][row] -> MFMA operand layout
+// [site][d][rt][ks][lane]: lane l holds row rt*16 + l%16, complex columns ks*16 + 4*(l/16) + 0..3.
+__global__ void k_pack_mfma(uint4* __restrict__ M, const uint4* __restrict__ L, int64_t V, int N, int J) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int T = N / 16;
+    if (g >= V * 9 * T * T * 64) return;
+    const int l = (int)(g % 64);
+    int64_t t = g / 64;
+    const int ks = (int)(t % T);
+    t /= T;
+    const int rt = (int)(t % T);
+    t /= T;
+    const int d = (int)(t % 9);
+    const int64_t site = t / 9;
+    const int row = rt * 16 + (l % 16);
+    const int e = d * N + ks * 16 + 4 * (l / 16);  // first of 4 complex in the 9N row
+    M[g] = L[(site * J + e / 4) * N + row];
+}
+
+template <int F, int N, int NRHS, int RPW>
+__global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 64) void k_coarse_mrhs(
+    const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
+    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y) {
+    constexpr int T = N / 16;                       // row tiles = k steps per direction
+    constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;  // right-hand-side tiles
+    constexpr int NW = T * (NT / RPW);              // waves per work-group
+    constexpr int UW = NRHS * N;                    // dwords per input block in HBM
+    constexpr int LD = N + 4;                       // LDS row stride (dwords), padded against bank conflicts
+    constexpr int US = NRHS * LD;                   // dwords per staged block
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* Us = reinterpret_cast<uint32_t*>(smem);       // [9][NRHS][LD]
+    float* Sc = reinterpret_cast<float*>(Us + 9 * US);       // [9][NRHS]
+
+    const int site = blockIdx.x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int rt = w % T, tg = w / T;
+    const uint4* Ms = M + ((int64_t)site * 9 * T + rt) * T * 64 + l;
+
+    uint4 Acur[T], Anext[T];
+#pragma unroll
+    for (int ks = 0; ks < T; ++ks) Acur[ks] = Ms[(int64_t)ks * 64];
+
+    // stage the nine input blocks and their scales
+    for (int d = 0; d < 9; ++d) {
+        const int src = d == 0 ? site : nbr[site * 8 + d - 1];
+        const uint4* g = reinterpret_cast<const uint4*>(u + (int64_t)src * UW);
+        for (int i = threadIdx.x; i < UW / 4; i += NW * 64) {
+            const int j = (4 * i) / N, c = (4 * i) % N;
+            *reinterpret_cast<uint4*>(Us + d * US + j * LD + c) = g[i];
+        }
+        const float sl = lscale[(int64_t)site * 9 + d];
+        for (int j = threadIdx.x; j < NRHS; j += NW * 64) Sc[d * NRHS + j] = sl * uscale[(int64_t)src * NRHS + j];
+    }
+    __syncthreads();
+
+    f4v tot[RPW][2];
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) tot[t][0] = tot[t][1] = f4v{0, 0, 0, 0};
+    const int jl = l % 16;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        if (d < 8) {
+#pragma unroll
+            for (int ks = 0; ks < T; ++ks) Anext[ks] = Ms[((int64_t)(d + 1) * T * T + ks) * 64];
+        }
+        f4v acc[RPW][2];
+#pragma unroll
+        for (int t = 0; t < RPW; ++t) acc[t][0] = acc[t][1] = f4v{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < T; ++ks) {
+            const uint4 a = Acur[ks];
+            const uint4 ar = make_uint4(a.x ^ 0x80000000u, a.y ^ 0x80000000u, a.z ^ 0x80000000u, a.w ^ 0x80000000u);
+            const uint4 ai = make_uint4(rot16(a.x), rot16(a.y), rot16(a.z), rot16(a.w));
+#pragma unroll
+            for (int t = 0; t < RPW; ++t) {
+                const int j = (tg * RPW + t) * 16 + jl;
+                uint4 b = make_uint4(0, 0, 0, 0);
+                if (NRHS >= 16 || j < NRHS)
+                    b = *reinterpret_cast<const uint4*>(Us + d * US + j * LD + ks * 16 + 4 * (l / 16));
+                acc[t][0] = mfma<F>(ar, b, acc[t][0]);
+                acc[t][1] = mfma<F>(ai, b, acc[t][1]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < RPW; ++t) {
+            const int j = (tg * RPW + t) * 16 + jl;
+            const float s = (NRHS >= 16 || j < NRHS) ? Sc[d * NRHS + j] : 0.0f;
+            tot[t][0] += s * acc[t][0];
+            tot[t][1] += s * acc[t][1];
+        }
+        if (d < 8) {
+#pragma unroll
+            for (int ks = 0; ks < T; ++ks) Acur[ks] = Anext[ks];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RPW; ++t) {
+        const int j = (tg * RPW + t) * 16 + jl;
+        if (NRHS < 16 && j >= NRHS) continue;
+        float2* o = y + ((int64_t)site * NRHS + j) * N + rt * 16 + 4 * (l / 16);
+        float4* o4 = reinterpret_cast<float4*>(o);
+        o4[0] = make_float4(tot[t][0][0], tot[t][1][0], tot[t][0][1], tot[t][1][1]);
+        o4[1] = make_float4(tot[t][0][2], tot[t][1][2], tot[t][0][3], tot[t][1][3]);
+    }
+}
+
+template <int F, int N, int NRHS, int RPW>
+static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const float* sc, void* out, hipStream_t s) {
+    constexpr int T = N / 16;
+    constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
+    constexpr int NW = T * (NT / RPW);
+    const size_t lds = 9 * (size_t)NRHS * (N + 4) * 4 + 9 * NRHS * 4;
+    auto kern = k_coarse_mrhs<F, N, NRHS, RPW>;
+    if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)op->V), dim3(NW * 64), lds, s, (const uint4*)op->mlinks, op->lscale, op->nbr,
+                       (const uint32_t*)in, sc, (float2*)out);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+template <int F, int N, int NRHS>
+static qmg_status launch_rpw(const qmg_coarse_op_s* op, int rpw, const void* in, const float* sc, void* out, hipStream_t s) {
+    constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
+    if (rpw == 1) return launch_mrhs_t<F, N, NRHS, 1>(op, in, sc, out, s);
+    if constexpr (NT >= 2) if (rpw == 2) return launch_mrhs_t<F, N, NRHS, 2>(op, in, sc, out, s);
+    if constexpr (NT >= 4) if (rpw == 4) return launch_mrhs_t<F, N, NRHS, 4>(op, in, sc, out, s);
+    return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: rpw %d not available for nrhs %d", rpw, NRHS);
+}
+
+template <int F, int N>
+static qmg_status launch_n(const qmg_coarse_op_s* op, int nrhs, int rpw, const void* in, const float* sc, void* out,
+                           hipStream_t s) {
+    switch (nrhs) {
+        case 8: return launch_rpw<F, N, 8>(op, rpw, in, sc, out, s);
+        case 16: return launch_rpw<F, N, 16>(op, rpw, in, sc, out, s);
+        case 32: return launch_rpw<F, N, 32>(op, rpw, in, sc, out, s);
+        case 64: return launch_rpw<F, N, 64>(op, rpw, in, sc, out, s);
+    }
+    return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: nrhs %d not in {8,16,32,64}", nrhs);
+}
+
+static int log2i(int n) { int k = 0; while ((1 << k) < n) ++k; return k; }
+
+static int max_rpw(int nrhs) { return nrhs >= 64 ? 4 : nrhs >= 32 ? 2 : 1; }
+
+static int default_rpw(const qmg_coarse_op_s* op, int nrhs) {
+    // enough waves per work-group to keep several link loads in flight per SIMD,
+    // at most 16 waves; the autotuner refines this
+    const int T = op->N / 16, NT = nrhs >= 16 ? nrhs / 16 : 1;
+    int rpw = 1;
+    while (T * (NT / rpw) > 16 && rpw < max_rpw(nrhs)) rpw *= 2;
+    return rpw;
+}
+
+qmg_status coarse_mrhs(qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int nrhs, int rpw,
+                       hipStream_t s) {
+    if (!op->mlinks) {
+        const int T = op->N / 16;
+        const int64_t n = op->V * 9 * T * T * 64;
+        QMG_HIP(hipMalloc(&op->mlinks, (size_t)n * 16));
+        hipLaunchKernelGGL(k_pack_mfma, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint4*)op->mlinks,
+                           (const uint4*)op->links, op->V, op->N, op->J);
+        QMG_LAUNCH_CHECK();
+    }
+    if (rpw <= 0) rpw = op->rpw[log2i(nrhs)] > 0 ? op->rpw[log2i(nrhs)] : default_rpw(op, nrhs);
+    const bool h = op->storage == QMG_H16;
+    if (op->N == 48) return h ? launch_n<MF_H16, 48>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 48>(op, nrhs, rpw, in, sc, out, s);
+    if (op->N == 64) return h ? launch_n<MF_H16, 64>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 64>(op, nrhs, rpw, in, sc, out, s);
+    if (op->N == 32) return h ? launch_n<MF_H16, 32>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 32>(op, nrhs, rpw, in, sc, out, s);
+    if (op->N == 16) return h ? launch_n<MF_H16, 16>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 16>(op, nrhs, rpw, in, sc, out, s);
+    return fail(QMG_ERR_SHAPE, "coarse_dslash_mrhs: N=%d not in {16,32,48,64}", op->N);
+}
+
+}  // namespace qmg
+
+using namespace qmg;
+
+extern "C" qmg_status qmg_coarse_dslash_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                                             int nrhs, void* stream) {
+    if (!op || !in || !in_scale || !out) return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: NULL argument");
+    if (op->storage != QMG_H16 && op->storage != QMG_B16)
+        return fail(QMG_ERR_PREC, "coarse_dslash_mrhs: needs an operator with 16-bit storage");
+    if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
+        return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: nrhs %d not in {8,16,32,64}", nrhs);
+    if (op->N % 16 || op->N > 64) return fail(QMG_ERR_SHAPE, "coarse_dslash_mrhs: N=%d must be 16, 32, 48 or 64", op->N);
+    if (in == out) return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: in and out alias");
+    return coarse_mrhs(op, in, in_scale, out, nrhs, 0, as_stream(stream));
+}
+
+extern "C" qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, int rhs_tiles_per_wave) {
+    if (!op) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: NULL op");
+    if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
+        return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: nrhs %d not in {8,16,32,64}", nrhs);
+    const int r = rhs_tiles_per_wave;
+    if (r != 0 && r != 1 && r != 2 && r != 4) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: tiles %d not in {0,1,2,4}", r);
+    if (r > max_rpw(nrhs)) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: %d tiles exceed nrhs %d", r, nrhs);
+    op->rpw[log2i(nrhs)] = r;
+    return QMG_OK;
+}

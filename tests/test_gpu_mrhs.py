@@ -1,0 +1,85 @@
+"""Multi-RHS coarse operator on the matrix cores: parity against the oracle's
+Eq. (3) applied column by column to the dequantised links and vectors (FP16
+products are exact in FP32, so only the accumulation order differs: 1e-5), and
+against nrhs separate applications of the single-RHS 16-bit kernel."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import coarse, lattice
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+def run_case(cd, N, nrhs, fmt, tiles=None, seed=0):
+    from paper_1612_07873_amd import CoarseOp, dequantize_sites, quantize_sites
+    V = lattice.volume(cd)
+    X = synth.gaussian((V, N, N), seed, 2)
+    Y = synth.gaussian((8, V, N, N), seed + 1, 2)
+    g = CoarseOp(cd, dev(X), dev(Y), fmt)
+    Xq, Yq = (host(t) for t in g.export())
+    # nrhs right-hand sides with seeds 0..nrhs-1, layout [V][nrhs][N]
+    u = np.stack([synth.gaussian((V, N), j, 2) for j in range(nrhs)], axis=1)
+    uq, us = quantize_sites(dev(u.reshape(V * nrhs, N), torch.complex64), fmt)
+    ud = host(dequantize_sites(uq, us, fmt)).reshape(V, nrhs, N)
+    if tiles is not None:
+        g.set_mrhs_tiles(nrhs, tiles)
+    y = host(g.apply_mrhs(uq.reshape(V, nrhs, N), us.reshape(V, nrhs)))
+    qop = coarse.CoarseOp(cd, Xq, Yq)
+    # the oracle one site at a time on a sample of at most 64 sites (all on small lattices)
+    sites = np.arange(V) if V <= 64 else np.random.default_rng(seed).choice(V, 64, replace=False)
+    ref = qop.apply_sites(np.ascontiguousarray(np.transpose(ud, (0, 2, 1))), sites)   # [s][N][nrhs]
+    ref = np.transpose(ref, (0, 2, 1))
+    ys = y[sites]
+    err = float(np.linalg.norm(ys - ref) / np.linalg.norm(ref))
+    emax = float(np.abs(ys - ref).max() / np.abs(ref).max())
+    return err, emax, g, uq, us, y
+
+
+@pytest.mark.parametrize('cd,N', [((4, 4, 4, 8), 64), ((8, 8, 8, 16), 48), ((2, 2, 2, 2), 48)])
+@pytest.mark.parametrize('nrhs', [8, 16, 32, 64])
+def test_mrhs_parity(cd, N, nrhs):
+    for fmt in ('h16', 'b16'):
+        err, emax, *_ = run_case(cd, N, nrhs, fmt)
+        print('%s N%d nrhs %d %s: rel err %.2e (max %.2e)' % (cd, N, nrhs, fmt, err, emax))
+        assert emax <= 1e-5
+
+
+@pytest.mark.parametrize('tiles', [1, 2, 4])
+def test_every_tile_shape(tiles):
+    err, emax, *_ = run_case((2, 2, 2, 4), 64, 64, 'h16', tiles=tiles, seed=3)
+    assert emax <= 1e-5
+
+
+def test_mrhs_equals_single_rhs_kernel():
+    """Column j of the batched result equals the single-RHS 16-bit kernel on
+    column j with FP32 vectors holding the same dequantised values."""
+    from paper_1612_07873_amd import dequantize_sites
+    cd, N, nrhs = (2, 2, 2, 4), 48, 16
+    V = lattice.volume(cd)
+    err, emax, g, uq, us, y = run_case(cd, N, nrhs, 'h16', seed=5)
+    ud = dequantize_sites(uq, us, 'h16').reshape(V, nrhs, N)
+    for j in (0, 7, 15):
+        yj = host(g.apply(ud[:, j, :].contiguous()))
+        assert np.abs(yj - y[:, j, :]).max() <= 1e-5 * np.abs(yj).max()
+
+
+def test_mrhs_rejects_bad_arguments():
+    from paper_1612_07873_amd import CoarseOp, QmgError
+    cd, N = (2, 2, 2, 2), 48
+    V = 16
+    X = synth.gaussian((V, N, N), 0, 2)
+    Y = synth.gaussian((8, V, N, N), 1, 2)
+    g32 = CoarseOp(cd, dev(X), dev(Y), 'c64')
+    u = torch.zeros((V, 8, N), dtype=torch.int32, device='cuda')
+    s = torch.ones((V, 8), dtype=torch.float32, device='cuda')
+    with pytest.raises(QmgError):
+        g32.apply_mrhs(u, s)                      # FP32 operator
+    g16 = CoarseOp(cd, dev(X), dev(Y), 'h16')
+    u12 = torch.zeros((V, 12, N), dtype=torch.int32, device='cuda')
+    with pytest.raises(QmgError):
+        g16.apply_mrhs(u12, torch.ones((V, 12), dtype=torch.float32, device='cuda'))   # nrhs 12
+    with pytest.raises(QmgError):
+        g16.set_mrhs_tiles(16, 2)                 # only one 16-wide tile at nrhs 16

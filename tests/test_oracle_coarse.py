@@ -213,3 +213,12 @@ def test_multi_rhs_apply_equals_columnwise_apply():
     y = op.apply(u)
     for r in range(5):
         assert np.abs(y[:, :, r] - op.apply(u[:, :, r].copy())).max() < 1e-14
+
+
+def test_apply_at_sampled_sites_equals_full_apply():
+    cd = (2, 4, 2, 4)
+    Vc, N = lattice.volume(cd), 6
+    op = coarse.CoarseOp(cd, synth.gaussian((Vc, N, N), 3, 2), synth.gaussian((8, Vc, N, N), 4, 2))
+    u = synth.gaussian((Vc, N, 3), 5, 2)
+    sites = [0, 5, 17, 63]
+    assert np.abs(op.apply_sites(u, sites) - op.apply(u)[sites]).max() < 1e-14
