@@ -1,0 +1,95 @@
+"""Pins of the oracle's parallel-transport convolution smoother: exact
+reduction to the Wilson operator, gauge equivariance, adjointness of the
+transports, and central finite differences of the loss gradients."""
+import numpy as np
+
+import synth
+from oracle import lattice, ptc, wilson
+from oracle_helpers import gauge_rotate
+
+
+def setup(dims=(4, 2, 2, 4), seed=0):
+    U = synth.gauge_field(dims, 0.5, seed)
+    return U, lattice.volume(dims)
+
+
+def test_one_layer_with_wilson_weights_is_the_wilson_operator():
+    """W_0 = (4+m0) 1, W_{+mu} = -1/2 (1-gamma_mu), W_{-mu} = -1/2 (1+gamma_mu)
+    gives M at c_sw = 0 exactly."""
+    dims = (4, 4, 2, 4)
+    U, V = setup(dims, 1)
+    m0 = -0.3
+    Pm, Pp = lattice.projectors()
+    W = np.zeros((9, 1, 1, 4, 4), dtype=np.complex128)
+    W[0, 0, 0] = (4 + m0) * np.eye(4)
+    for mu in range(4):
+        W[1 + 2 * mu, 0, 0] = -0.5 * Pm[mu]
+        W[2 + 2 * mu, 0, 0] = -0.5 * Pp[mu]
+    r = synth.gaussian((V, 4, 3), 2, 2)
+    y = ptc.layer(W, r[None], U, dims)[0]
+    assert np.abs(y - wilson.apply_wilson_clover(r, U, None, m0, dims)).max() < 1e-13
+    # W_0 = alpha 1 alone scales
+    W2 = np.zeros_like(W)
+    W2[0, 0, 0] = (0.7 - 0.2j) * np.eye(4)
+    assert np.abs(ptc.layer(W2, r[None], U, dims)[0] - (0.7 - 0.2j) * r).max() < 1e-15
+
+
+def test_transport_adjoint_and_gauge_equivariance():
+    dims = (4, 2, 4, 2)
+    U, V = setup(dims, 2)
+    a = synth.gaussian((V, 4, 3), 3, 2)
+    b = synth.gaussian((V, 4, 3), 4, 2)
+    for p in range(9):
+        lhs = np.vdot(a, ptc.transport(b, U, dims, p))
+        rhs = np.vdot(ptc.transport(a, U, dims, ptc.reverse(p)), b)
+        assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    # network equivariance: N[gU](g r) = g N[U](r)
+    Ws = [synth.gaussian((9, 3, 1, 4, 4), 5, 4), synth.gaussian((9, 1, 3, 4, 4), 6, 4)]
+    g = synth.gauge_rotation(dims, 7)
+    Ug = gauge_rotate(U, g, dims)
+    rot = lambda h: np.einsum('xab,xsb->xsa', g, h)
+    y1, _ = ptc.forward(Ws, rot(a), Ug, dims)
+    y0, _ = ptc.forward(Ws, a, U, dims)
+    assert np.abs(y1 - rot(y0)).max() < 1e-12 * np.abs(y0).max()
+
+
+def test_gradients_match_central_finite_differences():
+    dims = (2, 2, 2, 4)
+    U, V = setup(dims, 3)
+    Ws = [0.3 * synth.gaussian((9, 2, 1, 4, 4), 8, 4), 0.3 * synth.gaussian((9, 1, 2, 4, 4), 9, 4)]
+    pairs = [(synth.gaussian((V, 4, 3), 10 + i, 2), synth.gaussian((V, 4, 3), 20 + i, 2)) for i in range(2)]
+    L, Gs = ptc.loss_and_grads(Ws, pairs, U, dims)
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for l in range(2):
+        for _ in range(12):
+            idx = tuple(int(rng.integers(0, s)) for s in Ws[l].shape)
+            num = 0j
+            for unit in (1.0, 1j):
+                Wp = [w.copy() for w in Ws]
+                Wm = [w.copy() for w in Ws]
+                Wp[l][idx] += h * unit
+                Wm[l][idx] -= h * unit
+                Lp, _ = ptc.loss_and_grads(Wp, pairs, U, dims)
+                Lm, _ = ptc.loss_and_grads(Wm, pairs, U, dims)
+                num += unit * (Lp - Lm) / (2 * h)
+            assert abs(num - Gs[l][idx]) <= 1e-6 * max(1.0, abs(Gs[l][idx])), (l, idx, num, Gs[l][idx])
+
+
+def test_adam_decreases_the_loss():
+    dims = (2, 2, 2, 4)
+    U, V = setup(dims, 4)
+    from oracle import wilson as w
+    # pairs from the Wilson operator: e Gaussian, r = M e
+    pairs = []
+    for i in range(4):
+        e = synth.gaussian((V, 4, 3), 30 + i, 4)
+        pairs.append((w.apply_wilson_clover(e, U, None, 0.2, dims), e))
+    Ws = [0.1 * synth.gaussian((9, 2, 1, 4, 4), 1, 4), 0.1 * synth.gaussian((9, 1, 2, 4, 4), 2, 4)]
+    opt = ptc.Adam([W.shape for W in Ws], lr=1e-2)
+    L0, _ = ptc.loss_and_grads(Ws, pairs, U, dims)
+    for _ in range(30):
+        L, G = ptc.loss_and_grads(Ws, pairs, U, dims)
+        Ws = opt.step(Ws, G)
+    L1, _ = ptc.loss_and_grads(Ws, pairs, U, dims)
+    assert L1 < 0.5 * L0
