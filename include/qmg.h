@@ -59,6 +59,7 @@ typedef struct qmg_coarse_op_s* qmg_coarse_op;
 typedef struct qmg_fine_op_s* qmg_fine_op;
 typedef struct qmg_transfer_s* qmg_transfer;
 typedef struct qmg_mg_s* qmg_mg;
+typedef struct qmg_ptc_s* qmg_ptc;
 
 /* Message describing the most recent failure on this host thread. */
 const char* qmg_last_error(void);
@@ -257,6 +258,7 @@ typedef struct {
     int converged;
     double true_rel_residual; /* |b - M x| / |b| from the FP64 operator */
     double seconds;           /* host wall time of the solve */
+    int smoother_fallbacks;   /* learned-smoother applications replaced by MR */
 } qmg_solve_info;
 
 /* Build the hierarchy on DEVICE gauge [4][V][3][3] complex128 (as in
@@ -286,6 +288,56 @@ qmg_status qmg_mg_level(qmg_mg mg, int level, int dims[4], int* dof, qmg_coarse_
 qmg_status qmg_mg_fine_op(qmg_mg mg, qmg_fine_op* fine64);
 
 void qmg_mg_destroy(qmg_mg mg);
+
+/* ---------------------------------------------------------------------------
+ * Learned smoother: a gauge-equivariant parallel-transport convolution
+ * network, two linear layers 1 -> hidden -> 1 channels (the paper's smoother
+ * is MR, Sec. 7.1; this network replaces it, with MR as the fallback):
+ *   (T_0 h)(x) = h(x), (T_{+mu} h)(x) = U_mu(x) h(x+mu), (T_{-mu} h)(x) = U_mu(x-mu)^+ h(x-mu)
+ *   (with the operator's time boundary sign), paths p = 0, 1+2mu (+mu), 2+2mu (-mu);
+ *   h'_a(x) = sum_b sum_p W[p][a][b] (T_p h_b)(x), W[p][a][b] complex 4x4 on spin;
+ *   loss L = sum_i |N(r_i) - e_i|^2 / |e_i|^2.
+ * Weights W1 [9][hidden][1][4][4], W2 [9][1][hidden][4][4] complex64 (DEVICE).
+ * Fields r, e, y are DEVICE complex64 [V][4][3].
+ * ------------------------------------------------------------------------- */
+
+/* Network on the lattice of `links` (a complex64-storage fine operator,
+ * borrowed: it must outlive the network), 1 <= hidden <= 16; weights start at 0. */
+qmg_status qmg_ptc_create(qmg_fine_op links, int hidden, void* stream, qmg_ptc* out);
+/* Copy weights in (resets the Adam state) or out. */
+qmg_status qmg_ptc_set_weights(qmg_ptc net, const void* W1, const void* W2, void* stream);
+qmg_status qmg_ptc_get_weights(qmg_ptc net, void* W1, void* W2, void* stream);
+/* y = N(r); r and y must not overlap. */
+qmg_status qmg_ptc_forward(qmg_ptc net, const void* r, void* y, void* stream);
+/* Add the loss |N(r) - e|^2/|e|^2 of one pair and its gradients
+ * G = dL/dRe W + i dL/dIm W to the network's accumulators. */
+qmg_status qmg_ptc_accumulate_grad(qmg_ptc net, const void* r, const void* e, void* stream);
+/* Clear the gradient and loss accumulators. */
+qmg_status qmg_ptc_zero_grad(qmg_ptc net, void* stream);
+/* Copy the accumulated gradients (DEVICE, same shapes as the weights) and the
+ * accumulated loss (host double); blocks. */
+qmg_status qmg_ptc_get_grad(qmg_ptc net, void* G1, void* G2, double* loss, void* stream);
+/* One Adam step on the real and imaginary parts with the accumulated gradients. */
+qmg_status qmg_ptc_adam_step(qmg_ptc net, float lr, float beta1, float beta2, float eps, void* stream);
+void qmg_ptc_destroy(qmg_ptc net);
+
+/* Use `net` (NULL: MR) as the level-0 smoother of an FP32-inner hierarchy.
+ * Each application keeps the network's result only if |r - M N(r)| < |r|;
+ * otherwise that application uses MR (counted in smoother_fallbacks).  The
+ * network is borrowed and must outlive its use. */
+qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net);
+
+/* As qmg_mg_gcr_solve, and also copy the iterate x_k after each of the first
+ * maxrec outer steps into xhist (DEVICE complex128 [maxrec][V][4][3]);
+ * *nrec (host) receives the number recorded. */
+qmg_status qmg_mg_gcr_solve_record(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
+                                   qmg_solve_info* info, void* xhist, int maxrec, int* nrec, void* stream);
+
+/* Training pairs from recorded iterates: e_k = x* - x_k (computed in FP64),
+ * r_k = M e_k (FP64 operator), both written as complex64 [n][V][4][3]
+ * (r_out, e_out DEVICE). */
+qmg_status qmg_mg_make_pairs(qmg_mg mg, const void* xstar, const void* xhist, int n, void* r_out, void* e_out,
+                             void* stream);
 
 #ifdef __cplusplus
 }

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
@@ -279,12 +279,45 @@ class Multigrid:
         st = _lib.lib().qmg_mg_gcr_solve(self._h, _dev_ptr(b, torch.complex128, (self.V, 4, 3), 'b'),
                                          _dev_ptr(x, torch.complex128, (self.V, 4, 3), 'x'),
                                          ctypes.byref(sp), ctypes.byref(info), stream_ptr())
-        out = {'outer_iters': info.outer_iters, 'level_iters': list(info.level_iters)[:self.nlevels],
-               'restarts': info.restarts, 'converged': bool(info.converged),
-               'true_rel_residual': info.true_rel_residual, 'seconds': info.seconds, 'status': st}
+        out = self._info(info, st)
         if check:
             _lib.check(st, 'qmg_mg_gcr_solve')
         return x, out
+
+    def _info(self, info, st):
+        return {'outer_iters': info.outer_iters, 'level_iters': list(info.level_iters)[:self.nlevels],
+                'restarts': info.restarts, 'converged': bool(info.converged),
+                'true_rel_residual': info.true_rel_residual, 'seconds': info.seconds,
+                'smoother_fallbacks': info.smoother_fallbacks, 'status': st}
+
+    def solve_record(self, b, maxrec, tol=1e-10, maxit=500):
+        """Solve and keep the outer iterates x_1..x_n (complex128 [n][V][4][3])."""
+        x = torch.empty_like(b)
+        hist = torch.empty((maxrec, self.V, 4, 3), dtype=torch.complex128, device=b.device)
+        sp = _lib.SolveParams(tol=float(tol), restart=10, maxit=int(maxit))
+        info = _lib.SolveInfo()
+        n = ctypes.c_int()
+        st = _lib.lib().qmg_mg_gcr_solve_record(self._h, _dev_ptr(b, torch.complex128, (self.V, 4, 3), 'b'),
+                                                _dev_ptr(x, torch.complex128, (self.V, 4, 3), 'x'),
+                                                ctypes.byref(sp), ctypes.byref(info),
+                                                ctypes.c_void_p(hist.data_ptr()), int(maxrec), ctypes.byref(n),
+                                                stream_ptr())
+        _lib.check(st, 'qmg_mg_gcr_solve_record')
+        return x, hist[:n.value], self._info(info, st)
+
+    def make_pairs(self, xstar, hist):
+        """(r_k, e_k) = (M (x* - x_k), x* - x_k) as complex64 [n][V][4][3] each."""
+        n = hist.shape[0]
+        r = torch.empty((n, self.V, 4, 3), dtype=torch.complex64, device=xstar.device)
+        e = torch.empty_like(r)
+        _lib.call('qmg_mg_make_pairs', self._h, _dev_ptr(xstar, torch.complex128, (self.V, 4, 3), 'xstar'),
+                  _dev_ptr(hist, torch.complex128, (n, self.V, 4, 3), 'hist'), int(n),
+                  ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(e.data_ptr()), stream_ptr())
+        return r, e
+
+    def set_smoother(self, net):
+        _lib.call('qmg_mg_set_smoother', self._h, net._h if net is not None else None)
+        self._smoother = net
 
     def level(self, l):
         d = _lib.c_dims()
@@ -325,3 +358,66 @@ def dequantize_sites(q, sc, prec='h16'):
               _dev_ptr(sc, torch.float32, (V,), 'scale'), ctypes.c_void_p(out.data_ptr()), V, N, PREC[prec],
               stream_ptr())
     return out
+
+
+class PTC:
+    """Learned parallel-transport convolution smoother (qmg_ptc_*).  `fine` must be a
+    complex64-storage FineOp on the same lattice; it is kept alive by this object."""
+
+    def __init__(self, fine, hidden=8):
+        if fine.storage != 'c64':
+            raise ValueError('PTC needs a complex64 FineOp')
+        self.fine = fine
+        self.C = int(hidden)
+        self.V = fine.V
+        h = ctypes.c_void_p()
+        _lib.call('qmg_ptc_create', fine._h, self.C, stream_ptr(), ctypes.byref(h))
+        self._h = h
+
+    def wshapes(self):
+        return (9, self.C, 1, 4, 4), (9, 1, self.C, 4, 4)
+
+    def set_weights(self, W1, W2):
+        s1, s2 = self.wshapes()
+        _lib.call('qmg_ptc_set_weights', self._h, _dev_ptr(W1, torch.complex64, s1, 'W1'),
+                  _dev_ptr(W2, torch.complex64, s2, 'W2'), stream_ptr())
+
+    def weights(self):
+        s1, s2 = self.wshapes()
+        W1 = torch.empty(s1, dtype=torch.complex64, device='cuda')
+        W2 = torch.empty(s2, dtype=torch.complex64, device='cuda')
+        _lib.call('qmg_ptc_get_weights', self._h, ctypes.c_void_p(W1.data_ptr()), ctypes.c_void_p(W2.data_ptr()),
+                  stream_ptr())
+        return W1, W2
+
+    def forward(self, r, y=None):
+        if y is None:
+            y = torch.empty_like(r)
+        _lib.call('qmg_ptc_forward', self._h, _dev_ptr(r, torch.complex64, (self.V, 4, 3), 'r'),
+                  _dev_ptr(y, torch.complex64, (self.V, 4, 3), 'y'), stream_ptr())
+        return y
+
+    def zero_grad(self):
+        _lib.call('qmg_ptc_zero_grad', self._h, stream_ptr())
+
+    def accumulate(self, r, e):
+        _lib.call('qmg_ptc_accumulate_grad', self._h, _dev_ptr(r, torch.complex64, (self.V, 4, 3), 'r'),
+                  _dev_ptr(e, torch.complex64, (self.V, 4, 3), 'e'), stream_ptr())
+
+    def grad(self):
+        s1, s2 = self.wshapes()
+        G1 = torch.empty(s1, dtype=torch.complex64, device='cuda')
+        G2 = torch.empty(s2, dtype=torch.complex64, device='cuda')
+        loss = ctypes.c_double()
+        _lib.call('qmg_ptc_get_grad', self._h, ctypes.c_void_p(G1.data_ptr()), ctypes.c_void_p(G2.data_ptr()),
+                  ctypes.byref(loss), stream_ptr())
+        return G1, G2, loss.value
+
+    def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+        _lib.call('qmg_ptc_adam_step', self._h, float(lr), float(beta1), float(beta2), float(eps), stream_ptr())
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.qmg_ptc_destroy(h)
+            self._h = None

@@ -58,7 +58,7 @@ class SolveParams(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [('outer_iters', c_int), ('level_iters', c_int * 4), ('restarts', c_int), ('converged', c_int),
-                ('true_rel_residual', c_double), ('seconds', c_double)]
+                ('true_rel_residual', c_double), ('seconds', c_double), ('smoother_fallbacks', c_int)]
 
 
 SIGNATURES.update({
@@ -69,6 +69,19 @@ SIGNATURES.update({
     'qmg_mg_level': (c_int, [c_void_p, c_int, c_int_p, c_int_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     'qmg_mg_fine_op': (c_int, [c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_destroy': (None, [c_void_p]),
+    'qmg_mg_set_smoother': (c_int, [c_void_p, c_void_p]),
+    'qmg_mg_gcr_solve_record': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
+                                        ctypes.POINTER(SolveInfo), c_void_p, c_int, c_int_p, c_void_p]),
+    'qmg_mg_make_pairs': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]),
+    'qmg_ptc_create': (c_int, [c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_ptc_set_weights': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    'qmg_ptc_get_weights': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    'qmg_ptc_forward': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    'qmg_ptc_accumulate_grad': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    'qmg_ptc_zero_grad': (c_int, [c_void_p, c_void_p]),
+    'qmg_ptc_get_grad': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]),
+    'qmg_ptc_adam_step': (c_int, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
+    'qmg_ptc_destroy': (None, [c_void_p]),
 })
 
 _lib = None

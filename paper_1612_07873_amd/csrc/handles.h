@@ -39,6 +39,22 @@ struct qmg_transfer_s {
     int* owner;        // [V]
 };
 
+struct qmg_ptc_s {
+    qmg_fine_op op;   // links (complex64 storage) and neighbour table, borrowed
+    int C;            // hidden channels
+    int64_t V;
+    float2 *W1, *W2;  // [9][C][1][16], [9][1][C][16]
+    float2 *G1, *G2;  // gradients (accumulated)
+    float2 *m1, *v1, *m2, *v2;  // Adam moments (re, im as independent reals)
+    float2* h1;       // [C][V][12] hidden activations
+    float2* D1;       // [C][V][12] dL/dh1*
+    float2* y;        // [V][12] output
+    float2* D2;       // [V][12] dL/dy*
+    double* part;     // partial sums for reductions
+    double* loss;     // [2]: accumulated loss, scratch
+    int adam_t;
+};
+
 namespace qmg {
 // Chiral-basis Dirac matrices: gamma_mu = [[0, g_mu], [g_mu^+, 0]] with
 // g_k = -i sigma_k (k = 1..3), g_4 = 1.  gamma(mu, r, c) as (re, im).

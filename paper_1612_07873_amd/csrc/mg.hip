@@ -29,6 +29,7 @@ struct qmg_mg_s;
 namespace qmg {
 qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s);
 qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s);
+qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s);
 }
 
 using namespace qmg;
@@ -65,6 +66,10 @@ struct qmg_mg_s {
     std::vector<void*> allocs;
     hipStream_t s = nullptr;
     int level_iters[8] = {0};
+    qmg_ptc ptc = nullptr;      // learned level-0 smoother (NULL: MR)
+    int fallbacks = 0;          // smoother applications that fell back to MR
+    void* rec = nullptr;        // recording of outer iterates (complex128 [maxrec][V][12])
+    int rec_max = 0, rec_n = 0;
 };
 
 namespace {
@@ -76,6 +81,7 @@ constexpr int S_GCR = 32;     // 3
 constexpr int S_NRM = 36;     // 1
 constexpr int S_MR = 40;      // 3
 constexpr int S_BN = 44;      // 1
+constexpr int S_SM = 48;      // 2: smoother residual norms
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
 
@@ -180,6 +186,25 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     return QMG_OK;
 }
 
+// Level smoother: MR, or on level 0 the learned network when one is attached.
+// The network's result is kept only if it reduces the residual; otherwise
+// (including NaN/Inf from bad weights) MR is used for this application.
+// On exit lv.mr_r holds r - A x.
+template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void* x) {
+    Level& L = mg->lv[l];
+    if (l == 0 && mg->ptc && sizeof(R) == 4) {
+        QMG_TRY(ptc_forward(mg->ptc, r, x, mg->s));
+        QMG_TRY(apply_op<R>(mg, 0, x, L.mr_Ar));
+        QMG_TRY(mg->blas.xmy<R>(r, L.mr_Ar, L.mr_r, L.n));
+        QMG_TRY(mg->blas.norm2<R>(r, L.n, mg->dsc + S_SM));
+        QMG_TRY(mg->blas.norm2<R>(L.mr_r, L.n, mg->dsc + S_SM + 1));
+        QMG_TRY(read_scalars(mg, S_SM, 2));
+        if (mg->hsc[S_SM + 1] < mg->hsc[S_SM]) return QMG_OK;
+        ++mg->fallbacks;
+    }
+    return mr<R>(mg, l, r, x);
+}
+
 template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, void* zout) {
     Level& L = mg->lv[l];
     Level& C = mg->lv[l + 1];
@@ -187,7 +212,7 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
     const int nl = (int)mg->lv.size();
     // pre-smoothing; L.mr_r = rin - A zout afterwards
-    QMG_TRY(mr<R>(mg, l, rin, zout));
+    QMG_TRY(smooth<R>(mg, l, rin, zout));
     QMG_TRY(transfer_restrict(L.T, L.mr_r, C.b, p, mg->s));
     const bool coarsest = (l + 1 == nl - 1);
     int it = 0;
@@ -198,7 +223,7 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     // post-smoothing on r - A z
     QMG_TRY(apply_op<R>(mg, l, zout, L.kt));
     QMG_TRY(mg->blas.xmy<R>(rin, L.kt, L.kr2, n));
-    QMG_TRY(mr<R>(mg, l, L.kr2, L.kx2));
+    QMG_TRY(smooth<R>(mg, l, L.kr2, L.kx2));
     QMG_TRY(mg->blas.axpy<R>(1.0, L.kx2, zout, n));
     return QMG_OK;
 }
@@ -264,6 +289,8 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
     const int m = mg->restart;
     const int nl = (int)mg->lv.size();
     for (int i = 0; i < 8; ++i) mg->level_iters[i] = 0;
+    mg->fallbacks = 0;
+    mg->rec_n = 0;
     auto t0 = std::chrono::steady_clock::now();
     QMG_TRY(mg->blas.norm2<double>(b, n, mg->dsc + S_BN));
     QMG_TRY(read_scalars(mg, S_BN, 1));
@@ -292,6 +319,10 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
             QMG_TRY(mg->blas.norm2<double>(mg->r64, n, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
             ++iters;
+            if (mg->rec && mg->rec_n < mg->rec_max) {
+                QMG_HIP(hipMemcpyAsync((char*)mg->rec + (size_t)mg->rec_n * vb64, x, vb64, hipMemcpyDeviceToDevice, mg->s));
+                ++mg->rec_n;
+            }
             const double rn = std::sqrt(mg->hsc[S_NRM]);
             if (!std::isfinite(rn)) return fail(QMG_ERR_NONFINITE, "mg_gcr_solve: non-finite residual at step %d", iters);
             if (rn <= target || mg->hsc[S_GCR] <= 0.0) break;
@@ -316,6 +347,7 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
         info->true_rel_residual = true_rel;
         info->seconds = std::chrono::duration<double>(t1 - t0).count();
         info->converged = converged ? 1 : 0;
+        info->smoother_fallbacks = mg->fallbacks;
     }
     if (!converged) return fail(QMG_ERR_NOCONV, "mg_gcr_solve: %d steps, relative residual %.3e", iters, true_rel);
     return QMG_OK;
@@ -435,5 +467,65 @@ extern "C" qmg_status qmg_mg_level(qmg_mg mg, int level, int dims[4], int* dof, 
 extern "C" qmg_status qmg_mg_fine_op(qmg_mg mg, qmg_fine_op* fine64) {
     if (!mg || !fine64) return fail(QMG_ERR_ARG, "mg_fine_op: NULL argument");
     *fine64 = mg->fine64;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net) {
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_smoother: NULL mg");
+    if (net) {
+        if (mg->inner != QMG_C64) return fail(QMG_ERR_PREC, "mg_set_smoother: the learned smoother runs in complex64");
+        if (net->V != mg->lv[0].V) return fail(QMG_ERR_SHAPE, "mg_set_smoother: network lattice does not match");
+        if (mg->lv.size() < 2) return fail(QMG_ERR_STATE, "mg_set_smoother: a single-level solver has no smoother");
+    }
+    mg->ptc = net;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_gcr_solve_record(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
+                                              qmg_solve_info* info, void* xhist, int maxrec, int* nrec,
+                                              void* stream) {
+    if (!xhist || maxrec < 1 || !nrec) return fail(QMG_ERR_ARG, "mg_gcr_solve_record: bad record buffer");
+    if (!mg) return fail(QMG_ERR_ARG, "mg_gcr_solve_record: NULL mg");
+    mg->rec = xhist;
+    mg->rec_max = maxrec;
+    const qmg_status st = qmg_mg_gcr_solve(mg, b, x, p, info, stream);
+    *nrec = mg->rec_n;
+    mg->rec = nullptr;
+    mg->rec_max = 0;
+    return st;
+}
+
+namespace {
+// e = x* - x_k in FP64, stored as complex64
+__global__ void k_pair_error(const double2* __restrict__ xs, const double2* __restrict__ xk, double2* __restrict__ e64,
+                             float2* __restrict__ e32, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double2 d = make_double2(xs[i].x - xk[i].x, xs[i].y - xk[i].y);
+    e64[i] = d;
+    e32[i] = make_float2((float)d.x, (float)d.y);
+}
+__global__ void k_to32(const double2* __restrict__ a, float2* __restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = make_float2((float)a[i].x, (float)a[i].y);
+}
+}  // namespace
+
+extern "C" qmg_status qmg_mg_make_pairs(qmg_mg mg, const void* xstar, const void* xhist, int n, void* r_out,
+                                        void* e_out, void* stream) {
+    if (!mg || !xstar || !xhist || !r_out || !e_out || n < 1) return fail(QMG_ERR_ARG, "mg_make_pairs: bad argument");
+    hipStream_t s = as_stream(stream);
+    const int64_t nv = mg->lv[0].n;
+    const unsigned g = (unsigned)((nv + 255) / 256);
+    for (int k = 0; k < n; ++k) {
+        const double2* xk = (const double2*)xhist + (size_t)k * nv;
+        float2* e32 = (float2*)e_out + (size_t)k * nv;
+        float2* r32 = (float2*)r_out + (size_t)k * nv;
+        hipLaunchKernelGGL(k_pair_error, dim3(g), dim3(256), 0, s, (const double2*)xstar, xk, (double2*)mg->t64, e32, nv);
+        QMG_LAUNCH_CHECK();
+        QMG_TRY(qmg_wilson_clover_dslash(mg->fine64, mg->t64, mg->r64, QMG_C128, stream));
+        hipLaunchKernelGGL(k_to32, dim3(g), dim3(256), 0, s, (const double2*)mg->r64, r32, nv);
+        QMG_LAUNCH_CHECK();
+    }
     return QMG_OK;
 }
