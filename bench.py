@@ -1,13 +1,21 @@
-"""Benchmark of the coarse-grid operator (Eq. 3) on one MI355X.
+"""Benchmark of the adaptive-multigrid hot path on one MI355X.
 
-Workload: the level-1 coarse grid of the 3-level hierarchy on a 16^3x32
-fine lattice (block 4^4, Nvec 24): coarse lattice 4^3x8, N = 48, FP32
-storage and arithmetic.  One step = one application of the operator to one
-vector.  Links are Gaussian synthetic blocks of that shape (the values do not
-change bytes or flops).  To measure HBM rather than the 256 MB Infinity
-Cache, the steps cycle over R copies of the operator whose total size is far
-above the cache; the `warm` record repeats one copy.
+Headline (value): the coarse-grid operator of Eq. (3) on the level-1 grid of
+the 16^3x32 hierarchy (coarse lattice 4^3x8, N = 48, FP32), one step = one
+application to one vector, GFLOP/s = 72 N^2 V / time.  Links are Gaussian
+synthetic blocks of that shape (values do not change bytes or flops).  To
+measure HBM rather than the 256 MB Infinity Cache the steps cycle over R
+copies of the operator whose total size is well above the cache.
 
+Further records on the same line:
+  warm_cache  the same kernel repeated on one copy (cache resident);
+  precision   16-bit storage (FP16 links + FP32 scales, 16-bit vectors) on
+              8^3x16/N48 and 4^3x8/N64;
+  multi_rhs   the MFMA multi-right-hand-side form, nrhs 8..64, same shapes;
+  mg_gcr      MG-GCR time to a true residual of 1e-10 on 16^3x32 (3 levels,
+              FP32 inner, FP64 outer, MR smoother): 12 solves, the first
+              discarded, mean and standard deviation of the rest;
+  cpu_baseline the oracle's Eq. (3) apply timed on the host.
 Prints one JSON line.
 """
 import argparse
@@ -20,18 +28,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MG_M0_FILE = os.path.join(ROOT, 'tests', 'golden', 'config2_m0.json')
 
 
-def algorithmic(V, N, nrhs, cbytes, scale_bytes=0):
-    """Flops and bytes of one application: each link, the input vector and the
-    output counted once (perfect neighbour reuse)."""
+def algorithmic(V, N, nrhs, cbytes, scale_bytes=0, out_cbytes=None, out_scale_bytes=None):
+    """Flops and bytes of one application: each link, the input vectors and the
+    outputs counted once (perfect neighbour reuse)."""
+    out_cbytes = cbytes if out_cbytes is None else out_cbytes
+    out_scale_bytes = scale_bytes if out_scale_bytes is None else out_scale_bytes
     flops = 72 * N * N * nrhs * V
-    byts = V * (9 * N * N * cbytes + 9 * scale_bytes + 2 * N * nrhs * cbytes + 2 * nrhs * scale_bytes)
+    byts = V * (9 * N * N * cbytes + 9 * scale_bytes + N * nrhs * cbytes + nrhs * scale_bytes
+                + N * nrhs * out_cbytes + nrhs * out_scale_bytes)
     return flops, byts
 
 
+def timed(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn(0)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for i in range(steps):
+        fn(i)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
 def cpu_baseline(cd, N, X, Y, u, budget_s=12.0):
-    """The oracle's Eq. 3 apply (numpy einsum, complex128) on the same shape."""
+    """The oracle's Eq. (3) apply (numpy einsum, complex128) on the same shape."""
     import numpy as np
     from oracle import coarse
     op = coarse.CoarseOp(cd, X.astype(np.complex128), Y.astype(np.complex128))
@@ -41,11 +67,100 @@ def cpu_baseline(cd, N, X, Y, u, budget_s=12.0):
         op.apply(u)
         n += 1
     dt = (time.perf_counter() - t0) / n
-    V = X.shape[0]
-    flops, _ = algorithmic(V, N, 1, 16)
+    flops, _ = algorithmic(X.shape[0], N, 1, 16)
     return ref, {'value': round(flops / dt / 1e9, 3), 'unit': 'GFLOP/s', 'cores': 1, 'kind': 'oracle',
                  'sample': '%d applications of the oracle Eq. 3 apply (numpy, complex128, single thread) '
                            'on the same %dx%dx%dx%d N=%d operator, %.1f s' % (n, *cd, N, n * dt)}
+
+
+def cold_ops(cd, N, storage, X, Y, byts):
+    import numpy as np
+    from paper_1612_07873_amd import CoarseOp
+    R = max(2, int(np.ceil(3 * 256e6 / byts)))
+    return [CoarseOp(cd, X, Y, storage) for _ in range(R)]
+
+
+def precision_and_mrhs(steps):
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import quantize_sites
+    dev = torch.device('cuda')
+    out = {'precision': [], 'multi_rhs': []}
+    for cd, N in (((8, 8, 8, 16), 48), ((4, 4, 4, 8), 64)):
+        V = int(np.prod(cd))
+        X = torch.from_numpy(synth.gaussian((V, N, N), 0, 2)).to(dev)
+        Y = torch.from_numpy(synth.gaussian((8, V, N, N), 1, 2)).to(dev)
+        # single RHS, 16-bit links and vectors
+        flops, byts = algorithmic(V, N, 1, 4, 4)
+        ops = cold_ops(cd, N, 'h16', X, Y, byts)
+        u = torch.from_numpy(synth.gaussian((V, N), 2, 2)).to(dev).to(torch.complex64)
+        uq, us = quantize_sites(u, 'h16')
+        yq, ys = torch.empty_like(uq), torch.empty_like(us)
+        ms = timed(lambda i: ops[i % len(ops)].apply_scaled(uq, us, yq, ys), steps, 20)
+        out['precision'].append({'lattice': list(cd), 'N': N, 'storage': 'fp16+fp32 scale', 'ms': round(ms, 5),
+                                 'GFLOP/s': round(flops / ms / 1e6, 1), 'GB/s': round(byts / ms / 1e6, 1),
+                                 'hbm_frac': round(byts / ms / 1e6 / HBM_PEAK_GBS, 4), 'copies': len(ops)})
+        del ops
+        for nrhs in (8, 16, 32, 64):
+            flops, byts = algorithmic(V, N, nrhs, 4, 4, out_cbytes=8, out_scale_bytes=0)
+            ops = cold_ops(cd, N, 'h16', X, Y, byts)
+            um = torch.from_numpy(np.stack([synth.gaussian((V, N), j, 2) for j in range(nrhs)], axis=1)
+                                  ).to(dev).to(torch.complex64)
+            q, s = quantize_sites(um.reshape(V * nrhs, N), 'h16')
+            q, s = q.reshape(V, nrhs, N), s.reshape(V, nrhs)
+            y = torch.empty((V, nrhs, N), dtype=torch.complex64, device=dev)
+            for op in ops:
+                op.apply_mrhs(q, s, y)      # builds the operand-order copy outside the timing
+            ms = timed(lambda i: ops[i % len(ops)].apply_mrhs(q, s, y), max(20, steps // 4), 5)
+            out['multi_rhs'].append({'lattice': list(cd), 'N': N, 'nrhs': nrhs, 'ms': round(ms, 5),
+                                     'GFLOP/s': round(flops / ms / 1e6, 1), 'GB/s': round(byts / ms / 1e6, 1),
+                                     'hbm_frac': round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
+                                     'mfma_frac_fp16': round(flops / ms / 1e9 / 2500.0, 4)})
+            del ops
+    return out
+
+
+def mg_gcr(nsolves=12):
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import Multigrid
+    dev = torch.device('cuda')
+    dims = (16, 16, 16, 32)
+    m0 = -0.25
+    m0_src = 'provisional'
+    if os.path.exists(MG_M0_FILE):
+        with open(MG_M0_FILE) as f:
+            m0 = float(json.load(f)['m0'])
+        m0_src = 'tests/golden/config2_m0.json'
+    V = int(np.prod(dims))
+    U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
+    levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10),
+              dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100)]
+    starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
+              torch.from_numpy(synth.gaussian((32, 512, 48), 1, 1)).to(dev)]
+    t0 = time.perf_counter()
+    mg = Multigrid(dims, U, m0, 1.0, levels, starts, inner='c64')
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    times, iters, res = [], [], []
+    for i in range(nsolves):
+        b = torch.from_numpy(synth.gaussian((V, 4, 3), i, 2)).to(dev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = mg.solve(b, tol=1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        iters.append(info['outer_iters'])
+        res.append(info['true_rel_residual'])
+        lvl = info['level_iters']
+    t = np.array(times[1:])
+    return {'lattice': list(dims), 'm0': m0, 'm0_source': m0_src, 'levels': '16^3x32 -(4^4,Nvec24)-> 4^3x8 N48 '
+            '-(2^4,Nvec32)-> 2^3x4 N64', 'inner': 'fp32', 'outer': 'fp64 GCR(10)', 'smoother': 'MR(4)',
+            'solves': nsolves, 'time_to_1e-10_s': round(float(t.mean()), 4), 'std_s': round(float(t.std()), 4),
+            'outer_iters_mean': float(np.mean(iters[1:])), 'level_iters_last': lvl,
+            'max_true_rel_residual': float(max(res)), 'setup_s': round(setup, 2)}
 
 
 def main():
@@ -54,10 +169,11 @@ def main():
     ap.add_argument('--steps', type=int, default=2000)
     ap.add_argument('--warmup', type=int, default=200)
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle leg')
+    ap.add_argument('--only-headline', action='store_true', help='time the headline kernel only')
     args = ap.parse_args()
     if args.gpus != 1:
-        print('bench.py measures one GPU only: the coarse-operator path is built and timed on a '
-              'single MI355X; --gpus %d is not supported' % args.gpus, file=sys.stderr)
+        print('bench.py measures one GPU only: the multigrid hot path is built and timed on a single MI355X; '
+              '--gpus %d is not supported' % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -73,51 +189,13 @@ def main():
     u = synth.gaussian((V, N), 2, 2)
     Xd, Yd = torch.from_numpy(X).to(dev), torch.from_numpy(Y).to(dev)
     flops, byts = algorithmic(V, N, 1, 8)
-    R = max(2, int(np.ceil(3 * 256e6 / byts)))      # copies: total >= 3x the Infinity Cache
-    ops = [CoarseOp(cd, Xd, Yd, 'c64') for _ in range(R)]
-    del Xd, Yd
+    ops = cold_ops(cd, N, 'c64', Xd, Yd, byts)
+    R = len(ops)
     ud = torch.from_numpy(u).to(dev).to(torch.complex64)
     out = torch.empty_like(ud)
-    torch.cuda.synchronize()
-
-    for i in range(args.warmup):
-        ops[i % R].apply(ud, out)
-    torch.cuda.synchronize()
-
-    # timed region: exactly K steps
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    start.record()
-    for i in range(args.steps):
-        ops[i % R].apply(ud, out)
-    stop.record()
-    torch.cuda.synchronize()
-    ms_total = start.elapsed_time(stop)
-    ms_step = ms_total / args.steps
-
-    # per-launch kernel duration (events right around each launch)
-    nper = min(args.steps, 400)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nper)]
-    for i, (a, b) in enumerate(evs):
-        a.record()
-        ops[i % R].apply(ud, out)
-        b.record()
-    torch.cuda.synchronize()
-    per = np.array([a.elapsed_time(b) for a, b in evs])
-    kern_ms = float(np.mean(per))
-
-    # warm: one copy, Infinity-Cache resident
-    for _ in range(50):
-        ops[0].apply(ud, out)
-    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    a.record()
-    for _ in range(500):
-        ops[0].apply(ud, out)
-    b.record()
-    torch.cuda.synchronize()
-    warm_ms = a.elapsed_time(b) / 500
-
+    ms_step = timed(lambda i: ops[i % R].apply(ud, out), args.steps, args.warmup)
     y = out.cpu().numpy().astype(np.complex128)
-    achieved = byts / (kern_ms * 1e-3) / 1e9
+    achieved = byts / (ms_step * 1e-3) / 1e9
     rec = {
         'metric': 'coarse-Dslash GFLOP/s & %HBM roofline; MG-GCR time to 1e-10 vs plain',
         'value': round(flops / (ms_step * 1e-3) / 1e9, 2),
@@ -131,11 +209,15 @@ def main():
                    'lattice': list(cd), 'N': N, 'nrhs': 1, 'launch': list(ops[0].launch())},
         'roofline': {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                      'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
-                     'algorithmic_bytes_per_launch': byts, 'kernel_ms': round(kern_ms, 6)},
-        'warm_cache': {'ms_per_step': round(warm_ms, 6),
-                       'GFLOP/s': round(flops / (warm_ms * 1e-3) / 1e9, 2),
-                       'effective_GB/s': round(byts / (warm_ms * 1e-3) / 1e9, 1)},
+                     'algorithmic_bytes_per_launch': byts, 'kernel': 'qmg::k_coarse_dslash<1,0,16> (FP32)'},
     }
+    warm_ms = timed(lambda i: ops[0].apply(ud, out), 500, 50)
+    rec['warm_cache'] = {'ms_per_step': round(warm_ms, 6), 'GFLOP/s': round(flops / (warm_ms * 1e-3) / 1e9, 2),
+                         'effective_GB/s': round(byts / (warm_ms * 1e-3) / 1e9, 1)}
+    del ops, Xd, Yd
+    if not args.only_headline:
+        rec.update(precision_and_mrhs(max(100, args.steps // 4)))
+        rec['mg_gcr'] = mg_gcr()
     if not args.no_cpu:
         ref, rec['cpu_baseline'] = cpu_baseline(cd, N, X, Y, u)
         rec['parity_rel_err'] = float(np.abs(y - ref).max() / np.abs(ref).max())
