@@ -146,6 +146,25 @@ qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, int rhs_tile
 qmg_status qmg_coarse_op_set_launch(qmg_coarse_op op, int rows, int split);
 qmg_status qmg_coarse_op_get_launch(qmg_coarse_op op, int* rows, int* split);
 
+/* Prefetch depth installed by the autotuner (link chunks per thread loaded
+ * before the LDS staging barrier; 0 = chosen from the chunks per thread). */
+qmg_status qmg_coarse_op_get_prefetch(qmg_coarse_op op, int* pre);
+
+/* Autotune the single-RHS launch (rows, split, prefetch depth) by timing every
+ * candidate with HIP events on `stream` (cold != 0: caches flushed with a
+ * 1 GiB write before each timed launch, so links stream from HBM), install
+ * the fastest on `op`, and remember it for operators of the same shape and
+ * precision in this process.  in/out (and scales for 16-bit vectors, vprec
+ * QMG_H16/QMG_B16) are valid DEVICE fields as for the apply calls; their
+ * contents are overwritten.  Blocks; *best_ms (host, may be NULL) receives the
+ * best average time. */
+qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                              float* out_scale, qmg_prec vprec, int cold, void* stream, float* best_ms);
+
+/* The same for the multi-RHS kernel's tile shape at this nrhs. */
+qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out, int nrhs,
+                                   int cold, void* stream, float* best_ms);
+
 void qmg_coarse_op_destroy(qmg_coarse_op op);
 
 /* ---------------------------------------------------------------------------

@@ -106,6 +106,34 @@ class CoarseOp:
                   ctypes.c_void_p(Y.data_ptr()), stream_ptr())
         return X, Y
 
+    def tune(self, u, out, cold=False, u16=None, uscale=None, o16=None, oscale=None):
+        """Autotune the single-RHS launch on these fields; returns the best time in ms."""
+        ms = ctypes.c_float()
+        if u16 is None:
+            vp = self.storage if self.storage in ('c128', 'c64') else 'c64'
+            _lib.call('qmg_coarse_op_tune', self._h, _dev_ptr(u, self.dtype, (self.V, self.N), 'in'), None,
+                      _dev_ptr(out, self.dtype, (self.V, self.N), 'out'), None, PREC[vp], int(bool(cold)),
+                      stream_ptr(), ctypes.byref(ms))
+        else:
+            _lib.call('qmg_coarse_op_tune', self._h, ctypes.c_void_p(u16.data_ptr()), ctypes.c_void_p(uscale.data_ptr()),
+                      ctypes.c_void_p(o16.data_ptr()), ctypes.c_void_p(oscale.data_ptr()), PREC[self.storage],
+                      int(bool(cold)), stream_ptr(), ctypes.byref(ms))
+        return ms.value
+
+    def tune_mrhs(self, u16, uscale, out, cold=False):
+        V, nrhs, N = u16.shape
+        ms = ctypes.c_float()
+        _lib.call('qmg_coarse_op_tune_mrhs', self._h, _dev_ptr(u16, torch.int32, (self.V, nrhs, self.N), 'in'),
+                  _dev_ptr(uscale, torch.float32, (self.V, nrhs), 'in_scale'),
+                  _dev_ptr(out, torch.complex64, (self.V, nrhs, self.N), 'out'), int(nrhs), int(bool(cold)),
+                  stream_ptr(), ctypes.byref(ms))
+        return ms.value
+
+    def prefetch(self):
+        p = ctypes.c_int()
+        _lib.call('qmg_coarse_op_get_prefetch', self._h, ctypes.byref(p))
+        return p.value
+
     def set_launch(self, rows=0, split=0):
         _lib.call('qmg_coarse_op_set_launch', self._h, int(rows), int(split))
 

@@ -23,6 +23,11 @@ SIGNATURES = {
     'qmg_coarse_op_export': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_launch': (c_int, [c_void_p, c_int, c_int]),
+    'qmg_coarse_op_get_prefetch': (c_int, [c_void_p, c_int_p]),
+    'qmg_coarse_op_tune': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
+                                   ctypes.POINTER(ctypes.c_float)]),
+    'qmg_coarse_op_tune_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
+                                        ctypes.POINTER(ctypes.c_float)]),
     'qmg_coarse_dslash_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_mrhs_tiles': (c_int, [c_void_p, c_int, c_int]),
     'qmg_coarse_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),

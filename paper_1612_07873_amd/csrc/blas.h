@@ -30,7 +30,9 @@ struct Blas {
     template <typename R> qmg_status gcr_update(const double* s3, void* q, void* z, void* x, void* r, int64_t n);
     // MR step with s = dot_norm(Ar, r) = [<Ar,Ar>, <Ar,r>.re, <Ar,r>.im]:
     // alpha = (s1 + i s2)/s0; x = alpha r (first) or x += alpha r; r -= alpha Ar
-    template <typename R> qmg_status mr_update(const double* s3, void* r, const void* Ar, void* x, int first, int64_t n);
+    // (r may equal rin; the result residual goes to r)
+    template <typename R> qmg_status mr_update(const double* s3, const void* rin, void* r, const void* Ar, void* x,
+                                               int first, int64_t n);
     template <typename R> qmg_status axpy(double a, const void* x, void* y, int64_t n);       // y += a x
     template <typename R> qmg_status xmy(const void* b, const void* ax, void* r, int64_t n);  // r = b - ax
     template <typename Rs, typename Rd> qmg_status convert(const void* src, void* dst, int64_t n);

@@ -4,13 +4,15 @@
 namespace qmg {
 
 static constexpr int kThreads = 256;
+static constexpr int64_t kOneBlock = 1 << 15;  // up to this many entries one 1024-thread block reduces alone
 
 static int nblocks(int64_t n) {
+    if (n <= kOneBlock) return 1;
     int64_t b = (n + kThreads - 1) / kThreads;
     if (b > Blas::kMaxBlocks) b = Blas::kMaxBlocks;
-    if (b < 1) b = 1;
     return (int)b;
 }
+static int rthreads(int nb) { return nb == 1 ? 1024 : kThreads; }
 
 // sum of v over the work-group, valid in thread 0
 __device__ __forceinline__ double wg_sum(double v, double* lds) {
@@ -25,18 +27,28 @@ __device__ __forceinline__ double wg_sum(double v, double* lds) {
     return t;
 }
 
-// phase 2: out[v] = sum over blocks of partials[b][v], fixed order
-__global__ void k_final(const double* __restrict__ partials, int nb, int nv, double* __restrict__ out) {
-    const int v = threadIdx.x;
-    if (v >= nv) return;
-    double t = 0;
-    for (int b = 0; b < nb; ++b) t += partials[b * Blas::kMaxVals + v];
-    out[v] = t;
+// phase 2: out[v] = sum over blocks of partials[b][v]; thread t adds blocks
+// t, t+256, ..., then a fixed tree: the same order on every run
+__global__ __launch_bounds__(256) void k_final(const double* __restrict__ partials, int nb, int nv,
+                                               double* __restrict__ out) {
+    __shared__ double lds[16];
+    for (int v = 0; v < nv; ++v) {
+        double t = 0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) t += partials[b * Blas::kMaxVals + v];
+        t = wg_sum(t, lds);
+        if (threadIdx.x == 0) out[v] = t;
+    }
+}
+
+// a work-group's sums: to the partials, or straight to the result when the grid is one block
+__device__ __forceinline__ void put(double* part, double* out, int v, double val) {
+    if (gridDim.x == 1) out[v] = val;
+    else part[blockIdx.x * Blas::kMaxVals + v] = val;
 }
 
 template <typename R>
-__global__ void k_dot(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, int64_t n,
-                      double* __restrict__ part) {
+__global__ __launch_bounds__(1024) void k_dot(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, int64_t n,
+                      double* __restrict__ part, double* __restrict__ out) {
     __shared__ double lds[16];
     double re = 0, im = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -47,13 +59,14 @@ __global__ void k_dot(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b
     re = wg_sum(re, lds);
     im = wg_sum(im, lds);
     if (threadIdx.x == 0) {
-        part[blockIdx.x * Blas::kMaxVals + 0] = re;
-        part[blockIdx.x * Blas::kMaxVals + 1] = im;
+        put(part, out, 0, re);
+        put(part, out, 1, im);
     }
 }
 
 template <typename R>
-__global__ void k_norm2(const cpx<R>* __restrict__ a, int64_t n, double* __restrict__ part) {
+__global__ __launch_bounds__(1024) void k_norm2(const cpx<R>* __restrict__ a, int64_t n, double* __restrict__ part,
+                                                double* __restrict__ out) {
     __shared__ double lds[16];
     double s = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -61,12 +74,12 @@ __global__ void k_norm2(const cpx<R>* __restrict__ a, int64_t n, double* __restr
         s += (double)x.re * x.re + (double)x.im * x.im;
     }
     s = wg_sum(s, lds);
-    if (threadIdx.x == 0) part[blockIdx.x * Blas::kMaxVals] = s;
+    if (threadIdx.x == 0) put(part, out, 0, s);
 }
 
 template <typename R>
-__global__ void k_dot_norm(const cpx<R>* __restrict__ q, const cpx<R>* __restrict__ r, int64_t n,
-                           double* __restrict__ part) {
+__global__ __launch_bounds__(1024) void k_dot_norm(const cpx<R>* __restrict__ q, const cpx<R>* __restrict__ r,
+                                                   int64_t n, double* __restrict__ part, double* __restrict__ out) {
     __shared__ double lds[16];
     double qq = 0, re = 0, im = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -79,33 +92,40 @@ __global__ void k_dot_norm(const cpx<R>* __restrict__ q, const cpx<R>* __restric
     re = wg_sum(re, lds);
     im = wg_sum(im, lds);
     if (threadIdx.x == 0) {
-        double* p = part + blockIdx.x * Blas::kMaxVals;
-        p[0] = qq;
-        p[1] = re;
-        p[2] = im;
+        put(part, out, 0, qq);
+        put(part, out, 1, re);
+        put(part, out, 2, im);
     }
 }
 
 template <typename R>
-__global__ void k_multi_dot(const cpx<R>* __restrict__ Q, int64_t ld, int k, const cpx<R>* __restrict__ q,
-                            int64_t n, double* __restrict__ part) {
+__global__ __launch_bounds__(1024) void k_multi_dot(const cpx<R>* __restrict__ Q, int64_t ld, int k,
+                                                    const cpx<R>* __restrict__ q, int64_t n,
+                                                    double* __restrict__ part, double* __restrict__ out) {
     __shared__ double lds[16];
     double re[16], im[16];
+#pragma unroll
     for (int j = 0; j < 16; ++j) re[j] = im[j] = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const cpx<R> y = q[i];
-        for (int j = 0; j < k; ++j) {
-            const cpx<R> x = Q[j * ld + i];
-            re[j] += (double)x.re * y.re + (double)x.im * y.im;
-            im[j] += (double)x.re * y.im - (double)x.im * y.re;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j < k) {
+                const cpx<R> x = Q[j * ld + i];
+                re[j] += (double)x.re * y.re + (double)x.im * y.im;
+                im[j] += (double)x.re * y.im - (double)x.im * y.re;
+            }
         }
     }
-    for (int j = 0; j < k; ++j) {
-        const double a = wg_sum(re[j], lds);
-        const double b = wg_sum(im[j], lds);
-        if (threadIdx.x == 0) {
-            part[blockIdx.x * Blas::kMaxVals + 2 * j] = a;
-            part[blockIdx.x * Blas::kMaxVals + 2 * j + 1] = b;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if (j < k) {
+            const double a = wg_sum(re[j], lds);
+            const double b = wg_sum(im[j], lds);
+            if (threadIdx.x == 0) {
+                put(part, out, 2 * j, a);
+                put(part, out, 2 * j + 1, b);
+            }
         }
     }
 }
@@ -157,13 +177,13 @@ __global__ void k_gcr_update(const double* __restrict__ s3, cpx<R>* __restrict__
 }
 
 template <typename R>
-__global__ void k_mr_update(const double* __restrict__ s3, cpx<R>* __restrict__ r, const cpx<R>* __restrict__ Ar,
+__global__ void k_mr_update(const double* __restrict__ s3, const cpx<R>* rin, cpx<R>* r, const cpx<R>* __restrict__ Ar,
                             cpx<R>* __restrict__ x, int first, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double den = s3[0];
     const R ar = den > 0 ? (R)(s3[1] / den) : (R)0, ai = den > 0 ? (R)(s3[2] / den) : (R)0;
-    cpx<R> rr = r[i];
+    cpx<R> rr = rin[i];
     const cpx<R> a = Ar[i];
     cpx<R> xx = first ? cpx<R>{0, 0} : x[i];
     xx.re += ar * rr.re - ai * rr.im;
@@ -218,24 +238,29 @@ void Blas::release() {
 
 static unsigned grid1(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
+static void finish(hipStream_t s, double* partials, int nb, int nv, double* out) {
+    if (nb > 1) hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partials, nb, nv, out);
+}
+
 template <typename R> qmg_status Blas::dot(const void* a, const void* b, int64_t n, double* out) {
     const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_dot<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n, partials);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 2, out);
+    hipLaunchKernelGGL(k_dot<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n, partials, out);
+    finish(s, partials, nb, 2, out);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::norm2(const void* a, int64_t n, double* out) {
     const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_norm2<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)a, n, partials);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 1, out);
+    hipLaunchKernelGGL(k_norm2<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)a, n, partials, out);
+    finish(s, partials, nb, 1, out);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::dot_norm(const void* q, const void* r, int64_t n, double* out) {
     const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_dot_norm<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)q, (const cpx<R>*)r, n, partials);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 3, out);
+    hipLaunchKernelGGL(k_dot_norm<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)q, (const cpx<R>*)r, n,
+                       partials, out);
+    finish(s, partials, nb, 3, out);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -244,9 +269,9 @@ qmg_status Blas::multi_dot(const void* Q, int64_t ld, int k, const void* q, int6
     if (k <= 0) return QMG_OK;
     if (k > 16) return fail(QMG_ERR_ARG, "multi_dot: k=%d > 16", k);
     const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_multi_dot<R>, dim3(nb), dim3(kThreads), 0, s, (const cpx<R>*)Q, ld, k, (const cpx<R>*)q, n,
-                       partials);
-    hipLaunchKernelGGL(k_final, dim3(1), dim3(64), 0, s, partials, nb, 2 * k, out);
+    hipLaunchKernelGGL(k_multi_dot<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)Q, ld, k, (const cpx<R>*)q, n,
+                       partials, out);
+    finish(s, partials, nb, 2 * k, out);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -267,9 +292,9 @@ qmg_status Blas::gcr_update(const double* s3, void* q, void* z, void* x, void* r
     return QMG_OK;
 }
 template <typename R>
-qmg_status Blas::mr_update(const double* s3, void* r, const void* Ar, void* x, int first, int64_t n) {
-    hipLaunchKernelGGL(k_mr_update<R>, dim3(grid1(n)), dim3(kThreads), 0, s, s3, (cpx<R>*)r, (const cpx<R>*)Ar,
-                       (cpx<R>*)x, first, n);
+qmg_status Blas::mr_update(const double* s3, const void* rin, void* r, const void* Ar, void* x, int first, int64_t n) {
+    hipLaunchKernelGGL(k_mr_update<R>, dim3(grid1(n)), dim3(kThreads), 0, s, s3, (const cpx<R>*)rin, (cpx<R>*)r,
+                       (const cpx<R>*)Ar, (cpx<R>*)x, first, n);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -304,7 +329,7 @@ template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, in
     template qmg_status Blas::multi_axpy<R>(const double*, const void*, const void*, int64_t, int, void*, \
                                             void*, int64_t);                                               \
     template qmg_status Blas::gcr_update<R>(const double*, void*, void*, void*, void*, int64_t);           \
-    template qmg_status Blas::mr_update<R>(const double*, void*, const void*, void*, int, int64_t);        \
+    template qmg_status Blas::mr_update<R>(const double*, const void*, void*, const void*, void*, int, int64_t); \
     template qmg_status Blas::axpy<R>(double, const void*, void*, int64_t);                                \
     template qmg_status Blas::xmy<R>(const void*, const void*, void*, int64_t);                            \
     template qmg_status Blas::normalize<R>(void*, const double*, int64_t);

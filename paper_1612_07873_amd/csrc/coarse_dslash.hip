@@ -350,44 +350,53 @@ static qmg_status validate_launch(const qmg_coarse_op_s* op, int rows, int split
 }
 
 template <int F, int VF>
-static qmg_status launch_f(const qmg_coarse_op_s* op, int rows, int split, const void* in, const float* in_scale,
-                           void* out, float* out_scale, hipStream_t s) {
+static qmg_status launch_f(const qmg_coarse_op_s* op, int rows, int split, int pre, const void* in,
+                           const float* in_scale, void* out, float* out_scale, hipStream_t s) {
     using R = typename Fmt<F>::R;
     const int ntiles = op->N / rows;
     const size_t lds = sizeof(cpx<R>) * (9 * op->N + std::max(rows * split, rows + 1));
     const dim3 grid((unsigned)(op->V * ntiles)), block((unsigned)(rows * split));
     const auto* L = reinterpret_cast<const typename Fmt<F>::C*>(op->links);
     const int K = op->J / split;
-    if (K >= 16)
-        hipLaunchKernelGGL((k_coarse_dslash<F, VF, 16>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale,
-                           out, out_scale, op->N, op->J, rows, split, ntiles);
-    else
-        hipLaunchKernelGGL((k_coarse_dslash<F, VF, 4>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale,
-                           out, out_scale, op->N, op->J, rows, split, ntiles);
+    if (pre <= 0) pre = K >= 16 ? 16 : 4;
+#define QMG_CD_LAUNCH(P)                                                                                          \
+    hipLaunchKernelGGL((k_coarse_dslash<F, VF, P>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale, out, \
+                       out_scale, op->N, op->J, rows, split, ntiles)
+    if (pre >= 16) QMG_CD_LAUNCH(16);
+    else if (pre >= 8) QMG_CD_LAUNCH(8);
+    else if (pre >= 4) QMG_CD_LAUNCH(4);
+    else QMG_CD_LAUNCH(1);
+#undef QMG_CD_LAUNCH
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
-qmg_status coarse_dslash_any(const qmg_coarse_op_s* op, const void* in, const float* in_scale, void* out,
-                             float* out_scale, qmg_prec vprec, hipStream_t s) {
-    int rows = op->rows, split = op->split;
+qmg_status coarse_dslash_launch(const qmg_coarse_op_s* op, int rows, int split, int pre, const void* in,
+                                const float* in_scale, void* out, float* out_scale, qmg_prec vprec, hipStream_t s) {
     const bool v16 = is16(vprec);
     if (v16 && rows != op->N) {  // per-site output scale needs the whole site in one work-group
         rows = op->N;
         while (rows * split > 1024 || op->J % split) --split;
     }
     switch (op->storage) {
-        case QMG_C128: return launch_f<FMT_F64, 0>(op, rows, split, in, nullptr, out, nullptr, s);
-        case QMG_C64: return launch_f<FMT_F32, 0>(op, rows, split, in, nullptr, out, nullptr, s);
+        case QMG_C128: return launch_f<FMT_F64, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
+        case QMG_C64: return launch_f<FMT_F32, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
         case QMG_H16:
-            if (vprec == QMG_C64) return launch_f<FMT_H16, 0>(op, rows, split, in, nullptr, out, nullptr, s);
-            if (vprec == QMG_H16) return launch_f<FMT_H16, FMT_H16>(op, rows, split, in, in_scale, out, out_scale, s);
-            return launch_f<FMT_H16, FMT_B16>(op, rows, split, in, in_scale, out, out_scale, s);
+            if (vprec == QMG_C64) return launch_f<FMT_H16, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
+            if (vprec == QMG_H16)
+                return launch_f<FMT_H16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
+            return launch_f<FMT_H16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
         default:
-            if (vprec == QMG_C64) return launch_f<FMT_B16, 0>(op, rows, split, in, nullptr, out, nullptr, s);
-            if (vprec == QMG_H16) return launch_f<FMT_B16, FMT_H16>(op, rows, split, in, in_scale, out, out_scale, s);
-            return launch_f<FMT_B16, FMT_B16>(op, rows, split, in, in_scale, out, out_scale, s);
+            if (vprec == QMG_C64) return launch_f<FMT_B16, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
+            if (vprec == QMG_H16)
+                return launch_f<FMT_B16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
+            return launch_f<FMT_B16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
     }
+}
+
+qmg_status coarse_dslash_any(const qmg_coarse_op_s* op, const void* in, const float* in_scale, void* out,
+                             float* out_scale, qmg_prec vprec, hipStream_t s) {
+    return coarse_dslash_launch(op, op->rows, op->split, op->pre, in, in_scale, out, out_scale, vprec, s);
 }
 
 }  // namespace qmg

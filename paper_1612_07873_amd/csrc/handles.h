@@ -13,6 +13,7 @@ struct qmg_coarse_op_s {
     float* lscale;  // [V][9] scales of the 16-bit storages (X, then Y_0..Y_7), else NULL
     int* nbr;       // [V][8]
     int rows, split;
+    int pre;        // link chunks each thread loads before the LDS staging barrier (0 = by K)
     void* mlinks;   // 16-bit links in MFMA operand order (built on first multi-RHS use), else NULL
     int rpw[7];     // multi-RHS: right-hand-side tiles per wave for nrhs = 1,2,4,..,64 (0 = built-in)
 };

@@ -124,13 +124,16 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
 template <typename R> qmg_status mr(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
     const int64_t n = L.n;
-    QMG_HIP(hipMemcpyAsync(L.mr_r, r, n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
     for (int it = 0; it < L.p.smoother_steps; ++it) {
-        QMG_TRY(apply_op<R>(mg, l, L.mr_r, L.mr_Ar));
-        QMG_TRY(mg->blas.dot_norm<R>(L.mr_Ar, L.mr_r, n, mg->dsc + S_MR));
-        QMG_TRY(mg->blas.mr_update<R>(mg->dsc + S_MR, L.mr_r, L.mr_Ar, x, it == 0, n));
+        const void* cur = it == 0 ? r : L.mr_r;   // the first step reads r itself
+        QMG_TRY(apply_op<R>(mg, l, cur, L.mr_Ar));
+        QMG_TRY(mg->blas.dot_norm<R>(L.mr_Ar, cur, n, mg->dsc + S_MR));
+        QMG_TRY(mg->blas.mr_update<R>(mg->dsc + S_MR, cur, L.mr_r, L.mr_Ar, x, it == 0, n));
     }
-    if (L.p.smoother_steps <= 0) QMG_HIP(hipMemsetAsync(x, 0, n * sizeof(cpx<R>), mg->s));
+    if (L.p.smoother_steps <= 0) {
+        QMG_HIP(hipMemsetAsync(x, 0, n * sizeof(cpx<R>), mg->s));
+        QMG_HIP(hipMemcpyAsync(L.mr_r, r, n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
+    }
     return QMG_OK;
 }
 

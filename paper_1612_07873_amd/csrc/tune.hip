@@ -1,0 +1,166 @@
+// Autotuner of the coarse-operator kernels.  Each candidate launch shape is
+// timed with HIP events on the caller's stream (optionally with the caches
+// flushed before every timed launch, so the links come from HBM), the fastest
+// is installed on the operator, and the result is cached in-process by
+// (lattice, N, storage, vector precision, nrhs) so operators of the same shape
+// reuse it.  The candidate spaces:
+//   single right-hand side: rows | N (rows >= 4 or rows = N), split | J with at
+//     least 2 chunks per thread, rows*split <= 1024, prefetch depth in {4, 8, 16};
+//   multi right-hand side: right-hand-side tiles per wave in {1, 2, 4}.
+#include "handles.h"
+
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+namespace qmg {
+qmg_status coarse_dslash_launch(const qmg_coarse_op_s* op, int rows, int split, int pre, const void* in,
+                                const float* in_scale, void* out, float* out_scale, qmg_prec vprec, hipStream_t s);
+qmg_status coarse_mrhs(qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int nrhs, int rpw,
+                       hipStream_t s);
+}  // namespace qmg
+
+using namespace qmg;
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int, int, int, int>;  // dims, N, storage, vprec, nrhs, cold
+struct Best { int a, b, c; float ms; };
+std::map<Key, Best>& cache() { static std::map<Key, Best> m; return m; }
+std::mutex& cache_mu() { static std::mutex m; return m; }
+
+struct Timer {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    void* flush = nullptr;
+    size_t flush_bytes = 0;
+    hipStream_t s;
+    qmg_status init(hipStream_t st, bool cold) {
+        s = st;
+        QMG_HIP(hipEventCreate(&e0));
+        QMG_HIP(hipEventCreate(&e1));
+        if (cold) {
+            flush_bytes = (size_t)1 << 30;
+            QMG_HIP(hipMalloc(&flush, flush_bytes));
+        }
+        return QMG_OK;
+    }
+    ~Timer() {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (flush) (void)hipFree(flush);
+    }
+    // median-free average of `reps` timed runs of f (each preceded by a flush when cold)
+    template <class F> qmg_status time(F f, int reps, float* ms) {
+        QMG_TRY(f());  // warm-up (also builds lazily created data)
+        float tot = 0;
+        for (int r = 0; r < reps; ++r) {
+            if (flush) QMG_HIP(hipMemsetAsync(flush, r & 0xff, flush_bytes, s));
+            QMG_HIP(hipEventRecord(e0, s));
+            QMG_TRY(f());
+            QMG_HIP(hipEventRecord(e1, s));
+            QMG_HIP(hipEventSynchronize(e1));
+            float t = 0;
+            QMG_HIP(hipEventElapsedTime(&t, e0, e1));
+            tot += t;
+        }
+        *ms = tot / reps;
+        return QMG_OK;
+    }
+};
+
+Key make_key(const qmg_coarse_op_s* op, qmg_prec vprec, int nrhs, int cold) {
+    return Key(op->dims[0], op->dims[1], op->dims[2], op->dims[3], op->N, (int)op->storage, (int)vprec, nrhs, cold);
+}
+
+}  // namespace
+
+extern "C" qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                                         float* out_scale, qmg_prec vprec, int cold, void* stream,
+                                         float* best_ms) {
+    if (!op || !in || !out) return fail(QMG_ERR_ARG, "coarse_op_tune: NULL argument");
+    const bool v16 = vprec == QMG_H16 || vprec == QMG_B16;
+    if (v16 && (!in_scale || !out_scale)) return fail(QMG_ERR_ARG, "coarse_op_tune: 16-bit vectors need scales");
+    hipStream_t s = as_stream(stream);
+    const Key key = make_key(op, vprec, 1, cold ? 1 : 0);
+    {
+        std::lock_guard<std::mutex> g(cache_mu());
+        auto it = cache().find(key);
+        if (it != cache().end()) {
+            op->rows = it->second.a;
+            op->split = it->second.b;
+            op->pre = it->second.c;
+            if (best_ms) *best_ms = it->second.ms;
+            return QMG_OK;
+        }
+    }
+    Timer tm;
+    QMG_TRY(tm.init(s, cold != 0));
+    Best best{op->rows, op->split, op->pre, 1e30f};
+    const int N = op->N, J = op->J;
+    for (int rows = 1; rows <= N; ++rows) {
+        if (N % rows || (rows < 4 && rows != N)) continue;
+        if (v16 && rows != N) continue;
+        for (int split = 1; split <= J; ++split) {
+            if (J % split || J / split < 2 || rows * split > 1024) continue;
+            const int64_t threads = op->V * N * (int64_t)split;
+            if (threads < (1 << 12) || threads > (1 << 23)) continue;
+            for (int pre : {4, 8, 16}) {
+                if (pre > J / split && pre != 4) continue;
+                float ms = 0;
+                QMG_TRY(tm.time([&]() { return coarse_dslash_launch(op, rows, split, pre, in, in_scale, out, out_scale, vprec, s); },
+                                cold ? 3 : 5, &ms));
+                if (ms < best.ms) best = Best{rows, split, pre, ms};
+            }
+        }
+    }
+    op->rows = best.a;
+    op->split = best.b;
+    op->pre = best.c;
+    if (best_ms) *best_ms = best.ms;
+    std::lock_guard<std::mutex> g(cache_mu());
+    cache()[key] = best;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
+                                              int nrhs, int cold, void* stream, float* best_ms) {
+    if (!op || !in || !in_scale || !out) return fail(QMG_ERR_ARG, "coarse_op_tune_mrhs: NULL argument");
+    if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
+        return fail(QMG_ERR_ARG, "coarse_op_tune_mrhs: nrhs %d not in {8,16,32,64}", nrhs);
+    if (op->storage != QMG_H16 && op->storage != QMG_B16)
+        return fail(QMG_ERR_PREC, "coarse_op_tune_mrhs: needs an operator with 16-bit storage");
+    hipStream_t s = as_stream(stream);
+    int lg = 0;
+    while ((1 << lg) < nrhs) ++lg;
+    const Key key = make_key(op, op->storage, nrhs, cold ? 1 : 0);
+    {
+        std::lock_guard<std::mutex> g(cache_mu());
+        auto it = cache().find(key);
+        if (it != cache().end()) {
+            op->rpw[lg] = it->second.a;
+            if (best_ms) *best_ms = it->second.ms;
+            return QMG_OK;
+        }
+    }
+    Timer tm;
+    QMG_TRY(tm.init(s, cold != 0));
+    Best best{0, 0, 0, 1e30f};
+    const int maxr = nrhs >= 64 ? 4 : nrhs >= 32 ? 2 : 1;
+    for (int r = 1; r <= maxr; r *= 2) {
+        float ms = 0;
+        QMG_TRY(tm.time([&]() { return coarse_mrhs(op, in, in_scale, out, nrhs, r, s); }, cold ? 3 : 5, &ms));
+        if (ms < best.ms) best = Best{r, 0, 0, ms};
+    }
+    op->rpw[lg] = best.a;
+    if (best_ms) *best_ms = best.ms;
+    std::lock_guard<std::mutex> g(cache_mu());
+    cache()[key] = best;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_coarse_op_get_prefetch(qmg_coarse_op op, int* pre) {
+    if (!op || !pre) return fail(QMG_ERR_ARG, "coarse_op_get_prefetch: NULL argument");
+    *pre = op->pre;
+    return QMG_OK;
+}
