@@ -134,6 +134,18 @@ qmg_status qmg_dequantize_sites(const void* in, const float* scale, void* out, l
 qmg_status qmg_coarse_dslash_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
                                   int nrhs, void* stream);
 
+/* One persistent launch applying several operators (the levels of a
+ * hierarchy, of different size; N in {48, 64}; all with the same 16-bit
+ * storage) to nrhs right-hand sides each: the sites of all operators form one
+ * work queue that `grid` work-groups (0: min(total sites, 2048)) walk until
+ * it is exhausted.  ops/in/in_scale/out are host arrays of nops (1..4)
+ * entries with the same meaning as in qmg_coarse_dslash_mrhs.  Launches no
+ * memset and allocates nothing once each operator has been applied in the
+ * multi-RHS form before, so it can be captured into a HIP graph. */
+qmg_status qmg_coarse_dslash_mrhs_multi(int nops, const qmg_coarse_op* ops, const void* const* in,
+                                        const float* const* in_scale, void* const* out, int nrhs, int grid,
+                                        void* stream);
+
 /* Tile shape of the multi-RHS kernel: each wave computes 16 rows x
  * (16 * rhs_tiles_per_wave) right-hand sides (1, 2 or 4; 0 = built-in). */
 qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, int rhs_tiles_per_wave);
@@ -331,6 +343,10 @@ qmg_status qmg_ptc_forward(qmg_ptc net, const void* r, void* y, void* stream);
 /* Add the loss |N(r) - e|^2/|e|^2 of one pair and its gradients
  * G = dL/dRe W + i dL/dIm W to the network's accumulators. */
 qmg_status qmg_ptc_accumulate_grad(qmg_ptc net, const void* r, const void* e, void* stream);
+/* Residual form of the loss for one residual r: add |r - M N(r)|^2/|r|^2
+ * (M = the Wilson-clover operator the network was created on) and its
+ * gradients, back-propagated through M^+ = gamma5 M gamma5. */
+qmg_status qmg_ptc_accumulate_grad_residual(qmg_ptc net, const void* r, void* stream);
 /* Clear the gradient and loss accumulators. */
 qmg_status qmg_ptc_zero_grad(qmg_ptc net, void* stream);
 /* Copy the accumulated gradients (DEVICE, same shapes as the weights) and the

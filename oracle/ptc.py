@@ -132,3 +132,23 @@ class Adam:
             upd_i = self.lr * (mi / c1) / (np.sqrt(vi / c2) + self.eps)
             out.append(W - (upd_r + 1j * upd_i))
         return out
+
+
+def loss_and_grads_residual(Ws, rs, U, dims, apply_M, antiperiodic_t=True):
+    """Residual form of the loss, L = sum_i |r_i - M N(r_i)|^2 / |r_i|^2, with M
+    given as a callable on [V][4][3] fields.  D = dL/dN* = M^+ (M N(r) - r)/|r|^2,
+    M^+ = gamma5 M gamma5 (gamma5-hermiticity of Eq. (2))."""
+    g5 = np.diag(lattice.gamma5()).real.astype(np.complex128)
+    flip = lambda v: v * g5[None, :, None]
+    L = 0.0
+    Gs = [np.zeros_like(W) for W in Ws]
+    for r in rs:
+        y, inputs = forward(Ws, r, U, dims, antiperiodic_t)
+        nr = float(np.vdot(r, r).real)
+        t = apply_M(y) - r
+        L += float(np.vdot(t, t).real) / nr
+        D = flip(apply_M(flip(t / nr)))[None]
+        for l in range(len(Ws) - 1, -1, -1):
+            G, D = layer_backward(Ws[l], inputs[l], D, U, dims, antiperiodic_t)
+            Gs[l] += G
+    return L, Gs

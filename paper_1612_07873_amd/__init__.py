@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
@@ -432,6 +432,10 @@ class PTC:
         _lib.call('qmg_ptc_accumulate_grad', self._h, _dev_ptr(r, torch.complex64, (self.V, 4, 3), 'r'),
                   _dev_ptr(e, torch.complex64, (self.V, 4, 3), 'e'), stream_ptr())
 
+    def accumulate_residual(self, r):
+        _lib.call('qmg_ptc_accumulate_grad_residual', self._h, _dev_ptr(r, torch.complex64, (self.V, 4, 3), 'r'),
+                  stream_ptr())
+
     def grad(self):
         s1, s2 = self.wshapes()
         G1 = torch.empty(s1, dtype=torch.complex64, device='cuda')
@@ -449,3 +453,18 @@ class PTC:
         if h is not None and h.value and _lib._lib is not None:
             _lib._lib.qmg_ptc_destroy(h)
             self._h = None
+
+
+def apply_mrhs_multi(ops, u16s, uscales, outs, grid=0):
+    """One persistent launch of the multi-RHS operator over several coarse operators
+    (qmg_coarse_dslash_mrhs_multi); u16s/uscales/outs as for CoarseOp.apply_mrhs."""
+    n = len(ops)
+    nrhs = int(u16s[0].shape[1])
+    P = ctypes.c_void_p * n
+    for op, u, sc, o in zip(ops, u16s, uscales, outs):
+        _dev_ptr(u, torch.int32, (op.V, nrhs, op.N), 'in')
+        _dev_ptr(sc, torch.float32, (op.V, nrhs), 'in_scale')
+        _dev_ptr(o, torch.complex64, (op.V, nrhs, op.N), 'out')
+    _lib.call('qmg_coarse_dslash_mrhs_multi', n, P(*[op._h.value for op in ops]), P(*[u.data_ptr() for u in u16s]),
+              P(*[s.data_ptr() for s in uscales]), P(*[o.data_ptr() for o in outs]), nrhs, int(grid), stream_ptr())
+    return outs

@@ -30,6 +30,8 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_float)]),
     'qmg_coarse_dslash_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_mrhs_tiles': (c_int, [c_void_p, c_int, c_int]),
+    'qmg_coarse_dslash_mrhs_multi': (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
+                                             ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int, c_int, c_void_p]),
     'qmg_coarse_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_quantize_sites': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, c_void_p]),
     'qmg_dequantize_sites': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_int, c_int, c_void_p]),
@@ -84,6 +86,7 @@ SIGNATURES.update({
     'qmg_ptc_forward': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_ptc_accumulate_grad': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_ptc_zero_grad': (c_int, [c_void_p, c_void_p]),
+    'qmg_ptc_accumulate_grad_residual': (c_int, [c_void_p, c_void_p, c_void_p]),
     'qmg_ptc_get_grad': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_double), c_void_p]),
     'qmg_ptc_adam_step': (c_int, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p]),
     'qmg_ptc_destroy': (None, [c_void_p]),

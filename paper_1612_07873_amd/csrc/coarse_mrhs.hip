@@ -65,90 +65,134 @@ __global__ void k_pack_mfma(uint4* __restrict__ M, const uint4* __restrict__ L, 
     M[g] = L[(site * J + e / 4) * N + row];
 }
 
+// Work of one coarse site; the work-group has `nthreads` threads, of which the
+// first NW waves compute (all of them stage).
 template <int F, int N, int NRHS, int RPW>
-__global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 64) void k_coarse_mrhs(
-    const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
-    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y) {
+__device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* __restrict__ M,
+                                          const float* __restrict__ lscale, const int* __restrict__ nbr,
+                                          const uint32_t* __restrict__ u, const float* __restrict__ uscale,
+                                          float2* __restrict__ y, unsigned char* smem) {
     constexpr int T = N / 16;                       // row tiles = k steps per direction
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;  // right-hand-side tiles
-    constexpr int NW = T * (NT / RPW);              // waves per work-group
+    constexpr int NW = T * (NT / RPW);              // computing waves
     constexpr int UW = NRHS * N;                    // dwords per input block in HBM
     constexpr int LD = N + 4;                       // LDS row stride (dwords), padded against bank conflicts
     constexpr int US = NRHS * LD;                   // dwords per staged block
-    extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* Us = reinterpret_cast<uint32_t*>(smem);       // [9][NRHS][LD]
     float* Sc = reinterpret_cast<float*>(Us + 9 * US);       // [9][NRHS]
 
-    const int site = blockIdx.x;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const bool computes = w < NW;
     const int rt = w % T, tg = w / T;
     const uint4* Ms = M + ((int64_t)site * 9 * T + rt) * T * 64 + l;
 
     uint4 Acur[T], Anext[T];
+    if (computes) {
 #pragma unroll
-    for (int ks = 0; ks < T; ++ks) Acur[ks] = Ms[(int64_t)ks * 64];
+        for (int ks = 0; ks < T; ++ks) Acur[ks] = Ms[(int64_t)ks * 64];
+    }
 
     // stage the nine input blocks and their scales
     for (int d = 0; d < 9; ++d) {
         const int src = d == 0 ? site : nbr[site * 8 + d - 1];
         const uint4* g = reinterpret_cast<const uint4*>(u + (int64_t)src * UW);
-        for (int i = threadIdx.x; i < UW / 4; i += NW * 64) {
+        for (int i = threadIdx.x; i < UW / 4; i += nthreads) {
             const int j = (4 * i) / N, c = (4 * i) % N;
             *reinterpret_cast<uint4*>(Us + d * US + j * LD + c) = g[i];
         }
         const float sl = lscale[(int64_t)site * 9 + d];
-        for (int j = threadIdx.x; j < NRHS; j += NW * 64) Sc[d * NRHS + j] = sl * uscale[(int64_t)src * NRHS + j];
+        for (int j = threadIdx.x; j < NRHS; j += nthreads) Sc[d * NRHS + j] = sl * uscale[(int64_t)src * NRHS + j];
     }
     __syncthreads();
-
-    f4v tot[RPW][2];
+    if (computes) {
+        f4v tot[RPW][2];
 #pragma unroll
-    for (int t = 0; t < RPW; ++t) tot[t][0] = tot[t][1] = f4v{0, 0, 0, 0};
-    const int jl = l % 16;
+        for (int t = 0; t < RPW; ++t) tot[t][0] = tot[t][1] = f4v{0, 0, 0, 0};
+        const int jl = l % 16;
 #pragma unroll
-    for (int d = 0; d < 9; ++d) {
-        if (d < 8) {
+        for (int d = 0; d < 9; ++d) {
+            if (d < 8) {
 #pragma unroll
-            for (int ks = 0; ks < T; ++ks) Anext[ks] = Ms[((int64_t)(d + 1) * T * T + ks) * 64];
-        }
-        f4v acc[RPW][2];
+                for (int ks = 0; ks < T; ++ks) Anext[ks] = Ms[((int64_t)(d + 1) * T * T + ks) * 64];
+            }
+            f4v acc[RPW][2];
 #pragma unroll
-        for (int t = 0; t < RPW; ++t) acc[t][0] = acc[t][1] = f4v{0, 0, 0, 0};
+            for (int t = 0; t < RPW; ++t) acc[t][0] = acc[t][1] = f4v{0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < T; ++ks) {
-            const uint4 a = Acur[ks];
-            const uint4 ar = make_uint4(a.x ^ 0x80000000u, a.y ^ 0x80000000u, a.z ^ 0x80000000u, a.w ^ 0x80000000u);
-            const uint4 ai = make_uint4(rot16(a.x), rot16(a.y), rot16(a.z), rot16(a.w));
+            for (int ks = 0; ks < T; ++ks) {
+                const uint4 a = Acur[ks];
+                const uint4 ar = make_uint4(a.x ^ 0x80000000u, a.y ^ 0x80000000u, a.z ^ 0x80000000u, a.w ^ 0x80000000u);
+                const uint4 ai = make_uint4(rot16(a.x), rot16(a.y), rot16(a.z), rot16(a.w));
+#pragma unroll
+                for (int t = 0; t < RPW; ++t) {
+                    const int j = (tg * RPW + t) * 16 + jl;
+                    uint4 b = make_uint4(0, 0, 0, 0);
+                    if (NRHS >= 16 || j < NRHS)
+                        b = *reinterpret_cast<const uint4*>(Us + d * US + j * LD + ks * 16 + 4 * (l / 16));
+                    acc[t][0] = mfma<F>(ar, b, acc[t][0]);
+                    acc[t][1] = mfma<F>(ai, b, acc[t][1]);
+                }
+            }
 #pragma unroll
             for (int t = 0; t < RPW; ++t) {
                 const int j = (tg * RPW + t) * 16 + jl;
-                uint4 b = make_uint4(0, 0, 0, 0);
-                if (NRHS >= 16 || j < NRHS)
-                    b = *reinterpret_cast<const uint4*>(Us + d * US + j * LD + ks * 16 + 4 * (l / 16));
-                acc[t][0] = mfma<F>(ar, b, acc[t][0]);
-                acc[t][1] = mfma<F>(ai, b, acc[t][1]);
+                const float sc = (NRHS >= 16 || j < NRHS) ? Sc[d * NRHS + j] : 0.0f;
+                tot[t][0] += sc * acc[t][0];
+                tot[t][1] += sc * acc[t][1];
+            }
+            if (d < 8) {
+#pragma unroll
+                for (int ks = 0; ks < T; ++ks) Acur[ks] = Anext[ks];
             }
         }
 #pragma unroll
         for (int t = 0; t < RPW; ++t) {
             const int j = (tg * RPW + t) * 16 + jl;
-            const float s = (NRHS >= 16 || j < NRHS) ? Sc[d * NRHS + j] : 0.0f;
-            tot[t][0] += s * acc[t][0];
-            tot[t][1] += s * acc[t][1];
-        }
-        if (d < 8) {
-#pragma unroll
-            for (int ks = 0; ks < T; ++ks) Acur[ks] = Anext[ks];
+            if (NRHS < 16 && j >= NRHS) continue;
+            float2* o = y + ((int64_t)site * NRHS + j) * N + rt * 16 + 4 * (l / 16);
+            float4* o4 = reinterpret_cast<float4*>(o);
+            o4[0] = make_float4(tot[t][0][0], tot[t][1][0], tot[t][0][1], tot[t][1][1]);
+            o4[1] = make_float4(tot[t][0][2], tot[t][1][2], tot[t][0][3], tot[t][1][3]);
         }
     }
-#pragma unroll
-    for (int t = 0; t < RPW; ++t) {
-        const int j = (tg * RPW + t) * 16 + jl;
-        if (NRHS < 16 && j >= NRHS) continue;
-        float2* o = y + ((int64_t)site * NRHS + j) * N + rt * 16 + 4 * (l / 16);
-        float4* o4 = reinterpret_cast<float4*>(o);
-        o4[0] = make_float4(tot[t][0][0], tot[t][1][0], tot[t][0][1], tot[t][1][1]);
-        o4[1] = make_float4(tot[t][0][2], tot[t][1][2], tot[t][0][3], tot[t][1][3]);
+}
+
+template <int F, int N, int NRHS, int RPW>
+__global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 64) void k_coarse_mrhs(
+    const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
+    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    mrhs_site<F, N, NRHS, RPW>(blockIdx.x, blockDim.x, M, lscale, nbr, u, uscale, y, smem);
+}
+
+// Persistent form over several operators ("levels") of possibly different
+// size and N in {48, 64}: work item i of the queue [level 0 sites, level 1
+// sites, ...] is taken by work-group i mod gridDim.x; work-groups loop until
+// the queue is exhausted (every work-group reaches the end).
+struct MultiLevel {
+    int nlev;
+    int64_t start[5];  // prefix offsets of the queue, start[nlev] = total
+    int N[4];
+    const uint4* M[4];
+    const float* lscale[4];
+    const int* nbr[4];
+    const uint32_t* u[4];
+    const float* uscale[4];
+    float2* y[4];
+};
+
+template <int F, int NRHS>
+__global__ __launch_bounds__(4 * (NRHS >= 16 ? NRHS / 16 : 1) * 64) void k_coarse_mrhs_multi(MultiLevel ml) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    for (int64_t item = blockIdx.x; item < ml.start[ml.nlev]; item += gridDim.x) {
+        int l = 0;
+        while (l + 1 < ml.nlev && item >= ml.start[l + 1]) ++l;
+        const int site = (int)(item - ml.start[l]);
+        if (ml.N[l] == 48)
+            mrhs_site<F, 48, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l], smem);
+        else
+            mrhs_site<F, 64, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l], smem);
+        __syncthreads();  // LDS is reused by the next item
     }
 }
 
@@ -244,4 +288,66 @@ extern "C" qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, i
     if (r > max_rpw(nrhs)) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: %d tiles exceed nrhs %d", r, nrhs);
     op->rpw[log2i(nrhs)] = r;
     return QMG_OK;
+}
+
+namespace qmg {
+template <int F, int NRHS>
+static qmg_status launch_multi(const MultiLevel& ml, size_t lds, int grid, hipStream_t s) {
+    auto kern = k_coarse_mrhs_multi<F, NRHS>;
+    if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(4 * NT * 64), lds, s, ml);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+}  // namespace qmg
+
+extern "C" qmg_status qmg_coarse_dslash_mrhs_multi(int nops, const qmg_coarse_op* ops, const void* const* in,
+                                                   const float* const* in_scale, void* const* out, int nrhs,
+                                                   int grid, void* stream) {
+    if (nops < 1 || nops > 4 || !ops || !in || !in_scale || !out)
+        return fail(QMG_ERR_ARG, "coarse_dslash_mrhs_multi: 1..4 operators with their fields");
+    if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
+        return fail(QMG_ERR_ARG, "coarse_dslash_mrhs_multi: nrhs %d not in {8,16,32,64}", nrhs);
+    if (grid < 0) return fail(QMG_ERR_ARG, "coarse_dslash_mrhs_multi: grid %d < 0", grid);
+    hipStream_t s = as_stream(stream);
+    MultiLevel ml{};
+    ml.nlev = nops;
+    int64_t tot = 0;
+    size_t lds = 0;
+    for (int i = 0; i < nops; ++i) {
+        qmg_coarse_op op = ops[i];
+        if (!op || !in[i] || !in_scale[i] || !out[i]) return fail(QMG_ERR_ARG, "coarse_dslash_mrhs_multi: NULL entry %d", i);
+        if (op->storage != ops[0]->storage || (op->storage != QMG_H16 && op->storage != QMG_B16))
+            return fail(QMG_ERR_PREC, "coarse_dslash_mrhs_multi: all operators need the same 16-bit storage");
+        if (op->N != 48 && op->N != 64) return fail(QMG_ERR_SHAPE, "coarse_dslash_mrhs_multi: N=%d not 48 or 64", op->N);
+        if (!op->mlinks) {  // operand-order links (not created inside a capture: call once beforehand)
+            const int T = op->N / 16;
+            const int64_t n = op->V * 9 * T * T * 64;
+            QMG_HIP(hipMalloc(&op->mlinks, (size_t)n * 16));
+            hipLaunchKernelGGL(k_pack_mfma, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint4*)op->mlinks,
+                               (const uint4*)op->links, op->V, op->N, op->J);
+            QMG_LAUNCH_CHECK();
+        }
+        ml.start[i] = tot;
+        tot += op->V;
+        ml.N[i] = op->N;
+        ml.M[i] = (const uint4*)op->mlinks;
+        ml.lscale[i] = op->lscale;
+        ml.nbr[i] = op->nbr;
+        ml.u[i] = (const uint32_t*)in[i];
+        ml.uscale[i] = in_scale[i];
+        ml.y[i] = (float2*)out[i];
+        const size_t l = 9 * (size_t)nrhs * (op->N + 4) * 4 + 9 * nrhs * 4;
+        if (l > lds) lds = l;
+    }
+    ml.start[nops] = tot;
+    if (grid == 0) grid = (int)(tot < 2048 ? tot : 2048);
+    const bool h = ops[0]->storage == QMG_H16;
+    switch (nrhs) {
+        case 8: return h ? launch_multi<MF_H16, 8>(ml, lds, grid, s) : launch_multi<MF_B16, 8>(ml, lds, grid, s);
+        case 16: return h ? launch_multi<MF_H16, 16>(ml, lds, grid, s) : launch_multi<MF_B16, 16>(ml, lds, grid, s);
+        case 32: return h ? launch_multi<MF_H16, 32>(ml, lds, grid, s) : launch_multi<MF_B16, 32>(ml, lds, grid, s);
+        default: return h ? launch_multi<MF_H16, 64>(ml, lds, grid, s) : launch_multi<MF_B16, 64>(ml, lds, grid, s);
+    }
 }

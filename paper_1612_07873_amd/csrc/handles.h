@@ -51,6 +51,7 @@ struct qmg_ptc_s {
     float2* D1;       // [C][V][12] dL/dh1*
     float2* y;        // [V][12] output
     float2* D2;       // [V][12] dL/dy*
+    float2 *t1, *t2;  // [V][12] scratch of the residual-form loss
     double* part;     // partial sums for reductions
     double* loss;     // [2]: accumulated loss, scratch
     int adam_t;

@@ -244,6 +244,18 @@ __global__ void k_ptc_adam(float2* __restrict__ W, const float2* __restrict__ G,
     W[i] = w;
 }
 
+// out = gamma5 in * scale  (chiral basis: spins 2, 3 change sign)
+__global__ void k_gamma5_scale(float2* __restrict__ out, const float2* __restrict__ in, const double* __restrict__ nrm,
+                               int use_norm, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float sc = 1.0f;
+    if (use_norm) sc = nrm[1] > 0 ? (float)(1.0 / nrm[1]) : 0.0f;
+    const int f = (int)(i % 12);
+    if (f >= 6) sc = -sc;
+    out[i] = make_float2(in[i].x * sc, in[i].y * sc);
+}
+
 static int ptc_blocks(int64_t V) {
     int64_t b = (V + kPtcThreads - 1) / kPtcThreads;
     return (int)(b > kPtcMaxBlocks ? kPtcMaxBlocks : b);
@@ -260,13 +272,15 @@ qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s) {
     return QMG_OK;
 }
 
+qmg_status ptc_backward(qmg_ptc t, const void* r, hipStream_t s);
+
 }  // namespace qmg
 
 using namespace qmg;
 
 extern "C" void qmg_ptc_destroy(qmg_ptc t) {
     if (!t) return;
-    float2* bufs[] = {t->W1, t->W2, t->G1, t->G2, t->m1, t->v1, t->m2, t->v2, t->h1, t->D1, t->y, t->D2};
+    float2* bufs[] = {t->W1, t->W2, t->G1, t->G2, t->m1, t->v1, t->m2, t->v2, t->h1, t->D1, t->y, t->D2, t->t1, t->t2};
     for (float2* b : bufs)
         if (b) (void)hipFree(b);
     if (t->part) (void)hipFree(t->part);
@@ -295,6 +309,8 @@ extern "C" qmg_status qmg_ptc_create(qmg_fine_op links, int hidden, void* stream
     if (e == hipSuccess) e = hipMalloc(&t->D1, sizeof(float2) * fv * hidden);
     if (e == hipSuccess) e = hipMalloc(&t->y, sizeof(float2) * fv);
     if (e == hipSuccess) e = hipMalloc(&t->D2, sizeof(float2) * fv);
+    if (e == hipSuccess) e = hipMalloc(&t->t1, sizeof(float2) * fv);
+    if (e == hipSuccess) e = hipMalloc(&t->t2, sizeof(float2) * fv);
     if (e == hipSuccess) e = hipMalloc(&t->part, sizeof(double) * kPtcMaxBlocks * 9 * hidden * 32);
     if (e == hipSuccess) e = hipMalloc(&t->loss, sizeof(double) * 2);
     for (float2** p : wb)
@@ -347,6 +363,34 @@ extern "C" qmg_status qmg_ptc_accumulate_grad(qmg_ptc t, const void* r, const vo
     hipLaunchKernelGGL(k_ptc_loss_final, dim3(1), dim3(64), 0, s, t->loss, t->part, nb);
     hipLaunchKernelGGL(k_ptc_dloss, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t->D2, t->y,
                        (const float2*)e, t->loss, n);
+    return ptc_backward(t, r, s);
+}
+
+extern "C" qmg_status qmg_ptc_accumulate_grad_residual(qmg_ptc t, const void* r, void* stream) {
+    if (!t || !r) return fail(QMG_ERR_ARG, "ptc_accumulate_grad_residual: NULL argument");
+    hipStream_t s = as_stream(stream);
+    const int64_t n = t->V * 12;
+    QMG_TRY(ptc_forward(t, r, t->y, s));
+    // t1 = M y ; loss += |M y - r|^2/|r|^2 ; t2 = (M y - r)/|r|^2 = dL/d(My)*
+    QMG_TRY(qmg_wilson_clover_dslash(t->op, t->y, t->t1, QMG_C64, stream));
+    const int nb = ptc_blocks(n);
+    hipLaunchKernelGGL(k_ptc_loss_part, dim3(nb), dim3(256), 0, s, t->part, t->t1, (const float2*)r, n);
+    hipLaunchKernelGGL(k_ptc_loss_final, dim3(1), dim3(64), 0, s, t->loss, t->part, nb);
+    hipLaunchKernelGGL(k_ptc_dloss, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, t->t2, t->t1,
+                       (const float2*)r, t->loss, n);
+    // D2 = M^+ t2 = gamma5 M gamma5 t2
+    const unsigned g = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_gamma5_scale, dim3(g), dim3(256), 0, s, t->t1, t->t2, t->loss, 0, n);
+    QMG_LAUNCH_CHECK();
+    QMG_TRY(qmg_wilson_clover_dslash(t->op, t->t1, t->t2, QMG_C64, stream));
+    hipLaunchKernelGGL(k_gamma5_scale, dim3(g), dim3(256), 0, s, t->D2, t->t2, t->loss, 0, n);
+    QMG_LAUNCH_CHECK();
+    return ptc_backward(t, r, s);
+}
+
+namespace qmg {
+qmg_status ptc_backward(qmg_ptc t, const void* r, hipStream_t s) {
+    const int64_t V = t->V;
     const float2* U = (const float2*)t->op->U;
     const int* nbr = t->op->nbr;
     const int C = t->C;
@@ -362,6 +406,7 @@ extern "C" qmg_status qmg_ptc_accumulate_grad(qmg_ptc t, const void* r, const vo
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
+}  // namespace qmg
 
 extern "C" qmg_status qmg_ptc_zero_grad(qmg_ptc t, void* stream) {
     if (!t) return fail(QMG_ERR_ARG, "ptc_zero_grad: NULL argument");

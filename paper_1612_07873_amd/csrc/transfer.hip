@@ -123,56 +123,100 @@ __global__ void k_to_c64(float2* __restrict__ o, const double2* __restrict__ i, 
     if (g < n) o[g] = make_float2((float)i[g].x, (float)i[g].y);
 }
 
-template <typename R>
-__global__ void k_prolong(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
-                          const cpx<R>* __restrict__ uc, const int* __restrict__ owner, int64_t V,
-                          int dof, int nvec) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= V * dof) return;
-    const int64_t x = g / dof;
-    const int f = (int)(g - x * dof);
-    const int chi = f / (dof / 2);
-    const cpx<R>* b = B + g * nvec;
-    const cpx<R>* u = uc + (int64_t)owner[x] * 2 * nvec + chi * nvec;
+// Prolongation: one thread per 16-byte chunk of the basis ([x][f][k] row
+// major, so a wave reads one contiguous span); the `cpr` chunks of a row (x, f)
+// are summed in LDS in a fixed order by the row's first thread.
+template <typename R, int CPC>
+__global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
+                                                 const cpx<R>* __restrict__ uc, const int* __restrict__ owner,
+                                                 int64_t V, int dof, int nvec, int rows_per_wg) {
+    constexpr int cpc = CPC;                       // complex per chunk
+    __shared__ cpx<R> part[256];
+    const int cpr = nvec / cpc;                    // chunks per row
+    const int t = threadIdx.x;
+    const int lr = t / cpr, kc = t - (t / cpr) * cpr;
+    const int64_t row = (int64_t)blockIdx.x * rows_per_wg + lr;
+    const bool active = lr < rows_per_wg && row < V * dof;
     R ar = 0, ai = 0;
-    for (int k = 0; k < nvec; ++k) cmac(ar, ai, b[k].re, b[k].im, u[k].re, u[k].im);
-    out[g] = cpx<R>{ar, ai};
+    if (active) {
+        const int64_t x = row / dof;
+        const int f = (int)(row - x * dof);
+        const int chi = f / (dof / 2);
+        const cpx<R>* u = uc + (int64_t)owner[x] * 2 * nvec + chi * nvec + kc * cpc;
+        const cpx<R>* b = B + row * nvec + kc * cpc;
+#pragma unroll
+        for (int q = 0; q < cpc; ++q) cmac(ar, ai, b[q].re, b[q].im, u[q].re, u[q].im);
+    }
+    part[t] = cpx<R>{ar, ai};
+    __syncthreads();
+    if (active && kc == 0) {
+        R sr = 0, si = 0;
+        for (int q = 0; q < cpr; ++q) {
+            sr += part[lr * cpr + q].re;
+            si += part[lr * cpr + q].im;
+        }
+        out[row] = cpx<R>{sr, si};
+    }
 }
 
-// One work-group per aggregate; thread (chi, k, part) sums a strided slice.
-template <typename R>
-__global__ __launch_bounds__(256) void k_restrict(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
-                                                   const cpx<R>* __restrict__ in,
-                                                   const int* __restrict__ members, int dof, int nvec,
-                                                   int bsites, int parts) {
+// Restriction: one work-group per aggregate; thread q owns chunk q of the
+// per-site basis block (dof x nvec, contiguous), loops over the aggregate's
+// sites accumulating conj(V) psi, then the dof/2 rows of each chirality are
+// summed in LDS in a fixed order.  No atomics; bitwise repeatable.
+template <typename R, int CPC>
+__global__ __launch_bounds__(1024) void k_restrict(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
+                                                   const cpx<R>* __restrict__ in, const int* __restrict__ members,
+                                                   int dof, int nvec, int bsites) {
+    constexpr int cpc = CPC;
     extern __shared__ __align__(16) unsigned char smem[];
-    cpx<R>* red = reinterpret_cast<cpx<R>*>(smem);  // [parts][2*nvec]
+    cpx<R>* acc_l = reinterpret_cast<cpx<R>*>(smem);   // [dof][nvec]
     const int64_t xc = blockIdx.x;
-    const int half = dof / 2;
-    const int nout = 2 * nvec;
-    const int t = threadIdx.x;
-    if (t < nout * parts) {
-        const int n = t % nout, part = t / nout;
-        const int chi = n / nvec, k = n - chi * nvec;
-        const int Lb = bsites * half;
-        R ar = 0, ai = 0;
-        for (int p = part; p < Lb; p += parts) {
-            const int64_t x = members[xc * bsites + p / half];
-            const int f = chi * half + p % half;
-            const cpx<R> b = B[(x * dof + f) * nvec + k];
-            const cpx<R> v = in[x * dof + f];
-            cmac_conj(ar, ai, b.re, b.im, v.re, v.im);
+    const int cpr = nvec / cpc;
+    const int nchunk = dof * cpr;
+    for (int q = threadIdx.x; q < nchunk; q += blockDim.x) {
+        const int f = q / cpr, kc = q - (q / cpr) * cpr;
+        R ar[cpc], ai[cpc];
+#pragma unroll
+        for (int c = 0; c < cpc; ++c) ar[c] = ai[c] = 0;
+        int b = 0;
+        for (; b + 4 <= bsites; b += 4) {
+            int64_t x[4];
+            cpx<R> v[4], bb[4][cpc];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                x[j] = members[xc * bsites + b + j];
+                v[j] = in[x[j] * dof + f];
+#pragma unroll
+                for (int c = 0; c < cpc; ++c) bb[j][c] = B[(x[j] * dof + f) * nvec + kc * cpc + c];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int c = 0; c < cpc; ++c) cmac_conj(ar[c], ai[c], bb[j][c].re, bb[j][c].im, v[j].re, v[j].im);
         }
-        red[part * nout + n] = cpx<R>{ar, ai};
+        for (; b < bsites; ++b) {
+            const int64_t x = members[xc * bsites + b];
+            const cpx<R> v = in[x * dof + f];
+#pragma unroll
+            for (int c = 0; c < cpc; ++c) {
+                const cpx<R> bv = B[(x * dof + f) * nvec + kc * cpc + c];
+                cmac_conj(ar[c], ai[c], bv.re, bv.im, v.re, v.im);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < cpc; ++c) acc_l[f * nvec + kc * cpc + c] = cpx<R>{ar[c], ai[c]};
     }
     __syncthreads();
-    if (t < nout) {
-        R ar = 0, ai = 0;
-        for (int q = 0; q < parts; ++q) {
-            ar += red[q * nout + t].re;
-            ai += red[q * nout + t].im;
+    const int half = dof / 2;
+    for (int n = threadIdx.x; n < 2 * nvec; n += blockDim.x) {
+        const int chi = n / nvec, k = n - chi * nvec;
+        R sr = 0, si = 0;
+        for (int ff = 0; ff < half; ++ff) {
+            const cpx<R> a = acc_l[(chi * half + ff) * nvec + k];
+            sr += a.re;
+            si += a.im;
         }
-        out[xc * nout + t] = cpx<R>{ar, ai};
+        out[xc * 2 * nvec + n] = cpx<R>{sr, si};
     }
 }
 
@@ -305,32 +349,42 @@ extern "C" qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* str
 }
 
 namespace qmg {
-qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
-    const int64_t n = t->V * t->dof;
-    const unsigned nb = (unsigned)((n + 255) / 256);
-    if (p == QMG_C128)
-        hipLaunchKernelGGL(k_prolong<double>, dim3(nb), dim3(256), 0, s, (cpx<double>*)out,
-                           (const cpx<double>*)t->basis64, (const cpx<double>*)in, t->owner, t->V, t->dof, t->nvec);
-    else
-        hipLaunchKernelGGL(k_prolong<float>, dim3(nb), dim3(256), 0, s, (cpx<float>*)out,
-                           (const cpx<float>*)t->basis, (const cpx<float>*)in, t->owner, t->V, t->dof, t->nvec);
+template <typename R, int CPC>
+static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void* out, hipStream_t s) {
+    const int cpr = t->nvec / CPC;
+    const int rows_per_wg = 256 / cpr;
+    const int64_t rows = t->V * t->dof;
+    const unsigned nb = (unsigned)((rows + rows_per_wg - 1) / rows_per_wg);
+    hipLaunchKernelGGL((k_prolong<R, CPC>), dim3(nb), dim3(256), 0, s, (cpx<R>*)out, (const cpx<R>*)B,
+                       (const cpx<R>*)in, t->owner, t->V, t->dof, t->nvec, rows_per_wg);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
-qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
-    const int nout = 2 * t->nvec;
-    const int parts = 256 / nout;
-    if (p == QMG_C128)
-        hipLaunchKernelGGL(k_restrict<double>, dim3((unsigned)t->Vc), dim3(256), sizeof(cpx<double>) * nout * parts, s,
-                           (cpx<double>*)out, (const cpx<double>*)t->basis64, (const cpx<double>*)in, t->members,
-                           t->dof, t->nvec, t->bsites, parts);
-    else
-        hipLaunchKernelGGL(k_restrict<float>, dim3((unsigned)t->Vc), dim3(256), sizeof(cpx<float>) * nout * parts, s,
-                           (cpx<float>*)out, (const cpx<float>*)t->basis, (const cpx<float>*)in, t->members,
-                           t->dof, t->nvec, t->bsites, parts);
+template <typename R, int CPC>
+static qmg_status restrict_t(qmg_transfer t, const void* B, const void* in, void* out, hipStream_t s) {
+    const int nchunk = t->dof * (t->nvec / CPC);
+    int threads = ((nchunk + 63) / 64) * 64;
+    if (threads > 1024) threads = 1024;
+    const size_t lds = sizeof(cpx<R>) * t->dof * t->nvec;
+    if (lds > 65536)
+        QMG_HIP(hipFuncSetAttribute((const void*)k_restrict<R, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL((k_restrict<R, CPC>), dim3((unsigned)t->Vc), dim3(threads), lds, s, (cpx<R>*)out,
+                       (const cpx<R>*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
+}
+
+qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
+    if (p == QMG_C128) return prolong_t<double, 1>(t, t->basis64, in, out, s);
+    if (t->nvec % 2) return prolong_t<float, 1>(t, t->basis, in, out, s);
+    return prolong_t<float, 2>(t, t->basis, in, out, s);
+}
+
+qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
+    if (p == QMG_C128) return restrict_t<double, 1>(t, t->basis64, in, out, s);
+    if (t->nvec % 2) return restrict_t<float, 1>(t, t->basis, in, out, s);
+    return restrict_t<float, 2>(t, t->basis, in, out, s);
 }
 }  // namespace qmg
 

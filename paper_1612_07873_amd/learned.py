@@ -4,7 +4,9 @@ Pairs: for each right-hand side b the multigrid solve records its outer
 iterates x_k; with the converged x*, e_k = x* - x_k and r_k = M e_k (both made
 by the library, qmg_mg_make_pairs).  Pairs whose error has fallen below
 `min_rel_err` of |x*| are dropped (they carry little beyond rounding).
-Training: Adam on the loss sum_i |N(r_i) - e_i|^2/|e_i|^2 over mini-batches,
+Training: Adam on the loss sum_i |N(r_i) - e_i|^2/|e_i|^2 (or its residual
+form sum_i |r_i - M N(r_i)|^2/|r_i|^2, which asks the network for exactly what
+the solver's fallback test checks) over mini-batches,
 every forward, backward and update in the library's kernels; random numbers
 (initial weights, batch order) come from the caller.
 """
@@ -42,8 +44,9 @@ def initial_weights(hidden, m0, gen):
     return W1.astype(np.complex64), W2.astype(np.complex64)
 
 
-def train(net, R, E, epochs, batch, lr, gen, log_every=1):
-    """Adam over shuffled mini-batches; returns the mean loss per epoch."""
+def train(net, R, E, epochs, batch, lr, gen, log_every=1, loss='error'):
+    """Adam over shuffled mini-batches; returns the mean loss per epoch.
+    loss='error': |N(r) - e|^2/|e|^2; loss='residual': |r - M N(r)|^2/|r|^2."""
     n = R.shape[0]
     hist = []
     for ep in range(epochs):
@@ -53,7 +56,10 @@ def train(net, R, E, epochs, batch, lr, gen, log_every=1):
             net.zero_grad()
             idx = order[s:s + batch]
             for i in idx:
-                net.accumulate(R[int(i)], E[int(i)])
+                if loss == 'residual':
+                    net.accumulate_residual(R[int(i)])
+                else:
+                    net.accumulate(R[int(i)], E[int(i)])
             if ep % log_every == 0 or ep == epochs - 1:
                 tot += net.grad()[2]
             net.adam_step(lr=lr)
@@ -61,8 +67,11 @@ def train(net, R, E, epochs, batch, lr, gen, log_every=1):
     return hist
 
 
-def mean_loss(net, R, E):
+def mean_loss(net, R, E, loss='error'):
     net.zero_grad()
     for i in range(R.shape[0]):
-        net.accumulate(R[i], E[i])
+        if loss == 'residual':
+            net.accumulate_residual(R[i])
+        else:
+            net.accumulate(R[i], E[i])
     return net.grad()[2] / R.shape[0]

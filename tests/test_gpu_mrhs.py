@@ -83,3 +83,57 @@ def test_mrhs_rejects_bad_arguments():
         g16.apply_mrhs(u12, torch.ones((V, 12), dtype=torch.float32, device='cuda'))   # nrhs 12
     with pytest.raises(QmgError):
         g16.set_mrhs_tiles(16, 2)                 # only one 16-wide tile at nrhs 16
+
+
+def _level(cd, N, nrhs, seed):
+    from paper_1612_07873_amd import CoarseOp, quantize_sites
+    V = lattice.volume(cd)
+    g = CoarseOp(cd, dev(synth.gaussian((V, N, N), seed, 2)), dev(synth.gaussian((8, V, N, N), seed + 1, 2)), 'h16')
+    u = np.stack([synth.gaussian((V, N), seed + 10 + j, 2) for j in range(nrhs)], axis=1)
+    q, s = quantize_sites(dev(u.reshape(V * nrhs, N), torch.complex64), 'h16')
+    return g, q.reshape(V, nrhs, N), s.reshape(V, nrhs)
+
+
+@pytest.mark.parametrize('nrhs', [16, 64])
+def test_persistent_multi_level_launch_in_a_graph(nrhs):
+    """8^3x16 (N 48), 4^3x8 (N 64) and 2^4 (N 48) in one persistent launch, captured
+    in a HIP graph and replayed several times between eager work: every replay
+    equals the per-level launches bitwise."""
+    from paper_1612_07873_amd import apply_mrhs_multi
+    levels = [_level((8, 8, 8, 16), 48, nrhs, 0), _level((4, 4, 4, 8), 64, nrhs, 100), _level((2, 2, 2, 2), 48, nrhs, 200)]
+    ops = [l[0] for l in levels]
+    ref = [op.apply_mrhs(q, s) for op, q, s in levels]          # also builds the operand-order links
+    outs = [torch.empty_like(r) for r in ref]
+    apply_mrhs_multi(ops, [l[1] for l in levels], [l[2] for l in levels], outs)
+    torch.cuda.synchronize()
+    for o, r in zip(outs, ref):
+        assert torch.equal(o, r)
+    for grid in (7, 256):      # any grid walks the whole queue
+        outs2 = [torch.zeros_like(r) for r in ref]
+        apply_mrhs_multi(ops, [l[1] for l in levels], [l[2] for l in levels], outs2, grid=grid)
+        torch.cuda.synchronize()
+        assert all(torch.equal(o, r) for o, r in zip(outs2, ref))
+    gout = [torch.zeros_like(r) for r in ref]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            apply_mrhs_multi(ops, [l[1] for l in levels], [l[2] for l in levels], gout)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(4):
+        for o in gout:
+            o.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert all(torch.equal(o, r) for o, r in zip(gout, ref)), rep
+        _ = [op.apply_mrhs(q, sc) for op, q, sc in levels]      # eager work between replays
+    # parity of the coarsest level with the oracle (dequantised inputs)
+    from paper_1612_07873_amd import dequantize_sites
+    op, q, sc = levels[2]
+    Xq, Yq = (host(t) for t in op.export())
+    V = 16
+    ud = host(dequantize_sites(q.reshape(V * nrhs, 48), sc.reshape(-1), 'h16')).reshape(V, nrhs, 48)
+    refo = np.transpose(coarse.CoarseOp((2, 2, 2, 2), Xq, Yq).apply(np.ascontiguousarray(np.transpose(ud, (0, 2, 1)))), (0, 2, 1))
+    assert np.abs(host(gout[2]) - refo).max() <= 1e-5 * np.abs(refo).max()

@@ -48,6 +48,28 @@ def test_forward_and_gradients_match_oracle():
     assert rel_err(A1, N1) <= 1e-5 and rel_err(A2, N2) <= 1e-5
 
 
+def test_residual_loss_matches_oracle():
+    from paper_1612_07873_amd import PTC, FineOp
+    dims, C, m0 = (4, 4, 2, 8), 4, -0.2
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 6)
+    A = wilson.clover_field(U, dims, 1.0)
+    net = PTC(FineOp(dims, dev(U), m0, 1.0, True, 'c64'), C)
+    W1, W2 = weights(C, 7)
+    net.set_weights(dev(W1, torch.complex64), dev(W2, torch.complex64))
+    q = lambda a: a.astype(np.complex64).astype(np.complex128)
+    rs = [synth.gaussian((V, 4, 3), 50 + i, 2) for i in range(2)]
+    net.zero_grad()
+    for r in rs:
+        net.accumulate_residual(dev(r, torch.complex64))
+    G1, G2, L = net.grad()
+    M = lambda v: wilson.apply_wilson_clover(v, U, A, m0, dims)
+    Lo, (G1o, G2o) = optc.loss_and_grads_residual([q(W1), q(W2)], [q(r) for r in rs], U, dims, M)
+    print('residual loss gpu %.8f oracle %.8f; grad errs %.2e %.2e' % (L, Lo, rel_err(host(G1), G1o), rel_err(host(G2), G2o)))
+    assert abs(L - Lo) <= 1e-5 * Lo
+    assert rel_err(host(G1), G1o) <= 1e-4 and rel_err(host(G2), G2o) <= 1e-4
+
+
 def test_wilson_weights_reproduce_the_wilson_kernel():
     """hidden = 1, W1 = identity, W2 = Wilson stencil weights: the network is M at c_sw = 0."""
     from paper_1612_07873_amd import PTC, FineOp
@@ -105,6 +127,14 @@ def test_training_on_solver_pairs_and_mg_with_learned_smoother():
     L1 = learned.mean_loss(net, R, E)
     print('training loss %.4f -> %.4f' % (L0, L1), ['%.4f' % h for h in hist])
     assert L1 < L0
+    # the residual form of the loss on the same residuals
+    net_r = PTC(FineOp(dims, dev(U), m0, 1.0, True, 'c64'), 8)
+    net_r.set_weights(dev(W1, torch.complex64), dev(W2, torch.complex64))
+    Lr0 = learned.mean_loss(net_r, R, E, loss='residual')
+    learned.train(net_r, R, E, epochs=6, batch=8, lr=2e-3, gen=gen, loss='residual')
+    Lr1 = learned.mean_loss(net_r, R, E, loss='residual')
+    print('residual-form training loss %.4f -> %.4f' % (Lr0, Lr1))
+    assert Lr1 < Lr0
     b = synth.gaussian((V, 4, 3), 7, 2)
     _, base = mg.solve(dev(b))
     mg.set_smoother(net)
@@ -118,4 +148,9 @@ def test_training_on_solver_pairs_and_mg_with_learned_smoother():
     x, info2 = mg.solve(dev(b))
     assert info2['converged'] and info2['smoother_fallbacks'] > 0
     assert info2['outer_iters'] == base['outer_iters']
+    mg.set_smoother(net_r)
+    x, info3 = mg.solve(dev(b))
+    tr = np.linalg.norm(b - wilson.apply_wilson_clover_c(host(x), U, A, m0, dims)) / np.linalg.norm(b)
+    print('residual-trained smoother', info3, 'oracle-M residual %.2e' % tr)
+    assert info3['converged'] and tr <= 1e-10
     mg.set_smoother(None)

@@ -93,3 +93,27 @@ def test_adam_decreases_the_loss():
         Ws = opt.step(Ws, G)
     L1, _ = ptc.loss_and_grads(Ws, pairs, U, dims)
     assert L1 < 0.5 * L0
+
+
+def test_residual_loss_gradients_match_finite_differences():
+    dims = (2, 2, 2, 4)
+    U, V = setup(dims, 6)
+    A = wilson.clover_field(U, dims, 1.0)
+    M = lambda v: wilson.apply_wilson_clover(v, U, A, -0.1, dims)
+    Ws = [0.3 * synth.gaussian((9, 2, 1, 4, 4), 11, 4), 0.3 * synth.gaussian((9, 1, 2, 4, 4), 12, 4)]
+    rs = [synth.gaussian((V, 4, 3), 40 + i, 2) for i in range(2)]
+    L, Gs = ptc.loss_and_grads_residual(Ws, rs, U, dims, M)
+    rng = np.random.default_rng(1)
+    h = 1e-6
+    for l in range(2):
+        for _ in range(10):
+            idx = tuple(int(rng.integers(0, s)) for s in Ws[l].shape)
+            num = 0j
+            for unit in (1.0, 1j):
+                Wp = [w.copy() for w in Ws]
+                Wm = [w.copy() for w in Ws]
+                Wp[l][idx] += h * unit
+                Wm[l][idx] -= h * unit
+                num += unit * (ptc.loss_and_grads_residual(Wp, rs, U, dims, M)[0]
+                               - ptc.loss_and_grads_residual(Wm, rs, U, dims, M)[0]) / (2 * h)
+            assert abs(num - Gs[l][idx]) <= 1e-6 * max(1.0, abs(Gs[l][idx])), (l, idx, num, Gs[l][idx])
