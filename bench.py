@@ -125,6 +125,94 @@ def precision_and_mrhs(steps):
     return out
 
 
+def build_mg_16x32():
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import Multigrid
+    dev = torch.device('cuda')
+    dims = (16, 16, 16, 32)
+    m0 = -0.25
+    m0_src = 'provisional'
+    if os.path.exists(MG_M0_FILE):
+        with open(MG_M0_FILE) as f:
+            m0 = float(json.load(f)['m0'])
+        m0_src = 'tests/golden/config2_m0.json'
+    V = int(np.prod(dims))
+    U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
+    levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10),
+              dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100)]
+    starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
+              torch.from_numpy(synth.gaussian((32, 512, 48), 1, 1)).to(dev)]
+    t0 = time.perf_counter()
+    mg = Multigrid(dims, U, m0, 1.0, levels, starts, inner='c64')
+    torch.cuda.synchronize()
+    return mg, U, m0, m0_src, time.perf_counter() - t0
+
+
+def timed_solves(mg, nsolves, seed0):
+    import numpy as np
+    import torch
+    import synth
+    times, iters, res, fb = [], [], [], []
+    for i in range(nsolves):
+        b = torch.from_numpy(synth.gaussian((mg.V, 4, 3), seed0 + i, 2)).to('cuda')
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = mg.solve(b, tol=1e-10)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+        iters.append(info['outer_iters'])
+        res.append(info['true_rel_residual'])
+        fb.append(info['smoother_fallbacks'])
+    t = np.array(times[1:])
+    return {'solves': nsolves, 'time_to_1e-10_s': round(float(t.mean()), 4), 'std_s': round(float(t.std()), 4),
+            'outer_iters_mean': float(np.mean(iters[1:])), 'level_iters_last': info['level_iters'],
+            'max_true_rel_residual': float(max(res)), 'smoother_fallbacks_mean': float(np.mean(fb[1:]))}
+
+
+def learned(npairs, epochs, loss):
+    """Learned-smoother comparison on 16^3x32: pairs from the solver, training on the GPU."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import PTC, FineOp, learned as L
+    mg, U, m0, m0_src, setup = build_mg_16x32()
+    dims = (16, 16, 16, 32)
+    plain = timed_solves(mg, 12, 1000)
+    t0 = time.perf_counter()
+    R, E, n = [], [], 0
+    seed = 2000
+    while n < npairs:
+        b = torch.from_numpy(synth.gaussian((mg.V, 4, 3), seed, 2)).to('cuda')
+        r, e, _ = L.generate_pairs(mg, [b], maxrec=40)
+        if loss == 'residual':
+            e = e[:0]
+        R.append(r)
+        E.append(e)
+        n += r.shape[0]
+        seed += 1
+    R = torch.cat(R)[:npairs]
+    E = torch.cat(E)[:npairs] if loss != 'residual' else R[:0]
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    net = PTC(FineOp(dims, U, m0, 1.0, True, 'c64'), 8)
+    gen = np.random.default_rng(0)
+    W1, W2 = L.initial_weights(8, m0, gen)
+    net.set_weights(torch.from_numpy(W1).cuda(), torch.from_numpy(W2).cuda())
+    t0 = time.perf_counter()
+    hist = L.train(net, R, E, epochs=epochs, batch=16, lr=2e-3, gen=gen, loss=loss)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    mg.set_smoother(net)
+    withnet = timed_solves(mg, 12, 1000)
+    mg.set_smoother(None)
+    return {'lattice': list(dims), 'm0': m0, 'pairs': int(R.shape[0]), 'pair_seconds': round(t_pairs, 2),
+            'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
+            'train_seconds': round(t_train, 2), 'mg_with_MR': plain, 'mg_with_learned': withnet,
+            'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3)}
+
+
 def mg_gcr(nsolves=12):
     import numpy as np
     import torch
@@ -174,6 +262,10 @@ def main():
     ap.add_argument('--warmup', type=int, default=200)
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle leg')
     ap.add_argument('--only-headline', action='store_true', help='time the headline kernel only')
+    ap.add_argument('--learned', action='store_true', help='learned-smoother comparison on 16^3x32 instead')
+    ap.add_argument('--pairs', type=int, default=512)
+    ap.add_argument('--epochs', type=int, default=4)
+    ap.add_argument('--loss', choices=['error', 'residual'], default='residual')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py measures one GPU only: the multigrid hot path is built and timed on a single MI355X; '
@@ -185,13 +277,18 @@ def main():
     import synth
     from paper_1612_07873_amd import CoarseOp
 
+    if args.learned:
+        print(json.dumps({'learned_smoother': learned(args.pairs, args.epochs, args.loss)}), flush=True)
+        return
     dev = torch.device('cuda')
     # a plain device copy of known size (512 MiB read, 512 MiB written), outside
     # any timed region: under a counter run it calibrates FETCH_SIZE / WRITE_SIZE
     calib = torch.ones(1 << 26, dtype=torch.complex64, device=dev)
-    torch.empty_like(calib).copy_(calib)
-    torch.cuda.synchronize()
-    del calib
+    dst = torch.empty_like(calib)
+    dst.copy_(calib)
+    copy_ms = timed(lambda i: dst.copy_(calib), 10, 2)      # achievable copy bandwidth on this machine
+    copy_gbs = 2 * calib.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    del calib, dst
     cd, N = (4, 4, 4, 8), 48
     V = int(np.prod(cd))
     X = synth.gaussian((V, N, N), 0, 2)
@@ -224,7 +321,9 @@ def main():
                               'tuned_cold_ms': round(tuned_ms, 5)}},
         'roofline': {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
                      'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
-                     'algorithmic_bytes_per_launch': byts, 'kernel': 'qmg::k_coarse_dslash<1,0,16> (FP32)'},
+                     'algorithmic_bytes_per_launch': byts, 'kernel': 'qmg::k_coarse_dslash (FP32 links)',
+                     'achievable_copy_GB/s': round(copy_gbs, 1),
+                     'frac_of_achievable_copy': round(achieved / copy_gbs, 4)},
     }
     warm_ms = timed(lambda i: ops[0].apply(ud, out), 500, 50)
     rec['warm_cache'] = {'ms_per_step': round(warm_ms, 6), 'GFLOP/s': round(flops / (warm_ms * 1e-3) / 1e9, 2),
