@@ -28,6 +28,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'coarse_dslash_4x4x4x8_N48_c64_traffic.json')
+
+
+def measured_traffic(launch):
+    """HBM bytes per launch of the headline kernel from the counter summary, if it
+    was taken on this kernel source and launch shape; else None."""
+    import hashlib
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        rec = json.load(f)
+    src = os.path.join(ROOT, 'paper_1612_07873_amd', 'csrc', 'coarse_dslash.hip')
+    sha = hashlib.sha256(open(src, 'rb').read()).hexdigest()
+    if rec.get('source_sha256') != sha or rec.get('launch') != launch:
+        return None
+    return rec['traffic_bytes_per_launch']
 MG_M0_FILE = os.path.join(ROOT, 'tests', 'golden', 'config2_m0.json')
 
 
@@ -320,7 +336,8 @@ def main():
                    'launch': {'rows': ops[0].launch()[0], 'split': ops[0].launch()[1], 'prefetch': ops[0].prefetch(),
                               'tuned_cold_ms': round(tuned_ms, 5)}},
         'roofline': {'bound': 'hbm', 'achieved': round(achieved, 1), 'peak': HBM_PEAK_GBS, 'unit': 'GB/s',
-                     'frac': round(achieved / HBM_PEAK_GBS, 4), 'traffic': None,
+                     'frac': round(achieved / HBM_PEAK_GBS, 4),
+                     'traffic': measured_traffic([ops[0].launch()[0], ops[0].launch()[1], ops[0].prefetch()]),
                      'algorithmic_bytes_per_launch': byts, 'kernel': 'qmg::k_coarse_dslash (FP32 links)',
                      'achievable_copy_GB/s': round(copy_gbs, 1),
                      'frac_of_achievable_copy': round(achieved / copy_gbs, 4)},

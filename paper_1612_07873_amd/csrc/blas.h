@@ -36,6 +36,13 @@ struct Blas {
     template <typename R> qmg_status axpy(double a, const void* x, void* y, int64_t n);       // y += a x
     template <typename R> qmg_status xmy(const void* b, const void* ax, void* r, int64_t n);  // r = b - ax
     template <typename Rs, typename Rd> qmg_status convert(const void* src, void* dst, int64_t n);
+    // A whole GCR step after q = A z for vectors of at most kSmall entries, in one
+    // work-group: CGS2 of (q, z) against the k stored pairs, normalisation,
+    // x += alpha z, r -= alpha q; out = [<q,q>, <q,r>.re, <q,r>.im, |r|^2];
+    // znext (may be NULL) receives the new r.
+    static constexpr int64_t kSmall = 1 << 13;
+    template <typename R> qmg_status gcr_step_small(const void* Q, const void* Z, int64_t ld, int k, void* q, void* z,
+                                                    void* x, void* r, int64_t n, double* out, void* znext);
     // x /= sqrt(nrm2[0])
     template <typename R> qmg_status normalize(void* x, const double* nrm2, int64_t n);
 };

@@ -4,7 +4,7 @@
 namespace qmg {
 
 static constexpr int kThreads = 256;
-static constexpr int64_t kOneBlock = 1 << 15;  // up to this many entries one 1024-thread block reduces alone
+static constexpr int64_t kOneBlock = 1 << 12;  // up to this many entries one 1024-thread block reduces alone
 
 static int nblocks(int64_t n) {
     if (n <= kOneBlock) return 1;
@@ -225,6 +225,126 @@ __global__ void k_normalize(cpx<R>* __restrict__ x, const double* __restrict__ n
     x[i].im *= inv;
 }
 
+// One whole GCR step after q = A z, for short vectors, in a single work-group:
+// two classical Gram-Schmidt passes of (q, z) against the k stored pairs,
+// normalisation, x += alpha z, r -= alpha q, and |r|^2.  out = [<q,q>,
+// <q,r>.re, <q,r>.im, |r|^2] (before normalisation for the first three).  When
+// znext is given it receives r (the next step's unpreconditioned direction).
+template <typename R>
+__global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restrict__ Q, const cpx<R>* __restrict__ Z,
+                                                         int64_t ld, int k, cpx<R>* __restrict__ q,
+                                                         cpx<R>* __restrict__ z, cpx<R>* __restrict__ x,
+                                                         cpx<R>* __restrict__ r, int64_t n, double* __restrict__ out,
+                                                         cpx<R>* __restrict__ znext) {
+    __shared__ double lds[16];
+    __shared__ double sc[40];
+    __shared__ double part[16][32];
+    const int t = threadIdx.x, T = blockDim.x;
+    const int w = t >> 6, lane = t & 63, nw = T >> 6;
+    for (int pass = 0; pass < 2; ++pass) {
+        // all k inner products in one sweep, then one combined work-group reduction
+        double acc[32];
+#pragma unroll
+        for (int v = 0; v < 32; ++v) acc[v] = 0;
+        for (int64_t i = t; i < n; i += T) {
+            const cpx<R> b = q[i];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < k) {
+                    const cpx<R> a = Q[j * ld + i];
+                    acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+                    acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
+                }
+        }
+#pragma unroll
+        for (int v = 0; v < 32; ++v) {
+            if (v < 2 * k) {
+                double x = acc[v];
+                for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+                if (lane == 0) part[w][v] = x;
+            }
+        }
+        __syncthreads();
+        if (t < 2 * k) {
+            double x = 0;
+            for (int i = 0; i < nw; ++i) x += part[i][t];
+            sc[t] = x;
+        }
+        __syncthreads();
+        for (int64_t i = t; i < n; i += T) {
+            R qr = q[i].re, qi = q[i].im, zr = z[i].re, zi = z[i].im;
+            for (int j = 0; j < k; ++j) {
+                const R br = (R)sc[2 * j], bi = (R)sc[2 * j + 1];
+                const cpx<R> a = Q[j * ld + i], c = Z[j * ld + i];
+                qr -= br * a.re - bi * a.im;
+                qi -= br * a.im + bi * a.re;
+                zr -= br * c.re - bi * c.im;
+                zi -= br * c.im + bi * c.re;
+            }
+            q[i] = cpx<R>{qr, qi};
+            z[i] = cpx<R>{zr, zi};
+        }
+        __syncthreads();
+    }
+    double qq = 0, re = 0, im = 0;
+    for (int64_t i = t; i < n; i += T) {
+        const cpx<R> a = q[i], b = r[i];
+        qq += (double)a.re * a.re + (double)a.im * a.im;
+        re += (double)a.re * b.re + (double)a.im * b.im;
+        im += (double)a.re * b.im - (double)a.im * b.re;
+    }
+    qq = wg_sum(qq, lds);
+    re = wg_sum(re, lds);
+    im = wg_sum(im, lds);
+    if (t == 0) { sc[0] = qq; sc[1] = re; sc[2] = im; }
+    __syncthreads();
+    qq = sc[0];
+    re = sc[1];
+    im = sc[2];
+    double rr = 0;
+    if (qq > 0) {
+        const double nq = sqrt(qq);
+        const R inv = (R)(1.0 / nq), ar = (R)(re / nq), ai = (R)(im / nq);
+        for (int64_t i = t; i < n; i += T) {
+            cpx<R> a = q[i], c = z[i], xx = x[i], b = r[i];
+            a.re *= inv; a.im *= inv;
+            c.re *= inv; c.im *= inv;
+            xx.re += ar * c.re - ai * c.im;
+            xx.im += ar * c.im + ai * c.re;
+            b.re -= ar * a.re - ai * a.im;
+            b.im -= ar * a.im + ai * a.re;
+            q[i] = a;
+            z[i] = c;
+            x[i] = xx;
+            r[i] = b;
+            if (znext) znext[i] = b;
+            rr += (double)b.re * b.re + (double)b.im * b.im;
+        }
+    } else {
+        for (int64_t i = t; i < n; i += T) {
+            const cpx<R> b = r[i];
+            if (znext) znext[i] = b;
+            rr += (double)b.re * b.re + (double)b.im * b.im;
+        }
+    }
+    rr = wg_sum(rr, lds);
+    if (t == 0) {
+        out[0] = qq;
+        out[1] = re;
+        out[2] = im;
+        out[3] = rr;
+    }
+}
+
+template <typename R>
+qmg_status Blas::gcr_step_small(const void* Q, const void* Z, int64_t ld, int k, void* q, void* z, void* x, void* r,
+                                int64_t n, double* out, void* znext) {
+    hipLaunchKernelGGL(k_gcr_step_small<R>, dim3(1), dim3(1024), 0, s, (const cpx<R>*)Q, (const cpx<R>*)Z, ld, k,
+                       (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x, (cpx<R>*)r, n, out, (cpx<R>*)znext);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
 qmg_status Blas::init() {
     if (partials) return QMG_OK;
     QMG_HIP(hipMalloc(&partials, sizeof(double) * kMaxBlocks * kMaxVals));
@@ -332,7 +452,9 @@ template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, in
     template qmg_status Blas::mr_update<R>(const double*, const void*, void*, const void*, void*, int, int64_t); \
     template qmg_status Blas::axpy<R>(double, const void*, void*, int64_t);                                \
     template qmg_status Blas::xmy<R>(const void*, const void*, void*, int64_t);                            \
-    template qmg_status Blas::normalize<R>(void*, const double*, int64_t);
+    template qmg_status Blas::normalize<R>(void*, const double*, int64_t);                                 \
+    template qmg_status Blas::gcr_step_small<R>(const void*, const void*, int64_t, int, void*, void*, void*,  \
+                                                void*, int64_t, double*, void*);
 
 QMG_BLAS_INST(double)
 QMG_BLAS_INST(float)

@@ -160,11 +160,28 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     const double target = tol * bnorm;
     int iters = 0;
     bool done = false;
+    // short unpreconditioned systems (the coarsest level): the whole step's
+    // vector work is one single-work-group kernel, so a step is two launches
+    const bool small = !precond && n <= Blas::kSmall;
     while (!done && iters < maxit) {
         int j = 0;
+        if (small) QMG_HIP(hipMemcpyAsync(L.Z, L.r, vb, hipMemcpyDeviceToDevice, mg->s));
         for (; j < m && iters < maxit; ++j) {
             void* z = (char*)L.Z + j * vb;
             void* q = (char*)L.Q + j * vb;
+            if (small) {
+                QMG_TRY(apply_op<R>(mg, l, z, q));
+                void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * vb : nullptr;
+                QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, n, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext));
+                QMG_TRY(read_scalars(mg, S_GCR, 4));
+                ++iters;
+                const double rn = std::sqrt(mg->hsc[S_GCR + 3]);
+                if (!std::isfinite(rn) || !std::isfinite(mg->hsc[S_GCR]))
+                    return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
+                if (mg->hsc[S_GCR] <= 0.0) { done = true; ++j; break; }
+                if (bnorm > 0 && rn <= target) { done = true; ++j; break; }
+                continue;
+            }
             if (precond) QMG_TRY(kcycle<R>(mg, l, L.r, z));
             else QMG_HIP(hipMemcpyAsync(z, L.r, vb, hipMemcpyDeviceToDevice, mg->s));
             QMG_TRY(apply_op<R>(mg, l, z, q));

@@ -4,8 +4,12 @@
 // is installed on the operator, and the result is cached in-process by
 // (lattice, N, storage, vector precision, nrhs) so operators of the same shape
 // reuse it.  The candidate spaces:
-//   single right-hand side: rows | N (rows >= 4 or rows = N), split | J with at
-//     least 2 chunks per thread, rows*split <= 1024, prefetch depth in {4, 8, 16};
+//   single right-hand side: rows | N, split | J with at least 2 chunks per
+//     thread, rows*split <= 1024, prefetch depth in {4, 8, 16}; row tiles
+//     (rows < N, at least 4) only on grids too small to fill the chip
+//     otherwise (V*N/rows <= 1024 work-groups): on large grids a tiled site
+//     re-stages its inputs and was measured to fetch 1.35x the algorithmic
+//     bytes, so whole-site work-groups are kept there;
 //   multi right-hand side: right-hand-side tiles per wave in {1, 2, 4}.
 #include "handles.h"
 
@@ -100,6 +104,7 @@ extern "C" qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const
     const int N = op->N, J = op->J;
     for (int rows = 1; rows <= N; ++rows) {
         if (N % rows || (rows < 4 && rows != N)) continue;
+        if (rows < N && op->V * (N / rows) > 1024) continue;
         if (v16 && rows != N) continue;
         for (int split = 1; split <= J; ++split) {
             if (J % split || J / split < 2 || rows * split > 1024) continue;

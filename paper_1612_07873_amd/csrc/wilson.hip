@@ -67,14 +67,41 @@ __device__ __forceinline__ void load_link(cpx<R> u[9], const cpx<R>* __restrict_
     for (int e = 0; e < 9; ++e) u[e] = U[((int64_t)mu * 9 + e) * V + site];
 }
 
+// A site's 12 spinor components, with 16-byte loads (6 in FP32, 12 in FP64).
+template <typename R>
+__device__ __forceinline__ void load_spinor(cpx<R> p[12], const cpx<R>* __restrict__ src) {
+    if constexpr (sizeof(R) == 4) {
+        const float4* s4 = reinterpret_cast<const float4*>(src);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const float4 v = s4[i];
+            p[2 * i] = cpx<R>{v.x, v.y};
+            p[2 * i + 1] = cpx<R>{v.z, v.w};
+        }
+    } else {
+#pragma unroll
+        for (int f = 0; f < 12; ++f) p[f] = src[f];
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void store_spinor(cpx<R>* __restrict__ dst, const cpx<R> p[12]) {
+    if constexpr (sizeof(R) == 4) {
+        float4* d4 = reinterpret_cast<float4*>(dst);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) d4[i] = make_float4(p[2 * i].re, p[2 * i].im, p[2 * i + 1].re, p[2 * i + 1].im);
+    } else {
+#pragma unroll
+        for (int f = 0; f < 12; ++f) dst[f] = p[f];
+    }
+}
+
 // One hop in direction MU; BACK selects the backward hop.  acc += -1/2 * P (x) W psi(n).
 template <int MU, bool BACK, typename R>
 __device__ __forceinline__ void hop(cpx<R> acc[12], const cpx<R>* __restrict__ in,
                                     const cpx<R>* __restrict__ U, int64_t V, int64_t site, int64_t n) {
     cpx<R> p[12];
-    const cpx<R>* src = in + n * 12;
-#pragma unroll
-    for (int f = 0; f < 12; ++f) p[f] = src[f];
+    load_spinor(p, in + n * 12);
     cpx<R> a[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -122,11 +149,9 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const cpx<R>* __restrict_
     if (site >= V) return;
     cpx<R> acc[12];
     cpx<R> p[12];
+    load_spinor(p, in + site * 12);
 #pragma unroll
-    for (int f = 0; f < 12; ++f) {
-        p[f] = in[site * 12 + f];
-        acc[f] = {diag * p[f].re, diag * p[f].im};
-    }
+    for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
     if (use_clover) {
 #pragma unroll
         for (int chi = 0; chi < 2; ++chi) {
@@ -162,8 +187,7 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const cpx<R>* __restrict_
     hop<2, true>(acc, in, U, V, site, nb[5]);
     hop<3, false>(acc, in, U, V, site, nb[6]);
     hop<3, true>(acc, in, U, V, site, nb[7]);
-#pragma unroll
-    for (int f = 0; f < 12; ++f) out[site * 12 + f] = acc[f];
+    store_spinor(out + site * 12, acc);
 }
 
 // ------------------------------------------------------------ clover build
