@@ -15,11 +15,12 @@
 //
 // Work decomposition: one work-group per coarse site; wave w owns row tile
 // w mod (N/16) (16 output rows) and `rpw` tiles of 16 right-hand sides.  The
-// wave's link operands for all nine directions are loaded straight from HBM
-// into registers (the links are repacked once so every wave load is one
-// contiguous 1 KB: [site][d][row tile][k step][lane] x 16 bytes), while the
-// work-group stages the nine input blocks U_d ([nrhs][N] per site, contiguous)
-// and their scales in LDS.  B operands are 16-byte LDS reads.
+// wave's link operands are loaded straight from HBM into registers one
+// direction ahead (the links are repacked once so every wave load is one
+// contiguous 1 KB: [site][d][row tile][k step][lane] x 16 bytes), and the
+// input blocks U_d ([nrhs][N] per site, contiguous) stream through two LDS
+// buffers one direction ahead of the multiplication.  B operands are 16-byte
+// LDS reads.
 //
 // Field layout: u, y [V][nrhs][N] (each right-hand side's N components
 // contiguous within a site); 16-bit u with FP32 scales [V][nrhs]; y complex64.
@@ -66,7 +67,11 @@ __global__ void k_pack_mfma(uint4* __restrict__ M, const uint4* __restrict__ L, 
 }
 
 // Work of one coarse site; the work-group has `nthreads` threads, of which the
-// first NW waves compute (all of them stage).
+// first NW waves compute (all of them stage).  The nine input blocks pass
+// through two LDS buffers: while direction d is multiplied, every thread
+// holds its share of block d+1 in registers and writes it to the other buffer
+// afterwards, so staging overlaps the matrix-core work and the LDS footprint is
+// two blocks instead of nine.
 template <int F, int N, int NRHS, int RPW>
 __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* __restrict__ M,
                                           const float* __restrict__ lscale, const int* __restrict__ nbr,
@@ -78,8 +83,9 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
     constexpr int UW = NRHS * N;                    // dwords per input block in HBM
     constexpr int LD = N + 4;                       // LDS row stride (dwords), padded against bank conflicts
     constexpr int US = NRHS * LD;                   // dwords per staged block
-    uint32_t* Us = reinterpret_cast<uint32_t*>(smem);       // [9][NRHS][LD]
-    float* Sc = reinterpret_cast<float*>(Us + 9 * US);       // [9][NRHS]
+    constexpr int PER = (UW / 4 + NW * 64 - 1) / (NW * 64);  // 16-byte pieces per thread per block
+    uint32_t* Us = reinterpret_cast<uint32_t*>(smem);       // [2][NRHS][LD]
+    float* Sc = reinterpret_cast<float*>(Us + 2 * US);       // [9][NRHS]
 
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const bool computes = w < NW;
@@ -91,30 +97,43 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
 #pragma unroll
         for (int ks = 0; ks < T; ++ks) Acur[ks] = Ms[(int64_t)ks * 64];
     }
-
-    // stage the nine input blocks and their scales
-    for (int d = 0; d < 9; ++d) {
-        const int src = d == 0 ? site : nbr[site * 8 + d - 1];
-        const uint4* g = reinterpret_cast<const uint4*>(u + (int64_t)src * UW);
+    // block 0 and all scales
+    {
+        const uint4* g = reinterpret_cast<const uint4*>(u + (int64_t)site * UW);
         for (int i = threadIdx.x; i < UW / 4; i += nthreads) {
             const int j = (4 * i) / N, c = (4 * i) % N;
-            *reinterpret_cast<uint4*>(Us + d * US + j * LD + c) = g[i];
+            *reinterpret_cast<uint4*>(Us + j * LD + c) = g[i];
         }
-        const float sl = lscale[(int64_t)site * 9 + d];
-        for (int j = threadIdx.x; j < NRHS; j += nthreads) Sc[d * NRHS + j] = sl * uscale[(int64_t)src * NRHS + j];
+        for (int e = threadIdx.x; e < 9 * NRHS; e += nthreads) {
+            const int d = e / NRHS, j = e % NRHS;
+            const int sd = d == 0 ? site : nbr[site * 8 + d - 1];
+            Sc[e] = lscale[(int64_t)site * 9 + d] * uscale[(int64_t)sd * NRHS + j];
+        }
     }
     __syncthreads();
-    if (computes) {
-        f4v tot[RPW][2];
+    f4v tot[RPW][2];
 #pragma unroll
-        for (int t = 0; t < RPW; ++t) tot[t][0] = tot[t][1] = f4v{0, 0, 0, 0};
-        const int jl = l % 16;
+    for (int t = 0; t < RPW; ++t) tot[t][0] = tot[t][1] = f4v{0, 0, 0, 0};
+    const int jl = l % 16;
 #pragma unroll
-        for (int d = 0; d < 9; ++d) {
-            if (d < 8) {
+    for (int d = 0; d < 9; ++d) {
+        const uint32_t* Ub = Us + (d & 1) * US;
+        uint4 nxt[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) nxt[q] = make_uint4(0, 0, 0, 0);
+        if (d < 8) {
+            const uint4* g = reinterpret_cast<const uint4*>(u + (int64_t)nbr[site * 8 + d] * UW);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int i = threadIdx.x + q * nthreads;
+                if (i < UW / 4) nxt[q] = g[i];
+            }
+            if (computes) {
 #pragma unroll
                 for (int ks = 0; ks < T; ++ks) Anext[ks] = Ms[((int64_t)(d + 1) * T * T + ks) * 64];
             }
+        }
+        if (computes) {
             f4v acc[RPW][2];
 #pragma unroll
             for (int t = 0; t < RPW; ++t) acc[t][0] = acc[t][1] = f4v{0, 0, 0, 0};
@@ -128,7 +147,7 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
                     const int j = (tg * RPW + t) * 16 + jl;
                     uint4 b = make_uint4(0, 0, 0, 0);
                     if (NRHS >= 16 || j < NRHS)
-                        b = *reinterpret_cast<const uint4*>(Us + d * US + j * LD + ks * 16 + 4 * (l / 16));
+                        b = *reinterpret_cast<const uint4*>(Ub + j * LD + ks * 16 + 4 * (l / 16));
                     acc[t][0] = mfma<F>(ar, b, acc[t][0]);
                     acc[t][1] = mfma<F>(ai, b, acc[t][1]);
                 }
@@ -145,6 +164,20 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
                 for (int ks = 0; ks < T; ++ks) Acur[ks] = Anext[ks];
             }
         }
+        if (d < 8) {
+            uint32_t* Un = Us + ((d + 1) & 1) * US;
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int i = threadIdx.x + q * nthreads;
+                if (i < UW / 4) {
+                    const int j = (4 * i) / N, c = (4 * i) % N;
+                    *reinterpret_cast<uint4*>(Un + j * LD + c) = nxt[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (computes) {
 #pragma unroll
         for (int t = 0; t < RPW; ++t) {
             const int j = (tg * RPW + t) * 16 + jl;
@@ -201,7 +234,7 @@ static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const
     constexpr int T = N / 16;
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
     constexpr int NW = T * (NT / RPW);
-    const size_t lds = 9 * (size_t)NRHS * (N + 4) * 4 + 9 * NRHS * 4;
+    const size_t lds = 2 * (size_t)NRHS * (N + 4) * 4 + 9 * NRHS * 4;
     auto kern = k_coarse_mrhs<F, N, NRHS, RPW>;
     if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3((unsigned)op->V), dim3(NW * 64), lds, s, (const uint4*)op->mlinks, op->lscale, op->nbr,
@@ -338,7 +371,7 @@ extern "C" qmg_status qmg_coarse_dslash_mrhs_multi(int nops, const qmg_coarse_op
         ml.u[i] = (const uint32_t*)in[i];
         ml.uscale[i] = in_scale[i];
         ml.y[i] = (float2*)out[i];
-        const size_t l = 9 * (size_t)nrhs * (op->N + 4) * 4 + 9 * nrhs * 4;
+        const size_t l = 2 * (size_t)nrhs * (op->N + 4) * 4 + 9 * nrhs * 4;
         if (l > lds) lds = l;
     }
     ml.start[nops] = tot;
