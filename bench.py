@@ -33,7 +33,8 @@ TRAFFIC_FILE = os.path.join(ROOT, 'profiles', 'coarse_dslash_4x4x4x8_N48_c64_tra
 
 def measured_traffic(launch):
     """HBM bytes per launch of the headline kernel from the counter summary, if it
-    was taken on this kernel source and launch shape; else None."""
+    was taken on this kernel source and the same launch family (whole-site
+    work-groups, rows = N); else None."""
     import hashlib
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -41,7 +42,7 @@ def measured_traffic(launch):
         rec = json.load(f)
     src = os.path.join(ROOT, 'paper_1612_07873_amd', 'csrc', 'coarse_dslash.hip')
     sha = hashlib.sha256(open(src, 'rb').read()).hexdigest()
-    if rec.get('source_sha256') != sha or rec.get('launch') != launch:
+    if rec.get('source_sha256') != sha or rec.get('rows') != launch[0]:
         return None
     return rec['traffic_bytes_per_launch']
 MG_M0_FILE = os.path.join(ROOT, 'tests', 'golden', 'config2_m0.json')
