@@ -142,7 +142,7 @@ def precision_and_mrhs(steps):
     return out
 
 
-def build_mg_16x32():
+def build_mg_16x32(coarse_storage=None, fine_storage=None):
     import numpy as np
     import torch
     import synth
@@ -157,14 +157,42 @@ def build_mg_16x32():
         m0_src = 'tests/golden/config2_m0.json'
     V = int(np.prod(dims))
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
-    levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10),
-              dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100)]
+    levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10,
+                   coarse_storage=coarse_storage),
+              dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100,
+                   coarse_storage=coarse_storage)]
     starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
               torch.from_numpy(synth.gaussian((32, 512, 48), 1, 1)).to(dev)]
     t0 = time.perf_counter()
-    mg = Multigrid(dims, U, m0, 1.0, levels, starts, inner='c64')
+    mg = Multigrid(dims, U, m0, 1.0, levels, starts, inner='c64', fine_storage=fine_storage)
     torch.cuda.synchronize()
     return mg, U, m0, m0_src, time.perf_counter() - t0
+
+
+def timed_batches(mg, nrhs, nbatches, seed0):
+    """Time-to-solution per right-hand side of batched solves (first batch untimed)."""
+    import numpy as np
+    import torch
+    import synth
+    times, iters, res, fb = [], [], [], []
+    for i in range(nbatches + 1):
+        B = torch.from_numpy(np.stack([synth.gaussian((mg.V, 4, 3), seed0 + i * nrhs + k, 2)
+                                       for k in range(nrhs)])).to('cuda')
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, infos = mg.solve_multi(B, tol=1e-10)
+        torch.cuda.synchronize()
+        if i == 0:
+            continue
+        times.append(time.perf_counter() - t)
+        iters.append(infos[0]['outer_iters'])
+        res.append(max(x['true_rel_residual'] for x in infos))
+        fb.append(infos[0]['smoother_fallbacks'])
+    t = np.array(times)
+    return {'nrhs': nrhs, 'batches': nbatches, 'batch_time_s': round(float(t.mean()), 4),
+            'time_per_rhs_s': round(float(t.mean()) / nrhs, 5), 'outer_iters_mean': float(np.mean(iters)),
+            'level_iters_last': infos[0]['level_iters'], 'max_true_rel_residual': float(max(res)),
+            'smoother_fallbacks_mean': float(np.mean(fb))}
 
 
 def timed_solves(mg, nsolves, seed0):
@@ -224,52 +252,107 @@ def learned(npairs, epochs, loss):
     mg.set_smoother(net)
     withnet = timed_solves(mg, 12, 1000)
     mg.set_smoother(None)
+    del mg
+    mg16, _, _, _, _ = build_mg_16x32(coarse_storage='h16')
+    mg16.set_smoother(net)
+    combo = timed_batches(mg16, 16, 2, 1000)
+    mg16.set_smoother(None)
+    combo['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo['time_per_rhs_s'], 3)
     return {'lattice': list(dims), 'm0': m0, 'pairs': int(R.shape[0]), 'pair_seconds': round(t_pairs, 2),
             'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
             'train_seconds': round(t_train, 2), 'mg_with_MR': plain, 'mg_with_learned': withnet,
+            'multi_rhs_fp16_coarse_with_learned': combo,
             'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3)}
 
 
-def mg_gcr(nsolves=12):
+def mg_gcr(nsolves=12, nrhs=16):
+    mg, U, m0, m0_src, setup = build_mg_16x32()
+    out = {'lattice': [16, 16, 16, 32], 'm0': m0, 'm0_source': m0_src,
+           'levels': '16^3x32 -(4^4,Nvec24)-> 4^3x8 N48 -(2^4,Nvec32)-> 2^3x4 N64', 'inner': 'fp32',
+           'outer': 'fp64 GCR(10)', 'smoother': 'MR(4)', 'setup_s': round(setup, 2)}
+    out.update(timed_solves(mg, nsolves, 0))
+    del mg
+    # mixed precision, several right-hand sides at once: FP16 coarse operators,
+    # matrix-core coarse stencils, the same FP64 outer solver and tolerance
+    mg16, _, _, _, setup16 = build_mg_16x32(coarse_storage='h16')
+    out['multi_rhs_fp16_coarse'] = dict(setup_s=round(setup16, 2), **timed_batches(mg16, nrhs, 2, 5000))
+    out['multi_rhs_fp16_coarse']['speedup_per_rhs_vs_single_fp32'] = round(
+        out['time_to_1e-10_s'] / out['multi_rhs_fp16_coarse']['time_per_rhs_s'], 3)
+    return out
+
+
+def precision_form(nsolves=3, dims=(32, 32, 32, 64)):
+    """The 16-bit precision form on 32^3x64 against the plain FP32 inner
+    precision, same hierarchy recipe and start vectors: fine links and clover
+    and every coarse operator in FP16 (per-(site, block) FP32 scales), FP32
+    vectors and arithmetic, FP64 outer GCR.  The error of each level's stored
+    operator is measured against the FP64 operators the library builds from
+    the same block bases."""
     import numpy as np
     import torch
     import synth
-    from paper_1612_07873_amd import Multigrid
+    from paper_1612_07873_amd import FineOp, Multigrid, Transfer, build_coarse_op
     dev = torch.device('cuda')
-    dims = (16, 16, 16, 32)
     m0 = -0.25
     m0_src = 'provisional'
     if os.path.exists(MG_M0_FILE):
         with open(MG_M0_FILE) as f:
             m0 = float(json.load(f)['m0'])
-        m0_src = 'tests/golden/config2_m0.json'
+        m0_src = 'tests/golden/config2_m0.json (16^3x32 value, same gauge recipe)'
     V = int(np.prod(dims))
+    t0 = time.perf_counter()
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
+    b1 = [d // 4 for d in dims]
     levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10),
               dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100)]
     starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
-              torch.from_numpy(synth.gaussian((32, 512, 48), 1, 1)).to(dev)]
-    t0 = time.perf_counter()
-    mg = Multigrid(dims, U, m0, 1.0, levels, starts, inner='c64')
+              torch.from_numpy(synth.gaussian((32, int(np.prod(b1)), 48), 1, 1)).to(dev)]
+    print('precision form: inputs %.1f s' % (time.perf_counter() - t0), file=sys.stderr, flush=True)
+    out = {'lattice': list(dims), 'm0': m0, 'm0_source': m0_src,
+           'levels': '%s -(4^4,Nvec24)-> %s N48 -(2^4,Nvec32)-> %s N64'
+                     % ('x'.join(map(str, dims)), 'x'.join(map(str, b1)), 'x'.join(str(d // 2) for d in b1))}
+    runs = {}
+    for name, fs, cs in (('fp32', None, None), ('fp16', 'h16', 'h16')):
+        t0 = time.perf_counter()
+        mg = Multigrid(dims, U, m0, 1.0, [dict(L, coarse_storage=cs) for L in levels], starts, inner='c64',
+                       fine_storage=fs)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        r = {'setup_s': round(setup, 2)}
+        r.update(timed_solves(mg, nsolves, 0))
+        print('precision form: %s %s' % (name, r), file=sys.stderr, flush=True)
+        runs[name] = (mg, r)
+    # FP64 operators from the same block bases, and each stored operator's error against them
+    mg16 = runs['fp16'][0]
+    mg32 = runs['fp32'][0]
+    f64 = FineOp(dims, U, m0, 1.0, True, 'c128')
+    f16 = FineOp(dims, U, m0, 1.0, True, 'h16')
+    psi = torch.from_numpy(synth.gaussian((V, 4, 3), 77, 2)).to(dev)
+    ref = f64.apply(psi)
+    errs = {'fp16': [float((f16.apply(psi.to(torch.complex64)).to(torch.complex128) - ref).norm() / ref.norm())],
+            'fp32': [float((FineOp(dims, U, m0, 1.0, True, 'c64').apply(psi.to(torch.complex64))
+                            .to(torch.complex128) - ref).norm() / ref.norm())]}
+    parent, fine = None, f64
+    for l in (1, 2):
+        pdims, pdof, _, T = mg16.level(l - 1)
+        B = T.basis().permute(2, 0, 1).contiguous()
+        t64 = Transfer(pdims, pdof, levels[l - 1]['block'], B, 'c128')
+        op64 = build_coarse_op(t64, fine=fine, parent=parent, storage='c128')
+        del B
+        cdims, N, op16, _ = mg16.level(l)
+        _, _, op32, _ = mg32.level(l)
+        u = torch.from_numpy(synth.gaussian((op64.V, N), 80 + l, 2)).to(dev)
+        y64 = op64.apply(u)
+        for name, op in (('fp16', op16), ('fp32', op32)):
+            y = op.apply(u.to(torch.complex64)).to(torch.complex128)
+            errs[name].append(float((y - y64).norm() / y64.norm()))
+        parent, fine = op64, None
     torch.cuda.synchronize()
-    setup = time.perf_counter() - t0
-    times, iters, res = [], [], []
-    for i in range(nsolves):
-        b = torch.from_numpy(synth.gaussian((V, 4, 3), i, 2)).to(dev)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, info = mg.solve(b, tol=1e-10)
-        torch.cuda.synchronize()
-        times.append(time.perf_counter() - t)
-        iters.append(info['outer_iters'])
-        res.append(info['true_rel_residual'])
-        lvl = info['level_iters']
-    t = np.array(times[1:])
-    return {'lattice': list(dims), 'm0': m0, 'm0_source': m0_src, 'levels': '16^3x32 -(4^4,Nvec24)-> 4^3x8 N48 '
-            '-(2^4,Nvec32)-> 2^3x4 N64', 'inner': 'fp32', 'outer': 'fp64 GCR(10)', 'smoother': 'MR(4)',
-            'solves': nsolves, 'time_to_1e-10_s': round(float(t.mean()), 4), 'std_s': round(float(t.std()), 4),
-            'outer_iters_mean': float(np.mean(iters[1:])), 'level_iters_last': lvl,
-            'max_true_rel_residual': float(max(res)), 'setup_s': round(setup, 2)}
+    out['error_vs_fp64_per_level'] = {k: [float('%.3e' % e) for e in v] for k, v in errs.items()}
+    out['fp32'] = runs['fp32'][1]
+    out['fp16'] = runs['fp16'][1]
+    out['speedup_time'] = round(runs['fp32'][1]['time_to_1e-10_s'] / runs['fp16'][1]['time_to_1e-10_s'], 3)
+    return out
 
 
 def main():
@@ -280,6 +363,8 @@ def main():
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle leg')
     ap.add_argument('--only-headline', action='store_true', help='time the headline kernel only')
     ap.add_argument('--learned', action='store_true', help='learned-smoother comparison on 16^3x32 instead')
+    ap.add_argument('--precision-form', action='store_true',
+                    help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
     ap.add_argument('--pairs', type=int, default=512)
     ap.add_argument('--epochs', type=int, default=4)
     ap.add_argument('--loss', choices=['error', 'residual'], default='residual')
@@ -296,6 +381,9 @@ def main():
 
     if args.learned:
         print(json.dumps({'learned_smoother': learned(args.pairs, args.epochs, args.loss)}), flush=True)
+        return
+    if args.precision_form:
+        print(json.dumps({'precision_form': precision_form()}), flush=True)
         return
     dev = torch.device('cuda')
     # a plain device copy of known size (512 MiB read, 512 MiB written), outside

@@ -193,14 +193,26 @@ void qmg_coarse_op_destroy(qmg_coarse_op op);
  *     gauge [4][V][3][3] complex128  (U_mu(x), row-major colour matrices),
  * every extent >= 2.  The clover term is computed on the device here.  The
  * gauge array may be freed once the stream has passed this call.
- * storage: QMG_C128 or QMG_C64. */
+ * storage: QMG_C128, QMG_C64, or QMG_H16 / QMG_B16 (the 16-bit precision form
+ * of Sec. 4: link entries as FP16 / BF16 pairs with no scale, which assumes
+ * unitary links, |entry| <= 1; the clover term as 16-bit pairs with one FP32
+ * scale per (chirality, site), built in FP64 first; FP32 arithmetic). */
 qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, double m0, double csw,
                               int antiperiodic_t, qmg_prec storage, void* stream, qmg_fine_op* out);
 
 /* out = M in for one field; in/out DEVICE [V][4][3] in the operator's storage
- * precision; in and out must not overlap. */
+ * precision (complex64 for the 16-bit storages); in and out must not overlap. */
 qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, qmg_prec prec,
                                     void* stream);
+
+/* The same with 16-bit vectors (operator storage QMG_H16 / QMG_B16; prec =
+ * QMG_H16 or QMG_B16 names the vector format): in/out DEVICE [V][12] 32-bit
+ * words, each an (re, im) pair of the 16-bit format, value = scale[site] *
+ * stored; in_scale/out_scale DEVICE float [V].  The output scale of a site is
+ * the largest |re| or |im| of its 12 components (0 for a zero spinor).
+ * Arithmetic in FP32.  Buffers must not overlap. */
+qmg_status qmg_wilson_clover_dslash_scaled(qmg_fine_op op, const void* in, const float* in_scale, void* out,
+                                           float* out_scale, qmg_prec prec, void* stream);
 
 /* Write the clover term as dense DEVICE complex128 [V][12][12] (row/column
  * index 3*spin + colour). */
@@ -274,6 +286,9 @@ typedef struct {
     int smoother_steps;  /* MR steps before and after the coarse correction (4) */
     double coarse_tol;   /* relative tolerance of the GCR solve on the next level (0.25) */
     int coarse_maxit;    /* its iteration cap (10 intermediate, 100 coarsest) */
+    int coarse_storage;  /* storage of the next level's operator in the solve: 0 = the inner
+                            precision, QMG_H16 / QMG_B16 = 16-bit links with FP32 scales
+                            (FP32 vectors; inner precision must be QMG_C64) */
 } qmg_level_params;
 
 typedef struct {
@@ -298,16 +313,41 @@ typedef struct {
  * the near-null relaxation on level l (dof_0 = 12, dof_l = 2*nvec_{l-1}).
  * `inner` (QMG_C64 or QMG_C128) is the precision of the K-cycle, the
  * relaxation and the coarse operators; the outer GCR and the true residual
- * always use FP64.  Blocks until the setup is complete. */
+ * always use FP64.  `fine_storage` is the storage of the fine operator used
+ * inside the K-cycle (smoothing and the residual handed to level 1): 0 or
+ * `inner` for the inner precision, QMG_H16 / QMG_B16 for 16-bit links and
+ * clover with complex64 vectors (inner must then be QMG_C64).  The setup
+ * (relaxation, Galerkin build) always runs on the inner-precision operators;
+ * 16-bit storages are made from them afterwards.  Every coarse operator's
+ * stencil launch is autotuned here.  Blocks until the setup is complete. */
 qmg_status qmg_mg_create(const int dims[4], const void* gauge, double m0, double csw, int antiperiodic_t,
                          int nlevels, const qmg_level_params* lp, const void* const* starts,
-                         qmg_prec inner, void* stream, qmg_mg* out);
+                         qmg_prec inner, qmg_prec fine_storage, void* stream, qmg_mg* out);
 
 /* Solve M x = b: b, x DEVICE complex128 [V][4][3] (x is overwritten, start
  * x = 0).  Blocks; returns QMG_ERR_NOCONV if maxit is reached and
  * QMG_ERR_NONFINITE on NaN/Inf; *info (host, may be NULL) is filled in any case. */
 qmg_status qmg_mg_gcr_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
                             qmg_solve_info* info, void* stream);
+
+/* Solve M x_k = b_k for nrhs (1..64) right-hand sides together: b, x DEVICE
+ * complex128 [nrhs][V][4][3]; info: host array of nrhs entries (may be NULL).
+ * The members run in lock step (the multi-RHS form the paper names as future
+ * work, Sec. 9): every launch covers all of them, each keeps its own Krylov
+ * space, step lengths and FP64 stopping test, and a level's GCR ends when
+ * every member meets its tolerance, so one member may take more inner steps
+ * than it would alone.  With a 16-bit coarse operator (level params'
+ * coarse_storage) and nrhs in {8, 16, 32, 64}, the coarse stencil of that
+ * level runs on the matrix cores (qmg_coarse_dslash_mrhs) after rounding the
+ * batch's vectors to 16 bits with one scale per (site, member).  A learned
+ * smoother is applied to every member and kept only if it lowers every
+ * member's residual (else MR for the batch; info's smoother_fallbacks counts
+ * the members whose residual grew).  The solve workspace grows to nrhs members
+ * on first use and is kept (about nrhs times the single-solve workspace).
+ * outer_iters and level_iters are shared by the batch.  Blocks; returns
+ * QMG_ERR_NOCONV unless every member converged. */
+qmg_status qmg_mg_gcr_solve_multi(qmg_mg mg, const void* b, void* x, int nrhs, const qmg_solve_params* p,
+                                  qmg_solve_info* info, void* stream);
 
 /* Borrowed views of level l: lattice dims, components per site, its coarse
  * operator (NULL on level 0) and the transfer to level l+1 (NULL on the

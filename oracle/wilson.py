@@ -21,11 +21,12 @@ def _links_at(U, idx):
     return U[idx]
 
 
-def clover_leaves(U, dims, mu, nu):
-    """Q_{mu nu}(x): sum of the four same-orientation plaquettes touching x."""
+def clover_leaves(U, dims, mu, nu, sites=None):
+    """Q_{mu nu}(x): sum of the four same-orientation plaquettes touching x
+    (at every site, or at the given sites only)."""
     V = lattice.volume(dims)
-    f = lambda m, s: lattice.neighbour(dims, m, s)
-    x = np.arange(V)
+    x = np.arange(V) if sites is None else np.asarray(sites)
+    f = lambda m, s: lattice.neighbour(dims, m, s)[x]
     Um, Un = U[mu], U[nu]
     dag = lambda a: np.conj(np.swapaxes(a, -1, -2))
     mm = lambda *ms: _chain(ms)
@@ -52,40 +53,52 @@ def _chain(ms):
     return out
 
 
-def clover_field(U, dims, csw):
-    """A(x) as dense 12x12 matrices [V][12][12] (row/column index 3*spin + colour)."""
-    V = lattice.volume(dims)
+def clover_field(U, dims, csw, sites=None):
+    """A(x) as dense 12x12 matrices [V][12][12] (row/column index 3*spin + colour);
+    with `sites`, only at those sites ([len(sites)][12][12])."""
+    V = lattice.volume(dims) if sites is None else len(sites)
     A = np.zeros((V, 4, 3, 4, 3), dtype=np.complex128)
     for mu in range(4):
         for nu in range(mu + 1, 4):
-            Q = clover_leaves(U, dims, mu, nu)
+            Q = clover_leaves(U, dims, mu, nu, sites)
             F = (Q - np.conj(np.swapaxes(Q, -1, -2))) / 8.0
             A += (0.5j * csw) * np.einsum('st,xab->xsatb', lattice.sigma(mu, nu), F)
     return A.reshape(V, 12, 12)
 
 
-def apply_wilson_clover(psi, U, clover, m0, dims, antiperiodic_t=True):
-    """M psi for psi of shape [V][4][3] (or [V][12]); clover may be None (c_sw = 0)."""
+def apply_wilson_clover(psi, U, clover, m0, dims, antiperiodic_t=True, sites=None):
+    """M psi for psi of shape [V][4][3] (or [V][12]); clover may be None (c_sw = 0).
+
+    With `sites`, (M psi)(x) at those sites only, [len(sites)][4][3], and
+    `clover` holds the clover term at those sites."""
     V = lattice.volume(dims)
     shape = psi.shape
     psi = psi.reshape(V, 4, 3)
+    x = np.arange(V) if sites is None else np.asarray(sites)
     Pm, Pp = lattice.projectors()
-    out = (4.0 + m0) * psi
+    out = (4.0 + m0) * psi[x]
     if clover is not None:
-        out = out + np.einsum('xij,xj->xi', clover, psi.reshape(V, 12)).reshape(V, 4, 3)
+        out = out + np.einsum('xij,xj->xi', clover, psi[x].reshape(len(x), 12)).reshape(len(x), 4, 3)
     for mu in range(4):
-        fwd = lattice.neighbour(dims, mu, +1)
-        bwd = lattice.neighbour(dims, mu, -1)
-        eta_f = lattice.boundary_sign(dims, mu, +1, antiperiodic_t)
-        eta_b = lattice.boundary_sign(dims, mu, -1, antiperiodic_t)
+        fwd = lattice.neighbour(dims, mu, +1)[x]
+        bwd = lattice.neighbour(dims, mu, -1)[x]
+        eta_f = lattice.boundary_sign(dims, mu, +1, antiperiodic_t)[x]
+        eta_b = lattice.boundary_sign(dims, mu, -1, antiperiodic_t)[x]
         # forward hop: (1 - gamma_mu) (x) U_mu(x) psi(x + mu)
-        h = np.einsum('st,xta->xsa', Pm[mu], np.einsum('xab,xtb->xta', U[mu], psi[fwd]))
+        h = np.einsum('st,xta->xsa', Pm[mu], np.einsum('xab,xtb->xta', U[mu][x], psi[fwd]))
         out = out - 0.5 * eta_f[:, None, None] * h
         # backward hop: (1 + gamma_mu) (x) U_mu(x - mu)^dagger psi(x - mu)
         Ub = U[mu][bwd]
         h = np.einsum('st,xta->xsa', Pp[mu], np.einsum('xba,xtb->xta', np.conj(Ub), psi[bwd]))
         out = out - 0.5 * eta_b[:, None, None] * h
-    return out.reshape(shape)
+    return out.reshape(shape) if sites is None else out
+
+
+def apply_wilson_clover_sites(psi, U, csw, m0, dims, sites, antiperiodic_t=True):
+    """(M psi)(x) at the given sites only, the clover term computed there from
+    the links: spot checks on lattices too large for the whole-field oracle."""
+    A = clover_field(U, dims, csw, sites) if csw != 0 else None
+    return apply_wilson_clover(psi, U, A, m0, dims, antiperiodic_t, sites)
 
 
 def hop_matrices(U, dims, d, antiperiodic_t=True):

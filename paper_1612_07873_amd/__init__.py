@@ -154,13 +154,15 @@ class CoarseOp:
 
 
 class FineOp:
-    """Wilson-clover operator of Eq. (2) held by the library (qmg_fine_op_create)."""
+    """Wilson-clover operator of Eq. (2) held by the library (qmg_fine_op_create).
+    storage 'h16' / 'b16' keeps links and clover in 16 bits; apply() then takes
+    complex64 vectors and apply_scaled() 16-bit vectors with per-site scales."""
 
     def __init__(self, dims, gauge, m0, csw=1.0, antiperiodic_t=True, storage='c128'):
         self.dims = tuple(int(d) for d in dims)
         self.V = _vol(self.dims)
         self.storage = storage
-        self.dtype = _CDTYPE[storage]
+        self.dtype = _VECDTYPE[storage]
         self.m0, self.csw = float(m0), float(csw)
         h = ctypes.c_void_p()
         _lib.call('qmg_fine_op_create', _lib.c_dims(*self.dims),
@@ -172,10 +174,24 @@ class FineOp:
     def apply(self, psi, out=None):
         if out is None:
             out = torch.empty_like(psi)
+        vp = self.storage if self.storage in ('c128', 'c64') else 'c64'
         _lib.call('qmg_wilson_clover_dslash', self._h,
                   _dev_ptr(psi, self.dtype, (self.V, 4, 3), 'in'),
-                  _dev_ptr(out, self.dtype, (self.V, 4, 3), 'out'), PREC[self.storage], stream_ptr())
+                  _dev_ptr(out, self.dtype, (self.V, 4, 3), 'out'), PREC[vp], stream_ptr())
         return out
+
+    def apply_scaled(self, u16, uscale, out16=None, oscale=None, vprec=None):
+        """16-bit spinors: u16 int32 [V][12] (packed pairs), uscale float32 [V]."""
+        vprec = vprec or self.storage
+        if out16 is None:
+            out16 = torch.empty_like(u16)
+        if oscale is None:
+            oscale = torch.empty_like(uscale)
+        _lib.call('qmg_wilson_clover_dslash_scaled', self._h, _dev_ptr(u16, torch.int32, (self.V, 12), 'in'),
+                  _dev_ptr(uscale, torch.float32, (self.V,), 'in_scale'),
+                  _dev_ptr(out16, torch.int32, (self.V, 12), 'out'),
+                  _dev_ptr(oscale, torch.float32, (self.V,), 'out_scale'), PREC[vprec], stream_ptr())
+        return out16, oscale
 
     def clover(self):
         A = torch.empty((self.V, 12, 12), dtype=torch.complex128, device='cuda')
@@ -269,10 +285,13 @@ class Multigrid:
     """Adaptive multigrid hierarchy + K-cycle FGCR solver (qmg_mg_create / qmg_mg_gcr_solve).
 
     levels: list of dicts with keys block, nvec, setup_iters, smoother_steps,
-    coarse_tol, coarse_maxit (one per coarsened level); starts: list of device
-    complex128 tensors [nvec_l][V_l][dof_l]."""
+    coarse_tol, coarse_maxit and optionally coarse_storage ('h16' / 'b16': the
+    next level's operator in 16-bit storage during the solve), one per
+    coarsened level; starts: list of device complex128 tensors
+    [nvec_l][V_l][dof_l]; fine_storage: None or 'h16' / 'b16' for the fine
+    operator inside the K-cycle."""
 
-    def __init__(self, dims, gauge, m0, csw, levels, starts, antiperiodic_t=True, inner='c64'):
+    def __init__(self, dims, gauge, m0, csw, levels, starts, antiperiodic_t=True, inner='c64', fine_storage=None):
         self.dims = tuple(int(d) for d in dims)
         self.V = _vol(self.dims)
         self.inner = inner
@@ -285,6 +304,7 @@ class Multigrid:
             lp[i].smoother_steps = int(L.get('smoother_steps', 4))
             lp[i].coarse_tol = float(L.get('coarse_tol', 0.25))
             lp[i].coarse_maxit = int(L.get('coarse_maxit', 10))
+            lp[i].coarse_storage = PREC[L['coarse_storage']] if L.get('coarse_storage') else 0
         ptrs = (ctypes.c_void_p * max(1, len(starts)))()
         for i, t in enumerate(starts):
             if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
@@ -295,7 +315,7 @@ class Multigrid:
         _lib.call('qmg_mg_create', _lib.c_dims(*self.dims),
                   _dev_ptr(gauge, torch.complex128, (4, self.V, 3, 3), 'gauge'),
                   float(m0), float(csw), int(bool(antiperiodic_t)), self.nlevels, lp, ptrs, PREC[inner],
-                  stream_ptr(), ctypes.byref(h))
+                  PREC[fine_storage] if fine_storage else 0, stream_ptr(), ctypes.byref(h))
         self._h = h
         self._levels = levels
 
@@ -310,6 +330,22 @@ class Multigrid:
         out = self._info(info, st)
         if check:
             _lib.check(st, 'qmg_mg_gcr_solve')
+        return x, out
+
+    def solve_multi(self, b, x=None, tol=1e-10, maxit=500, check=True):
+        """Solve for the right-hand sides b [nrhs][V][4][3] together (qmg_mg_gcr_solve_multi);
+        returns x and one info dict per right-hand side."""
+        nrhs = int(b.shape[0])
+        if x is None:
+            x = torch.empty_like(b)
+        sp = _lib.SolveParams(tol=float(tol), restart=10, maxit=int(maxit))
+        infos = (_lib.SolveInfo * nrhs)()
+        st = _lib.lib().qmg_mg_gcr_solve_multi(self._h, _dev_ptr(b, torch.complex128, (nrhs, self.V, 4, 3), 'b'),
+                                               _dev_ptr(x, torch.complex128, (nrhs, self.V, 4, 3), 'x'), nrhs,
+                                               ctypes.byref(sp), infos, stream_ptr())
+        out = [self._info(infos[k], st) for k in range(nrhs)]
+        if check:
+            _lib.check(st, 'qmg_mg_gcr_solve_multi')
         return x, out
 
     def _info(self, info, st):

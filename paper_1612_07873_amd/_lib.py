@@ -40,6 +40,7 @@ SIGNATURES = {
     'qmg_fine_op_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, c_void_p,
                                    ctypes.POINTER(c_void_p)]),
     'qmg_wilson_clover_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_wilson_clover_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_fine_op_export_clover': (c_int, [c_void_p, c_void_p, c_void_p]),
     'qmg_fine_op_destroy': (None, [c_void_p]),
     'qmg_transfer_create': (c_int, [c_dims, c_int, c_dims, c_int, c_void_p, c_int, c_void_p,
@@ -56,7 +57,7 @@ SIGNATURES = {
 
 class LevelParams(ctypes.Structure):
     _fields_ = [('block', c_int * 4), ('nvec', c_int), ('setup_iters', c_int), ('smoother_steps', c_int),
-                ('coarse_tol', c_double), ('coarse_maxit', c_int)]
+                ('coarse_tol', c_double), ('coarse_maxit', c_int), ('coarse_storage', c_int)]
 
 
 class SolveParams(ctypes.Structure):
@@ -70,9 +71,11 @@ class SolveInfo(ctypes.Structure):
 
 SIGNATURES.update({
     'qmg_mg_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, ctypes.POINTER(LevelParams),
-                              ctypes.POINTER(c_void_p), c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+                              ctypes.POINTER(c_void_p), c_int, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_gcr_solve': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
                                  ctypes.POINTER(SolveInfo), c_void_p]),
+    'qmg_mg_gcr_solve_multi': (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.POINTER(SolveParams),
+                                       ctypes.POINTER(SolveInfo), c_void_p]),
     'qmg_mg_level': (c_int, [c_void_p, c_int, c_int_p, c_int_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),
     'qmg_mg_fine_op': (c_int, [c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_destroy': (None, [c_void_p]),

@@ -1,6 +1,13 @@
 // BLAS-1 layer of the Krylov solvers: every scalar stays in device memory;
 // reductions are two-phase (per-block partials, then one block sums them in a
 // fixed order) so results are bitwise repeatable and need no atomics.
+//
+// Batches: with nb > 1 every call works on nb independent members at once
+// (grid dimension y = member).  Member b of a vector argument of length n
+// starts at element b*n; multi-vector arguments (Q, Z with stride ld) are
+// offset the same way, so a Krylov space of nb members is laid out
+// [direction][member][n] with ld = nb*n.  Member b's scalars (inputs and
+// results) sit at b*ss doubles after the given pointer.
 #pragma once
 
 #include "qmg_internal.h"
@@ -9,9 +16,12 @@ namespace qmg {
 
 struct Blas {
     hipStream_t s = nullptr;
-    double* partials = nullptr;  // [kMaxBlocks][kMaxVals]
+    double* partials = nullptr;  // [kMaxBatch][kMaxBlocks][kMaxVals]
     static constexpr int kMaxBlocks = 512;
     static constexpr int kMaxVals = 40;
+    static constexpr int kMaxBatch = 64;
+    int nb = 1;    // members per call
+    int ss = 64;   // doubles between consecutive members' scalars
 
     qmg_status init();
     void release();

@@ -30,8 +30,10 @@ __device__ __forceinline__ double wg_sum(double v, double* lds) {
 // phase 2: out[v] = sum over blocks of partials[b][v]; thread t adds blocks
 // t, t+256, ..., then a fixed tree: the same order on every run
 __global__ __launch_bounds__(256) void k_final(const double* __restrict__ partials, int nb, int nv,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, int ss) {
     __shared__ double lds[16];
+    partials += (int64_t)blockIdx.y * Blas::kMaxBlocks * Blas::kMaxVals;
+    out += (int64_t)blockIdx.y * ss;
     for (int v = 0; v < nv; ++v) {
         double t = 0;
         for (int b = threadIdx.x; b < nb; b += blockDim.x) t += partials[b * Blas::kMaxVals + v];
@@ -39,6 +41,12 @@ __global__ __launch_bounds__(256) void k_final(const double* __restrict__ partia
         if (threadIdx.x == 0) out[v] = t;
     }
 }
+
+// this work-group's batch member: shift its vectors by member*n, its scalars
+// by member*ss and its partial sums to the member's own table
+#define QMG_MEMBER_SCAL(p) p += (int64_t)blockIdx.y * ss
+#define QMG_MEMBER_VEC(p) p += (int64_t)blockIdx.y * n
+#define QMG_MEMBER_PART(p) p += (int64_t)blockIdx.y * Blas::kMaxBlocks * Blas::kMaxVals
 
 // a work-group's sums: to the partials, or straight to the result when the grid is one block
 __device__ __forceinline__ void put(double* part, double* out, int v, double val) {
@@ -48,8 +56,9 @@ __device__ __forceinline__ void put(double* part, double* out, int v, double val
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_dot(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, int64_t n,
-                      double* __restrict__ part, double* __restrict__ out) {
+                      double* __restrict__ part, double* __restrict__ out, int ss) {
     __shared__ double lds[16];
+    QMG_MEMBER_VEC(a); QMG_MEMBER_VEC(b); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double re = 0, im = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const cpx<R> x = a[i], y = b[i];
@@ -66,8 +75,9 @@ __global__ __launch_bounds__(1024) void k_dot(const cpx<R>* __restrict__ a, cons
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_norm2(const cpx<R>* __restrict__ a, int64_t n, double* __restrict__ part,
-                                                double* __restrict__ out) {
+                                                double* __restrict__ out, int ss) {
     __shared__ double lds[16];
+    QMG_MEMBER_VEC(a); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double s = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const cpx<R> x = a[i];
@@ -79,8 +89,10 @@ __global__ __launch_bounds__(1024) void k_norm2(const cpx<R>* __restrict__ a, in
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_dot_norm(const cpx<R>* __restrict__ q, const cpx<R>* __restrict__ r,
-                                                   int64_t n, double* __restrict__ part, double* __restrict__ out) {
+                                                   int64_t n, double* __restrict__ part, double* __restrict__ out,
+                                                   int ss) {
     __shared__ double lds[16];
+    QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(r); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double qq = 0, re = 0, im = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const cpx<R> x = q[i], y = r[i];
@@ -101,8 +113,9 @@ __global__ __launch_bounds__(1024) void k_dot_norm(const cpx<R>* __restrict__ q,
 template <typename R>
 __global__ __launch_bounds__(1024) void k_multi_dot(const cpx<R>* __restrict__ Q, int64_t ld, int k,
                                                     const cpx<R>* __restrict__ q, int64_t n,
-                                                    double* __restrict__ part, double* __restrict__ out) {
+                                                    double* __restrict__ part, double* __restrict__ out, int ss) {
     __shared__ double lds[16];
+    QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(q); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double re[16], im[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) re[j] = im[j] = 0;
@@ -133,9 +146,11 @@ __global__ __launch_bounds__(1024) void k_multi_dot(const cpx<R>* __restrict__ Q
 template <typename R>
 __global__ void k_multi_axpy(const double* __restrict__ beta, const cpx<R>* __restrict__ Q,
                              const cpx<R>* __restrict__ Z, int64_t ld, int k, cpx<R>* __restrict__ q,
-                             cpx<R>* __restrict__ z, int64_t n) {
+                             cpx<R>* __restrict__ z, int64_t n, int ss) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    QMG_MEMBER_SCAL(beta); QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(q);
+    if (z) { QMG_MEMBER_VEC(Z); QMG_MEMBER_VEC(z); }
     R qr = q[i].re, qi = q[i].im;
     R zr = 0, zi = 0;
     if (z) { zr = z[i].re; zi = z[i].im; }
@@ -156,7 +171,8 @@ __global__ void k_multi_axpy(const double* __restrict__ beta, const cpx<R>* __re
 
 template <typename R>
 __global__ void k_gcr_update(const double* __restrict__ s3, cpx<R>* __restrict__ q, cpx<R>* __restrict__ z,
-                             cpx<R>* __restrict__ x, cpx<R>* __restrict__ r, int64_t n) {
+                             cpx<R>* __restrict__ x, cpx<R>* __restrict__ r, int64_t n, int ss) {
+    QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x); QMG_MEMBER_VEC(r);
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !(s3[0] > 0)) return;  // q = 0: no update (breakdown is reported by the caller)
     const double nq = sqrt(s3[0]);
@@ -178,9 +194,10 @@ __global__ void k_gcr_update(const double* __restrict__ s3, cpx<R>* __restrict__
 
 template <typename R>
 __global__ void k_mr_update(const double* __restrict__ s3, const cpx<R>* rin, cpx<R>* r, const cpx<R>* __restrict__ Ar,
-                            cpx<R>* __restrict__ x, int first, int64_t n) {
+                            cpx<R>* __restrict__ x, int first, int64_t n, int ss) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(rin); QMG_MEMBER_VEC(r); QMG_MEMBER_VEC(Ar); QMG_MEMBER_VEC(x);
     const double den = s3[0];
     const R ar = den > 0 ? (R)(s3[1] / den) : (R)0, ai = den > 0 ? (R)(s3[2] / den) : (R)0;
     cpx<R> rr = rin[i];
@@ -198,6 +215,7 @@ template <typename R>
 __global__ void k_axpy(R a, const cpx<R>* __restrict__ x, cpx<R>* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    QMG_MEMBER_VEC(x); QMG_MEMBER_VEC(y);
     y[i].re += a * x[i].re;
     y[i].im += a * x[i].im;
 }
@@ -206,6 +224,7 @@ template <typename R>
 __global__ void k_xmy(const cpx<R>* __restrict__ b, const cpx<R>* __restrict__ ax, cpx<R>* __restrict__ r, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    QMG_MEMBER_VEC(b); QMG_MEMBER_VEC(ax); QMG_MEMBER_VEC(r);
     r[i] = cpx<R>{b[i].re - ax[i].re, b[i].im - ax[i].im};
 }
 
@@ -213,13 +232,15 @@ template <typename Rs, typename Rd>
 __global__ void k_convert(const cpx<Rs>* __restrict__ s, cpx<Rd>* __restrict__ d, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    QMG_MEMBER_VEC(s); QMG_MEMBER_VEC(d);
     d[i] = cpx<Rd>{(Rd)s[i].re, (Rd)s[i].im};
 }
 
 template <typename R>
-__global__ void k_normalize(cpx<R>* __restrict__ x, const double* __restrict__ nrm2, int64_t n) {
+__global__ void k_normalize(cpx<R>* __restrict__ x, const double* __restrict__ nrm2, int64_t n, int ss) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    QMG_MEMBER_VEC(x); QMG_MEMBER_SCAL(nrm2);
     const R inv = (R)(1.0 / sqrt(nrm2[0]));
     x[i].re *= inv;
     x[i].im *= inv;
@@ -235,8 +256,11 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
                                                          int64_t ld, int k, cpx<R>* __restrict__ q,
                                                          cpx<R>* __restrict__ z, cpx<R>* __restrict__ x,
                                                          cpx<R>* __restrict__ r, int64_t n, double* __restrict__ out,
-                                                         cpx<R>* __restrict__ znext) {
+                                                         cpx<R>* __restrict__ znext, int ss) {
     __shared__ double lds[16];
+    QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(Z); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x);
+    QMG_MEMBER_VEC(r); QMG_MEMBER_SCAL(out);
+    if (znext) QMG_MEMBER_VEC(znext);
     __shared__ double sc[40];
     __shared__ double part[16][32];
     const int t = threadIdx.x, T = blockDim.x;
@@ -339,15 +363,15 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
 template <typename R>
 qmg_status Blas::gcr_step_small(const void* Q, const void* Z, int64_t ld, int k, void* q, void* z, void* x, void* r,
                                 int64_t n, double* out, void* znext) {
-    hipLaunchKernelGGL(k_gcr_step_small<R>, dim3(1), dim3(1024), 0, s, (const cpx<R>*)Q, (const cpx<R>*)Z, ld, k,
-                       (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x, (cpx<R>*)r, n, out, (cpx<R>*)znext);
+    hipLaunchKernelGGL(k_gcr_step_small<R>, dim3(1, nb), dim3(1024), 0, s, (const cpx<R>*)Q, (const cpx<R>*)Z, ld, k,
+                       (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x, (cpx<R>*)r, n, out, (cpx<R>*)znext, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
 qmg_status Blas::init() {
     if (partials) return QMG_OK;
-    QMG_HIP(hipMalloc(&partials, sizeof(double) * kMaxBlocks * kMaxVals));
+    QMG_HIP(hipMalloc(&partials, sizeof(double) * kMaxBatch * kMaxBlocks * kMaxVals));
     return QMG_OK;
 }
 
@@ -358,29 +382,30 @@ void Blas::release() {
 
 static unsigned grid1(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-static void finish(hipStream_t s, double* partials, int nb, int nv, double* out) {
-    if (nb > 1) hipLaunchKernelGGL(k_final, dim3(1), dim3(256), 0, s, partials, nb, nv, out);
+static void finish(hipStream_t s, double* partials, int nblk, int nv, double* out, int members, int ss) {
+    if (nblk > 1) hipLaunchKernelGGL(k_final, dim3(1, members), dim3(256), 0, s, partials, nblk, nv, out, ss);
 }
 
 template <typename R> qmg_status Blas::dot(const void* a, const void* b, int64_t n, double* out) {
-    const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_dot<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n, partials, out);
-    finish(s, partials, nb, 2, out);
+    const int nblk = nblocks(n);
+    hipLaunchKernelGGL(k_dot<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n,
+                       partials, out, ss);
+    finish(s, partials, nblk, 2, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::norm2(const void* a, int64_t n, double* out) {
-    const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_norm2<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)a, n, partials, out);
-    finish(s, partials, nb, 1, out);
+    const int nblk = nblocks(n);
+    hipLaunchKernelGGL(k_norm2<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)a, n, partials, out, ss);
+    finish(s, partials, nblk, 1, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::dot_norm(const void* q, const void* r, int64_t n, double* out) {
-    const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_dot_norm<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)q, (const cpx<R>*)r, n,
-                       partials, out);
-    finish(s, partials, nb, 3, out);
+    const int nblk = nblocks(n);
+    hipLaunchKernelGGL(k_dot_norm<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)q, (const cpx<R>*)r, n,
+                       partials, out, ss);
+    finish(s, partials, nblk, 3, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -388,10 +413,10 @@ template <typename R>
 qmg_status Blas::multi_dot(const void* Q, int64_t ld, int k, const void* q, int64_t n, double* out) {
     if (k <= 0) return QMG_OK;
     if (k > 16) return fail(QMG_ERR_ARG, "multi_dot: k=%d > 16", k);
-    const int nb = nblocks(n);
-    hipLaunchKernelGGL(k_multi_dot<R>, dim3(nb), dim3(rthreads(nb)), 0, s, (const cpx<R>*)Q, ld, k, (const cpx<R>*)q, n,
-                       partials, out);
-    finish(s, partials, nb, 2 * k, out);
+    const int nblk = nblocks(n);
+    hipLaunchKernelGGL(k_multi_dot<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)Q, ld, k,
+                       (const cpx<R>*)q, n, partials, out, ss);
+    finish(s, partials, nblk, 2 * k, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -399,44 +424,44 @@ template <typename R>
 qmg_status Blas::multi_axpy(const double* beta, const void* Q, const void* Z, int64_t ld, int k, void* q, void* z,
                             int64_t n) {
     if (k <= 0) return QMG_OK;
-    hipLaunchKernelGGL(k_multi_axpy<R>, dim3(grid1(n)), dim3(kThreads), 0, s, beta, (const cpx<R>*)Q,
-                       (const cpx<R>*)Z, ld, k, (cpx<R>*)q, (cpx<R>*)z, n);
+    hipLaunchKernelGGL(k_multi_axpy<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, beta, (const cpx<R>*)Q,
+                       (const cpx<R>*)Z, ld, k, (cpx<R>*)q, (cpx<R>*)z, n, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R>
 qmg_status Blas::gcr_update(const double* s3, void* q, void* z, void* x, void* r, int64_t n) {
-    hipLaunchKernelGGL(k_gcr_update<R>, dim3(grid1(n)), dim3(kThreads), 0, s, s3, (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x,
-                       (cpx<R>*)r, n);
+    hipLaunchKernelGGL(k_gcr_update<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, s3, (cpx<R>*)q, (cpx<R>*)z,
+                       (cpx<R>*)x, (cpx<R>*)r, n, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R>
 qmg_status Blas::mr_update(const double* s3, const void* rin, void* r, const void* Ar, void* x, int first, int64_t n) {
-    hipLaunchKernelGGL(k_mr_update<R>, dim3(grid1(n)), dim3(kThreads), 0, s, s3, (const cpx<R>*)rin, (cpx<R>*)r,
-                       (const cpx<R>*)Ar, (cpx<R>*)x, first, n);
+    hipLaunchKernelGGL(k_mr_update<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, s3, (const cpx<R>*)rin, (cpx<R>*)r,
+                       (const cpx<R>*)Ar, (cpx<R>*)x, first, n, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::axpy(double a, const void* x, void* y, int64_t n) {
-    hipLaunchKernelGGL(k_axpy<R>, dim3(grid1(n)), dim3(kThreads), 0, s, (R)a, (const cpx<R>*)x, (cpx<R>*)y, n);
+    hipLaunchKernelGGL(k_axpy<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, (R)a, (const cpx<R>*)x, (cpx<R>*)y, n);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::xmy(const void* b, const void* ax, void* r, int64_t n) {
-    hipLaunchKernelGGL(k_xmy<R>, dim3(grid1(n)), dim3(kThreads), 0, s, (const cpx<R>*)b, (const cpx<R>*)ax,
+    hipLaunchKernelGGL(k_xmy<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, (const cpx<R>*)b, (const cpx<R>*)ax,
                        (cpx<R>*)r, n);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename Rs, typename Rd> qmg_status Blas::convert(const void* src, void* dst, int64_t n) {
-    hipLaunchKernelGGL((k_convert<Rs, Rd>), dim3(grid1(n)), dim3(kThreads), 0, s, (const cpx<Rs>*)src,
+    hipLaunchKernelGGL((k_convert<Rs, Rd>), dim3(grid1(n), nb), dim3(kThreads), 0, s, (const cpx<Rs>*)src,
                        (cpx<Rd>*)dst, n);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, int64_t n) {
-    hipLaunchKernelGGL(k_normalize<R>, dim3(grid1(n)), dim3(kThreads), 0, s, (cpx<R>*)x, nrm2, n);
+    hipLaunchKernelGGL(k_normalize<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, (cpx<R>*)x, nrm2, n, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }

@@ -34,6 +34,7 @@
 //         direction block), value = scale * stored; FP32 arithmetic; vectors
 //         either complex64 or 16-bit pairs with one FP32 scale per site
 //         (scale = largest |re| or |im| of the site's N components).
+#include "codes16.h"
 #include "handles.h"
 
 #include <algorithm>
@@ -41,36 +42,11 @@
 
 namespace qmg {
 
-// ------------------------------------------------------------ 16-bit codes
-__device__ __forceinline__ uint16_t f32_to_h16(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
-__device__ __forceinline__ float h16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
-__device__ __forceinline__ uint16_t f32_to_b16(float f) {  // round to nearest even
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float b16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
-
-enum { FMT_F64 = 0, FMT_F32 = 1, FMT_H16 = 2, FMT_B16 = 3 };
-
 template <int F> struct Fmt;
 template <> struct Fmt<FMT_F64> { using R = double; using C = double2; static constexpr int cpc = 1; };
 template <> struct Fmt<FMT_F32> { using R = float; using C = float4; static constexpr int cpc = 2; };
 template <> struct Fmt<FMT_H16> { using R = float; using C = uint4; static constexpr int cpc = 4; };
 template <> struct Fmt<FMT_B16> { using R = float; using C = uint4; static constexpr int cpc = 4; };
-
-template <int F> __device__ __forceinline__ float dec16(uint16_t v) {
-    return F == FMT_H16 ? h16_to_f32(v) : b16_to_f32(v);
-}
-template <int F> __device__ __forceinline__ uint16_t enc16(float v) {
-    return F == FMT_H16 ? f32_to_h16(v) : f32_to_b16(v);
-}
-template <int F> __device__ __forceinline__ cpx<float> dec_pair(uint32_t w) {
-    return cpx<float>{dec16<F>((uint16_t)(w & 0xffffu)), dec16<F>((uint16_t)(w >> 16))};
-}
-template <int F> __device__ __forceinline__ uint32_t enc_pair(float re, float im) {
-    return (uint32_t)enc16<F>(re) | ((uint32_t)enc16<F>(im) << 16);
-}
 
 // a += chunk * b[0..cpc)
 __device__ __forceinline__ void chunk_mac(const double2 a, const cpx<double>* b, double& ar, double& ai) {
@@ -184,7 +160,7 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
                                                         const int* __restrict__ nbr, const void* __restrict__ uin,
                                                         const float* __restrict__ uscale, void* __restrict__ yout,
                                                         float* __restrict__ yscale, int N, int J, int rows, int split,
-                                                        int ntiles) {
+                                                        int ntiles, int64_t V) {
     using R = typename Fmt<F>::R;
     using C = typename Fmt<F>::C;
     constexpr int cpc = Fmt<F>::cpc;
@@ -194,6 +170,7 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
 
     const int site = blockIdx.x / ntiles;
     const int tile = blockIdx.x - site * ntiles;
+    const int64_t vo = (int64_t)blockIdx.y * V;      // batch member: its fields follow at member*V sites
     const int t = threadIdx.x;
     const int T = rows * split;
     const int rl = t % rows;
@@ -211,7 +188,7 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
     for (int idx = t; idx < 9 * N; idx += T) {
         const int d = idx / N;
         const int c = idx - d * N;
-        const int src = d == 0 ? site : nbr[site * 8 + d - 1];
+        const int64_t src = (d == 0 ? site : nbr[site * 8 + d - 1]) + vo;
         cpx<R> v;
         if constexpr (VF == 0) {
             v = reinterpret_cast<const cpx<R>*>(uin)[(int64_t)src * N + c];
@@ -255,7 +232,7 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
             }
     }
     if constexpr (VF == 0) {
-        if (s == 0) reinterpret_cast<cpx<R>*>(yout)[(int64_t)site * N + r] = cpx<R>{sr, si};
+        if (s == 0) reinterpret_cast<cpx<R>*>(yout)[(site + vo) * N + r] = cpx<R>{sr, si};
     } else {
         // per-site output scale: all N rows of the site are in this work-group (ntiles == 1)
         __syncthreads();
@@ -266,13 +243,13 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
             float m = 0.f;
             for (int i = 0; i < rows; ++i) m = fmaxf(m, mx[i]);
             mx[rows] = m;
-            yscale[site] = m;
+            yscale[site + vo] = m;
         }
         __syncthreads();
         if (s == 0) {
             const float m = mx[rows];
             const float inv = m > 0 ? 1.0f / m : 0.0f;
-            reinterpret_cast<uint32_t*>(yout)[(int64_t)site * N + r] = enc_pair<VF>((float)sr * inv, (float)si * inv);
+            reinterpret_cast<uint32_t*>(yout)[(site + vo) * N + r] = enc_pair<VF>((float)sr * inv, (float)si * inv);
         }
     }
 }
@@ -294,6 +271,27 @@ __global__ __launch_bounds__(64) void k_quantize(const float2* __restrict__ in, 
         out[site * N + c] = enc_pair<VF>(v.x * inv, v.y * inv);
     }
     if (threadIdx.x == 0) scale[site] = m;
+}
+
+// [m][V][N] complex64 -> 16-bit [V][m][N] with one scale per (site, member) [V][m]
+template <int VF>
+__global__ __launch_bounds__(64) void k_quantize_perm(const float2* __restrict__ in, uint32_t* __restrict__ out,
+                                                      float* __restrict__ scale, int64_t V, int m, int N) {
+    const int64_t g = blockIdx.x;           // input row: member g / V, site g % V
+    const int64_t site = g % V, j = g / V;
+    const int64_t o = site * m + j;         // output row
+    float mx = 0.f;
+    for (int c = threadIdx.x; c < N; c += 64) {
+        const float2 v = in[g * N + c];
+        mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
+    for (int k = 32; k > 0; k >>= 1) mx = fmaxf(mx, __shfl_xor(mx, k, 64));
+    const float inv = mx > 0 ? 1.0f / mx : 0.0f;
+    for (int c = threadIdx.x; c < N; c += 64) {
+        const float2 v = in[g * N + c];
+        out[o * N + c] = enc_pair<VF>(v.x * inv, v.y * inv);
+    }
+    if (threadIdx.x == 0) scale[o] = mx;
 }
 
 template <int VF>
@@ -351,17 +349,17 @@ static qmg_status validate_launch(const qmg_coarse_op_s* op, int rows, int split
 
 template <int F, int VF>
 static qmg_status launch_f(const qmg_coarse_op_s* op, int rows, int split, int pre, const void* in,
-                           const float* in_scale, void* out, float* out_scale, hipStream_t s) {
+                           const float* in_scale, void* out, float* out_scale, int m, hipStream_t s) {
     using R = typename Fmt<F>::R;
     const int ntiles = op->N / rows;
     const size_t lds = sizeof(cpx<R>) * (9 * op->N + std::max(rows * split, rows + 1));
-    const dim3 grid((unsigned)(op->V * ntiles)), block((unsigned)(rows * split));
+    const dim3 grid((unsigned)(op->V * ntiles), (unsigned)m), block((unsigned)(rows * split));
     const auto* L = reinterpret_cast<const typename Fmt<F>::C*>(op->links);
     const int K = op->J / split;
     if (pre <= 0) pre = K >= 16 ? 16 : 4;
 #define QMG_CD_LAUNCH(P)                                                                                          \
     hipLaunchKernelGGL((k_coarse_dslash<F, VF, P>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale, out, \
-                       out_scale, op->N, op->J, rows, split, ntiles)
+                       out_scale, op->N, op->J, rows, split, ntiles, op->V)
     if (pre >= 16) QMG_CD_LAUNCH(16);
     else if (pre >= 8) QMG_CD_LAUNCH(8);
     else if (pre >= 4) QMG_CD_LAUNCH(4);
@@ -372,31 +370,60 @@ static qmg_status launch_f(const qmg_coarse_op_s* op, int rows, int split, int p
 }
 
 qmg_status coarse_dslash_launch(const qmg_coarse_op_s* op, int rows, int split, int pre, const void* in,
-                                const float* in_scale, void* out, float* out_scale, qmg_prec vprec, hipStream_t s) {
+                                const float* in_scale, void* out, float* out_scale, qmg_prec vprec, hipStream_t s,
+                                int m) {
     const bool v16 = is16(vprec);
     if (v16 && rows != op->N) {  // per-site output scale needs the whole site in one work-group
         rows = op->N;
         while (rows * split > 1024 || op->J % split) --split;
     }
     switch (op->storage) {
-        case QMG_C128: return launch_f<FMT_F64, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
-        case QMG_C64: return launch_f<FMT_F32, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
+        case QMG_C128: return launch_f<FMT_F64, 0>(op, rows, split, pre, in, nullptr, out, nullptr, m, s);
+        case QMG_C64: return launch_f<FMT_F32, 0>(op, rows, split, pre, in, nullptr, out, nullptr, m, s);
         case QMG_H16:
-            if (vprec == QMG_C64) return launch_f<FMT_H16, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
+            if (vprec == QMG_C64) return launch_f<FMT_H16, 0>(op, rows, split, pre, in, nullptr, out, nullptr, m, s);
             if (vprec == QMG_H16)
-                return launch_f<FMT_H16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
-            return launch_f<FMT_H16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
+                return launch_f<FMT_H16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, m, s);
+            return launch_f<FMT_H16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, m, s);
         default:
-            if (vprec == QMG_C64) return launch_f<FMT_B16, 0>(op, rows, split, pre, in, nullptr, out, nullptr, s);
+            if (vprec == QMG_C64) return launch_f<FMT_B16, 0>(op, rows, split, pre, in, nullptr, out, nullptr, m, s);
             if (vprec == QMG_H16)
-                return launch_f<FMT_B16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
-            return launch_f<FMT_B16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, s);
+                return launch_f<FMT_B16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, m, s);
+            return launch_f<FMT_B16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, m, s);
     }
 }
 
 qmg_status coarse_dslash_any(const qmg_coarse_op_s* op, const void* in, const float* in_scale, void* out,
                              float* out_scale, qmg_prec vprec, hipStream_t s) {
-    return coarse_dslash_launch(op, op->rows, op->split, op->pre, in, in_scale, out, out_scale, vprec, s);
+    return coarse_dslash_launch(op, op->rows, op->split, op->pre, in, in_scale, out, out_scale, vprec, s, 1);
+}
+
+qmg_status coarse_mrhs(qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int nrhs, int rpw,
+                       hipStream_t s, int64_t ors);
+
+bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m) {
+    return is16(op->storage) && op->N % 16 == 0 && op->N <= 64 && (m == 8 || m == 16 || m == 32 || m == 64);
+}
+
+// Solver-side batched application, fields [m][V][N] in `vprec` (complex128 or
+// complex64).  A 16-bit operator with m in {8, 16, 32, 64} runs on the matrix
+// cores: the inputs are rounded to 16 bits with one scale per (site, member)
+// into q16 [V][m][N] / qsc [V][m] (caller-provided), then one multi-RHS launch
+// writes the complex64 outputs in place.  Otherwise one launch of the
+// single-RHS kernel covers all members (grid dimension y).
+qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec vprec, int m, void* q16,
+                        float* qsc, hipStream_t s) {
+    if (m > 1 && vprec == QMG_C64 && q16 && coarse_batch_uses_mfma(op, m)) {
+        if (op->storage == QMG_H16)
+            hipLaunchKernelGGL(k_quantize_perm<FMT_H16>, dim3((unsigned)(op->V * m)), dim3(64), 0, s, (const float2*)in,
+                               (uint32_t*)q16, qsc, op->V, m, op->N);
+        else
+            hipLaunchKernelGGL(k_quantize_perm<FMT_B16>, dim3((unsigned)(op->V * m)), dim3(64), 0, s, (const float2*)in,
+                               (uint32_t*)q16, qsc, op->V, m, op->N);
+        QMG_LAUNCH_CHECK();
+        return coarse_mrhs(op, q16, qsc, out, m, 0, s, op->V * op->N);
+    }
+    return coarse_dslash_launch(op, op->rows, op->split, op->pre, in, nullptr, out, nullptr, vprec, s, m);
 }
 
 }  // namespace qmg

@@ -76,7 +76,7 @@ template <int F, int N, int NRHS, int RPW>
 __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* __restrict__ M,
                                           const float* __restrict__ lscale, const int* __restrict__ nbr,
                                           const uint32_t* __restrict__ u, const float* __restrict__ uscale,
-                                          float2* __restrict__ y, unsigned char* smem) {
+                                          float2* __restrict__ y, int64_t oss, int64_t ors, unsigned char* smem) {
     constexpr int T = N / 16;                       // row tiles = k steps per direction
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;  // right-hand-side tiles
     constexpr int NW = T * (NT / RPW);              // computing waves
@@ -182,7 +182,7 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
         for (int t = 0; t < RPW; ++t) {
             const int j = (tg * RPW + t) * 16 + jl;
             if (NRHS < 16 && j >= NRHS) continue;
-            float2* o = y + ((int64_t)site * NRHS + j) * N + rt * 16 + 4 * (l / 16);
+            float2* o = y + (int64_t)site * oss + (int64_t)j * ors + rt * 16 + 4 * (l / 16);
             float4* o4 = reinterpret_cast<float4*>(o);
             o4[0] = make_float4(tot[t][0][0], tot[t][1][0], tot[t][0][1], tot[t][1][1]);
             o4[1] = make_float4(tot[t][0][2], tot[t][1][2], tot[t][0][3], tot[t][1][3]);
@@ -193,9 +193,9 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
 template <int F, int N, int NRHS, int RPW>
 __global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 64) void k_coarse_mrhs(
     const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
-    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y) {
+    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y, int64_t oss, int64_t ors) {
     extern __shared__ __align__(16) unsigned char smem[];
-    mrhs_site<F, N, NRHS, RPW>(blockIdx.x, blockDim.x, M, lscale, nbr, u, uscale, y, smem);
+    mrhs_site<F, N, NRHS, RPW>(blockIdx.x, blockDim.x, M, lscale, nbr, u, uscale, y, oss, ors, smem);
 }
 
 // Persistent form over several operators ("levels") of possibly different
@@ -222,15 +222,18 @@ __global__ __launch_bounds__(4 * (NRHS >= 16 ? NRHS / 16 : 1) * 64) void k_coars
         while (l + 1 < ml.nlev && item >= ml.start[l + 1]) ++l;
         const int site = (int)(item - ml.start[l]);
         if (ml.N[l] == 48)
-            mrhs_site<F, 48, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l], smem);
+            mrhs_site<F, 48, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l],
+                                      (int64_t)NRHS * 48, 48, smem);
         else
-            mrhs_site<F, 64, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l], smem);
+            mrhs_site<F, 64, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l],
+                                      (int64_t)NRHS * 64, 64, smem);
         __syncthreads();  // LDS is reused by the next item
     }
 }
 
 template <int F, int N, int NRHS, int RPW>
-static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const float* sc, void* out, hipStream_t s) {
+static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int64_t ors,
+                                hipStream_t s) {
     constexpr int T = N / 16;
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
     constexpr int NW = T * (NT / RPW);
@@ -238,28 +241,29 @@ static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const
     auto kern = k_coarse_mrhs<F, N, NRHS, RPW>;
     if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(kern, dim3((unsigned)op->V), dim3(NW * 64), lds, s, (const uint4*)op->mlinks, op->lscale, op->nbr,
-                       (const uint32_t*)in, sc, (float2*)out);
+                       (const uint32_t*)in, sc, (float2*)out, ors ? (int64_t)N : (int64_t)NRHS * N, ors ? ors : (int64_t)N);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
 template <int F, int N, int NRHS>
-static qmg_status launch_rpw(const qmg_coarse_op_s* op, int rpw, const void* in, const float* sc, void* out, hipStream_t s) {
+static qmg_status launch_rpw(const qmg_coarse_op_s* op, int rpw, const void* in, const float* sc, void* out, int64_t ors,
+                             hipStream_t s) {
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
-    if (rpw == 1) return launch_mrhs_t<F, N, NRHS, 1>(op, in, sc, out, s);
-    if constexpr (NT >= 2) if (rpw == 2) return launch_mrhs_t<F, N, NRHS, 2>(op, in, sc, out, s);
-    if constexpr (NT >= 4) if (rpw == 4) return launch_mrhs_t<F, N, NRHS, 4>(op, in, sc, out, s);
+    if (rpw == 1) return launch_mrhs_t<F, N, NRHS, 1>(op, in, sc, out, ors, s);
+    if constexpr (NT >= 2) if (rpw == 2) return launch_mrhs_t<F, N, NRHS, 2>(op, in, sc, out, ors, s);
+    if constexpr (NT >= 4) if (rpw == 4) return launch_mrhs_t<F, N, NRHS, 4>(op, in, sc, out, ors, s);
     return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: rpw %d not available for nrhs %d", rpw, NRHS);
 }
 
 template <int F, int N>
 static qmg_status launch_n(const qmg_coarse_op_s* op, int nrhs, int rpw, const void* in, const float* sc, void* out,
-                           hipStream_t s) {
+                           int64_t ors, hipStream_t s) {
     switch (nrhs) {
-        case 8: return launch_rpw<F, N, 8>(op, rpw, in, sc, out, s);
-        case 16: return launch_rpw<F, N, 16>(op, rpw, in, sc, out, s);
-        case 32: return launch_rpw<F, N, 32>(op, rpw, in, sc, out, s);
-        case 64: return launch_rpw<F, N, 64>(op, rpw, in, sc, out, s);
+        case 8: return launch_rpw<F, N, 8>(op, rpw, in, sc, out, ors, s);
+        case 16: return launch_rpw<F, N, 16>(op, rpw, in, sc, out, ors, s);
+        case 32: return launch_rpw<F, N, 32>(op, rpw, in, sc, out, ors, s);
+        case 64: return launch_rpw<F, N, 64>(op, rpw, in, sc, out, ors, s);
     }
     return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: nrhs %d not in {8,16,32,64}", nrhs);
 }
@@ -277,8 +281,10 @@ static int default_rpw(const qmg_coarse_op_s* op, int nrhs) {
     return rpw;
 }
 
+// ors = 0: output [V][nrhs][N]; otherwise right-hand side j of site x at
+// out + j*ors + x*N (ors = V*N gives [nrhs][V][N])
 qmg_status coarse_mrhs(qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int nrhs, int rpw,
-                       hipStream_t s) {
+                       hipStream_t s, int64_t ors) {
     if (!op->mlinks) {
         const int T = op->N / 16;
         const int64_t n = op->V * 9 * T * T * 64;
@@ -289,10 +295,10 @@ qmg_status coarse_mrhs(qmg_coarse_op_s* op, const void* in, const float* sc, voi
     }
     if (rpw <= 0) rpw = op->rpw[log2i(nrhs)] > 0 ? op->rpw[log2i(nrhs)] : default_rpw(op, nrhs);
     const bool h = op->storage == QMG_H16;
-    if (op->N == 48) return h ? launch_n<MF_H16, 48>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 48>(op, nrhs, rpw, in, sc, out, s);
-    if (op->N == 64) return h ? launch_n<MF_H16, 64>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 64>(op, nrhs, rpw, in, sc, out, s);
-    if (op->N == 32) return h ? launch_n<MF_H16, 32>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 32>(op, nrhs, rpw, in, sc, out, s);
-    if (op->N == 16) return h ? launch_n<MF_H16, 16>(op, nrhs, rpw, in, sc, out, s) : launch_n<MF_B16, 16>(op, nrhs, rpw, in, sc, out, s);
+    if (op->N == 48) return h ? launch_n<MF_H16, 48>(op, nrhs, rpw, in, sc, out, ors, s) : launch_n<MF_B16, 48>(op, nrhs, rpw, in, sc, out, ors, s);
+    if (op->N == 64) return h ? launch_n<MF_H16, 64>(op, nrhs, rpw, in, sc, out, ors, s) : launch_n<MF_B16, 64>(op, nrhs, rpw, in, sc, out, ors, s);
+    if (op->N == 32) return h ? launch_n<MF_H16, 32>(op, nrhs, rpw, in, sc, out, ors, s) : launch_n<MF_B16, 32>(op, nrhs, rpw, in, sc, out, ors, s);
+    if (op->N == 16) return h ? launch_n<MF_H16, 16>(op, nrhs, rpw, in, sc, out, ors, s) : launch_n<MF_B16, 16>(op, nrhs, rpw, in, sc, out, ors, s);
     return fail(QMG_ERR_SHAPE, "coarse_dslash_mrhs: N=%d not in {16,32,48,64}", op->N);
 }
 
@@ -309,7 +315,7 @@ extern "C" qmg_status qmg_coarse_dslash_mrhs(qmg_coarse_op op, const void* in, c
         return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: nrhs %d not in {8,16,32,64}", nrhs);
     if (op->N % 16 || op->N > 64) return fail(QMG_ERR_SHAPE, "coarse_dslash_mrhs: N=%d must be 16, 32, 48 or 64", op->N);
     if (in == out) return fail(QMG_ERR_ARG, "coarse_dslash_mrhs: in and out alias");
-    return coarse_mrhs(op, in, in_scale, out, nrhs, 0, as_stream(stream));
+    return coarse_mrhs(op, in, in_scale, out, nrhs, 0, as_stream(stream), 0);
 }
 
 extern "C" qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, int rhs_tiles_per_wave) {

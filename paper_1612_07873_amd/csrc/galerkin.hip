@@ -201,6 +201,9 @@ extern "C" qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_
         return fail(QMG_ERR_SHAPE, "build_coarse_op: parent dof x N = %d exceeds 4096", pdof * N);
     if (storage != QMG_C128 && storage != QMG_C64)
         return fail(QMG_ERR_PREC, "build_coarse_op: storage %d not supported", (int)storage);
+    const qmg_prec from = fine ? fine->storage : parent->storage;
+    if (from != QMG_C128 && from != QMG_C64)
+        return fail(QMG_ERR_PREC, "build_coarse_op: the parent operator must use complex128 or complex64 storage");
     hipStream_t s = as_stream(stream);
     const int64_t Vc = t->Vc;
     const size_t blk = (size_t)Vc * N * N;

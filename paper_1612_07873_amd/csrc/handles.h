@@ -26,6 +26,8 @@ struct qmg_fine_op_s {
     qmg_prec storage;
     void* U;     // [4][9][V] complex, time sign folded into U_3 on the last slice
     void* clov;  // [2][36][V] reals: 6 diagonal, then 15 upper off-diagonal complex
+                 // (16-bit storages: [2][18][V] pairs of those reals)
+    float* cscale;  // [2][V] clover scales of the 16-bit storages, else NULL
     int* nbr;    // [V][8]
 };
 

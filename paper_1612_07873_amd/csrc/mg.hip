@@ -17,6 +17,14 @@
 // passes keep it as stable).  When the iterated residual reaches the
 // tolerance, or after `restart` steps, the true residual b - A x is recomputed
 // in FP64 (a reliable update) and the cycle restarts from it.
+//
+// Several right-hand sides are solved together as a batch of nb members run
+// in lock step: every field of the batch is [member][site][component], each
+// kernel launch covers all members (grid dimension y), each member keeps its
+// own scalars (its own Krylov space, step lengths and stopping test), and a
+// level's GCR stops when every member has reached its tolerance.  With a
+// 16-bit coarse operator and 8, 16, 32 or 64 members the coarse stencil runs
+// as one multi-right-hand-side matrix-core product.
 #include "blas.h"
 #include "handles.h"
 
@@ -27,9 +35,14 @@
 struct qmg_mg_s;
 
 namespace qmg {
-qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s);
-qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s);
+qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, int nb, hipStream_t s);
+qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, int nb, hipStream_t s);
 qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s);
+qmg_status wilson_apply(const qmg_fine_op_s* op, const void* in, void* out, qmg_prec vprec, int members,
+                        hipStream_t s);
+qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec vprec, int m, void* q16,
+                        float* qsc, hipStream_t s);
+bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m);
 }
 
 using namespace qmg;
@@ -49,6 +62,8 @@ struct Level {
     // K-cycle on this level
     void *mr_r = nullptr, *mr_Ar = nullptr, *kt = nullptr, *kr2 = nullptr, *kx2 = nullptr;
     void *kin = nullptr, *kout = nullptr;  // level 0 only: inner-precision copies
+    void* q16 = nullptr;            // batched 16-bit stencil input [V][nb][N] (multi-RHS matrix-core path)
+    float* qsc = nullptr;           // its scales [V][nb]
 };
 
 }  // namespace
@@ -63,7 +78,10 @@ struct qmg_mg_s {
     double* hsc = nullptr;   // pinned host mirror
     // outer FP64 workspace (level 0)
     void *Q64 = nullptr, *Z64 = nullptr, *r64 = nullptr, *x64 = nullptr, *t64 = nullptr;
-    std::vector<void*> allocs;
+    std::vector<void*> allocs;   // setup-time and lifetime allocations
+    std::vector<void*> sallocs;  // solve workspace, sized for `cap` batch members
+    int cap = 0;                 // batch members the solve workspace holds
+    int nb = 1;                  // members of the running solve
     hipStream_t s = nullptr;
     int level_iters[8] = {0};
     qmg_ptc ptc = nullptr;      // learned level-0 smoother (NULL: MR)
@@ -74,7 +92,7 @@ struct qmg_mg_s {
 
 namespace {
 
-constexpr int kScal = 64;  // device scalar slots
+constexpr int kScal = 64;  // device scalar slots per batch member (member b at b*kScal)
 // slot map
 constexpr int S_BETA = 0;     // 32 doubles (16 complex)
 constexpr int S_GCR = 32;     // 3
@@ -92,14 +110,30 @@ qmg_status alloc(qmg_mg_s* mg, void** p, size_t bytes) {
     return QMG_OK;
 }
 
-template <typename R> qmg_status apply_op(qmg_mg_s* mg, int l, const void* in, void* out) {
-    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
-    if (l == 0) return qmg_wilson_clover_dslash(mg->fine_in, in, out, p, mg->s);
-    return qmg_coarse_dslash(mg->lv[l].op, in, out, p, mg->s);
+qmg_status salloc(qmg_mg_s* mg, void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(QMG_ERR_NOMEM, "mg: workspace of %zu bytes: %s", bytes, hipGetErrorString(e));
+    mg->sallocs.push_back(*p);
+    return QMG_OK;
 }
 
+// scalar slot `slot` of batch member b (host mirror)
+inline double& hs(qmg_mg_s* mg, int b, int slot) { return mg->hsc[(size_t)b * kScal + slot]; }
+
+template <typename R> qmg_status apply_op(qmg_mg_s* mg, int l, const void* in, void* out) {
+    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    if (l == 0) return wilson_apply(mg->fine_in, in, out, p, mg->nb, mg->s);
+    Level& L = mg->lv[l];
+    return coarse_apply(L.op, in, out, p, mg->nb, L.q16, L.qsc, mg->s);
+}
+
+// copy every member's slots [first, first+count) to the host and wait
 qmg_status read_scalars(qmg_mg_s* mg, int first, int count) {
-    QMG_HIP(hipMemcpyAsync(mg->hsc + first, mg->dsc + first, sizeof(double) * count, hipMemcpyDeviceToHost, mg->s));
+    if (mg->nb == 1)
+        QMG_HIP(hipMemcpyAsync(mg->hsc + first, mg->dsc + first, sizeof(double) * count, hipMemcpyDeviceToHost, mg->s));
+    else
+        QMG_HIP(hipMemcpy2DAsync(mg->hsc + first, sizeof(double) * kScal, mg->dsc + first, sizeof(double) * kScal,
+                                 sizeof(double) * count, mg->nb, hipMemcpyDeviceToHost, mg->s));
     QMG_HIP(hipStreamSynchronize(mg->s));
     return QMG_OK;
 }
@@ -124,6 +158,7 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
 template <typename R> qmg_status mr(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
     const int64_t n = L.n;
+    const int nb = mg->nb;
     for (int it = 0; it < L.p.smoother_steps; ++it) {
         const void* cur = it == 0 ? r : L.mr_r;   // the first step reads r itself
         QMG_TRY(apply_op<R>(mg, l, cur, L.mr_Ar));
@@ -131,71 +166,83 @@ template <typename R> qmg_status mr(qmg_mg_s* mg, int l, const void* r, void* x)
         QMG_TRY(mg->blas.mr_update<R>(mg->dsc + S_MR, cur, L.mr_r, L.mr_Ar, x, it == 0, n));
     }
     if (L.p.smoother_steps <= 0) {
-        QMG_HIP(hipMemsetAsync(x, 0, n * sizeof(cpx<R>), mg->s));
-        QMG_HIP(hipMemcpyAsync(L.mr_r, r, n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
+        QMG_HIP(hipMemsetAsync(x, 0, nb * n * sizeof(cpx<R>), mg->s));
+        QMG_HIP(hipMemcpyAsync(L.mr_r, r, nb * n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
     }
     return QMG_OK;
 }
 
 // GCR on level l (l >= 1 uses the level's op; l == 0 with inner precision is
-// used by the setup).  Solves A x = b from x (if x0) or from 0.
+// used by the setup).  Solves A x = b from x (if x0) or from 0, for every
+// batch member; stops when all members reach tol (or after maxit steps).
 template <typename R>
 qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol, int maxit, bool precond,
                int* iters_out) {
     Level& L = mg->lv[l];
     const int64_t n = L.n;
     const int m = mg->restart;
-    const size_t vb = n * sizeof(cpx<R>);
-    double bnorm;
+    const int nb = mg->nb;
+    const size_t vb = n * sizeof(cpx<R>);   // one member's field
+    const size_t bb = nb * vb;              // the batch's field (one Krylov direction of all members)
+    double bnorm[Blas::kMaxBatch];
     QMG_TRY(mg->blas.norm2<R>(b, n, mg->dsc + S_BN));
     QMG_TRY(read_scalars(mg, S_BN, 1));
-    bnorm = std::sqrt(mg->hsc[S_BN]);
+    for (int k = 0; k < nb; ++k) bnorm[k] = std::sqrt(hs(mg, k, S_BN));
     if (x0) {
         QMG_TRY(apply_op<R>(mg, l, x, L.t));
         QMG_TRY(mg->blas.xmy<R>(b, L.t, L.r, n));
     } else {
-        QMG_HIP(hipMemsetAsync(x, 0, vb, mg->s));
-        QMG_HIP(hipMemcpyAsync(L.r, b, vb, hipMemcpyDeviceToDevice, mg->s));
+        QMG_HIP(hipMemsetAsync(x, 0, bb, mg->s));
+        QMG_HIP(hipMemcpyAsync(L.r, b, bb, hipMemcpyDeviceToDevice, mg->s));
     }
-    const double target = tol * bnorm;
+    // all members converged (or broken down: q = 0) after the scalars in slots
+    // S_GCR (and rnorm2 at `rslot`) were read
+    auto all_done = [&](int rslot, bool* fault) {
+        bool done = true;
+        for (int k = 0; k < nb; ++k) {
+            const double rn = std::sqrt(hs(mg, k, rslot));
+            if (!std::isfinite(rn) || !std::isfinite(hs(mg, k, S_GCR))) *fault = true;
+            const bool ok = hs(mg, k, S_GCR) <= 0.0 || (bnorm[k] > 0 && rn <= tol * bnorm[k]) || bnorm[k] == 0;
+            done = done && ok;
+        }
+        return done;
+    };
     int iters = 0;
     bool done = false;
+    const int64_t ld = (int64_t)nb * n;
     // short unpreconditioned systems (the coarsest level): the whole step's
-    // vector work is one single-work-group kernel, so a step is two launches
+    // vector work is one single-work-group kernel per member, so a step is two launches
     const bool small = !precond && n <= Blas::kSmall;
     while (!done && iters < maxit) {
         int j = 0;
-        if (small) QMG_HIP(hipMemcpyAsync(L.Z, L.r, vb, hipMemcpyDeviceToDevice, mg->s));
+        if (small) QMG_HIP(hipMemcpyAsync(L.Z, L.r, bb, hipMemcpyDeviceToDevice, mg->s));
         for (; j < m && iters < maxit; ++j) {
-            void* z = (char*)L.Z + j * vb;
-            void* q = (char*)L.Q + j * vb;
+            void* z = (char*)L.Z + j * bb;
+            void* q = (char*)L.Q + j * bb;
+            bool fault = false;
             if (small) {
                 QMG_TRY(apply_op<R>(mg, l, z, q));
-                void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * vb : nullptr;
-                QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, n, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext));
+                void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * bb : nullptr;
+                QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, ld, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext));
                 QMG_TRY(read_scalars(mg, S_GCR, 4));
                 ++iters;
-                const double rn = std::sqrt(mg->hsc[S_GCR + 3]);
-                if (!std::isfinite(rn) || !std::isfinite(mg->hsc[S_GCR]))
-                    return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
-                if (mg->hsc[S_GCR] <= 0.0) { done = true; ++j; break; }
-                if (bnorm > 0 && rn <= target) { done = true; ++j; break; }
+                done = all_done(S_GCR + 3, &fault);
+                if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
+                if (done) { ++j; break; }
                 continue;
             }
             if (precond) QMG_TRY(kcycle<R>(mg, l, L.r, z));
-            else QMG_HIP(hipMemcpyAsync(z, L.r, vb, hipMemcpyDeviceToDevice, mg->s));
+            else QMG_HIP(hipMemcpyAsync(z, L.r, bb, hipMemcpyDeviceToDevice, mg->s));
             QMG_TRY(apply_op<R>(mg, l, z, q));
-            QMG_TRY(orthogonalize<R>(mg, L.Q, L.Z, n, j, q, z, n));
+            QMG_TRY(orthogonalize<R>(mg, L.Q, L.Z, ld, j, q, z, n));
             QMG_TRY(mg->blas.dot_norm<R>(q, L.r, n, mg->dsc + S_GCR));
             QMG_TRY(mg->blas.gcr_update<R>(mg->dsc + S_GCR, q, z, x, L.r, n));
             QMG_TRY(mg->blas.norm2<R>(L.r, n, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
             ++iters;
-            const double rn = std::sqrt(mg->hsc[S_NRM]);
-            if (!std::isfinite(rn) || !std::isfinite(mg->hsc[S_GCR]))
-                return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
-            if (mg->hsc[S_GCR] <= 0.0) { done = true; ++j; break; }  // breakdown: q = 0
-            if (bnorm > 0 && rn <= target) { done = true; ++j; break; }
+            done = all_done(S_NRM, &fault);
+            if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
+            if (done) { ++j; break; }
         }
         if (done || iters >= maxit) break;
         // restart from the true residual
@@ -208,19 +255,26 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
 
 // Level smoother: MR, or on level 0 the learned network when one is attached.
 // The network's result is kept only if it reduces the residual; otherwise
-// (including NaN/Inf from bad weights) MR is used for this application.
+// (including NaN/Inf from bad weights) MR is used for this application.  In a
+// batch the network runs on every member and is kept only if it reduces every
+// member's residual; each member whose residual grew counts as a fallback.
 // On exit lv.mr_r holds r - A x.
 template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
     if (l == 0 && mg->ptc && sizeof(R) == 4) {
-        QMG_TRY(ptc_forward(mg->ptc, r, x, mg->s));
+        const size_t vb = L.n * sizeof(cpx<R>);
+        for (int k = 0; k < mg->nb; ++k)
+            QMG_TRY(ptc_forward(mg->ptc, (const char*)r + k * vb, (char*)x + k * vb, mg->s));
         QMG_TRY(apply_op<R>(mg, 0, x, L.mr_Ar));
         QMG_TRY(mg->blas.xmy<R>(r, L.mr_Ar, L.mr_r, L.n));
         QMG_TRY(mg->blas.norm2<R>(r, L.n, mg->dsc + S_SM));
         QMG_TRY(mg->blas.norm2<R>(L.mr_r, L.n, mg->dsc + S_SM + 1));
         QMG_TRY(read_scalars(mg, S_SM, 2));
-        if (mg->hsc[S_SM + 1] < mg->hsc[S_SM]) return QMG_OK;
-        ++mg->fallbacks;
+        int worse = 0;
+        for (int k = 0; k < mg->nb; ++k)
+            if (!(hs(mg, k, S_SM + 1) < hs(mg, k, S_SM))) ++worse;
+        if (worse == 0) return QMG_OK;
+        mg->fallbacks += worse;
     }
     return mr<R>(mg, l, r, x);
 }
@@ -233,12 +287,12 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     const int nl = (int)mg->lv.size();
     // pre-smoothing; L.mr_r = rin - A zout afterwards
     QMG_TRY(smooth<R>(mg, l, rin, zout));
-    QMG_TRY(transfer_restrict(L.T, L.mr_r, C.b, p, mg->s));
+    QMG_TRY(transfer_restrict(L.T, L.mr_r, C.b, p, mg->nb, mg->s));
     const bool coarsest = (l + 1 == nl - 1);
     int it = 0;
     QMG_TRY(gcr<R>(mg, l + 1, C.b, C.x, false, L.p.coarse_tol, L.p.coarse_maxit, !coarsest, &it));
     mg->level_iters[l + 1] += it;
-    QMG_TRY(transfer_prolong(L.T, C.x, L.kt, p, mg->s));
+    QMG_TRY(transfer_prolong(L.T, C.x, L.kt, p, mg->nb, mg->s));
     QMG_TRY(mg->blas.axpy<R>(1.0, L.kt, zout, n));
     // post-smoothing on r - A z
     QMG_TRY(apply_op<R>(mg, l, zout, L.kt));
@@ -248,13 +302,33 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     return QMG_OK;
 }
 
-template <typename R> qmg_status level_buffers(qmg_mg_s* mg, int l) {
-    Level& L = mg->lv[l];
-    const size_t vb = L.n * sizeof(cpx<R>);
-    void** one[] = {&L.r, &L.x, &L.b, &L.t, &L.mr_r, &L.mr_Ar, &L.kt, &L.kr2, &L.kx2, &L.kin, &L.kout};
-    for (void** p : one) QMG_TRY(alloc(mg, p, vb));
-    QMG_TRY(alloc(mg, &L.Q, vb * mg->restart));
-    QMG_TRY(alloc(mg, &L.Z, vb * mg->restart));
+// Solve workspace of every level and of the FP64 outer solver for `cap`
+// batch members (replacing any smaller one).
+qmg_status workspace(qmg_mg_s* mg, int cap) {
+    for (void* p : mg->sallocs) (void)hipFree(p);
+    mg->sallocs.clear();
+    mg->cap = 0;
+    const size_t cb = mg->inner == QMG_C128 ? 16 : 8;
+    for (size_t l = 0; l < mg->lv.size(); ++l) {
+        Level& L = mg->lv[l];
+        const size_t vb = L.n * cb * cap;
+        void** one[] = {&L.r, &L.x, &L.b, &L.t, &L.mr_r, &L.mr_Ar, &L.kt, &L.kr2, &L.kx2, &L.kin, &L.kout};
+        for (void** p : one) QMG_TRY(salloc(mg, p, vb));
+        QMG_TRY(salloc(mg, &L.Q, vb * mg->restart));
+        QMG_TRY(salloc(mg, &L.Z, vb * mg->restart));
+        L.q16 = nullptr;
+        L.qsc = nullptr;
+        if (l >= 1 && L.op && cap >= 8 && coarse_batch_uses_mfma(L.op, 8)) {
+            QMG_TRY(salloc(mg, &L.q16, (size_t)L.V * cap * L.dof * 4));
+            QMG_TRY(salloc(mg, (void**)&L.qsc, (size_t)L.V * cap * 4));
+        }
+    }
+    const size_t vb64 = mg->lv[0].n * 16 * cap;
+    QMG_TRY(salloc(mg, &mg->Q64, vb64 * mg->restart));
+    QMG_TRY(salloc(mg, &mg->Z64, vb64 * mg->restart));
+    QMG_TRY(salloc(mg, &mg->r64, vb64));
+    QMG_TRY(salloc(mg, &mg->t64, vb64));
+    mg->cap = cap;
     return QMG_OK;
 }
 
@@ -301,11 +375,15 @@ qmg_status setup_level(qmg_mg_s* mg, int l, const void* starts, int setup_iters)
     return st;
 }
 
+// b, x: nb members of [V][12] complex128; info: nb entries (or NULL)
 template <typename R>
 qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_params* sp, qmg_solve_info* info) {
     Level& L0 = mg->lv[0];
     const int64_t n = L0.n;
-    const size_t vb64 = n * 16;
+    const int nb = mg->nb;
+    const size_t vb64 = n * 16;       // one member
+    const size_t bb64 = nb * vb64;    // the batch
+    const int64_t ld = (int64_t)nb * n;
     const int m = mg->restart;
     const int nl = (int)mg->lv.size();
     for (int i = 0; i < 8; ++i) mg->level_iters[i] = 0;
@@ -314,26 +392,31 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
     auto t0 = std::chrono::steady_clock::now();
     QMG_TRY(mg->blas.norm2<double>(b, n, mg->dsc + S_BN));
     QMG_TRY(read_scalars(mg, S_BN, 1));
-    const double bnorm = std::sqrt(mg->hsc[S_BN]);
-    QMG_HIP(hipMemsetAsync(x, 0, vb64, mg->s));
-    QMG_HIP(hipMemcpyAsync(mg->r64, b, vb64, hipMemcpyDeviceToDevice, mg->s));
-    const double target = sp->tol * bnorm;
+    double bnorm[Blas::kMaxBatch], true_rel[Blas::kMaxBatch];
+    bool conv[Blas::kMaxBatch];
+    bool all_conv = true;
+    for (int k = 0; k < nb; ++k) {
+        bnorm[k] = std::sqrt(hs(mg, k, S_BN));
+        true_rel[k] = bnorm[k] > 0 ? 1.0 : 0.0;
+        conv[k] = bnorm[k] == 0.0;
+        all_conv = all_conv && conv[k];
+    }
+    QMG_HIP(hipMemsetAsync(x, 0, bb64, mg->s));
+    QMG_HIP(hipMemcpyAsync(mg->r64, b, bb64, hipMemcpyDeviceToDevice, mg->s));
     int iters = 0, restarts = 0;
-    double true_rel = bnorm > 0 ? 1.0 : 0.0;
-    bool converged = bnorm == 0.0;
-    while (!converged && iters < sp->maxit) {
+    while (!all_conv && iters < sp->maxit) {
         for (int j = 0; j < m && iters < sp->maxit; ++j) {
-            void* z = (char*)mg->Z64 + j * vb64;
-            void* q = (char*)mg->Q64 + j * vb64;
+            void* z = (char*)mg->Z64 + j * bb64;
+            void* q = (char*)mg->Q64 + j * bb64;
             if (nl > 1) {
                 QMG_TRY(mg->blas.convert<double, R>(mg->r64, L0.kin, n));
                 QMG_TRY(kcycle<R>(mg, 0, L0.kin, L0.kout));
                 QMG_TRY(mg->blas.convert<R, double>(L0.kout, z, n));
             } else {
-                QMG_HIP(hipMemcpyAsync(z, mg->r64, vb64, hipMemcpyDeviceToDevice, mg->s));
+                QMG_HIP(hipMemcpyAsync(z, mg->r64, bb64, hipMemcpyDeviceToDevice, mg->s));
             }
-            QMG_TRY(qmg_wilson_clover_dslash(mg->fine64, z, q, QMG_C128, mg->s));
-            QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, n, j, q, z, n));
+            QMG_TRY(wilson_apply(mg->fine64, z, q, QMG_C128, nb, mg->s));
+            QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, n));
             QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
             QMG_TRY(mg->blas.gcr_update<double>(mg->dsc + S_GCR, q, z, x, mg->r64, n));
             QMG_TRY(mg->blas.norm2<double>(mg->r64, n, mg->dsc + S_NRM));
@@ -343,33 +426,46 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
                 QMG_HIP(hipMemcpyAsync((char*)mg->rec + (size_t)mg->rec_n * vb64, x, vb64, hipMemcpyDeviceToDevice, mg->s));
                 ++mg->rec_n;
             }
-            const double rn = std::sqrt(mg->hsc[S_NRM]);
-            if (!std::isfinite(rn)) return fail(QMG_ERR_NONFINITE, "mg_gcr_solve: non-finite residual at step %d", iters);
-            if (rn <= target || mg->hsc[S_GCR] <= 0.0) break;
+            bool stop = true;
+            for (int k = 0; k < nb; ++k) {
+                const double rn = std::sqrt(hs(mg, k, S_NRM));
+                if (!std::isfinite(rn)) return fail(QMG_ERR_NONFINITE, "mg_gcr_solve: non-finite residual at step %d", iters);
+                stop = stop && (rn <= sp->tol * bnorm[k] || hs(mg, k, S_GCR) <= 0.0);
+            }
+            if (stop) break;
         }
         // reliable update: true residual in FP64
-        QMG_TRY(qmg_wilson_clover_dslash(mg->fine64, x, mg->t64, QMG_C128, mg->s));
+        QMG_TRY(wilson_apply(mg->fine64, x, mg->t64, QMG_C128, nb, mg->s));
         QMG_TRY(mg->blas.xmy<double>(b, mg->t64, mg->r64, n));
         QMG_TRY(mg->blas.norm2<double>(mg->r64, n, mg->dsc + S_NRM));
         QMG_TRY(read_scalars(mg, S_NRM, 1));
-        const double tr = std::sqrt(mg->hsc[S_NRM]);
-        true_rel = tr / bnorm;
-        if (!std::isfinite(tr)) return fail(QMG_ERR_NONFINITE, "mg_gcr_solve: non-finite true residual");
-        if (tr <= target) converged = true;
-        else ++restarts;
+        all_conv = true;
+        for (int k = 0; k < nb; ++k) {
+            const double tr = std::sqrt(hs(mg, k, S_NRM));
+            if (!std::isfinite(tr)) return fail(QMG_ERR_NONFINITE, "mg_gcr_solve: non-finite true residual");
+            true_rel[k] = bnorm[k] > 0 ? tr / bnorm[k] : 0.0;
+            conv[k] = tr <= sp->tol * bnorm[k];
+            all_conv = all_conv && conv[k];
+        }
+        if (!all_conv) ++restarts;
     }
     auto t1 = std::chrono::steady_clock::now();
+    double worst = 0;
+    for (int k = 0; k < nb; ++k) worst = true_rel[k] > worst ? true_rel[k] : worst;
     if (info) {
-        info->outer_iters = iters;
-        for (int l = 0; l < 4; ++l) info->level_iters[l] = l < nl ? mg->level_iters[l] : 0;
-        info->level_iters[0] = iters;
-        info->restarts = restarts;
-        info->true_rel_residual = true_rel;
-        info->seconds = std::chrono::duration<double>(t1 - t0).count();
-        info->converged = converged ? 1 : 0;
-        info->smoother_fallbacks = mg->fallbacks;
+        for (int k = 0; k < nb; ++k) {
+            qmg_solve_info& I = info[k];
+            I.outer_iters = iters;
+            for (int l = 0; l < 4; ++l) I.level_iters[l] = l < nl ? mg->level_iters[l] : 0;
+            I.level_iters[0] = iters;
+            I.restarts = restarts;
+            I.true_rel_residual = true_rel[k];
+            I.seconds = std::chrono::duration<double>(t1 - t0).count();
+            I.converged = conv[k] ? 1 : 0;
+            I.smoother_fallbacks = mg->fallbacks;
+        }
     }
-    if (!converged) return fail(QMG_ERR_NOCONV, "mg_gcr_solve: %d steps, relative residual %.3e", iters, true_rel);
+    if (!all_conv) return fail(QMG_ERR_NOCONV, "mg_gcr_solve: %d steps, relative residual %.3e", iters, worst);
     return QMG_OK;
 }
 
@@ -384,6 +480,7 @@ extern "C" void qmg_mg_destroy(qmg_mg mg) {
     if (mg->fine64) qmg_fine_op_destroy(mg->fine64);
     if (mg->fine_in && mg->fine_in != mg->fine64) qmg_fine_op_destroy(mg->fine_in);
     for (void* p : mg->allocs) (void)hipFree(p);
+    for (void* p : mg->sallocs) (void)hipFree(p);
     if (mg->hsc) (void)hipHostFree(mg->hsc);
     mg->blas.release();
     delete mg;
@@ -391,7 +488,8 @@ extern "C" void qmg_mg_destroy(qmg_mg mg) {
 
 extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double m0, double csw,
                                     int antiperiodic_t, int nlevels, const qmg_level_params* lp,
-                                    const void* const* starts, qmg_prec inner, void* stream, qmg_mg* out) {
+                                    const void* const* starts, qmg_prec inner, qmg_prec fine_storage,
+                                    void* stream, qmg_mg* out) {
     if (!out) return fail(QMG_ERR_ARG, "mg_create: out is NULL");
     *out = nullptr;
     QMG_TRY(check_dims(dims, 2, "mg_create"));
@@ -399,20 +497,31 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
     if (nlevels < 1 || nlevels > 4) return fail(QMG_ERR_ARG, "mg_create: nlevels %d outside [1,4]", nlevels);
     if (nlevels > 1 && (!lp || !starts)) return fail(QMG_ERR_ARG, "mg_create: level params / starts missing");
     if (inner != QMG_C128 && inner != QMG_C64) return fail(QMG_ERR_PREC, "mg_create: inner precision %d", (int)inner);
+    const bool fine16 = fine_storage == QMG_H16 || fine_storage == QMG_B16;
+    if (fine_storage != 0 && fine_storage != inner && !fine16)
+        return fail(QMG_ERR_PREC, "mg_create: fine storage %d", (int)fine_storage);
+    if (fine16 && inner != QMG_C64)
+        return fail(QMG_ERR_PREC, "mg_create: 16-bit fine storage needs complex64 inner precision");
     for (int l = 0; l + 1 < nlevels; ++l) {
         if (!starts[l]) return fail(QMG_ERR_ARG, "mg_create: starts[%d] is NULL", l);
         if (lp[l].nvec < 1 || lp[l].nvec > 64) return fail(QMG_ERR_ARG, "mg_create: nvec %d", lp[l].nvec);
         if (lp[l].smoother_steps < 0 || lp[l].coarse_maxit < 1 || lp[l].setup_iters < 0)
             return fail(QMG_ERR_ARG, "mg_create: bad level %d parameters", l);
+        const int cs = lp[l].coarse_storage;
+        if (cs != 0 && cs != QMG_H16 && cs != QMG_B16)
+            return fail(QMG_ERR_PREC, "mg_create: coarse_storage %d of level %d", cs, l);
+        if (cs != 0 && (inner != QMG_C64 || (2 * lp[l].nvec) % 4))
+            return fail(QMG_ERR_PREC, "mg_create: 16-bit coarse storage needs complex64 inner precision and N %% 4 == 0");
     }
     auto* mg = new qmg_mg_s();
     mg->s = as_stream(stream);
     mg->inner = inner;
     mg->blas.s = mg->s;
     qmg_status st = mg->blas.init();
-    if (st == QMG_OK && hipHostMalloc((void**)&mg->hsc, sizeof(double) * kScal) != hipSuccess)
+    if (st == QMG_OK && hipHostMalloc((void**)&mg->hsc, sizeof(double) * kScal * Blas::kMaxBatch) != hipSuccess)
         st = fail(QMG_ERR_NOMEM, "mg_create: pinned scalars");
-    if (st == QMG_OK) st = alloc(mg, (void**)&mg->dsc, sizeof(double) * kScal);
+    if (st == QMG_OK) st = alloc(mg, (void**)&mg->dsc, sizeof(double) * kScal * Blas::kMaxBatch);
+    mg->blas.ss = kScal;
     if (st == QMG_OK) st = qmg_fine_op_create(dims, gauge, m0, csw, antiperiodic_t, QMG_C128, stream, &mg->fine64);
     if (st == QMG_OK) {
         if (inner == QMG_C128) mg->fine_in = mg->fine64;
@@ -440,16 +549,47 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
             }
             dof = 2 * L.p.nvec;
         }
-        if (st == QMG_OK) st = inner == QMG_C128 ? level_buffers<double>(mg, l) : level_buffers<float>(mg, l);
     }
-    const size_t vb64 = mg->lv[0].n * 16;
-    if (st == QMG_OK) st = alloc(mg, &mg->Q64, vb64 * mg->restart);
-    if (st == QMG_OK) st = alloc(mg, &mg->Z64, vb64 * mg->restart);
-    if (st == QMG_OK) st = alloc(mg, &mg->r64, vb64);
-    if (st == QMG_OK) st = alloc(mg, &mg->t64, vb64);
+    if (st == QMG_OK) st = workspace(mg, 1);
     for (int l = 0; l + 1 < nlevels && st == QMG_OK; ++l)
         st = inner == QMG_C128 ? setup_level<double>(mg, l, starts[l], lp[l].setup_iters)
                                : setup_level<float>(mg, l, starts[l], lp[l].setup_iters);
+    // 16-bit storage of coarse operators for the solve: every level was built
+    // from the full-precision parent above; now convert the flagged ones
+    for (int l = 0; l + 1 < nlevels && st == QMG_OK; ++l) {
+        const int cs = lp[l].coarse_storage;
+        if (cs == 0) continue;
+        Level& C = mg->lv[l + 1];
+        const size_t blk = (size_t)C.V * C.dof * C.dof * 16;
+        void *X = nullptr, *Y = nullptr;
+        hipError_t e = hipMalloc(&X, blk);
+        if (e == hipSuccess) e = hipMalloc(&Y, 8 * blk);
+        qmg_coarse_op op16 = nullptr;
+        if (e != hipSuccess) st = fail(QMG_ERR_NOMEM, "mg_create: 16-bit conversion: %s", hipGetErrorString(e));
+        if (st == QMG_OK) st = qmg_coarse_op_export(C.op, X, Y, mg->s);
+        if (st == QMG_OK) st = qmg_coarse_op_create(C.dims, C.dof, X, Y, (qmg_prec)cs, mg->s, &op16);
+        (void)hipStreamSynchronize(mg->s);
+        if (X) (void)hipFree(X);
+        if (Y) (void)hipFree(Y);
+        if (st == QMG_OK) {
+            qmg_coarse_op_destroy(C.op);
+            C.op = op16;
+        }
+    }
+    if (st == QMG_OK && fine16) {
+        qmg_fine_op f16 = nullptr;
+        st = qmg_fine_op_create(dims, gauge, m0, csw, antiperiodic_t, fine_storage, stream, &f16);
+        if (st == QMG_OK) {
+            qmg_fine_op_destroy(mg->fine_in);
+            mg->fine_in = f16;
+        }
+    }
+    // autotune every coarse operator's stencil on the level's own buffers
+    for (int l = 1; l < nlevels && st == QMG_OK; ++l) {
+        Level& L = mg->lv[l];
+        const qmg_prec vp = inner == QMG_C128 ? QMG_C128 : QMG_C64;
+        st = qmg_coarse_op_tune(L.op, L.x, nullptr, L.t, nullptr, vp, 0, mg->s, nullptr);
+    }
     if (st != QMG_OK) {
         qmg_mg_destroy(mg);
         return st;
@@ -458,18 +598,44 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
     return QMG_OK;
 }
 
-extern "C" qmg_status qmg_mg_gcr_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
-                                       qmg_solve_info* info, void* stream) {
-    if (!mg || !b || !x || !p) return fail(QMG_ERR_ARG, "mg_gcr_solve: NULL argument");
-    if (b == x) return fail(QMG_ERR_ARG, "mg_gcr_solve: b and x alias");
-    if (!(p->tol > 0) || p->maxit < 1) return fail(QMG_ERR_ARG, "mg_gcr_solve: tol/maxit invalid");
+static qmg_status check_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p, const char* what) {
+    if (!mg || !b || !x || !p) return fail(QMG_ERR_ARG, "%s: NULL argument", what);
+    if (b == x) return fail(QMG_ERR_ARG, "%s: b and x alias", what);
+    if (!(p->tol > 0) || p->maxit < 1) return fail(QMG_ERR_ARG, "%s: tol/maxit invalid", what);
     if (p->restart != 0 && p->restart != mg->restart)
-        return fail(QMG_ERR_ARG, "mg_gcr_solve: restart must be 0 or %d", mg->restart);
+        return fail(QMG_ERR_ARG, "%s: restart must be 0 or %d", what, mg->restart);
+    return QMG_OK;
+}
+
+static qmg_status run_solve(qmg_mg mg, const void* b, void* x, int nrhs, const qmg_solve_params* p,
+                            qmg_solve_info* info, void* stream) {
     mg->s = as_stream(stream);
     mg->blas.s = mg->s;
-    if (info) *info = qmg_solve_info{};
-    if (mg->inner == QMG_C128) return solve_impl<double>(mg, b, x, p, info);
-    return solve_impl<float>(mg, b, x, p, info);
+    if (info)
+        for (int k = 0; k < nrhs; ++k) info[k] = qmg_solve_info{};
+    if (nrhs > mg->cap) QMG_TRY(workspace(mg, nrhs));
+    mg->nb = nrhs;
+    mg->blas.nb = nrhs;
+    const qmg_status st = mg->inner == QMG_C128 ? solve_impl<double>(mg, b, x, p, info)
+                                                : solve_impl<float>(mg, b, x, p, info);
+    mg->nb = 1;
+    mg->blas.nb = 1;
+    return st;
+}
+
+extern "C" qmg_status qmg_mg_gcr_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
+                                       qmg_solve_info* info, void* stream) {
+    QMG_TRY(check_solve(mg, b, x, p, "mg_gcr_solve"));
+    return run_solve(mg, b, x, 1, p, info, stream);
+}
+
+extern "C" qmg_status qmg_mg_gcr_solve_multi(qmg_mg mg, const void* b, void* x, int nrhs, const qmg_solve_params* p,
+                                             qmg_solve_info* info, void* stream) {
+    QMG_TRY(check_solve(mg, b, x, p, "mg_gcr_solve_multi"));
+    if (nrhs < 1 || nrhs > Blas::kMaxBatch)
+        return fail(QMG_ERR_ARG, "mg_gcr_solve_multi: nrhs %d outside [1, %d]", nrhs, Blas::kMaxBatch);
+    if (mg->rec) return fail(QMG_ERR_STATE, "mg_gcr_solve_multi: recording is for single solves");
+    return run_solve(mg, b, x, nrhs, p, info, stream);
 }
 
 extern "C" qmg_status qmg_mg_level(qmg_mg mg, int level, int dims[4], int* dof, qmg_coarse_op* op,

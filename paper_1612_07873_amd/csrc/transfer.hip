@@ -129,9 +129,11 @@ __global__ void k_to_c64(float2* __restrict__ o, const double2* __restrict__ i, 
 template <typename R, int CPC>
 __global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
                                                  const cpx<R>* __restrict__ uc, const int* __restrict__ owner,
-                                                 int64_t V, int dof, int nvec, int rows_per_wg) {
+                                                 int64_t V, int dof, int nvec, int rows_per_wg, int64_t cstride) {
     constexpr int cpc = CPC;                       // complex per chunk
     __shared__ cpx<R> part[256];
+    out += (int64_t)blockIdx.y * V * dof;          // batch member
+    uc += (int64_t)blockIdx.y * cstride;
     const int cpr = nvec / cpc;                    // chunks per row
     const int t = threadIdx.x;
     const int lr = t / cpr, kc = t - (t / cpr) * cpr;
@@ -166,9 +168,11 @@ __global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const
 template <typename R, int CPC>
 __global__ __launch_bounds__(1024) void k_restrict(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
                                                    const cpx<R>* __restrict__ in, const int* __restrict__ members,
-                                                   int dof, int nvec, int bsites) {
+                                                   int dof, int nvec, int bsites, int64_t fstride) {
     constexpr int cpc = CPC;
     extern __shared__ __align__(16) unsigned char smem[];
+    in += (int64_t)blockIdx.y * fstride;           // batch member
+    out += (int64_t)blockIdx.y * gridDim.x * 2 * nvec;
     cpx<R>* acc_l = reinterpret_cast<cpx<R>*>(smem);   // [dof][nvec]
     const int64_t xc = blockIdx.x;
     const int cpr = nvec / cpc;
@@ -350,41 +354,41 @@ extern "C" qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* str
 
 namespace qmg {
 template <typename R, int CPC>
-static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void* out, hipStream_t s) {
+static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void* out, int nb, hipStream_t s) {
     const int cpr = t->nvec / CPC;
     const int rows_per_wg = 256 / cpr;
     const int64_t rows = t->V * t->dof;
-    const unsigned nb = (unsigned)((rows + rows_per_wg - 1) / rows_per_wg);
-    hipLaunchKernelGGL((k_prolong<R, CPC>), dim3(nb), dim3(256), 0, s, (cpx<R>*)out, (const cpx<R>*)B,
-                       (const cpx<R>*)in, t->owner, t->V, t->dof, t->nvec, rows_per_wg);
+    const unsigned nblk = (unsigned)((rows + rows_per_wg - 1) / rows_per_wg);
+    hipLaunchKernelGGL((k_prolong<R, CPC>), dim3(nblk, nb), dim3(256), 0, s, (cpx<R>*)out, (const cpx<R>*)B,
+                       (const cpx<R>*)in, t->owner, t->V, t->dof, t->nvec, rows_per_wg, t->Vc * 2 * t->nvec);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
 template <typename R, int CPC>
-static qmg_status restrict_t(qmg_transfer t, const void* B, const void* in, void* out, hipStream_t s) {
+static qmg_status restrict_t(qmg_transfer t, const void* B, const void* in, void* out, int nb, hipStream_t s) {
     const int nchunk = t->dof * (t->nvec / CPC);
     int threads = ((nchunk + 63) / 64) * 64;
     if (threads > 1024) threads = 1024;
     const size_t lds = sizeof(cpx<R>) * t->dof * t->nvec;
     if (lds > 65536)
         QMG_HIP(hipFuncSetAttribute((const void*)k_restrict<R, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_restrict<R, CPC>), dim3((unsigned)t->Vc), dim3(threads), lds, s, (cpx<R>*)out,
-                       (const cpx<R>*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites);
+    hipLaunchKernelGGL((k_restrict<R, CPC>), dim3((unsigned)t->Vc, nb), dim3(threads), lds, s, (cpx<R>*)out,
+                       (const cpx<R>*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites, t->V * t->dof);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
-qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
-    if (p == QMG_C128) return prolong_t<double, 1>(t, t->basis64, in, out, s);
-    if (t->nvec % 2) return prolong_t<float, 1>(t, t->basis, in, out, s);
-    return prolong_t<float, 2>(t, t->basis, in, out, s);
+qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, int nb, hipStream_t s) {
+    if (p == QMG_C128) return prolong_t<double, 1>(t, t->basis64, in, out, nb, s);
+    if (t->nvec % 2) return prolong_t<float, 1>(t, t->basis, in, out, nb, s);
+    return prolong_t<float, 2>(t, t->basis, in, out, nb, s);
 }
 
-qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, hipStream_t s) {
-    if (p == QMG_C128) return restrict_t<double, 1>(t, t->basis64, in, out, s);
-    if (t->nvec % 2) return restrict_t<float, 1>(t, t->basis, in, out, s);
-    return restrict_t<float, 2>(t, t->basis, in, out, s);
+qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, int nb, hipStream_t s) {
+    if (p == QMG_C128) return restrict_t<double, 1>(t, t->basis64, in, out, nb, s);
+    if (t->nvec % 2) return restrict_t<float, 1>(t, t->basis, in, out, nb, s);
+    return restrict_t<float, 2>(t, t->basis, in, out, nb, s);
 }
 }  // namespace qmg
 
@@ -398,11 +402,11 @@ static qmg_status check_transfer_prec(qmg_transfer t, qmg_prec p, const char* wh
 extern "C" qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, qmg_prec p, void* stream) {
     if (!t || !coarse_in || !fine_out) return fail(QMG_ERR_ARG, "prolong: NULL argument");
     QMG_TRY(check_transfer_prec(t, p, "prolong"));
-    return transfer_prolong(t, coarse_in, fine_out, p, as_stream(stream));
+    return transfer_prolong(t, coarse_in, fine_out, p, 1, as_stream(stream));
 }
 
 extern "C" qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, qmg_prec p, void* stream) {
     if (!t || !fine_in || !coarse_out) return fail(QMG_ERR_ARG, "restrict: NULL argument");
     QMG_TRY(check_transfer_prec(t, p, "restrict"));
-    return transfer_restrict(t, fine_in, coarse_out, p, as_stream(stream));
+    return transfer_restrict(t, fine_in, coarse_out, p, 1, as_stream(stream));
 }

@@ -20,9 +20,10 @@
 
 namespace qmg {
 qmg_status coarse_dslash_launch(const qmg_coarse_op_s* op, int rows, int split, int pre, const void* in,
-                                const float* in_scale, void* out, float* out_scale, qmg_prec vprec, hipStream_t s);
+                                const float* in_scale, void* out, float* out_scale, qmg_prec vprec, hipStream_t s,
+                                int m);
 qmg_status coarse_mrhs(qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int nrhs, int rpw,
-                       hipStream_t s);
+                       hipStream_t s, int64_t ors);
 }  // namespace qmg
 
 using namespace qmg;
@@ -113,7 +114,7 @@ extern "C" qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const
             for (int pre : {4, 8, 16}) {
                 if (pre > J / split && pre != 4) continue;
                 float ms = 0;
-                QMG_TRY(tm.time([&]() { return coarse_dslash_launch(op, rows, split, pre, in, in_scale, out, out_scale, vprec, s); },
+                QMG_TRY(tm.time([&]() { return coarse_dslash_launch(op, rows, split, pre, in, in_scale, out, out_scale, vprec, s, 1); },
                                 cold ? 3 : 5, &ms));
                 all.push_back(Best{rows, split, pre, ms});
             }
@@ -166,7 +167,7 @@ extern "C" qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, 
     const int maxr = nrhs >= 64 ? 4 : nrhs >= 32 ? 2 : 1;
     for (int r = 1; r <= maxr; r *= 2) {
         float ms = 0;
-        QMG_TRY(tm.time([&]() { return coarse_mrhs(op, in, in_scale, out, nrhs, r, s); }, cold ? 3 : 5, &ms));
+        QMG_TRY(tm.time([&]() { return coarse_mrhs(op, in, in_scale, out, nrhs, r, s, 0); }, cold ? 3 : 5, &ms));
         if (ms < 0.97f * best.ms) best = Best{r, 0, 0, ms};   // a larger tile must win by 3%
     }
     op->rpw[lg] = best.a;

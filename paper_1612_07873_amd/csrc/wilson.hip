@@ -18,6 +18,15 @@
 // forward hop out of that slice and the backward hop into it); clover SoA
 // [2][36][V] reals (6 diagonal reals, then the 15 upper off-diagonal complex
 // entries row by row); spinors [V][4][3] complex (the canonical layout).
+//
+// 16-bit storage (FP16 or BF16 pairs, FP32 arithmetic): the links as one pair
+// per complex entry, [4][9][V] words, with no scale (SU(3) entries are
+// bounded by 1 in magnitude); the clover term as [2][18][V] words (pair q of
+// a chirality block holds its reals 2q and 2q+1 of the layout above) with one
+// FP32 scale per (chirality, site), value = scale * stored.  Vectors are then
+// either complex64 or 16-bit pairs [V][12] words with one FP32 scale per site
+// (the largest |re| or |im| of its 12 components).
+#include "codes16.h"
 #include "handles.h"
 
 #include <vector>
@@ -60,18 +69,71 @@ __device__ __forceinline__ void gdmul(cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q
     else { o0 = p; o1 = q; }
 }
 
-template <typename R>
-__device__ __forceinline__ void load_link(cpx<R> u[9], const cpx<R>* __restrict__ U, int mu, int64_t site,
+template <int LF> struct FineT { using R = float; };
+template <> struct FineT<FMT_F64> { using R = double; };
+template <int F> constexpr bool is16f() { return F == FMT_H16 || F == FMT_B16; }
+
+template <int LF, typename R>
+__device__ __forceinline__ void load_link(cpx<R> u[9], const void* __restrict__ U, int mu, int64_t site,
                                           int64_t V) {
+    if constexpr (is16f<LF>()) {
+        const uint32_t* W = static_cast<const uint32_t*>(U);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) u[e] = U[((int64_t)mu * 9 + e) * V + site];
+        for (int e = 0; e < 9; ++e) u[e] = dec_pair<LF>(W[((int64_t)mu * 9 + e) * V + site]);
+    } else {
+        const cpx<R>* P = static_cast<const cpx<R>*>(U);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = P[((int64_t)mu * 9 + e) * V + site];
+    }
 }
 
-// A site's 12 spinor components, with 16-byte loads (6 in FP32, 12 in FP64).
-template <typename R>
-__device__ __forceinline__ void load_spinor(cpx<R> p[12], const cpx<R>* __restrict__ src) {
-    if constexpr (sizeof(R) == 4) {
-        const float4* s4 = reinterpret_cast<const float4*>(src);
+// One chirality block of the clover term: 6 diagonal reals, 15 upper entries.
+template <int LF, typename R>
+__device__ __forceinline__ void load_clover(R d[6], cpx<R> o[15], const void* __restrict__ clov,
+                                            const float* __restrict__ cscale, int chi, int64_t site, int64_t V) {
+    if constexpr (is16f<LF>()) {
+        const uint32_t* W = static_cast<const uint32_t*>(clov) + (int64_t)chi * 18 * V + site;
+        const float k = cscale[(int64_t)chi * V + site];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            const cpx<float> v = dec_pair<LF>(W[q * V]);
+            d[2 * q] = k * v.re;
+            d[2 * q + 1] = k * v.im;
+        }
+#pragma unroll
+        for (int q = 0; q < 15; ++q) {
+            const cpx<float> v = dec_pair<LF>(W[(3 + q) * V]);
+            o[q] = {k * v.re, k * v.im};
+        }
+    } else {
+        const R* A = static_cast<const R*>(clov) + (int64_t)chi * 36 * V + site;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) d[i] = A[i * V];
+#pragma unroll
+        for (int q = 0; q < 15; ++q) o[q] = {A[(6 + 2 * q) * V], A[(7 + 2 * q) * V]};
+    }
+}
+
+// A site's 12 spinor components, with 16-byte loads (3 for 16-bit pairs, 6 in
+// FP32, 12 in FP64).
+template <int VF, typename R>
+__device__ __forceinline__ void load_spinor(cpx<R> p[12], const void* __restrict__ src,
+                                            const float* __restrict__ scale, int64_t site) {
+    if constexpr (is16f<VF>()) {
+        const uint4* s4 = static_cast<const uint4*>(src) + site * 3;
+        const float k = scale[site];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const uint4 w = s4[i];
+            const uint32_t q[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const cpx<float> v = dec_pair<VF>(q[j]);
+                p[4 * i + j] = cpx<R>{k * v.re, k * v.im};
+            }
+        }
+    } else if constexpr (VF == FMT_F32) {
+        const float4* s4 = static_cast<const float4*>(src) + site * 6;
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             const float4 v = s4[i];
@@ -79,29 +141,47 @@ __device__ __forceinline__ void load_spinor(cpx<R> p[12], const cpx<R>* __restri
             p[2 * i + 1] = cpx<R>{v.z, v.w};
         }
     } else {
+        const cpx<R>* s = static_cast<const cpx<R>*>(src) + site * 12;
 #pragma unroll
-        for (int f = 0; f < 12; ++f) p[f] = src[f];
+        for (int f = 0; f < 12; ++f) p[f] = s[f];
     }
 }
 
-template <typename R>
-__device__ __forceinline__ void store_spinor(cpx<R>* __restrict__ dst, const cpx<R> p[12]) {
-    if constexpr (sizeof(R) == 4) {
-        float4* d4 = reinterpret_cast<float4*>(dst);
+template <int VF, typename R>
+__device__ __forceinline__ void store_spinor(void* __restrict__ dst, float* __restrict__ scale, int64_t site,
+                                             const cpx<R> p[12]) {
+    if constexpr (is16f<VF>()) {
+        float m = 0.0f;
+#pragma unroll
+        for (int f = 0; f < 12; ++f) m = fmaxf(m, fmaxf(fabsf(p[f].re), fabsf(p[f].im)));
+        const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+        uint4* d4 = static_cast<uint4*>(dst) + site * 3;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            uint32_t q[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) q[j] = enc_pair<VF>(p[4 * i + j].re * inv, p[4 * i + j].im * inv);
+            d4[i] = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+        scale[site] = m;
+    } else if constexpr (VF == FMT_F32) {
+        float4* d4 = static_cast<float4*>(dst) + site * 6;
 #pragma unroll
         for (int i = 0; i < 6; ++i) d4[i] = make_float4(p[2 * i].re, p[2 * i].im, p[2 * i + 1].re, p[2 * i + 1].im);
     } else {
+        cpx<R>* d = static_cast<cpx<R>*>(dst) + site * 12;
 #pragma unroll
-        for (int f = 0; f < 12; ++f) dst[f] = p[f];
+        for (int f = 0; f < 12; ++f) d[f] = p[f];
     }
 }
 
 // One hop in direction MU; BACK selects the backward hop.  acc += -1/2 * P (x) W psi(n).
-template <int MU, bool BACK, typename R>
-__device__ __forceinline__ void hop(cpx<R> acc[12], const cpx<R>* __restrict__ in,
-                                    const cpx<R>* __restrict__ U, int64_t V, int64_t site, int64_t n) {
+// vo: offset (in sites) of the batch member's vectors
+template <int MU, bool BACK, int LF, int VF, typename R>
+__device__ __forceinline__ void hop(cpx<R> acc[12], const void* __restrict__ in, const float* __restrict__ in_scale,
+                                    const void* __restrict__ U, int64_t V, int64_t site, int64_t n, int64_t vo) {
     cpx<R> p[12];
-    load_spinor(p, in + n * 12);
+    load_spinor<VF>(p, in, in_scale, n + vo);
     cpx<R> a[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -111,7 +191,7 @@ __device__ __forceinline__ void hop(cpx<R> acc[12], const cpx<R>* __restrict__ i
         else { a[0][c] = cadd(p[c], g0); a[1][c] = cadd(p[3 + c], g1); }
     }
     cpx<R> u[9];
-    load_link(u, U, MU, BACK ? n : site, V);
+    load_link<LF>(u, U, MU, BACK ? n : site, V);
     cpx<R> w[2][3];
 #pragma unroll
     for (int s = 0; s < 2; ++s)
@@ -138,30 +218,32 @@ __device__ __forceinline__ void hop(cpx<R> acc[12], const cpx<R>* __restrict__ i
     }
 }
 
-template <typename R>
-__global__ __launch_bounds__(256) void k_wilson_clover(const cpx<R>* __restrict__ U,
-                                                       const R* __restrict__ clov,
-                                                       const int* __restrict__ nbr,
-                                                       const cpx<R>* __restrict__ in,
-                                                       cpx<R>* __restrict__ out, int64_t V, R diag,
-                                                       int use_clover) {
+// LF: storage of links and clover; VF: storage of the vectors (the same as LF
+// for complex128 / complex64, complex64 or 16-bit pairs for 16-bit links).
+// Grid dimension y runs over batch members: member b's fields follow the
+// first at b*V sites.
+template <int LF, int VF>
+__global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ U, const void* __restrict__ clov,
+                                                       const float* __restrict__ cscale,
+                                                       const int* __restrict__ nbr, const void* __restrict__ in,
+                                                       const float* __restrict__ in_scale, void* __restrict__ out,
+                                                       float* __restrict__ out_scale, int64_t V,
+                                                       typename FineT<LF>::R diag, int use_clover) {
+    using R = typename FineT<LF>::R;
     const int64_t site = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (site >= V) return;
+    const int64_t vo = (int64_t)blockIdx.y * V;
     cpx<R> acc[12];
     cpx<R> p[12];
-    load_spinor(p, in + site * 12);
+    load_spinor<VF>(p, in, in_scale, site + vo);
 #pragma unroll
     for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
     if (use_clover) {
 #pragma unroll
         for (int chi = 0; chi < 2; ++chi) {
-            const R* A = clov + (int64_t)chi * 36 * V + site;
             R d[6];
             cpx<R> o[15];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) d[i] = A[i * V];
-#pragma unroll
-            for (int k = 0; k < 15; ++k) o[k] = {A[(6 + 2 * k) * V], A[(7 + 2 * k) * V]};
+            load_clover<LF>(d, o, clov, cscale, chi, site, V);
             const cpx<R>* x = p + 6 * chi;
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
@@ -179,15 +261,15 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const cpx<R>* __restrict_
         }
     }
     const int* nb = nbr + site * 8;
-    hop<0, false>(acc, in, U, V, site, nb[0]);
-    hop<0, true>(acc, in, U, V, site, nb[1]);
-    hop<1, false>(acc, in, U, V, site, nb[2]);
-    hop<1, true>(acc, in, U, V, site, nb[3]);
-    hop<2, false>(acc, in, U, V, site, nb[4]);
-    hop<2, true>(acc, in, U, V, site, nb[5]);
-    hop<3, false>(acc, in, U, V, site, nb[6]);
-    hop<3, true>(acc, in, U, V, site, nb[7]);
-    store_spinor(out + site * 12, acc);
+    hop<0, false, LF, VF>(acc, in, in_scale, U, V, site, nb[0], vo);
+    hop<0, true, LF, VF>(acc, in, in_scale, U, V, site, nb[1], vo);
+    hop<1, false, LF, VF>(acc, in, in_scale, U, V, site, nb[2], vo);
+    hop<1, true, LF, VF>(acc, in, in_scale, U, V, site, nb[3], vo);
+    hop<2, false, LF, VF>(acc, in, in_scale, U, V, site, nb[4], vo);
+    hop<2, true, LF, VF>(acc, in, in_scale, U, V, site, nb[5], vo);
+    hop<3, false, LF, VF>(acc, in, in_scale, U, V, site, nb[6], vo);
+    hop<3, true, LF, VF>(acc, in, in_scale, U, V, site, nb[7], vo);
+    store_spinor<VF>(out, out_scale, site + vo, acc);
 }
 
 // ------------------------------------------------------------ clover build
@@ -292,23 +374,57 @@ __global__ void k_clover_build(R* __restrict__ clov, const double2* __restrict__
     }
 }
 
-template <typename R>
-__global__ void k_clover_export(double2* __restrict__ out, const R* __restrict__ clov, int64_t V) {
+template <int LF>
+__global__ void k_clover_export(double2* __restrict__ out, const void* __restrict__ clov,
+                                const float* __restrict__ cscale, int64_t V) {
+    using R = typename FineT<LF>::R;
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= V) return;
     double2* o = out + x * 144;
     for (int e = 0; e < 144; ++e) o[e] = make_double2(0, 0);
     for (int chi = 0; chi < 2; ++chi) {
-        const R* A = clov + (int64_t)chi * 36 * V + x;
-        for (int i = 0; i < 6; ++i) o[(6 * chi + i) * 12 + 6 * chi + i] = make_double2(A[i * V], 0);
+        R d[6];
+        cpx<R> u[15];
+        load_clover<LF>(d, u, clov, cscale, chi, x, V);
+        for (int i = 0; i < 6; ++i) o[(6 * chi + i) * 12 + 6 * chi + i] = make_double2(d[i], 0);
         int k = 0;
         for (int r = 0; r < 6; ++r)
             for (int c = r + 1; c < 6; ++c, ++k) {
-                const double re = A[(6 + 2 * k) * V], im = A[(7 + 2 * k) * V];
-                o[(6 * chi + r) * 12 + 6 * chi + c] = make_double2(re, im);
-                o[(6 * chi + c) * 12 + 6 * chi + r] = make_double2(re, -im);
+                o[(6 * chi + r) * 12 + 6 * chi + c] = make_double2(u[k].re, u[k].im);
+                o[(6 * chi + c) * 12 + 6 * chi + r] = make_double2(u[k].re, -u[k].im);
             }
     }
+}
+
+// FP64 clover [2][36][V] -> 16-bit pairs [2][18][V] with one scale per (chirality, site).
+template <int LF>
+__global__ void k_clover_pack16(uint32_t* __restrict__ W, float* __restrict__ cscale,
+                                const double* __restrict__ clov, int64_t V) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= V) return;
+    for (int chi = 0; chi < 2; ++chi) {
+        const double* A = clov + (int64_t)chi * 36 * V + x;
+        float m = 0.0f;
+        for (int i = 0; i < 36; ++i) m = fmaxf(m, fabsf((float)A[i * V]));
+        const float inv = m > 0.0f ? 1.0f / m : 0.0f;
+        for (int q = 0; q < 18; ++q)
+            W[((int64_t)chi * 18 + q) * V + x] = enc_pair<LF>((float)A[2 * q * V] * inv, (float)A[(2 * q + 1) * V] * inv);
+        cscale[(int64_t)chi * V + x] = m;
+    }
+}
+
+// Canonical gauge -> 16-bit pairs [4][9][V], time sign folded.
+template <int LF>
+__global__ void k_pack_gauge16(uint32_t* __restrict__ U, const double2* __restrict__ G, int64_t V,
+                               int64_t last_slice_start, int anti) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 4 * 9 * V) return;
+    const int64_t site = g % V;
+    const int e = (int)((g / V) % 9);
+    const int mu = (int)(g / (9 * V));
+    const double2 v = G[((int64_t)mu * V + site) * 9 + e];
+    const double sgn = (anti && mu == 3 && site >= last_slice_start) ? -1.0 : 1.0;
+    U[g] = enc_pair<LF>((float)(sgn * v.x), (float)(sgn * v.y));
 }
 
 // Canonical gauge [4][V][3][3] complex128 -> SoA [4][9][V] in R, time sign folded.
@@ -361,17 +477,43 @@ static SigmaBlocks sigma_blocks(double csw) {
     return sb;
 }
 
-template <typename R>
-static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, void* out, hipStream_t s) {
+template <int LF, int VF>
+static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const float* in_scale, void* out,
+                                float* out_scale, int members, hipStream_t s) {
+    using R = typename FineT<LF>::R;
     const unsigned nb = (unsigned)((op->V + 255) / 256);
-    hipLaunchKernelGGL(k_wilson_clover<R>, dim3(nb), dim3(256), 0, s, (const cpx<R>*)op->U,
-                       (const R*)op->clov, op->nbr, (const cpx<R>*)in, (cpx<R>*)out, op->V,
-                       (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0);
+    hipLaunchKernelGGL((k_wilson_clover<LF, VF>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale, op->nbr,
+                       in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
-static size_t real_bytes(qmg_prec p) { return p == QMG_C128 ? 8 : 4; }
+// vprec: the vector storage (checked by the callers against the operator's)
+static qmg_status wilson_any(const qmg_fine_op_s* op, const void* in, const float* in_scale, void* out,
+                             float* out_scale, qmg_prec vprec, int m, hipStream_t s) {
+    switch (op->storage) {
+        case QMG_C128: return launch_wilson<FMT_F64, FMT_F64>(op, in, nullptr, out, nullptr, m, s);
+        case QMG_C64: return launch_wilson<FMT_F32, FMT_F32>(op, in, nullptr, out, nullptr, m, s);
+        case QMG_H16:
+            if (vprec == QMG_C64) return launch_wilson<FMT_H16, FMT_F32>(op, in, nullptr, out, nullptr, m, s);
+            if (vprec == QMG_H16) return launch_wilson<FMT_H16, FMT_H16>(op, in, in_scale, out, out_scale, m, s);
+            return launch_wilson<FMT_H16, FMT_B16>(op, in, in_scale, out, out_scale, m, s);
+        default:
+            if (vprec == QMG_C64) return launch_wilson<FMT_B16, FMT_F32>(op, in, nullptr, out, nullptr, m, s);
+            if (vprec == QMG_H16) return launch_wilson<FMT_B16, FMT_H16>(op, in, in_scale, out, out_scale, m, s);
+            return launch_wilson<FMT_B16, FMT_B16>(op, in, in_scale, out, out_scale, m, s);
+    }
+}
+
+// Solver-side entry: `members` fields of V sites one after another (vectors
+// in complex128 / complex64 as `vprec`, checked by the caller).
+qmg_status wilson_apply(const qmg_fine_op_s* op, const void* in, void* out, qmg_prec vprec, int members,
+                        hipStream_t s) {
+    return wilson_any(op, in, nullptr, out, nullptr, vprec, members, s);
+}
+
+static size_t real_bytes(qmg_prec p) { return p == QMG_C128 ? 8 : p == QMG_C64 ? 4 : 2; }
+static bool is16p(qmg_prec p) { return p == QMG_H16 || p == QMG_B16; }
 
 void gamma_matrix(int mu, double g[4][4][2]) {
     // off-diagonal block g_mu (upper right); the lower-left block is g_mu^+
@@ -399,6 +541,7 @@ extern "C" void qmg_fine_op_destroy(qmg_fine_op op) {
     if (!op) return;
     if (op->U) (void)hipFree(op->U);
     if (op->clov) (void)hipFree(op->clov);
+    if (op->cscale) (void)hipFree(op->cscale);
     if (op->nbr) (void)hipFree(op->nbr);
     delete op;
 }
@@ -410,7 +553,7 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
     *out = nullptr;
     QMG_TRY(check_dims(dims, 2, "fine_op_create"));
     if (!gauge) return fail(QMG_ERR_ARG, "fine_op_create: gauge is NULL");
-    if (storage != QMG_C128 && storage != QMG_C64)
+    if (storage != QMG_C128 && storage != QMG_C64 && !is16p(storage))
         return fail(QMG_ERR_PREC, "fine_op_create: storage %d not supported", (int)storage);
     hipStream_t s = as_stream(stream);
     auto* op = new qmg_fine_op_s();
@@ -423,6 +566,7 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
     const size_t rb = real_bytes(storage);
     hipError_t e = hipMalloc(&op->U, 2 * rb * 36 * op->V);
     if (e == hipSuccess) e = hipMalloc(&op->clov, rb * 72 * op->V);
+    if (e == hipSuccess && is16p(storage)) e = hipMalloc(&op->cscale, sizeof(float) * 2 * op->V);
     if (e != hipSuccess) {
         qmg_fine_op_destroy(op);
         return fail(QMG_ERR_NOMEM, "fine_op_create: %s", hipGetErrorString(e));
@@ -440,11 +584,35 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
                            (const double2*)gauge, op->V, last, op->antiperiodic_t);
         hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)op->clov,
                            (const double2*)gauge, op->nbr, op->V, sb);
-    } else {
+    } else if (storage == QMG_C64) {
         hipLaunchKernelGGL(k_pack_gauge<float>, dim3(nbU), dim3(256), 0, s, (cpx<float>*)op->U,
                            (const double2*)gauge, op->V, last, op->antiperiodic_t);
         hipLaunchKernelGGL(k_clover_build<float>, dim3(nbS), dim3(128), 0, s, (float*)op->clov,
                            (const double2*)gauge, op->nbr, op->V, sb);
+    } else {
+        // the clover term is built in FP64 in a temporary, then scaled per
+        // (chirality, site) and rounded to 16 bits
+        void* c64 = nullptr;
+        e = hipMalloc(&c64, sizeof(double) * 72 * op->V);
+        if (e != hipSuccess) {
+            qmg_fine_op_destroy(op);
+            return fail(QMG_ERR_NOMEM, "fine_op_create: clover temporary: %s", hipGetErrorString(e));
+        }
+        hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)c64,
+                           (const double2*)gauge, op->nbr, op->V, sb);
+        if (storage == QMG_H16) {
+            hipLaunchKernelGGL(k_pack_gauge16<FMT_H16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
+                               (const double2*)gauge, op->V, last, op->antiperiodic_t);
+            hipLaunchKernelGGL(k_clover_pack16<FMT_H16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
+                               op->cscale, (const double*)c64, op->V);
+        } else {
+            hipLaunchKernelGGL(k_pack_gauge16<FMT_B16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
+                               (const double2*)gauge, op->V, last, op->antiperiodic_t);
+            hipLaunchKernelGGL(k_clover_pack16<FMT_B16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
+                               op->cscale, (const double*)c64, op->V);
+        }
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(c64);
     }
     e = hipGetLastError();
     if (e != hipSuccess) {
@@ -459,12 +627,12 @@ extern "C" qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* s
     if (!op || !A) return fail(QMG_ERR_ARG, "fine_op_export_clover: NULL argument");
     hipStream_t s = as_stream(stream);
     const unsigned nb = (unsigned)((op->V + 127) / 128);
-    if (op->storage == QMG_C128)
-        hipLaunchKernelGGL(k_clover_export<double>, dim3(nb), dim3(128), 0, s, (double2*)A,
-                           (const double*)op->clov, op->V);
-    else
-        hipLaunchKernelGGL(k_clover_export<float>, dim3(nb), dim3(128), 0, s, (double2*)A,
-                           (const float*)op->clov, op->V);
+    switch (op->storage) {
+        case QMG_C128: hipLaunchKernelGGL(k_clover_export<FMT_F64>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V); break;
+        case QMG_C64: hipLaunchKernelGGL(k_clover_export<FMT_F32>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V); break;
+        case QMG_H16: hipLaunchKernelGGL(k_clover_export<FMT_H16>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V); break;
+        default: hipLaunchKernelGGL(k_clover_export<FMT_B16>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V);
+    }
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -472,11 +640,21 @@ extern "C" qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* s
 extern "C" qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, qmg_prec prec,
                                                void* stream) {
     if (!op || !in || !out) return fail(QMG_ERR_ARG, "wilson_clover_dslash: NULL argument");
-    if (prec != op->storage)
-        return fail(QMG_ERR_PREC, "wilson_clover_dslash: vector precision %d != operator storage %d",
+    const bool ok = prec == op->storage || (is16p(op->storage) && prec == QMG_C64);
+    if (!ok)
+        return fail(QMG_ERR_PREC, "wilson_clover_dslash: vector precision %d does not fit operator storage %d",
                     (int)prec, (int)op->storage);
+    if (is16p(prec)) return fail(QMG_ERR_PREC, "wilson_clover_dslash: 16-bit vectors go through wilson_clover_dslash_scaled");
     if (in == out) return fail(QMG_ERR_ARG, "wilson_clover_dslash: in and out alias");
-    hipStream_t s = as_stream(stream);
-    if (op->storage == QMG_C128) return launch_wilson<double>(op, in, out, s);
-    return launch_wilson<float>(op, in, out, s);
+    return wilson_any(op, in, nullptr, out, nullptr, prec, 1, as_stream(stream));
+}
+
+extern "C" qmg_status qmg_wilson_clover_dslash_scaled(qmg_fine_op op, const void* in, const float* in_scale,
+                                                      void* out, float* out_scale, qmg_prec prec, void* stream) {
+    if (!op || !in || !in_scale || !out || !out_scale)
+        return fail(QMG_ERR_ARG, "wilson_clover_dslash_scaled: NULL argument");
+    if (!is16p(op->storage) || !is16p(prec))
+        return fail(QMG_ERR_PREC, "wilson_clover_dslash_scaled: needs 16-bit operator storage and vectors");
+    if (in == out || in_scale == out_scale) return fail(QMG_ERR_ARG, "wilson_clover_dslash_scaled: in and out alias");
+    return wilson_any(op, in, in_scale, out, out_scale, prec, 1, as_stream(stream));
 }

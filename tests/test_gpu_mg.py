@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import synth
-from oracle import lattice, mg as omg, solvers, transfer, wilson
+from oracle import coarse, lattice, mg as omg, solvers, transfer, wilson
 from gpu_util import dev, host, rel_err
 
 pytestmark = pytest.mark.gpu
@@ -98,3 +98,94 @@ def test_config2_shape_three_levels_to_1e10():
     tr = np.linalg.norm(r) / np.linalg.norm(b)
     print('config2 shape', info, 'oracle-M residual %.2e' % tr)
     assert info['converged'] and tr <= 1e-10
+
+
+@pytest.mark.parametrize('storage', ['h16', 'b16'])
+def test_three_level_16bit_coarse_storage(storage):
+    """Coarse operators stored as 16-bit links with per-(site, direction)
+    scales inside an FP32 K-cycle; the FP64 outer GCR still reaches 1e-10
+    under the oracle's M, the stored level operators equal the full-precision
+    build to 16-bit rounding, and the iteration count stays close to the
+    FP32-storage solve of the same hierarchy."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U, A, fine = problem(dims, 0.3, 2, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 5)]
+    ref_levels = level_list(blocks, nvecs, 30, [10, 100])
+    mg32 = Multigrid(dims, dev(U), m0, 1.0, ref_levels, st, inner='c64')
+    lv16 = [dict(L, coarse_storage=storage) for L in ref_levels]
+    mg16 = Multigrid(dims, dev(U), m0, 1.0, lv16, st, inner='c64')
+    unit = 2.0 ** -11 if storage == 'h16' else 2.0 ** -8
+    for l in (1, 2):
+        X32, Y32 = (host(a) for a in mg32.level(l)[2].export())
+        X16, Y16 = (host(a) for a in mg16.level(l)[2].export())
+        # per-entry error is bounded by half a unit of the block's largest component
+        for a, b in ((X16, X32), (Y16, Y32)):
+            bound = unit * np.abs(b).max() * 1.5
+            assert np.abs(a - b).max() <= bound
+    b = synth.gaussian((fine.V, 4, 3), 1, 2)
+    x32, i32 = mg32.solve(dev(b), tol=1e-10)
+    x16, i16 = mg16.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x16).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print(storage, 'fp32 storage', i32, '16-bit coarse storage', i16, 'oracle-M residual %.2e' % tr)
+    assert i16['converged'] and tr <= 1e-10
+    assert i16['outer_iters'] <= i32['outer_iters'] + 3
+    # and the fine operator of the K-cycle in 16 bits as well
+    mgf = Multigrid(dims, dev(U), m0, 1.0, lv16, st, inner='c64', fine_storage=storage)
+    xf, inf = mgf.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(xf).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print(storage, 'all 16-bit', inf, 'oracle-M residual %.2e' % tr)
+    assert inf['converged'] and tr <= 1e-10
+    assert inf['outer_iters'] <= i32['outer_iters'] + 4
+
+
+def test_16bit_coarse_storage_needs_fp32_inner():
+    from paper_1612_07873_amd import Multigrid
+    from paper_1612_07873_amd._lib import QmgError
+    dims, m0 = (4, 4, 4, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2)], [6]
+    U, A, fine = problem(dims, 0.4, 1, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 0)]
+    lv = [dict(L, coarse_storage='h16') for L in level_list(blocks, nvecs, 0, [100])]
+    with pytest.raises(QmgError):
+        Multigrid(dims, dev(U), m0, 1.0, lv, st, inner='c128')
+    with pytest.raises(QmgError):
+        Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 0, [100]), st, inner='c128', fine_storage='b16')
+
+
+@pytest.mark.parametrize('storage', ['h16', 'b16'])
+def test_precision_form_error_at_every_level(storage):
+    """Every level of a hierarchy in the 16-bit precision form against the
+    FP64 oracle: the oracle rebuilds each level's Galerkin operator from the
+    block bases the GPU setup produced (exported in FP64), and each stored
+    operator, applied with FP32 vectors, must stay within 4u (norm-wise
+    relative) of the oracle's operator; the fine level is compared with the
+    oracle's M directly."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U, A, fine = problem(dims, 0.3, 2, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 5)]
+    lv = [dict(L, coarse_storage=storage) for L in level_list(blocks, nvecs, 30, [10, 100])]
+    mg = Multigrid(dims, dev(U), m0, 1.0, lv, st, inner='c64', fine_storage=storage)
+    ur = 2.0 ** -11 if storage == 'h16' else 2.0 ** -8
+    from paper_1612_07873_amd import FineOp
+    f16 = FineOp(dims, dev(U), m0, 1.0, True, storage)
+    psi = synth.gaussian((lattice.volume(dims), 4, 3), 9, 2)
+    e0 = float(np.linalg.norm(host(f16.apply(dev(psi, torch.complex64))) - fine.apply(psi.reshape(-1)).reshape(psi.shape))
+               / np.linalg.norm(fine.apply(psi.reshape(-1))))
+    errs = [e0]
+    parent = coarse.FineParent(U, A, m0, dims)
+    for l in (1, 2):
+        pdims, pdof, _, T = mg.level(l - 1)
+        Vb = np.ascontiguousarray(host(T.basis()).transpose(2, 0, 1))
+        ref = coarse.galerkin(parent, Vb, blocks[l - 1])
+        _, N, op, _ = mg.level(l)
+        u = synth.gaussian((ref.X.shape[0], N), 20 + l, 2)
+        y = host(op.apply(dev(u, torch.complex64)))
+        yr = ref.apply(u)
+        errs.append(float(np.linalg.norm(y - yr) / np.linalg.norm(yr)))
+        parent = coarse.CoarseParent(ref)
+    print(storage, 'error against the FP64 oracle per level', ['%.2e' % e for e in errs], 'u=%.2e' % ur)
+    assert all(e <= 4 * ur for e in errs)

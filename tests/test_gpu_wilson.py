@@ -69,3 +69,84 @@ def test_free_field_plane_wave_eigenvector():
     op = FineOp(dims, dev(U), m0, 1.0, True, 'c128')
     y = host(op.apply(dev(psi)))
     assert np.abs(y - w[0] * psi).max() < 1e-13
+
+
+U_ROUND = {'h16': 2.0 ** -11, 'b16': 2.0 ** -8}
+
+
+def round16(z, fmt):
+    """Host rounding of complex entries to the 16-bit format, through FP32 as
+    the packing kernel does (round to nearest even)."""
+    def r(x):
+        f = np.ascontiguousarray(x, dtype=np.float32)
+        if fmt == 'h16':
+            return f.astype(np.float16).astype(np.float64)
+        u = f.view(np.uint32).astype(np.uint64)
+        u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+        return u.astype(np.uint32).view(np.float32).astype(np.float64)
+    return r(z.real) + 1j * r(z.imag)
+
+
+@pytest.mark.parametrize('fmt', ['h16', 'b16'])
+@pytest.mark.parametrize('dims', [(8, 8, 8, 8), (3, 5, 2, 7)])
+def test_sixteen_bit_fine_operator(fmt, dims):
+    """Links and clover in 16 bits (FP32 arithmetic).  Arithmetic parity: the
+    GPU result equals the FP64 oracle applied to the rounded links, the
+    exported (exactly dequantised) clover and the same vector, to FP32
+    rounding.  Storage: the clover entries lie within u of their (chirality,
+    site) scale, and the result against the oracle on unrounded inputs stays
+    within a few u.  16-bit vectors with per-site scales: only the output
+    rounding is added."""
+    from paper_1612_07873_amd import FineOp, dequantize_sites, quantize_sites
+    V = lattice.volume(dims)
+    m0, eps = -0.2, 0.4
+    U = synth.gauge_field(dims, eps, 0)
+    A = wilson.clover_field(U, dims, 1.0)
+    psi = synth.gaussian((V, 4, 3), 5, 2)
+    ref = wilson.apply_wilson_clover(psi, U, A, m0, dims, True)
+    op = FineOp(dims, dev(U), m0, 1.0, True, fmt)
+    ur = U_ROUND[fmt]
+    Aq = host(op.clover())
+    for chi in range(2):
+        blk = slice(6 * chi, 6 * chi + 6)
+        a, aq = A[:, blk, blk], Aq[:, blk, blk]
+        sc = np.maximum(np.abs(a.real), np.abs(a.imag)).max(axis=(1, 2))
+        assert np.all(np.abs(aq.real - a.real) <= ur * sc[:, None, None] * (1 + 1e-6))
+        assert np.all(np.abs(aq.imag - a.imag) <= ur * sc[:, None, None] * (1 + 1e-6))
+    assert np.abs(Aq[:, :6, 6:]).max() == 0 and np.abs(Aq[:, 6:, :6]).max() == 0
+    Uq = round16(U, fmt)
+    psi32 = psi.astype(np.complex64).astype(np.complex128)
+    y = host(op.apply(dev(psi, torch.complex64)))
+    exact = wilson.apply_wilson_clover(psi32, Uq, Aq, m0, dims, True)
+    e_arith = rel_err(y, exact)
+    e_store = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    uq, us = quantize_sites(dev(psi.reshape(V, 12), torch.complex64), fmt)
+    pd = host(dequantize_sites(uq, us, fmt))
+    yq, ys = op.apply_scaled(uq, us)
+    y16 = host(dequantize_sites(yq, ys, fmt))
+    exact16 = wilson.apply_wilson_clover(pd.reshape(V, 4, 3), Uq, Aq, m0, dims, True).reshape(V, 12)
+    e_arith16 = float(np.linalg.norm(y16 - exact16) / np.linalg.norm(exact16))
+    e_store16 = float(np.linalg.norm(y16 - ref.reshape(V, 12)) / np.linalg.norm(ref))
+    print('%s %s: arithmetic %.2e / %.2e, storage error %.2e (fp32 vec) %.2e (16-bit vec), u=%.2e'
+          % (dims, fmt, e_arith, e_arith16, e_store, e_store16, ur))
+    assert e_arith <= 1e-5
+    assert e_arith16 <= 1.5 * ur
+    assert e_store <= 4 * ur
+    assert e_store16 <= 5 * ur
+    ysh = host(ys.to(torch.complex128)).real
+    assert np.allclose(ysh, np.maximum(np.abs(exact16.real), np.abs(exact16.imag)).max(axis=1), rtol=1e-5)
+
+
+def test_sixteen_bit_fine_operator_errors():
+    """complex128 vectors do not fit a 16-bit operator; 16-bit vectors need the scaled entry point."""
+    import ctypes
+    from paper_1612_07873_amd import FineOp, QmgError, _lib
+    dims = (4, 4, 4, 4)
+    U = synth.gauge_field(dims, 0.3, 1)
+    op = FineOp(dims, dev(U), -0.1, 1.0, True, 'h16')
+    x = torch.zeros((lattice.volume(dims), 4, 3), dtype=torch.complex128, device='cuda')
+    y = torch.empty_like(x)
+    for prec in ('c128', 'h16'):
+        with pytest.raises(QmgError):
+            _lib.call('qmg_wilson_clover_dslash', op._h, ctypes.c_void_p(x.data_ptr()),
+                      ctypes.c_void_p(y.data_ptr()), _lib.PREC[prec], None)

@@ -129,3 +129,18 @@ def test_clover_enters_the_operator_through_A(apply_M):
     psi = synth.gaussian((V, 4, 3), 4, 2)
     d = apply_M(psi, U, A, 0.1, dims) - apply_M(psi, U, None, 0.1, dims)
     assert np.abs(d.reshape(V, 12) - np.einsum('xij,xj->xi', A, psi.reshape(V, 12))).max() < 1e-14
+
+
+def test_sampled_sites_agree_with_whole_field():
+    """The site-restricted forms (clover term and M at chosen sites) give the
+    rows of the whole-field results."""
+    dims = (4, 2, 6, 4)
+    U = synth.gauge_field(dims, 0.5, 7)
+    V = lattice.volume(dims)
+    psi = synth.gaussian((V, 4, 3), 7, 2)
+    A = wilson.clover_field(U, dims, 1.3)
+    full = wilson.apply_wilson_clover(psi, U, A, -0.1, dims)
+    sites = np.array([0, 5, 17, V - 1, 40, 41])
+    assert np.allclose(wilson.clover_field(U, dims, 1.3, sites), A[sites], rtol=0, atol=1e-14)
+    part = wilson.apply_wilson_clover_sites(psi, U, 1.3, -0.1, dims, sites)
+    assert np.allclose(part, full[sites], rtol=0, atol=1e-13)
