@@ -246,55 +246,72 @@ __global__ void k_normalize(cpx<R>* __restrict__ x, const double* __restrict__ n
     x[i].im *= inv;
 }
 
+// Sums of per-thread values over the work-group, in a fixed order: each wave
+// reduces by shuffles, then thread v adds the waves' partials in wave order.
+// Slots v < nv (and slot 32 when with32) are summed into sc[v], visible to
+// every thread on return.
+__device__ __forceinline__ void wg_sums(const double* acc, int nv, bool with32, double (*part)[36], double* sc) {
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int v = 0; v < 36; ++v) {
+        if (v < nv || (with32 && v == 32)) {
+            double x = acc[v];
+            for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+            if (lane == 0) part[w][v] = x;
+        }
+    }
+    __syncthreads();
+    if (t < nv || (with32 && t == 32)) {
+        double x = 0;
+        for (int i = 0; i < nw; ++i) x += part[i][t];
+        sc[t] = x;
+    }
+    __syncthreads();
+}
+
 // One whole GCR step after q = A z, for short vectors, in a single work-group:
-// two classical Gram-Schmidt passes of (q, z) against the k stored pairs,
-// normalisation, x += alpha z, r -= alpha q, and |r|^2.  out = [<q,q>,
-// <q,r>.re, <q,r>.im, |r|^2] (before normalisation for the first three).  When
-// znext is given it receives r (the next step's unpreconditioned direction).
+// classical Gram-Schmidt of (q, z) against the k stored pairs, repeated only
+// when it cancelled most of q (|q'|^2 < |q|^2 / 2, the Daniel-Gragg-Kaufman-
+// Stewart test: one pass is then not enough for orthogonality to working
+// precision); the norms and <q', r> needed next are summed in the same sweep
+// that updates q and z.  Then normalisation, x += alpha z, r -= alpha q, and
+// |r|^2.  out = [<q,q>, <q,r>.re, <q,r>.im, |r|^2] (the first three for the
+// orthogonalised q before normalisation).  When znext is given it receives r
+// (the next step's unpreconditioned direction).  Common case: three sweeps
+// over the vectors.
 template <typename R>
 __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restrict__ Q, const cpx<R>* __restrict__ Z,
                                                          int64_t ld, int k, cpx<R>* __restrict__ q,
                                                          cpx<R>* __restrict__ z, cpx<R>* __restrict__ x,
                                                          cpx<R>* __restrict__ r, int64_t n, double* __restrict__ out,
                                                          cpx<R>* __restrict__ znext, int ss) {
-    __shared__ double lds[16];
+    __shared__ double sc[36];
+    __shared__ double part[16][36];
     QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(Z); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x);
     QMG_MEMBER_VEC(r); QMG_MEMBER_SCAL(out);
     if (znext) QMG_MEMBER_VEC(znext);
-    __shared__ double sc[40];
-    __shared__ double part[16][32];
     const int t = threadIdx.x, T = blockDim.x;
-    const int w = t >> 6, lane = t & 63, nw = T >> 6;
-    for (int pass = 0; pass < 2; ++pass) {
-        // all k inner products in one sweep, then one combined work-group reduction
-        double acc[32];
+    double acc[36];
+    // sweep A: <Q_j, q> (j < k) and |q|^2
 #pragma unroll
-        for (int v = 0; v < 32; ++v) acc[v] = 0;
-        for (int64_t i = t; i < n; i += T) {
-            const cpx<R> b = q[i];
+    for (int v = 0; v < 36; ++v) acc[v] = 0;
+    for (int64_t i = t; i < n; i += T) {
+        const cpx<R> b = q[i];
+        acc[32] += (double)b.re * b.re + (double)b.im * b.im;
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (j < k) {
-                    const cpx<R> a = Q[j * ld + i];
-                    acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
-                    acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
-                }
-        }
-#pragma unroll
-        for (int v = 0; v < 32; ++v) {
-            if (v < 2 * k) {
-                double x = acc[v];
-                for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-                if (lane == 0) part[w][v] = x;
+        for (int j = 0; j < 16; ++j)
+            if (j < k) {
+                const cpx<R> a = Q[j * ld + i];
+                acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+                acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
             }
-        }
-        __syncthreads();
-        if (t < 2 * k) {
-            double x = 0;
-            for (int i = 0; i < nw; ++i) x += part[i][t];
-            sc[t] = x;
-        }
-        __syncthreads();
+    }
+    wg_sums(acc, 2 * k, true, part, sc);
+    double qq0 = sc[32];
+    double qq = qq0, re = 0, im = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        // sweep B: q -= sum beta_j Q_j, z -= sum beta_j Z_j (beta in sc), with |q'|^2 and <q', r>
+        double n2 = 0, dr = 0, di = 0;
         for (int64_t i = t; i < n; i += T) {
             R qr = q[i].re, qi = q[i].im, zr = z[i].re, zi = z[i].im;
             for (int j = 0; j < k; ++j) {
@@ -307,24 +324,34 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
             }
             q[i] = cpx<R>{qr, qi};
             z[i] = cpx<R>{zr, zi};
+            const cpx<R> b = r[i];
+            n2 += (double)qr * qr + (double)qi * qi;
+            dr += (double)qr * b.re + (double)qi * b.im;
+            di += (double)qr * b.im - (double)qi * b.re;
+        }
+        double a3[36];
+        a3[0] = n2; a3[1] = dr; a3[2] = di;
+        __syncthreads();   // every thread has read sc (the betas) before it is overwritten
+        wg_sums(a3, 3, false, part, sc);
+        qq = sc[0]; re = sc[1]; im = sc[2];
+        if (pass == 1 || k == 0 || !(qq < 0.5 * qq0)) break;
+        // the projection cancelled most of q: orthogonalise once more (sweep A again, dots only)
+        qq0 = qq;
+#pragma unroll
+        for (int v = 0; v < 36; ++v) acc[v] = 0;
+        for (int64_t i = t; i < n; i += T) {
+            const cpx<R> b = q[i];
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                if (j < k) {
+                    const cpx<R> a = Q[j * ld + i];
+                    acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+                    acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
+                }
         }
         __syncthreads();
+        wg_sums(acc, 2 * k, false, part, sc);
     }
-    double qq = 0, re = 0, im = 0;
-    for (int64_t i = t; i < n; i += T) {
-        const cpx<R> a = q[i], b = r[i];
-        qq += (double)a.re * a.re + (double)a.im * a.im;
-        re += (double)a.re * b.re + (double)a.im * b.im;
-        im += (double)a.re * b.im - (double)a.im * b.re;
-    }
-    qq = wg_sum(qq, lds);
-    re = wg_sum(re, lds);
-    im = wg_sum(im, lds);
-    if (t == 0) { sc[0] = qq; sc[1] = re; sc[2] = im; }
-    __syncthreads();
-    qq = sc[0];
-    re = sc[1];
-    im = sc[2];
     double rr = 0;
     if (qq > 0) {
         const double nq = sqrt(qq);
@@ -351,12 +378,15 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
             rr += (double)b.re * b.re + (double)b.im * b.im;
         }
     }
-    rr = wg_sum(rr, lds);
+    double a1[36];
+    a1[0] = rr;
+    __syncthreads();
+    wg_sums(a1, 1, false, part, sc);
     if (t == 0) {
         out[0] = qq;
         out[1] = re;
         out[2] = im;
-        out[3] = rr;
+        out[3] = sc[0];
     }
 }
 
