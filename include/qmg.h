@@ -218,6 +218,11 @@ qmg_status qmg_wilson_clover_dslash_scaled(qmg_fine_op op, const void* in, const
  * index 3*spin + colour). */
 qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* stream);
 
+/* Write the links the operator holds (after rounding to its storage) as
+ * DEVICE complex128 [4][V][3][3], in the layout of qmg_fine_op_create's
+ * gauge argument (the antiperiodic time sign taken back out). */
+qmg_status qmg_fine_op_export_links(qmg_fine_op op, void* gauge, void* stream);
+
 void qmg_fine_op_destroy(qmg_fine_op op);
 
 /* ---------------------------------------------------------------------------

@@ -198,6 +198,12 @@ class FineOp:
         _lib.call('qmg_fine_op_export_clover', self._h, ctypes.c_void_p(A.data_ptr()), stream_ptr())
         return A
 
+    def links(self):
+        """The links as stored (complex128 [4][V][3][3], time sign removed)."""
+        G = torch.empty((4, self.V, 3, 3), dtype=torch.complex128, device='cuda')
+        _lib.call('qmg_fine_op_export_links', self._h, ctypes.c_void_p(G.data_ptr()), stream_ptr())
+        return G
+
     def __del__(self):
         h = getattr(self, '_h', None)
         if h is not None and h.value and _lib._lib is not None:

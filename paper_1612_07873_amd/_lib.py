@@ -42,6 +42,7 @@ SIGNATURES = {
     'qmg_wilson_clover_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_wilson_clover_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_fine_op_export_clover': (c_int, [c_void_p, c_void_p, c_void_p]),
+    'qmg_fine_op_export_links': (c_int, [c_void_p, c_void_p, c_void_p]),
     'qmg_fine_op_destroy': (None, [c_void_p]),
     'qmg_transfer_create': (c_int, [c_dims, c_int, c_dims, c_int, c_void_p, c_int, c_void_p,
                                     ctypes.POINTER(c_void_p)]),

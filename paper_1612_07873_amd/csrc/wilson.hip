@@ -479,6 +479,28 @@ __global__ void k_clover_export(double2* __restrict__ out, const void* __restric
     }
 }
 
+// The links as the operator holds them -> canonical [4][V][3][3] complex128,
+// with the antiperiodic time sign taken back out.  One thread per entry.
+template <int LF>
+__global__ void k_links_export(double2* __restrict__ G, const void* __restrict__ U, int64_t V,
+                               int64_t last_slice_start, int anti) {
+    using R = typename FineT<LF>::R;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= 4 * 9 * V) return;
+    const int64_t site = g % V;
+    const int e = (int)((g / V) % 9);
+    const int mu = (int)(g / (9 * V));
+    cpx<R> v;
+    if constexpr (is16f<LF>()) {
+        const cpx<float> d = dec_pair<LF>(static_cast<const uint32_t*>(U)[g]);
+        v = cpx<R>{d.re, d.im};
+    } else {
+        v = static_cast<const cpx<R>*>(U)[g];
+    }
+    const double sgn = (anti && mu == 3 && site >= last_slice_start) ? -1.0 : 1.0;
+    G[((int64_t)mu * V + site) * 9 + e] = make_double2(sgn * (double)v.re, sgn * (double)v.im);
+}
+
 // FP64 clover [2][36][V] -> 16-bit pairs [2][18][V] with one scale per (chirality, site).
 template <int LF>
 __global__ void k_clover_pack16(uint32_t* __restrict__ W, float* __restrict__ cscale,
@@ -715,6 +737,22 @@ extern "C" qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* s
         case QMG_C64: hipLaunchKernelGGL(k_clover_export<FMT_F32>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V); break;
         case QMG_H16: hipLaunchKernelGGL(k_clover_export<FMT_H16>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V); break;
         default: hipLaunchKernelGGL(k_clover_export<FMT_B16>, dim3(nb), dim3(128), 0, s, (double2*)A, op->clov, op->cscale, op->V);
+    }
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_fine_op_export_links(qmg_fine_op op, void* gauge, void* stream) {
+    if (!op || !gauge) return fail(QMG_ERR_ARG, "fine_op_export_links: NULL argument");
+    hipStream_t s = as_stream(stream);
+    const unsigned nb = (unsigned)((36 * op->V + 255) / 256);
+    const int64_t last = op->V - op->V / op->dims[3];
+    double2* G = static_cast<double2*>(gauge);
+    switch (op->storage) {
+        case QMG_C128: hipLaunchKernelGGL(k_links_export<FMT_F64>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
+        case QMG_C64: hipLaunchKernelGGL(k_links_export<FMT_F32>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
+        case QMG_H16: hipLaunchKernelGGL(k_links_export<FMT_H16>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
+        default: hipLaunchKernelGGL(k_links_export<FMT_B16>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t);
     }
     QMG_LAUNCH_CHECK();
     return QMG_OK;

@@ -26,6 +26,9 @@ def check(dims, eps, seed, m0, csw, anti, prec):
     err = rel_err(y, ref)
     print('%s eps %.1f csw %.1f anti %d %s rel err %.3e' % (dims, eps, csw, anti, prec, err))
     assert err <= TOL[prec]
+    # the stored links (time sign folded on the device, taken out by the export)
+    Ug = host(op.links())
+    assert np.abs(Ug - U).max() <= (0.0 if prec == 'c128' else 2.0 ** -24)
     if A is not None:
         Ag = host(op.clover())
         tol_c = 1e-13 if prec == 'c128' else 1e-6
@@ -76,7 +79,8 @@ U_ROUND = {'h16': 2.0 ** -11, 'b16': 2.0 ** -8}
 
 def round16(z, fmt):
     """Host rounding of complex entries to the 16-bit format, through FP32 as
-    the packing kernel does (round to nearest even)."""
+    the packing kernel does (round to nearest even; FP16 subnormals as numpy
+    rounds them, which the device conversion need not reproduce)."""
     def r(x):
         f = np.ascontiguousarray(x, dtype=np.float32)
         if fmt == 'h16':
@@ -114,7 +118,13 @@ def test_sixteen_bit_fine_operator(fmt, dims):
         assert np.all(np.abs(aq.real - a.real) <= ur * sc[:, None, None] * (1 + 1e-6))
         assert np.all(np.abs(aq.imag - a.imag) <= ur * sc[:, None, None] * (1 + 1e-6))
     assert np.abs(Aq[:, :6, 6:]).max() == 0 and np.abs(Aq[:, 6:, :6]).max() == 0
-    Uq = round16(U, fmt)
+    # the stored links: each component within u of the links' scale (1: SU(3) entries are bounded by 1)
+    Uq = host(op.links())
+    assert np.abs(Uq.real - U.real).max() <= ur and np.abs(Uq.imag - U.imag).max() <= ur
+    # and on normal-range values the round-to-nearest-even result (the host rounding)
+    Uh = round16(U, fmt)
+    normal = np.abs(U.real) >= 2.0 ** -14
+    assert np.array_equal(Uq.real[normal], Uh.real[normal])
     psi32 = psi.astype(np.complex64).astype(np.complex128)
     y = host(op.apply(dev(psi, torch.complex64)))
     exact = wilson.apply_wilson_clover(psi32, Uq, Aq, m0, dims, True)
