@@ -7,7 +7,23 @@
 
 namespace qmg {
 
-__device__ __forceinline__ uint16_t f32_to_h16(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+// FP32 -> binary16, round to nearest even, written out from the formats (a
+// plain conversion was lowered to a mixed-precision FMA whose rounding did not
+// match round-to-nearest-even on every value): normal results round at
+// mantissa bit 13 and re-bias the exponent (127 -> 15); results below 2^-14
+// are multiples of 2^-24, rounded by rintf; from 65520 up the result is Inf.
+__device__ __forceinline__ uint16_t f32_to_h16(float f) {
+    const uint32_t x = __float_as_uint(f);
+    const uint32_t sign = (x >> 16) & 0x8000u;
+    const uint32_t ax = x & 0x7fffffffu;
+    if (ax >= 0x7f800000u) return (uint16_t)(sign | (ax > 0x7f800000u ? 0x7e00u : 0x7c00u));   // NaN, Inf
+    if (ax >= 0x477ff000u) return (uint16_t)(sign | 0x7c00u);                                  // overflow
+    if (ax >= 0x38800000u) {                                                                   // normal
+        const uint32_t r = ax + 0x0fffu + ((ax >> 13) & 1u) - 0x38000000u;
+        return (uint16_t)(sign | (r >> 13));
+    }
+    return (uint16_t)(sign | (uint32_t)rintf(__uint_as_float(ax) * 16777216.0f));             // subnormal, zero
+}
 __device__ __forceinline__ float h16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
 __device__ __forceinline__ uint16_t f32_to_b16(float f) {  // round to nearest even
     uint32_t u = __float_as_uint(f);
