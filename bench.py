@@ -265,6 +265,58 @@ def learned(npairs, epochs, loss):
             'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3)}
 
 
+def fine_and_transfer(steps=200):
+    """Rows a8 and a9 on 16^3x32: the fine Wilson-clover apply (FP32 storage;
+    16-bit links and clover with FP32 and with 16-bit spinors) and the
+    level-0 prolongation / restriction (Nvec 24, block 4^4, FP32), each as
+    achieved GB/s against 8 TB/s from algorithmic bytes per launch.  Operator
+    copies are cycled so that one launch's data is not left in the 256 MB
+    Infinity Cache by the previous launch."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import FineOp, Transfer, quantize_sites
+    dev = torch.device('cuda')
+    dims = (16, 16, 16, 32)
+    V = int(np.prod(dims))
+    U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
+    psi = [torch.from_numpy(synth.gaussian((V, 4, 3), 10 + k, 2)).to(dev).to(torch.complex64) for k in range(4)]
+    out = {}
+    site_bytes = {'c64': 768, 'h16_fp32_vectors': 144 + 152 + 192, 'h16_16bit_vectors': 144 + 152 + 2 * (48 + 4)}
+    for name, storage in (('c64', 'c64'), ('h16_fp32_vectors', 'h16'), ('h16_16bit_vectors', 'h16')):
+        R = 4 if storage == 'c64' else 8
+        ops = [FineOp(dims, U, -0.18, 1.0, True, storage) for _ in range(R)]
+        if name == 'h16_16bit_vectors':
+            qs = [quantize_sites(p.reshape(V, 12), 'h16') for p in psi]
+            o16, osc = torch.empty_like(qs[0][0]), torch.empty_like(qs[0][1])
+            fn = lambda i: ops[i % R].apply_scaled(qs[i % 4][0], qs[i % 4][1], o16, osc)
+        else:
+            y = torch.empty_like(psi[0])
+            fn = lambda i: ops[i % R].apply(psi[i % 4], y)
+        ms = timed(fn, steps, 20)
+        gbs = site_bytes[name] * V / (ms * 1e-3) / 1e9
+        out['wilson_clover_' + name] = {'lattice': list(dims), 'us_per_launch': round(ms * 1e3, 2),
+                                        'algorithmic_bytes_per_site': site_bytes[name], 'GB/s': round(gbs, 1),
+                                        'frac_of_hbm_peak': round(gbs / HBM_PEAK_GBS, 4), 'copies_cycled': R}
+        del ops
+    vecs = torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev)
+    T = Transfer(dims, 12, (4, 4, 4, 4), vecs, 'c64')
+    del vecs
+    f = psi[0].reshape(V, 12)
+    c = torch.empty((T.Vc, T.N), dtype=torch.complex64, device=dev)
+    fo = torch.empty_like(f)
+    basis = V * 12 * 24 * 8
+    for name, fn, byts in (('restrict', lambda i: T.restrict(f, c), basis + V * 12 * 8 + T.Vc * T.N * 8),
+                           ('prolong', lambda i: T.prolong(c, fo), basis + V * 12 * 8 + T.Vc * T.N * 8)):
+        ms = timed(fn, steps, 20)
+        gbs = byts / (ms * 1e-3) / 1e9
+        out[name] = {'lattice': list(dims), 'nvec': 24, 'block': [4, 4, 4, 4], 'us_per_launch': round(ms * 1e3, 2),
+                     'algorithmic_bytes_per_launch': byts, 'GB/s': round(gbs, 1),
+                     'frac_of_hbm_peak': round(gbs / HBM_PEAK_GBS, 4),
+                     'note': 'basis (302 MB) exceeds the Infinity Cache; the fine vector may stay cached'}
+    return out
+
+
 def mg_gcr(nsolves=12, nrhs=16):
     mg, U, m0, m0_src, setup = build_mg_16x32()
     out = {'lattice': [16, 16, 16, 32], 'm0': m0, 'm0_source': m0_src,
@@ -442,6 +494,7 @@ def main():
     del ops, Xd, Yd
     if not args.only_headline:
         rec.update(precision_and_mrhs(max(100, args.steps // 4)))
+        rec['fine_and_transfer'] = fine_and_transfer()
         rec['mg_gcr'] = mg_gcr()
     if not args.no_cpu:
         ref, rec['cpu_baseline'] = cpu_baseline(cd, N, X, Y, u)

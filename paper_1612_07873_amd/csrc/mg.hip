@@ -196,13 +196,15 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
         QMG_HIP(hipMemcpyAsync(L.r, b, bb, hipMemcpyDeviceToDevice, mg->s));
     }
     // all members converged (or broken down: q = 0) after the scalars in slots
-    // S_GCR (and rnorm2 at `rslot`) were read
+    // S_GCR (and rnorm2 at `rslot`) were read.  A member with b = 0 is not
+    // done by itself: from a start x0 that is the relaxation A x = 0 of the
+    // setup, which runs to maxit; from x = 0 its q is 0 and it breaks down.
     auto all_done = [&](int rslot, bool* fault) {
         bool done = true;
         for (int k = 0; k < nb; ++k) {
             const double rn = std::sqrt(hs(mg, k, rslot));
             if (!std::isfinite(rn) || !std::isfinite(hs(mg, k, S_GCR))) *fault = true;
-            const bool ok = hs(mg, k, S_GCR) <= 0.0 || (bnorm[k] > 0 && rn <= tol * bnorm[k]) || bnorm[k] == 0;
+            const bool ok = hs(mg, k, S_GCR) <= 0.0 || (bnorm[k] > 0 && rn <= tol * bnorm[k]);
             done = done && ok;
         }
         return done;

@@ -80,6 +80,11 @@ def test_three_level_with_relaxed_null_vectors():
     # better conditioned for the smooth error than plain GCR on the fine level
     x2, info2 = mg.solve(dev(b), tol=1e-10)
     assert info2['outer_iters'] == info['outer_iters']       # repeatable
+    # the relaxation did its work: the same starts without it give a weaker hierarchy
+    mg0 = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 0, [10, 100]), [dev(s) for s in st], inner='c64')
+    _, info0 = mg0.solve(dev(b), tol=1e-10)
+    print('unrelaxed start vectors', info0)
+    assert info['outer_iters'] < info0['outer_iters']
 
 
 def test_config2_shape_three_levels_to_1e10():
