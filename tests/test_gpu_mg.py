@@ -184,7 +184,7 @@ def test_precision_form_error_at_every_level(storage):
     parent = coarse.FineParent(U, A, m0, dims)
     for l in (1, 2):
         pdims, pdof, _, T = mg.level(l - 1)
-        Vb = np.ascontiguousarray(host(T.basis()).transpose(2, 0, 1))
+        Vb = host(T.basis())          # [V][dof][Nvec], the oracle's basis layout
         ref = coarse.galerkin(parent, Vb, blocks[l - 1])
         _, N, op, _ = mg.level(l)
         u = synth.gaussian((ref.X.shape[0], N), 20 + l, 2)
