@@ -446,11 +446,6 @@ def main():
     copy_ms = timed(lambda i: dst.copy_(calib), 10, 2)      # achievable copy bandwidth on this machine
     copy_gbs = 2 * calib.numel() * 8 / (copy_ms * 1e-3) / 1e9
     del calib, dst
-    # achievable read-only bandwidth (a library reduction over 2 GiB), for reference
-    big = torch.ones(1 << 29, dtype=torch.float32, device=dev)
-    read_ms = timed(lambda i: big.sum(), 10, 2)
-    read_gbs = big.numel() * 4 / (read_ms * 1e-3) / 1e9
-    del big
     cd, N = (4, 4, 4, 8), 48
     V = int(np.prod(cd))
     X = synth.gaussian((V, N, N), 0, 2)
@@ -485,7 +480,7 @@ def main():
                      'frac': round(achieved / HBM_PEAK_GBS, 4),
                      'traffic': measured_traffic([ops[0].launch()[0], ops[0].launch()[1], ops[0].prefetch()]),
                      'algorithmic_bytes_per_launch': byts, 'kernel': 'qmg::k_coarse_dslash (FP32 links)',
-                     'achievable_copy_GB/s': round(copy_gbs, 1), 'achievable_read_GB/s': round(read_gbs, 1),
+                     'achievable_copy_GB/s': round(copy_gbs, 1),
                      'frac_of_achievable_copy': round(achieved / copy_gbs, 4)},
     }
     warm_ms = timed(lambda i: ops[0].apply(ud, out), 500, 50)

@@ -291,6 +291,11 @@ template <typename R> __device__ __forceinline__ R shfl_xor_r(R v, int m) { retu
 // direction k, and the diagonal and clover rows 3k..3k+2 (chirality k/2);
 // the four partial spinors are summed by two lane exchanges in a fixed order
 // (every lane ends with the same sum) and the site's first lane stores it.
+// Work-groups are dispatched to the eight XCDs in turn, and each XCD has its
+// own L2; the kernel renumbers them so that XCD j processes one contiguous
+// eighth of the lattice (the grid is padded to a multiple of 8 and the extra
+// work-groups leave at once), keeping a site's neighbours and shared links in
+// the L2 that already holds them.
 // Four lanes per site quadruple the
 // waves in flight against one thread per site, which left the 16^3x32 lattice
 // at two waves per SIMD.  Grid dimension y runs over batch members: member b's
@@ -303,7 +308,9 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
                                                        float* __restrict__ out_scale, int64_t V,
                                                        typename FineT<LF>::R diag, int use_clover) {
     using R = typename FineT<LF>::R;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = gridDim.x >> 3;   // gridDim.x is a multiple of 8
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t g = wg * blockDim.x + threadIdx.x;
     const int64_t site = g >> 2;
     const int k = (int)(g & 3);
     if (site >= V) return;   // all four lanes of a site leave together
@@ -586,7 +593,7 @@ template <int LF, int VF>
 static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const float* in_scale, void* out,
                                 float* out_scale, int members, hipStream_t s) {
     using R = typename FineT<LF>::R;
-    const unsigned nb = (unsigned)((4 * op->V + 255) / 256);
+    const unsigned nb = (unsigned)(((4 * op->V + 255) / 256 + 7) / 8 * 8);   // a multiple of 8 (XCD remap)
     hipLaunchKernelGGL((k_wilson_clover<LF, VF>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale, op->nbr,
                        in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0);
     QMG_LAUNCH_CHECK();
