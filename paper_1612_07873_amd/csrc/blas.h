@@ -1,7 +1,6 @@
 // BLAS-1 layer of the Krylov solvers: every scalar stays in device memory;
-// reductions are two-phase (per-block partials, then the last block to finish
-// sums them in a fixed order, in the same launch) so results are bitwise
-// repeatable; the only atomic is the per-member ticket counter.
+// reductions are two-phase (per-block partials, then one block sums them in a
+// fixed order) so results are bitwise repeatable and need no atomics.
 //
 // Batches: with nb > 1 every call works on nb independent members at once
 // (grid dimension y = member).  Member b of a vector argument of length n
@@ -18,7 +17,6 @@ namespace qmg {
 struct Blas {
     hipStream_t s = nullptr;
     double* partials = nullptr;  // [kMaxBatch][kMaxBlocks][kMaxVals]
-    unsigned* tickets = nullptr; // [kMaxBatch]: work-groups of the running reduction that have finished
     static constexpr int kMaxBlocks = 512;
     static constexpr int kMaxVals = 40;
     static constexpr int kMaxBatch = 64;

@@ -27,6 +27,21 @@ __device__ __forceinline__ double wg_sum(double v, double* lds) {
     return t;
 }
 
+// phase 2: out[v] = sum over blocks of partials[b][v]; thread t adds blocks
+// t, t+256, ..., then a fixed tree: the same order on every run
+__global__ __launch_bounds__(256) void k_final(const double* __restrict__ partials, int nb, int nv,
+                                               double* __restrict__ out, int ss) {
+    __shared__ double lds[16];
+    partials += (int64_t)blockIdx.y * Blas::kMaxBlocks * Blas::kMaxVals;
+    out += (int64_t)blockIdx.y * ss;
+    for (int v = 0; v < nv; ++v) {
+        double t = 0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) t += partials[b * Blas::kMaxVals + v];
+        t = wg_sum(t, lds);
+        if (threadIdx.x == 0) out[v] = t;
+    }
+}
+
 // this work-group's batch member: shift its vectors by member*n, its scalars
 // by member*ss and its partial sums to the member's own table
 #define QMG_MEMBER_SCAL(p) p += (int64_t)blockIdx.y * ss
@@ -39,33 +54,9 @@ __device__ __forceinline__ void put(double* part, double* out, int v, double val
     else part[blockIdx.x * Blas::kMaxVals + v] = val;
 }
 
-// Phase 2 in the same launch: every work-group publishes its partial sums
-// (written by its thread 0) and takes a ticket; the one that finishes last
-// sums all partials, thread t adding blocks t, t + 256, ... and then a fixed
-// tree, so the order is the same on every run, and resets the member's ticket
-// for the next reduction on the stream.  Called by every thread at the end of
-// a reduction kernel.
-__device__ void finish_last(const double* part, double* out, int nv, unsigned* ticket, double* lds) {
-    if (gridDim.x == 1) return;
-    __shared__ int last;
-    __threadfence();   // release: this work-group's partials before its ticket
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1 ? 1 : 0;
-    __syncthreads();
-    if (!last) return;
-    __threadfence();   // acquire: the other work-groups' partials
-    for (int v = 0; v < nv; ++v) {
-        double t = 0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) t += part[b * Blas::kMaxVals + v];
-        t = wg_sum(t, lds);
-        if (threadIdx.x == 0) out[v] = t;
-    }
-    if (threadIdx.x == 0) *ticket = 0;
-}
-
 template <typename R>
 __global__ __launch_bounds__(1024) void k_dot(const cpx<R>* __restrict__ a, const cpx<R>* __restrict__ b, int64_t n,
-                      double* __restrict__ part, double* __restrict__ out, int ss, unsigned* tickets) {
+                      double* __restrict__ part, double* __restrict__ out, int ss) {
     __shared__ double lds[16];
     QMG_MEMBER_VEC(a); QMG_MEMBER_VEC(b); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double re = 0, im = 0;
@@ -80,12 +71,11 @@ __global__ __launch_bounds__(1024) void k_dot(const cpx<R>* __restrict__ a, cons
         put(part, out, 0, re);
         put(part, out, 1, im);
     }
-    finish_last(part, out, 2, tickets + blockIdx.y, lds);
 }
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_norm2(const cpx<R>* __restrict__ a, int64_t n, double* __restrict__ part,
-                                                double* __restrict__ out, int ss, unsigned* tickets) {
+                                                double* __restrict__ out, int ss) {
     __shared__ double lds[16];
     QMG_MEMBER_VEC(a); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double s = 0;
@@ -95,13 +85,12 @@ __global__ __launch_bounds__(1024) void k_norm2(const cpx<R>* __restrict__ a, in
     }
     s = wg_sum(s, lds);
     if (threadIdx.x == 0) put(part, out, 0, s);
-    finish_last(part, out, 1, tickets + blockIdx.y, lds);
 }
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_dot_norm(const cpx<R>* __restrict__ q, const cpx<R>* __restrict__ r,
                                                    int64_t n, double* __restrict__ part, double* __restrict__ out,
-                                                   int ss, unsigned* tickets) {
+                                                   int ss) {
     __shared__ double lds[16];
     QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(r); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double qq = 0, re = 0, im = 0;
@@ -119,14 +108,12 @@ __global__ __launch_bounds__(1024) void k_dot_norm(const cpx<R>* __restrict__ q,
         put(part, out, 1, re);
         put(part, out, 2, im);
     }
-    finish_last(part, out, 3, tickets + blockIdx.y, lds);
 }
 
 template <typename R>
 __global__ __launch_bounds__(1024) void k_multi_dot(const cpx<R>* __restrict__ Q, int64_t ld, int k,
                                                     const cpx<R>* __restrict__ q, int64_t n,
-                                                    double* __restrict__ part, double* __restrict__ out, int ss,
-                                                    unsigned* tickets) {
+                                                    double* __restrict__ part, double* __restrict__ out, int ss) {
     __shared__ double lds[16];
     QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(q); QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
     double re[16], im[16];
@@ -154,7 +141,6 @@ __global__ __launch_bounds__(1024) void k_multi_dot(const cpx<R>* __restrict__ Q
             }
         }
     }
-    finish_last(part, out, 2 * k, tickets + blockIdx.y, lds);
 }
 
 template <typename R>
@@ -416,40 +402,40 @@ qmg_status Blas::gcr_step_small(const void* Q, const void* Z, int64_t ld, int k,
 qmg_status Blas::init() {
     if (partials) return QMG_OK;
     QMG_HIP(hipMalloc(&partials, sizeof(double) * kMaxBatch * kMaxBlocks * kMaxVals));
-    QMG_HIP(hipMalloc(&tickets, sizeof(unsigned) * kMaxBatch));
-    QMG_HIP(hipMemset(tickets, 0, sizeof(unsigned) * kMaxBatch));
     return QMG_OK;
 }
 
 void Blas::release() {
     if (partials) (void)hipFree(partials);
-    if (tickets) (void)hipFree(tickets);
     partials = nullptr;
-    tickets = nullptr;
 }
 
 static unsigned grid1(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
-
+static void finish(hipStream_t s, double* partials, int nblk, int nv, double* out, int members, int ss) {
+    if (nblk > 1) hipLaunchKernelGGL(k_final, dim3(1, members), dim3(256), 0, s, partials, nblk, nv, out, ss);
+}
 
 template <typename R> qmg_status Blas::dot(const void* a, const void* b, int64_t n, double* out) {
     const int nblk = nblocks(n);
     hipLaunchKernelGGL(k_dot<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n,
-                       partials, out, ss, tickets);
+                       partials, out, ss);
+    finish(s, partials, nblk, 2, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::norm2(const void* a, int64_t n, double* out) {
     const int nblk = nblocks(n);
-    hipLaunchKernelGGL(k_norm2<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)a, n, partials, out, ss,
-                       tickets);
+    hipLaunchKernelGGL(k_norm2<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)a, n, partials, out, ss);
+    finish(s, partials, nblk, 1, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 template <typename R> qmg_status Blas::dot_norm(const void* q, const void* r, int64_t n, double* out) {
     const int nblk = nblocks(n);
     hipLaunchKernelGGL(k_dot_norm<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)q, (const cpx<R>*)r, n,
-                       partials, out, ss, tickets);
+                       partials, out, ss);
+    finish(s, partials, nblk, 3, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -459,7 +445,8 @@ qmg_status Blas::multi_dot(const void* Q, int64_t ld, int k, const void* q, int6
     if (k > 16) return fail(QMG_ERR_ARG, "multi_dot: k=%d > 16", k);
     const int nblk = nblocks(n);
     hipLaunchKernelGGL(k_multi_dot<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)Q, ld, k,
-                       (const cpx<R>*)q, n, partials, out, ss, tickets);
+                       (const cpx<R>*)q, n, partials, out, ss);
+    finish(s, partials, nblk, 2 * k, out, nb, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }

@@ -52,45 +52,21 @@ template <typename R> __device__ __forceinline__ cpx<R> ci(cpx<R> a) { return {-
 template <typename R> __device__ __forceinline__ cpx<R> cmi(cpx<R> a) { return {a.im, -a.re}; }  // -i a
 template <typename R> __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return {-a.re, -a.im}; }
 
-// The 2x2 off-diagonal block g_mu of gamma_mu, as data: every g_mu is a
-// (possibly swapped) diagonal of unit phases, g_mu (p, q) = (c0 * (swap ? q : p),
-// c1 * (swap ? p : q)), so one code path serves all four directions and the
-// lanes of a wave can work on different mu without diverging.
-//   mu = 0: -i sigma_1 = [[0,-i],[-i,0]]   mu = 1: -i sigma_2 = [[0,-1],[1,0]]
-//   mu = 2: -i sigma_3 = diag(-i, i)       mu = 3: 1
-struct GBlock {
-    bool swap;
-    float c0r, c0i, c1r, c1i;
-};
-__device__ __forceinline__ GBlock gblock(int mu) {
-    GBlock g;
-    g.swap = mu < 2;
-    g.c0r = mu == 1 ? -1.f : mu == 3 ? 1.f : 0.f;
-    g.c0i = mu == 0 || mu == 2 ? -1.f : 0.f;
-    g.c1r = mu == 1 || mu == 3 ? 1.f : 0.f;
-    g.c1i = mu == 0 ? -1.f : mu == 2 ? 1.f : 0.f;
-    return g;
+// g_mu * (p, q) for the 2x2 off-diagonal block of gamma_mu
+template <int MU, typename R>
+__device__ __forceinline__ void gmul(cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q) {
+    if (MU == 0) { o0 = cmi(q); o1 = cmi(p); }          // -i sigma_1
+    else if (MU == 1) { o0 = cneg(q); o1 = p; }         // -i sigma_2 = [[0,-1],[1,0]]
+    else if (MU == 2) { o0 = cmi(p); o1 = ci(q); }      // -i sigma_3 = diag(-i, i)
+    else { o0 = p; o1 = q; }                            // 1
 }
-template <typename R> __device__ __forceinline__ cpx<R> cunit(cpx<R> a, float cr, float ci) {
-    return {(R)cr * a.re - (R)ci * a.im, (R)cr * a.im + (R)ci * a.re};
-}
-// (o0, o1) = g (p, q)
-template <typename R>
-__device__ __forceinline__ void gmul(const GBlock& g, cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q) {
-    o0 = cunit(g.swap ? q : p, g.c0r, g.c0i);
-    o1 = cunit(g.swap ? p : q, g.c1r, g.c1i);
-}
-// (o0, o1) = g^+ (p, q): for the swapped form g^+ = [[0, conj c1], [conj c0, 0]],
-// for the diagonal form diag(conj c0, conj c1)
-template <typename R>
-__device__ __forceinline__ void gdmul(const GBlock& g, cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q) {
-    if (g.swap) {
-        o0 = cunit(q, g.c1r, -g.c1i);
-        o1 = cunit(p, g.c0r, -g.c0i);
-    } else {
-        o0 = cunit(p, g.c0r, -g.c0i);
-        o1 = cunit(q, g.c1r, -g.c1i);
-    }
+// g_mu^+ * (p, q)
+template <int MU, typename R>
+__device__ __forceinline__ void gdmul(cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q) {
+    if (MU == 0) { o0 = ci(q); o1 = ci(p); }            // i sigma_1
+    else if (MU == 1) { o0 = q; o1 = cneg(p); }         // i sigma_2 = [[0,1],[-1,0]]
+    else if (MU == 2) { o0 = ci(p); o1 = cmi(q); }      // i sigma_3 = diag(i, -i)
+    else { o0 = p; o1 = q; }
 }
 
 template <int LF> struct FineT { using R = float; };
@@ -199,107 +175,53 @@ __device__ __forceinline__ void store_spinor(void* __restrict__ dst, float* __re
     }
 }
 
-// One chirality half (6 components) of a site's spinor; the half is chosen at
-// run time through the address, so no register array is indexed dynamically.
-template <int VF, typename R>
-__device__ __forceinline__ void load_half(cpx<R> x[6], const void* __restrict__ src, const float* __restrict__ scale,
-                                          int64_t site, int chi) {
-    if constexpr (is16f<VF>()) {
-        const uint2* s2 = static_cast<const uint2*>(src) + site * 6 + 3 * chi;
-        const float k = scale[site];
+// One hop in direction MU; BACK selects the backward hop.  acc += -1/2 * P (x) W psi(n).
+// vo: offset (in sites) of the batch member's vectors
+template <int MU, bool BACK, int LF, int VF, typename R>
+__device__ __forceinline__ void hop(cpx<R> acc[12], const void* __restrict__ in, const float* __restrict__ in_scale,
+                                    const void* __restrict__ U, int64_t V, int64_t site, int64_t n, int64_t vo) {
+    cpx<R> p[12];
+    load_spinor<VF>(p, in, in_scale, n + vo);
+    cpx<R> a[2][3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const uint2 w = s2[i];
-            const cpx<float> a = dec_pair<VF>(w.x), b = dec_pair<VF>(w.y);
-            x[2 * i] = cpx<R>{k * a.re, k * a.im};
-            x[2 * i + 1] = cpx<R>{k * b.re, k * b.im};
-        }
-    } else if constexpr (VF == FMT_F32) {
-        const float4* s4 = static_cast<const float4*>(src) + site * 6 + 3 * chi;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const float4 v = s4[i];
-            x[2 * i] = cpx<R>{v.x, v.y};
-            x[2 * i + 1] = cpx<R>{v.z, v.w};
-        }
-    } else {
-        const cpx<R>* s = static_cast<const cpx<R>*>(src) + site * 12 + 6 * chi;
-#pragma unroll
-        for (int f = 0; f < 6; ++f) x[f] = s[f];
+    for (int c = 0; c < 3; ++c) {
+        cpx<R> g0, g1;
+        gmul<MU>(g0, g1, p[6 + c], p[9 + c]);
+        if (!BACK) { a[0][c] = csub(p[c], g0); a[1][c] = csub(p[3 + c], g1); }
+        else { a[0][c] = cadd(p[c], g0); a[1][c] = cadd(p[3 + c], g1); }
     }
-}
-
-// Both hops along direction mu (runtime): acc += -1/2 [ (1 - gamma_mu) U_mu(x) psi(x+mu)
-// + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ].  Each hop works on the projected
-// half spinor: a = psi_up + s g psi_dn with s = -1 forward, +1 backward, then
-// W = U a (or U^+ a); since g^+ g = 1 the projected spinor is [a; s g^+ a],
-// so upper += -W/2 and lower += -(s/2) g^+ W.  vo: offset (in
-// sites) of the batch member's vectors.
-template <int LF, int VF, typename R>
-__device__ __forceinline__ void hops(cpx<R> acc[12], const void* __restrict__ in, const float* __restrict__ in_scale,
-                                     const void* __restrict__ U, int64_t V, int64_t site, const int* nb, int mu,
-                                     int64_t vo) {
-    const GBlock g = gblock(mu);
+    cpx<R> u[9];
+    load_link<LF>(u, U, MU, BACK ? n : site, V);
+    cpx<R> w[2][3];
 #pragma unroll
-    for (int back = 0; back < 2; ++back) {
-        const int64_t n = nb[2 * mu + back];
-        cpx<R> p[12];
-        load_spinor<VF>(p, in, in_scale, n + vo);
-        const R s = back ? R(1) : R(-1);
-        cpx<R> a[2][3];
+    for (int s = 0; s < 2; ++s)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            cpx<R> g0, g1;
-            gmul(g, g0, g1, p[6 + c], p[9 + c]);
-            a[0][c] = {p[c].re + s * g0.re, p[c].im + s * g0.im};
-            a[1][c] = {p[3 + c].re + s * g1.re, p[3 + c].im + s * g1.im};
-        }
-        cpx<R> u[9];
-        load_link<LF>(u, U, mu, back ? n : site, V);
-        cpx<R> w[2][3];
+        for (int r = 0; r < 3; ++r) {
+            cpx<R> t = {0, 0};
 #pragma unroll
-        for (int sp = 0; sp < 2; ++sp)
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-                cpx<R> t = {0, 0};
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    // U a forward, U^+ a backward
-                    const cpx<R> m = back ? cpx<R>{u[c * 3 + r].re, -u[c * 3 + r].im} : u[r * 3 + c];
-                    t = cadd(t, cmul(m, a[sp][c]));
-                }
-                w[sp][r] = t;
+            for (int c = 0; c < 3; ++c) {
+                if (!BACK) t = cadd(t, cmul(u[r * 3 + c], a[s][c]));      // U a
+                else t = cadd(t, cmulc(u[c * 3 + r], a[s][c]));           // U^+ a
             }
-        const R h = R(-0.5), hl = R(-0.5) * s;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            cpx<R> l0, l1;
-            gdmul(g, l0, l1, w[0][c], w[1][c]);
-            acc[c].re += h * w[0][c].re; acc[c].im += h * w[0][c].im;
-            acc[3 + c].re += h * w[1][c].re; acc[3 + c].im += h * w[1][c].im;
-            acc[6 + c].re += hl * l0.re; acc[6 + c].im += hl * l0.im;
-            acc[9 + c].re += hl * l1.re; acc[9 + c].im += hl * l1.im;
+            w[s][r] = t;
         }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        cpx<R> l0, l1;
+        gdmul<MU>(l0, l1, w[0][c], w[1][c]);
+        const R h = R(-0.5);
+        acc[c].re += h * w[0][c].re; acc[c].im += h * w[0][c].im;
+        acc[3 + c].re += h * w[1][c].re; acc[3 + c].im += h * w[1][c].im;
+        if (!BACK) { l0 = cneg(l0); l1 = cneg(l1); }      // lower = -g^+ a (fwd), +g^+ b (bwd)
+        acc[6 + c].re += h * l0.re; acc[6 + c].im += h * l0.im;
+        acc[9 + c].re += h * l1.re; acc[9 + c].im += h * l1.im;
     }
 }
-
-template <typename R> __device__ __forceinline__ R shfl_xor_r(R v, int m) { return __shfl_xor(v, m, 64); }
 
 // LF: storage of links and clover; VF: storage of the vectors (the same as LF
 // for complex128 / complex64, complex64 or 16-bit pairs for 16-bit links).
-// Four lanes per site (consecutive lanes of a wave): lane k does both hops of
-// direction k, and the diagonal and clover rows 3k..3k+2 (chirality k/2);
-// the four partial spinors are summed by two lane exchanges in a fixed order
-// (every lane ends with the same sum) and the site's first lane stores it.
-// Work-groups are dispatched to the eight XCDs in turn, and each XCD has its
-// own L2; the kernel renumbers them so that XCD j processes one contiguous
-// eighth of the lattice (the grid is padded to a multiple of 8 and the extra
-// work-groups leave at once), keeping a site's neighbours and shared links in
-// the L2 that already holds them.
-// Four lanes per site quadruple the
-// waves in flight against one thread per site, which left the 16^3x32 lattice
-// at two waves per SIMD.  Grid dimension y runs over batch members: member b's
-// fields follow the first at b*V sites.
+// Grid dimension y runs over batch members: member b's fields follow the
+// first at b*V sites.
 template <int LF, int VF>
 __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ U, const void* __restrict__ clov,
                                                        const float* __restrict__ cscale,
@@ -308,58 +230,46 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
                                                        float* __restrict__ out_scale, int64_t V,
                                                        typename FineT<LF>::R diag, int use_clover) {
     using R = typename FineT<LF>::R;
-    const int64_t per = gridDim.x >> 3;   // gridDim.x is a multiple of 8
-    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int64_t g = wg * blockDim.x + threadIdx.x;
-    const int64_t site = g >> 2;
-    const int k = (int)(g & 3);
-    if (site >= V) return;   // all four lanes of a site leave together
+    const int64_t site = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (site >= V) return;
     const int64_t vo = (int64_t)blockIdx.y * V;
-    const int chi = k >> 1, r0 = 3 * (k & 1);   // this lane's clover rows: 6 chi + r0 .. +2
     cpx<R> acc[12];
+    cpx<R> p[12];
+    load_spinor<VF>(p, in, in_scale, site + vo);
 #pragma unroll
-    for (int f = 0; f < 12; ++f) acc[f] = {0, 0};
-    {
-        // diagonal and clover rows of this lane
-        cpx<R> x[6];
-        load_half<VF>(x, in, in_scale, site + vo, chi);
-        R d[6];
-        cpx<R> o[15];
-        if (use_clover) load_clover<LF>(d, o, clov, cscale, chi, site, V);
+    for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
+    if (use_clover) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            if (i < r0 || i >= r0 + 3) continue;
-            cpx<R> t = {diag * x[i].re, diag * x[i].im};
-            if (use_clover) {
-                t.re += d[i] * x[i].re;
-                t.im += d[i] * x[i].im;
-                int q = 0;
+        for (int chi = 0; chi < 2; ++chi) {
+            R d[6];
+            cpx<R> o[15];
+            load_clover<LF>(d, o, clov, cscale, chi, site, V);
+            const cpx<R>* x = p + 6 * chi;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                cpx<R> t = {d[i] * x[i].re, d[i] * x[i].im};
+                int k = 0;
 #pragma unroll
                 for (int r = 0; r < 6; ++r)
 #pragma unroll
-                    for (int c = r + 1; c < 6; ++c, ++q) {
-                        if (r == i) t = cadd(t, cmul(o[q], x[c]));
-                        if (c == i) t = cadd(t, cmulc(o[q], x[r]));
+                    for (int c = r + 1; c < 6; ++c, ++k) {
+                        if (r == i) t = cadd(t, cmul(o[k], x[c]));
+                        if (c == i) t = cadd(t, cmulc(o[k], x[r]));
                     }
+                acc[6 * chi + i] = cadd(acc[6 * chi + i], t);
             }
-            // static indices with value selects: a store to acc[6 chi + i] would put acc in scratch
-            const cpx<R> zero = {0, 0};
-            acc[i] = chi ? zero : t;
-            acc[6 + i] = chi ? t : zero;
         }
     }
-    hops<LF, VF>(acc, in, in_scale, U, V, site, nbr + site * 8, k, vo);
-#pragma unroll
-    for (int f = 0; f < 12; ++f) {
-        acc[f].re += shfl_xor_r(acc[f].re, 1);
-        acc[f].im += shfl_xor_r(acc[f].im, 1);
-    }
-#pragma unroll
-    for (int f = 0; f < 12; ++f) {
-        acc[f].re += shfl_xor_r(acc[f].re, 2);
-        acc[f].im += shfl_xor_r(acc[f].im, 2);
-    }
-    if (k == 0) store_spinor<VF>(out, out_scale, site + vo, acc);
+    const int* nb = nbr + site * 8;
+    hop<0, false, LF, VF>(acc, in, in_scale, U, V, site, nb[0], vo);
+    hop<0, true, LF, VF>(acc, in, in_scale, U, V, site, nb[1], vo);
+    hop<1, false, LF, VF>(acc, in, in_scale, U, V, site, nb[2], vo);
+    hop<1, true, LF, VF>(acc, in, in_scale, U, V, site, nb[3], vo);
+    hop<2, false, LF, VF>(acc, in, in_scale, U, V, site, nb[4], vo);
+    hop<2, true, LF, VF>(acc, in, in_scale, U, V, site, nb[5], vo);
+    hop<3, false, LF, VF>(acc, in, in_scale, U, V, site, nb[6], vo);
+    hop<3, true, LF, VF>(acc, in, in_scale, U, V, site, nb[7], vo);
+    store_spinor<VF>(out, out_scale, site + vo, acc);
 }
 
 // ------------------------------------------------------------ clover build
@@ -593,7 +503,7 @@ template <int LF, int VF>
 static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const float* in_scale, void* out,
                                 float* out_scale, int members, hipStream_t s) {
     using R = typename FineT<LF>::R;
-    const unsigned nb = (unsigned)(((4 * op->V + 255) / 256 + 7) / 8 * 8);   // a multiple of 8 (XCD remap)
+    const unsigned nb = (unsigned)((op->V + 255) / 256);
     hipLaunchKernelGGL((k_wilson_clover<LF, VF>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale, op->nbr,
                        in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0);
     QMG_LAUNCH_CHECK();
