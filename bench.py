@@ -142,6 +142,35 @@ def precision_and_mrhs(steps):
     return out
 
 
+def small_grids(steps=2000):
+    """The smallest coarse grids (the Amdahl limit the fine-grained split is
+    for): 2^4 N48 in FP64 and FP32 (the 8^4 workload's coarse level) and
+    2^3x4 N64 in FP32 (level 2 of 16^3x32), tuned, back-to-back launches.  The
+    operators (5.3 / 2.7 / 9.5 MB) stay in the caches, so the figure is
+    launch-to-launch time, reported against the algorithmic bytes."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import CoarseOp
+    dev = torch.device('cuda')
+    out = []
+    for cd, N, prec, cb in (((2, 2, 2, 2), 48, 'c128', 16), ((2, 2, 2, 2), 48, 'c64', 8), ((2, 2, 2, 4), 64, 'c64', 8)):
+        V = int(np.prod(cd))
+        X = torch.from_numpy(synth.gaussian((V, N, N), 0, 2)).to(dev)
+        Y = torch.from_numpy(synth.gaussian((8, V, N, N), 1, 2)).to(dev)
+        op = CoarseOp(cd, X, Y, prec)
+        dt = torch.complex128 if prec == 'c128' else torch.complex64
+        u = torch.from_numpy(synth.gaussian((V, N), 2, 2)).to(dev).to(dt)
+        y = torch.empty_like(u)
+        op.tune(u, y)
+        ms = timed(lambda i: op.apply(u, y), steps, 200)
+        flops, byts = algorithmic(V, N, 1, cb)
+        out.append({'lattice': list(cd), 'N': N, 'prec': prec, 'us': round(ms * 1e3, 3),
+                    'GFLOP/s': round(flops / ms / 1e6, 1), 'GB/s_algorithmic': round(byts / ms / 1e6, 1),
+                    'launch': list(op.launch()) + [op.prefetch()]})
+    return out
+
+
 def build_mg_16x32(coarse_storage=None, fine_storage=None):
     import numpy as np
     import torch
@@ -330,6 +359,14 @@ def mg_gcr(nsolves=12, nrhs=16):
     out['multi_rhs_fp16_coarse'] = dict(setup_s=round(setup16, 2), **timed_batches(mg16, nrhs, 2, 5000))
     out['multi_rhs_fp16_coarse']['speedup_per_rhs_vs_single_fp32'] = round(
         out['time_to_1e-10_s'] / out['multi_rhs_fp16_coarse']['time_per_rhs_s'], 3)
+    # time per right-hand side against the batch size
+    per = {}
+    for m in (8, 32, 64):
+        r = timed_batches(mg16, m, 1, 7000 + 100 * m)
+        per[str(m)] = {'time_per_rhs_s': r['time_per_rhs_s'], 'outer_iters': r['outer_iters_mean'],
+                       'max_true_rel_residual': r['max_true_rel_residual']}
+    per[str(nrhs)] = {k: out['multi_rhs_fp16_coarse'][k] for k in ('time_per_rhs_s', 'max_true_rel_residual')}
+    out['multi_rhs_fp16_coarse']['by_nrhs'] = per
     return out
 
 
@@ -489,6 +526,7 @@ def main():
     del ops, Xd, Yd
     if not args.only_headline:
         rec.update(precision_and_mrhs(max(100, args.steps // 4)))
+        rec['small_grids'] = small_grids()
         rec['fine_and_transfer'] = fine_and_transfer()
         rec['mg_gcr'] = mg_gcr()
     if not args.no_cpu:
