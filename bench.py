@@ -245,8 +245,11 @@ def timed_solves(mg, nsolves, seed0):
             'max_true_rel_residual': float(max(res)), 'smoother_fallbacks_mean': float(np.mean(fb[1:]))}
 
 
-def learned(npairs, epochs, loss):
-    """Learned-smoother comparison on 16^3x32: pairs from the solver, training on the GPU."""
+def learned(npairs, epochs, loss, source='smoother'):
+    """Learned-smoother comparison on 16^3x32: training data from the solver
+    (source 'smoother': the residuals the level-0 smoother is applied to, for
+    the residual loss; 'iterates': error/residual pairs of the outer
+    iterates), training on the GPU."""
     import numpy as np
     import torch
     import synth
@@ -259,7 +262,11 @@ def learned(npairs, epochs, loss):
     seed = 2000
     while n < npairs:
         b = torch.from_numpy(synth.gaussian((mg.V, 4, 3), seed, 2)).to('cuda')
-        r, e, _ = L.generate_pairs(mg, [b], maxrec=40)
+        if source == 'smoother':
+            r, _ = L.generate_smoother_inputs(mg, [b], maxrec=64)
+            e = r[:0]
+        else:
+            r, e, _ = L.generate_pairs(mg, [b], maxrec=40)
         if loss == 'residual':
             e = e[:0]
         R.append(r)
@@ -287,7 +294,8 @@ def learned(npairs, epochs, loss):
     combo = timed_batches(mg16, 16, 2, 1000)
     mg16.set_smoother(None)
     combo['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo['time_per_rhs_s'], 3)
-    return {'lattice': list(dims), 'm0': m0, 'pairs': int(R.shape[0]), 'pair_seconds': round(t_pairs, 2),
+    return {'lattice': list(dims), 'm0': m0, 'training_data': source, 'pairs': int(R.shape[0]),
+            'pair_seconds': round(t_pairs, 2),
             'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
             'train_seconds': round(t_train, 2), 'mg_with_MR': plain, 'mg_with_learned': withnet,
             'multi_rhs_fp16_coarse_with_learned': combo,
@@ -454,9 +462,10 @@ def main():
     ap.add_argument('--learned', action='store_true', help='learned-smoother comparison on 16^3x32 instead')
     ap.add_argument('--precision-form', action='store_true',
                     help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
-    ap.add_argument('--pairs', type=int, default=512)
+    ap.add_argument('--pairs', type=int, default=1024)
     ap.add_argument('--epochs', type=int, default=4)
     ap.add_argument('--loss', choices=['error', 'residual'], default='residual')
+    ap.add_argument('--pairs-from', choices=['smoother', 'iterates'], default='smoother')
     args = ap.parse_args()
     if args.gpus != 1:
         print('bench.py measures one GPU only: the multigrid hot path is built and timed on a single MI355X; '
@@ -469,7 +478,11 @@ def main():
     from paper_1612_07873_amd import CoarseOp
 
     if args.learned:
-        print(json.dumps({'learned_smoother': learned(args.pairs, args.epochs, args.loss)}), flush=True)
+        if args.pairs_from == 'smoother' and args.loss != 'residual':
+            print('smoother inputs have no error partner: use --loss residual', file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({'learned_smoother': learned(args.pairs, args.epochs, args.loss, args.pairs_from)}),
+              flush=True)
         return
     if args.precision_form:
         print(json.dumps({'precision_form': precision_form()}), flush=True)

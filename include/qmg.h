@@ -413,6 +413,17 @@ qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net);
 qmg_status qmg_mg_gcr_solve_record(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
                                    qmg_solve_info* info, void* xhist, int maxrec, int* nrec, void* stream);
 
+/* Solve as qmg_mg_gcr_solve and keep a copy of every input of the level-0
+ * smoother, in the order they occur: the K-cycle's input residual (before
+ * pre-smoothing) and the residual left after the coarse-grid correction
+ * (before post-smoothing), as DEVICE complex64 [maxrec][V][4][3]; *nrec
+ * (host) receives the count kept (at most maxrec).  These are the residuals a
+ * smoother is applied to, for training a learned smoother (residual form of
+ * the loss).  Needs complex64 inner precision and at least two levels. */
+qmg_status qmg_mg_gcr_solve_record_smoother(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
+                                            qmg_solve_info* info, void* rhist, int maxrec, int* nrec,
+                                            void* stream);
+
 /* Training pairs from recorded iterates: e_k = x* - x_k (computed in FP64),
  * r_k = M e_k (FP64 operator), both written as complex64 [n][V][4][3]
  * (r_out, e_out DEVICE). */

@@ -375,6 +375,20 @@ class Multigrid:
         _lib.check(st, 'qmg_mg_gcr_solve_record')
         return x, hist[:n.value], self._info(info, st)
 
+    def solve_record_smoother(self, b, maxrec, tol=1e-10, maxit=500):
+        """Solve and keep the level-0 smoother inputs (complex64 [n][V][4][3])."""
+        x = torch.empty_like(b)
+        hist = torch.empty((maxrec, self.V, 4, 3), dtype=torch.complex64, device=b.device)
+        sp = _lib.SolveParams(tol=float(tol), restart=10, maxit=int(maxit))
+        info = _lib.SolveInfo()
+        n = ctypes.c_int()
+        st = _lib.lib().qmg_mg_gcr_solve_record_smoother(
+            self._h, _dev_ptr(b, torch.complex128, (self.V, 4, 3), 'b'),
+            _dev_ptr(x, torch.complex128, (self.V, 4, 3), 'x'), ctypes.byref(sp), ctypes.byref(info),
+            ctypes.c_void_p(hist.data_ptr()), int(maxrec), ctypes.byref(n), stream_ptr())
+        _lib.check(st, 'qmg_mg_gcr_solve_record_smoother')
+        return x, hist[:n.value], self._info(info, st)
+
     def make_pairs(self, xstar, hist):
         """(r_k, e_k) = (M (x* - x_k), x* - x_k) as complex64 [n][V][4][3] each."""
         n = hist.shape[0]

@@ -75,6 +75,8 @@ SIGNATURES.update({
                               ctypes.POINTER(c_void_p), c_int, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_gcr_solve': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
                                  ctypes.POINTER(SolveInfo), c_void_p]),
+    'qmg_mg_gcr_solve_record_smoother': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
+                                                 ctypes.POINTER(SolveInfo), c_void_p, c_int, c_int_p, c_void_p]),
     'qmg_mg_gcr_solve_multi': (c_int, [c_void_p, c_void_p, c_void_p, c_int, ctypes.POINTER(SolveParams),
                                        ctypes.POINTER(SolveInfo), c_void_p]),
     'qmg_mg_level': (c_int, [c_void_p, c_int, c_int_p, c_int_p, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p)]),

@@ -88,6 +88,8 @@ struct qmg_mg_s {
     int fallbacks = 0;          // smoother applications that fell back to MR
     void* rec = nullptr;        // recording of outer iterates (complex128 [maxrec][V][12])
     int rec_max = 0, rec_n = 0;
+    void* srec = nullptr;       // recording of level-0 smoother inputs (complex64 [maxrec][V][12])
+    int srec_max = 0, srec_n = 0;
 };
 
 namespace {
@@ -281,12 +283,22 @@ template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void
     return mr<R>(mg, l, r, x);
 }
 
+// keep a copy of a level-0 smoother input when recording (single solves, complex64)
+template <typename R> qmg_status record_smoother_input(qmg_mg_s* mg, const void* v, int64_t n) {
+    if (!mg->srec || mg->srec_n >= mg->srec_max || sizeof(R) != 4) return QMG_OK;
+    const size_t vb = n * sizeof(cpx<float>);
+    QMG_HIP(hipMemcpyAsync((char*)mg->srec + (size_t)mg->srec_n * vb, v, vb, hipMemcpyDeviceToDevice, mg->s));
+    ++mg->srec_n;
+    return QMG_OK;
+}
+
 template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, void* zout) {
     Level& L = mg->lv[l];
     Level& C = mg->lv[l + 1];
     const int64_t n = L.n;
     const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
     const int nl = (int)mg->lv.size();
+    if (l == 0) QMG_TRY(record_smoother_input<R>(mg, rin, n));
     // pre-smoothing; L.mr_r = rin - A zout afterwards
     QMG_TRY(smooth<R>(mg, l, rin, zout));
     QMG_TRY(transfer_restrict(L.T, L.mr_r, C.b, p, mg->nb, mg->s));
@@ -299,6 +311,7 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     // post-smoothing on r - A z
     QMG_TRY(apply_op<R>(mg, l, zout, L.kt));
     QMG_TRY(mg->blas.xmy<R>(rin, L.kt, L.kr2, n));
+    if (l == 0) QMG_TRY(record_smoother_input<R>(mg, L.kr2, n));
     QMG_TRY(smooth<R>(mg, l, L.kr2, L.kx2));
     QMG_TRY(mg->blas.axpy<R>(1.0, L.kx2, zout, n));
     return QMG_OK;
@@ -391,6 +404,7 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
     for (int i = 0; i < 8; ++i) mg->level_iters[i] = 0;
     mg->fallbacks = 0;
     mg->rec_n = 0;
+    mg->srec_n = 0;
     auto t0 = std::chrono::steady_clock::now();
     QMG_TRY(mg->blas.norm2<double>(b, n, mg->dsc + S_BN));
     QMG_TRY(read_scalars(mg, S_BN, 1));
@@ -636,7 +650,7 @@ extern "C" qmg_status qmg_mg_gcr_solve_multi(qmg_mg mg, const void* b, void* x, 
     QMG_TRY(check_solve(mg, b, x, p, "mg_gcr_solve_multi"));
     if (nrhs < 1 || nrhs > Blas::kMaxBatch)
         return fail(QMG_ERR_ARG, "mg_gcr_solve_multi: nrhs %d outside [1, %d]", nrhs, Blas::kMaxBatch);
-    if (mg->rec) return fail(QMG_ERR_STATE, "mg_gcr_solve_multi: recording is for single solves");
+    if (mg->rec || mg->srec) return fail(QMG_ERR_STATE, "mg_gcr_solve_multi: recording is for single solves");
     return run_solve(mg, b, x, nrhs, p, info, stream);
 }
 
@@ -680,6 +694,22 @@ extern "C" qmg_status qmg_mg_gcr_solve_record(qmg_mg mg, const void* b, void* x,
     *nrec = mg->rec_n;
     mg->rec = nullptr;
     mg->rec_max = 0;
+    return st;
+}
+
+extern "C" qmg_status qmg_mg_gcr_solve_record_smoother(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
+                                                       qmg_solve_info* info, void* rhist, int maxrec, int* nrec,
+                                                       void* stream) {
+    if (!rhist || maxrec < 1 || !nrec) return fail(QMG_ERR_ARG, "mg_gcr_solve_record_smoother: bad record buffer");
+    if (!mg) return fail(QMG_ERR_ARG, "mg_gcr_solve_record_smoother: NULL mg");
+    if (mg->inner != QMG_C64) return fail(QMG_ERR_PREC, "mg_gcr_solve_record_smoother: needs complex64 inner precision");
+    if (mg->lv.size() < 2) return fail(QMG_ERR_STATE, "mg_gcr_solve_record_smoother: a single level has no smoother");
+    mg->srec = rhist;
+    mg->srec_max = maxrec;
+    const qmg_status st = qmg_mg_gcr_solve(mg, b, x, p, info, stream);
+    *nrec = mg->srec_n;
+    mg->srec = nullptr;
+    mg->srec_max = 0;
     return st;
 }
 

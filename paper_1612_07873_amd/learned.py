@@ -2,7 +2,10 @@
 
 Pairs: for each right-hand side b the multigrid solve records its outer
 iterates x_k; with the converged x*, e_k = x* - x_k and r_k = M e_k (both made
-by the library, qmg_mg_make_pairs).  Pairs whose error has fallen below
+by the library, qmg_mg_make_pairs).  Alternatively the solve records the
+residuals the level-0 smoother itself is applied to (the K-cycle's input and
+the residual left after the coarse-grid correction), which carry the high
+modes a smoother has to remove; these train the residual form of the loss.  Pairs whose error has fallen below
 `min_rel_err` of |x*| are dropped (they carry little beyond rounding).
 Training: Adam on the loss sum_i |N(r_i) - e_i|^2/|e_i|^2 (or its residual
 form sum_i |r_i - M N(r_i)|^2/|r_i|^2, which asks the network for exactly what
@@ -30,6 +33,19 @@ def generate_pairs(mg, rhs, maxrec=32, min_rel_err=1e-6, tol=1e-10):
         infos.append(info)
         del hist
     return torch.cat(Rs), torch.cat(Es), infos
+
+
+def generate_smoother_inputs(mg, rhs, maxrec=64, tol=1e-10):
+    """The residuals the level-0 smoother is applied to during solves of `rhs`
+    (K-cycle inputs and residuals after the coarse-grid correction), complex64
+    [n][V][4][3], for the residual form of the loss (no error partner)."""
+    Rs, infos = [], []
+    for b in rhs:
+        _, hist, info = mg.solve_record_smoother(b, maxrec, tol=tol)
+        Rs.append(hist.clone())
+        infos.append(info)
+        del hist
+    return torch.cat(Rs), infos
 
 
 def initial_weights(hidden, m0, gen):

@@ -154,3 +154,35 @@ def test_training_on_solver_pairs_and_mg_with_learned_smoother():
     print('residual-trained smoother', info3, 'oracle-M residual %.2e' % tr)
     assert info3['converged'] and tr <= 1e-10
     mg.set_smoother(None)
+
+
+def test_recorded_smoother_inputs_match_the_oracle_kcycle():
+    """The recorded level-0 smoother inputs of a 2-level solve: the first is
+    the K-cycle's input b itself (x0 = 0), the second the residual after the
+    pre-smoother and the coarse-grid correction, which the oracle's K-cycle
+    steps reproduce from the same hierarchy (FP32 inner vs FP64: 1e-4)."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (4, 4, 4, 8), -0.3
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 1)
+    A = wilson.clover_field(U, dims, 1.0)
+    fine = omg.FineLevel(U, A, m0, dims)
+    st = synth.gaussian((6, V, 12), 0, 1)
+    h = omg.Hierarchy(fine, [(2, 2, 2, 2)], [6], [st.reshape(6, -1)], setup_iters=0)
+    mg = Multigrid(dims, dev(U), m0, 1.0, [dict(block=(2, 2, 2, 2), nvec=6, setup_iters=0, smoother_steps=4,
+                                                coarse_tol=0.25, coarse_maxit=100)], [dev(st)], inner='c64')
+    b = synth.gaussian((V, 4, 3), 3, 2)
+    x, R, info = mg.solve_record_smoother(dev(b), 16)
+    assert info['converged'] and R.shape[0] == 16
+    Rh = host(R).reshape(16, -1)
+    assert np.array_equal(Rh[0], b.reshape(-1).astype(np.complex64).astype(np.complex128))
+    K = omg.KCycle(h)
+    r = b.reshape(-1)
+    xs = K.smooth(0, r)
+    rc = h.restrict(0, r - fine.apply(xs))
+    xc, _ = solvers.gcr(h.levels[1].apply, rc, 0.25, 10, 100)
+    xs = xs + h.prolong(0, xc)
+    r2 = r - fine.apply(xs)
+    err = np.linalg.norm(Rh[1] - r2) / np.linalg.norm(r2)
+    print('post-smoother input vs oracle K-cycle: %.2e' % err)
+    assert err <= 1e-4
