@@ -354,6 +354,31 @@ def fine_and_transfer(steps=200):
     return out
 
 
+def plain_gcr(maxit=40000):
+    """The same 16^3x32 system (right-hand side of the first MG solve) solved
+    by plain restarted GCR(10) in FP64 on the fine operator alone (a one-level
+    hierarchy: no preconditioner), to the same 1e-10 true residual."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import Multigrid
+    dims = (16, 16, 16, 32)
+    m0 = -0.25
+    if os.path.exists(MG_M0_FILE):
+        with open(MG_M0_FILE) as f:
+            m0 = float(json.load(f)['m0'])
+    U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to('cuda')
+    mg = Multigrid(dims, U, m0, 1.0, [], [], inner='c64')
+    b = torch.from_numpy(synth.gaussian((mg.V, 4, 3), 0, 2)).to('cuda')
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, info = mg.solve(b, tol=1e-10, maxit=maxit, check=False)
+    torch.cuda.synchronize()
+    return {'solver': 'GCR(10), FP64, no preconditioner', 'time_to_1e-10_s': round(time.perf_counter() - t, 3),
+            'iterations': info['outer_iters'], 'converged': info['converged'],
+            'true_rel_residual': info['true_rel_residual']}
+
+
 def mg_gcr(nsolves=12, nrhs=16):
     mg, U, m0, m0_src, setup = build_mg_16x32()
     out = {'lattice': [16, 16, 16, 32], 'm0': m0, 'm0_source': m0_src,
@@ -361,6 +386,8 @@ def mg_gcr(nsolves=12, nrhs=16):
            'outer': 'fp64 GCR(10)', 'smoother': 'MR(4)', 'setup_s': round(setup, 2)}
     out.update(timed_solves(mg, nsolves, 0))
     del mg
+    out['plain_gcr'] = plain_gcr()
+    out['speedup_vs_plain_gcr'] = round(out['plain_gcr']['time_to_1e-10_s'] / out['time_to_1e-10_s'], 1)
     # mixed precision, several right-hand sides at once: FP16 coarse operators,
     # matrix-core coarse stencils, the same FP64 outer solver and tolerance
     mg16, _, _, _, setup16 = build_mg_16x32(coarse_storage='h16')

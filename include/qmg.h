@@ -402,9 +402,11 @@ qmg_status qmg_ptc_adam_step(qmg_ptc net, float lr, float beta1, float beta2, fl
 void qmg_ptc_destroy(qmg_ptc net);
 
 /* Use `net` (NULL: MR) as the level-0 smoother of an FP32-inner hierarchy.
- * Each application keeps the network's result only if |r - M N(r)| < |r|;
- * otherwise that application uses MR (counted in smoother_fallbacks).  The
- * network is borrowed and must outlive its use. */
+ * Each application takes the network's output d = N(r) with the
+ * minimal-residual step length, x = alpha d, alpha = <M d, r>/|M d|^2 (so
+ * |r - M x| <= |r|); when that step is not usable (M d = 0, NaN/Inf) the
+ * application uses MR instead (counted in smoother_fallbacks).  The network
+ * is borrowed and must outlive its use. */
 qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net);
 
 /* As qmg_mg_gcr_solve, and also copy the iterate x_k after each of the first

@@ -43,6 +43,10 @@ struct Blas {
     // (r may equal rin; the result residual goes to r)
     template <typename R> qmg_status mr_update(const double* s3, const void* rin, void* r, const void* Ar, void* x,
                                                int first, int64_t n);
+    // minimal-residual step along d with Ad = A d, s3 = dot_norm(Ad, r): alpha = <Ad,r>/<Ad,Ad>;
+    // x = alpha d; rout = r - alpha Ad
+    template <typename R> qmg_status dir_step(const double* s3, const void* d, const void* Ad, const void* r, void* x,
+                                              void* rout, int64_t n);
     template <typename R> qmg_status axpy(double a, const void* x, void* y, int64_t n);       // y += a x
     template <typename R> qmg_status xmy(const void* b, const void* ax, void* r, int64_t n);  // r = b - ax
     template <typename Rs, typename Rd> qmg_status convert(const void* src, void* dst, int64_t n);

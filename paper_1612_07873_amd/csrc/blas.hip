@@ -211,6 +211,24 @@ __global__ void k_mr_update(const double* __restrict__ s3, const cpx<R>* rin, cp
     r[i] = rr;
 }
 
+// Minimal-residual step along a given direction d with Ad = A d, from
+// s3 = dot_norm(Ad, r) = [<Ad,Ad>, <Ad,r>.re, <Ad,r>.im]: alpha = <Ad,r>/<Ad,Ad>,
+// x = alpha d, rout = r - alpha Ad (alpha = 0 when <Ad,Ad> = 0).
+template <typename R>
+__global__ void k_dir_step(const double* __restrict__ s3, const cpx<R>* __restrict__ d, const cpx<R>* __restrict__ Ad,
+                           const cpx<R>* __restrict__ r, cpx<R>* __restrict__ x, cpx<R>* __restrict__ rout, int64_t n,
+                           int ss) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(d); QMG_MEMBER_VEC(Ad); QMG_MEMBER_VEC(r); QMG_MEMBER_VEC(x);
+    QMG_MEMBER_VEC(rout);
+    const double den = s3[0];
+    const R ar = den > 0 ? (R)(s3[1] / den) : (R)0, ai = den > 0 ? (R)(s3[2] / den) : (R)0;
+    const cpx<R> dd = d[i], a = Ad[i], rr = r[i];
+    x[i] = cpx<R>{ar * dd.re - ai * dd.im, ar * dd.im + ai * dd.re};
+    rout[i] = cpx<R>{rr.re - (ar * a.re - ai * a.im), rr.im - (ar * a.im + ai * a.re)};
+}
+
 template <typename R>
 __global__ void k_axpy(R a, const cpx<R>* __restrict__ x, cpx<R>* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -473,6 +491,15 @@ qmg_status Blas::mr_update(const double* s3, const void* rin, void* r, const voi
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
+template <typename R>
+qmg_status Blas::dir_step(const double* s3, const void* d, const void* Ad, const void* r, void* x, void* rout,
+                          int64_t n) {
+    hipLaunchKernelGGL(k_dir_step<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, s3, (const cpx<R>*)d,
+                       (const cpx<R>*)Ad, (const cpx<R>*)r, (cpx<R>*)x, (cpx<R>*)rout, n, ss);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
 template <typename R> qmg_status Blas::axpy(double a, const void* x, void* y, int64_t n) {
     hipLaunchKernelGGL(k_axpy<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, (R)a, (const cpx<R>*)x, (cpx<R>*)y, n);
     QMG_LAUNCH_CHECK();
@@ -506,6 +533,8 @@ template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, in
     template qmg_status Blas::gcr_update<R>(const double*, void*, void*, void*, void*, int64_t);           \
     template qmg_status Blas::mr_update<R>(const double*, const void*, void*, const void*, void*, int, int64_t); \
     template qmg_status Blas::axpy<R>(double, const void*, void*, int64_t);                                \
+    template qmg_status Blas::dir_step<R>(const double*, const void*, const void*, const void*, void*, void*, \
+                                          int64_t);                                                        \
     template qmg_status Blas::xmy<R>(const void*, const void*, void*, int64_t);                            \
     template qmg_status Blas::normalize<R>(void*, const double*, int64_t);                                 \
     template qmg_status Blas::gcr_step_small<R>(const void*, const void*, int64_t, int, void*, void*, void*,  \

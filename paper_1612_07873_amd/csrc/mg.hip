@@ -101,7 +101,7 @@ constexpr int S_GCR = 32;     // 3
 constexpr int S_NRM = 36;     // 1
 constexpr int S_MR = 40;      // 3
 constexpr int S_BN = 44;      // 1
-constexpr int S_SM = 48;      // 2: smoother residual norms
+constexpr int S_SM = 48;      // 3: learned-smoother step scalars
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
 
@@ -258,27 +258,28 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
 }
 
 // Level smoother: MR, or on level 0 the learned network when one is attached.
-// The network's result is kept only if it reduces the residual; otherwise
-// (including NaN/Inf from bad weights) MR is used for this application.  In a
-// batch the network runs on every member and is kept only if it reduces every
-// member's residual; each member whose residual grew counts as a fallback.
-// On exit lv.mr_r holds r - A x.
+// The network's output d = N(r) is taken with the minimal-residual step
+// length, x = alpha d with alpha = <A d, r>/|A d|^2, which never raises the
+// residual; if the step is not usable (A d = 0, or NaN/Inf from bad weights)
+// MR is used for this application.  In a batch the network runs on every
+// member and is kept only if its step is usable for every member; each member
+// without a usable step counts as a fallback.  On exit lv.mr_r holds r - A x.
 template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
     if (l == 0 && mg->ptc && sizeof(R) == 4) {
         const size_t vb = L.n * sizeof(cpx<R>);
         for (int k = 0; k < mg->nb; ++k)
-            QMG_TRY(ptc_forward(mg->ptc, (const char*)r + k * vb, (char*)x + k * vb, mg->s));
-        QMG_TRY(apply_op<R>(mg, 0, x, L.mr_Ar));
-        QMG_TRY(mg->blas.xmy<R>(r, L.mr_Ar, L.mr_r, L.n));
-        QMG_TRY(mg->blas.norm2<R>(r, L.n, mg->dsc + S_SM));
-        QMG_TRY(mg->blas.norm2<R>(L.mr_r, L.n, mg->dsc + S_SM + 1));
-        QMG_TRY(read_scalars(mg, S_SM, 2));
-        int worse = 0;
-        for (int k = 0; k < mg->nb; ++k)
-            if (!(hs(mg, k, S_SM + 1) < hs(mg, k, S_SM))) ++worse;
-        if (worse == 0) return QMG_OK;
-        mg->fallbacks += worse;
+            QMG_TRY(ptc_forward(mg->ptc, (const char*)r + k * vb, (char*)L.kt + k * vb, mg->s));
+        QMG_TRY(apply_op<R>(mg, 0, L.kt, L.mr_Ar));
+        QMG_TRY(mg->blas.dot_norm<R>(L.mr_Ar, r, L.n, mg->dsc + S_SM));
+        QMG_TRY(read_scalars(mg, S_SM, 3));
+        int bad = 0;
+        for (int k = 0; k < mg->nb; ++k) {
+            const double den = hs(mg, k, S_SM), re = hs(mg, k, S_SM + 1), im = hs(mg, k, S_SM + 2);
+            if (!(den > 0) || !std::isfinite(den) || !std::isfinite(re) || !std::isfinite(im)) ++bad;
+        }
+        if (bad == 0) return mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n);
+        mg->fallbacks += bad;
     }
     return mr<R>(mg, l, r, x);
 }

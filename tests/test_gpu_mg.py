@@ -194,3 +194,21 @@ def test_precision_form_error_at_every_level(storage):
         parent = coarse.CoarseParent(ref)
     print(storage, 'error against the FP64 oracle per level', ['%.2e' % e for e in errs], 'u=%.2e' % ur)
     assert all(e <= 4 * ur for e in errs)
+
+
+def test_one_level_is_plain_gcr():
+    """With no coarse level the solver is plain FP64 GCR(10) with reliable
+    restarts; on a small well-conditioned system it reaches 1e-10 under the
+    oracle's M, and the oracle's GCR(10) needs the same number of steps (+-2)."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (4, 4, 4, 4), 0.2
+    U, A, fine = problem(dims, 0.4, 3, m0)
+    mg = Multigrid(dims, dev(U), m0, 1.0, [], [], inner='c64')
+    b = synth.gaussian((fine.V, 4, 3), 4, 2)
+    x, info = mg.solve(dev(b), tol=1e-10, maxit=2000)
+    r = b.reshape(-1) - fine.apply(host(x).reshape(-1))
+    tr = solvers.norm(r) / solvers.norm(b.reshape(-1))
+    _, oi = solvers.gcr(fine.apply, b.reshape(-1), 1e-10, 10, 2000)
+    print('plain GCR', info, 'oracle steps', oi.iters, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    assert abs(info['outer_iters'] - oi.iters) <= 2
