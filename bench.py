@@ -171,7 +171,7 @@ def small_grids(steps=2000):
     return out
 
 
-def build_mg_16x32(coarse_storage=None, fine_storage=None):
+def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
     import numpy as np
     import torch
     import synth
@@ -189,7 +189,7 @@ def build_mg_16x32(coarse_storage=None, fine_storage=None):
     levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10,
                    coarse_storage=coarse_storage),
               dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100,
-                   coarse_storage=coarse_storage)]
+                   coarse_storage=coarse_storage, coarse_direct=coarse_direct)]
     starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
               torch.from_numpy(synth.gaussian((32, 512, 48), 1, 1)).to(dev)]
     t0 = time.perf_counter()
@@ -394,6 +394,17 @@ def mg_gcr(nsolves=12, nrhs=16):
     out['multi_rhs_fp16_coarse'] = dict(setup_s=round(setup16, 2), **timed_batches(mg16, nrhs, 2, 5000))
     out['multi_rhs_fp16_coarse']['speedup_per_rhs_vs_single_fp32'] = round(
         out['time_to_1e-10_s'] / out['multi_rhs_fp16_coarse']['time_per_rhs_s'], 3)
+    # the coarsest level solved exactly by its dense inverse (an option: the
+    # paper's coarsest solve is GCR), single and batched
+    mgd, _, _, _, setupd = build_mg_16x32(coarse_direct=True)
+    d = {'setup_s': round(setupd, 2)}
+    d.update(timed_solves(mgd, nsolves, 0))
+    del mgd
+    mgd16, _, _, _, _ = build_mg_16x32(coarse_storage='h16', coarse_direct=True)
+    d['multi_rhs_fp16_coarse'] = timed_batches(mgd16, nrhs, 2, 5000)
+    del mgd16
+    d['speedup_vs_plain_gcr'] = round(out['plain_gcr']['time_to_1e-10_s'] / d['time_to_1e-10_s'], 1)
+    out['direct_coarsest'] = d
     # time per right-hand side against the batch size
     per = {}
     for m in (8, 32, 64):

@@ -294,6 +294,11 @@ typedef struct {
     int coarse_storage;  /* storage of the next level's operator in the solve: 0 = the inner
                             precision, QMG_H16 / QMG_B16 = 16-bit links with FP32 scales
                             (FP32 vectors; inner precision must be QMG_C64) */
+    int coarse_direct;   /* last level entry only: solve the coarsest level exactly with a dense
+                            inverse of its operator, built at setup by Gauss-Jordan elimination
+                            in FP64 (at most 4096 coarsest unknowns) and applied in the inner
+                            precision, instead of the paper's GCR (coarse_tol/coarse_maxit are
+                            then unused); 0 = GCR */
 } qmg_level_params;
 
 typedef struct {
@@ -402,9 +407,9 @@ qmg_status qmg_ptc_adam_step(qmg_ptc net, float lr, float beta1, float beta2, fl
 void qmg_ptc_destroy(qmg_ptc net);
 
 /* Use `net` (NULL: MR) as the level-0 smoother of an FP32-inner hierarchy.
- * Each application takes the network's output d = N(r) with the
- * minimal-residual step length, x = alpha d, alpha = <M d, r>/|M d|^2 (so
- * |r - M x| <= |r|); when that step is not usable (M d = 0, NaN/Inf) the
+ * Each application keeps the network's output d = N(r) only if
+ * |r - M d| < |r|, and then takes it with the minimal-residual step length,
+ * x = alpha d, alpha = <M d, r>/|M d|^2; otherwise (including NaN/Inf) the
  * application uses MR instead (counted in smoother_fallbacks).  The network
  * is borrowed and must outlive its use. */
 qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net);

@@ -103,9 +103,13 @@ class Hierarchy:
 
 class KCycle:
     def __init__(self, hier, smoother_steps=4, inner_tol=0.25, inner_maxit=10,
-                 coarsest_tol=0.25, coarsest_maxit=100, smoother=None):
+                 coarsest_tol=0.25, coarsest_maxit=100, smoother=None, coarsest_direct=False):
         self.h = hier
         self.s = smoother_steps
+        # coarsest_direct: the exact coarse-grid correction on the coarsest
+        # level, x = Mhat^-1 r (a dense LAPACK solve), instead of its GCR
+        self.coarsest_direct = coarsest_direct
+        self._dense = None
         self.inner_tol, self.inner_maxit = inner_tol, inner_maxit
         self.coarsest_tol, self.coarsest_maxit = coarsest_tol, coarsest_maxit
         self.smoother = smoother          # optional replacement for MR on level 0
@@ -124,7 +128,12 @@ class KCycle:
         nl = l + 1
         last = nl == len(self.h.levels) - 1
         info = solvers.SolveInfo()
-        if last:
+        if last and self.coarsest_direct:
+            if self._dense is None:
+                self._dense = self.h.levels[nl].op.dense()
+            xc = np.linalg.solve(self._dense, rc)
+            info.iters = 1
+        elif last:
             xc, info = solvers.gcr(self.h.levels[nl].apply, rc, self.coarsest_tol, 10,
                                    self.coarsest_maxit, info=info)
         else:

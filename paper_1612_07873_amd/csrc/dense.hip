@@ -1,0 +1,235 @@
+// Exact solve of the coarsest level through an explicit inverse (an option of
+// the multigrid solver; the paper's coarsest solve is GCR, Sec. 7.1).  The
+// coarsest operator is small (n = V*N unknowns, at most 4096), so its dense
+// matrix is assembled from X and Y, inverted once at setup by Gauss-Jordan
+// elimination with partial pivoting in FP64, and stored in the solver's inner
+// precision; every coarsest solve is then one matrix-vector product (one
+// matrix-matrix product for a batch), a single launch with no global
+// reductions -- the latency the coarsest GCR spends on synchronisations.
+#include "handles.h"
+
+#include <cmath>
+
+namespace qmg {
+
+// A[(x,i), (x,j)] = X(x)_{ij}; A[(x,i), (nbr_d(x), j)] += Y_d(x)_{ij}.  One
+// thread per (x, i, j), adding the nine blocks of its row in a fixed order (on
+// extent-2 lattices two directions reach the same neighbour).  A starts zeroed.
+__global__ void k_assemble(double2* __restrict__ A, const double2* __restrict__ X, const double2* __restrict__ Y,
+                           const int* __restrict__ nbr, int64_t V, int N) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= V * N * N) return;
+    const int j = (int)(g % N);
+    const int i = (int)((g / N) % N);
+    const int64_t x = g / ((int64_t)N * N);
+    const int64_t n = V * N;
+    double2* row = A + (x * N + i) * n;
+    double2 v = X[(x * N + i) * N + j];
+    row[x * N + j].x += v.x;
+    row[x * N + j].y += v.y;
+    for (int d = 0; d < 8; ++d) {
+        const int64_t y = nbr[x * 8 + d];
+        v = Y[((int64_t)d * V + x) * N * N + (int64_t)i * N + j];
+        row[y * N + j].x += v.x;
+        row[y * N + j].y += v.y;
+    }
+}
+
+// M is n x 2n ([A | I]).  Step k, part 1 (one work-group): the row p >= k of
+// largest |M[p][k]|; stores p and M[p][k].
+__global__ __launch_bounds__(1024) void k_pivot(const double2* __restrict__ M, int n, int k, int* __restrict__ piv,
+                                                double2* __restrict__ pval) {
+    __shared__ double best[1024];
+    __shared__ int where[1024];
+    double b = -1.0;
+    int w = k;
+    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+        const double2 a = M[(int64_t)i * 2 * n + k];
+        const double m = a.x * a.x + a.y * a.y;
+        if (m > b) { b = m; w = i; }
+    }
+    best[threadIdx.x] = b;
+    where[threadIdx.x] = w;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            const double o = best[threadIdx.x + s];
+            const int ow = where[threadIdx.x + s];
+            if (o > best[threadIdx.x] || (o == best[threadIdx.x] && ow < where[threadIdx.x])) {
+                best[threadIdx.x] = o;
+                where[threadIdx.x] = ow;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *piv = where[0];
+        *pval = M[(int64_t)where[0] * 2 * n + k];
+    }
+}
+
+// Part 2: swap rows k and p, divide row k by the pivot; save column k of every
+// row (the elimination factors) before part 3 overwrites it.
+__global__ void k_swap_scale(double2* __restrict__ M, int n, int k, const int* __restrict__ piv,
+                             const double2* __restrict__ pval, int* __restrict__ singular) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= 2 * n) return;
+    const int p = *piv;
+    const double2 pv = *pval;
+    const double den = pv.x * pv.x + pv.y * pv.y;
+    if (c == 0 && !(den > 0)) *singular = 1;
+    const double2 inv = make_double2(pv.x / den, -pv.y / den);
+    double2* rk = M + (int64_t)k * 2 * n;
+    double2* rp = M + (int64_t)p * 2 * n;
+    const double2 t = rp[c];
+    if (p != k) rp[c] = rk[c];
+    rk[c] = make_double2(t.x * inv.x - t.y * inv.y, t.x * inv.y + t.y * inv.x);
+}
+
+__global__ void k_save_col(const double2* __restrict__ M, int n, int k, double2* __restrict__ f) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f[i] = M[(int64_t)i * 2 * n + k];
+}
+
+// Part 3: M[i][c] -= f_i M[k][c] for i != k, columns c >= k (left of k the
+// pivot row is zero).  Grid: (columns, rows).
+__global__ void k_eliminate(double2* __restrict__ M, int n, int k, const double2* __restrict__ f) {
+    const int c = k + blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (c >= 2 * n || i == k) return;
+    const double2 a = f[i];
+    const double2 b = M[(int64_t)k * 2 * n + c];
+    double2& m = M[(int64_t)i * 2 * n + c];
+    m.x -= a.x * b.x - a.y * b.y;
+    m.y -= a.x * b.y + a.y * b.x;
+}
+
+__global__ void k_identity_right(double2* __restrict__ M, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) M[(int64_t)i * 2 * n + n + i] = make_double2(1.0, 0.0);
+}
+
+template <typename R>
+__global__ void k_take_inverse(cpx<R>* __restrict__ inv, const double2* __restrict__ M, int n) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (int64_t)n * n) return;
+    const int64_t i = g / n, j = g % n;
+    const double2 v = M[i * 2 * n + n + j];
+    inv[g] = cpx<R>{(R)v.x, (R)v.y};
+}
+
+// y_m = Ainv b_m for members m of a batch ([nb][n] fields).  One wave per
+// (row, group of up to 8 members): lanes stride the row (coalesced), each
+// keeps one partial per member, then a fixed shuffle tree sums the lanes.
+template <typename R>
+__global__ __launch_bounds__(256) void k_dense_apply(const cpx<R>* __restrict__ Ainv, const cpx<R>* __restrict__ b,
+                                                     cpx<R>* __restrict__ y, int n, int nb) {
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    const int groups = (nb + 7) / 8;
+    if (wave >= n * groups) return;
+    const int row = wave / groups, m0 = (wave % groups) * 8;
+    R ar[8], ai[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) ar[m] = ai[m] = 0;
+    const cpx<R>* a = Ainv + (int64_t)row * n;
+    for (int c = lane; c < n; c += 64) {
+        const cpx<R> v = a[c];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (m0 + m < nb) {
+                const cpx<R> u = b[(int64_t)(m0 + m) * n + c];
+                ar[m] += v.re * u.re - v.im * u.im;
+                ai[m] += v.re * u.im + v.im * u.re;
+            }
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        for (int o = 32; o > 0; o >>= 1) {
+            ar[m] += __shfl_down(ar[m], o, 64);
+            ai[m] += __shfl_down(ai[m], o, 64);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+            if (m0 + m < nb) y[(int64_t)(m0 + m) * n + row] = cpx<R>{ar[m], ai[m]};
+    }
+}
+
+// Build the inverse of the coarse operator in precision `prec` (complex128 or
+// complex64) into *out (allocated here, owned by the caller).  Blocks.
+qmg_status dense_inverse(qmg_coarse_op_s* op, qmg_prec prec, void** out, hipStream_t s) {
+    const int64_t n = op->V * op->N;
+    if (n > 4096) return fail(QMG_ERR_SHAPE, "coarse direct solve: %lld unknowns exceed 4096", (long long)n);
+    const size_t blk = (size_t)op->V * op->N * op->N;
+    double2 *X = nullptr, *Y = nullptr, *M = nullptr, *f = nullptr, *pval = nullptr;
+    int* piv = nullptr;   // piv[0]: pivot row; piv[1]: set when a pivot was zero
+    void* inv = nullptr;
+    const size_t eb = prec == QMG_C128 ? 16 : 8;
+    hipError_t e = hipMalloc(&X, blk * 16);
+    if (e == hipSuccess) e = hipMalloc(&Y, 8 * blk * 16);
+    if (e == hipSuccess) e = hipMalloc(&M, (size_t)n * 2 * n * 16);
+    if (e == hipSuccess) e = hipMalloc(&f, n * 16);
+    if (e == hipSuccess) e = hipMalloc(&pval, 16);
+    if (e == hipSuccess) e = hipMalloc(&piv, 2 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&inv, (size_t)n * n * eb);
+    auto cleanup = [&]() {
+        for (void* p : {(void*)X, (void*)Y, (void*)M, (void*)f, (void*)pval, (void*)piv})
+            if (p) (void)hipFree(p);
+    };
+    if (e != hipSuccess) {
+        cleanup();
+        if (inv) (void)hipFree(inv);
+        return fail(QMG_ERR_NOMEM, "coarse direct solve: %s", hipGetErrorString(e));
+    }
+    qmg_status st = qmg_coarse_op_export(op, X, Y, s);
+    if (st == QMG_OK) {
+        (void)hipMemsetAsync(M, 0, (size_t)n * 2 * n * 16, s);
+        (void)hipMemsetAsync(piv, 0, 2 * sizeof(int), s);
+        const int64_t tot = op->V * op->N * op->N;
+        hipLaunchKernelGGL(k_assemble, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, M, X, Y, op->nbr, op->V, op->N);
+        hipLaunchKernelGGL(k_identity_right, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, (int)n);
+    }
+    for (int k = 0; k < n && st == QMG_OK; ++k) {
+        hipLaunchKernelGGL(k_pivot, dim3(1), dim3(1024), 0, s, M, (int)n, k, piv, pval);
+        hipLaunchKernelGGL(k_swap_scale, dim3((unsigned)((2 * n + 255) / 256)), dim3(256), 0, s, M, (int)n, k, piv, pval,
+                           piv + 1);
+        hipLaunchKernelGGL(k_save_col, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, M, (int)n, k, f);
+        hipLaunchKernelGGL(k_eliminate, dim3((unsigned)((2 * n - k + 255) / 256), (unsigned)n), dim3(256), 0, s, M,
+                           (int)n, k, f);
+        if (hipGetLastError() != hipSuccess) st = fail(QMG_ERR_HIP, "coarse direct solve: launch failed at step %d", k);
+    }
+    if (st == QMG_OK) {
+        const unsigned g = (unsigned)(((int64_t)n * n + 255) / 256);
+        if (prec == QMG_C128) hipLaunchKernelGGL(k_take_inverse<double>, dim3(g), dim3(256), 0, s, (cpx<double>*)inv, M, (int)n);
+        else hipLaunchKernelGGL(k_take_inverse<float>, dim3(g), dim3(256), 0, s, (cpx<float>*)inv, M, (int)n);
+        int sing = 0;
+        e = hipMemcpyAsync(&sing, piv + 1, sizeof(int), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) st = fail(QMG_ERR_HIP, "coarse direct solve: %s", hipGetErrorString(e));
+        else if (sing) st = fail(QMG_ERR_NONFINITE, "coarse direct solve: the coarsest operator is singular");
+    }
+    cleanup();
+    if (st != QMG_OK) {
+        (void)hipFree(inv);
+        return st;
+    }
+    *out = inv;
+    return QMG_OK;
+}
+
+qmg_status dense_apply(const void* Ainv, const void* b, void* y, int64_t n, int nb, qmg_prec prec, hipStream_t s) {
+    const int64_t waves = n * ((nb + 7) / 8);
+    const unsigned g = (unsigned)((waves * 64 + 255) / 256);
+    if (prec == QMG_C128)
+        hipLaunchKernelGGL(k_dense_apply<double>, dim3(g), dim3(256), 0, s, (const cpx<double>*)Ainv,
+                           (const cpx<double>*)b, (cpx<double>*)y, (int)n, nb);
+    else
+        hipLaunchKernelGGL(k_dense_apply<float>, dim3(g), dim3(256), 0, s, (const cpx<float>*)Ainv,
+                           (const cpx<float>*)b, (cpx<float>*)y, (int)n, nb);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+}  // namespace qmg

@@ -43,6 +43,8 @@ qmg_status wilson_apply(const qmg_fine_op_s* op, const void* in, void* out, qmg_
 qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec vprec, int m, void* q16,
                         float* qsc, hipStream_t s);
 bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m);
+qmg_status dense_inverse(qmg_coarse_op_s* op, qmg_prec prec, void** out, hipStream_t s);
+qmg_status dense_apply(const void* Ainv, const void* b, void* y, int64_t n, int nb, qmg_prec prec, hipStream_t s);
 }
 
 using namespace qmg;
@@ -62,6 +64,7 @@ struct Level {
     // K-cycle on this level
     void *mr_r = nullptr, *mr_Ar = nullptr, *kt = nullptr, *kr2 = nullptr, *kx2 = nullptr;
     void *kin = nullptr, *kout = nullptr;  // level 0 only: inner-precision copies
+    void* Ainv = nullptr;           // coarsest level solved exactly: dense inverse [n][n] (inner precision)
     void* q16 = nullptr;            // batched 16-bit stencil input [V][nb][N] (multi-RHS matrix-core path)
     float* qsc = nullptr;           // its scales [V][nb]
 };
@@ -182,6 +185,11 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
                int* iters_out) {
     Level& L = mg->lv[l];
     const int64_t n = L.n;
+    if (L.Ainv) {   // the coarsest level with its dense inverse: x = A^-1 b, one launch
+        QMG_TRY(dense_apply(L.Ainv, b, x, n, mg->nb, sizeof(R) == 8 ? QMG_C128 : QMG_C64, mg->s));
+        if (iters_out) *iters_out += 1;
+        return QMG_OK;
+    }
     const int m = mg->restart;
     const int nb = mg->nb;
     const size_t vb = n * sizeof(cpx<R>);   // one member's field
@@ -258,12 +266,13 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
 }
 
 // Level smoother: MR, or on level 0 the learned network when one is attached.
-// The network's output d = N(r) is taken with the minimal-residual step
-// length, x = alpha d with alpha = <A d, r>/|A d|^2, which never raises the
-// residual; if the step is not usable (A d = 0, or NaN/Inf from bad weights)
-// MR is used for this application.  In a batch the network runs on every
-// member and is kept only if its step is usable for every member; each member
-// without a usable step counts as a fallback.  On exit lv.mr_r holds r - A x.
+// The network's output d = N(r) is kept only if it lowers the residual
+// (|r - A d| < |r|); it is then taken with the minimal-residual step length,
+// x = alpha d with alpha = <A d, r>/|A d|^2, which lowers it further.
+// Otherwise (including NaN/Inf from bad weights) MR is used for this
+// application.  In a batch the network runs on every member and is kept only
+// if it passes for every member; each member that fails counts as a fallback.
+// On exit lv.mr_r holds r - A x.
 template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
     if (l == 0 && mg->ptc && sizeof(R) == 4) {
@@ -275,8 +284,11 @@ template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void
         QMG_TRY(read_scalars(mg, S_SM, 3));
         int bad = 0;
         for (int k = 0; k < mg->nb; ++k) {
+            // kept only if the network's own output lowers the residual:
+            // |r - M d|^2 - |r|^2 = |M d|^2 - 2 Re <M d, r> < 0
             const double den = hs(mg, k, S_SM), re = hs(mg, k, S_SM + 1), im = hs(mg, k, S_SM + 2);
-            if (!(den > 0) || !std::isfinite(den) || !std::isfinite(re) || !std::isfinite(im)) ++bad;
+            const bool ok = den > 0 && std::isfinite(den) && std::isfinite(re) && std::isfinite(im) && den - 2 * re < 0;
+            if (!ok) ++bad;
         }
         if (bad == 0) return mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n);
         mg->fallbacks += bad;
@@ -529,6 +541,8 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
             return fail(QMG_ERR_PREC, "mg_create: coarse_storage %d of level %d", cs, l);
         if (cs != 0 && (inner != QMG_C64 || (2 * lp[l].nvec) % 4))
             return fail(QMG_ERR_PREC, "mg_create: 16-bit coarse storage needs complex64 inner precision and N %% 4 == 0");
+        if (lp[l].coarse_direct && l + 2 != nlevels)
+            return fail(QMG_ERR_ARG, "mg_create: coarse_direct is for the last level entry only (level %d)", l);
     }
     auto* mg = new qmg_mg_s();
     mg->s = as_stream(stream);
@@ -571,6 +585,12 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
     for (int l = 0; l + 1 < nlevels && st == QMG_OK; ++l)
         st = inner == QMG_C128 ? setup_level<double>(mg, l, starts[l], lp[l].setup_iters)
                                : setup_level<float>(mg, l, starts[l], lp[l].setup_iters);
+    // exact coarsest solve: the dense inverse of the full-precision operator
+    if (st == QMG_OK && nlevels > 1 && lp[nlevels - 2].coarse_direct) {
+        Level& C = mg->lv[nlevels - 1];
+        st = dense_inverse(C.op, inner, &C.Ainv, mg->s);
+        if (st == QMG_OK) mg->allocs.push_back(C.Ainv);
+    }
     // 16-bit storage of coarse operators for the solve: every level was built
     // from the full-precision parent above; now convert the flagged ones
     for (int l = 0; l + 1 < nlevels && st == QMG_OK; ++l) {

@@ -212,3 +212,47 @@ def test_one_level_is_plain_gcr():
     print('plain GCR', info, 'oracle steps', oi.iters, 'oracle-M residual %.2e' % tr)
     assert info['converged'] and tr <= 1e-10
     assert abs(info['outer_iters'] - oi.iters) <= 2
+
+
+def test_direct_coarsest_solve_matches_oracle():
+    """Coarsest level solved exactly by the dense inverse built at setup: the
+    FP64 two-level solve takes the oracle's outer step count (+-1) with its
+    exact coarsest solve, and FP32 three levels reach 1e-10 under the
+    oracle's M, in no more outer steps than with the GCR coarsest solve."""
+    from paper_1612_07873_amd import Multigrid, QmgError
+    dims, m0 = (4, 4, 4, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2)], [6]
+    U, A, fine = problem(dims, 0.4, 1, m0)
+    st = starts_for(dims, blocks, nvecs, 0)
+    h = omg.Hierarchy(fine, blocks, nvecs, [s.reshape(nvecs[0], -1) for s in st], setup_iters=0)
+    b = synth.gaussian((fine.V, 4, 3), 0, 2)
+    _, io = omg.solve(h, b.reshape(-1), tol=1e-10, coarsest_direct=True)
+    lv = [dict(L, coarse_direct=True) for L in level_list(blocks, nvecs, 0, [100])]
+    mg = Multigrid(dims, dev(U), m0, 1.0, lv, [dev(s) for s in st], inner='c128')
+    x, info = mg.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('direct coarsest FP64', info, 'oracle', io.iters, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    assert abs(info['outer_iters'] - io.iters) <= 1
+    # three levels in FP32, and a batch
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U, A, fine = problem(dims, 0.3, 2, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 5)]
+    base = level_list(blocks, nvecs, 30, [10, 100])
+    mg_gcr = Multigrid(dims, dev(U), m0, 1.0, base, st, inner='c64')
+    mg_dir = Multigrid(dims, dev(U), m0, 1.0, base[:1] + [dict(base[1], coarse_direct=True)], st, inner='c64')
+    b = synth.gaussian((fine.V, 4, 3), 1, 2)
+    _, ig = mg_gcr.solve(dev(b), tol=1e-10)
+    x, idr = mg_dir.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('3 levels: GCR coarsest', ig, 'direct coarsest', idr, 'oracle-M residual %.2e' % tr)
+    assert idr['converged'] and tr <= 1e-10
+    assert idr['outer_iters'] <= ig['outer_iters']
+    B = np.stack([synth.gaussian((fine.V, 4, 3), 50 + k, 2) for k in range(4)])
+    X, infos = mg_dir.solve_multi(dev(B), tol=1e-10)
+    for k in range(4):
+        r = B[k].reshape(-1) - fine.apply(host(X)[k].reshape(-1))
+        assert solvers.norm(r) <= 1e-10 * solvers.norm(B[k].reshape(-1))
+    with pytest.raises(QmgError):
+        Multigrid(dims, dev(U), m0, 1.0, [dict(base[0], coarse_direct=True), base[1]], st, inner='c64')

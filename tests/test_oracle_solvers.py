@@ -93,3 +93,30 @@ def test_three_level_kcycle_converges():
     assert info.converged
     assert solvers.norm(b - fine.apply(x)) <= 1e-10 * solvers.norm(b)
     assert info.inner_iters[1] > 0 and info.inner_iters[2] > 0
+
+
+def test_exact_coarse_correction_zeroes_the_restricted_residual():
+    """The direct coarsest solve is the exact coarse-grid correction: after
+    x += P Mhat^-1 R r1 the restricted residual R (r1 - A P xc) vanishes,
+    because Mhat = R A P (Galerkin).  A two-level K-cycle built on it
+    converges to 1e-10 against the dense LAPACK solution, in no more outer
+    steps than with the GCR coarsest solve."""
+    fine = small_problem()
+    starts = [synth.gaussian((6, fine.V * 12), 1, 1)]
+    h = mg.Hierarchy(fine, [(2, 2, 2, 2)], [6], starts, setup_iters=20)
+    K = mg.KCycle(h, coarsest_direct=True)
+    r = synth.gaussian(fine.V * 12, 3, 2)
+    xs = K.smooth(0, r)
+    r1 = r - fine.apply(xs)
+    rc = h.restrict(0, r1)
+    xc = np.linalg.solve(h.levels[1].op.dense(), rc)
+    after = h.restrict(0, r1 - fine.apply(h.prolong(0, xc)))
+    assert solvers.norm(after) <= 1e-12 * solvers.norm(rc)
+    b = synth.gaussian(fine.V * 12, 4, 2)
+    x, info = mg.solve(h, b, tol=1e-10, coarsest_direct=True)
+    assert solvers.norm(b - fine.apply(x)) <= 1e-10 * solvers.norm(b)
+    M = wilson.dense_matrix(fine.apply, fine.V * 12)
+    ref = np.linalg.solve(M, b)
+    assert solvers.norm(x - ref) <= np.linalg.cond(M) * 1e-10 * solvers.norm(ref)
+    _, info_gcr = mg.solve(h, b, tol=1e-10)
+    assert info.iters <= info_gcr.iters
