@@ -12,10 +12,11 @@
 
 namespace qmg {
 
-// A[(x,i), (x,j)] = X(x)_{ij}; A[(x,i), (nbr_d(x), j)] += Y_d(x)_{ij}.  One
-// thread per (x, i, j), adding the nine blocks of its row in a fixed order (on
-// extent-2 lattices two directions reach the same neighbour).  A starts zeroed.
-__global__ void k_assemble(double2* __restrict__ A, const double2* __restrict__ X, const double2* __restrict__ Y,
+// A[(x,i), (x,j)] = X(x)_{ij}; A[(x,i), (nbr_d(x), j)] += Y_d(x)_{ij}, into the
+// left half of the n x 2n matrix M = [A | I] (row stride 2n).  One thread per
+// (x, i, j), adding the nine blocks of its row in a fixed order (on extent-2
+// lattices two directions reach the same neighbour).  M starts zeroed.
+__global__ void k_assemble(double2* __restrict__ M, const double2* __restrict__ X, const double2* __restrict__ Y,
                            const int* __restrict__ nbr, int64_t V, int N) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= V * N * N) return;
@@ -23,7 +24,7 @@ __global__ void k_assemble(double2* __restrict__ A, const double2* __restrict__ 
     const int i = (int)((g / N) % N);
     const int64_t x = g / ((int64_t)N * N);
     const int64_t n = V * N;
-    double2* row = A + (x * N + i) * n;
+    double2* row = M + (x * N + i) * 2 * n;
     double2 v = X[(x * N + i) * N + j];
     row[x * N + j].x += v.x;
     row[x * N + j].y += v.y;
