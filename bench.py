@@ -498,6 +498,9 @@ def main():
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle leg')
     ap.add_argument('--only-headline', action='store_true', help='time the headline kernel only')
     ap.add_argument('--learned', action='store_true', help='learned-smoother comparison on 16^3x32 instead')
+    ap.add_argument('--mg-solves', type=int, default=0,
+                    help='only time this many MG-GCR solves on 16^3x32 (after the setup) instead')
+    ap.add_argument('--coarse-direct', action='store_true', help='with --mg-solves: exact coarsest solve')
     ap.add_argument('--precision-form', action='store_true',
                     help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
     ap.add_argument('--pairs', type=int, default=1024)
@@ -521,6 +524,12 @@ def main():
             sys.exit(2)
         print(json.dumps({'learned_smoother': learned(args.pairs, args.epochs, args.loss, args.pairs_from)}),
               flush=True)
+        return
+    if args.mg_solves:
+        mg, _, m0, _, setup = build_mg_16x32(coarse_direct=args.coarse_direct)
+        r = {'lattice': [16, 16, 16, 32], 'm0': m0, 'coarse_direct': args.coarse_direct, 'setup_s': round(setup, 2)}
+        r.update(timed_solves(mg, args.mg_solves, 0))
+        print(json.dumps({'mg_solves': r}), flush=True)
         return
     if args.precision_form:
         print(json.dumps({'precision_form': precision_form()}), flush=True)
