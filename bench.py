@@ -498,6 +498,8 @@ def main():
     ap.add_argument('--no-cpu', action='store_true', help='skip the CPU oracle leg')
     ap.add_argument('--only-headline', action='store_true', help='time the headline kernel only')
     ap.add_argument('--learned', action='store_true', help='learned-smoother comparison on 16^3x32 instead')
+    ap.add_argument('--only-fine', action='store_true',
+                    help='only the Wilson-clover and transfer records (rows a8, a9) instead')
     ap.add_argument('--mg-solves', type=int, default=0,
                     help='only time this many MG-GCR solves on 16^3x32 (after the setup) instead')
     ap.add_argument('--coarse-direct', action='store_true', help='with --mg-solves: exact coarsest solve')
@@ -524,6 +526,9 @@ def main():
             sys.exit(2)
         print(json.dumps({'learned_smoother': learned(args.pairs, args.epochs, args.loss, args.pairs_from)}),
               flush=True)
+        return
+    if args.only_fine:
+        print(json.dumps({'fine_and_transfer': fine_and_transfer()}), flush=True)
         return
     if args.mg_solves:
         mg, _, m0, _, setup = build_mg_16x32(coarse_direct=args.coarse_direct)
