@@ -80,7 +80,7 @@ struct qmg_mg_s {
     double* dsc = nullptr;   // device scalars
     double* hsc = nullptr;   // pinned host mirror
     // outer FP64 workspace (level 0)
-    void *Q64 = nullptr, *Z64 = nullptr, *r64 = nullptr, *x64 = nullptr, *t64 = nullptr;
+    void *Q64 = nullptr, *Z64 = nullptr, *r64 = nullptr, *t64 = nullptr;
     std::vector<void*> allocs;   // setup-time and lifetime allocations
     std::vector<void*> sallocs;  // solve workspace, sized for `cap` batch members
     int cap = 0;                 // batch members the solve workspace holds
