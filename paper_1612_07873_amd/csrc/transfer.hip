@@ -124,102 +124,133 @@ __global__ void k_to_c64(float2* __restrict__ o, const double2* __restrict__ i, 
 }
 
 // Prolongation: one thread per 16-byte chunk of the basis ([x][f][k] row
-// major, so a wave reads one contiguous span); the `cpr` chunks of a row (x, f)
-// are summed in LDS in a fixed order by the row's first thread.
-template <typename R, int CPC>
+// major, so a wave reads one contiguous span).  A work-group covers RPT
+// consecutive spans of rows_per_wg rows; each thread issues its RPT chunk
+// loads before any arithmetic so that enough bytes are in flight to cover
+// HBM latency.  The `cpr` chunks of a row (x, f) are then summed in LDS in a
+// fixed order, one thread per row.
+template <typename R, int CPC, int RPT>
 __global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
                                                  const cpx<R>* __restrict__ uc, const int* __restrict__ owner,
                                                  int64_t V, int dof, int nvec, int rows_per_wg, int64_t cstride) {
-    constexpr int cpc = CPC;                       // complex per chunk
-    __shared__ cpx<R> part[256];
+    constexpr int cpc = CPC;
+    __shared__ cpx<R> part[RPT][256];
     out += (int64_t)blockIdx.y * V * dof;          // batch member
     uc += (int64_t)blockIdx.y * cstride;
     const int cpr = nvec / cpc;                    // chunks per row
     const int t = threadIdx.x;
     const int lr = t / cpr, kc = t - (t / cpr) * cpr;
-    const int64_t row = (int64_t)blockIdx.x * rows_per_wg + lr;
-    const bool active = lr < rows_per_wg && row < V * dof;
-    R ar = 0, ai = 0;
-    if (active) {
-        const int64_t x = row / dof;
-        const int f = (int)(row - x * dof);
-        const int chi = f / (dof / 2);
-        const cpx<R>* u = uc + (int64_t)owner[x] * 2 * nvec + chi * nvec + kc * cpc;
-        const cpx<R>* b = B + row * nvec + kc * cpc;
+    const int64_t rows = V * dof;
+    const int64_t base = (int64_t)blockIdx.x * rows_per_wg * RPT;
+    cpx<R> b[RPT][cpc];
 #pragma unroll
-        for (int q = 0; q < cpc; ++q) cmac(ar, ai, b[q].re, b[q].im, u[q].re, u[q].im);
-    }
-    part[t] = cpx<R>{ar, ai};
-    __syncthreads();
-    if (active && kc == 0) {
-        R sr = 0, si = 0;
-        for (int q = 0; q < cpr; ++q) {
-            sr += part[lr * cpr + q].re;
-            si += part[lr * cpr + q].im;
+    for (int j = 0; j < RPT; ++j) {
+        const int64_t row = base + (int64_t)j * rows_per_wg + lr;
+        if (lr < rows_per_wg && row < rows) {
+#pragma unroll
+            for (int q = 0; q < cpc; ++q) b[j][q] = B[row * nvec + kc * cpc + q];
         }
-        out[row] = cpx<R>{sr, si};
+    }
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+        const int64_t row = base + (int64_t)j * rows_per_wg + lr;
+        R ar = 0, ai = 0;
+        if (lr < rows_per_wg && row < rows) {
+            const int64_t x = row / dof;
+            const int f = (int)(row - x * dof);
+            const int chi = f / (dof / 2);
+            const cpx<R>* u = uc + (int64_t)owner[x] * 2 * nvec + chi * nvec + kc * cpc;
+#pragma unroll
+            for (int q = 0; q < cpc; ++q) cmac(ar, ai, b[j][q].re, b[j][q].im, u[q].re, u[q].im);
+        }
+        part[j][t] = cpx<R>{ar, ai};
+    }
+    __syncthreads();
+    for (int rr = t; rr < rows_per_wg * RPT; rr += 256) {
+        const int j = rr / rows_per_wg, r = rr - j * rows_per_wg;
+        const int64_t row = base + rr;
+        if (row < rows) {
+            R sr = 0, si = 0;
+            for (int q = 0; q < cpr; ++q) {
+                sr += part[j][r * cpr + q].re;
+                si += part[j][r * cpr + q].im;
+            }
+            out[row] = cpx<R>{sr, si};
+        }
     }
 }
 
-// Restriction: one work-group per aggregate; thread q owns chunk q of the
-// per-site basis block (dof x nvec, contiguous), loops over the aggregate's
-// sites accumulating conj(V) psi, then the dof/2 rows of each chirality are
-// summed in LDS in a fixed order.  No atomics; bitwise repeatable.
+// Restriction: one work-group per aggregate.  Thread (slice, q) owns chunk q
+// of the per-site basis block (dof x nvec, contiguous) and accumulates
+// conj(V) psi over the aggregate's sites slice, slice + S, ...; the S slices
+// and then the dof/2 rows of each chirality are summed in LDS in a fixed
+// order.  No atomics; bitwise repeatable.  With S = 1 the threads stride over
+// the chunks instead (blocks with more chunks than threads).
 template <typename R, int CPC>
 __global__ __launch_bounds__(1024) void k_restrict(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
                                                    const cpx<R>* __restrict__ in, const int* __restrict__ members,
-                                                   int dof, int nvec, int bsites, int64_t fstride) {
+                                                   int dof, int nvec, int bsites, int64_t fstride, int S) {
     constexpr int cpc = CPC;
     extern __shared__ __align__(16) unsigned char smem[];
     in += (int64_t)blockIdx.y * fstride;           // batch member
     out += (int64_t)blockIdx.y * gridDim.x * 2 * nvec;
-    cpx<R>* acc_l = reinterpret_cast<cpx<R>*>(smem);   // [dof][nvec]
+    cpx<R>* acc_l = reinterpret_cast<cpx<R>*>(smem);   // [S][dof][nvec]
     const int64_t xc = blockIdx.x;
+    const int* mem = members + xc * bsites;
     const int cpr = nvec / cpc;
     const int nchunk = dof * cpr;
-    for (int q = threadIdx.x; q < nchunk; q += blockDim.x) {
-        const int f = q / cpr, kc = q - (q / cpr) * cpr;
-        R ar[cpc], ai[cpc];
+    const int slice = S > 1 ? (int)threadIdx.x / nchunk : 0;
+    const int q0 = S > 1 ? (int)threadIdx.x - slice * nchunk : (int)threadIdx.x;
+    const int qstep = S > 1 ? nchunk : (int)blockDim.x;
+    if (slice < S) {
+        cpx<R>* acc_s = acc_l + (int64_t)slice * dof * nvec;
+        for (int q = q0; q < nchunk; q += qstep) {
+            const int f = q / cpr, kc = q - (q / cpr) * cpr;
+            R ar[cpc], ai[cpc];
 #pragma unroll
-        for (int c = 0; c < cpc; ++c) ar[c] = ai[c] = 0;
-        int b = 0;
-        for (; b + 4 <= bsites; b += 4) {
-            int64_t x[4];
-            cpx<R> v[4], bb[4][cpc];
+            for (int c = 0; c < cpc; ++c) ar[c] = ai[c] = 0;
+            int b = slice;
+            for (; b + 3 * S < bsites; b += 4 * S) {
+                int64_t x[4];
+                cpx<R> v[4], bb[4][cpc];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                x[j] = members[xc * bsites + b + j];
-                v[j] = in[x[j] * dof + f];
+                for (int j = 0; j < 4; ++j) {
+                    x[j] = mem[b + j * S];
+                    v[j] = in[x[j] * dof + f];
 #pragma unroll
-                for (int c = 0; c < cpc; ++c) bb[j][c] = B[(x[j] * dof + f) * nvec + kc * cpc + c];
+                    for (int c = 0; c < cpc; ++c) bb[j][c] = B[(x[j] * dof + f) * nvec + kc * cpc + c];
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < cpc; ++c)
+                        cmac_conj(ar[c], ai[c], bb[j][c].re, bb[j][c].im, v[j].re, v[j].im);
+            }
+            for (; b < bsites; b += S) {
+                const int64_t x = mem[b];
+                const cpx<R> v = in[x * dof + f];
+#pragma unroll
+                for (int c = 0; c < cpc; ++c) {
+                    const cpx<R> bv = B[(x * dof + f) * nvec + kc * cpc + c];
+                    cmac_conj(ar[c], ai[c], bv.re, bv.im, v.re, v.im);
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-#pragma unroll
-                for (int c = 0; c < cpc; ++c) cmac_conj(ar[c], ai[c], bb[j][c].re, bb[j][c].im, v[j].re, v[j].im);
+            for (int c = 0; c < cpc; ++c) acc_s[f * nvec + kc * cpc + c] = cpx<R>{ar[c], ai[c]};
         }
-        for (; b < bsites; ++b) {
-            const int64_t x = members[xc * bsites + b];
-            const cpx<R> v = in[x * dof + f];
-#pragma unroll
-            for (int c = 0; c < cpc; ++c) {
-                const cpx<R> bv = B[(x * dof + f) * nvec + kc * cpc + c];
-                cmac_conj(ar[c], ai[c], bv.re, bv.im, v.re, v.im);
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < cpc; ++c) acc_l[f * nvec + kc * cpc + c] = cpx<R>{ar[c], ai[c]};
     }
     __syncthreads();
     const int half = dof / 2;
+    const int64_t sstride = (int64_t)dof * nvec;
     for (int n = threadIdx.x; n < 2 * nvec; n += blockDim.x) {
         const int chi = n / nvec, k = n - chi * nvec;
         R sr = 0, si = 0;
-        for (int ff = 0; ff < half; ++ff) {
-            const cpx<R> a = acc_l[(chi * half + ff) * nvec + k];
-            sr += a.re;
-            si += a.im;
-        }
+        for (int ff = 0; ff < half; ++ff)
+            for (int sl = 0; sl < S; ++sl) {
+                const cpx<R> a = acc_l[sl * sstride + (chi * half + ff) * nvec + k];
+                sr += a.re;
+                si += a.im;
+            }
         out[xc * 2 * nvec + n] = cpx<R>{sr, si};
     }
 }
@@ -355,11 +386,13 @@ extern "C" qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* str
 namespace qmg {
 template <typename R, int CPC>
 static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void* out, int nb, hipStream_t s) {
+    constexpr int RPT = 4;
     const int cpr = t->nvec / CPC;
     const int rows_per_wg = 256 / cpr;
     const int64_t rows = t->V * t->dof;
-    const unsigned nblk = (unsigned)((rows + rows_per_wg - 1) / rows_per_wg);
-    hipLaunchKernelGGL((k_prolong<R, CPC>), dim3(nblk, nb), dim3(256), 0, s, (cpx<R>*)out, (const cpx<R>*)B,
+    const int64_t per_wg = (int64_t)rows_per_wg * RPT;
+    const unsigned nblk = (unsigned)((rows + per_wg - 1) / per_wg);
+    hipLaunchKernelGGL((k_prolong<R, CPC, RPT>), dim3(nblk, nb), dim3(256), 0, s, (cpx<R>*)out, (const cpx<R>*)B,
                        (const cpx<R>*)in, t->owner, t->V, t->dof, t->nvec, rows_per_wg, t->Vc * 2 * t->nvec);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
@@ -368,13 +401,22 @@ static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void*
 template <typename R, int CPC>
 static qmg_status restrict_t(qmg_transfer t, const void* B, const void* in, void* out, int nb, hipStream_t s) {
     const int nchunk = t->dof * (t->nvec / CPC);
-    int threads = ((nchunk + 63) / 64) * 64;
+    const size_t lds1 = sizeof(cpx<R>) * t->dof * t->nvec;
+    // site slices per aggregate: as many as fit in 1024 threads and 64 KiB of
+    // LDS, at most 8 and at most the aggregate's sites
+    int S = 1024 / nchunk;
+    if (S > 8) S = 8;
+    if (S > t->bsites) S = t->bsites;
+    while (S > 1 && (size_t)S * lds1 > 65536) --S;
+    if (S < 1) S = 1;
+    int threads = S > 1 ? S * nchunk : nchunk;
+    threads = ((threads + 63) / 64) * 64;
     if (threads > 1024) threads = 1024;
-    const size_t lds = sizeof(cpx<R>) * t->dof * t->nvec;
+    const size_t lds = lds1 * S;
     if (lds > 65536)
         QMG_HIP(hipFuncSetAttribute((const void*)k_restrict<R, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL((k_restrict<R, CPC>), dim3((unsigned)t->Vc, nb), dim3(threads), lds, s, (cpx<R>*)out,
-                       (const cpx<R>*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites, t->V * t->dof);
+                       (const cpx<R>*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites, t->V * t->dof, S);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }

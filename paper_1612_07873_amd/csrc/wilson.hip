@@ -233,7 +233,12 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
                                                        float* __restrict__ out_scale, int64_t V,
                                                        typename FineT<LF>::R diag, int use_clover) {
     using R = typename FineT<LF>::R;
-    const int64_t site = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // Work-groups are dealt to the 8 XCDs round-robin; renumber them so that
+    // each XCD sweeps one contiguous range of sites and the neighbours one
+    // x2-plane away stay in that XCD's L2.  The grid is a multiple of 8.
+    const int64_t per = gridDim.x >> 3;
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t site = wg * blockDim.x + threadIdx.x;
     if (site >= V) return;
     const int64_t vo = (int64_t)blockIdx.y * V;
     const int* nb = nbr + site * 8;
@@ -540,7 +545,7 @@ template <int LF, int VF>
 static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const float* in_scale, void* out,
                                 float* out_scale, int members, hipStream_t s) {
     using R = typename FineT<LF>::R;
-    const unsigned nb = (unsigned)((op->V + 255) / 256);
+    const unsigned nb = (unsigned)(((op->V + 255) / 256 + 7) / 8 * 8);
     hipLaunchKernelGGL((k_wilson_clover<LF, VF>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale, op->nbr,
                        in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0);
     QMG_LAUNCH_CHECK();

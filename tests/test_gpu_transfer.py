@@ -16,6 +16,7 @@ CASES = [  # fine dims, dof, block, nvec
     ((4, 4, 4, 8), 48, (2, 2, 2, 2), 32),          # 4^3x8 level 1 -> 2
     ((4, 6, 2, 4), 12, (2, 3, 1, 2), 3),           # ragged blocks, extent-1 block dims
     ((6, 2, 4, 2), 8, (3, 1, 2, 1), 5),            # coarse parent with N = 8
+    ((4, 4, 4, 6), 12, (2, 2, 2, 3), 1),           # one vector: a prolong work-group spans 1024 rows
 ]
 
 
