@@ -119,33 +119,56 @@ __global__ void k_take_inverse(cpx<R>* __restrict__ inv, const double2* __restri
     inv[g] = cpx<R>{(R)v.x, (R)v.y};
 }
 
-// y_m = Ainv b_m for members m of a batch ([nb][n] fields).  One wave per
-// (row, group of up to 8 members): lanes stride the row (coalesced), each
-// keeps one partial per member, then a fixed shuffle tree sums the lanes.
-template <typename R>
+// y_m = Ainv b_m for members m of a batch ([nb][n] fields).  One work-group
+// per (row, group of up to M members): its 256 threads stride the row, VEC
+// complex numbers per load, four loads issued before any arithmetic so that
+// HBM latency is covered; each thread keeps one partial per member.  Members
+// past the last of a group read the last member's data and are not stored.
+// A shuffle tree per wave and then the four waves in order sum the partials
+// (fixed order, repeatable).
+template <typename R, int VEC, int M>
 __global__ __launch_bounds__(256) void k_dense_apply(const cpx<R>* __restrict__ Ainv, const cpx<R>* __restrict__ b,
                                                      cpx<R>* __restrict__ y, int n, int nb) {
-    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
-    const int lane = threadIdx.x & 63;
-    const int groups = (nb + 7) / 8;
-    if (wave >= n * groups) return;
-    const int row = wave / groups, m0 = (wave % groups) * 8;
-    R ar[8], ai[8];
+    constexpr int U = 4;
+    __shared__ R red[2][M][4];
+    const int groups = (nb + M - 1) / M;
+    const int row = (int)blockIdx.x / groups, m0 = ((int)blockIdx.x % groups) * M;
+    const int nm = nb - m0 < M ? nb - m0 : M;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    R ar[M], ai[M];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) ar[m] = ai[m] = 0;
+    for (int m = 0; m < M; ++m) ar[m] = ai[m] = 0;
     const cpx<R>* a = Ainv + (int64_t)row * n;
-    for (int c = lane; c < n; c += 64) {
-        const cpx<R> v = a[c];
+    for (int c0 = threadIdx.x * VEC; c0 < n; c0 += 256 * VEC * U) {
+        cpx<R> v[U][VEC];
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
-            if (m0 + m < nb) {
-                const cpx<R> u = b[(int64_t)(m0 + m) * n + c];
-                ar[m] += v.re * u.re - v.im * u.im;
-                ai[m] += v.re * u.im + v.im * u.re;
+        for (int j = 0; j < U; ++j) {
+            const int c = c0 + j * 256 * VEC;
+#pragma unroll
+            for (int q = 0; q < VEC; ++q) v[j][q] = c < n ? a[c + q] : cpx<R>{0, 0};
+        }
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const int mm = m < nm ? m0 + m : m0 + nm - 1;
+            const cpx<R>* bm = b + (int64_t)mm * n;
+            cpx<R> u[U][VEC];
+#pragma unroll
+            for (int j = 0; j < U; ++j) {
+                const int c = c0 + j * 256 * VEC;
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) u[j][q] = c < n ? bm[c + q] : cpx<R>{0, 0};
             }
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+#pragma unroll
+                for (int q = 0; q < VEC; ++q) {
+                    ar[m] += v[j][q].re * u[j][q].re - v[j][q].im * u[j][q].im;
+                    ai[m] += v[j][q].re * u[j][q].im + v[j][q].im * u[j][q].re;
+                }
+        }
     }
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
+    for (int m = 0; m < M; ++m) {
         for (int o = 32; o > 0; o >>= 1) {
             ar[m] += __shfl_down(ar[m], o, 64);
             ai[m] += __shfl_down(ai[m], o, 64);
@@ -153,8 +176,17 @@ __global__ __launch_bounds__(256) void k_dense_apply(const cpx<R>* __restrict__ 
     }
     if (lane == 0) {
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
-            if (m0 + m < nb) y[(int64_t)(m0 + m) * n + row] = cpx<R>{ar[m], ai[m]};
+        for (int m = 0; m < M; ++m) {
+            red[0][m][w] = ar[m];
+            red[1][m][w] = ai[m];
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nm) {
+        const int m = threadIdx.x;
+        const R re = ((red[0][m][0] + red[0][m][1]) + red[0][m][2]) + red[0][m][3];
+        const R im = ((red[1][m][0] + red[1][m][1]) + red[1][m][2]) + red[1][m][3];
+        y[(int64_t)(m0 + m) * n + row] = cpx<R>{re, im};
     }
 }
 
@@ -220,15 +252,20 @@ qmg_status dense_inverse(qmg_coarse_op_s* op, qmg_prec prec, void** out, hipStre
     return QMG_OK;
 }
 
-qmg_status dense_apply(const void* Ainv, const void* b, void* y, int64_t n, int nb, qmg_prec prec, hipStream_t s) {
-    const int64_t waves = n * ((nb + 7) / 8);
-    const unsigned g = (unsigned)((waves * 64 + 255) / 256);
-    if (prec == QMG_C128)
-        hipLaunchKernelGGL(k_dense_apply<double>, dim3(g), dim3(256), 0, s, (const cpx<double>*)Ainv,
-                           (const cpx<double>*)b, (cpx<double>*)y, (int)n, nb);
+template <typename R, int VEC>
+static void dense_apply_t(const void* Ainv, const void* b, void* y, int64_t n, int nb, hipStream_t s) {
+    if (nb == 1)
+        hipLaunchKernelGGL((k_dense_apply<R, VEC, 1>), dim3((unsigned)n), dim3(256), 0, s, (const cpx<R>*)Ainv,
+                           (const cpx<R>*)b, (cpx<R>*)y, (int)n, nb);
     else
-        hipLaunchKernelGGL(k_dense_apply<float>, dim3(g), dim3(256), 0, s, (const cpx<float>*)Ainv,
-                           (const cpx<float>*)b, (cpx<float>*)y, (int)n, nb);
+        hipLaunchKernelGGL((k_dense_apply<R, VEC, 8>), dim3((unsigned)(n * ((nb + 7) / 8))), dim3(256), 0, s,
+                           (const cpx<R>*)Ainv, (const cpx<R>*)b, (cpx<R>*)y, (int)n, nb);
+}
+
+qmg_status dense_apply(const void* Ainv, const void* b, void* y, int64_t n, int nb, qmg_prec prec, hipStream_t s) {
+    if (prec == QMG_C128) dense_apply_t<double, 1>(Ainv, b, y, n, nb, s);
+    else if (n % 2 == 0) dense_apply_t<float, 2>(Ainv, b, y, n, nb, s);
+    else dense_apply_t<float, 1>(Ainv, b, y, n, nb, s);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
