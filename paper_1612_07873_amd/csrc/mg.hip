@@ -222,6 +222,12 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     int iters = 0;
     bool done = false;
     const int64_t ld = (int64_t)nb * n;
+    // With tol = 0 (the setup's relaxation) only a breakdown (q = 0) or a
+    // non-finite value can end the iteration early.  After a breakdown every
+    // later step of the cycle is a no-op (the update skips q = 0 and the next
+    // q is 0 again), so reading the scalars only at the end of a cycle stops
+    // with the same x while saving a host round trip per step.
+    const bool defer = !(tol > 0.0);
     // short unpreconditioned systems (the coarsest level): the whole step's
     // vector work is one single-work-group kernel per member, so a step is two launches
     const bool small = !precond && n <= Blas::kSmall;
@@ -236,8 +242,9 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
                 QMG_TRY(apply_op<R>(mg, l, z, q));
                 void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * bb : nullptr;
                 QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, ld, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext));
-                QMG_TRY(read_scalars(mg, S_GCR, 4));
                 ++iters;
+                if (defer && j + 1 < m && iters < maxit) continue;
+                QMG_TRY(read_scalars(mg, S_GCR, 4));
                 done = all_done(S_GCR + 3, &fault);
                 if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
                 if (done) { ++j; break; }
@@ -249,9 +256,10 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
             QMG_TRY(orthogonalize<R>(mg, L.Q, L.Z, ld, j, q, z, n));
             QMG_TRY(mg->blas.dot_norm<R>(q, L.r, n, mg->dsc + S_GCR));
             QMG_TRY(mg->blas.gcr_update<R>(mg->dsc + S_GCR, q, z, x, L.r, n));
+            ++iters;
+            if (defer && j + 1 < m && iters < maxit) continue;
             QMG_TRY(mg->blas.norm2<R>(L.r, n, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
-            ++iters;
             done = all_done(S_NRM, &fault);
             if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
             if (done) { ++j; break; }
