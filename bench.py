@@ -503,6 +503,8 @@ def main():
     ap.add_argument('--mg-solves', type=int, default=0,
                     help='only time this many MG-GCR solves on 16^3x32 (after the setup) instead')
     ap.add_argument('--coarse-direct', action='store_true', help='with --mg-solves: exact coarsest solve')
+    ap.add_argument('--only-16bit', action='store_true',
+                    help='only the 16-bit single-RHS and multi-RHS matrix-core records (rows a6, a7) instead')
     ap.add_argument('--precision-form', action='store_true',
                     help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
     ap.add_argument('--pairs', type=int, default=1024)
@@ -529,6 +531,9 @@ def main():
         return
     if args.only_fine:
         print(json.dumps({'fine_and_transfer': fine_and_transfer()}), flush=True)
+        return
+    if args.only_16bit:
+        print(json.dumps(precision_and_mrhs(args.steps)), flush=True)
         return
     if args.mg_solves:
         mg, _, m0, _, setup = build_mg_16x32(coarse_direct=args.coarse_direct)

@@ -47,6 +47,15 @@ def test_mrhs_parity(cd, N, nrhs):
         assert emax <= 1e-5
 
 
+@pytest.mark.parametrize('cd,N', [((3, 3, 2, 2), 32), ((3, 2, 3, 3), 16)])
+def test_mrhs_site_count_not_a_multiple_of_8(cd, N):
+    """36 and 54 sites, N = 32 and 16: site counts and operator sizes off
+    the shapes of the other cases."""
+    for nrhs in (16, 64):
+        err, emax, *_ = run_case(cd, N, nrhs, 'h16', seed=5)
+        assert emax <= 1e-5, (cd, N, nrhs, emax)
+
+
 @pytest.mark.parametrize('tiles', [1, 2, 4])
 def test_every_tile_shape(tiles):
     err, emax, *_ = run_case((2, 2, 2, 4), 64, 64, 'h16', tiles=tiles, seed=3)
