@@ -14,9 +14,10 @@
 // eight Y_d, and X split into its eight inside-hop sums and the on-site sum
 // (written to separate slots and added in a fixed order afterwards, so the
 // build is deterministic and needs no atomics).  For every contributing fine
-// site the work-group first forms W = H Pf(x') in LDS, then each thread adds
-// Pf(x)^+ W to the N x N entries it owns.  All arithmetic is FP64.  This is
-// setup work, done once per hierarchy.
+// site the work-group first forms the parent's block H (dof x dof) in LDS,
+// then W = H Pf(x') in LDS, then each thread adds Pf(x)^+ W to the N x N
+// entries it owns.  All arithmetic is FP64.  This is setup work, done once
+// per hierarchy.
 #include "handles.h"
 
 #include <vector>
@@ -87,10 +88,11 @@ __global__ __launch_bounds__(1024) void k_galerkin(double2* __restrict__ Yout, d
                                                    const void* __restrict__ parent_b,
                                                    const int* __restrict__ nbr, const double2* __restrict__ B,
                                                    const int* __restrict__ members, const int* __restrict__ owner,
-                                                   int64_t Vc, int dof, int nvec, int bsites, Proj P) {
+                                                   int64_t Vc, int dof, int nvec, int bsites, Proj P, int hlds) {
     extern __shared__ __align__(16) unsigned char smem[];
-    cpx<double>* W = reinterpret_cast<cpx<double>*>(smem);  // [dof][N]
     const int N = 2 * nvec, half = dof / 2;
+    cpx<double>* W = reinterpret_cast<cpx<double>*>(smem);  // [dof][N]
+    cpx<double>* H = W + dof * N;                           // [dof][dof]
     const int64_t xc = blockIdx.x / 17;
     const int term = (int)(blockIdx.x % 17);
     const bool isY = term < 8;
@@ -108,19 +110,25 @@ __global__ __launch_bounds__(1024) void k_galerkin(double2* __restrict__ Yout, d
             const bool inside = owner[xn] == xc;
             if (isY == inside) continue;  // Y wants hops leaving the aggregate, X the ones inside
         }
-        // W[f][m] = sum_{g in chi(m)} H[f][g] Pf(xn)[g][m'] ; Pf(xn)[g][m'] = B[xn][g][m']
+        // the parent's block H[f][g] for this (x, term), once (when it fits
+        // in LDS; otherwise each element is formed where it is used)
+        auto Hfg = [&](int f, int g) {
+            return FINE ? fine_H<R>(fop, (const cpx<R>*)parent_a, (const R*)parent_b, P, hterm, x, xn, f, g)
+                        : coarse_H<R>(cop, (const R*)parent_a, hterm, x, f, g);
+        };
         __syncthreads();
+        if (hlds) {
+            for (int e = threadIdx.x; e < dof * dof; e += T) H[e] = Hfg(e / dof, e % dof);
+            __syncthreads();
+        }
+        // W[f][m] = sum_{g in chi(m)} H[f][g] Pf(xn)[g][m'] ; Pf(xn)[g][m'] = B[xn][g][m']
         for (int e = threadIdx.x; e < dof * N; e += T) {
             const int f = e / N, m = e % N;
             const int chi = m / nvec, mp = m - chi * nvec;
             cpx<double> w = {0.0, 0.0};
             for (int gg = 0; gg < half; ++gg) {
                 const int g = chi * half + gg;
-                cpx<double> h;
-                if (FINE)
-                    h = fine_H<R>(fop, (const cpx<R>*)parent_a, (const R*)parent_b, P, hterm, x, xn, f, g);
-                else
-                    h = coarse_H<R>(cop, (const R*)parent_a, hterm, x, f, g);
+                const cpx<double> h = hlds ? H[f * dof + g] : Hfg(f, g);
                 const double2 bv = B[(xn * dof + g) * nvec + mp];
                 cmac(w.re, w.im, h.re, h.im, bv.x, bv.y);
             }
@@ -226,8 +234,24 @@ extern "C" qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_
         cleanup();
         return fail(QMG_ERR_SHAPE, "build_coarse_op: N=%d too large", N);
     }
-    const size_t lds = sizeof(cpx<double>) * pdof * N;
+    // W [pdof][N], then H [pdof][pdof] when both fit in 64 KiB (the fine
+    // parent: 11.5 KiB); a larger block would cost more in occupancy than it
+    // saves (measured on a 48 -> 64 coarse parent: 2.2 ms with H formed in
+    // place, 2.75 ms with it in LDS)
+    const int hlds = sizeof(cpx<double>) * ((size_t)pdof * N + (size_t)pdof * pdof) <= 65536 ? 1 : 0;
+    const size_t lds = sizeof(cpx<double>) * ((size_t)pdof * N + (hlds ? (size_t)pdof * pdof : 0));
     const dim3 grid((unsigned)(Vc * 17));
+    if (lds > 65536) {
+        const void* kern = fine ? (fine->storage == QMG_C128 ? (const void*)k_galerkin<true, double>
+                                                              : (const void*)k_galerkin<true, float>)
+                                : (parent->storage == QMG_C128 ? (const void*)k_galerkin<false, double>
+                                                               : (const void*)k_galerkin<false, float>);
+        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            cleanup();
+            return fail(QMG_ERR_HIP, "build_coarse_op: %s", hipGetErrorString(e));
+        }
+    }
     const Proj P = projectors();
     qmg_fine_op_s fop{};
     qmg_coarse_op_s cop{};
@@ -236,21 +260,21 @@ extern "C" qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_
         if (fine->storage == QMG_C128)
             hipLaunchKernelGGL((k_galerkin<true, double>), grid, dim3(threads), lds, s, Y, Xp, fop, cop, fine->U,
                                fine->clov, fine->nbr, t->basis64, t->members, t->owner, Vc, pdof, t->nvec,
-                               t->bsites, P);
+                               t->bsites, P, hlds);
         else
             hipLaunchKernelGGL((k_galerkin<true, float>), grid, dim3(threads), lds, s, Y, Xp, fop, cop, fine->U,
                                fine->clov, fine->nbr, t->basis64, t->members, t->owner, Vc, pdof, t->nvec,
-                               t->bsites, P);
+                               t->bsites, P, hlds);
     } else {
         cop = *parent;
         if (parent->storage == QMG_C128)
             hipLaunchKernelGGL((k_galerkin<false, double>), grid, dim3(threads), lds, s, Y, Xp, fop, cop,
                                parent->links, nullptr, parent->nbr, t->basis64, t->members, t->owner, Vc, pdof,
-                               t->nvec, t->bsites, P);
+                               t->nvec, t->bsites, P, hlds);
         else
             hipLaunchKernelGGL((k_galerkin<false, float>), grid, dim3(threads), lds, s, Y, Xp, fop, cop,
                                parent->links, nullptr, parent->nbr, t->basis64, t->members, t->owner, Vc, pdof,
-                               t->nvec, t->bsites, P);
+                               t->nvec, t->bsites, P, hlds);
     }
     hipLaunchKernelGGL(k_sum_xparts, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, X, Xp, (int64_t)blk);
     e = hipGetLastError();

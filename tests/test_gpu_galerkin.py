@@ -74,6 +74,27 @@ def test_coarse_parent_recursion():
         assert err <= tol
 
 
+def test_coarse_parent_block_too_large_for_lds():
+    """A parent with N = 96 and 16 vectors (its block is formed element by
+    element where it is used, not staged in LDS), a shape off the
+    hierarchy's."""
+    from paper_1612_07873_amd import CoarseOp, Transfer, build_coarse_op
+    cd, N, block = (4, 4, 2, 2), 96, (2, 2, 1, 1)
+    Vc = lattice.volume(cd)
+    X1 = synth.gaussian((Vc, N, N), 11, 2)
+    Y1 = synth.gaussian((8, Vc, N, N), 12, 2)
+    op1 = coarse.CoarseOp(cd, X1, Y1)
+    vecs = synth.gaussian((16, Vc, N), 13, 1)
+    Vb = transfer.block_orthonormalize(vecs, cd, block)
+    ref = coarse.galerkin(coarse.CoarseParent(op1), Vb, block)
+    g1 = CoarseOp(cd, dev(X1), dev(Y1), 'c128')
+    op2 = build_coarse_op(Transfer(cd, N, block, dev(vecs)), parent=g1, storage='c128')
+    X, Y = op2.export()
+    err = max(rel_err(host(X), ref.X), rel_err(host(Y), ref.Y))
+    print('N=96 parent rel err %.3e' % err)
+    assert err <= 1e-12
+
+
 def test_config2_full_size_sampled_sites():
     """16^3x32 -> 4^3x8 (Nvec 24): GPU build of all 512 coarse sites, eight of
     them recomputed one by one by the oracle."""
