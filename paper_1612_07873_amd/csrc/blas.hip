@@ -119,16 +119,25 @@ __global__ __launch_bounds__(1024) void k_multi_dot(const cpx<R>* __restrict__ Q
     double re[16], im[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) re[j] = im[j] = 0;
+    // unconditional loads in blocks of CW slots (slots past the last one
+    // re-read it and are not used), so a block's loads are in flight together
+    constexpr int CW = sizeof(R) == 8 ? 8 : 16;
+    const int kc = k - 1;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const cpx<R> y = q[i];
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            if (j < k) {
-                const cpx<R> x = Q[j * ld + i];
-                re[j] += (double)x.re * y.re + (double)x.im * y.im;
-                im[j] += (double)x.re * y.im - (double)x.im * y.re;
+        for (int j0 = 0; j0 < 16; j0 += CW)
+            if (j0 < k) {
+                cpx<R> x[CW];
+#pragma unroll
+                for (int j = 0; j < CW; ++j) x[j] = Q[(int64_t)(j0 + j < k ? j0 + j : kc) * ld + i];
+#pragma unroll
+                for (int j = 0; j < CW; ++j)
+                    if (j0 + j < k) {
+                        re[j0 + j] += (double)x[j].re * y.re + (double)x[j].im * y.im;
+                        im[j0 + j] += (double)x[j].re * y.im - (double)x[j].im * y.re;
+                    }
             }
-        }
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
