@@ -105,6 +105,8 @@ constexpr int S_NRM = 36;     // 1
 constexpr int S_MR = 40;      // 3
 constexpr int S_BN = 44;      // 1
 constexpr int S_SM = 48;      // 3: learned-smoother step scalars
+constexpr int S_OK = 52;      // 2: single-work-group GCR steps: stopping test passed, steps done
+constexpr int kCheck = 4;     // such steps queued per host read of the scalars
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
 
@@ -231,6 +233,8 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     // short unpreconditioned systems (the coarsest level): the whole step's
     // vector work is one single-work-group kernel per member, so a step is two launches
     const bool small = !precond && n <= Blas::kSmall;
+    if (small)   // stopping-test flags and step counters of every member
+        QMG_HIP(hipMemset2DAsync(mg->dsc + S_OK, sizeof(double) * kScal, 0, 2 * sizeof(double), nb, mg->s));
     while (!done && iters < maxit) {
         int j = 0;
         if (small) QMG_HIP(hipMemcpyAsync(L.Z, L.r, bb, hipMemcpyDeviceToDevice, mg->s));
@@ -239,13 +243,22 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
             void* q = (char*)L.Q + j * bb;
             bool fault = false;
             if (small) {
+                // the step evaluates the stopping test itself (a step queued
+                // after every member has passed it does nothing), so the
+                // scalars are read every kCheck steps and at the end of a cycle
                 QMG_TRY(apply_op<R>(mg, l, z, q));
                 void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * bb : nullptr;
-                QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, ld, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext));
+                QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, ld, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext,
+                                                   tol > 0.0 ? tol : 0.0, S_OK - S_GCR, S_BN - S_GCR));
                 ++iters;
-                if (defer && j + 1 < m && iters < maxit) continue;
-                QMG_TRY(read_scalars(mg, S_GCR, 4));
-                done = all_done(S_GCR + 3, &fault);
+                if ((defer || iters % kCheck) && j + 1 < m && iters < maxit) continue;
+                QMG_TRY(read_scalars(mg, S_GCR, S_OK + 2 - S_GCR));
+                iters = (int)hs(mg, 0, S_OK + 1);   // steps that ran (the same for every member)
+                done = true;
+                for (int b = 0; b < nb; ++b) {
+                    if (!std::isfinite(hs(mg, b, S_GCR + 3)) || !std::isfinite(hs(mg, b, S_GCR))) fault = true;
+                    done = done && hs(mg, b, S_OK) != 0.0;
+                }
                 if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
                 if (done) { ++j; break; }
                 continue;
