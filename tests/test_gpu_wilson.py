@@ -147,6 +147,37 @@ def test_sixteen_bit_fine_operator(fmt, dims):
     assert np.allclose(ysh, np.maximum(np.abs(exact16.real), np.abs(exact16.imag)).max(axis=1), rtol=1e-5)
 
 
+@pytest.mark.parametrize('fmt', ['h16'])
+def test_precision_form_fine_operator_full_size(fmt):
+    """The 32^3x64 precision-form fine operator (16-bit links and clover) at
+    its full size, on 64 sampled sites the oracle computes one by one: with
+    FP32 vectors and with 16-bit vectors, the result stays within the storage
+    bound of the 16-bit tests above (4u / 5u, norm-wise over the sample)
+    against the FP64 oracle on unrounded inputs; every stored link component
+    lies within u of the link."""
+    from paper_1612_07873_amd import FineOp, dequantize_sites, quantize_sites
+    dims, m0, eps = (32, 32, 32, 64), -0.18, 0.3
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, eps, 0)
+    psi = synth.gaussian((V, 4, 3), 7, 2)
+    sites = np.sort(np.random.default_rng(3).choice(V, 64, replace=False))
+    ref = wilson.apply_wilson_clover_sites(psi, U, 1.0, m0, dims, sites).reshape(len(sites), 12)
+    op = FineOp(dims, dev(U), m0, 1.0, True, fmt)
+    ur = U_ROUND[fmt]
+    Uq = op.links()
+    Ud = dev(U)
+    assert float((Uq.real - Ud.real).abs().max()) <= ur and float((Uq.imag - Ud.imag).abs().max()) <= ur
+    del Uq, Ud
+    y = host(op.apply(dev(psi, torch.complex64))).reshape(V, 12)[sites]
+    e32 = float(np.linalg.norm(y - ref) / np.linalg.norm(ref))
+    uq, us = quantize_sites(dev(psi.reshape(V, 12), torch.complex64), fmt)
+    yq, ys = op.apply_scaled(uq, us)
+    y16 = host(dequantize_sites(yq, ys, fmt))[sites]
+    e16 = float(np.linalg.norm(y16 - ref) / np.linalg.norm(ref))
+    print('%s %s sampled sites: %.2e (fp32 vectors) %.2e (16-bit vectors), u=%.2e' % (dims, fmt, e32, e16, ur))
+    assert e32 <= 4 * ur and e16 <= 5 * ur
+
+
 def test_sixteen_bit_fine_operator_errors():
     """complex128 vectors do not fit a 16-bit operator; 16-bit vectors need the scaled entry point."""
     import ctypes
