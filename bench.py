@@ -134,7 +134,7 @@ def precision_and_mrhs(steps):
                 op.tune_mrhs(q, s, y, cold=True)
             ms = timed(lambda i: ops[i % len(ops)].apply_mrhs(q, s, y), max(20, steps // 4), 5)
             out['multi_rhs'].append({'lattice': list(cd), 'N': N, 'nrhs': nrhs, 'ms': round(ms, 5),
-                                     'rhs_tiles_per_wave': 'tuned',
+                                     'tiles_tuned': ops[0].mrhs_tiles(nrhs),
                                      'GFLOP/s': round(flops / ms / 1e6, 1), 'GB/s': round(byts / ms / 1e6, 1),
                                      'hbm_frac': round(byts / ms / 1e6 / HBM_PEAK_GBS, 4),
                                      'mfma_frac_fp16': round(flops / ms / 1e9 / 2500.0, 4)})

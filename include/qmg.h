@@ -147,8 +147,15 @@ qmg_status qmg_coarse_dslash_mrhs_multi(int nops, const qmg_coarse_op* ops, cons
                                         void* stream);
 
 /* Tile shape of the multi-RHS kernel: each wave computes 16 rows x
- * (16 * rhs_tiles_per_wave) right-hand sides (1, 2 or 4; 0 = built-in). */
+ * (16 * rhs_tiles_per_wave) right-hand sides (1, 2 or 4; 0 = built-in), the
+ * nine directions in turn through two LDS buffers; 8 selects the whole-site
+ * form instead (each wave 16 rows x all right-hand sides, the link operands
+ * of all nine directions in registers and all nine input blocks in LDS at
+ * once, so a site waits for memory once).  QMG_ERR_ARG for other values or
+ * for 2 / 4 tiles beyond nrhs / 16. */
 qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, int rhs_tiles_per_wave);
+/* The tile code in use for nrhs (set, tuned or built-in default) into *tiles. */
+qmg_status qmg_coarse_op_get_mrhs_tiles(qmg_coarse_op op, int nrhs, int* tiles);
 
 /* Launch shape of the fine-grained stencil (Sec. 6.2-6.4): each work-group
  * covers `rows` output rows of one coarse site (rows divides N), and the

@@ -85,6 +85,11 @@ class CoarseOp:
     def set_mrhs_tiles(self, nrhs, tiles):
         _lib.call('qmg_coarse_op_set_mrhs_tiles', self._h, int(nrhs), int(tiles))
 
+    def mrhs_tiles(self, nrhs):
+        t = ctypes.c_int()
+        _lib.call('qmg_coarse_op_get_mrhs_tiles', self._h, int(nrhs), ctypes.byref(t))
+        return t.value
+
     def apply_scaled(self, u16, uscale, out16=None, oscale=None, vprec=None):
         """16-bit vectors: u16 int32 tensor [V][N] (packed pairs), uscale float32 [V]."""
         vprec = vprec or self.storage

@@ -30,6 +30,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_float)]),
     'qmg_coarse_dslash_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_mrhs_tiles': (c_int, [c_void_p, c_int, c_int]),
+    'qmg_coarse_op_get_mrhs_tiles': (c_int, [c_void_p, c_int, c_int_p]),
     'qmg_coarse_dslash_mrhs_multi': (c_int, [c_int, ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p),
                                              ctypes.POINTER(c_void_p), ctypes.POINTER(c_void_p), c_int, c_int, c_void_p]),
     'qmg_coarse_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),

@@ -198,6 +198,105 @@ __global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 6
     mrhs_site<F, N, NRHS, RPW>(blockIdx.x, blockDim.x, M, lscale, nbr, u, uscale, y, oss, ors, smem);
 }
 
+// Whole-site form: one wave per row tile, each owning every right-hand-side
+// tile; the link operands of all nine directions are requested into
+// registers and all nine input blocks are copied into LDS by direct
+// global->LDS loads (no registers) at the start, so a site waits for memory
+// once instead of once per direction.  LDS: 9 padded blocks (159 KB at N = 64,
+// 64 right-hand sides: one work-group per CU).  Chunk c of a padded row holds
+// columns 4c..4c+3 for c < N/4; the last chunk of each row is padding (filled
+// with a copy of the row's last data chunk, never read).
+template <int F, int N, int NRHS>
+__global__ __launch_bounds__((N / 16) * 64) void k_coarse_mrhs_all(
+    const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
+    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y, int64_t oss, int64_t ors) {
+    constexpr int T = N / 16;                       // row tiles = waves = k steps per direction
+    constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;  // right-hand-side tiles
+    constexpr int UW = NRHS * N;                    // dwords per input block in HBM
+    constexpr int RL = N / 4 + 1;                   // 16-byte chunks per padded LDS row
+    constexpr int LD = 4 * RL;                      // LDS row stride (dwords)
+    constexpr int US = NRHS * LD;                   // dwords per staged block
+    constexpr int CH = NRHS * RL;                   // 16-byte chunks per staged block
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* Us = reinterpret_cast<uint32_t*>(smem);   // [9][NRHS][LD]
+    float* Sc = reinterpret_cast<float*>(Us + 9 * US);   // [9][NRHS]
+    const int site = blockIdx.x;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int rt = w;
+
+    uint4 A[9][T];
+    {
+        const uint4* Ms = M + ((int64_t)site * 9 * T + rt) * T * 64 + l;
+#pragma unroll
+        for (int d = 0; d < 9; ++d)
+#pragma unroll
+            for (int ks = 0; ks < T; ++ks) A[d][ks] = Ms[((int64_t)d * T * T + ks) * 64];
+    }
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        const int src = d == 0 ? site : nbr[site * 8 + d - 1];
+        const uint4* g = reinterpret_cast<const uint4*>(u + (int64_t)src * UW);
+        for (int c0 = w * 64; c0 < CH; c0 += T * 64) {
+            const int c = c0 + l;
+            if (c < CH) {
+                const int row = c / RL, col = c - (c / RL) * RL;
+                const int gc = row * (N / 4) + (col < N / 4 ? col : N / 4 - 1);
+                __builtin_amdgcn_global_load_lds(g + gc, (__attribute__((address_space(3))) void*)(Us + d * US + 4 * c0),
+                                                 16, 0, 0);
+            }
+        }
+    }
+    for (int e = threadIdx.x; e < 9 * NRHS; e += T * 64) {
+        const int d = e / NRHS, j = e % NRHS;
+        const int sd = d == 0 ? site : nbr[site * 8 + d - 1];
+        Sc[e] = lscale[(int64_t)site * 9 + d] * uscale[(int64_t)sd * NRHS + j];
+    }
+    __builtin_amdgcn_s_waitcnt(0);   // the direct-to-LDS copies have landed
+    __syncthreads();
+
+    f4v tot[NT][2];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) tot[t][0] = tot[t][1] = f4v{0, 0, 0, 0};
+    const int jl = l % 16;
+#pragma unroll
+    for (int d = 0; d < 9; ++d) {
+        const uint32_t* Ub = Us + d * US;
+        f4v acc[NT][2];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t][0] = acc[t][1] = f4v{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < T; ++ks) {
+            const uint4 a = A[d][ks];
+            const uint4 ar = make_uint4(a.x ^ 0x80000000u, a.y ^ 0x80000000u, a.z ^ 0x80000000u, a.w ^ 0x80000000u);
+            const uint4 ai = make_uint4(rot16(a.x), rot16(a.y), rot16(a.z), rot16(a.w));
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int j = t * 16 + jl;
+                uint4 b = make_uint4(0, 0, 0, 0);
+                if (NRHS >= 16 || j < NRHS) b = *reinterpret_cast<const uint4*>(Ub + j * LD + ks * 16 + 4 * (l / 16));
+                acc[t][0] = mfma<F>(ar, b, acc[t][0]);
+                acc[t][1] = mfma<F>(ai, b, acc[t][1]);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int j = t * 16 + jl;
+            const float sc = (NRHS >= 16 || j < NRHS) ? Sc[d * NRHS + j] : 0.0f;
+            tot[t][0] += sc * acc[t][0];
+            tot[t][1] += sc * acc[t][1];
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const int j = t * 16 + jl;
+        if (NRHS < 16 && j >= NRHS) continue;
+        float2* o = y + (int64_t)site * oss + (int64_t)j * ors + rt * 16 + 4 * (l / 16);
+        float4* o4 = reinterpret_cast<float4*>(o);
+        o4[0] = make_float4(tot[t][0][0], tot[t][1][0], tot[t][0][1], tot[t][1][1]);
+        o4[1] = make_float4(tot[t][0][2], tot[t][1][2], tot[t][0][3], tot[t][1][3]);
+    }
+}
+
 // Persistent form over several operators ("levels") of possibly different
 // size and N in {48, 64}: work item i of the queue [level 0 sites, level 1
 // sites, ...] is taken by work-group i mod gridDim.x; work-groups loop until
@@ -247,9 +346,23 @@ static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const
 }
 
 template <int F, int N, int NRHS>
+static qmg_status launch_all_t(const qmg_coarse_op_s* op, const void* in, const float* sc, void* out, int64_t ors,
+                               hipStream_t s) {
+    const size_t lds = 9 * (size_t)NRHS * (N + 4) * 4 + 9 * NRHS * 4;
+    auto kern = k_coarse_mrhs_all<F, N, NRHS>;
+    if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    hipLaunchKernelGGL(kern, dim3((unsigned)op->V), dim3((N / 16) * 64), lds, s, (const uint4*)op->mlinks, op->lscale,
+                       op->nbr, (const uint32_t*)in, sc, (float2*)out, ors ? (int64_t)N : (int64_t)NRHS * N,
+                       ors ? ors : (int64_t)N);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+template <int F, int N, int NRHS>
 static qmg_status launch_rpw(const qmg_coarse_op_s* op, int rpw, const void* in, const float* sc, void* out, int64_t ors,
                              hipStream_t s) {
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
+    if (rpw == 8) return launch_all_t<F, N, NRHS>(op, in, sc, out, ors, s);
     if (rpw == 1) return launch_mrhs_t<F, N, NRHS, 1>(op, in, sc, out, ors, s);
     if constexpr (NT >= 2) if (rpw == 2) return launch_mrhs_t<F, N, NRHS, 2>(op, in, sc, out, ors, s);
     if constexpr (NT >= 4) if (rpw == 4) return launch_mrhs_t<F, N, NRHS, 4>(op, in, sc, out, ors, s);
@@ -323,9 +436,19 @@ extern "C" qmg_status qmg_coarse_op_set_mrhs_tiles(qmg_coarse_op op, int nrhs, i
     if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
         return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: nrhs %d not in {8,16,32,64}", nrhs);
     const int r = rhs_tiles_per_wave;
-    if (r != 0 && r != 1 && r != 2 && r != 4) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: tiles %d not in {0,1,2,4}", r);
-    if (r > max_rpw(nrhs)) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: %d tiles exceed nrhs %d", r, nrhs);
+    if (r != 0 && r != 1 && r != 2 && r != 4 && r != 8)
+        return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: tiles %d not in {0,1,2,4,8}", r);
+    if (r != 8 && r > max_rpw(nrhs)) return fail(QMG_ERR_ARG, "coarse_op_set_mrhs_tiles: %d tiles exceed nrhs %d", r, nrhs);
     op->rpw[log2i(nrhs)] = r;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_coarse_op_get_mrhs_tiles(qmg_coarse_op op, int nrhs, int* tiles) {
+    if (!op || !tiles) return fail(QMG_ERR_ARG, "coarse_op_get_mrhs_tiles: NULL argument");
+    if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
+        return fail(QMG_ERR_ARG, "coarse_op_get_mrhs_tiles: nrhs %d not in {8,16,32,64}", nrhs);
+    const int r = op->rpw[log2i(nrhs)];
+    *tiles = r > 0 ? r : default_rpw(op, nrhs);
     return QMG_OK;
 }
 

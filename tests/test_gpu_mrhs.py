@@ -56,7 +56,17 @@ def test_mrhs_site_count_not_a_multiple_of_8(cd, N):
         assert emax <= 1e-5, (cd, N, nrhs, emax)
 
 
-@pytest.mark.parametrize('tiles', [1, 2, 4])
+@pytest.mark.parametrize('cd,N', [((4, 4, 4, 8), 64), ((2, 2, 2, 4), 48), ((3, 3, 2, 2), 32), ((3, 2, 3, 3), 16)])
+@pytest.mark.parametrize('nrhs', [8, 16, 32, 64])
+def test_whole_site_form(cd, N, nrhs):
+    """Tile code 8: every wave owns one row tile and all right-hand sides, the
+    nine input blocks staged in LDS by direct global->LDS copies."""
+    for fmt in ('h16', 'b16'):
+        err, emax, *_ = run_case(cd, N, nrhs, fmt, tiles=8, seed=7)
+        assert emax <= 1e-5, (cd, N, nrhs, fmt, emax)
+
+
+@pytest.mark.parametrize('tiles', [1, 2, 4, 8])
 def test_every_tile_shape(tiles):
     err, emax, *_ = run_case((2, 2, 2, 4), 64, 64, 'h16', tiles=tiles, seed=3)
     assert emax <= 1e-5
