@@ -81,18 +81,21 @@ __device__ __forceinline__ cpx<double> coarse_H(const qmg_coarse_op_s& op, const
     return {(double)c[2 * q], (double)c[2 * q + 1]};
 }
 
-template <bool FINE, typename R>
+template <bool FINE, typename R, bool ST>
 __global__ __launch_bounds__(1024) void k_galerkin(double2* __restrict__ Yout, double2* __restrict__ Xpart,
                                                    qmg_fine_op_s fop, qmg_coarse_op_s cop,
                                                    const void* __restrict__ parent_a,
                                                    const void* __restrict__ parent_b,
                                                    const int* __restrict__ nbr, const double2* __restrict__ B,
                                                    const int* __restrict__ members, const int* __restrict__ owner,
-                                                   int64_t Vc, int dof, int nvec, int bsites, Proj P, int hlds) {
+                                                   int64_t Vc, int dof, int nvec, int bsites, Proj P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int N = 2 * nvec, half = dof / 2;
     cpx<double>* W = reinterpret_cast<cpx<double>*>(smem);  // [dof][N]
+    // ST: the parent's block and the two basis blocks are staged in LDS
     cpx<double>* H = W + dof * N;                           // [dof][dof]
+    cpx<double>* Px = H + dof * dof;                        // Pf(x) [dof][nvec]
+    cpx<double>* Pn = Px + dof * nvec;                      // Pf(x') [dof][nvec]
     const int64_t xc = blockIdx.x / 17;
     const int term = (int)(blockIdx.x % 17);
     const bool isY = term < 8;
@@ -117,8 +120,13 @@ __global__ __launch_bounds__(1024) void k_galerkin(double2* __restrict__ Yout, d
                         : coarse_H<R>(cop, (const R*)parent_a, hterm, x, f, g);
         };
         __syncthreads();
-        if (hlds) {
+        if constexpr (ST) {
             for (int e = threadIdx.x; e < dof * dof; e += T) H[e] = Hfg(e / dof, e % dof);
+            for (int e = threadIdx.x; e < dof * nvec; e += T) {   // coalesced loads of both basis blocks
+                const double2 a = B[x * dof * nvec + e], c = B[xn * dof * nvec + e];
+                Px[e] = cpx<double>{a.x, a.y};
+                Pn[e] = cpx<double>{c.x, c.y};
+            }
             __syncthreads();
         }
         // W[f][m] = sum_{g in chi(m)} H[f][g] Pf(xn)[g][m'] ; Pf(xn)[g][m'] = B[xn][g][m']
@@ -128,9 +136,16 @@ __global__ __launch_bounds__(1024) void k_galerkin(double2* __restrict__ Yout, d
             cpx<double> w = {0.0, 0.0};
             for (int gg = 0; gg < half; ++gg) {
                 const int g = chi * half + gg;
-                const cpx<double> h = hlds ? H[f * dof + g] : Hfg(f, g);
-                const double2 bv = B[(xn * dof + g) * nvec + mp];
-                cmac(w.re, w.im, h.re, h.im, bv.x, bv.y);
+                cpx<double> h, bv;
+                if constexpr (ST) {
+                    h = H[f * dof + g];
+                    bv = Pn[g * nvec + mp];
+                } else {
+                    h = Hfg(f, g);
+                    const double2 b2 = B[(xn * dof + g) * nvec + mp];
+                    bv = cpx<double>{b2.x, b2.y};
+                }
+                cmac(w.re, w.im, h.re, h.im, bv.re, bv.im);
             }
             W[e] = w;
         }
@@ -144,9 +159,14 @@ __global__ __launch_bounds__(1024) void k_galerkin(double2* __restrict__ Yout, d
             const int chi = n / nvec, np = n - chi * nvec;
             for (int ff = 0; ff < half; ++ff) {
                 const int f = chi * half + ff;
-                const double2 bv = B[(x * dof + f) * nvec + np];
+                cpx<double> bv;
+                if constexpr (ST) bv = Px[f * nvec + np];
+                else {
+                    const double2 b2 = B[(x * dof + f) * nvec + np];
+                    bv = cpx<double>{b2.x, b2.y};
+                }
                 const cpx<double> w = W[f * N + m];
-                cmac_conj(acc[i].re, acc[i].im, bv.x, bv.y, w.re, w.im);
+                cmac_conj(acc[i].re, acc[i].im, bv.re, bv.im, w.re, w.im);
             }
         }
     }
@@ -234,48 +254,44 @@ extern "C" qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_
         cleanup();
         return fail(QMG_ERR_SHAPE, "build_coarse_op: N=%d too large", N);
     }
-    // W [pdof][N], then H [pdof][pdof] when both fit in 64 KiB (the fine
-    // parent: 11.5 KiB); a larger block would cost more in occupancy than it
-    // saves (measured on a 48 -> 64 coarse parent: 2.2 ms with H formed in
-    // place, 2.75 ms with it in LDS)
-    const int hlds = sizeof(cpx<double>) * ((size_t)pdof * N + (size_t)pdof * pdof) <= 65536 ? 1 : 0;
-    const size_t lds = sizeof(cpx<double>) * ((size_t)pdof * N + (hlds ? (size_t)pdof * pdof : 0));
+    // W [pdof][N]; with the parent's block H [pdof][pdof] and the two basis
+    // blocks [pdof][nvec] staged too when all of it fits in 64 KiB (the fine
+    // parent: 21 KiB).  A larger staging area would cost more in occupancy
+    // than it saves (measured on a 48 -> 64 coarse parent: 2.2 ms unstaged,
+    // 2.75 ms with H staged).
+    const size_t lds_st = sizeof(cpx<double>) * ((size_t)pdof * N + (size_t)pdof * pdof + 2 * (size_t)pdof * t->nvec);
+    const bool st_lds = lds_st <= 65536;
+    const size_t lds = st_lds ? lds_st : sizeof(cpx<double>) * (size_t)pdof * N;
     const dim3 grid((unsigned)(Vc * 17));
-    if (lds > 65536) {
-        const void* kern = fine ? (fine->storage == QMG_C128 ? (const void*)k_galerkin<true, double>
-                                                              : (const void*)k_galerkin<true, float>)
-                                : (parent->storage == QMG_C128 ? (const void*)k_galerkin<false, double>
-                                                               : (const void*)k_galerkin<false, float>);
-        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) {
-            cleanup();
-            return fail(QMG_ERR_HIP, "build_coarse_op: %s", hipGetErrorString(e));
-        }
-    }
     const Proj P = projectors();
     qmg_fine_op_s fop{};
     qmg_coarse_op_s cop{};
+#define QMG_GAL(FINE, R, ST, A, B_)                                                                            \
+    hipLaunchKernelGGL((k_galerkin<FINE, R, ST>), grid, dim3(threads), lds, s, Y, Xp, fop, cop, A, B_,           \
+                       FINE ? fine->nbr : parent->nbr, t->basis64, t->members, t->owner, Vc, pdof, t->nvec,     \
+                       t->bsites, P)
     if (fine) {
         fop = *fine;
-        if (fine->storage == QMG_C128)
-            hipLaunchKernelGGL((k_galerkin<true, double>), grid, dim3(threads), lds, s, Y, Xp, fop, cop, fine->U,
-                               fine->clov, fine->nbr, t->basis64, t->members, t->owner, Vc, pdof, t->nvec,
-                               t->bsites, P, hlds);
-        else
-            hipLaunchKernelGGL((k_galerkin<true, float>), grid, dim3(threads), lds, s, Y, Xp, fop, cop, fine->U,
-                               fine->clov, fine->nbr, t->basis64, t->members, t->owner, Vc, pdof, t->nvec,
-                               t->bsites, P, hlds);
+        const bool d = fine->storage == QMG_C128;
+        if (st_lds) {
+            if (d) QMG_GAL(true, double, true, fine->U, fine->clov);
+            else QMG_GAL(true, float, true, fine->U, fine->clov);
+        } else {
+            if (d) QMG_GAL(true, double, false, fine->U, fine->clov);
+            else QMG_GAL(true, float, false, fine->U, fine->clov);
+        }
     } else {
         cop = *parent;
-        if (parent->storage == QMG_C128)
-            hipLaunchKernelGGL((k_galerkin<false, double>), grid, dim3(threads), lds, s, Y, Xp, fop, cop,
-                               parent->links, nullptr, parent->nbr, t->basis64, t->members, t->owner, Vc, pdof,
-                               t->nvec, t->bsites, P, hlds);
-        else
-            hipLaunchKernelGGL((k_galerkin<false, float>), grid, dim3(threads), lds, s, Y, Xp, fop, cop,
-                               parent->links, nullptr, parent->nbr, t->basis64, t->members, t->owner, Vc, pdof,
-                               t->nvec, t->bsites, P, hlds);
+        const bool d = parent->storage == QMG_C128;
+        if (st_lds) {
+            if (d) QMG_GAL(false, double, true, parent->links, nullptr);
+            else QMG_GAL(false, float, true, parent->links, nullptr);
+        } else {
+            if (d) QMG_GAL(false, double, false, parent->links, nullptr);
+            else QMG_GAL(false, float, false, parent->links, nullptr);
+        }
     }
+#undef QMG_GAL
     hipLaunchKernelGGL(k_sum_xparts, dim3((unsigned)((blk + 255) / 256)), dim3(256), 0, s, X, Xp, (int64_t)blk);
     e = hipGetLastError();
     if (e != hipSuccess) {
