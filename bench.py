@@ -147,14 +147,19 @@ def small_grids(steps=2000):
     for): 2^4 N48 in FP64 and FP32 (the 8^4 workload's coarse level) and
     2^3x4 N64 in FP32 (level 2 of 16^3x32), tuned, back-to-back launches.  The
     operators (5.3 / 2.7 / 9.5 MB) stay in the caches, so the figure is
-    launch-to-launch time, reported against the algorithmic bytes."""
+    launch-to-launch time, reported against the algorithmic bytes.  The last
+    entry, the same kernel on a 2^4 operator with N = 2 (10 KB), is the fixed
+    cost of one launch that the others are to be read against.  `us_in_graph`
+    replays 200 captured launches: the device time per launch without the
+    host's submission rate."""
     import numpy as np
     import torch
     import synth
     from paper_1612_07873_amd import CoarseOp
     dev = torch.device('cuda')
     out = []
-    for cd, N, prec, cb in (((2, 2, 2, 2), 48, 'c128', 16), ((2, 2, 2, 2), 48, 'c64', 8), ((2, 2, 2, 4), 64, 'c64', 8)):
+    for cd, N, prec, cb in (((2, 2, 2, 2), 48, 'c128', 16), ((2, 2, 2, 2), 48, 'c64', 8), ((2, 2, 2, 4), 64, 'c64', 8),
+                            ((2, 2, 2, 2), 2, 'c128', 16)):
         V = int(np.prod(cd))
         X = torch.from_numpy(synth.gaussian((V, N, N), 0, 2)).to(dev)
         Y = torch.from_numpy(synth.gaussian((8, V, N, N), 1, 2)).to(dev)
@@ -164,9 +169,31 @@ def small_grids(steps=2000):
         y = torch.empty_like(u)
         op.tune(u, y)
         ms = timed(lambda i: op.apply(u, y), steps, 200)
+        # the same launches captured in a HIP graph and replayed: device time per
+        # launch without the host's submission rate
+        g, reps = torch.cuda.CUDAGraph(), 200
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            op.apply(u, y)
+        torch.cuda.current_stream().wait_stream(side)
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                op.apply(u, y)
+        g.replay()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(10):
+            g.replay()
+        b.record()
+        torch.cuda.synchronize()
+        ms_graph = a.elapsed_time(b) / (10 * reps)
         flops, byts = algorithmic(V, N, 1, cb)
         out.append({'lattice': list(cd), 'N': N, 'prec': prec, 'us': round(ms * 1e3, 3),
+                    'us_in_graph': round(ms_graph * 1e3, 3),
                     'GFLOP/s': round(flops / ms / 1e6, 1), 'GB/s_algorithmic': round(byts / ms / 1e6, 1),
+                    'GB/s_algorithmic_in_graph': round(byts / ms_graph / 1e6, 1),
                     'launch': list(op.launch()) + [op.prefetch()]})
     return out
 

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize('cd,N,prec,tol', [((4, 4, 4, 8), 48, 'c64', 1e-5), ((2, 2, 2, 2), 48, 'c128', 1e-12),
-                                           ((2, 2, 2, 4), 64, 'c64', 1e-5)])
+                                           ((2, 2, 2, 4), 64, 'c64', 1e-5), ((2, 2, 2, 2), 2, 'c128', 1e-12)])
 def test_tuned_launch_matches_oracle(cd, N, prec, tol):
     from paper_1612_07873_amd import CoarseOp
     V = lattice.volume(cd)
