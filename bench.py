@@ -142,6 +142,57 @@ def precision_and_mrhs(steps):
     return out
 
 
+def multi_level(nrhs_list=(16, 64), reps=50):
+    """The multi-RHS stencil on the three batched levels of the hierarchy
+    (8^3x16 N48, 4^3x8 N64, 2^4 N48, FP16): the three tuned per-level launches
+    back to back, against one persistent launch that walks the sites of all
+    three (qmg_coarse_dslash_mrhs_multi) captured in a HIP graph and replayed."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import CoarseOp, apply_mrhs_multi, quantize_sites
+    dev = torch.device('cuda')
+    shapes = (((8, 8, 8, 16), 48), ((4, 4, 4, 8), 64), ((2, 2, 2, 2), 48))
+    ops = []
+    for k, (cd, N) in enumerate(shapes):
+        V = int(np.prod(cd))
+        X = torch.from_numpy(synth.gaussian((V, N, N), 10 * k, 2)).to(dev)
+        Y = torch.from_numpy(synth.gaussian((8, V, N, N), 10 * k + 1, 2)).to(dev)
+        ops.append(CoarseOp(cd, X, Y, 'h16'))
+        del X, Y
+    out = []
+    for nrhs in nrhs_list:
+        qs, ss, ys, byts = [], [], [], 0
+        for k, ((cd, N), op) in enumerate(zip(shapes, ops)):
+            V = int(np.prod(cd))
+            um = torch.from_numpy(np.stack([synth.gaussian((V, N), 100 * k + j, 2) for j in range(nrhs)], axis=1)
+                                  ).to(dev).to(torch.complex64)
+            q, sc = quantize_sites(um.reshape(V * nrhs, N), 'h16')
+            qs.append(q.reshape(V, nrhs, N))
+            ss.append(sc.reshape(V, nrhs))
+            ys.append(torch.empty((V, nrhs, N), dtype=torch.complex64, device=dev))
+            op.apply_mrhs(qs[-1], ss[-1], ys[-1])
+            op.tune_mrhs(qs[-1], ss[-1], ys[-1], cold=True)
+            byts += algorithmic(V, N, nrhs, 4, 4, out_cbytes=8, out_scale_bytes=0)[1]
+        ms_sep = timed(lambda i: [op.apply_mrhs(q, sc, y) for op, q, sc, y in zip(ops, qs, ss, ys)], reps, 5)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            apply_mrhs_multi(ops, qs, ss, ys)
+            with torch.cuda.graph(g, stream=side):
+                apply_mrhs_multi(ops, qs, ss, ys)
+        torch.cuda.current_stream().wait_stream(side)
+        ms_graph = timed(lambda i: g.replay(), reps, 5)
+        out.append({'nrhs': nrhs, 'levels': [list(cd) + [N] for cd, N in shapes],
+                    'separate_launches_us': round(ms_sep * 1e3, 2), 'persistent_graph_us': round(ms_graph * 1e3, 2),
+                    'hbm_frac_separate': round(byts / ms_sep / 1e6 / HBM_PEAK_GBS, 4),
+                    'hbm_frac_persistent': round(byts / ms_graph / 1e6 / HBM_PEAK_GBS, 4),
+                    'tiles_tuned': [op.mrhs_tiles(nrhs) for op in ops]})
+        del qs, ss, ys, g
+    return out
+
+
 def small_grids(steps=2000):
     """The smallest coarse grids (the Amdahl limit the fine-grained split is
     for): 2^4 N48 in FP64 and FP32 (the 8^4 workload's coarse level) and
@@ -560,7 +611,9 @@ def main():
         print(json.dumps({'fine_and_transfer': fine_and_transfer()}), flush=True)
         return
     if args.only_16bit:
-        print(json.dumps(precision_and_mrhs(args.steps)), flush=True)
+        rec16 = precision_and_mrhs(args.steps)
+        rec16['multi_level'] = multi_level()
+        print(json.dumps(rec16), flush=True)
         return
     if args.mg_solves:
         mg, _, m0, _, setup = build_mg_16x32(coarse_direct=args.coarse_direct)
@@ -624,6 +677,7 @@ def main():
     if not args.only_headline:
         rec.update(precision_and_mrhs(max(100, args.steps // 4)))
         rec['small_grids'] = small_grids()
+        rec['multi_level'] = multi_level()
         rec['fine_and_transfer'] = fine_and_transfer()
         rec['mg_gcr'] = mg_gcr()
     if not args.no_cpu:

@@ -137,8 +137,9 @@ qmg_status qmg_coarse_dslash_mrhs(qmg_coarse_op op, const void* in, const float*
 /* One persistent launch applying several operators (the levels of a
  * hierarchy, of different size; N in {48, 64}; all with the same 16-bit
  * storage) to nrhs right-hand sides each: the sites of all operators form one
- * work queue that `grid` work-groups (0: min(total sites, 2048)) walk until
- * it is exhausted.  ops/in/in_scale/out are host arrays of nops (1..4)
+ * work queue that `grid` work-groups (0: as many as are resident on the
+ * device at once, at most the total number of sites) walk until it is
+ * exhausted.  ops/in/in_scale/out are host arrays of nops (1..4)
  * entries with the same meaning as in qmg_coarse_dslash_mrhs.  Launches no
  * memset and allocates nothing once each operator has been applied in the
  * multi-RHS form before, so it can be captured into a HIP graph. */

@@ -313,19 +313,21 @@ struct MultiLevel {
     float2* y[4];
 };
 
-template <int F, int NRHS>
-__global__ __launch_bounds__(4 * (NRHS >= 16 ? NRHS / 16 : 1) * 64) void k_coarse_mrhs_multi(MultiLevel ml) {
+// RP right-hand-side tiles per wave (the widest the batch allows: the
+// largest level, which dominates the queue, is fastest with it).
+template <int F, int NRHS, int RP>
+__global__ __launch_bounds__(4 * ((NRHS >= 16 ? NRHS / 16 : 1) / RP) * 64) void k_coarse_mrhs_multi(MultiLevel ml) {
     extern __shared__ __align__(16) unsigned char smem[];
     for (int64_t item = blockIdx.x; item < ml.start[ml.nlev]; item += gridDim.x) {
         int l = 0;
         while (l + 1 < ml.nlev && item >= ml.start[l + 1]) ++l;
         const int site = (int)(item - ml.start[l]);
         if (ml.N[l] == 48)
-            mrhs_site<F, 48, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l],
-                                      (int64_t)NRHS * 48, 48, smem);
+            mrhs_site<F, 48, NRHS, RP>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l],
+                                       (int64_t)NRHS * 48, 48, smem);
         else
-            mrhs_site<F, 64, NRHS, 1>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l],
-                                      (int64_t)NRHS * 64, 64, smem);
+            mrhs_site<F, 64, NRHS, RP>(site, blockDim.x, ml.M[l], ml.lscale[l], ml.nbr[l], ml.u[l], ml.uscale[l], ml.y[l],
+                                       (int64_t)NRHS * 64, 64, smem);
         __syncthreads();  // LDS is reused by the next item
     }
 }
@@ -455,10 +457,21 @@ extern "C" qmg_status qmg_coarse_op_get_mrhs_tiles(qmg_coarse_op op, int nrhs, i
 namespace qmg {
 template <int F, int NRHS>
 static qmg_status launch_multi(const MultiLevel& ml, size_t lds, int grid, hipStream_t s) {
-    auto kern = k_coarse_mrhs_multi<F, NRHS>;
-    if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(4 * NT * 64), lds, s, ml);
+    constexpr int RP = NRHS >= 64 ? 4 : NRHS >= 32 ? 2 : 1;
+    auto kern = k_coarse_mrhs_multi<F, NRHS, RP>;
+    if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    const int block = 4 * (NT / RP) * 64;
+    if (grid == 0) {   // as many work-groups as are resident at once: each walks its share of the queue
+        int per_cu = 0, dev = 0, cus = 0;
+        QMG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)kern, block, lds));
+        QMG_HIP(hipGetDevice(&dev));
+        QMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        grid = per_cu * cus;
+        if (grid < 1) grid = 1;
+        if ((int64_t)grid > ml.start[ml.nlev]) grid = (int)ml.start[ml.nlev];
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(block), lds, s, ml);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -504,7 +517,6 @@ extern "C" qmg_status qmg_coarse_dslash_mrhs_multi(int nops, const qmg_coarse_op
         if (l > lds) lds = l;
     }
     ml.start[nops] = tot;
-    if (grid == 0) grid = (int)(tot < 2048 ? tot : 2048);
     const bool h = ops[0]->storage == QMG_H16;
     switch (nrhs) {
         case 8: return h ? launch_multi<MF_H16, 8>(ml, lds, grid, s) : launch_multi<MF_B16, 8>(ml, lds, grid, s);
