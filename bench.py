@@ -585,7 +585,7 @@ def main():
                     help='only the 16-bit single-RHS and multi-RHS matrix-core records (rows a6, a7) instead')
     ap.add_argument('--precision-form', action='store_true',
                     help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
-    ap.add_argument('--pairs', type=int, default=1024)
+    ap.add_argument('--pairs', type=int, default=4096)
     ap.add_argument('--epochs', type=int, default=4)
     ap.add_argument('--loss', choices=['error', 'residual'], default='residual')
     ap.add_argument('--pairs-from', choices=['smoother', 'iterates'], default='smoother')
