@@ -581,6 +581,8 @@ def main():
     ap.add_argument('--mg-solves', type=int, default=0,
                     help='only time this many MG-GCR solves on 16^3x32 (after the setup) instead')
     ap.add_argument('--coarse-direct', action='store_true', help='with --mg-solves: exact coarsest solve')
+    ap.add_argument('--only-small', action='store_true',
+                    help='only the smallest-grid records (rows a1, a3-a5) instead')
     ap.add_argument('--only-16bit', action='store_true',
                     help='only the 16-bit single-RHS and multi-RHS matrix-core records (rows a6, a7) instead')
     ap.add_argument('--precision-form', action='store_true',
@@ -609,6 +611,9 @@ def main():
         return
     if args.only_fine:
         print(json.dumps({'fine_and_transfer': fine_and_transfer()}), flush=True)
+        return
+    if args.only_small:
+        print(json.dumps({'small_grids': small_grids()}), flush=True)
         return
     if args.only_16bit:
         rec16 = precision_and_mrhs(args.steps)
