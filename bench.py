@@ -45,7 +45,7 @@ def measured_traffic(launch):
     if rec.get('source_sha256') != sha or rec.get('rows') != launch[0]:
         return None
     return rec['traffic_bytes_per_launch']
-MG_M0_FILE = os.path.join(ROOT, 'tests', 'golden', 'config2_m0.json')
+MG_M0_FILE = os.path.join(ROOT, 'tests', 'golden', 'm0_16x16x16x32.json')
 
 
 def algorithmic(V, N, nrhs, cbytes, scale_bytes=0, out_cbytes=None, out_scale_bytes=None):
@@ -261,7 +261,7 @@ def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
     if os.path.exists(MG_M0_FILE):
         with open(MG_M0_FILE) as f:
             m0 = float(json.load(f)['m0'])
-        m0_src = 'tests/golden/config2_m0.json'
+        m0_src = 'tests/golden/m0_16x16x16x32.json'
     V = int(np.prod(dims))
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
     levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10,
@@ -511,7 +511,7 @@ def precision_form(nsolves=3, dims=(32, 32, 32, 64)):
     if os.path.exists(MG_M0_FILE):
         with open(MG_M0_FILE) as f:
             m0 = float(json.load(f)['m0'])
-        m0_src = 'tests/golden/config2_m0.json (16^3x32 value, same gauge recipe)'
+        m0_src = 'tests/golden/m0_16x16x16x32.json (16^3x32 value, same gauge recipe)'
     V = int(np.prod(dims))
     t0 = time.perf_counter()
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)

@@ -8,7 +8,7 @@ restatement of Eq. (2).  If
 1e-2 lies below the minimum of sigma_min over m0 (the antiperiodic time
 direction keeps the lowest mode's momentum away from zero), the m0 that
 minimises sigma_min is taken instead, the closest the workload can come to the
-target.  Writes config2_m0.json next to this file.
+target.  Writes m0_16x16x16x32.json next to this file.
 
 Usage: python tests/golden/tune_m0.py [--dims 16 16 16 32] [--eps 0.3] [--seed 0]
 """
@@ -39,7 +39,7 @@ def main():
     ap.add_argument('--tol', type=float, default=2e-3, help='relative change of the Ritz value per 50 steps')
     ap.add_argument('--maxit', type=int, default=3000)
     ap.add_argument('--steps', type=int, default=5, help='golden-section steps')
-    ap.add_argument('--out', default=os.path.join(HERE, 'config2_m0.json'))
+    ap.add_argument('--out', default=os.path.join(HERE, 'm0_16x16x16x32.json'))
     args = ap.parse_args()
     dims = tuple(args.dims)
     V = lattice.volume(dims)

@@ -17,7 +17,7 @@ CDT = {'c128': torch.complex128, 'c64': torch.complex64}
 
 
 @pytest.fixture(scope='module')
-def config1_op():
+def galerkin_8x8x8x8_op():
     """Fine 8^4, eps 0.4, seed 0, c_sw 1, m0 -0.2; Gaussian Nvec 24; block 4^4 -> 2^4, N 48."""
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     V = lattice.volume(dims)
@@ -42,12 +42,12 @@ def gpu_apply(op, u, prec, launch=None):
 
 
 @pytest.mark.parametrize('prec', ['c128', 'c64'])
-def test_config1_galerkin_operator(config1_op, prec):
+def test_galerkin_operator_8x8x8x8(galerkin_8x8x8x8_op, prec):
     u = synth.gaussian((16, 48), 0, 2)
-    ref = config1_op.apply(u)
-    y, _ = gpu_apply(config1_op, u, prec)
+    ref = galerkin_8x8x8x8_op.apply(u)
+    y, _ = gpu_apply(galerkin_8x8x8x8_op, u, prec)
     err = rel_err(y, ref)
-    print('config1 2^4 N48 %s rel err %.3e' % (prec, err))
+    print('8^4 Galerkin 2^4 N48 %s rel err %.3e' % (prec, err))
     assert err <= TOL[prec]
 
 
@@ -96,23 +96,23 @@ def test_ragged_and_extreme_sizes(cdims, N):
         assert rel_err(y, ref) <= TOL[prec]
 
 
-def test_export_round_trip_and_repeatability(config1_op):
+def test_export_round_trip_and_repeatability(galerkin_8x8x8x8_op):
     from paper_1612_07873_amd import CoarseOp
-    g = CoarseOp(config1_op.dims, dev(config1_op.X), dev(config1_op.Y), 'c128')
+    g = CoarseOp(galerkin_8x8x8x8_op.dims, dev(galerkin_8x8x8x8_op.X), dev(galerkin_8x8x8x8_op.Y), 'c128')
     X, Y = g.export()
-    assert np.array_equal(host(X), config1_op.X) and np.array_equal(host(Y), config1_op.Y)
-    g32 = CoarseOp(config1_op.dims, dev(config1_op.X), dev(config1_op.Y), 'c64')
+    assert np.array_equal(host(X), galerkin_8x8x8x8_op.X) and np.array_equal(host(Y), galerkin_8x8x8x8_op.Y)
+    g32 = CoarseOp(galerkin_8x8x8x8_op.dims, dev(galerkin_8x8x8x8_op.X), dev(galerkin_8x8x8x8_op.Y), 'c64')
     X32, _ = g32.export()
-    assert np.array_equal(host(X32), config1_op.X.astype(np.complex64).astype(np.complex128))
+    assert np.array_equal(host(X32), galerkin_8x8x8x8_op.X.astype(np.complex64).astype(np.complex128))
     u = dev(synth.gaussian((16, 48), 1, 2))
     a = host(g.apply(u))
     for _ in range(3):
         assert np.array_equal(host(g.apply(u)), a)     # no atomics: bitwise repeatable
 
 
-def test_interface_errors(config1_op):
+def test_interface_errors(galerkin_8x8x8x8_op):
     from paper_1612_07873_amd import CoarseOp, QmgError
-    g = CoarseOp(config1_op.dims, dev(config1_op.X), dev(config1_op.Y), 'c128')
+    g = CoarseOp(galerkin_8x8x8x8_op.dims, dev(galerkin_8x8x8x8_op.X), dev(galerkin_8x8x8x8_op.Y), 'c128')
     u = dev(synth.gaussian((16, 48), 1, 2))
     with pytest.raises(TypeError):
         g.apply(u.to(torch.complex64))

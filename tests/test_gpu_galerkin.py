@@ -18,7 +18,7 @@ def fine_inputs(dims, eps, seed):
 
 
 @pytest.mark.parametrize('storage,tol', [('c128', 1e-12), ('c64', 1e-5)])
-def test_config1_build_and_galerkin_identity(storage, tol):
+def test_build_and_galerkin_identity_8x8x8x8(storage, tol):
     from paper_1612_07873_amd import FineOp, Transfer, build_coarse_op
     dims, block, nvec, m0 = (8, 8, 8, 8), (4, 4, 4, 4), 24, -0.2
     V = lattice.volume(dims)
@@ -31,7 +31,7 @@ def test_config1_build_and_galerkin_identity(storage, tol):
     op = build_coarse_op(t, fine=fop, storage=storage)
     X, Y = op.export()
     ex = max(rel_err(host(X), ref.X), rel_err(host(Y), ref.Y))
-    print('config1 build %s rel err %.3e' % (storage, ex))
+    print('8^4 build %s rel err %.3e' % (storage, ex))
     assert ex <= tol
     # Galerkin identity through the GPU kernels: Mhat u == R M P u
     u = synth.gaussian((16, 48), 0, 2)
@@ -95,7 +95,7 @@ def test_coarse_parent_block_too_large_for_lds():
     assert err <= 1e-12
 
 
-def test_config2_full_size_sampled_sites():
+def test_16x16x16x32_full_size_sampled_sites():
     """16^3x32 -> 4^3x8 (Nvec 24): GPU build of all 512 coarse sites, eight of
     them recomputed one by one by the oracle."""
     from paper_1612_07873_amd import FineOp, Transfer, build_coarse_op

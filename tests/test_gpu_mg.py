@@ -1,5 +1,5 @@
 """GPU multigrid: hierarchy built on the device (null-vector relaxation,
-transfers, Galerkin) and the K-cycle FGCR solve.  Judged by the oracle: the
+transfers, Galerkin) and the K-cycle FGCR solve.  Checked against the oracle: the
 true residual under the oracle's FP64 M, the oracle's iteration count for the
 same hierarchy inputs, and the levels' operators against the oracle's
 Galerkin build from the same vectors."""
@@ -87,7 +87,7 @@ def test_three_level_with_relaxed_null_vectors():
     assert info['outer_iters'] < info0['outer_iters']
 
 
-def test_config2_shape_three_levels_to_1e10():
+def test_16x16x16x32_three_levels_to_1e10():
     """16^3x32, eps 0.3: block 4^4 / Nvec 24 -> 4^3x8 (N 48), block 2^4 / Nvec 32 -> 2^3x4 (N 64),
     FP32 inner, MR(4) smoothing, FP64 outer GCR(10) to 1e-10 (true residual under the oracle's M)."""
     from paper_1612_07873_amd import Multigrid
@@ -101,7 +101,7 @@ def test_config2_shape_three_levels_to_1e10():
     x, info = mg.solve(dev(b), tol=1e-10)
     r = b - wilson.apply_wilson_clover_c(host(x).reshape(b.shape), U, A, m0, dims)
     tr = np.linalg.norm(r) / np.linalg.norm(b)
-    print('config2 shape', info, 'oracle-M residual %.2e' % tr)
+    print('16^3x32', info, 'oracle-M residual %.2e' % tr)
     assert info['converged'] and tr <= 1e-10
 
 

@@ -28,7 +28,7 @@ def nrm_err(a, ref):
     return float(np.linalg.norm(a - ref) / np.linalg.norm(ref))
 
 
-def galerkin_config1():
+def galerkin_8x8x8x8():
     dims, block = (8, 8, 8, 8), (4, 4, 4, 4)
     V = lattice.volume(dims)
     U = synth.gauge_field(dims, 0.4, 0)
@@ -42,7 +42,7 @@ def random_op(cd, N, seed):
     return coarse.CoarseOp(cd, synth.gaussian((V, N, N), seed, 2), synth.gaussian((8, V, N, N), seed + 1, 2))
 
 
-OPS = {'config1_2^4_N48': galerkin_config1, '4^3x8_N48': lambda: random_op((4, 4, 4, 8), 48, 3),
+OPS = {'galerkin_8^4_2^4_N48': galerkin_8x8x8x8, '4^3x8_N48': lambda: random_op((4, 4, 4, 8), 48, 3),
        '2^3x4_N64': lambda: random_op((2, 2, 2, 4), 64, 5), '8^3x16_N48': lambda: random_op((8, 8, 8, 16), 48, 7)}
 
 

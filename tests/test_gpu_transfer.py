@@ -11,7 +11,7 @@ from gpu_util import dev, host, rel_err
 pytestmark = pytest.mark.gpu
 
 CASES = [  # fine dims, dof, block, nvec
-    ((8, 8, 8, 8), 12, (4, 4, 4, 4), 24),          # configuration 1
+    ((8, 8, 8, 8), 12, (4, 4, 4, 4), 24),          # 8^4, level 0 -> 1
     ((16, 16, 16, 32), 12, (4, 4, 4, 4), 24),      # 16^3x32 level 0 -> 1
     ((4, 4, 4, 8), 48, (2, 2, 2, 2), 32),          # 4^3x8 level 1 -> 2
     ((4, 6, 2, 4), 12, (2, 3, 1, 2), 3),           # ragged blocks, extent-1 block dims

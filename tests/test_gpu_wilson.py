@@ -37,12 +37,12 @@ def check(dims, eps, seed, m0, csw, anti, prec):
 
 
 @pytest.mark.parametrize('prec', ['c128', 'c64'])
-def test_config1_fine_operator(prec):
+def test_fine_operator_8x8x8x8(prec):
     check((8, 8, 8, 8), 0.4, 0, -0.2, 1.0, True, prec)
 
 
 @pytest.mark.parametrize('prec', ['c128', 'c64'])
-def test_config2_fine_operator_full_size(prec):
+def test_fine_operator_16x16x16x32_full_size(prec):
     check((16, 16, 16, 32), 0.3, 0, -0.2, 1.0, True, prec)
 
 
