@@ -106,6 +106,21 @@ def test_matrix_core_coarse_stencil_in_the_batch(storage, nrhs):
     assert infos[0]['outer_iters'] <= i1['outer_iters'] + 4
 
 
+def test_largest_batch_of_64():
+    """64 distinct members (the largest batch) with 16-bit coarse operators
+    (N = 16 and 32): the coarse stencils run as 64-right-hand-side matrix-core
+    products, and every member meets the 1e-10 bar under the oracle's M."""
+    dims, m0 = (8, 8, 8, 8), -0.3
+    mg, fine = setup(dims, m0, [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 16], 3, coarse_storage='h16')
+    V = lattice.volume(dims)
+    B = np.stack([synth.gaussian((V, 4, 3), 300 + k, 2) for k in range(64)])
+    X, infos = mg.solve_multi(dev(B))
+    res = oracle_residuals(fine, B, host(X))
+    print('64 members:', infos[0], 'worst oracle residual %.2e' % max(res))
+    assert len(infos) == 64 and all(i['converged'] for i in infos)
+    assert max(res) <= 1e-10
+
+
 def test_bad_batch_arguments():
     from paper_1612_07873_amd import QmgError
     dims, m0 = (4, 4, 4, 8), -0.3
