@@ -171,17 +171,21 @@ qmg_status qmg_coarse_op_get_launch(qmg_coarse_op op, int* rows, int* split);
 qmg_status qmg_coarse_op_get_prefetch(qmg_coarse_op op, int* pre);
 
 /* Autotune the single-RHS launch (rows, split, prefetch depth) by timing every
- * candidate with HIP events on `stream` (cold != 0: caches flushed with a
- * 1 GiB write before each timed launch, so links stream from HBM), install
- * the fastest on `op`, and remember it for operators of the same shape and
- * precision in this process.  in/out (and scales for 16-bit vectors, vprec
+ * candidate with HIP events on `stream` (cold != 0: the caches are evicted by
+ * reading a 1 GiB buffer before each of nine timed launches, so links stream
+ * from HBM; the buffer is allocated for the call), install the fastest (among
+ * candidates within 3 % of it: most rows, smallest split, deepest prefetch)
+ * on `op`, and remember it for operators of the same shape and precision in
+ * this process.  in/out (and scales for 16-bit vectors, vprec
  * QMG_H16/QMG_B16) are valid DEVICE fields as for the apply calls; their
  * contents are overwritten.  Blocks; *best_ms (host, may be NULL) receives the
  * best average time. */
 qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
                               float* out_scale, qmg_prec vprec, int cold, void* stream, float* best_ms);
 
-/* The same for the multi-RHS kernel's tile shape at this nrhs. */
+/* The same for the multi-RHS kernel's tile shape at this nrhs (candidates 1,
+ * 2, 4 right-hand-side tiles per wave as nrhs allows, then the whole-site
+ * form 8; a later candidate must be 3 % faster to be taken). */
 qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out, int nrhs,
                                    int cold, void* stream, float* best_ms);
 
