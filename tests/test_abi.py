@@ -61,3 +61,12 @@ def test_coarse_create_rejects_bad_arguments_without_a_device(lib):
     assert st == 1
     st = lib.qmg_coarse_dslash(None, fake, fake, 0, None)
     assert st == 1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libqmg.so the binding raises; there is no CPU fallback."""
+    from paper_1612_07873_amd import _lib
+    monkeypatch.setattr(_lib, '_lib', None)
+    monkeypatch.setattr(_lib, 'LIB_PATH', str(tmp_path / 'libqmg.so'))
+    with pytest.raises(RuntimeError, match='not built'):
+        _lib.lib()
