@@ -106,6 +106,7 @@ constexpr int S_MR = 40;      // 3
 constexpr int S_BN = 44;      // 1
 constexpr int S_SM = 48;      // 3: learned-smoother step scalars
 constexpr int S_OK = 52;      // 2: single-work-group GCR steps: stopping test passed, steps done
+constexpr int S_QQ = 54;      // 1: outer GCR: |q|^2 before the projection
 constexpr int kCheck = 4;     // such steps queued per host read of the scalars
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
@@ -145,10 +146,11 @@ qmg_status read_scalars(qmg_mg_s* mg, int first, int count) {
     return QMG_OK;
 }
 
-// classical Gram-Schmidt, two passes: q -= Q beta; z -= Z beta
+// classical Gram-Schmidt, `passes` passes (two by default): q -= Q beta; z -= Z beta
 template <typename R>
-qmg_status orthogonalize(qmg_mg_s* mg, const void* Q, const void* Z, int64_t ld, int k, void* q, void* z, int64_t n) {
-    for (int pass = 0; pass < 2; ++pass)
+qmg_status orthogonalize(qmg_mg_s* mg, const void* Q, const void* Z, int64_t ld, int k, void* q, void* z, int64_t n,
+                         int passes = 2) {
+    for (int pass = 0; pass < passes; ++pass)
         for (int j0 = 0; j0 < k; j0 += 16) {
             const int kk = k - j0 < 16 ? k - j0 : 16;
             const size_t off = (size_t)j0 * ld * sizeof(cpx<R>);
@@ -466,8 +468,24 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
                 QMG_HIP(hipMemcpyAsync(z, mg->r64, bb64, hipMemcpyDeviceToDevice, mg->s));
             }
             QMG_TRY(wilson_apply(mg->fine64, z, q, QMG_C128, nb, mg->s));
-            QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, n));
-            QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+            if (j == 0) {
+                QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+            } else {
+                // one projection pass, and a second only if it cancelled more
+                // than half of |q|^2 for some member (the Daniel-Gragg-Kaufman-
+                // Stewart test; the preconditioned directions are nearly
+                // orthogonal already, so the second pass is rarely needed)
+                QMG_TRY(mg->blas.norm2<double>(q, n, mg->dsc + S_QQ));
+                QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, n, 1));
+                QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+                QMG_TRY(read_scalars(mg, S_GCR, S_QQ + 1 - S_GCR));
+                bool again = false;
+                for (int b = 0; b < nb; ++b) again = again || !(hs(mg, b, S_GCR) >= 0.5 * hs(mg, b, S_QQ));
+                if (again) {
+                    QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, n, 1));
+                    QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+                }
+            }
             QMG_TRY(mg->blas.gcr_update<double>(mg->dsc + S_GCR, q, z, x, mg->r64, n));
             QMG_TRY(mg->blas.norm2<double>(mg->r64, n, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
