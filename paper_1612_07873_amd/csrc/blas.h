@@ -16,7 +16,7 @@ namespace qmg {
 
 struct Blas {
     hipStream_t s = nullptr;
-    double* partials = nullptr;  // [kMaxBatch][kMaxBlocks][kMaxVals]
+    double* partials = nullptr;  // [kMaxBatch][kMaxVals][kMaxBlocks]
     static constexpr int kMaxBlocks = 512;
     static constexpr int kMaxVals = 40;
     static constexpr int kMaxBatch = 64;

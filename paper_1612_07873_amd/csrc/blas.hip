@@ -27,18 +27,40 @@ __device__ __forceinline__ double wg_sum(double v, double* lds) {
     return t;
 }
 
-// phase 2: out[v] = sum over blocks of partials[b][v]; thread t adds blocks
-// t, t+256, ..., then a fixed tree: the same order on every run
+// phase 2: out[v] = sum over blocks of the partials; thread t adds blocks t
+// and t+256, then a fixed tree: the same order on every run.  The partials of
+// one value are contiguous ([value][block]), so the loads coalesce, and four
+// values are summed per round: their loads are issued together and share one
+// pass through LDS.  Loads past the nb blocks (or the nv values) stay inside
+// the table and are not used.
+static_assert(Blas::kMaxBlocks == 512, "k_final: each of its 256 threads adds two blocks");
 __global__ __launch_bounds__(256) void k_final(const double* __restrict__ partials, int nb, int nv,
                                                double* __restrict__ out, int ss) {
-    __shared__ double lds[16];
+    __shared__ double lds[4][4];   // [value][wave]
     partials += (int64_t)blockIdx.y * Blas::kMaxBlocks * Blas::kMaxVals;
     out += (int64_t)blockIdx.y * ss;
-    for (int v = 0; v < nv; ++v) {
-        double t = 0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) t += partials[b * Blas::kMaxVals + v];
-        t = wg_sum(t, lds);
-        if (threadIdx.x == 0) out[v] = t;
+    const int t = threadIdx.x, w = t >> 6, l = t & 63;
+    for (int v0 = 0; v0 < nv; v0 += 4) {
+        double sv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = v0 + i < Blas::kMaxVals ? v0 + i : 0;
+            const double a = partials[v * Blas::kMaxBlocks + t], b = partials[v * Blas::kMaxBlocks + t + 256];
+            sv[i] = (t < nb ? a : 0.0) + (t + 256 < nb ? b : 0.0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            for (int o = 32; o > 0; o >>= 1) sv[i] += __shfl_down(sv[i], o, 64);
+        __syncthreads();
+        if (l == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lds[i][w] = sv[i];
+        __syncthreads();
+        if (t < 4 && v0 + t < nv) {
+            double r = 0;
+            for (int j = 0; j < 4; ++j) r += lds[t][j];
+            out[v0 + t] = r;
+        }
     }
 }
 
@@ -51,7 +73,7 @@ __global__ __launch_bounds__(256) void k_final(const double* __restrict__ partia
 // a work-group's sums: to the partials, or straight to the result when the grid is one block
 __device__ __forceinline__ void put(double* part, double* out, int v, double val) {
     if (gridDim.x == 1) out[v] = val;
-    else part[blockIdx.x * Blas::kMaxVals + v] = val;
+    else part[v * Blas::kMaxBlocks + blockIdx.x] = val;
 }
 
 template <typename R>
