@@ -31,6 +31,9 @@ struct Blas {
     template <typename R> qmg_status norm2(const void* a, int64_t n, double* out);                // |a|^2 (1)
     // out = [<q,q>, <q,r>.re, <q,r>.im]
     template <typename R> qmg_status dot_norm(const void* q, const void* r, int64_t n, double* out);
+    // second phase alone: out[v] = sum of partials[v][g] over g < groups, v < nv
+    // (for kernels that leave per-work-group sums in the partials table)
+    qmg_status final_sum(int groups, int nv, double* out);
     // out[2i..2i+1] = <Q_i, q>, i < k; Q_i = Q + i*ld
     template <typename R> qmg_status multi_dot(const void* Q, int64_t ld, int k, const void* q, int64_t n, double* out);
     // q -= sum_i beta_i Q_i ; z -= sum_i beta_i Z_i (z may be NULL)

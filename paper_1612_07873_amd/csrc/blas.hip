@@ -484,6 +484,14 @@ static void finish(hipStream_t s, double* partials, int nblk, int nv, double* ou
     if (nblk > 1) hipLaunchKernelGGL(k_final, dim3(1, members), dim3(256), 0, s, partials, nblk, nv, out, ss);
 }
 
+qmg_status Blas::final_sum(int groups, int nv, double* out) {
+    if (groups < 1 || groups > kMaxBlocks || nv < 1 || nv > kMaxVals)
+        return fail(QMG_ERR_ARG, "final_sum: %d groups, %d values", groups, nv);
+    hipLaunchKernelGGL(k_final, dim3(1, nb), dim3(256), 0, s, partials, groups, nv, out, ss);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
 template <typename R> qmg_status Blas::dot(const void* a, const void* b, int64_t n, double* out) {
     const int nblk = nblocks(n);
     hipLaunchKernelGGL(k_dot<R>, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const cpx<R>*)a, (const cpx<R>*)b, n,

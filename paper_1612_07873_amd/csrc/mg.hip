@@ -40,6 +40,9 @@ qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec
 qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s);
 qmg_status wilson_apply(const qmg_fine_op_s* op, const void* in, void* out, qmg_prec vprec, int members,
                         hipStream_t s);
+qmg_status wilson_apply_dot(const qmg_fine_op_s* op, const void* in, void* out, qmg_prec vprec, int members,
+                            double* part, int64_t pmember, int pvalue, hipStream_t s);
+int wilson_groups(const qmg_fine_op_s* op);
 qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec vprec, int m, void* q16,
                         float* qsc, hipStream_t s);
 bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m);
@@ -170,8 +173,17 @@ template <typename R> qmg_status mr(qmg_mg_s* mg, int l, const void* r, void* x)
     const int nb = mg->nb;
     for (int it = 0; it < L.p.smoother_steps; ++it) {
         const void* cur = it == 0 ? r : L.mr_r;   // the first step reads r itself
-        QMG_TRY(apply_op<R>(mg, l, cur, L.mr_Ar));
-        QMG_TRY(mg->blas.dot_norm<R>(L.mr_Ar, cur, n, mg->dsc + S_MR));
+        const int groups = l == 0 ? wilson_groups(mg->fine_in) : 0;
+        if (l == 0 && groups <= Blas::kMaxBlocks) {
+            // the fine operator also sums <Ar,Ar>, <Ar,r> per work-group
+            QMG_TRY(wilson_apply_dot(mg->fine_in, cur, L.mr_Ar, sizeof(R) == 8 ? QMG_C128 : QMG_C64, nb,
+                                     mg->blas.partials, (int64_t)Blas::kMaxBlocks * Blas::kMaxVals, Blas::kMaxBlocks,
+                                     mg->s));
+            QMG_TRY(mg->blas.final_sum(groups, 3, mg->dsc + S_MR));
+        } else {
+            QMG_TRY(apply_op<R>(mg, l, cur, L.mr_Ar));
+            QMG_TRY(mg->blas.dot_norm<R>(L.mr_Ar, cur, n, mg->dsc + S_MR));
+        }
         QMG_TRY(mg->blas.mr_update<R>(mg->dsc + S_MR, cur, L.mr_r, L.mr_Ar, x, it == 0, n));
     }
     if (L.p.smoother_steps <= 0) {

@@ -225,21 +225,29 @@ __device__ __forceinline__ void hop_apply(cpx<R> acc[12], const cpx<R> p[12], co
 // for complex128 / complex64, complex64 or 16-bit pairs for 16-bit links).
 // Grid dimension y runs over batch members: member b's fields follow the
 // first at b*V sites.
-template <int LF, int VF>
+// DOT: also the minimal-residual step's inner products of the result with
+// the input, <out,out> and <out,in> (re, im), summed over the work-group in
+// FP64 (fixed order) into part[member*pmember + value*pvalue + blockIdx.x].
+template <int LF, int VF, bool DOT = false>
 __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ U, const void* __restrict__ clov,
                                                        const float* __restrict__ cscale,
                                                        const int* __restrict__ nbr, const void* __restrict__ in,
                                                        const float* __restrict__ in_scale, void* __restrict__ out,
                                                        float* __restrict__ out_scale, int64_t V,
-                                                       typename FineT<LF>::R diag, int use_clover) {
+                                                       typename FineT<LF>::R diag, int use_clover,
+                                                       double* __restrict__ part, int64_t pmember, int pvalue) {
     using R = typename FineT<LF>::R;
     // Work-groups are dealt to the 8 XCDs round-robin; renumber them so that
     // each XCD sweeps one contiguous range of sites and the neighbours one
     // x2-plane away stay in that XCD's L2.  The grid is a multiple of 8.
     const int64_t per = gridDim.x >> 3;
     const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int64_t site = wg * blockDim.x + threadIdx.x;
-    if (site >= V) return;
+    const int64_t site0 = wg * blockDim.x + threadIdx.x;
+    if (!DOT && site0 >= V) return;
+    // with DOT every thread reaches the work-group sum: one past the last
+    // site computes the last site again, stores nothing and adds zero
+    const bool live = site0 < V;
+    const int64_t site = live ? site0 : V - 1;
     const int64_t vo = (int64_t)blockIdx.y * V;
     const int* nb = nbr + site * 8;
     // FP32: the first two hops' operands are requested before the local terms
@@ -311,7 +319,35 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
         hop_load<3, true, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[7], vo);
         hop_apply<3, true>(acc, pa, ua);
     }
-    store_spinor<VF>(out, out_scale, site + vo, acc);
+    if (live) store_spinor<VF>(out, out_scale, site + vo, acc);
+    if constexpr (DOT) {
+        // the site's input is read again (a cache hit, normally) rather than
+        // kept live across the hops, which would cost half the occupancy; the
+        // empty asm keeps the compiler from reusing the first load instead
+        asm volatile("" ::: "memory");
+        load_spinor<VF>(p, in, in_scale, site + vo);
+        double s3[3] = {0, 0, 0};
+        if (live)
+#pragma unroll
+            for (int f = 0; f < 12; ++f) {
+                s3[0] += (double)acc[f].re * acc[f].re + (double)acc[f].im * acc[f].im;
+                s3[1] += (double)acc[f].re * p[f].re + (double)acc[f].im * p[f].im;
+                s3[2] += (double)acc[f].re * p[f].im - (double)acc[f].im * p[f].re;
+            }
+        __shared__ double red[3][4];   // [value][wave]
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+            for (int o = 32; o > 0; o >>= 1) s3[i] += __shfl_down(s3[i], o, 64);
+        if ((threadIdx.x & 63) == 0)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) red[i][threadIdx.x >> 6] = s3[i];
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            double t = 0;
+            for (int j = 0; j < 4; ++j) t += red[threadIdx.x][j];
+            part[(int64_t)blockIdx.y * pmember + threadIdx.x * pvalue + blockIdx.x] = t;
+        }
+    }
 }
 
 // ------------------------------------------------------------ clover build
@@ -541,13 +577,18 @@ static SigmaBlocks sigma_blocks(double csw) {
     return sb;
 }
 
-template <int LF, int VF>
+// work-groups of one member's launch (256 sites each, a multiple of 8)
+int wilson_groups(const qmg_fine_op_s* op) { return (int)(((op->V + 255) / 256 + 7) / 8 * 8); }
+
+template <int LF, int VF, bool DOT = false>
 static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const float* in_scale, void* out,
-                                float* out_scale, int members, hipStream_t s) {
+                                float* out_scale, int members, hipStream_t s, double* part = nullptr,
+                                int64_t pmember = 0, int pvalue = 0) {
     using R = typename FineT<LF>::R;
-    const unsigned nb = (unsigned)(((op->V + 255) / 256 + 7) / 8 * 8);
-    hipLaunchKernelGGL((k_wilson_clover<LF, VF>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale, op->nbr,
-                       in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0);
+    const unsigned nb = (unsigned)wilson_groups(op);
+    hipLaunchKernelGGL((k_wilson_clover<LF, VF, DOT>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale,
+                       op->nbr, in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0, part,
+                       pmember, pvalue);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -574,6 +615,29 @@ static qmg_status wilson_any(const qmg_fine_op_s* op, const void* in, const floa
 qmg_status wilson_apply(const qmg_fine_op_s* op, const void* in, void* out, qmg_prec vprec, int members,
                         hipStream_t s) {
     return wilson_any(op, in, nullptr, out, nullptr, vprec, members, s);
+}
+
+// wilson_apply with the minimal-residual inner products of every member:
+// <out,out>, <out,in>.re, <out,in>.im per work-group, value v of work-group g
+// of member b at part[b*pmember + v*pvalue + g] (wilson_groups(op) groups).
+// Vectors in complex128 / complex64 only.
+qmg_status wilson_apply_dot(const qmg_fine_op_s* op, const void* in, void* out, qmg_prec vprec, int members,
+                            double* part, int64_t pmember, int pvalue, hipStream_t s) {
+    if (vprec == QMG_C128 && op->storage == QMG_C128)
+        return launch_wilson<FMT_F64, FMT_F64, true>(op, in, nullptr, out, nullptr, members, s, part, pmember, pvalue);
+    if (vprec != QMG_C64 || op->storage == QMG_C128)
+        return fail(QMG_ERR_PREC, "wilson_apply_dot: vectors must be in the operator's inner precision");
+    switch (op->storage) {
+        case QMG_C64:
+            return launch_wilson<FMT_F32, FMT_F32, true>(op, in, nullptr, out, nullptr, members, s, part, pmember,
+                                                        pvalue);
+        case QMG_H16:
+            return launch_wilson<FMT_H16, FMT_F32, true>(op, in, nullptr, out, nullptr, members, s, part, pmember,
+                                                        pvalue);
+        default:
+            return launch_wilson<FMT_B16, FMT_F32, true>(op, in, nullptr, out, nullptr, members, s, part, pmember,
+                                                        pvalue);
+    }
 }
 
 static size_t real_bytes(qmg_prec p) { return p == QMG_C128 ? 8 : p == QMG_C64 ? 4 : 2; }
