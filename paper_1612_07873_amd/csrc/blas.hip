@@ -226,7 +226,11 @@ __global__ void k_gcr_update(const double* __restrict__ s3, cpx<R>* __restrict__
 template <typename R>
 __global__ void k_mr_update(const double* __restrict__ s3, const cpx<R>* rin, cpx<R>* r, const cpx<R>* __restrict__ Ar,
                             cpx<R>* __restrict__ x, int first, int64_t n, int ss) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD-contiguous ranges (the grid is a multiple of 8), as in the fine
+    // operator's kernel: each XCD updates the sites whose A r it just wrote
+    const int64_t per = gridDim.x >> 3;
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t i = wg * blockDim.x + threadIdx.x;
     if (i >= n) return;
     QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(rin); QMG_MEMBER_VEC(r); QMG_MEMBER_VEC(Ar); QMG_MEMBER_VEC(x);
     const double den = s3[0];
@@ -544,8 +548,8 @@ qmg_status Blas::gcr_update(const double* s3, void* q, void* z, void* x, void* r
 }
 template <typename R>
 qmg_status Blas::mr_update(const double* s3, const void* rin, void* r, const void* Ar, void* x, int first, int64_t n) {
-    hipLaunchKernelGGL(k_mr_update<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, s3, (const cpx<R>*)rin, (cpx<R>*)r,
-                       (const cpx<R>*)Ar, (cpx<R>*)x, first, n, ss);
+    hipLaunchKernelGGL(k_mr_update<R>, dim3((grid1(n) + 7) / 8 * 8, nb), dim3(kThreads), 0, s, s3, (const cpx<R>*)rin,
+                       (cpx<R>*)r, (const cpx<R>*)Ar, (cpx<R>*)x, first, n, ss);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
