@@ -54,7 +54,8 @@ struct Blas {
     template <typename R> qmg_status xmy(const void* b, const void* ax, void* r, int64_t n);  // r = b - ax
     template <typename Rs, typename Rd> qmg_status convert(const void* src, void* dst, int64_t n);
     // A whole GCR step after q = A z for vectors of at most kSmall entries, in one
-    // work-group: CGS2 of (q, z) against the k stored pairs, normalisation,
+    // work-group: Gram-Schmidt of (q, z) against the k stored pairs (a second
+    // pass only when the first cancelled more than half of |q|^2), normalisation,
     // x += alpha z, r -= alpha q; out = [<q,q>, <q,r>.re, <q,r>.im, |r|^2];
     // znext (may be NULL) receives the new r.
     static constexpr int64_t kSmall = 1 << 13;
