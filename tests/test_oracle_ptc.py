@@ -117,3 +117,70 @@ def test_residual_loss_gradients_match_finite_differences():
                 num += unit * (ptc.loss_and_grads_residual(Wp, rs, U, dims, M)[0]
                                - ptc.loss_and_grads_residual(Wm, rs, U, dims, M)[0]) / (2 * h)
             assert abs(num - Gs[l][idx]) <= 1e-6 * max(1.0, abs(Gs[l][idx])), (l, idx, num, Gs[l][idx])
+
+
+# ---- Adam against its published closed form (Kingma & Ba, Algorithm 1) ----
+#
+# From zero moments, the bias-corrected first step is m_hat = g and
+# v_hat = g^2 exactly, so each real component moves by lr*g/(|g| + eps),
+# independently of beta1 and beta2.  A dropped bias correction (a step of
+# lr*(1-b1)/sqrt(1-b2) ~ 3.16*lr), a missing square root (lr*g/(g^2+eps)) or a
+# sign error fails it, since |g| != 1 below.
+
+def _adam_one(W0, gs, lr=0.1, b1=0.9, b2=0.999, eps=1e-8):
+    opt = ptc.Adam([W0.shape], lr=lr, beta1=b1, beta2=b2, eps=eps)
+    Ws = [W0.copy()]
+    out = []
+    for g in gs:
+        Ws = opt.step(Ws, [g])
+        out.append(Ws[0].copy())
+    return out
+
+
+def test_adam_first_step_is_lr_times_sign_of_gradient():
+    W0 = np.array([[0.3 - 0.7j, -1.1 + 0.2j]])
+    g = np.array([[0.5 - 2.0j, -3.0 + 0.25j]])
+    (W1,) = _adam_one(W0, [g])
+    eps = 1e-8
+    expect = W0 - 0.1 * (g.real / (np.abs(g.real) + eps) + 1j * g.imag / (np.abs(g.imag) + eps))
+    assert np.abs(W1 - expect).max() <= 1e-15
+    # the first step does not depend on the betas
+    (W1b,) = _adam_one(W0, [g], b1=0.5, b2=0.9)
+    assert np.abs(W1b - expect).max() <= 1e-15
+
+
+def test_adam_second_step_hand_computed():
+    """Two steps with lr = 0.1, beta1 = 0.9, beta2 = 0.999, eps = 1e-8.
+    Real part: g1 = 1/2, g2 = -3/2:
+      m2 = 0.9*0.1*(1/2) + 0.1*(-3/2) = -21/200,  m_hat = m2/(1 - 0.81) = -21/38,
+      v2 = 0.999*0.001*(1/4) + 0.001*(9/4) = 9999/4000000,
+      v_hat = v2/(1 - 0.998001) = 9999/7996,
+      step = 0.1*m_hat/(sqrt(v_hat) + eps) = -0.04941898288778031.
+    Imaginary part: g1 = -2, g2 = 1/4:
+      m2 = -31/200, m_hat = -31/38, v2 = 8117/2000000, v_hat = 8117/3998,
+      step = -0.05725345717104488.
+    Swapping beta1 and beta2 gives a different second step, so it fails."""
+    W0 = np.array([0.25 + 0.5j])
+    g1 = np.array([0.5 - 2.0j])
+    g2 = np.array([-1.5 + 0.25j])
+    W1, W2 = _adam_one(W0, [g1, g2])
+    step2 = -0.04941898288778031 - 0.05725345717104488j
+    assert abs((W1 - W2)[0] - step2) <= 1e-15
+    _, W2s = _adam_one(W0, [g1, g2], b1=0.999, b2=0.9)
+    assert abs((W1 - W2s)[0] - step2) > 1e-3
+
+
+def test_adam_constant_gradient_moves_by_lr_every_step():
+    """With the same gradient g at every step the bias corrections make
+    m_hat = g and v_hat = g^2 exactly at every t, so every step moves each
+    component by lr*g/(|g| + eps); a bias correction with the wrong power of
+    beta (t - 1 or t + 1) breaks it from the second step on."""
+    W0 = np.array([1.0 - 1.0j, 0.0 + 0.0j, -2.0 + 3.0j])
+    g = np.array([0.3 + 4.0j, -0.02 - 0.7j, 5.0 - 0.001j])
+    Ws = _adam_one(W0, [g] * 6, lr=0.01)
+    eps = 1e-8
+    d = 0.01 * (g.real / (np.abs(g.real) + eps) + 1j * g.imag / (np.abs(g.imag) + eps))
+    prev = W0
+    for W in Ws:
+        assert np.abs((prev - W) - d).max() <= 1e-13
+        prev = W
