@@ -56,6 +56,34 @@ class CoarseOp:
             y = y + np.einsum('xij,xjr->xir', self.Y[d][sites], u[self.nbr[d][sites]])
         return y
 
+    def _c_args(self, u):
+        import ctypes
+        Vc, N = self.X.shape[0], self.N
+        uu = np.ascontiguousarray(u, dtype=np.complex128).reshape(Vc, N, -1)
+        X = np.ascontiguousarray(self.X, dtype=np.complex128)
+        Y = np.ascontiguousarray(self.Y, dtype=np.complex128)
+        return (ctypes.c_int * 4)(*self.dims), X, Y, uu, np.empty_like(uu)
+
+    def apply_c(self, u):
+        """Eq. (3) from the plain C loop in csrc/coarse_apply.c (same summation order)."""
+        from .wilson import _clib
+        L, X, Y, uu, y = self._c_args(u)
+        _clib().oracle_coarse_apply(L, self.N, uu.shape[2], X.ctypes.data, Y.ctypes.data, uu.ctypes.data,
+                                    y.ctypes.data)
+        return y.reshape(np.shape(u))
+
+    def time_apply_c(self, u, reps, threads=0):
+        """Mean seconds per C apply over `reps` repetitions after a warm-up, with
+        `threads` OpenMP threads (0: the OpenMP default); returns (seconds, threads used, y)."""
+        import ctypes
+        from .wilson import _clib
+        L, X, Y, uu, y = self._c_args(u)
+        used = ctypes.c_int(0)
+        sec = _clib().oracle_coarse_apply_timed(L, self.N, uu.shape[2], X.ctypes.data, Y.ctypes.data,
+                                                uu.ctypes.data, y.ctypes.data, int(reps), int(threads),
+                                                ctypes.addressof(used))
+        return sec, used.value, y.reshape(np.shape(u))
+
     def dense(self):
         Vc, N = self.X.shape[0], self.N
         M = np.zeros((Vc, N, Vc, N), dtype=np.complex128)

@@ -143,6 +143,11 @@ def _clib():
         lib = ctypes.CDLL(path)
         lib.oracle_wilson_clover.restype = None
         lib.oracle_wilson_clover.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_double, ctypes.c_int] + [ctypes.c_void_p] * 3
+        lib.oracle_coarse_apply.restype = None
+        lib.oracle_coarse_apply.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 4
+        lib.oracle_coarse_apply_timed.restype = ctypes.c_double
+        lib.oracle_coarse_apply_timed.argtypes = ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 4
+                                                  + [ctypes.c_int, ctypes.c_int, ctypes.c_void_p])
         _C = lib
     return _C
 

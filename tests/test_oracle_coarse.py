@@ -68,6 +68,8 @@ def test_galerkin_identity_8to2_nvec24():
     rmp = transfer.restrict(Vb, wilson.apply_wilson_clover(
         transfer.prolong(Vb, u, dims, block), U, A, -0.2, dims), dims, block)
     assert np.abs(op.apply(u) - rmp).max() < 1e-13 * np.abs(rmp).max()
+    # the plain C loop holds the same identity
+    assert np.abs(op.apply_c(u) - rmp).max() < 1e-13 * np.abs(rmp).max()
 
 
 def test_dense_galerkin_matches_matrix_product():
@@ -151,6 +153,7 @@ def test_coarse_free_field_closed_form_two_levels():
     u = synth.gaussian((lattice.volume(op2.dims), 4, 3), 0, 2)
     ref = 0.25 * wilson.apply_wilson_clover(u, unit_gauge(op2.dims), None, 4 * m0, op2.dims)
     assert np.abs(op2.apply(u.reshape(-1, 12)) - ref.reshape(-1, 12)).max() < 1e-14
+    assert np.abs(op2.apply_c(u.reshape(-1, 12)) - ref.reshape(-1, 12)).max() < 1e-14
 
 
 def test_coarse_operator_is_gauge_invariant():
@@ -222,3 +225,18 @@ def test_apply_at_sampled_sites_equals_full_apply():
     u = synth.gaussian((Vc, N, 3), 5, 2)
     sites = [0, 5, 17, 63]
     assert np.abs(op.apply_sites(u, sites) - op.apply(u)[sites]).max() < 1e-14
+
+
+@pytest.mark.parametrize('cd,N,nrhs', [((3, 2, 5, 2), 8, 3), ((2, 4, 2, 3), 6, 1), ((4, 4, 4, 8), 48, 2)])
+def test_c_apply_matches_numpy_apply(cd, N, nrhs):
+    """The plain C loop of Eq. (3) (the host baseline) and the numpy restatement
+    agree on ragged lattices with several right-hand sides, with 1 and all threads."""
+    V = lattice.volume(cd)
+    op = coarse.CoarseOp(cd, synth.gaussian((V, N, N), 0, 2), synth.gaussian((8, V, N, N), 1, 2))
+    u = synth.gaussian((V, N, nrhs), 2, 2)
+    ref = op.apply(u)
+    assert np.abs(op.apply_c(u) - ref).max() < 1e-13 * np.abs(ref).max()
+    for th in (1, 0):
+        sec, used, y = op.time_apply_c(u, 1, th)
+        assert sec > 0 and used >= 1 and (th == 0 or used == th)
+        assert np.abs(y - ref).max() < 1e-13 * np.abs(ref).max()
