@@ -281,6 +281,31 @@ def small_grids(steps=2000):
     return out
 
 
+def golden_m0(with_source=False):
+    """m0 of the 16^3x32 workload (searched with the oracle, stored under tests/golden)."""
+    m0, src = -0.25, 'provisional'
+    if os.path.exists(MG_M0_FILE):
+        with open(MG_M0_FILE) as f:
+            m0 = float(json.load(f)['m0'])
+        src = 'tests/golden/m0_16x16x16x32.json'
+    return (m0, src) if with_source else m0
+
+
+def precision_form_levels(dims):
+    """Level recipe and start vectors (on the device) of the 32^3x64 precision form:
+    block 4^4 / Nvec 24, then block 2^4 / Nvec 32."""
+    import numpy as np
+    import torch
+    import synth
+    V = int(np.prod(dims))
+    b1 = [d // 4 for d in dims]
+    levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10),
+              dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100)]
+    starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to('cuda'),
+              torch.from_numpy(synth.gaussian((32, int(np.prod(b1)), 48), 1, 1)).to('cuda')]
+    return levels, starts
+
+
 def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
     import numpy as np
     import torch
@@ -288,12 +313,7 @@ def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
     from paper_1612_07873_amd import Multigrid
     dev = torch.device('cuda')
     dims = (16, 16, 16, 32)
-    m0 = -0.25
-    m0_src = 'provisional'
-    if os.path.exists(MG_M0_FILE):
-        with open(MG_M0_FILE) as f:
-            m0 = float(json.load(f)['m0'])
-        m0_src = 'tests/golden/m0_16x16x16x32.json'
+    m0, m0_src = golden_m0(True)
     V = int(np.prod(dims))
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
     levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10,
@@ -538,20 +558,14 @@ def precision_form(nsolves=3, dims=(32, 32, 32, 64)):
     import synth
     from paper_1612_07873_amd import FineOp, Multigrid, Transfer, build_coarse_op
     dev = torch.device('cuda')
-    m0 = -0.25
-    m0_src = 'provisional'
-    if os.path.exists(MG_M0_FILE):
-        with open(MG_M0_FILE) as f:
-            m0 = float(json.load(f)['m0'])
-        m0_src = 'tests/golden/m0_16x16x16x32.json (16^3x32 value, same gauge recipe)'
+    m0, m0_src = golden_m0(True)
+    if m0_src != 'provisional':
+        m0_src += ' (16^3x32 value, same gauge recipe)'
     V = int(np.prod(dims))
     t0 = time.perf_counter()
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
     b1 = [d // 4 for d in dims]
-    levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10),
-              dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100)]
-    starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
-              torch.from_numpy(synth.gaussian((32, int(np.prod(b1)), 48), 1, 1)).to(dev)]
+    levels, starts = precision_form_levels(dims)
     print('precision form: inputs %.1f s' % (time.perf_counter() - t0), file=sys.stderr, flush=True)
     out = {'lattice': list(dims), 'm0': m0, 'm0_source': m0_src,
            'levels': '%s -(4^4,Nvec24)-> %s N48 -(2^4,Nvec32)-> %s N64'

@@ -143,6 +143,9 @@ def _clib():
         lib = ctypes.CDLL(path)
         lib.oracle_wilson_clover.restype = None
         lib.oracle_wilson_clover.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_double, ctypes.c_int] + [ctypes.c_void_p] * 3
+        lib.oracle_wilson_clover_csw.restype = None
+        lib.oracle_wilson_clover_csw.argtypes = ([ctypes.c_void_p] * 2 + [ctypes.c_double, ctypes.c_double, ctypes.c_int]
+                                                 + [ctypes.c_void_p] * 3)
         lib.oracle_coarse_apply.restype = None
         lib.oracle_coarse_apply.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int] + [ctypes.c_void_p] * 4
         lib.oracle_coarse_apply_timed.restype = ctypes.c_double
@@ -165,4 +168,21 @@ def apply_wilson_clover_c(psi, U, clover, m0, dims, antiperiodic_t=True):
     L = (ctypes.c_int * 4)(*dims)
     _clib().oracle_wilson_clover(L, U.ctypes.data, None if cl is None else cl.ctypes.data, float(m0),
                                  int(bool(antiperiodic_t)), g.ctypes.data, psi.ctypes.data, out.ctypes.data)
+    return out.reshape(shape)
+
+
+def apply_wilson_clover_csw_c(psi, U, csw, m0, dims, antiperiodic_t=True):
+    """M psi with the clover term formed at each site from the links inside the
+    plain C loop (csrc/wilson_clover.c): no stored clover field, so it serves
+    as the true-residual check on lattices of millions of sites."""
+    import ctypes
+    V = lattice.volume(dims)
+    shape = psi.shape
+    psi = np.ascontiguousarray(psi, dtype=np.complex128).reshape(V, 12)
+    U = np.ascontiguousarray(U, dtype=np.complex128)
+    g = np.ascontiguousarray(lattice.gammas(), dtype=np.complex128)
+    out = np.empty_like(psi)
+    L = (ctypes.c_int * 4)(*dims)
+    _clib().oracle_wilson_clover_csw(L, U.ctypes.data, float(csw), float(m0), int(bool(antiperiodic_t)),
+                                     g.ctypes.data, psi.ctypes.data, out.ctypes.data)
     return out.reshape(shape)

@@ -60,11 +60,12 @@ struct Blas {
     // znext (may be NULL) receives the new r.
     static constexpr int64_t kSmall = 1 << 13;
     // The step also evaluates the stopping test |r| <= tol |b| (|b|^2 at
-    // out[bnoff]) into out[okoff] and counts itself in out[okoff + 1]; once a
+    // out[bnoff]) into out[okoff + 1 - par], reading the previous launch's
+    // flags from out[okoff + par], and counts itself in out[okoff + 2]; once a
     // step has passed it for every member, later launches do nothing.
     template <typename R> qmg_status gcr_step_small(const void* Q, const void* Z, int64_t ld, int k, void* q, void* z,
                                                     void* x, void* r, int64_t n, double* out, void* znext, double tol,
-                                                    int okoff, int bnoff);
+                                                    int okoff, int bnoff, int par);
     // x /= sqrt(nrm2[0])
     template <typename R> qmg_status normalize(void* x, const double* nrm2, int64_t n);
 };

@@ -334,24 +334,31 @@ __device__ __forceinline__ void wg_sums(const double* acc, int nv, bool with32, 
 // over the vectors.
 //
 // Stopping test on the device: the step also writes ok = (<q,q> <= 0 or
-// |r| <= tol |b|) to out[okoff] (|b|^2 is read from out[bnoff]) and counts
-// itself in out[okoff + 1].  A launch that finds ok set for every one of the
-// nbm members of the batch (the previous step passed the test for all of
-// them) returns at once, so the host can queue several steps and read the
-// scalars only now and then: the steps after convergence change nothing.
+// |r| <= tol |b|) (|b|^2 is read from out[bnoff]) and counts itself in
+// out[okoff + 2].  The flags alternate between two slots: a launch with
+// parity par reads every member's flag from out[okoff + par] (written by the
+// previous launch, which has completed) and writes its own to
+// out[okoff + 1 - par].  A launch that finds the flag set for every one of
+// the nbm members returns at once, after carrying its member's flag forward,
+// so the host can queue several steps and read the scalars only now and then:
+// the steps after convergence change nothing, and whether a step runs is
+// decided by the same data in every member's work-group.
 template <typename R>
 __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restrict__ Q, const cpx<R>* __restrict__ Z,
                                                          int64_t ld, int k, cpx<R>* __restrict__ q,
                                                          cpx<R>* __restrict__ z, cpx<R>* __restrict__ x,
                                                          cpx<R>* __restrict__ r, int64_t n, double* __restrict__ out,
                                                          cpx<R>* __restrict__ znext, int ss, double tol, int okoff,
-                                                         int bnoff, int nbm) {
+                                                         int bnoff, int nbm, int par) {
     __shared__ double sc[36];
     __shared__ double part[16][36];
     {
         bool all = true;
-        for (int b = 0; b < nbm; ++b) all = all && out[(int64_t)b * ss + okoff] != 0.0;
-        if (all) return;
+        for (int b = 0; b < nbm; ++b) all = all && out[(int64_t)b * ss + okoff + par] != 0.0;
+        if (all) {
+            if (threadIdx.x == 0) out[(int64_t)blockIdx.y * ss + okoff + 1 - par] = 1.0;
+            return;
+        }
     }
     QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(Z); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x);
     QMG_MEMBER_VEC(r); QMG_MEMBER_SCAL(out);
@@ -454,8 +461,8 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
         out[2] = im;
         out[3] = sc[0];
         const double bn = sqrt(out[bnoff]);
-        out[okoff] = (qq <= 0.0 || (bn > 0 && sqrt(sc[0]) <= tol * bn)) ? 1.0 : 0.0;
-        out[okoff + 1] += 1.0;
+        out[okoff + 1 - par] = (qq <= 0.0 || (bn > 0 && sqrt(sc[0]) <= tol * bn)) ? 1.0 : 0.0;
+        out[okoff + 2] += 1.0;
     }
 }
 
@@ -463,10 +470,10 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
 // 16^3x32 (42.5 vs 44.0 and 45.7 ms per MG solve)
 template <typename R>
 qmg_status Blas::gcr_step_small(const void* Q, const void* Z, int64_t ld, int k, void* q, void* z, void* x, void* r,
-                                int64_t n, double* out, void* znext, double tol, int okoff, int bnoff) {
+                                int64_t n, double* out, void* znext, double tol, int okoff, int bnoff, int par) {
     hipLaunchKernelGGL(k_gcr_step_small<R>, dim3(1, nb), dim3(512), 0, s, (const cpx<R>*)Q, (const cpx<R>*)Z, ld, k,
                        (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x, (cpx<R>*)r, n, out, (cpx<R>*)znext, ss, tol, okoff,
-                       bnoff, nb);
+                       bnoff, nb, par);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -600,7 +607,7 @@ template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, in
     template qmg_status Blas::xmy<R>(const void*, const void*, void*, int64_t);                            \
     template qmg_status Blas::normalize<R>(void*, const double*, int64_t);                                 \
     template qmg_status Blas::gcr_step_small<R>(const void*, const void*, int64_t, int, void*, void*, void*,  \
-                                                void*, int64_t, double*, void*, double, int, int);
+                                                void*, int64_t, double*, void*, double, int, int, int);
 
 QMG_BLAS_INST(double)
 QMG_BLAS_INST(float)

@@ -108,8 +108,8 @@ constexpr int S_NRM = 36;     // 1
 constexpr int S_MR = 40;      // 3
 constexpr int S_BN = 44;      // 1
 constexpr int S_SM = 48;      // 3: learned-smoother step scalars
-constexpr int S_OK = 52;      // 2: single-work-group GCR steps: stopping test passed, steps done
-constexpr int S_QQ = 54;      // 1: outer GCR: |q|^2 before the projection
+constexpr int S_OK = 52;      // 3: single-work-group GCR steps: stopping-test flags (two parities), steps done
+constexpr int S_QQ = 56;      // 1: outer GCR: |q|^2 before the projection
 constexpr int kCheck = 4;     // such steps queued per host read of the scalars
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
@@ -248,7 +248,8 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     // vector work is one single-work-group kernel per member, so a step is two launches
     const bool small = !precond && n <= Blas::kSmall;
     if (small)   // stopping-test flags and step counters of every member
-        QMG_HIP(hipMemset2DAsync(mg->dsc + S_OK, sizeof(double) * kScal, 0, 2 * sizeof(double), nb, mg->s));
+        QMG_HIP(hipMemset2DAsync(mg->dsc + S_OK, sizeof(double) * kScal, 0, 3 * sizeof(double), nb, mg->s));
+    int launches = 0;   // single-work-group steps queued: the flags of the last one are in slot S_OK + (launches & 1)
     while (!done && iters < maxit) {
         int j = 0;
         if (small) QMG_HIP(hipMemcpyAsync(L.Z, L.r, bb, hipMemcpyDeviceToDevice, mg->s));
@@ -263,15 +264,17 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
                 QMG_TRY(apply_op<R>(mg, l, z, q));
                 void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * bb : nullptr;
                 QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, ld, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext,
-                                                   tol > 0.0 ? tol : 0.0, S_OK - S_GCR, S_BN - S_GCR));
+                                                   tol > 0.0 ? tol : 0.0, S_OK - S_GCR, S_BN - S_GCR,
+                                                   launches & 1));
+                ++launches;
                 ++iters;
                 if ((defer || iters % kCheck) && j + 1 < m && iters < maxit) continue;
-                QMG_TRY(read_scalars(mg, S_GCR, S_OK + 2 - S_GCR));
-                iters = (int)hs(mg, 0, S_OK + 1);   // steps that ran (the same for every member)
+                QMG_TRY(read_scalars(mg, S_GCR, S_OK + 3 - S_GCR));
+                iters = (int)hs(mg, 0, S_OK + 2);   // steps that ran (the same for every member)
                 done = true;
                 for (int b = 0; b < nb; ++b) {
                     if (!std::isfinite(hs(mg, b, S_GCR + 3)) || !std::isfinite(hs(mg, b, S_GCR))) fault = true;
-                    done = done && hs(mg, b, S_OK) != 0.0;
+                    done = done && hs(mg, b, S_OK + (launches & 1)) != 0.0;
                 }
                 if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
                 if (done) { ++j; break; }

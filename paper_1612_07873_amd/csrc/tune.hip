@@ -143,6 +143,15 @@ extern "C" qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const
             }
         }
     }
+    // Tiny operators (fewer than 4096 threads at every split) have no candidate
+    // above: the launch the operator already has is timed, so the cached entry
+    // and best_ms are a measured time.
+    if (all.empty()) {
+        float ms = 0;
+        QMG_TRY(tm.time([&]() { return coarse_dslash_launch(op, op->rows, op->split, op->pre, in, in_scale, out, out_scale, vprec, s, 1); },
+                        cold ? 9 : 5, &ms));
+        all.push_back(Best{op->rows, op->split, op->pre, ms});
+    }
     // Timing noise makes near-equal candidates trade places from run to run;
     // among those within 3% of the fastest take, in order, the most rows per
     // work-group (whole sites), the smallest split, the deepest prefetch (the

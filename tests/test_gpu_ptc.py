@@ -39,7 +39,7 @@ def test_forward_and_gradients_match_oracle():
     Lo, (G1o, G2o) = optc.loss_and_grads([W1q, W2q], pq, U, dims)
     print('loss gpu %.8f oracle %.8f; grad errs %.2e %.2e' % (L, Lo, rel_err(host(G1), G1o), rel_err(host(G2), G2o)))
     assert abs(L - Lo) <= 1e-5 * Lo
-    assert rel_err(host(G1), G1o) <= 1e-4 and rel_err(host(G2), G2o) <= 1e-4
+    assert rel_err(host(G1), G1o) <= 1e-5 and rel_err(host(G2), G2o) <= 1e-5
     # one Adam step from the same gradients
     net.adam_step(lr=1e-2)
     A1, A2 = (host(w) for w in net.weights())
@@ -67,7 +67,7 @@ def test_residual_loss_matches_oracle():
     Lo, (G1o, G2o) = optc.loss_and_grads_residual([q(W1), q(W2)], [q(r) for r in rs], U, dims, M)
     print('residual loss gpu %.8f oracle %.8f; grad errs %.2e %.2e' % (L, Lo, rel_err(host(G1), G1o), rel_err(host(G2), G2o)))
     assert abs(L - Lo) <= 1e-5 * Lo
-    assert rel_err(host(G1), G1o) <= 1e-4 and rel_err(host(G2), G2o) <= 1e-4
+    assert rel_err(host(G1), G1o) <= 1e-5 and rel_err(host(G2), G2o) <= 1e-5
 
 
 def test_wilson_weights_reproduce_the_wilson_kernel():

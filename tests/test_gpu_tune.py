@@ -29,6 +29,8 @@ def test_tuned_launch_matches_oracle(cd, N, prec, tol):
         y = host(g.apply(ud))
         print(cd, N, prec, 'cold' if cold else 'warm', 'tuned', g.launch(), 'prefetch', g.prefetch(), '%.4f ms' % ms)
         assert rel_err(y, ref) <= tol
+        # a timed launch, also where no candidate passes the thread floor (2^4, N = 2)
+        assert 0 < ms < 1e3
     # a second operator of the same shape takes the cached choice
     g2 = CoarseOp(cd, dev(X), dev(Y), prec)
     g2.tune(ud, out, cold=True)

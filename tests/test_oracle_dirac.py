@@ -144,3 +144,58 @@ def test_sampled_sites_agree_with_whole_field():
     assert np.allclose(wilson.clover_field(U, dims, 1.3, sites), A[sites], rtol=0, atol=1e-14)
     part = wilson.apply_wilson_clover_sites(psi, U, 1.3, -0.1, dims, sites)
     assert np.allclose(part, full[sites], rtol=0, atol=1e-13)
+
+
+# ---- the C loop that forms the clover term from the links at each site ----
+
+def test_csw_c_constant_abelian_flux_closed_form():
+    """M(c_sw) - M(0) = -(c_sw/2) sigma_01 (x) diag(sin q theta) on every site
+    for the constant abelian flux, from the links alone."""
+    dims = (4, 4, 2, 2)
+    V = lattice.volume(dims)
+    psi = synth.gaussian((V, 4, 3), 5, 2)
+    for n in (1, 3):
+        U, theta, q = abelian_flux(dims, n)
+        for csw in (1.0, 1.7):
+            d = (wilson.apply_wilson_clover_csw_c(psi, U, csw, -0.1, dims)
+                 - wilson.apply_wilson_clover_csw_c(psi, U, 0.0, -0.1, dims))
+            A = -(csw / 2) * np.kron(lattice.sigma(0, 1), np.diag(np.sin(q * theta)))
+            assert np.abs(d.reshape(V, 12) - psi.reshape(V, 12) @ A.T).max() < 1e-14
+
+
+def test_csw_c_pure_gauge_spectrum_and_gamma5_hermiticity():
+    dims = (4, 2, 2, 4)
+    V = lattice.volume(dims)
+    U = pure_gauge(dims, 7)
+    M = lambda v: wilson.apply_wilson_clover_csw_c(v.reshape(V, 4, 3), U, 1.0, -0.2, dims).reshape(-1)
+    ev = np.linalg.eigvals(wilson.dense_matrix(M, V * 12))
+    assert match_multisets(ev, free_spectrum(dims, -0.2)) < 1e-12
+    dims = (4, 4, 4, 4)
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 3)
+    g5 = np.kron(lattice.gamma5(), np.eye(3))
+    phi, psi = synth.gaussian((V, 12), 1, 2), synth.gaussian((V, 12), 2, 2)
+    M = lambda v: wilson.apply_wilson_clover_csw_c(v, U, 1.0, -0.2, dims)
+    lhs = np.vdot(phi, M(psi @ g5.T) @ g5.T)
+    rhs = np.vdot(M(phi), psi)
+    assert abs(lhs - rhs) < 1e-12 * abs(rhs)
+
+
+def test_csw_c_gauge_covariance_and_agreement_with_stored_clover():
+    from oracle_helpers import gauge_rotate
+    dims = (4, 4, 2, 4)
+    V = lattice.volume(dims)
+    U = synth.gauge_field(dims, 0.4, 1)
+    g = synth.gauge_rotation(dims, 2)
+    Ug = gauge_rotate(U, g, dims)
+    psi = synth.gaussian((V, 4, 3), 3, 2)
+    rot = lambda p: np.einsum('xab,xsb->xsa', g, p)
+    a = wilson.apply_wilson_clover_csw_c(rot(psi), Ug, 1.0, -0.3, dims)
+    b = rot(wilson.apply_wilson_clover_csw_c(psi, U, 1.0, -0.3, dims))
+    assert np.abs(a - b).max() < 1e-13
+    for dims, csw, m0 in (((4, 4, 2, 6), 1.0, -0.2), ((2, 4, 3, 4), 0.7, 0.1)):
+        U = synth.gauge_field(dims, 0.4, 3)
+        V = lattice.volume(dims)
+        psi = synth.gaussian((V, 4, 3), 1, 2)
+        ref = wilson.apply_wilson_clover(psi, U, wilson.clover_field(U, dims, csw), m0, dims)
+        assert np.abs(wilson.apply_wilson_clover_csw_c(psi, U, csw, m0, dims) - ref).max() < 1e-13
