@@ -99,11 +99,14 @@ qmg_status qmg_coarse_op_create(const int dims[4], int N, const void* X, const v
  * shapes as in create), converting from the storage precision. */
 qmg_status qmg_coarse_op_export(qmg_coarse_op op, void* X, void* Y, void* stream);
 
-/* Apply Eq. (3): out = Mhat in, for one right-hand side.  `in` and `out` are
- * DEVICE arrays [V][N] in precision `prec`: the operator's storage precision
- * for QMG_C128 / QMG_C64 operators, and QMG_C64 (FP32 vectors) for QMG_H16 /
- * QMG_B16 operators.  in and out must not overlap. */
-qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_prec prec,
+/* Apply Eq. (3): out = Mhat in, for nrhs right-hand sides.  `in` and `out` are
+ * DEVICE arrays [nrhs][V][N] (each right-hand side contiguous) in precision
+ * `prec`: the operator's storage precision for QMG_C128 / QMG_C64 operators,
+ * and QMG_C64 (FP32 vectors) for QMG_H16 / QMG_B16 operators.  One launch
+ * covers every right-hand side (the single-RHS kernel; the matrix-core form
+ * is qmg_coarse_dslash_mrhs*).  1 <= nrhs <= 1024 (QMG_ERR_ARG otherwise).
+ * in and out must not overlap. */
+qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, int nrhs, qmg_prec prec,
                              void* stream);
 
 /* Apply Eq. (3) with 16-bit vectors (QMG_H16 or QMG_B16 operator; `prec` is
@@ -113,6 +116,18 @@ qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_pr
  * |re| or |im| of the site's N outputs).  Buffers must not overlap. */
 qmg_status qmg_coarse_dslash_scaled(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
                                     float* out_scale, qmg_prec prec, void* stream);
+
+/* Eq. (3) for a batch of complex64 fields on the matrix cores: in/out DEVICE
+ * complex64 [nrhs][V][N] (each right-hand side contiguous), operator storage
+ * QMG_H16 or QMG_B16, N in {16, 32, 48, 64}, nrhs in {8, 16, 32, 64}.  The
+ * inputs are rounded to the operator's 16-bit format with one FP32 scale per
+ * (site, right-hand side) into staging the operator owns (allocated, or
+ * grown, on the first call that needs more), then the multi-RHS kernel of
+ * qmg_coarse_dslash_mrhs (FP32 accumulation) writes the complex64 outputs in
+ * the same layout.  It is the batched coarse apply of the multi-RHS solve
+ * (the paper's multi-RHS future work, Sec. 9).  in and out must not overlap;
+ * QMG_ERR_PREC / QMG_ERR_ARG / QMG_ERR_SHAPE as the checks above say. */
+qmg_status qmg_coarse_dslash_mrhs_c64(qmg_coarse_op op, const void* in, void* out, int nrhs, void* stream);
 
 /* Convert a DEVICE complex64 field [V][N] to 16-bit pairs `out` [V][N] with
  * per-site scales `scale` [V] (prec QMG_H16 or QMG_B16), and back. */
@@ -212,9 +227,10 @@ void qmg_coarse_op_destroy(qmg_coarse_op op);
 qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, double m0, double csw,
                               int antiperiodic_t, qmg_prec storage, void* stream, qmg_fine_op* out);
 
-/* out = M in for one field; in/out DEVICE [V][4][3] in the operator's storage
- * precision (complex64 for the 16-bit storages); in and out must not overlap. */
-qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, qmg_prec prec,
+/* out = M in for nrhs fields; in/out DEVICE [nrhs][V][4][3] in the operator's
+ * storage precision (complex64 for the 16-bit storages); one launch covers
+ * every field; 1 <= nrhs <= 1024; in and out must not overlap. */
+qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, int nrhs, qmg_prec prec,
                                     void* stream);
 
 /* The same with 16-bit vectors (operator storage QMG_H16 / QMG_B16; prec =
@@ -268,13 +284,14 @@ qmg_status qmg_transfer_coarse_dims(qmg_transfer t, int cdims[4], int* N);
 /* Write the FP64 basis V as a DEVICE complex128 array [V][fine_dof][nvec]. */
 qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* stream);
 
-/* fine_out [V][fine_dof] = P coarse_in [Vc][N]; DEVICE fields, precision p
- * (QMG_C128, or QMG_C64 when the transfer was created with QMG_C64). */
-qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, qmg_prec p,
+/* fine_out [nrhs][V][fine_dof] = P coarse_in [nrhs][Vc][N]; DEVICE fields,
+ * precision p (QMG_C128, or QMG_C64 when the transfer was created with
+ * QMG_C64); one launch covers every right-hand side; 1 <= nrhs <= 1024. */
+qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, int nrhs, qmg_prec p,
                        void* stream);
 
-/* coarse_out [Vc][N] = R fine_in [V][fine_dof]; same precision rules. */
-qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, qmg_prec p,
+/* coarse_out [nrhs][Vc][N] = R fine_in [nrhs][V][fine_dof]; same rules. */
+qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, int nrhs, qmg_prec p,
                         void* stream);
 
 void qmg_transfer_destroy(qmg_transfer t);

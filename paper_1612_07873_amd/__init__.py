@@ -34,6 +34,13 @@ def _dev_ptr(t, dtype, shape, what):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _nrhs(t, tail, what):
+    """Right-hand sides of a field given as tail (one) or [nrhs] + tail (several)."""
+    if isinstance(t, torch.Tensor) and t.dim() == len(tail) + 1:
+        return int(t.shape[0]), (int(t.shape[0]),) + tuple(tail)
+    return 1, tuple(tail)
+
+
 def _vol(dims):
     v = 1
     for d in dims:
@@ -62,13 +69,15 @@ class CoarseOp:
         self._h = h
 
     def apply(self, u, out=None):
+        """Eq. (3) on u [V][N] or, for several right-hand sides, [nrhs][V][N]."""
         if out is None:
             out = torch.empty_like(u)
         vp = self.storage if self.storage in ('c128', 'c64') else 'c64'
+        m, shape = _nrhs(u, (self.V, self.N), 'in')
         _lib.call('qmg_coarse_dslash', self._h,
-                  _dev_ptr(u, self.dtype, (self.V, self.N), 'in'),
-                  _dev_ptr(out, self.dtype, (self.V, self.N), 'out'),
-                  PREC[vp], stream_ptr())
+                  _dev_ptr(u, self.dtype, shape, 'in'),
+                  _dev_ptr(out, self.dtype, shape, 'out'),
+                  m, PREC[vp], stream_ptr())
         return out
 
     def apply_mrhs(self, u16, uscale, out=None):
@@ -80,6 +89,15 @@ class CoarseOp:
         _lib.call('qmg_coarse_dslash_mrhs', self._h, _dev_ptr(u16, torch.int32, (self.V, nrhs, self.N), 'in'),
                   _dev_ptr(uscale, torch.float32, (self.V, nrhs), 'in_scale'),
                   _dev_ptr(out, torch.complex64, (self.V, nrhs, self.N), 'out'), int(nrhs), stream_ptr())
+        return out
+
+    def apply_mrhs_c64(self, u, out=None):
+        """Matrix-core batch from complex64 fields: u [nrhs][V][N] -> [nrhs][V][N] (16-bit operators)."""
+        nrhs = int(u.shape[0])
+        if out is None:
+            out = torch.empty_like(u)
+        _lib.call('qmg_coarse_dslash_mrhs_c64', self._h, _dev_ptr(u, torch.complex64, (nrhs, self.V, self.N), 'in'),
+                  _dev_ptr(out, torch.complex64, (nrhs, self.V, self.N), 'out'), nrhs, stream_ptr())
         return out
 
     def set_mrhs_tiles(self, nrhs, tiles):
@@ -177,12 +195,14 @@ class FineOp:
         self._h = h
 
     def apply(self, psi, out=None):
+        """Eq. (2) on psi [V][4][3] or, for several fields, [nrhs][V][4][3]."""
         if out is None:
             out = torch.empty_like(psi)
         vp = self.storage if self.storage in ('c128', 'c64') else 'c64'
+        m, shape = _nrhs(psi, (self.V, 4, 3), 'in')
         _lib.call('qmg_wilson_clover_dslash', self._h,
-                  _dev_ptr(psi, self.dtype, (self.V, 4, 3), 'in'),
-                  _dev_ptr(out, self.dtype, (self.V, 4, 3), 'out'), PREC[vp], stream_ptr())
+                  _dev_ptr(psi, self.dtype, shape, 'in'),
+                  _dev_ptr(out, self.dtype, shape, 'out'), m, PREC[vp], stream_ptr())
         return out
 
     def apply_scaled(self, u16, uscale, out16=None, oscale=None, vprec=None):
@@ -247,19 +267,25 @@ class Transfer:
         return 'c128' if t.dtype == torch.complex128 else 'c64'
 
     def prolong(self, uc, out=None):
+        """P uc for uc [Vc][N] or [nrhs][Vc][N]."""
         p = self._prec(uc)
+        m, cshape = _nrhs(uc, (self.Vc, self.N), 'coarse_in')
+        fshape = cshape[:-2] + (self.V, self.dof)
         if out is None:
-            out = torch.empty((self.V, self.dof), dtype=uc.dtype, device=uc.device)
-        _lib.call('qmg_prolong', self._h, _dev_ptr(uc, _CDTYPE[p], (self.Vc, self.N), 'coarse_in'),
-                  _dev_ptr(out, _CDTYPE[p], (self.V, self.dof), 'fine_out'), PREC[p], stream_ptr())
+            out = torch.empty(fshape, dtype=uc.dtype, device=uc.device)
+        _lib.call('qmg_prolong', self._h, _dev_ptr(uc, _CDTYPE[p], cshape, 'coarse_in'),
+                  _dev_ptr(out, _CDTYPE[p], fshape, 'fine_out'), m, PREC[p], stream_ptr())
         return out
 
     def restrict(self, f, out=None):
+        """R f for f [V][dof] or [nrhs][V][dof]."""
         p = self._prec(f)
+        m, fshape = _nrhs(f, (self.V, self.dof), 'fine_in')
+        cshape = fshape[:-2] + (self.Vc, self.N)
         if out is None:
-            out = torch.empty((self.Vc, self.N), dtype=f.dtype, device=f.device)
-        _lib.call('qmg_restrict', self._h, _dev_ptr(f, _CDTYPE[p], (self.V, self.dof), 'fine_in'),
-                  _dev_ptr(out, _CDTYPE[p], (self.Vc, self.N), 'coarse_out'), PREC[p], stream_ptr())
+            out = torch.empty(cshape, dtype=f.dtype, device=f.device)
+        _lib.call('qmg_restrict', self._h, _dev_ptr(f, _CDTYPE[p], fshape, 'fine_in'),
+                  _dev_ptr(out, _CDTYPE[p], cshape, 'coarse_out'), m, PREC[p], stream_ptr())
         return out
 
     def __del__(self):

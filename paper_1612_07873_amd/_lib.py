@@ -21,7 +21,8 @@ SIGNATURES = {
     'qmg_sync': (c_int, [c_void_p]),
     'qmg_coarse_op_create': (c_int, [c_dims, c_int, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_coarse_op_export': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
-    'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_coarse_dslash_mrhs_c64': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_launch': (c_int, [c_void_p, c_int, c_int]),
     'qmg_coarse_op_get_prefetch': (c_int, [c_void_p, c_int_p]),
     'qmg_coarse_op_tune': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
@@ -40,7 +41,7 @@ SIGNATURES = {
     'qmg_coarse_op_destroy': (None, [c_void_p]),
     'qmg_fine_op_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, c_void_p,
                                    ctypes.POINTER(c_void_p)]),
-    'qmg_wilson_clover_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_wilson_clover_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_wilson_clover_dslash_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_fine_op_export_clover': (c_int, [c_void_p, c_void_p, c_void_p]),
     'qmg_fine_op_export_links': (c_int, [c_void_p, c_void_p, c_void_p]),
@@ -49,8 +50,8 @@ SIGNATURES = {
                                     ctypes.POINTER(c_void_p)]),
     'qmg_transfer_coarse_dims': (c_int, [c_void_p, c_int_p, c_int_p]),
     'qmg_transfer_export': (c_int, [c_void_p, c_void_p, c_void_p]),
-    'qmg_prolong': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
-    'qmg_restrict': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_prolong': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_restrict': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_transfer_destroy': (None, [c_void_p]),
     'qmg_build_coarse_op': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
 }

@@ -500,15 +500,49 @@ extern "C" qmg_status qmg_coarse_op_export(qmg_coarse_op op, void* X, void* Y, v
     return QMG_OK;
 }
 
-extern "C" qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, qmg_prec prec, void* stream) {
+extern "C" qmg_status qmg_coarse_dslash(qmg_coarse_op op, const void* in, void* out, int nrhs, qmg_prec prec,
+                                        void* stream) {
     if (!op || !in || !out) return fail(QMG_ERR_ARG, "coarse_dslash: NULL argument");
+    if (nrhs < 1 || nrhs > kMaxFieldBatch) return fail(QMG_ERR_ARG, "coarse_dslash: nrhs %d not in [1, %d]", nrhs, kMaxFieldBatch);
     const bool ok = prec == op->storage || (is16(op->storage) && prec == QMG_C64);
     if (!ok)
         return fail(QMG_ERR_PREC, "coarse_dslash: vector precision %d does not fit operator storage %d", (int)prec,
                     (int)op->storage);
     if (is16(prec)) return fail(QMG_ERR_PREC, "coarse_dslash: 16-bit vectors go through qmg_coarse_dslash_scaled");
     if (in == out) return fail(QMG_ERR_ARG, "coarse_dslash: in and out alias");
-    return coarse_dslash_any(op, in, nullptr, out, nullptr, prec, as_stream(stream));
+    return coarse_dslash_launch(op, op->rows, op->split, op->pre, in, nullptr, out, nullptr, prec, as_stream(stream), nrhs);
+}
+
+// Staging bytes of a batch rounded to 16 bits: pairs [V][nrhs][N], then scales [V][nrhs].
+static size_t mrhs_stage_bytes(const qmg_coarse_op_s* op, int nrhs) {
+    const size_t pairs = (size_t)op->V * nrhs * op->N * sizeof(uint32_t);
+    return pairs + (size_t)op->V * nrhs * sizeof(float);
+}
+
+static qmg_status check_mrhs_c64(const qmg_coarse_op_s* op, const void* in, const void* out, int nrhs,
+                                 const char* what) {
+    if (!op || !in || !out) return fail(QMG_ERR_ARG, "%s: NULL argument", what);
+    if (!is16(op->storage)) return fail(QMG_ERR_PREC, "%s: needs an operator with 16-bit storage", what);
+    if (nrhs != 8 && nrhs != 16 && nrhs != 32 && nrhs != 64)
+        return fail(QMG_ERR_ARG, "%s: nrhs %d not in {8,16,32,64}", what, nrhs);
+    if (op->N % 16 || op->N > 64) return fail(QMG_ERR_SHAPE, "%s: N=%d must be 16, 32, 48 or 64", what, op->N);
+    if (in == out) return fail(QMG_ERR_ARG, "%s: in and out alias", what);
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_coarse_dslash_mrhs_c64(qmg_coarse_op op, const void* in, void* out, int nrhs,
+                                                 void* stream) {
+    QMG_TRY(check_mrhs_c64(op, in, out, nrhs, "coarse_dslash_mrhs_c64"));
+    const size_t need = mrhs_stage_bytes(op, nrhs);
+    if (op->stage_bytes < need) {   // grow the operator's staging (hipFree waits for work that used it)
+        if (op->stage) (void)hipFree(op->stage);
+        op->stage = nullptr;
+        op->stage_bytes = 0;
+        QMG_HIP(hipMalloc(&op->stage, need));
+        op->stage_bytes = need;
+    }
+    float* qsc = (float*)((char*)op->stage + (size_t)op->V * nrhs * op->N * sizeof(uint32_t));
+    return coarse_apply(op, in, out, QMG_C64, nrhs, op->stage, qsc, as_stream(stream));
 }
 
 extern "C" qmg_status qmg_coarse_dslash_scaled(qmg_coarse_op op, const void* in, const float* in_scale, void* out,
@@ -574,6 +608,7 @@ extern "C" void qmg_coarse_op_destroy(qmg_coarse_op op) {
     if (op->links) (void)hipFree(op->links);
     if (op->lscale) (void)hipFree(op->lscale);
     if (op->mlinks) (void)hipFree(op->mlinks);
+    if (op->stage) (void)hipFree(op->stage);
     if (op->nbr) (void)hipFree(op->nbr);
     delete op;
 }

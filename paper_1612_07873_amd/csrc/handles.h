@@ -16,6 +16,8 @@ struct qmg_coarse_op_s {
     int pre;        // link chunks each thread loads before the LDS staging barrier (0 = by K)
     void* mlinks;   // 16-bit links in MFMA operand order (built on first multi-RHS use), else NULL
     int rpw[7];     // multi-RHS: right-hand-side tiles per wave for nrhs = 1,2,4,..,64 (0 = built-in)
+    void* stage;    // staging of complex64 batches rounded to 16 bits ([V][nrhs][N] pairs, then [V][nrhs] scales)
+    size_t stage_bytes;
 };
 
 struct qmg_fine_op_s {

@@ -816,7 +816,7 @@ extern "C" qmg_status qmg_mg_make_pairs(qmg_mg mg, const void* xstar, const void
         float2* r32 = (float2*)r_out + (size_t)k * nv;
         hipLaunchKernelGGL(k_pair_error, dim3(g), dim3(256), 0, s, (const double2*)xstar, xk, (double2*)mg->t64, e32, nv);
         QMG_LAUNCH_CHECK();
-        QMG_TRY(qmg_wilson_clover_dslash(mg->fine64, mg->t64, mg->r64, QMG_C128, stream));
+        QMG_TRY(qmg_wilson_clover_dslash(mg->fine64, mg->t64, mg->r64, 1, QMG_C128, stream));
         hipLaunchKernelGGL(k_to32, dim3(g), dim3(256), 0, s, (const double2*)mg->r64, r32, nv);
         QMG_LAUNCH_CHECK();
     }

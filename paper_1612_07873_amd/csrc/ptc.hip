@@ -372,7 +372,7 @@ extern "C" qmg_status qmg_ptc_accumulate_grad_residual(qmg_ptc t, const void* r,
     const int64_t n = t->V * 12;
     QMG_TRY(ptc_forward(t, r, t->y, s));
     // t1 = M y ; loss += |M y - r|^2/|r|^2 ; t2 = (M y - r)/|r|^2 = dL/d(My)*
-    QMG_TRY(qmg_wilson_clover_dslash(t->op, t->y, t->t1, QMG_C64, stream));
+    QMG_TRY(qmg_wilson_clover_dslash(t->op, t->y, t->t1, 1, QMG_C64, stream));
     const int nb = ptc_blocks(n);
     hipLaunchKernelGGL(k_ptc_loss_part, dim3(nb), dim3(256), 0, s, t->part, t->t1, (const float2*)r, n);
     hipLaunchKernelGGL(k_ptc_loss_final, dim3(1), dim3(64), 0, s, t->loss, t->part, nb);
@@ -382,7 +382,7 @@ extern "C" qmg_status qmg_ptc_accumulate_grad_residual(qmg_ptc t, const void* r,
     const unsigned g = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(k_gamma5_scale, dim3(g), dim3(256), 0, s, t->t1, t->t2, t->loss, 0, n);
     QMG_LAUNCH_CHECK();
-    QMG_TRY(qmg_wilson_clover_dslash(t->op, t->t1, t->t2, QMG_C64, stream));
+    QMG_TRY(qmg_wilson_clover_dslash(t->op, t->t1, t->t2, 1, QMG_C64, stream));
     hipLaunchKernelGGL(k_gamma5_scale, dim3(g), dim3(256), 0, s, t->D2, t->t2, t->loss, 0, n);
     QMG_LAUNCH_CHECK();
     return ptc_backward(t, r, s);

@@ -32,6 +32,9 @@ void clear_error();
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Most right-hand sides one call of the field entry points takes (grid dimension y).
+constexpr int kMaxFieldBatch = 1024;
+
 inline int64_t volume(const int d[4]) { return (int64_t)d[0] * d[1] * d[2] * d[3]; }
 
 qmg_status check_dims(const int dims[4], int min_extent, const char* what);

@@ -441,14 +441,18 @@ static qmg_status check_transfer_prec(qmg_transfer t, qmg_prec p, const char* wh
     return QMG_OK;
 }
 
-extern "C" qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, qmg_prec p, void* stream) {
+extern "C" qmg_status qmg_prolong(qmg_transfer t, const void* coarse_in, void* fine_out, int nrhs, qmg_prec p,
+                                  void* stream) {
     if (!t || !coarse_in || !fine_out) return fail(QMG_ERR_ARG, "prolong: NULL argument");
+    if (nrhs < 1 || nrhs > kMaxFieldBatch) return fail(QMG_ERR_ARG, "prolong: nrhs %d not in [1, %d]", nrhs, kMaxFieldBatch);
     QMG_TRY(check_transfer_prec(t, p, "prolong"));
-    return transfer_prolong(t, coarse_in, fine_out, p, 1, as_stream(stream));
+    return transfer_prolong(t, coarse_in, fine_out, p, nrhs, as_stream(stream));
 }
 
-extern "C" qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, qmg_prec p, void* stream) {
+extern "C" qmg_status qmg_restrict(qmg_transfer t, const void* fine_in, void* coarse_out, int nrhs, qmg_prec p,
+                                   void* stream) {
     if (!t || !fine_in || !coarse_out) return fail(QMG_ERR_ARG, "restrict: NULL argument");
+    if (nrhs < 1 || nrhs > kMaxFieldBatch) return fail(QMG_ERR_ARG, "restrict: nrhs %d not in [1, %d]", nrhs, kMaxFieldBatch);
     QMG_TRY(check_transfer_prec(t, p, "restrict"));
-    return transfer_restrict(t, fine_in, coarse_out, p, 1, as_stream(stream));
+    return transfer_restrict(t, fine_in, coarse_out, p, nrhs, as_stream(stream));
 }

@@ -781,16 +781,18 @@ extern "C" qmg_status qmg_fine_op_export_links(qmg_fine_op op, void* gauge, void
     return QMG_OK;
 }
 
-extern "C" qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, qmg_prec prec,
+extern "C" qmg_status qmg_wilson_clover_dslash(qmg_fine_op op, const void* in, void* out, int nrhs, qmg_prec prec,
                                                void* stream) {
     if (!op || !in || !out) return fail(QMG_ERR_ARG, "wilson_clover_dslash: NULL argument");
+    if (nrhs < 1 || nrhs > kMaxFieldBatch)
+        return fail(QMG_ERR_ARG, "wilson_clover_dslash: nrhs %d not in [1, %d]", nrhs, kMaxFieldBatch);
     const bool ok = prec == op->storage || (is16p(op->storage) && prec == QMG_C64);
     if (!ok)
         return fail(QMG_ERR_PREC, "wilson_clover_dslash: vector precision %d does not fit operator storage %d",
                     (int)prec, (int)op->storage);
     if (is16p(prec)) return fail(QMG_ERR_PREC, "wilson_clover_dslash: 16-bit vectors go through wilson_clover_dslash_scaled");
     if (in == out) return fail(QMG_ERR_ARG, "wilson_clover_dslash: in and out alias");
-    return wilson_any(op, in, nullptr, out, nullptr, prec, 1, as_stream(stream));
+    return wilson_any(op, in, nullptr, out, nullptr, prec, nrhs, as_stream(stream));
 }
 
 extern "C" qmg_status qmg_wilson_clover_dslash_scaled(qmg_fine_op op, const void* in, const float* in_scale,

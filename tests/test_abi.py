@@ -59,8 +59,14 @@ def test_coarse_create_rejects_bad_arguments_without_a_device(lib):
         assert not h.value
     st = lib.qmg_coarse_op_create(_lib.c_dims(2, 2, 2, 2), 48, None, fake, 0, None, ctypes.byref(h))
     assert st == 1
-    st = lib.qmg_coarse_dslash(None, fake, fake, 0, None)
+    st = lib.qmg_coarse_dslash(None, fake, fake, 1, 0, None)
     assert st == 1
+    # a right-hand-side count out of range is refused before anything is touched
+    for name in ('qmg_coarse_dslash', 'qmg_wilson_clover_dslash', 'qmg_prolong', 'qmg_restrict'):
+        for nrhs in (0, -3, 1025):
+            st = getattr(lib, name)(fake, fake, ctypes.c_void_p(8), nrhs, 0, None)
+            assert st == 1, (name, nrhs, st)
+            assert b'nrhs' in lib.qmg_last_error()
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

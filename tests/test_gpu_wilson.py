@@ -190,4 +190,4 @@ def test_sixteen_bit_fine_operator_errors():
     for prec in ('c128', 'h16'):
         with pytest.raises(QmgError):
             _lib.call('qmg_wilson_clover_dslash', op._h, ctypes.c_void_p(x.data_ptr()),
-                      ctypes.c_void_p(y.data_ptr()), _lib.PREC[prec], None)
+                      ctypes.c_void_p(y.data_ptr()), 1, _lib.PREC[prec], None)
