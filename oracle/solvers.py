@@ -92,3 +92,44 @@ def gcr(A, b, tol, restart=10, maxit=1000, precond=None, x0=None, info=None):
         r = b - A(x)
         info.converged = norm(r) <= target
     return x, info
+
+
+def bicgstab(A, b, tol, maxit=10000, info=None):
+    """BiCGStab (van der Vorst 1992), the non-symmetric Krylov solver of
+    Sec. 3.3, from x = 0 with the shadow residual r~ = b:
+        rho = <r~, r>;  beta = (rho / rho_old) (alpha / omega)
+        p = r + beta (p - omega v);  v = A p;  alpha = rho / <r~, v>
+        s = r - alpha v;  t = A s;  omega = <t, s> / <t, t>
+        x += alpha p + omega s;  r = s - omega t
+    Stops when |r| <= tol |b| (the recursively updated residual) or after
+    maxit steps; info.iters counts steps (two applications of A each)."""
+    if info is None:
+        info = SolveInfo()
+    x = np.zeros_like(b)
+    r = b.copy()
+    rt = b.copy()
+    bnorm = norm(b)
+    target = tol * bnorm
+    rho_old = alpha = omega = 1.0
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    rn = norm(r)
+    info.history.append(rn)
+    while info.iters < maxit and rn > target:
+        rho = dot(rt, r)
+        beta = (rho / rho_old) * (alpha / omega)
+        p = r + beta * (p - omega * v)
+        v = A(p)
+        alpha = rho / dot(rt, v)
+        s = r - alpha * v
+        t = A(s)
+        tt = dot(t, t).real
+        omega = dot(t, s) / tt if tt > 0 else 0.0
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        rho_old = rho
+        info.iters += 1
+        rn = norm(r)
+        info.history.append(rn)
+    info.converged = norm(b - A(x)) <= target * 10 if bnorm > 0 else True
+    return x, info
