@@ -54,6 +54,14 @@ class Schur:
         v[self.even if p == 0 else self.odd] = half.reshape(-1, self.dof)
         return v
 
+    def embed_even(self, xe):
+        """Whole-lattice field [V][dof] with x_e on the even sites, 0 on the odd."""
+        return self._embed(xe, 0)
+
+    def even_part(self, v):
+        """The even-site half [V/2 * dof] of a whole-lattice field."""
+        return v.reshape(self.V, self.dof)[self.even].reshape(-1)
+
     def _oo_inv(self, vo):
         return np.einsum('xij,xj->xi', self.local_odd_inv, vo.reshape(-1, self.dof))
 

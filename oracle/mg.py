@@ -19,10 +19,24 @@ K-cycle K_0, where on level l
              x += MR_s(r - A_l x)             (post-smoothing)
 Inner tolerances are not given in the paper; readings: relative 0.25 with
 at most 10 steps on intermediate levels and 100 on the coarsest.
+
+Red-black preconditioning on every level (Sec. 7.1, with the Schur
+complement of Sec. 3.3, evenodd.py), option `evenodd`:
+  * smoother: MR_s on the Schur system S x_e = b_e - M_eo M_oo^-1 r_o of the
+    level, then the odd sites back-substituted, x_o = M_oo^-1 (r_o - M_oe x_e);
+    the residual it leaves is zero on the odd sites;
+  * every GCR (the coarse-grid solves and the outer FGCR) runs on the Schur
+    system of its level; a K-cycle preconditioner of level l is applied to
+    the even residual embedded in the whole lattice (odd part zero) and its
+    even part is kept (exact when K_l = A_l^-1, since (A^-1)_ee = S^-1);
+    the odd sites are back-substituted after the solve;
+  * tolerances are relative to the norm of the Schur source; the outer solve
+    stops when the Schur residual reaches tol |b|, which is the whole-lattice
+    residual after the back-substitution.
 """
 import numpy as np
 
-from . import coarse, lattice, solvers, transfer, wilson
+from . import coarse, evenodd, lattice, solvers, transfer, wilson
 
 
 class FineLevel:
@@ -40,6 +54,9 @@ class FineLevel:
     def parent(self):
         return coarse.FineParent(self.U, self.clover, self.m0, self.dims, self.anti)
 
+    def schur(self):
+        return evenodd.fine_schur(self.U, self.clover, self.m0, self.dims, self.anti)
+
 
 class CoarseLevel:
     def __init__(self, op):
@@ -53,6 +70,9 @@ class CoarseLevel:
 
     def parent(self):
         return coarse.CoarseParent(self.op)
+
+    def schur(self):
+        return evenodd.coarse_schur(self.op)
 
 
 def _orth_against(v, basis):
@@ -103,8 +123,11 @@ class Hierarchy:
 
 class KCycle:
     def __init__(self, hier, smoother_steps=4, inner_tol=0.25, inner_maxit=10,
-                 coarsest_tol=0.25, coarsest_maxit=100, smoother=None, coarsest_direct=False):
+                 coarsest_tol=0.25, coarsest_maxit=100, smoother=None, coarsest_direct=False,
+                 evenodd=False):
         self.h = hier
+        self.evenodd = evenodd
+        self._schur = {}
         self.s = smoother_steps
         # coarsest_direct: the exact coarse-grid correction on the coarsest
         # level, x = Mhat^-1 r (a dense LAPACK solve), instead of its GCR
@@ -115,10 +138,31 @@ class KCycle:
         self.smoother = smoother          # optional replacement for MR on level 0
         self.inner_iters = [0] * len(hier.levels)
 
+    def schur(self, l):
+        if l not in self._schur:
+            self._schur[l] = self.h.levels[l].schur()
+        return self._schur[l]
+
     def smooth(self, l, r):
         if l == 0 and self.smoother is not None:
             return self.smoother(r)
+        if self.evenodd:
+            S = self.schur(l)
+            xe = solvers.mr(lambda v: S.apply(v.reshape(-1, S.dof)).reshape(-1), S.source(r).reshape(-1), self.s)
+            return S.reconstruct(xe.reshape(-1, S.dof), r).reshape(r.shape)
         return solvers.mr(self.h.levels[l].apply, r, self.s)
+
+    def schur_gcr(self, l, b, tol, maxit, precond=None, info=None):
+        """GCR(10) on the Schur system of level l for the whole-lattice b,
+        tolerance relative to |source|; returns the whole-lattice solution."""
+        S = self.schur(l)
+        be = S.source(b).reshape(-1)
+        Sa = lambda v: S.apply(v.reshape(-1, S.dof)).reshape(-1)
+        pre = None
+        if precond is not None:
+            pre = lambda re: S.even_part(precond(S.embed_even(re).reshape(-1)))
+        xe, info = solvers.gcr(Sa, be, tol, 10, maxit, precond=pre, info=info)
+        return S.reconstruct(xe.reshape(-1, S.dof), b).reshape(-1), info
 
     def __call__(self, r, l=0):
         A = self.h.levels[l].apply
@@ -133,9 +177,14 @@ class KCycle:
                 self._dense = self.h.levels[nl].op.dense()
             xc = np.linalg.solve(self._dense, rc)
             info.iters = 1
+        elif last and self.evenodd:
+            xc, info = self.schur_gcr(nl, rc, self.coarsest_tol, self.coarsest_maxit, info=info)
         elif last:
             xc, info = solvers.gcr(self.h.levels[nl].apply, rc, self.coarsest_tol, 10,
                                    self.coarsest_maxit, info=info)
+        elif self.evenodd:
+            xc, info = self.schur_gcr(nl, rc, self.inner_tol, self.inner_maxit, precond=lambda z: self(z, nl),
+                                      info=info)
         else:
             xc, info = solvers.gcr(self.h.levels[nl].apply, rc, self.inner_tol, 10,
                                    self.inner_maxit, precond=lambda z: self(z, nl), info=info)
@@ -147,6 +196,17 @@ class KCycle:
 
 def solve(hier, b, tol=1e-10, restart=10, maxit=500, **kcycle_args):
     K = KCycle(hier, **kcycle_args)
-    x, info = solvers.gcr(hier.levels[0].apply, b, tol, restart, maxit, precond=K)
+    if K.evenodd:
+        # outer FGCR on the Schur system, stopping at |r_e| <= tol |b|
+        S = K.schur(0)
+        be = S.source(b).reshape(-1)
+        tol_e = tol * solvers.norm(b) / solvers.norm(be)
+        Sa = lambda v: S.apply(v.reshape(-1, S.dof)).reshape(-1)
+        pre = lambda re: S.even_part(K(S.embed_even(re).reshape(-1)))
+        xe, info = solvers.gcr(Sa, be, tol_e, restart, maxit, precond=pre)
+        x = S.reconstruct(xe.reshape(-1, S.dof), b).reshape(b.shape)
+        info.converged = solvers.norm(b - hier.levels[0].apply(x)) <= tol * solvers.norm(b) * (1 + 1e-6)
+    else:
+        x, info = solvers.gcr(hier.levels[0].apply, b, tol, restart, maxit, precond=K)
     info.inner_iters = K.inner_iters
     return x, info
