@@ -207,6 +207,33 @@ qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, const float
 void qmg_coarse_op_destroy(qmg_coarse_op op);
 
 /* ---------------------------------------------------------------------------
+ * Red-black (even-odd) form of Eq. (3) (Sec. 3.3, used on every level in
+ * Sec. 7.1): with the site-local block X and the hops Y,
+ *     S = X_ee - Y_eo X_oo^-1 Y_oe,   S x_e = b_e - Y_eo X_oo^-1 b_o,
+ *     x_o = X_oo^-1 (b_o - Y_oe x_e).
+ * qmg_coarse_op_prepare_schur builds it (blocks): X_oo^-1 per odd site and the
+ * products X_oo^-1 Y_d in FP64 (Gauss-Jordan elimination with partial
+ * pivoting), stored with the operator's storage as two operators on V/2 sites
+ * (about the size of the operator itself).  Needs every extent even
+ * (QMG_ERR_SHAPE); the other calls return QMG_ERR_STATE before it.
+ * Half-lattice fields [nrhs][V/2][N] (sites of one parity in lattice order),
+ * whole-lattice [nrhs][V][N]; vectors complex128 for QMG_C128 storage and
+ * complex64 otherwise; 1 <= nrhs <= 1024; inputs and outputs must not overlap.
+ * S is two launches over V/2 sites that read 17 of the 18 half-site link
+ * blocks one application of Eq. (3) reads.
+ * ------------------------------------------------------------------------- */
+qmg_status qmg_coarse_op_prepare_schur(qmg_coarse_op op, void* stream);
+/* out_e = S in_e. */
+qmg_status qmg_coarse_dslash_schur(qmg_coarse_op op, const void* in_e, void* out_e, int nrhs, qmg_prec prec,
+                                   void* stream);
+/* bhat_e = b_e - Y_eo X_oo^-1 b_o for whole-lattice b. */
+qmg_status qmg_coarse_schur_source(qmg_coarse_op op, const void* b, void* bhat_e, int nrhs, qmg_prec prec,
+                                   void* stream);
+/* Whole-lattice x: x_e copied, x_o = X_oo^-1 (b_o - Y_oe x_e). */
+qmg_status qmg_coarse_schur_reconstruct(qmg_coarse_op op, const void* x_e, const void* b, void* x, int nrhs,
+                                        qmg_prec prec, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Fine Wilson-clover operator, Eq. (2) (Sec. 3.2):
  *   M psi(x) = (4 + m0 + A(x)) psi(x)
  *       - 1/2 sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
@@ -252,6 +279,35 @@ qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* stream);
 qmg_status qmg_fine_op_export_links(qmg_fine_op op, void* gauge, void* stream);
 
 void qmg_fine_op_destroy(qmg_fine_op op);
+
+/* ---------------------------------------------------------------------------
+ * Red-black (even-odd) form of Eq. (2) (Sec. 3.3; the solver of Sec. 7.1
+ * uses it on every level).  Every hop joins sites of opposite parity
+ * p(x) = (x0 + x1 + x2 + x3) mod 2, so with the site-local block
+ * C(x) = 4 + m0 + A(x) and the hop term D (the sum over mu of Eq. 2, its
+ * -1/2 included) M x = b is solved through the Schur complement on the even
+ * sites,
+ *     S = C_ee - D_eo C_oo^-1 D_oe,   S x_e = b_e - D_eo C_oo^-1 b_o,
+ *     x_o = C_oo^-1 (b_o - D_oe x_e).
+ * Available when every lattice extent is even (QMG_ERR_SHAPE otherwise); the
+ * operator then holds C^-1 (inverted per site in FP64 at creation, stored as
+ * the clover term is).  Half-lattice fields hold the sites of one parity in
+ * lattice order, [nrhs][V/2][4][3] (the half-lattice index of site x is
+ * x >> 1); whole-lattice fields are [nrhs][V][4][3].  Vectors are complex128
+ * for a QMG_C128 operator and complex64 otherwise; 1 <= nrhs <= 1024.  The
+ * calls use a half-lattice scratch the operator owns (grown on first need,
+ * which synchronises the stream).  Inputs and outputs must not overlap.
+ * ------------------------------------------------------------------------- */
+
+/* out_e = S in_e. */
+qmg_status qmg_wilson_clover_schur(qmg_fine_op op, const void* in_e, void* out_e, int nrhs, qmg_prec prec,
+                                   void* stream);
+/* bhat_e = b_e - D_eo C_oo^-1 b_o for whole-lattice b. */
+qmg_status qmg_wilson_clover_schur_source(qmg_fine_op op, const void* b, void* bhat_e, int nrhs, qmg_prec prec,
+                                          void* stream);
+/* Whole-lattice x: x_e copied from the half-lattice x_e, x_o = C_oo^-1 (b_o - D_oe x_e). */
+qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const void* x_e, const void* b, void* x, int nrhs,
+                                               qmg_prec prec, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Transfer operators (Sec. 3.4 step 3, Sec. 6.6).  The near-null vectors are
@@ -388,6 +444,21 @@ qmg_status qmg_mg_gcr_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_p
 qmg_status qmg_mg_gcr_solve_multi(qmg_mg mg, const void* b, void* x, int nrhs, const qmg_solve_params* p,
                                   qmg_solve_info* info, void* stream);
 
+/* Red-black preconditioning on every level (Sec. 7.1, with the Schur
+ * complements of Sec. 3.3), on != 0; 0 switches it off.  With it on: the
+ * smoother of every level is MR on that level's Schur system (the odd sites
+ * back-substituted), every coarse-grid GCR runs on the next level's Schur
+ * system (preconditioned by the even part of its K-cycle applied to (r_e, 0);
+ * an exact coarsest solve, coarse_direct, stays on the whole coarsest
+ * lattice), and the outer FP64 FGCR runs on the fine Schur system, stopping
+ * when that residual reaches tol |b|; x_o is back-substituted at every
+ * reliable update, whose true residual is that of the whole system.  Needs
+ * every extent even on every level (QMG_ERR_SHAPE).  The first call builds
+ * the coarse operators' Schur form (qmg_coarse_op_prepare_schur) and grows
+ * the solve workspace by about half; blocks.  The learned smoother, when
+ * attached, keeps acting on the whole fine lattice. */
+qmg_status qmg_mg_set_evenodd(qmg_mg mg, int on, void* stream);
+
 /* Borrowed views of level l: lattice dims, components per site, its coarse
  * operator (NULL on level 0) and the transfer to level l+1 (NULL on the
  * coarsest).  The handles stay owned by the hierarchy. */
@@ -445,7 +516,8 @@ qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net);
 
 /* As qmg_mg_gcr_solve, and also copy the iterate x_k after each of the first
  * maxrec outer steps into xhist (DEVICE complex128 [maxrec][V][4][3]);
- * *nrec (host) receives the number recorded. */
+ * *nrec (host) receives the number recorded.  QMG_ERR_STATE with the
+ * red-black form on (its outer iterates live on the even sites only). */
 qmg_status qmg_mg_gcr_solve_record(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
                                    qmg_solve_info* info, void* xhist, int maxrec, int* nrec, void* stream);
 

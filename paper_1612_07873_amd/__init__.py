@@ -121,6 +121,43 @@ class CoarseOp:
                   _dev_ptr(oscale, torch.float32, (self.V,), 'out_scale'), PREC[vprec], stream_ptr())
         return out16, oscale
 
+    # red-black form (Sec. 3.3): half-lattice fields [V/2][N] of the even sites
+    def prepare_schur(self):
+        _lib.call('qmg_coarse_op_prepare_schur', self._h, stream_ptr())
+
+    def _vp(self):
+        return self.storage if self.storage in ('c128', 'c64') else 'c64'
+
+    def schur(self, ue, out=None):
+        """S u_e = (X_ee - Y_eo X_oo^-1 Y_oe) u_e for u_e [V/2][N] or [nrhs][V/2][N]."""
+        if out is None:
+            out = torch.empty_like(ue)
+        m, shape = _nrhs(ue, (self.V // 2, self.N), 'in_e')
+        _lib.call('qmg_coarse_dslash_schur', self._h, _dev_ptr(ue, self.dtype, shape, 'in_e'),
+                  _dev_ptr(out, self.dtype, shape, 'out_e'), m, PREC[self._vp()], stream_ptr())
+        return out
+
+    def schur_source(self, b, out=None):
+        """b_e - Y_eo X_oo^-1 b_o for whole-lattice b [V][N] (or [nrhs][V][N])."""
+        m, shape = _nrhs(b, (self.V, self.N), 'b')
+        hshape = shape[:-2] + (self.V // 2, self.N)
+        if out is None:
+            out = torch.empty(hshape, dtype=b.dtype, device=b.device)
+        _lib.call('qmg_coarse_schur_source', self._h, _dev_ptr(b, self.dtype, shape, 'b'),
+                  _dev_ptr(out, self.dtype, hshape, 'bhat_e'), m, PREC[self._vp()], stream_ptr())
+        return out
+
+    def schur_reconstruct(self, xe, b, out=None):
+        """Whole-lattice x: x_e given, x_o = X_oo^-1 (b_o - Y_oe x_e)."""
+        m, shape = _nrhs(b, (self.V, self.N), 'b')
+        hshape = shape[:-2] + (self.V // 2, self.N)
+        if out is None:
+            out = torch.empty_like(b)
+        _lib.call('qmg_coarse_schur_reconstruct', self._h, _dev_ptr(xe, self.dtype, hshape, 'x_e'),
+                  _dev_ptr(b, self.dtype, shape, 'b'), _dev_ptr(out, self.dtype, shape, 'x'), m,
+                  PREC[self._vp()], stream_ptr())
+        return out
+
     def export(self):
         dev = torch.device('cuda')
         X = torch.empty((self.V, self.N, self.N), dtype=torch.complex128, device=dev)
@@ -217,6 +254,40 @@ class FineOp:
                   _dev_ptr(out16, torch.int32, (self.V, 12), 'out'),
                   _dev_ptr(oscale, torch.float32, (self.V,), 'out_scale'), PREC[vprec], stream_ptr())
         return out16, oscale
+
+    # red-black form (Sec. 3.3): half-lattice fields [V/2][4][3] of the even sites
+    def _vp(self):
+        return self.storage if self.storage in ('c128', 'c64') else 'c64'
+
+    def schur(self, pe, out=None):
+        """S p_e = (C_ee - D_eo C_oo^-1 D_oe) p_e, C = 4 + m0 + A, D the hops of Eq. (2)."""
+        if out is None:
+            out = torch.empty_like(pe)
+        m, shape = _nrhs(pe, (self.V // 2, 4, 3), 'in_e')
+        _lib.call('qmg_wilson_clover_schur', self._h, _dev_ptr(pe, self.dtype, shape, 'in_e'),
+                  _dev_ptr(out, self.dtype, shape, 'out_e'), m, PREC[self._vp()], stream_ptr())
+        return out
+
+    def schur_source(self, b, out=None):
+        """b_e - D_eo C_oo^-1 b_o for whole-lattice b [V][4][3] (or [nrhs][V][4][3])."""
+        m, shape = _nrhs(b, (self.V, 4, 3), 'b')
+        hshape = shape[:-3] + (self.V // 2, 4, 3)
+        if out is None:
+            out = torch.empty(hshape, dtype=b.dtype, device=b.device)
+        _lib.call('qmg_wilson_clover_schur_source', self._h, _dev_ptr(b, self.dtype, shape, 'b'),
+                  _dev_ptr(out, self.dtype, hshape, 'bhat_e'), m, PREC[self._vp()], stream_ptr())
+        return out
+
+    def schur_reconstruct(self, xe, b, out=None):
+        """Whole-lattice x: x_e given, x_o = C_oo^-1 (b_o - D_oe x_e)."""
+        m, shape = _nrhs(b, (self.V, 4, 3), 'b')
+        hshape = shape[:-3] + (self.V // 2, 4, 3)
+        if out is None:
+            out = torch.empty_like(b)
+        _lib.call('qmg_wilson_clover_schur_reconstruct', self._h, _dev_ptr(xe, self.dtype, hshape, 'x_e'),
+                  _dev_ptr(b, self.dtype, shape, 'b'), _dev_ptr(out, self.dtype, shape, 'x'), m,
+                  PREC[self._vp()], stream_ptr())
+        return out
 
     def clover(self):
         A = torch.empty((self.V, 12, 12), dtype=torch.complex128, device='cuda')
@@ -435,6 +506,10 @@ class Multigrid:
     def set_smoother(self, net):
         _lib.call('qmg_mg_set_smoother', self._h, net._h if net is not None else None)
         self._smoother = net
+
+    def set_evenodd(self, on=True):
+        """Red-black preconditioning on every level (qmg_mg_set_evenodd)."""
+        _lib.call('qmg_mg_set_evenodd', self._h, int(bool(on)), stream_ptr())
 
     def level(self, l):
         d = _lib.c_dims()

@@ -54,6 +54,13 @@ SIGNATURES = {
     'qmg_restrict': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_transfer_destroy': (None, [c_void_p]),
     'qmg_build_coarse_op': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_wilson_clover_schur': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_wilson_clover_schur_source': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_wilson_clover_schur_reconstruct': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_coarse_op_prepare_schur': (c_int, [c_void_p, c_void_p]),
+    'qmg_coarse_dslash_schur': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_coarse_schur_source': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_coarse_schur_reconstruct': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
 }
 
 
@@ -86,6 +93,7 @@ SIGNATURES.update({
     'qmg_mg_fine_op': (c_int, [c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_destroy': (None, [c_void_p]),
     'qmg_mg_set_smoother': (c_int, [c_void_p, c_void_p]),
+    'qmg_mg_set_evenodd': (c_int, [c_void_p, c_int, c_void_p]),
     'qmg_mg_gcr_solve_record': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
                                         ctypes.POINTER(SolveInfo), c_void_p, c_int, c_int_p, c_void_p]),
     'qmg_mg_make_pairs': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]),

@@ -153,14 +153,23 @@ __global__ __launch_bounds__(256) void k_link_scales(float* __restrict__ lscale,
 }
 
 // ------------------------------------------------------------------ stencil
+// Red-black pieces (EO): the operator is one parity's half of a coarse
+// operator (sites = half-lattice sites, nbr = half-lattice indices of the
+// other parity), and only the directions d0 .. d0+nd-1 of the stacked row
+// [X | Y_0 .. Y_7] are applied: d0 = 1 drops the site-local block, nd = 1
+// keeps only it.  The site-local block multiplies `uself` (at sidx[site], or
+// at site if sidx is NULL, member stride vself sites) and the output goes to
+// oidx[site] (or site; member stride vout), so a piece can read and write
+// whole-lattice fields.
+
 // VF: 0 = vectors in the accumulation precision, else 16-bit pairs (format VF) + per-site scale.
-template <int F, int VF, int PRE>
+template <int F, int VF, int PRE, bool EO = false>
 __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C* __restrict__ L,
                                                         const float* __restrict__ lscale,
                                                         const int* __restrict__ nbr, const void* __restrict__ uin,
                                                         const float* __restrict__ uscale, void* __restrict__ yout,
                                                         float* __restrict__ yscale, int N, int J, int rows, int split,
-                                                        int ntiles, int64_t V) {
+                                                        int ntiles, int64_t V, EoArgs ea) {
     using R = typename Fmt<F>::R;
     using C = typename Fmt<F>::C;
     constexpr int cpc = Fmt<F>::cpc;
@@ -176,8 +185,10 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
     const int rl = t % rows;
     const int s = t / rows;
     const int r = tile * rows + rl;
-    const int K = J / split;
-    const C* Ls = L + (int64_t)site * J * N + r;
+    const int d0 = EO ? ea.d0 : 0;
+    const int nd = EO ? ea.nd : 9;
+    const int K = (EO ? nd * N / cpc : J) / split;
+    const C* Ls = L + ((int64_t)site * J + (EO ? d0 * N / cpc : 0)) * N + r;
 
     // first link chunks in flight before the staging barrier
     C a[PRE];
@@ -185,14 +196,21 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
     for (int q = 0; q < PRE; ++q)
         if (q < K) a[q] = Ls[(int64_t)(s + split * q) * N];
 
-    for (int idx = t; idx < 9 * N; idx += T) {
-        const int d = idx / N;
-        const int c = idx - d * N;
-        const int64_t src = (d == 0 ? site : nbr[site * 8 + d - 1]) + vo;
+    for (int idx = t; idx < nd * N; idx += T) {
+        const int dd = idx / N;
+        const int d = dd + d0;
+        const int c = idx - dd * N;
         cpx<R> v;
-        if constexpr (VF == 0) {
+        if constexpr (EO) {
+            const bool loc = d == 0;
+            const int64_t src = loc ? (ea.sidx ? ea.sidx[site] : site) + (int64_t)blockIdx.y * ea.vself
+                                    : nbr[site * 8 + d - 1] + vo;
+            v = reinterpret_cast<const cpx<R>*>(loc ? ea.uself : uin)[src * N + c];
+        } else if constexpr (VF == 0) {
+            const int64_t src = (d == 0 ? site : nbr[site * 8 + d - 1]) + vo;
             v = reinterpret_cast<const cpx<R>*>(uin)[(int64_t)src * N + c];
         } else {
+            const int64_t src = (d == 0 ? site : nbr[site * 8 + d - 1]) + vo;
             v = dec_pair<VF>(reinterpret_cast<const uint32_t*>(uin)[(int64_t)src * N + c]);
             const float su = uscale[src];
             v.re *= su;
@@ -231,7 +249,10 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
                 si += red[q * rows + rl].im;
             }
     }
-    if constexpr (VF == 0) {
+    if constexpr (EO) {
+        const int64_t o = (ea.oidx ? ea.oidx[site] : site) + (int64_t)blockIdx.y * ea.vout;
+        if (s == 0) reinterpret_cast<cpx<R>*>(yout)[o * N + r] = cpx<R>{sr, si};
+    } else if constexpr (VF == 0) {
         if (s == 0) reinterpret_cast<cpx<R>*>(yout)[(site + vo) * N + r] = cpx<R>{sr, si};
     } else {
         // per-site output scale: all N rows of the site are in this work-group (ntiles == 1)
@@ -359,7 +380,7 @@ static qmg_status launch_f(const qmg_coarse_op_s* op, int rows, int split, int p
     if (pre <= 0) pre = K >= 16 ? 16 : 4;
 #define QMG_CD_LAUNCH(P)                                                                                          \
     hipLaunchKernelGGL((k_coarse_dslash<F, VF, P>), grid, block, lds, s, L, op->lscale, op->nbr, in, in_scale, out, \
-                       out_scale, op->N, op->J, rows, split, ntiles, op->V)
+                       out_scale, op->N, op->J, rows, split, ntiles, op->V, EoArgs{})
     if (pre >= 16) QMG_CD_LAUNCH(16);
     else if (pre >= 8) QMG_CD_LAUNCH(8);
     else if (pre >= 4) QMG_CD_LAUNCH(4);
@@ -390,6 +411,63 @@ qmg_status coarse_dslash_launch(const qmg_coarse_op_s* op, int rows, int split, 
             if (vprec == QMG_H16)
                 return launch_f<FMT_B16, FMT_H16>(op, rows, split, pre, in, in_scale, out, out_scale, m, s);
             return launch_f<FMT_B16, FMT_B16>(op, rows, split, pre, in, in_scale, out, out_scale, m, s);
+    }
+}
+
+// Built-in launch for a piece of nd directions: all rows of a site per
+// work-group (as many as fit 1024 threads), the split the largest divisor of
+// the piece's chunk count that leaves at least 4 chunks per thread and keeps
+// about 2^18 threads in flight.
+void eo_piece_launch(const qmg_coarse_op_s* op, int nd, int* rows, int* split) {
+    const int cpc = complex_per_chunk(op->storage);
+    const int J = nd * op->N / cpc, N = op->N;
+    int best = 1;
+    for (int sp = 1; sp <= J; ++sp) {
+        if (J % sp) continue;
+        if (J / sp < 4) break;
+        if (N * sp > 1024) break;
+        best = sp;
+        if (op->V * N * (int64_t)sp >= ((int64_t)1 << 18)) break;
+    }
+    int rt = N;
+    while (rt * best > 1024 && rt % 2 == 0) rt /= 2;
+    *rows = rt;
+    *split = best;
+}
+
+// One red-black piece on a half operator (vectors complex128 / complex64 as
+// the storage: complex128 for complex128 storage, complex64 otherwise).
+template <int F>
+static qmg_status launch_eo_f(const qmg_coarse_op_s* op, const EoArgs& ea, const void* in, void* out, int m,
+                              hipStream_t s) {
+    using R = typename Fmt<F>::R;
+    int rows, split;
+    eo_piece_launch(op, ea.nd, &rows, &split);
+    const int ntiles = op->N / rows;
+    const size_t lds = sizeof(cpx<R>) * (9 * op->N + std::max(rows * split, rows + 1));
+    const dim3 grid((unsigned)(op->V * ntiles), (unsigned)m), block((unsigned)(rows * split));
+    const auto* L = reinterpret_cast<const typename Fmt<F>::C*>(op->links);
+    const int K = ea.nd * op->N / Fmt<F>::cpc / split;
+    if (K >= 16)
+        hipLaunchKernelGGL((k_coarse_dslash<F, 0, 16, true>), grid, block, lds, s, L, op->lscale, op->nbr, in, nullptr,
+                           out, nullptr, op->N, op->J, rows, split, ntiles, op->V, ea);
+    else
+        hipLaunchKernelGGL((k_coarse_dslash<F, 0, 4, true>), grid, block, lds, s, L, op->lscale, op->nbr, in, nullptr,
+                           out, nullptr, op->N, op->J, rows, split, ntiles, op->V, ea);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+qmg_status coarse_eo_launch(const qmg_coarse_op_s* op, const EoArgs& ea, const void* in, void* out, qmg_prec vprec,
+                            int m, hipStream_t s) {
+    const bool ok = op->storage == QMG_C128 ? vprec == QMG_C128 : vprec == QMG_C64;
+    if (!ok) return fail(QMG_ERR_PREC, "coarse red-black piece: vector precision %d for storage %d", (int)vprec,
+                         (int)op->storage);
+    switch (op->storage) {
+        case QMG_C128: return launch_eo_f<FMT_F64>(op, ea, in, out, m, s);
+        case QMG_C64: return launch_eo_f<FMT_F32>(op, ea, in, out, m, s);
+        case QMG_H16: return launch_eo_f<FMT_H16>(op, ea, in, out, m, s);
+        default: return launch_eo_f<FMT_B16>(op, ea, in, out, m, s);
     }
 }
 
@@ -430,21 +508,16 @@ qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec
 
 using namespace qmg;
 
-extern "C" qmg_status qmg_coarse_op_create(const int dims[4], int N, const void* X, const void* Y,
-                                           qmg_prec storage, void* stream, qmg_coarse_op* out) {
-    if (!out) return fail(QMG_ERR_ARG, "coarse_op_create: out is NULL");
-    *out = nullptr;
-    QMG_TRY(check_dims(dims, 2, "coarse_op_create"));
-    if (N < 2 || N > 128 || (N & 1)) return fail(QMG_ERR_SHAPE, "coarse_op_create: N=%d must be even in [2,128]", N);
-    if (!X || !Y) return fail(QMG_ERR_ARG, "coarse_op_create: X or Y is NULL");
-    if (storage != QMG_C128 && storage != QMG_C64 && storage != QMG_H16 && storage != QMG_B16)
-        return fail(QMG_ERR_PREC, "coarse_op_create: storage %d not supported", (int)storage);
-    if (is16(storage) && N % 4)
-        return fail(QMG_ERR_SHAPE, "coarse_op_create: 16-bit storage needs N %% 4 == 0 (N=%d)", N);
-    hipStream_t s = as_stream(stream);
+namespace qmg {
+// The operator from canonical complex128 X [V][N][N], Y [8][V][N][N] on V
+// sites; nbr: a device neighbour table [V][8] the operator takes over, or NULL
+// to build the lattice's own from dims (V = volume(dims) then).
+qmg_status coarse_op_build(const int dims[4], int64_t V, int N, const void* X, const void* Y, qmg_prec storage,
+                           int* nbr, hipStream_t s, qmg_coarse_op* out) {
     auto* op = new qmg_coarse_op_s();
+    op->nbr = nbr;   // owned from here on, also on failure
     for (int m = 0; m < 4; ++m) op->dims[m] = dims[m];
-    op->V = volume(dims);
+    op->V = V;
     op->N = N;
     op->storage = storage;
     op->J = 9 * N / complex_per_chunk(storage);
@@ -455,7 +528,8 @@ extern "C" qmg_status qmg_coarse_op_create(const int dims[4], int N, const void*
         qmg_coarse_op_destroy(op);
         return fail(QMG_ERR_NOMEM, "coarse_op_create: %zu bytes: %s", bytes, hipGetErrorString(e));
     }
-    qmg_status st = make_neighbour_table(dims, &op->nbr, s);
+    qmg_status st = QMG_OK;
+    if (!nbr) st = make_neighbour_table(dims, &op->nbr, s);
     if (st != QMG_OK) {
         qmg_coarse_op_destroy(op);
         return st;
@@ -482,6 +556,21 @@ extern "C" qmg_status qmg_coarse_op_create(const int dims[4], int N, const void*
     default_launch(op, &op->rows, &op->split);
     *out = op;
     return QMG_OK;
+}
+}  // namespace qmg
+
+extern "C" qmg_status qmg_coarse_op_create(const int dims[4], int N, const void* X, const void* Y,
+                                           qmg_prec storage, void* stream, qmg_coarse_op* out) {
+    if (!out) return fail(QMG_ERR_ARG, "coarse_op_create: out is NULL");
+    *out = nullptr;
+    QMG_TRY(check_dims(dims, 2, "coarse_op_create"));
+    if (N < 2 || N > 128 || (N & 1)) return fail(QMG_ERR_SHAPE, "coarse_op_create: N=%d must be even in [2,128]", N);
+    if (!X || !Y) return fail(QMG_ERR_ARG, "coarse_op_create: X or Y is NULL");
+    if (storage != QMG_C128 && storage != QMG_C64 && storage != QMG_H16 && storage != QMG_B16)
+        return fail(QMG_ERR_PREC, "coarse_op_create: storage %d not supported", (int)storage);
+    if (is16(storage) && N % 4)
+        return fail(QMG_ERR_SHAPE, "coarse_op_create: 16-bit storage needs N %% 4 == 0 (N=%d)", N);
+    return coarse_op_build(dims, volume(dims), N, X, Y, storage, nullptr, as_stream(stream), out);
 }
 
 extern "C" qmg_status qmg_coarse_op_export(qmg_coarse_op op, void* X, void* Y, void* stream) {
@@ -610,5 +699,9 @@ extern "C" void qmg_coarse_op_destroy(qmg_coarse_op op) {
     if (op->mlinks) (void)hipFree(op->mlinks);
     if (op->stage) (void)hipFree(op->stage);
     if (op->nbr) (void)hipFree(op->nbr);
+    if (op->eo_even) qmg_coarse_op_destroy(op->eo_even);
+    if (op->eo_odd) qmg_coarse_op_destroy(op->eo_odd);
+    if (op->hsite) (void)hipFree(op->hsite);
+    if (op->eo_tmp) (void)hipFree(op->eo_tmp);
     delete op;
 }

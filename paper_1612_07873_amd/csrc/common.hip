@@ -53,6 +53,35 @@ qmg_status make_neighbour_table(const int dims[4], int** dev_out, hipStream_t s)
     return QMG_OK;
 }
 
+// Red-black numbering: for each parity p (of x0 + x1 + x2 + x3) the lattice
+// indices of its sites in lattice order, [2][V/2].  With every extent even
+// the half-lattice index of site x is x >> 1 (x0 runs fastest), which the
+// kernels use for neighbours; that is checked here.
+qmg_status make_half_site_table(const int dims[4], int** dev_out, hipStream_t s) {
+    for (int m = 0; m < 4; ++m)
+        if (dims[m] % 2) return fail(QMG_ERR_SHAPE, "red-black form: extent %d of dimension %d is odd", dims[m], m);
+    const int64_t V = volume(dims), Vh = V / 2;
+    std::vector<int> h(V);
+    int64_t cnt[2] = {0, 0};
+    for (int64_t i = 0; i < V; ++i) {
+        int64_t t = i, par = 0;
+        for (int m = 0; m < 4; ++m) { par += t % dims[m]; t /= dims[m]; }
+        const int p = (int)(par & 1);
+        if (cnt[p] != (i >> 1)) return fail(QMG_ERR_SHAPE, "red-black form: half-lattice numbering mismatch");
+        h[p * Vh + cnt[p]++] = (int)i;
+    }
+    int* d = nullptr;
+    QMG_HIP(hipMalloc(&d, sizeof(int) * V));
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(int) * V, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(QMG_ERR_HIP, "half-site table upload: %s", hipGetErrorString(e));
+    }
+    *dev_out = d;
+    return QMG_OK;
+}
+
 const char* last_error() { return g_err; }
 
 }  // namespace qmg

@@ -18,6 +18,15 @@ struct qmg_coarse_op_s {
     int rpw[7];     // multi-RHS: right-hand-side tiles per wave for nrhs = 1,2,4,..,64 (0 = built-in)
     void* stage;    // staging of complex64 batches rounded to 16 bits ([V][nrhs][N] pairs, then [V][nrhs] scales)
     size_t stage_bytes;
+    // red-black form (built by qmg_coarse_op_prepare_schur): the even half
+    // [X_ee | Y_eo] and the odd half [X_oo^-1 | -X_oo^-1 Y_oe] as operators on
+    // V/2 sites whose neighbour tables hold half-lattice indices, and the
+    // lattice index of every half-lattice site of each parity [2][V/2]
+    qmg_coarse_op_s* eo_even = nullptr;
+    qmg_coarse_op_s* eo_odd = nullptr;
+    int* hsite = nullptr;
+    void* eo_tmp = nullptr;    // odd half-lattice scratch of the Schur entry points (grown on demand)
+    size_t eo_tmp_bytes = 0;
 };
 
 struct qmg_fine_op_s {
@@ -31,6 +40,14 @@ struct qmg_fine_op_s {
                  // (16-bit storages: [2][18][V] pairs of those reals)
     float* cscale;  // [2][V] clover scales of the 16-bit storages, else NULL
     int* nbr;    // [V][8]
+    // red-black form (every extent even): inverse of the site-local block
+    // (4 + m0 + A(x))^-1 in the clover's packed layout and storage, and the
+    // lattice index of every half-lattice site of each parity [2][V/2]
+    void* cinv = nullptr;
+    float* ciscale = nullptr;
+    int* hsite = nullptr;
+    void* eo_tmp = nullptr;    // half-lattice scratch of the Schur entry points (grown on demand)
+    size_t eo_tmp_bytes = 0;
 };
 
 struct qmg_transfer_s {
@@ -62,6 +79,18 @@ struct qmg_ptc_s {
 };
 
 namespace qmg {
+// Arguments of a red-black piece of the coarse stencil (coarse_dslash.hip):
+// directions d0 .. d0+nd-1 of the stacked row [X | Y_0 .. Y_7]; the
+// site-local block multiplies `uself` at sidx[site] (or site; member stride
+// vself sites), and the output goes to oidx[site] (or site; stride vout).
+struct EoArgs {
+    const void* uself;
+    const int* sidx;
+    const int* oidx;
+    int d0, nd;
+    int64_t vself, vout;
+};
+
 // Chiral-basis Dirac matrices: gamma_mu = [[0, g_mu], [g_mu^+, 0]] with
 // g_k = -i sigma_k (k = 1..3), g_4 = 1.  gamma(mu, r, c) as (re, im).
 void gamma_matrix(int mu, double out[4][4][2]);

@@ -48,6 +48,23 @@ qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec
 bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m);
 qmg_status dense_inverse(qmg_coarse_op_s* op, qmg_prec prec, void** out, hipStream_t s);
 qmg_status dense_apply(const void* Ainv, const void* b, void* y, int64_t n, int nb, qmg_prec prec, hipStream_t s);
+qmg_status fine_schur_apply(const qmg_fine_op_s* op, const void* in_e, void* out_e, void* tmp_o, qmg_prec vprec,
+                            int m, hipStream_t s);
+qmg_status fine_schur_source(const qmg_fine_op_s* op, const void* b, void* bhat_e, void* tmp_o, qmg_prec vprec,
+                             int m, hipStream_t s);
+qmg_status fine_schur_reconstruct(const qmg_fine_op_s* op, const void* x_e, const void* b, void* x, qmg_prec vprec,
+                                  int m, hipStream_t s);
+qmg_status coarse_schur_apply(const qmg_coarse_op_s* op, const void* in_e, void* out_e, void* tmp_o, qmg_prec vprec,
+                              int m, hipStream_t s);
+qmg_status coarse_schur_source(const qmg_coarse_op_s* op, const void* b, void* bhat_e, void* tmp_o, qmg_prec vprec,
+                               int m, hipStream_t s);
+qmg_status coarse_schur_reconstruct(const qmg_coarse_op_s* op, const void* x_e, const void* b, void* x,
+                                    qmg_prec vprec, int m, hipStream_t s);
+qmg_status coarse_schur_build(qmg_coarse_op_s* op, const void* Xc, const void* Yc, qmg_prec storage, hipStream_t s);
+qmg_status eo_gather(const int* hsite, int64_t Vh, int dof, const void* full, void* half, bool sub, qmg_prec vprec,
+                     int m, hipStream_t s);
+qmg_status eo_scatter(const int* hsite_p, const int* hsite_q, int64_t Vh, int dof, const void* half, void* full,
+                      qmg_prec vprec, int m, hipStream_t s);
 }
 
 using namespace qmg;
@@ -70,6 +87,12 @@ struct Level {
     void* Ainv = nullptr;           // coarsest level solved exactly: dense inverse [n][n] (inner precision)
     void* q16 = nullptr;            // batched 16-bit stencil input [V][nb][N] (multi-RHS matrix-core path)
     float* qsc = nullptr;           // its scales [V][nb]
+    // red-black form: half-lattice fields (n/2 entries per member)
+    void *eb = nullptr, *ex = nullptr, *er = nullptr, *et = nullptr;   // GCR on the Schur system
+    void *eQ = nullptr, *eZ = nullptr;                                 // its Krylov directions
+    void *sb = nullptr, *sx = nullptr, *sr = nullptr, *sAr = nullptr;  // Schur MR smoother
+    void *etmp = nullptr;   // odd half-lattice scratch of the Schur operator
+    void *ekin = nullptr;   // level 0: inner-precision half field of the outer solve
 };
 
 }  // namespace
@@ -96,6 +119,8 @@ struct qmg_mg_s {
     int rec_max = 0, rec_n = 0;
     void* srec = nullptr;       // recording of level-0 smoother inputs (complex64 [maxrec][V][12])
     int srec_max = 0, srec_n = 0;
+    bool eo = false;            // red-black form on every level
+    void *eb64 = nullptr, *ex64 = nullptr, *etmp64 = nullptr;   // outer FP64 Schur source, iterate, scratch
 };
 
 namespace {
@@ -136,6 +161,52 @@ template <typename R> qmg_status apply_op(qmg_mg_s* mg, int l, const void* in, v
     if (l == 0) return wilson_apply(mg->fine_in, in, out, p, mg->nb, mg->s);
     Level& L = mg->lv[l];
     return coarse_apply(L.op, in, out, p, mg->nb, L.q16, L.qsc, mg->s);
+}
+
+// ---------------------------------------------------------------- red-black form
+// On level l the Schur complement S of the level's operator acts on the even
+// half of the lattice (Sec. 3.3): fine level C_ee - D_eo C_oo^-1 D_oe
+// (wilson.hip), coarse levels X_ee - Y_eo X_oo^-1 Y_oe (evenodd.hip).
+const int* level_hsite(qmg_mg_s* mg, int l) { return l == 0 ? mg->fine_in->hsite : mg->lv[l].op->hsite; }
+
+template <typename R> qmg_status schur_apply(qmg_mg_s* mg, int l, const void* in_e, void* out_e) {
+    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    Level& L = mg->lv[l];
+    if (l == 0) return fine_schur_apply(mg->fine_in, in_e, out_e, L.etmp, p, mg->nb, mg->s);
+    return coarse_schur_apply(L.op, in_e, out_e, L.etmp, p, mg->nb, mg->s);
+}
+template <typename R> qmg_status schur_source(qmg_mg_s* mg, int l, const void* b, void* bhat_e) {
+    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    Level& L = mg->lv[l];
+    if (l == 0) return fine_schur_source(mg->fine_in, b, bhat_e, L.etmp, p, mg->nb, mg->s);
+    return coarse_schur_source(L.op, b, bhat_e, L.etmp, p, mg->nb, mg->s);
+}
+template <typename R> qmg_status schur_reconstruct(qmg_mg_s* mg, int l, const void* x_e, const void* b, void* x) {
+    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    if (l == 0) return fine_schur_reconstruct(mg->fine_in, x_e, b, x, p, mg->nb, mg->s);
+    return coarse_schur_reconstruct(mg->lv[l].op, x_e, b, x, p, mg->nb, mg->s);
+}
+
+// The system a GCR iterates on: level l's operator on the whole lattice, or
+// (schur) its Schur complement on the even sites.
+struct Sys {
+    int l;
+    bool schur;
+    int64_t n;                 // complex entries of one member's field
+    void *Q, *Z, *r, *t;       // Krylov directions, residual, scratch
+};
+
+Sys full_sys(qmg_mg_s* mg, int l) {
+    Level& L = mg->lv[l];
+    return Sys{l, false, L.n, L.Q, L.Z, L.r, L.t};
+}
+Sys schur_sys(qmg_mg_s* mg, int l) {
+    Level& L = mg->lv[l];
+    return Sys{l, true, L.n / 2, L.eQ, L.eZ, L.er, L.et};
+}
+
+template <typename R> qmg_status apply_sys(qmg_mg_s* mg, const Sys& sy, const void* in, void* out) {
+    return sy.schur ? schur_apply<R>(mg, sy.l, in, out) : apply_op<R>(mg, sy.l, in, out);
 }
 
 // copy every member's slots [first, first+count) to the host and wait
@@ -193,15 +264,56 @@ template <typename R> qmg_status mr(qmg_mg_s* mg, int l, const void* r, void* x)
     return QMG_OK;
 }
 
-// GCR on level l (l >= 1 uses the level's op; l == 0 with inner precision is
-// used by the setup).  Solves A x = b from x (if x0) or from 0, for every
-// batch member; stops when all members reach tol (or after maxit steps).
-template <typename R>
-qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol, int maxit, bool precond,
-               int* iters_out) {
+// K-cycle preconditioner of a system: K_l(r) on the whole lattice, or for
+// the Schur system the even part of K_l applied to (r_e, 0), which is S^-1 r_e
+// when K_l = A_l^-1.
+template <typename R> qmg_status precond_sys(qmg_mg_s* mg, const Sys& sy, const void* r, void* z) {
+    if (!sy.schur) return kcycle<R>(mg, sy.l, r, z);
+    Level& L = mg->lv[sy.l];
+    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    const int* hs = level_hsite(mg, sy.l);
+    const int64_t Vh = L.V / 2;
+    QMG_TRY(eo_scatter(hs, hs + Vh, Vh, L.dof, r, L.kin, p, mg->nb, mg->s));
+    QMG_TRY(kcycle<R>(mg, sy.l, L.kin, L.kout));
+    return eo_gather(hs, Vh, L.dof, L.kout, z, false, p, mg->nb, mg->s);
+}
+
+// Red-black smoother: MR_s on the Schur system S x_e = r_e - M_eo M_oo^-1 r_o
+// of level l, then x_o = M_oo^-1 (r_o - M_oe x_e).  The residual r - A x it
+// leaves is zero on the odd sites (up to rounding) and the MR residual on the
+// even ones; that is what lv.mr_r receives.
+template <typename R> qmg_status mr_schur(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
-    const int64_t n = L.n;
-    if (L.Ainv) {   // the coarsest level with its dense inverse: x = A^-1 b, one launch
+    const int64_t ne = L.n / 2;
+    const int nb = mg->nb;
+    const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    QMG_TRY(schur_source<R>(mg, l, r, L.sb));
+    for (int it = 0; it < L.p.smoother_steps; ++it) {
+        const void* cur = it == 0 ? L.sb : L.sr;
+        QMG_TRY(schur_apply<R>(mg, l, cur, L.sAr));
+        QMG_TRY(mg->blas.dot_norm<R>(L.sAr, cur, ne, mg->dsc + S_MR));
+        QMG_TRY(mg->blas.mr_update<R>(mg->dsc + S_MR, cur, L.sr, L.sAr, L.sx, it == 0, ne));
+    }
+    if (L.p.smoother_steps <= 0) {
+        QMG_HIP(hipMemsetAsync(L.sx, 0, nb * ne * sizeof(cpx<R>), mg->s));
+        QMG_HIP(hipMemcpyAsync(L.sr, L.sb, nb * ne * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
+    }
+    QMG_TRY(schur_reconstruct<R>(mg, l, L.sx, r, x));
+    const int* hs = level_hsite(mg, l);
+    return eo_scatter(hs, hs + L.V / 2, L.V / 2, L.dof, L.sr, L.mr_r, p, nb, mg->s);
+}
+
+// GCR on a system of level l (l >= 1 uses the level's op; l == 0 with inner
+// precision is used by the setup).  Solves A x = b from x (if x0) or from 0,
+// for every batch member; stops when all members reach tol (or after maxit
+// steps).
+template <typename R>
+qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, double tol, int maxit, bool precond,
+               int* iters_out) {
+    const int l = sy.l;
+    Level& L = mg->lv[l];
+    const int64_t n = sy.n;
+    if (L.Ainv && !sy.schur) {   // the coarsest level with its dense inverse: x = A^-1 b, one launch
         QMG_TRY(dense_apply(L.Ainv, b, x, n, mg->nb, sizeof(R) == 8 ? QMG_C128 : QMG_C64, mg->s));
         if (iters_out) *iters_out += 1;
         return QMG_OK;
@@ -215,11 +327,11 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     QMG_TRY(read_scalars(mg, S_BN, 1));
     for (int k = 0; k < nb; ++k) bnorm[k] = std::sqrt(hs(mg, k, S_BN));
     if (x0) {
-        QMG_TRY(apply_op<R>(mg, l, x, L.t));
-        QMG_TRY(mg->blas.xmy<R>(b, L.t, L.r, n));
+        QMG_TRY(apply_sys<R>(mg, sy, x, sy.t));
+        QMG_TRY(mg->blas.xmy<R>(b, sy.t, sy.r, n));
     } else {
         QMG_HIP(hipMemsetAsync(x, 0, bb, mg->s));
-        QMG_HIP(hipMemcpyAsync(L.r, b, bb, hipMemcpyDeviceToDevice, mg->s));
+        QMG_HIP(hipMemcpyAsync(sy.r, b, bb, hipMemcpyDeviceToDevice, mg->s));
     }
     // all members converged (or broken down: q = 0) after the scalars in slots
     // S_GCR (and rnorm2 at `rslot`) were read.  A member with b = 0 is not
@@ -252,18 +364,18 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
     int launches = 0;   // single-work-group steps queued: the flags of the last one are in slot S_OK + (launches & 1)
     while (!done && iters < maxit) {
         int j = 0;
-        if (small) QMG_HIP(hipMemcpyAsync(L.Z, L.r, bb, hipMemcpyDeviceToDevice, mg->s));
+        if (small) QMG_HIP(hipMemcpyAsync(sy.Z, sy.r, bb, hipMemcpyDeviceToDevice, mg->s));
         for (; j < m && iters < maxit; ++j) {
-            void* z = (char*)L.Z + j * bb;
-            void* q = (char*)L.Q + j * bb;
+            void* z = (char*)sy.Z + j * bb;
+            void* q = (char*)sy.Q + j * bb;
             bool fault = false;
             if (small) {
                 // the step evaluates the stopping test itself (a step queued
                 // after every member has passed it does nothing), so the
                 // scalars are read every kCheck steps and at the end of a cycle
-                QMG_TRY(apply_op<R>(mg, l, z, q));
-                void* znext = j + 1 < m ? (char*)L.Z + (j + 1) * bb : nullptr;
-                QMG_TRY(mg->blas.gcr_step_small<R>(L.Q, L.Z, ld, j, q, z, x, L.r, n, mg->dsc + S_GCR, znext,
+                QMG_TRY(apply_sys<R>(mg, sy, z, q));
+                void* znext = j + 1 < m ? (char*)sy.Z + (j + 1) * bb : nullptr;
+                QMG_TRY(mg->blas.gcr_step_small<R>(sy.Q, sy.Z, ld, j, q, z, x, sy.r, n, mg->dsc + S_GCR, znext,
                                                    tol > 0.0 ? tol : 0.0, S_OK - S_GCR, S_BN - S_GCR,
                                                    launches & 1));
                 ++launches;
@@ -280,15 +392,15 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
                 if (done) { ++j; break; }
                 continue;
             }
-            if (precond) QMG_TRY(kcycle<R>(mg, l, L.r, z));
-            else QMG_HIP(hipMemcpyAsync(z, L.r, bb, hipMemcpyDeviceToDevice, mg->s));
-            QMG_TRY(apply_op<R>(mg, l, z, q));
-            QMG_TRY(orthogonalize<R>(mg, L.Q, L.Z, ld, j, q, z, n));
-            QMG_TRY(mg->blas.dot_norm<R>(q, L.r, n, mg->dsc + S_GCR));
-            QMG_TRY(mg->blas.gcr_update<R>(mg->dsc + S_GCR, q, z, x, L.r, n));
+            if (precond) QMG_TRY(precond_sys<R>(mg, sy, sy.r, z));
+            else QMG_HIP(hipMemcpyAsync(z, sy.r, bb, hipMemcpyDeviceToDevice, mg->s));
+            QMG_TRY(apply_sys<R>(mg, sy, z, q));
+            QMG_TRY(orthogonalize<R>(mg, sy.Q, sy.Z, ld, j, q, z, n));
+            QMG_TRY(mg->blas.dot_norm<R>(q, sy.r, n, mg->dsc + S_GCR));
+            QMG_TRY(mg->blas.gcr_update<R>(mg->dsc + S_GCR, q, z, x, sy.r, n));
             ++iters;
             if (defer && j + 1 < m && iters < maxit) continue;
-            QMG_TRY(mg->blas.norm2<R>(L.r, n, mg->dsc + S_NRM));
+            QMG_TRY(mg->blas.norm2<R>(sy.r, n, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
             done = all_done(S_NRM, &fault);
             if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
@@ -296,8 +408,8 @@ qmg_status gcr(qmg_mg_s* mg, int l, const void* b, void* x, bool x0, double tol,
         }
         if (done || iters >= maxit) break;
         // restart from the true residual
-        QMG_TRY(apply_op<R>(mg, l, x, L.t));
-        QMG_TRY(mg->blas.xmy<R>(b, L.t, L.r, n));
+        QMG_TRY(apply_sys<R>(mg, sy, x, sy.t));
+        QMG_TRY(mg->blas.xmy<R>(b, sy.t, sy.r, n));
     }
     if (iters_out) *iters_out += iters;
     return QMG_OK;
@@ -331,6 +443,7 @@ template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void
         if (bad == 0) return mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n);
         mg->fallbacks += bad;
     }
+    if (mg->eo) return mr_schur<R>(mg, l, r, x);
     return mr<R>(mg, l, r, x);
 }
 
@@ -355,7 +468,14 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     QMG_TRY(transfer_restrict(L.T, L.mr_r, C.b, p, mg->nb, mg->s));
     const bool coarsest = (l + 1 == nl - 1);
     int it = 0;
-    QMG_TRY(gcr<R>(mg, l + 1, C.b, C.x, false, L.p.coarse_tol, L.p.coarse_maxit, !coarsest, &it));
+    if (mg->eo && !C.Ainv) {
+        // red-black: GCR on the next level's Schur system, odd sites back-substituted
+        QMG_TRY(schur_source<R>(mg, l + 1, C.b, C.eb));
+        QMG_TRY(gcr<R>(mg, schur_sys(mg, l + 1), C.eb, C.ex, false, L.p.coarse_tol, L.p.coarse_maxit, !coarsest, &it));
+        QMG_TRY(schur_reconstruct<R>(mg, l + 1, C.ex, C.b, C.x));
+    } else {
+        QMG_TRY(gcr<R>(mg, full_sys(mg, l + 1), C.b, C.x, false, L.p.coarse_tol, L.p.coarse_maxit, !coarsest, &it));
+    }
     mg->level_iters[l + 1] += it;
     QMG_TRY(transfer_prolong(L.T, C.x, L.kt, p, mg->nb, mg->s));
     QMG_TRY(mg->blas.axpy<R>(1.0, L.kt, zout, n));
@@ -388,12 +508,26 @@ qmg_status workspace(qmg_mg_s* mg, int cap) {
             QMG_TRY(salloc(mg, &L.q16, (size_t)L.V * cap * L.dof * 4));
             QMG_TRY(salloc(mg, (void**)&L.qsc, (size_t)L.V * cap * 4));
         }
+        void** half[] = {&L.eb, &L.ex, &L.er, &L.et, &L.sb, &L.sx, &L.sr, &L.sAr, &L.etmp, &L.ekin};
+        for (void** p : half) *p = nullptr;
+        L.eQ = L.eZ = nullptr;
+        if (mg->eo) {
+            for (void** p : half) QMG_TRY(salloc(mg, p, vb / 2));
+            QMG_TRY(salloc(mg, &L.eQ, vb / 2 * mg->restart));
+            QMG_TRY(salloc(mg, &L.eZ, vb / 2 * mg->restart));
+        }
     }
     const size_t vb64 = mg->lv[0].n * 16 * cap;
     QMG_TRY(salloc(mg, &mg->Q64, vb64 * mg->restart));
     QMG_TRY(salloc(mg, &mg->Z64, vb64 * mg->restart));
     QMG_TRY(salloc(mg, &mg->r64, vb64));
     QMG_TRY(salloc(mg, &mg->t64, vb64));
+    mg->eb64 = mg->ex64 = mg->etmp64 = nullptr;
+    if (mg->eo) {
+        QMG_TRY(salloc(mg, &mg->eb64, vb64 / 2));
+        QMG_TRY(salloc(mg, &mg->ex64, vb64 / 2));
+        QMG_TRY(salloc(mg, &mg->etmp64, vb64 / 2));
+    }
     mg->cap = cap;
     return QMG_OK;
 }
@@ -421,7 +555,7 @@ qmg_status setup_level(qmg_mg_s* mg, int l, const void* starts, int setup_iters)
         if (st == QMG_OK && setup_iters > 0) {
             // relax A x = 0 from x = v: b = 0
             st = hipMemsetAsync(L.b, 0, vb, mg->s) == hipSuccess ? QMG_OK : fail(QMG_ERR_HIP, "memset");
-            if (st == QMG_OK) st = gcr<R>(mg, l, L.b, v, true, 0.0, setup_iters, false, nullptr);
+            if (st == QMG_OK) st = gcr<R>(mg, full_sys(mg, l), L.b, v, true, 0.0, setup_iters, false, nullptr);
             if (st == QMG_OK) st = orthogonalize<R>(mg, NV, nullptr, n, k, v, nullptr, n);
         }
         if (st == QMG_OK) st = mg->blas.norm2<R>(v, n, mg->dsc + S_NRM);
@@ -449,9 +583,23 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
     const int nb = mg->nb;
     const size_t vb64 = n * 16;       // one member
     const size_t bb64 = nb * vb64;    // the batch
-    const int64_t ld = (int64_t)nb * n;
     const int m = mg->restart;
     const int nl = (int)mg->lv.size();
+    const qmg_prec pin = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
+    // Red-black form: the outer FGCR runs on the fine Schur system
+    // S x_e = b_e - D_eo C_oo^-1 b_o (fields of n/2 entries), preconditioned by
+    // the even part of K_0 applied to (r_e, 0); x_o is back-substituted at every
+    // reliable update, whose true residual is that of the whole system.
+    const bool eo = mg->eo;
+    const int64_t ns = eo ? n / 2 : n;             // entries of one member's outer field
+    const size_t bbs = nb * ns * 16;               // one outer field of the batch
+    const int64_t ld = (int64_t)nb * ns;
+    const int* hs0 = eo ? mg->fine_in->hsite : nullptr;
+    const int64_t Vh = L0.V / 2;
+    auto outer_apply = [&](const void* in, void* out) -> qmg_status {
+        if (eo) return fine_schur_apply(mg->fine64, in, out, mg->etmp64, QMG_C128, nb, mg->s);
+        return wilson_apply(mg->fine64, in, out, QMG_C128, nb, mg->s);
+    };
     for (int i = 0; i < 8; ++i) mg->level_iters[i] = 0;
     mg->fallbacks = 0;
     mg->rec_n = 0;
@@ -468,41 +616,55 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
         conv[k] = bnorm[k] == 0.0;
         all_conv = all_conv && conv[k];
     }
+    const void* bs = b;   // the outer system's right-hand side and iterate
+    void* xs = x;
     QMG_HIP(hipMemsetAsync(x, 0, bb64, mg->s));
-    QMG_HIP(hipMemcpyAsync(mg->r64, b, bb64, hipMemcpyDeviceToDevice, mg->s));
+    if (eo) {
+        QMG_TRY(fine_schur_source(mg->fine64, b, mg->eb64, mg->etmp64, QMG_C128, nb, mg->s));
+        bs = mg->eb64;
+        xs = mg->ex64;
+        QMG_HIP(hipMemsetAsync(xs, 0, bbs, mg->s));
+    }
+    QMG_HIP(hipMemcpyAsync(mg->r64, bs, bbs, hipMemcpyDeviceToDevice, mg->s));
     int iters = 0, restarts = 0;
     while (!all_conv && iters < sp->maxit) {
         for (int j = 0; j < m && iters < sp->maxit; ++j) {
-            void* z = (char*)mg->Z64 + j * bb64;
-            void* q = (char*)mg->Q64 + j * bb64;
-            if (nl > 1) {
+            void* z = (char*)mg->Z64 + j * bbs;
+            void* q = (char*)mg->Q64 + j * bbs;
+            if (nl > 1 && eo) {
+                QMG_TRY(mg->blas.convert<double, R>(mg->r64, L0.ekin, ns));
+                QMG_TRY(eo_scatter(hs0, hs0 + Vh, Vh, 12, L0.ekin, L0.kin, pin, nb, mg->s));
+                QMG_TRY(kcycle<R>(mg, 0, L0.kin, L0.kout));
+                QMG_TRY(eo_gather(hs0, Vh, 12, L0.kout, L0.ekin, false, pin, nb, mg->s));
+                QMG_TRY(mg->blas.convert<R, double>(L0.ekin, z, ns));
+            } else if (nl > 1) {
                 QMG_TRY(mg->blas.convert<double, R>(mg->r64, L0.kin, n));
                 QMG_TRY(kcycle<R>(mg, 0, L0.kin, L0.kout));
                 QMG_TRY(mg->blas.convert<R, double>(L0.kout, z, n));
             } else {
-                QMG_HIP(hipMemcpyAsync(z, mg->r64, bb64, hipMemcpyDeviceToDevice, mg->s));
+                QMG_HIP(hipMemcpyAsync(z, mg->r64, bbs, hipMemcpyDeviceToDevice, mg->s));
             }
-            QMG_TRY(wilson_apply(mg->fine64, z, q, QMG_C128, nb, mg->s));
+            QMG_TRY(outer_apply(z, q));
             if (j == 0) {
-                QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+                QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, ns, mg->dsc + S_GCR));
             } else {
                 // one projection pass, and a second only if it cancelled more
                 // than half of |q|^2 for some member (the Daniel-Gragg-Kaufman-
                 // Stewart test; the preconditioned directions are nearly
                 // orthogonal already, so the second pass is rarely needed)
-                QMG_TRY(mg->blas.norm2<double>(q, n, mg->dsc + S_QQ));
-                QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, n, 1));
-                QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+                QMG_TRY(mg->blas.norm2<double>(q, ns, mg->dsc + S_QQ));
+                QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, ns, 1));
+                QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, ns, mg->dsc + S_GCR));
                 QMG_TRY(read_scalars(mg, S_GCR, S_QQ + 1 - S_GCR));
                 bool again = false;
                 for (int b = 0; b < nb; ++b) again = again || !(hs(mg, b, S_GCR) >= 0.5 * hs(mg, b, S_QQ));
                 if (again) {
-                    QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, n, 1));
-                    QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, n, mg->dsc + S_GCR));
+                    QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, ns, 1));
+                    QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, ns, mg->dsc + S_GCR));
                 }
             }
-            QMG_TRY(mg->blas.gcr_update<double>(mg->dsc + S_GCR, q, z, x, mg->r64, n));
-            QMG_TRY(mg->blas.norm2<double>(mg->r64, n, mg->dsc + S_NRM));
+            QMG_TRY(mg->blas.gcr_update<double>(mg->dsc + S_GCR, q, z, xs, mg->r64, ns));
+            QMG_TRY(mg->blas.norm2<double>(mg->r64, ns, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
             ++iters;
             if (mg->rec && mg->rec_n < mg->rec_max) {
@@ -517,10 +679,13 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
             }
             if (stop) break;
         }
-        // reliable update: true residual in FP64
+        // reliable update: true residual in FP64 (of the whole system, after
+        // the odd sites are back-substituted in the red-black form)
+        void* rfull = eo ? mg->Q64 : mg->r64;   // the Krylov space is restarted, so Q64 is free
+        if (eo) QMG_TRY(fine_schur_reconstruct(mg->fine64, xs, b, x, QMG_C128, nb, mg->s));
         QMG_TRY(wilson_apply(mg->fine64, x, mg->t64, QMG_C128, nb, mg->s));
-        QMG_TRY(mg->blas.xmy<double>(b, mg->t64, mg->r64, n));
-        QMG_TRY(mg->blas.norm2<double>(mg->r64, n, mg->dsc + S_NRM));
+        QMG_TRY(mg->blas.xmy<double>(b, mg->t64, rfull, n));
+        QMG_TRY(mg->blas.norm2<double>(rfull, n, mg->dsc + S_NRM));
         QMG_TRY(read_scalars(mg, S_NRM, 1));
         all_conv = true;
         for (int k = 0; k < nb; ++k) {
@@ -530,7 +695,13 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
             conv[k] = tr <= sp->tol * bnorm[k];
             all_conv = all_conv && conv[k];
         }
-        if (!all_conv) ++restarts;
+        if (!all_conv) {
+            ++restarts;
+            if (eo) {   // restart from the Schur system's true residual
+                QMG_TRY(outer_apply(xs, mg->t64));
+                QMG_TRY(mg->blas.xmy<double>(bs, mg->t64, mg->r64, ns));
+            }
+        }
     }
     auto t1 = std::chrono::steady_clock::now();
     double worst = 0;
@@ -758,11 +929,33 @@ extern "C" qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net) {
     return QMG_OK;
 }
 
+extern "C" qmg_status qmg_mg_set_evenodd(qmg_mg mg, int on, void* stream) {
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_evenodd: NULL mg");
+    if (!on) {
+        mg->eo = false;
+        return QMG_OK;
+    }
+    if (!mg->fine_in->hsite || !mg->fine64->hsite)
+        return fail(QMG_ERR_SHAPE, "mg_set_evenodd: the red-black form needs every fine extent even");
+    // the Schur form of every coarse operator a GCR or a smoother runs on
+    const int nl = (int)mg->lv.size();
+    for (int l = 1; l < nl; ++l) {
+        Level& L = mg->lv[l];
+        if (L.Ainv || L.op->eo_even) continue;
+        QMG_TRY(qmg_coarse_op_prepare_schur(L.op, stream));
+    }
+    mg->eo = true;
+    const qmg_status st = workspace(mg, mg->cap > 0 ? mg->cap : 1);
+    if (st != QMG_OK) mg->eo = false;
+    return st;
+}
+
 extern "C" qmg_status qmg_mg_gcr_solve_record(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p,
                                               qmg_solve_info* info, void* xhist, int maxrec, int* nrec,
                                               void* stream) {
     if (!xhist || maxrec < 1 || !nrec) return fail(QMG_ERR_ARG, "mg_gcr_solve_record: bad record buffer");
     if (!mg) return fail(QMG_ERR_ARG, "mg_gcr_solve_record: NULL mg");
+    if (mg->eo) return fail(QMG_ERR_STATE, "mg_gcr_solve_record: records the whole-lattice iterates (red-black form off)");
     mg->rec = xhist;
     mg->rec_max = maxrec;
     const qmg_status st = qmg_mg_gcr_solve(mg, b, x, p, info, stream);

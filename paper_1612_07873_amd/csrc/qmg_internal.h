@@ -42,6 +42,10 @@ qmg_status check_dims(const int dims[4], int min_extent, const char* what);
 // Neighbour table [V][8] (d = 2mu forward, 2mu+1 backward, periodic) on the device.
 qmg_status make_neighbour_table(const int dims[4], int** dev_out, hipStream_t s);
 
+// Red-black numbering [2][V/2]: lattice index of each half-lattice site of
+// parity 0, then parity 1 (QMG_ERR_SHAPE unless every extent is even).
+qmg_status make_half_site_table(const int dims[4], int** dev_out, hipStream_t s);
+
 // Launch error check right after a kernel launch.
 #define QMG_LAUNCH_CHECK() QMG_HIP(hipGetLastError())
 

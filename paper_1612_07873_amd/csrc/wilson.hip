@@ -114,6 +114,33 @@ __device__ __forceinline__ void load_clover(R d[6], cpx<R> o[15], const void* __
     }
 }
 
+// acc += H x for a site-local matrix H stored as two packed Hermitian 6x6
+// chirality blocks (the clover term, or the inverse of the site-local block).
+template <int LF, typename R>
+__device__ __forceinline__ void herm_mul_add(cpx<R> acc[12], const cpx<R> x12[12], const void* __restrict__ H,
+                                             const float* __restrict__ hscale, int64_t site, int64_t V) {
+#pragma unroll
+    for (int chi = 0; chi < 2; ++chi) {
+        R d[6];
+        cpx<R> o[15];
+        load_clover<LF>(d, o, H, hscale, chi, site, V);
+        const cpx<R>* x = x12 + 6 * chi;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            cpx<R> t = {d[i] * x[i].re, d[i] * x[i].im};
+            int k = 0;
+#pragma unroll
+            for (int r = 0; r < 6; ++r)
+#pragma unroll
+                for (int c = r + 1; c < 6; ++c, ++k) {
+                    if (r == i) t = cadd(t, cmul(o[k], x[c]));
+                    if (c == i) t = cadd(t, cmulc(o[k], x[r]));
+                }
+            acc[6 * chi + i] = cadd(acc[6 * chi + i], t);
+        }
+    }
+}
+
 // A site's 12 spinor components, with 16-byte loads (3 for 16-bit pairs, 6 in
 // FP32, 12 in FP64).
 template <int VF, typename R>
@@ -175,8 +202,8 @@ __device__ __forceinline__ void store_spinor(void* __restrict__ dst, float* __re
     }
 }
 
-// One hop in direction MU; BACK selects the backward hop.  acc += -1/2 * P (x) W psi(n).
-// vo: offset (in sites) of the batch member's vectors
+// One hop in direction MU; BACK selects the backward hop: the operands of
+// acc += -1/2 * P (x) W psi(n).  vo: offset (in sites) of the batch member's vectors
 template <int MU, bool BACK, int LF, int VF, typename R>
 __device__ __forceinline__ void hop_load(cpx<R> p[12], cpx<R> u[9], const void* __restrict__ in,
                                          const float* __restrict__ in_scale, const void* __restrict__ U, int64_t V,
@@ -185,8 +212,9 @@ __device__ __forceinline__ void hop_load(cpx<R> p[12], cpx<R> u[9], const void* 
     load_link<LF>(u, U, MU, BACK ? n : site, V);
 }
 
+// acc += h * P (x) W psi(n): h = -1/2 is the hop term of Eq. (2)
 template <int MU, bool BACK, typename R>
-__device__ __forceinline__ void hop_apply(cpx<R> acc[12], const cpx<R> p[12], const cpx<R> u[9]) {
+__device__ __forceinline__ void hop_apply(cpx<R> acc[12], const cpx<R> p[12], const cpx<R> u[9], const R h = R(-0.5)) {
     cpx<R> a[2][3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -212,7 +240,6 @@ __device__ __forceinline__ void hop_apply(cpx<R> acc[12], const cpx<R> p[12], co
     for (int c = 0; c < 3; ++c) {
         cpx<R> l0, l1;
         gdmul<MU>(l0, l1, w[0][c], w[1][c]);
-        const R h = R(-0.5);
         acc[c].re += h * w[0][c].re; acc[c].im += h * w[0][c].im;
         acc[3 + c].re += h * w[1][c].re; acc[3 + c].im += h * w[1][c].im;
         if (!BACK) { l0 = cneg(l0); l1 = cneg(l1); }
@@ -261,28 +288,7 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
     load_spinor<VF>(p, in, in_scale, site + vo);
 #pragma unroll
     for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
-    if (use_clover) {
-#pragma unroll
-        for (int chi = 0; chi < 2; ++chi) {
-            R d[6];
-            cpx<R> o[15];
-            load_clover<LF>(d, o, clov, cscale, chi, site, V);
-            const cpx<R>* x = p + 6 * chi;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                cpx<R> t = {d[i] * x[i].re, d[i] * x[i].im};
-                int k = 0;
-#pragma unroll
-                for (int r = 0; r < 6; ++r)
-#pragma unroll
-                    for (int c = r + 1; c < 6; ++c, ++k) {
-                        if (r == i) t = cadd(t, cmul(o[k], x[c]));
-                        if (c == i) t = cadd(t, cmulc(o[k], x[r]));
-                    }
-                acc[6 * chi + i] = cadd(acc[6 * chi + i], t);
-            }
-        }
-    }
+    if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, site, V);
     if constexpr (sizeof(R) == 4) {
         // FP32 arithmetic: the next two hops' operands are loaded while the
         // current two are applied (measured 7-10% faster than one hop at a time)
@@ -347,6 +353,84 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
             for (int j = 0; j < 4; ++j) t += red[threadIdx.x][j];
             part[(int64_t)blockIdx.y * pmember + threadIdx.x * pvalue + blockIdx.x] = t;
         }
+    }
+}
+
+// ------------------------------------------------------------ red-black form
+// Red-black (even-odd) preconditioning (Sec. 3.3, used on every level in
+// Sec. 7.1): the hops of Eq. (2) join sites of opposite parity, so with the
+// site-local block C(x) = 4 + m0 + A(x) and the hop term D (the sum over mu
+// in Eq. 2, its -1/2 included) the Schur complement on the even sites is
+//     S = C_ee - D_eo C_oo^-1 D_oe,
+// and M x = b is solved by S x_e = b_e - D_eo C_oo^-1 b_o followed by
+// x_o = C_oo^-1 (b_o - D_oe x_e).  Every piece is one launch of k_wilson_eo
+// over the sites x of one parity (half-lattice index h, x = hsite[h]):
+//     out(x) = L_out( L_self(self(x)) + coef * [sum of the eight hops of hin](x) )
+// L_self: none (SELF 0), the identity (1) or C(x) (2); L_out: the identity or
+// C(x)^-1 (INV).  coef = 1 gives D, coef = -1 gives -D.  hin is a half-lattice
+// field of the other parity; the neighbour y of x has half index y >> 1,
+// because x0 runs fastest and L0 is even.  self and out are half-lattice
+// fields, or whole-lattice ones indexed by x (self_full, out_full).
+// Member b of a batch (grid dimension y) finds its fields at b*V/2 (half) or
+// b*V (whole) sites.
+template <int LF, int VF, int SELF, bool HOPS, bool INV>
+__global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, const void* __restrict__ clov,
+                                                   const float* __restrict__ cscale, const void* __restrict__ cinv,
+                                                   const float* __restrict__ ciscale, const int* __restrict__ nbr,
+                                                   const int* __restrict__ hsite, const void* __restrict__ self,
+                                                   const void* __restrict__ hin, void* __restrict__ out, int64_t Vh,
+                                                   int64_t V, typename FineT<LF>::R diag, typename FineT<LF>::R coef,
+                                                   int use_clover, int self_full, int out_full) {
+    using R = typename FineT<LF>::R;
+    // XCD-contiguous work-group numbering, as in k_wilson_clover (grid a multiple of 8)
+    const int64_t per = gridDim.x >> 3;
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t h = wg * blockDim.x + threadIdx.x;
+    if (h >= Vh) return;
+    const int64_t site = hsite[h];
+    const int64_t vh = (int64_t)blockIdx.y * Vh, vf = (int64_t)blockIdx.y * V;
+    cpx<R> acc[12];
+    if constexpr (SELF == 0) {
+#pragma unroll
+        for (int f = 0; f < 12; ++f) acc[f] = {R(0), R(0)};
+    } else {
+        cpx<R> p[12];
+        load_spinor<VF>(p, self, nullptr, self_full ? site + vf : h + vh);
+        if constexpr (SELF == 1) {
+#pragma unroll
+            for (int f = 0; f < 12; ++f) acc[f] = p[f];
+        } else {
+#pragma unroll
+            for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
+            if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, site, V);
+        }
+    }
+    if constexpr (HOPS) {
+        const int* nb = nbr + site * 8;
+        const R c = R(-0.5) * coef;
+        cpx<R> p[12], u[9];
+#define QMG_EO_HOP(MU, BACK, D)                                              \
+        load_spinor<VF>(p, hin, nullptr, (int64_t)(nb[D] >> 1) + vh);         \
+        load_link<LF>(u, U, MU, BACK ? (int64_t)nb[D] : site, V);            \
+        hop_apply<MU, BACK>(acc, p, u, c);
+        QMG_EO_HOP(0, false, 0)
+        QMG_EO_HOP(0, true, 1)
+        QMG_EO_HOP(1, false, 2)
+        QMG_EO_HOP(1, true, 3)
+        QMG_EO_HOP(2, false, 4)
+        QMG_EO_HOP(2, true, 5)
+        QMG_EO_HOP(3, false, 6)
+        QMG_EO_HOP(3, true, 7)
+#undef QMG_EO_HOP
+    }
+    if constexpr (INV) {
+        cpx<R> t[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) t[f] = {R(0), R(0)};
+        herm_mul_add<LF>(t, acc, cinv, ciscale, site, V);
+        store_spinor<VF>(out, nullptr, out_full ? site + vf : h + vh, t);
+    } else {
+        store_spinor<VF>(out, nullptr, out_full ? site + vf : h + vh, acc);
     }
 }
 
@@ -450,6 +534,68 @@ __global__ void k_clover_build(R* __restrict__ clov, const double2* __restrict__
                 o[(7 + 2 * k) * V] = (R)A[chi][r][c].im;
             }
     }
+}
+
+// (diag + A(x))^-1 per site and chirality block, in FP64: Gauss-Jordan
+// elimination with partial pivoting on the 6x6 block (Hermitian, so its
+// inverse is too and is stored packed like the clover term, from the upper
+// triangle).  A singular block gives non-finite entries, which the solvers
+// report as QMG_ERR_NONFINITE.
+__global__ void k_clover_invert(double* __restrict__ cinv, const double* __restrict__ clov, int64_t V, double diag) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= V) return;
+    for (int chi = 0; chi < 2; ++chi) {
+        const double* A = clov + (int64_t)chi * 36 * V + x;
+        cpx<double> a[6][6], b[6][6];
+        for (int i = 0; i < 6; ++i)
+            for (int j = 0; j < 6; ++j) b[i][j] = {i == j ? 1.0 : 0.0, 0.0};
+        for (int i = 0; i < 6; ++i) a[i][i] = {diag + A[i * V], 0.0};
+        int k = 0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = r + 1; c < 6; ++c, ++k) {
+                a[r][c] = {A[(6 + 2 * k) * V], A[(7 + 2 * k) * V]};
+                a[c][r] = {a[r][c].re, -a[r][c].im};
+            }
+        for (int col = 0; col < 6; ++col) {
+            int piv = col;
+            double best = a[col][col].re * a[col][col].re + a[col][col].im * a[col][col].im;
+            for (int i = col + 1; i < 6; ++i) {
+                const double m = a[i][col].re * a[i][col].re + a[i][col].im * a[i][col].im;
+                if (m > best) { best = m; piv = i; }
+            }
+            if (piv != col)
+                for (int j = 0; j < 6; ++j) {
+                    const cpx<double> t = a[col][j]; a[col][j] = a[piv][j]; a[piv][j] = t;
+                    const cpx<double> u = b[col][j]; b[col][j] = b[piv][j]; b[piv][j] = u;
+                }
+            // 1 / a[col][col]
+            const cpx<double> p = a[col][col];
+            const double den = p.re * p.re + p.im * p.im;
+            const cpx<double> ip = {p.re / den, -p.im / den};
+            for (int j = 0; j < 6; ++j) { a[col][j] = cmul(ip, a[col][j]); b[col][j] = cmul(ip, b[col][j]); }
+            for (int i = 0; i < 6; ++i) {
+                if (i == col) continue;
+                const cpx<double> f = a[i][col];
+                for (int j = 0; j < 6; ++j) {
+                    a[i][j] = csub(a[i][j], cmul(f, a[col][j]));
+                    b[i][j] = csub(b[i][j], cmul(f, b[col][j]));
+                }
+            }
+        }
+        double* o = cinv + (int64_t)chi * 36 * V + x;
+        for (int i = 0; i < 6; ++i) o[i * V] = b[i][i].re;
+        k = 0;
+        for (int r = 0; r < 6; ++r)
+            for (int c = r + 1; c < 6; ++c, ++k) {
+                o[(6 + 2 * k) * V] = b[r][c].re;
+                o[(7 + 2 * k) * V] = b[r][c].im;
+            }
+    }
+}
+
+__global__ void k_real_to_f32(float* __restrict__ out, const double* __restrict__ in, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = (float)in[i];
 }
 
 template <int LF>
@@ -640,6 +786,79 @@ qmg_status wilson_apply_dot(const qmg_fine_op_s* op, const void* in, void* out, 
     }
 }
 
+// Pieces of the red-black form (k_wilson_eo instances).
+enum EoPiece {
+    EO_HOP_INV = 0,   // out_o = C^-1 D in_e                 (first half of S)
+    EO_DIAG_HOP = 1,  // out_e = C self_e - D in_o           (second half of S)
+    EO_INV = 2,       // out = C^-1 self
+    EO_SELF_HOP = 3,  // out = self - D in
+    EO_RECON = 4,     // out = C^-1 (self - D in)
+    EO_COPY = 5       // out = self (re-indexing between half and whole lattice)
+};
+
+template <int LF, int VF>
+static qmg_status launch_eo(const qmg_fine_op_s* op, int piece, int parity, const void* self, int self_full,
+                            const void* hin, void* out, int out_full, int m, hipStream_t s) {
+    using R = typename FineT<LF>::R;
+    const int64_t Vh = op->V / 2;
+    const unsigned nb = (unsigned)(((Vh + 255) / 256 + 7) / 8 * 8);
+    const int* hs = op->hsite + parity * Vh;
+    const R diag = (R)(4.0 + op->m0);
+    const int uc = op->csw != 0.0 ? 1 : 0;
+    const dim3 grid(nb, (unsigned)m), block(256);
+#define QMG_EO_LAUNCH(SELF, HOPS, INV, COEF)                                                                    \
+    hipLaunchKernelGGL((k_wilson_eo<LF, VF, SELF, HOPS, INV>), grid, block, 0, s, op->U, op->clov, op->cscale,  \
+                       op->cinv, op->ciscale, op->nbr, hs, self, hin, out, Vh, op->V, diag, (R)(COEF), uc,        \
+                       self_full, out_full)
+    switch (piece) {
+        case EO_HOP_INV: QMG_EO_LAUNCH(0, true, true, 1.0); break;
+        case EO_DIAG_HOP: QMG_EO_LAUNCH(2, true, false, -1.0); break;
+        case EO_INV: QMG_EO_LAUNCH(1, false, true, 0.0); break;
+        case EO_SELF_HOP: QMG_EO_LAUNCH(1, true, false, -1.0); break;
+        case EO_RECON: QMG_EO_LAUNCH(1, true, true, -1.0); break;
+        default: QMG_EO_LAUNCH(1, false, false, 0.0);
+    }
+#undef QMG_EO_LAUNCH
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+// One red-black piece with vectors in `vprec` (complex128 for a complex128
+// operator, complex64 for the others).
+static qmg_status fine_eo(const qmg_fine_op_s* op, int piece, int parity, const void* self, int self_full,
+                          const void* hin, void* out, int out_full, qmg_prec vprec, int m, hipStream_t s) {
+    if (!op->hsite) return fail(QMG_ERR_SHAPE, "red-black form needs every lattice extent even");
+    const bool ok = op->storage == QMG_C128 ? vprec == QMG_C128 : vprec == QMG_C64;
+    if (!ok) return fail(QMG_ERR_PREC, "red-black form: vector precision %d for storage %d", (int)vprec, (int)op->storage);
+    switch (op->storage) {
+        case QMG_C128: return launch_eo<FMT_F64, FMT_F64>(op, piece, parity, self, self_full, hin, out, out_full, m, s);
+        case QMG_C64: return launch_eo<FMT_F32, FMT_F32>(op, piece, parity, self, self_full, hin, out, out_full, m, s);
+        case QMG_H16: return launch_eo<FMT_H16, FMT_F32>(op, piece, parity, self, self_full, hin, out, out_full, m, s);
+        default: return launch_eo<FMT_B16, FMT_F32>(op, piece, parity, self, self_full, hin, out, out_full, m, s);
+    }
+}
+
+// out_e = S in_e = C_ee in_e - D_eo C_oo^-1 D_oe in_e; tmp_o: odd half-lattice scratch (m members).
+qmg_status fine_schur_apply(const qmg_fine_op_s* op, const void* in_e, void* out_e, void* tmp_o, qmg_prec vprec,
+                            int m, hipStream_t s) {
+    QMG_TRY(fine_eo(op, EO_HOP_INV, 1, nullptr, 0, in_e, tmp_o, 0, vprec, m, s));
+    return fine_eo(op, EO_DIAG_HOP, 0, in_e, 0, tmp_o, out_e, 0, vprec, m, s);
+}
+
+// bhat_e = b_e - D_eo C_oo^-1 b_o for whole-lattice b.
+qmg_status fine_schur_source(const qmg_fine_op_s* op, const void* b, void* bhat_e, void* tmp_o, qmg_prec vprec,
+                             int m, hipStream_t s) {
+    QMG_TRY(fine_eo(op, EO_INV, 1, b, 1, nullptr, tmp_o, 0, vprec, m, s));
+    return fine_eo(op, EO_SELF_HOP, 0, b, 1, tmp_o, bhat_e, 0, vprec, m, s);
+}
+
+// whole-lattice x: x_e from the Schur solution, x_o = C_oo^-1 (b_o - D_oe x_e).
+qmg_status fine_schur_reconstruct(const qmg_fine_op_s* op, const void* x_e, const void* b, void* x, qmg_prec vprec,
+                                  int m, hipStream_t s) {
+    QMG_TRY(fine_eo(op, EO_RECON, 1, b, 1, x_e, x, 1, vprec, m, s));
+    return fine_eo(op, EO_COPY, 0, x_e, 0, nullptr, x, 1, vprec, m, s);
+}
+
 static size_t real_bytes(qmg_prec p) { return p == QMG_C128 ? 8 : p == QMG_C64 ? 4 : 2; }
 static bool is16p(qmg_prec p) { return p == QMG_H16 || p == QMG_B16; }
 
@@ -671,6 +890,10 @@ extern "C" void qmg_fine_op_destroy(qmg_fine_op op) {
     if (op->clov) (void)hipFree(op->clov);
     if (op->cscale) (void)hipFree(op->cscale);
     if (op->nbr) (void)hipFree(op->nbr);
+    if (op->cinv) (void)hipFree(op->cinv);
+    if (op->ciscale) (void)hipFree(op->ciscale);
+    if (op->hsite) (void)hipFree(op->hsite);
+    if (op->eo_tmp) (void)hipFree(op->eo_tmp);
     delete op;
 }
 
@@ -707,40 +930,80 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
     const int64_t last = op->V - op->V / dims[3];
     const unsigned nbU = (unsigned)((36 * op->V + 255) / 256), nbS = (unsigned)((op->V + 127) / 128);
     const SigmaBlocks sb = sigma_blocks(csw);
+    // red-black form when every extent is even: the half-site table and the
+    // inverse of the site-local block, built from the FP64 clover term
+    const bool eo = dims[0] % 2 == 0 && dims[1] % 2 == 0 && dims[2] % 2 == 0 && dims[3] % 2 == 0;
+    void* c64 = nullptr;   // FP64 clover temporary (16-bit storage, or the red-black inverse of a complex64 one)
+    void* i64 = nullptr;   // FP64 inverse temporary (storages other than complex128)
+    if (eo) {
+        st = make_half_site_table(dims, &op->hsite, s);
+        if (st != QMG_OK) {
+            qmg_fine_op_destroy(op);
+            return st;
+        }
+        e = hipMalloc(&op->cinv, rb * 72 * op->V);
+        if (e == hipSuccess && is16p(storage)) e = hipMalloc(&op->ciscale, sizeof(float) * 2 * op->V);
+        if (e == hipSuccess && storage != QMG_C128) e = hipMalloc(&i64, sizeof(double) * 72 * op->V);
+    }
+    if (e == hipSuccess && (is16p(storage) || (eo && storage == QMG_C64))) e = hipMalloc(&c64, sizeof(double) * 72 * op->V);
+    if (e != hipSuccess) {
+        if (c64) (void)hipFree(c64);
+        if (i64) (void)hipFree(i64);
+        qmg_fine_op_destroy(op);
+        return fail(QMG_ERR_NOMEM, "fine_op_create: clover temporaries: %s", hipGetErrorString(e));
+    }
+    const double diag = 4.0 + m0;
     if (storage == QMG_C128) {
         hipLaunchKernelGGL(k_pack_gauge<double>, dim3(nbU), dim3(256), 0, s, (cpx<double>*)op->U,
                            (const double2*)gauge, op->V, last, op->antiperiodic_t);
         hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)op->clov,
                            (const double2*)gauge, op->nbr, op->V, sb);
+        if (eo)
+            hipLaunchKernelGGL(k_clover_invert, dim3(nbS), dim3(128), 0, s, (double*)op->cinv,
+                               (const double*)op->clov, op->V, diag);
     } else if (storage == QMG_C64) {
         hipLaunchKernelGGL(k_pack_gauge<float>, dim3(nbU), dim3(256), 0, s, (cpx<float>*)op->U,
                            (const double2*)gauge, op->V, last, op->antiperiodic_t);
         hipLaunchKernelGGL(k_clover_build<float>, dim3(nbS), dim3(128), 0, s, (float*)op->clov,
                            (const double2*)gauge, op->nbr, op->V, sb);
+        if (eo) {
+            hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)c64,
+                               (const double2*)gauge, op->nbr, op->V, sb);
+            hipLaunchKernelGGL(k_clover_invert, dim3(nbS), dim3(128), 0, s, (double*)i64, (const double*)c64,
+                               op->V, diag);
+            hipLaunchKernelGGL(k_real_to_f32, dim3((unsigned)((72 * op->V + 255) / 256)), dim3(256), 0, s,
+                               (float*)op->cinv, (const double*)i64, 72 * op->V);
+        }
     } else {
         // the clover term is built in FP64 in a temporary, then scaled per
-        // (chirality, site) and rounded to 16 bits
-        void* c64 = nullptr;
-        e = hipMalloc(&c64, sizeof(double) * 72 * op->V);
-        if (e != hipSuccess) {
-            qmg_fine_op_destroy(op);
-            return fail(QMG_ERR_NOMEM, "fine_op_create: clover temporary: %s", hipGetErrorString(e));
-        }
+        // (chirality, site) and rounded to 16 bits (its inverse likewise)
         hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)c64,
                            (const double2*)gauge, op->nbr, op->V, sb);
+        if (eo)
+            hipLaunchKernelGGL(k_clover_invert, dim3(nbS), dim3(128), 0, s, (double*)i64, (const double*)c64,
+                               op->V, diag);
         if (storage == QMG_H16) {
             hipLaunchKernelGGL(k_pack_gauge16<FMT_H16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
                                (const double2*)gauge, op->V, last, op->antiperiodic_t);
             hipLaunchKernelGGL(k_clover_pack16<FMT_H16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
                                op->cscale, (const double*)c64, op->V);
+            if (eo)
+                hipLaunchKernelGGL(k_clover_pack16<FMT_H16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->cinv,
+                                   op->ciscale, (const double*)i64, op->V);
         } else {
             hipLaunchKernelGGL(k_pack_gauge16<FMT_B16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
                                (const double2*)gauge, op->V, last, op->antiperiodic_t);
             hipLaunchKernelGGL(k_clover_pack16<FMT_B16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
                                op->cscale, (const double*)c64, op->V);
+            if (eo)
+                hipLaunchKernelGGL(k_clover_pack16<FMT_B16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->cinv,
+                                   op->ciscale, (const double*)i64, op->V);
         }
+    }
+    if (c64 || i64) {
         (void)hipStreamSynchronize(s);
-        (void)hipFree(c64);
+        if (c64) (void)hipFree(c64);
+        if (i64) (void)hipFree(i64);
     }
     e = hipGetLastError();
     if (e != hipSuccess) {
@@ -803,4 +1066,58 @@ extern "C" qmg_status qmg_wilson_clover_dslash_scaled(qmg_fine_op op, const void
         return fail(QMG_ERR_PREC, "wilson_clover_dslash_scaled: needs 16-bit operator storage and vectors");
     if (in == out || in_scale == out_scale) return fail(QMG_ERR_ARG, "wilson_clover_dslash_scaled: in and out alias");
     return wilson_any(op, in, in_scale, out, out_scale, prec, 1, as_stream(stream));
+}
+
+// ---------------------------------------------------------- red-black entry points
+static qmg_status schur_checks(qmg_fine_op op, int nrhs, qmg_prec prec, const char* what) {
+    if (!op) return fail(QMG_ERR_ARG, "%s: NULL operator", what);
+    if (!op->hsite) return fail(QMG_ERR_SHAPE, "%s: the red-black form needs every lattice extent even", what);
+    if (nrhs < 1 || nrhs > kMaxFieldBatch) return fail(QMG_ERR_ARG, "%s: nrhs %d not in [1, %d]", what, nrhs, kMaxFieldBatch);
+    const bool ok = op->storage == QMG_C128 ? prec == QMG_C128 : prec == QMG_C64;
+    if (!ok) return fail(QMG_ERR_PREC, "%s: vector precision %d does not fit operator storage %d", what, (int)prec,
+                         (int)op->storage);
+    return QMG_OK;
+}
+
+// the operator's odd half-lattice scratch for nrhs members
+static qmg_status schur_tmp(qmg_fine_op op, int nrhs, qmg_prec prec, hipStream_t s) {
+    const size_t need = (size_t)nrhs * (op->V / 2) * 12 * (prec == QMG_C128 ? 16 : 8);
+    if (op->eo_tmp_bytes >= need) return QMG_OK;
+    if (op->eo_tmp) {
+        QMG_HIP(hipStreamSynchronize(s));
+        (void)hipFree(op->eo_tmp);
+        op->eo_tmp = nullptr;
+        op->eo_tmp_bytes = 0;
+    }
+    QMG_HIP(hipMalloc(&op->eo_tmp, need));
+    op->eo_tmp_bytes = need;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_wilson_clover_schur(qmg_fine_op op, const void* in_e, void* out_e, int nrhs, qmg_prec prec,
+                                              void* stream) {
+    QMG_TRY(schur_checks(op, nrhs, prec, "wilson_clover_schur"));
+    if (!in_e || !out_e) return fail(QMG_ERR_ARG, "wilson_clover_schur: NULL field");
+    if (in_e == out_e) return fail(QMG_ERR_ARG, "wilson_clover_schur: in and out alias");
+    hipStream_t s = as_stream(stream);
+    QMG_TRY(schur_tmp(op, nrhs, prec, s));
+    return fine_schur_apply(op, in_e, out_e, op->eo_tmp, prec, nrhs, s);
+}
+
+extern "C" qmg_status qmg_wilson_clover_schur_source(qmg_fine_op op, const void* b, void* bhat_e, int nrhs,
+                                                     qmg_prec prec, void* stream) {
+    QMG_TRY(schur_checks(op, nrhs, prec, "wilson_clover_schur_source"));
+    if (!b || !bhat_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_source: NULL field");
+    if (b == bhat_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_source: b and bhat alias");
+    hipStream_t s = as_stream(stream);
+    QMG_TRY(schur_tmp(op, nrhs, prec, s));
+    return fine_schur_source(op, b, bhat_e, op->eo_tmp, prec, nrhs, s);
+}
+
+extern "C" qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const void* x_e, const void* b, void* x,
+                                                          int nrhs, qmg_prec prec, void* stream) {
+    QMG_TRY(schur_checks(op, nrhs, prec, "wilson_clover_schur_reconstruct"));
+    if (!x_e || !b || !x) return fail(QMG_ERR_ARG, "wilson_clover_schur_reconstruct: NULL field");
+    if (x == b || x == x_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_reconstruct: x aliases an input");
+    return fine_schur_reconstruct(op, x_e, b, x, prec, nrhs, as_stream(stream));
 }

@@ -1,0 +1,251 @@
+"""GPU parity of the red-black (even-odd) form (Sec. 3.3) against the oracle's
+Schur complement: the Schur operator, its source and the odd-site
+back-substitution, for the fine operator of Eq. (2) and the coarse operator of
+Eq. (3), element by element (FP64 1e-12, FP32 1e-5 relative, max norm), for
+one and several right-hand sides, on lattices whose half volume is not a
+multiple of the work-group size."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import coarse, evenodd, lattice, transfer, wilson
+from gpu_util import dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {'c128': 1e-12, 'c64': 1e-5}
+CDT = {'c128': torch.complex128, 'c64': torch.complex64}
+
+
+def fine_case(dims, eps, seed, m0, csw):
+    U = synth.gauge_field(dims, eps, seed)
+    A = wilson.clover_field(U, dims, csw) if csw != 0 else None
+    return U, A, evenodd.fine_schur(U, A, m0, dims)
+
+
+@pytest.mark.parametrize('prec', ['c128', 'c64'])
+@pytest.mark.parametrize('dims,csw', [((4, 4, 4, 8), 1.0), ((6, 2, 2, 4), 1.3), ((2, 4, 6, 2), 0.0)])
+def test_fine_schur_pieces(prec, dims, csw):
+    from paper_1612_07873_amd import FineOp
+    m0 = -0.2
+    U, A, S = fine_case(dims, 0.4, 1, m0, csw)
+    V = lattice.volume(dims)
+    Vh = V // 2
+    op = FineOp(dims, dev(U), m0, csw, True, prec)
+    nrhs = 3
+    xe = synth.gaussian((nrhs, Vh, 12), 5, 2)
+    b = synth.gaussian((nrhs, V, 12), 6, 2)
+    ref_S = np.stack([S.apply(xe[k]) for k in range(nrhs)])
+    ref_src = np.stack([S.source(b[k]) for k in range(nrhs)])
+    ref_x = np.stack([S.reconstruct(xe[k], b[k]) for k in range(nrhs)])
+    dt = CDT[prec]
+    y = host(op.schur(dev(xe.reshape(nrhs, Vh, 4, 3), dt))).reshape(nrhs, Vh, 12)
+    src = host(op.schur_source(dev(b.reshape(nrhs, V, 4, 3), dt))).reshape(nrhs, Vh, 12)
+    x = host(op.schur_reconstruct(dev(xe.reshape(nrhs, Vh, 4, 3), dt), dev(b.reshape(nrhs, V, 4, 3), dt)))
+    x = x.reshape(nrhs, V, 12)
+    errs = (rel_err(y, ref_S), rel_err(src, ref_src), rel_err(x, ref_x))
+    print(dims, prec, 'S / source / reconstruct rel err', ['%.2e' % e for e in errs])
+    assert max(errs) <= TOL[prec]
+    # one right-hand side through the same entry points
+    y1 = host(op.schur(dev(xe[0].reshape(Vh, 4, 3), dt))).reshape(Vh, 12)
+    assert rel_err(y1, ref_S[0]) <= TOL[prec]
+
+
+def test_fine_schur_full_size_16x16x16x32():
+    """16^3x32 in FP32, checked on the whole half lattice."""
+    from paper_1612_07873_amd import FineOp
+    dims = (16, 16, 16, 32)
+    m0 = -0.1803
+    U, A, S = fine_case(dims, 0.3, 0, m0, 1.0)
+    Vh = lattice.volume(dims) // 2
+    xe = synth.gaussian((Vh, 12), 7, 2)
+    op = FineOp(dims, dev(U), m0, 1.0, True, 'c64')
+    y = host(op.schur(dev(xe.reshape(Vh, 4, 3), torch.complex64))).reshape(Vh, 12)
+    err = rel_err(y, S.apply(xe))
+    print('16^3x32 Schur c64 rel err %.2e' % err)
+    assert err <= 1e-5
+
+
+U_ROUND = {'h16': 2.0 ** -11, 'b16': 2.0 ** -8}
+
+
+@pytest.mark.parametrize('storage', ['h16', 'b16'])
+def test_fine_schur_16bit_storage(storage):
+    """16-bit links, clover and clover inverse: the Schur operator against the
+    FP64 oracle within a few units of the format's rounding."""
+    from paper_1612_07873_amd import FineOp
+    dims, m0 = (4, 4, 4, 8), -0.2
+    U, A, S = fine_case(dims, 0.4, 2, m0, 1.0)
+    Vh = lattice.volume(dims) // 2
+    xe = synth.gaussian((Vh, 12), 8, 2)
+    op = FineOp(dims, dev(U), m0, 1.0, True, storage)
+    y = host(op.schur(dev(xe.reshape(Vh, 4, 3), torch.complex64))).reshape(Vh, 12)
+    ref = S.apply(xe)
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    print(storage, 'Schur norm-wise rel err %.2e (u = %.1e)' % (err, U_ROUND[storage]))
+    assert err <= 8 * U_ROUND[storage]
+
+
+def test_fine_schur_refuses_odd_extent():
+    from paper_1612_07873_amd import FineOp, QmgError
+    dims = (3, 4, 2, 2)
+    U = synth.gauge_field(dims, 0.4, 0)
+    op = FineOp(dims, dev(U), -0.2, 1.0, True, 'c128')
+    Vh = lattice.volume(dims) // 2
+    with pytest.raises(QmgError, match='QMG_ERR_SHAPE'):
+        op.schur(torch.zeros((Vh, 4, 3), dtype=torch.complex128, device='cuda'))
+
+
+def galerkin_op(dims, block, nvec, seed):
+    fd = tuple(d * b for d, b in zip(dims, block))
+    V = lattice.volume(fd)
+    U = synth.gauge_field(fd, 0.4, seed)
+    A = wilson.clover_field(U, fd, 1.0)
+    Vb = transfer.block_orthonormalize(synth.gaussian((nvec, V, 12), seed + 1, 1), fd, block)
+    return coarse.galerkin(coarse.FineParent(U, A, -0.2, fd), Vb, block)
+
+
+def dominant_op(dims, N, seed):
+    """Gaussian hops with a diagonally dominant site-local block."""
+    V = lattice.volume(dims)
+    X = 4.0 * np.eye(N)[None] + 0.3 * synth.gaussian((V, N, N), seed, 2)
+    Y = 0.3 * synth.gaussian((8, V, N, N), seed + 1, 2)
+    return coarse.CoarseOp(dims, X, Y)
+
+
+@pytest.mark.parametrize('prec', ['c128', 'c64'])
+@pytest.mark.parametrize('case', ['galerkin_2x2x2x2_N12', 'dominant_4x2x2x6_N48', 'dominant_2x2x2x4_N64'])
+def test_coarse_schur_pieces(prec, case):
+    from paper_1612_07873_amd import CoarseOp
+    if case.startswith('galerkin'):
+        ref_op = galerkin_op((2, 2, 2, 2), (2, 2, 2, 2), 6, 3)
+    elif case == 'dominant_4x2x2x6_N48':
+        ref_op = dominant_op((4, 2, 2, 6), 48, 4)
+    else:
+        ref_op = dominant_op((2, 2, 2, 4), 64, 5)
+    S = evenodd.coarse_schur(ref_op)
+    dims, N = ref_op.dims, ref_op.N
+    V = lattice.volume(dims)
+    Vh = V // 2
+    op = CoarseOp(dims, dev(ref_op.X), dev(ref_op.Y), prec)
+    op.prepare_schur()
+    nrhs = 2
+    xe = synth.gaussian((nrhs, Vh, N), 9, 2)
+    b = synth.gaussian((nrhs, V, N), 10, 2)
+    dt = CDT[prec]
+    y = host(op.schur(dev(xe, dt)))
+    src = host(op.schur_source(dev(b, dt)))
+    x = host(op.schur_reconstruct(dev(xe, dt), dev(b, dt)))
+    errs = (rel_err(y, np.stack([S.apply(xe[k]) for k in range(nrhs)])),
+            rel_err(src, np.stack([S.source(b[k]) for k in range(nrhs)])),
+            rel_err(x, np.stack([S.reconstruct(xe[k], b[k]) for k in range(nrhs)])))
+    print(case, prec, 'S / source / reconstruct rel err', ['%.2e' % e for e in errs])
+    assert max(errs) <= TOL[prec]
+
+
+def test_coarse_schur_needs_prepare():
+    from paper_1612_07873_amd import CoarseOp, QmgError
+    ref_op = dominant_op((2, 2, 2, 2), 8, 1)
+    op = CoarseOp(ref_op.dims, dev(ref_op.X), dev(ref_op.Y), 'c128')
+    with pytest.raises(QmgError, match='QMG_ERR_STATE'):
+        op.schur(torch.zeros((8, 8), dtype=torch.complex128, device='cuda'))
+
+
+# ------------------------------------------------------------ red-black multigrid
+from oracle import mg as omg, solvers
+
+
+def level_list(blocks, nvecs, setup_iters, coarse_maxit, **extra):
+    return [dict(block=b, nvec=n, setup_iters=setup_iters, smoother_steps=4, coarse_tol=0.25,
+                 coarse_maxit=c, **extra) for b, n, c in zip(blocks, nvecs, coarse_maxit)]
+
+
+def starts_for(dims, blocks, nvecs, seed):
+    out, cur, dof = [], tuple(dims), 12
+    for l, (b, n) in enumerate(zip(blocks, nvecs)):
+        out.append(synth.gaussian((n, lattice.volume(cur), dof), seed + l, 1))
+        cur = tuple(c // bb for c, bb in zip(cur, b))
+        dof = 2 * n
+    return out
+
+
+@pytest.mark.parametrize('inner', ['c128', 'c64'])
+def test_red_black_two_level_matches_oracle_iterations(inner):
+    """Red-black on every level, setup vectors given as data: the GPU and the
+    oracle's red-black K-cycle build the same hierarchy; the FP64 outer
+    iteration counts agree within 1, and the solution reaches 1e-10 under the
+    oracle's M."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (4, 4, 4, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2)], [6]
+    U = synth.gauge_field(dims, 0.4, 1)
+    A = wilson.clover_field(U, dims, 1.0)
+    fine = omg.FineLevel(U, A, m0, dims)
+    st = starts_for(dims, blocks, nvecs, 0)
+    h = omg.Hierarchy(fine, blocks, nvecs, [s.reshape(nvecs[0], -1) for s in st], setup_iters=0)
+    b = synth.gaussian((fine.V, 4, 3), 0, 2)
+    xo, io = omg.solve(h, b.reshape(-1), tol=1e-10, coarsest_maxit=100, evenodd=True)
+    mg = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 0, [100]), [dev(s) for s in st], inner=inner)
+    mg.set_evenodd(True)
+    x, info = mg.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('red-black inner', inner, 'gpu', info, 'oracle iters', io.iters, io.inner_iters, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    if inner == 'c128':
+        assert abs(info['outer_iters'] - io.iters) <= 1
+    else:
+        assert info['outer_iters'] <= io.iters + 2
+    # switching it off gives back the whole-lattice solver
+    mg.set_evenodd(False)
+    _, info_full = mg.solve(dev(b), tol=1e-10)
+    _, io_full = omg.solve(h, b.reshape(-1), tol=1e-10, coarsest_maxit=100)
+    if inner == 'c128':
+        assert abs(info_full['outer_iters'] - io_full.iters) <= 1
+
+
+def test_red_black_three_levels_batch():
+    """Three levels in red-black form with relaxed null vectors; a batch of
+    right-hand sides solved together, each member checked under the oracle's M."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U = synth.gauge_field(dims, 0.3, 2)
+    A = wilson.clover_field(U, dims, 1.0)
+    fine = omg.FineLevel(U, A, m0, dims)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 5)]
+    mg = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 30, [10, 100]), st, inner='c64')
+    B = np.stack([synth.gaussian((fine.V, 4, 3), 30 + k, 2) for k in range(3)])
+    _, full = mg.solve(dev(B[0]), tol=1e-10)
+    mg.set_evenodd(True)
+    x, info = mg.solve(dev(B[0]), tol=1e-10)
+    tr = solvers.norm(B[0].reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(B[0].reshape(-1))
+    print('3-level 8^4 red-black', info, 'whole lattice', full, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    assert info['level_iters'][1] > 0 and info['level_iters'][2] > 0
+    X, infos = mg.solve_multi(dev(B), tol=1e-10)
+    Xh = host(X)
+    for k in range(3):
+        r = solvers.norm(B[k].reshape(-1) - fine.apply(Xh[k].reshape(-1))) / solvers.norm(B[k].reshape(-1))
+        assert infos[k]['converged'] and r <= 1e-10, (k, r)
+
+
+@pytest.mark.parametrize('coarse_direct', [False, True])
+def test_red_black_16x16x16x32_to_1e10(coarse_direct):
+    """The benchmarked 16^3x32 hierarchy with red-black on every level: true
+    residual 1e-10 under the oracle's M, in fewer outer steps than the
+    whole-lattice solve of the same hierarchy."""
+    import bench
+    mg, Ud, m0, _, _ = bench.build_mg_16x32(coarse_direct=coarse_direct)
+    dims = (16, 16, 16, 32)
+    b = synth.gaussian((mg.V, 4, 3), 0, 2)
+    bd = torch.from_numpy(b).to('cuda')
+    _, full = mg.solve(bd, tol=1e-10)
+    mg.set_evenodd(True)
+    x, info = mg.solve(bd, tol=1e-10)
+    U = host(Ud)
+    r = b - wilson.apply_wilson_clover_csw_c(host(x).reshape(b.shape), U, 1.0, m0, dims)
+    tr = float(np.linalg.norm(r) / np.linalg.norm(b))
+    print('16^3x32 red-black direct=%s' % coarse_direct, info, 'whole lattice', full, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    assert info['outer_iters'] <= full['outer_iters']
