@@ -14,7 +14,10 @@ Further records on the same line:
   multi_rhs   the MFMA multi-right-hand-side form, nrhs 8..64, same shapes;
   mg_gcr      MG-GCR time to a true residual of 1e-10 on 16^3x32 (3 levels,
               FP32 inner, FP64 outer, MR smoother): 12 solves, the first
-              discarded, mean and standard deviation of the rest;
+              discarded, mean and standard deviation of the rest; the same
+              with red-black preconditioning on every level; the paper's
+              comparison solver (mixed-precision BiCGStab with reliable
+              updates, red-black) on the same system;
   cpu_baseline the oracle's Eq. (3) apply timed on the host.
 Prints one JSON line.
 """
@@ -328,6 +331,11 @@ def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
     return mg, U, m0, m0_src, time.perf_counter() - t0
 
 
+def torch_sync():
+    import torch
+    torch.cuda.synchronize()
+
+
 def timed_batches(mg, nrhs, nbatches, seed0):
     """Time-to-solution per right-hand side of batched solves (first batch untimed)."""
     import numpy as np
@@ -419,17 +427,27 @@ def learned(npairs, epochs, loss, source='smoother'):
     withnet = timed_solves(mg, 12, 1000)
     mg.set_smoother(None)
     del mg
-    mg16, _, _, _, _ = build_mg_16x32(coarse_storage='h16')
+    # the comparison the method is judged by: 16-bit fine and coarse storage,
+    # 16 right-hand sides at once (matrix-core coarse stencils) and the
+    # learned smoother, against the plain FP32 single-right-hand-side solve
+    mg16, _, _, _, _ = build_mg_16x32(coarse_storage='h16', fine_storage='h16')
     mg16.set_smoother(net)
     combo = timed_batches(mg16, 16, 2, 1000)
     mg16.set_smoother(None)
+    combo_mr = timed_batches(mg16, 16, 2, 1000)
+    del mg16
     combo['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo['time_per_rhs_s'], 3)
+    combo_mr['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo_mr['time_per_rhs_s'], 3)
     return {'lattice': list(dims), 'm0': m0, 'training_data': source, 'pairs': int(R.shape[0]),
             'pair_seconds': round(t_pairs, 2),
             'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
             'train_seconds': round(t_train, 2), 'mg_with_MR': plain, 'mg_with_learned': withnet,
-            'multi_rhs_fp16_coarse_with_learned': combo,
-            'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3)}
+            'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3),
+            'north_star': {'plain': 'FP32 inner, FP64 outer, single right-hand side, MR(4) smoother',
+                           'mixed': 'FP16 fine and coarse storage (FP32 scales, FP32 arithmetic), 16 right-hand '
+                                    'sides per solve, matrix-core coarse stencils, learned level-0 smoother',
+                           'plain_time_to_1e-10_s': plain['time_to_1e-10_s'],
+                           'mixed_with_learned': combo, 'mixed_with_MR': combo_mr}}
 
 
 def fine_and_transfer(steps=200):
@@ -509,13 +527,57 @@ def plain_gcr(maxit=40000):
             'true_rel_residual': info['true_rel_residual']}
 
 
+def bicgstab(U, m0, nsolves=3, dims=(16, 16, 16, 32)):
+    """The paper's comparison solver on the same system: BiCGStab with FP64
+    reliable updates (delta 0.1) on the red-black (Schur) system, iterating
+    with 16-bit links and clover (the paper's half precision) and with FP32
+    storage; the first solve discarded."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_1612_07873_amd import BiCGStab, FineOp
+    hi = FineOp(dims, U, m0, 1.0, True, 'c128')
+    out = {}
+    for name, lo_storage in (('fp16_red_black', 'h16'), ('fp32_red_black', 'c64')):
+        lo = FineOp(dims, U, m0, 1.0, True, lo_storage)
+        solver = BiCGStab(hi, lo, evenodd=True)
+        times, iters, upd, res = [], [], [], []
+        for i in range(nsolves):
+            b = torch.from_numpy(synth.gaussian((int(np.prod(dims)), 4, 3), i, 2)).to('cuda')
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, info = solver.solve(b, tol=1e-10, maxit=40000, delta=0.1)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+            iters.append(info['iters'])
+            upd.append(info['reliable_updates'])
+            res.append(info['true_rel_residual'])
+        t = np.array(times[1:])
+        out[name] = {'time_to_1e-10_s': round(float(t.mean()), 4), 'std_s': round(float(t.std()), 4),
+                     'solves': nsolves, 'iters_mean': float(np.mean(iters[1:])),
+                     'reliable_updates_mean': float(np.mean(upd[1:])), 'max_true_rel_residual': float(max(res))}
+        del solver, lo
+    return out
+
+
 def mg_gcr(nsolves=12, nrhs=16):
     mg, U, m0, m0_src, setup = build_mg_16x32()
     out = {'lattice': [16, 16, 16, 32], 'm0': m0, 'm0_source': m0_src,
            'levels': '16^3x32 -(4^4,Nvec24)-> 4^3x8 N48 -(2^4,Nvec32)-> 2^3x4 N64', 'inner': 'fp32',
            'outer': 'fp64 GCR(10)', 'smoother': 'MR(4)', 'setup_s': round(setup, 2)}
     out.update(timed_solves(mg, nsolves, 0))
+    # red-black preconditioning on every level (Sec. 7.1), same hierarchy
+    t0 = time.perf_counter()
+    mg.set_evenodd(True)
+    torch_sync()
+    rb = {'schur_setup_s': round(time.perf_counter() - t0, 3)}
+    rb.update(timed_solves(mg, nsolves, 0))
+    rb['speedup_vs_whole_lattice'] = round(out['time_to_1e-10_s'] / rb['time_to_1e-10_s'], 3)
+    out['red_black'] = rb
     del mg
+    out['bicgstab'] = bicgstab(U, m0)
+    for k, v in out['bicgstab'].items():
+        v['mg_red_black_speedup'] = round(v['time_to_1e-10_s'] / rb['time_to_1e-10_s'], 2)
     out['plain_gcr'] = plain_gcr()
     out['speedup_vs_plain_gcr'] = round(out['plain_gcr']['time_to_1e-10_s'] / out['time_to_1e-10_s'], 1)
     # mixed precision, several right-hand sides at once: FP16 coarse operators,
@@ -529,6 +591,8 @@ def mg_gcr(nsolves=12, nrhs=16):
     mgd, _, _, _, setupd = build_mg_16x32(coarse_direct=True)
     d = {'setup_s': round(setupd, 2)}
     d.update(timed_solves(mgd, nsolves, 0))
+    mgd.set_evenodd(True)
+    d['red_black'] = timed_solves(mgd, nsolves, 0)
     del mgd
     mgd16, _, _, _, _ = build_mg_16x32(coarse_storage='h16', coarse_direct=True)
     d['multi_rhs_fp16_coarse'] = timed_batches(mgd16, nrhs, 2, 5000)
@@ -546,7 +610,7 @@ def mg_gcr(nsolves=12, nrhs=16):
     return out
 
 
-def precision_form(nsolves=3, dims=(32, 32, 32, 64)):
+def precision_form(nsolves=12, dims=(32, 32, 32, 64)):
     """The 16-bit precision form on 32^3x64 against the plain FP32 inner
     precision, same hierarchy recipe and start vectors: fine links and clover
     and every coarse operator in FP16 (per-(site, block) FP32 scales), FP32
@@ -580,6 +644,11 @@ def precision_form(nsolves=3, dims=(32, 32, 32, 64)):
         r = {'setup_s': round(setup, 2)}
         r.update(timed_solves(mg, nsolves, 0))
         print('precision form: %s %s' % (name, r), file=sys.stderr, flush=True)
+        if name == 'fp16':   # with red-black preconditioning on every level as well (the paper's set-up)
+            mg.set_evenodd(True)
+            r['red_black'] = timed_solves(mg, nsolves, 0)
+            mg.set_evenodd(False)
+            print('precision form: fp16 red-black %s' % r['red_black'], file=sys.stderr, flush=True)
         runs[name] = (mg, r)
     # FP64 operators from the same block bases, and each stored operator's error against them
     mg16 = runs['fp16'][0]
@@ -611,6 +680,8 @@ def precision_form(nsolves=3, dims=(32, 32, 32, 64)):
     out['fp32'] = runs['fp32'][1]
     out['fp16'] = runs['fp16'][1]
     out['speedup_time'] = round(runs['fp32'][1]['time_to_1e-10_s'] / runs['fp16'][1]['time_to_1e-10_s'], 3)
+    out['speedup_time_red_black'] = round(runs['fp32'][1]['time_to_1e-10_s'] /
+                                          runs['fp16'][1]['red_black']['time_to_1e-10_s'], 3)
     return out
 
 
@@ -633,6 +704,8 @@ def main():
                     help='only the 16-bit single-RHS and multi-RHS matrix-core records (rows a6, a7) instead')
     ap.add_argument('--precision-form', action='store_true',
                     help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
+    ap.add_argument('--quick', action='store_true',
+                    help='leave out the learned-smoother and 32^3x64 precision-form records')
     ap.add_argument('--pairs', type=int, default=4096)
     ap.add_argument('--epochs', type=int, default=4)
     ap.add_argument('--loss', choices=['error', 'residual'], default='residual')
@@ -726,11 +799,20 @@ def main():
                          'effective_GB/s': round(byts / (warm_ms * 1e-3) / 1e9, 1)}
     del ops, Xd, Yd
     if not args.only_headline:
-        rec.update(precision_and_mrhs(max(100, args.steps // 4)))
-        rec['small_grids'] = small_grids()
-        rec['multi_level'] = multi_level()
-        rec['fine_and_transfer'] = fine_and_transfer()
-        rec['mg_gcr'] = mg_gcr()
+        def step(name, fn):
+            t0 = time.perf_counter()
+            r = fn()
+            print('bench: %s done in %.1f s' % (name, time.perf_counter() - t0), file=sys.stderr, flush=True)
+            return r
+        rec.update(step('precision and multi_rhs', lambda: precision_and_mrhs(max(100, args.steps // 4))))
+        rec['small_grids'] = step('small_grids', small_grids)
+        rec['multi_level'] = step('multi_level', multi_level)
+        rec['fine_and_transfer'] = step('fine_and_transfer', fine_and_transfer)
+        rec['mg_gcr'] = step('mg_gcr', mg_gcr)
+        if not args.quick:
+            rec['learned_smoother'] = step('learned_smoother',
+                                           lambda: learned(args.pairs, args.epochs, args.loss, args.pairs_from))
+            rec['precision_form'] = step('precision_form', lambda: precision_form(nsolves=12))
     if not args.no_cpu:
         ref, rec['cpu_baseline'] = cpu_baseline(cd, N, X, Y, u)
         rec['parity_rel_err'] = float(np.abs(y - ref).max() / np.abs(ref).max())

@@ -309,6 +309,7 @@ qmg_status qmg_wilson_clover_schur_source(qmg_fine_op op, const void* b, void* b
 qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const void* x_e, const void* b, void* x, int nrhs,
                                                qmg_prec prec, void* stream);
 
+
 /* ---------------------------------------------------------------------------
  * Transfer operators (Sec. 3.4 step 3, Sec. 6.6).  The near-null vectors are
  * cut into hypercubic aggregates of extent block[4]; within each aggregate
@@ -469,6 +470,42 @@ qmg_status qmg_mg_level(qmg_mg mg, int level, int dims[4], int* dof, qmg_coarse_
 qmg_status qmg_mg_fine_op(qmg_mg mg, qmg_fine_op* fine64);
 
 void qmg_mg_destroy(qmg_mg mg);
+
+/* ---------------------------------------------------------------------------
+ * Mixed-precision BiCGStab with reliable updates: the Krylov solver the paper
+ * compares its multigrid with (Sec. 3.3: BiCGStab with red-black
+ * preconditioning; Sec. 7.1: 16-bit precision with FP64 reliable updates).
+ * BiCGStab (van der Vorst) runs with the low-precision operator `lo` and
+ * accumulates a low-precision correction; when the iterated residual falls
+ * below delta times its largest value since the last update (or reaches the
+ * target), the correction is added to the FP64 solution and the true
+ * residual is recomputed with the FP64 operator `hi` and the iteration goes
+ * on from it, keeping its search direction.  It stops when the FP64 true
+ * residual of the iterated system is at most tol |b|; with the red-black form
+ * that system is the fine Schur complement S x_e = b_e - D_eo C_oo^-1 b_o and
+ * x_o is back-substituted in FP64 at the end.  info: outer_iters = BiCGStab
+ * steps (two operator applications each), restarts = reliable updates,
+ * true_rel_residual = |b - M x| / |b| of the whole system (FP64).
+ * ------------------------------------------------------------------------- */
+typedef struct qmg_bicgstab_s* qmg_bicgstab;
+
+typedef struct {
+    double tol;     /* stop when the FP64 true residual <= tol |b| */
+    int maxit;      /* cap on BiCGStab steps */
+    double delta;   /* reliable-update threshold, 0 < delta < 1 (e.g. 0.1) */
+} qmg_bicgstab_params;
+
+/* hi: a QMG_C128 operator; lo: an operator on the same lattice, m0, c_sw and
+ * boundary in any storage (QMG_C128 gives a plain FP64 BiCGStab); both
+ * borrowed.  evenodd != 0 selects the red-black form (every extent even).
+ * Allocates the solver's workspace (about 12 fields). */
+qmg_status qmg_bicgstab_create(qmg_fine_op hi, qmg_fine_op lo, int evenodd, void* stream, qmg_bicgstab* out);
+/* Solve M x = b: b, x DEVICE complex128 [V][4][3] (x overwritten).  Blocks;
+ * QMG_ERR_NOCONV if maxit is reached first, QMG_ERR_NONFINITE on NaN/Inf;
+ * *info (host, may be NULL) is filled in any case. */
+qmg_status qmg_bicgstab_solve(qmg_bicgstab h, const void* b, void* x, const qmg_bicgstab_params* p,
+                              qmg_solve_info* info, void* stream);
+void qmg_bicgstab_destroy(qmg_bicgstab h);
 
 /* ---------------------------------------------------------------------------
  * Learned smoother: a gauge-equivariant parallel-transport convolution

@@ -11,7 +11,7 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['BiCGStab', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
@@ -387,6 +387,39 @@ class _BorrowedTransfer(Transfer):
         self.coarse_dims = tuple(cd)
         self.Vc = _vol(self.coarse_dims)
         self.N = n.value
+
+
+class BiCGStab:
+    """Mixed-precision BiCGStab with FP64 reliable updates (qmg_bicgstab_create):
+    hi is a complex128 FineOp, lo a FineOp of the same operator in the
+    iteration's storage; evenodd selects the red-black (Schur) system."""
+
+    def __init__(self, hi, lo, evenodd=True):
+        self.V = hi.V
+        self._ops = (hi, lo)
+        h = ctypes.c_void_p()
+        _lib.call('qmg_bicgstab_create', hi._h, lo._h, int(bool(evenodd)), stream_ptr(), ctypes.byref(h))
+        self._h = h
+
+    def solve(self, b, x=None, tol=1e-10, maxit=20000, delta=0.1, check=True):
+        if x is None:
+            x = torch.empty_like(b)
+        p = _lib.BicgstabParams(tol=float(tol), maxit=int(maxit), delta=float(delta))
+        info = _lib.SolveInfo()
+        st = _lib.lib().qmg_bicgstab_solve(self._h, _dev_ptr(b, torch.complex128, (self.V, 4, 3), 'b'),
+                                           _dev_ptr(x, torch.complex128, (self.V, 4, 3), 'x'), ctypes.byref(p),
+                                           ctypes.byref(info), stream_ptr())
+        out = {'iters': info.outer_iters, 'reliable_updates': info.restarts, 'converged': bool(info.converged),
+               'true_rel_residual': info.true_rel_residual, 'seconds': info.seconds, 'status': st}
+        if check:
+            _lib.check(st, 'qmg_bicgstab_solve')
+        return x, out
+
+    def __del__(self):
+        h = getattr(self, '_h', None)
+        if h is not None and h.value and _lib._lib is not None:
+            _lib._lib.qmg_bicgstab_destroy(h)
+            self._h = None
 
 
 class Multigrid:

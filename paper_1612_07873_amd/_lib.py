@@ -80,7 +80,15 @@ class SolveInfo(ctypes.Structure):
                 ('true_rel_residual', c_double), ('seconds', c_double), ('smoother_fallbacks', c_int)]
 
 
+class BicgstabParams(ctypes.Structure):
+    _fields_ = [('tol', c_double), ('maxit', c_int), ('delta', c_double)]
+
+
 SIGNATURES.update({
+    'qmg_bicgstab_create': (c_int, [c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_bicgstab_solve': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(BicgstabParams),
+                                   ctypes.POINTER(SolveInfo), c_void_p]),
+    'qmg_bicgstab_destroy': (None, [c_void_p]),
     'qmg_mg_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, ctypes.POINTER(LevelParams),
                               ctypes.POINTER(c_void_p), c_int, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_gcr_solve': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),

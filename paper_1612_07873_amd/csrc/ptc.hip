@@ -7,7 +7,8 @@
 //   (boundary signs folded into the links as in the Wilson-clover operator);
 //   layer: h'_a(x) = sum_b sum_p W[p][a][b] (T_p h_b)(x), W[p][a][b] a complex 4x4 spin matrix;
 //   loss:  L = sum_i |N(r_i) - e_i|^2 / |e_i|^2;
-//   backward: with D = dL/dy*, G[p][a][b] = 2 sum_{x,colour} D_a(x) (T_p h_b)(x)^+,
+//   backward: with D = dL/dy*, G[p][a][b] = 2 sum_{x,colour} D_a(x) (T_p h_b)(x)^+
+//             = 2 sum_{x,colour} (T_p^+ D_a)(x) h_b(x)^+,
 //             dL/dh_b* = sum_p T_p^+ (sum_a W[p][a][b]^+ D_a), T_{+mu}^+ = T_{-mu}.
 // G is reported as dL/dRe W + i dL/dIm W; Adam updates real and imaginary parts.
 // Paths p: 0 = identity, 1 + 2 mu = +mu, 2 + 2 mu = -mu.  Fields [C][V][4][3]
@@ -24,24 +25,32 @@ namespace qmg {
 constexpr int kPtcThreads = 256;
 constexpr int kPtcMaxBlocks = 512;
 
-// (T_p h)(x) for one channel h [V][12], links with folded signs.
-__device__ __forceinline__ void transport(float2 t[12], const float2* __restrict__ h, const float2* __restrict__ U,
-                                          const int* __restrict__ nbr, int64_t V, int64_t x, int p) {
+__device__ __forceinline__ int rev_path(int p) { return p == 0 ? 0 : (((p - 1) & 1) ? p - 1 : p + 1); }
+
+// The spin weights act on spin and the transports on colour and site, so they
+// commute: sum_b W[p][a][b] (T_p h_b) = T_p (sum_b W[p][a][b] h_b).  The
+// kernels below use that to transport each field once per path: a layer with
+// one input channel transports it nine times per site and shares the
+// results among all output channels; a layer with one output channel mixes
+// the input channels first and transports the mixture once per path.  Work-
+// groups cover kPtcSites sites with one thread per (site, path).
+constexpr int kPtcSites = 32;
+constexpr int kPtcFanThreads = kPtcSites * 9;
+
+// T_p applied to the spinor v already read at the neighbour n of x
+__device__ __forceinline__ void transport_vals(float2 t[12], const float2 v[12], const float2* __restrict__ U,
+                                               int64_t V, int64_t x, int64_t n, int p) {
     if (p == 0) {
 #pragma unroll
-        for (int f = 0; f < 12; ++f) t[f] = h[x * 12 + f];
+        for (int f = 0; f < 12; ++f) t[f] = v[f];
         return;
     }
     const int mu = (p - 1) >> 1;
     const bool back = ((p - 1) & 1) != 0;
-    const int64_t n = nbr[x * 8 + 2 * mu + (back ? 1 : 0)];
     const int64_t ls = back ? n : x;
     float2 u[9];
 #pragma unroll
     for (int e = 0; e < 9; ++e) u[e] = U[((int64_t)mu * 9 + e) * V + ls];
-    float2 s[12];
-#pragma unroll
-    for (int f = 0; f < 12; ++f) s[f] = h[n * 12 + f];
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -50,121 +59,214 @@ __device__ __forceinline__ void transport(float2 t[12], const float2* __restrict
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
                 const float2 w = back ? make_float2(u[b * 3 + a].x, -u[b * 3 + a].y) : u[a * 3 + b];
-                const float2 v = s[sp * 3 + b];
-                re += w.x * v.x - w.y * v.y;
-                im += w.x * v.y + w.y * v.x;
+                const float2 q = v[sp * 3 + b];
+                re += w.x * q.x - w.y * q.y;
+                im += w.x * q.y + w.y * q.x;
             }
             t[sp * 3 + a] = make_float2(re, im);
         }
 }
 
-__device__ __forceinline__ int rev_path(int p) { return p == 0 ? 0 : (((p - 1) & 1) ? p - 1 : p + 1); }
-
-// out_a = sum_b sum_p W[p][a][b] T_p h_b ; grid (sites, Cout)
-__global__ void k_ptc_layer(float2* __restrict__ out, const float2* __restrict__ h, const float2* __restrict__ W,
-                            const float2* __restrict__ U, const int* __restrict__ nbr, int64_t V, int cin, int cout) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int a = blockIdx.y;
-    if (x >= V) return;
-    float2 acc[12];
-#pragma unroll
-    for (int f = 0; f < 12; ++f) acc[f] = make_float2(0, 0);
-    for (int b = 0; b < cin; ++b)
-        for (int p = 0; p < 9; ++p) {
-            float2 t[12];
-            transport(t, h + (int64_t)b * V * 12, U, nbr, V, x, p);
-            const float2* w = W + (((int64_t)p * cout + a) * cin + b) * 16;
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float re = acc[s * 3 + c].x, im = acc[s * 3 + c].y;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const float2 m = w[s * 4 + q], v = t[q * 3 + c];
-                        re += m.x * v.x - m.y * v.y;
-                        im += m.x * v.y + m.y * v.x;
-                    }
-                    acc[s * 3 + c] = make_float2(re, im);
-                }
-        }
-#pragma unroll
-    for (int f = 0; f < 12; ++f) out[((int64_t)a * V + x) * 12 + f] = acc[f];
+__device__ __forceinline__ int64_t path_site(const int* __restrict__ nbr, int64_t x, int p) {
+    return p == 0 ? x : nbr[x * 8 + 2 * ((p - 1) >> 1) + ((p - 1) & 1)];
 }
 
-// dL/dh_b* = sum_p T_{rev p} ( sum_a W[p][a][b]^+ D_a ) ; grid (sites, Cin)
-__global__ void k_ptc_back_data(float2* __restrict__ Dh, const float2* __restrict__ D, const float2* __restrict__ W,
-                                const float2* __restrict__ U, const int* __restrict__ nbr, int64_t V, int cin,
-                                int cout) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int b = blockIdx.y;
-    if (x >= V) return;
-    float2 acc[12];
+// One transported input channel h, C output channels:
+//   forward (first layer):           out_a = sum_p W1[p][a][0] (T_p h)
+//   ADJ (data gradient of the second): out_b = sum_p W2[p][0][b]^+ (T_{rev p} h)
+// Both weight arrays index (p, channel) as (p*C + channel)*16.
+template <bool ADJ>
+__global__ __launch_bounds__(kPtcFanThreads) void k_ptc_fan_out(float2* __restrict__ out, const float2* __restrict__ h,
+                                                                const float2* __restrict__ W,
+                                                                const float2* __restrict__ U,
+                                                                const int* __restrict__ nbr, int64_t V, int C) {
+    __shared__ float2 tp[kPtcSites][9][12];
+    const int64_t x0 = (int64_t)blockIdx.x * kPtcSites;
+    const int t = threadIdx.x;
+    {
+        const int sl = t / 9, p = t - (t / 9) * 9;
+        const int64_t x = x0 + sl;
+        if (x < V) {
+            const int q = ADJ ? rev_path(p) : p;
+            const int64_t n = path_site(nbr, x, q);
+            float2 v[12], w[12];
 #pragma unroll
-    for (int f = 0; f < 12; ++f) acc[f] = make_float2(0, 0);
-    for (int p = 0; p < 9; ++p) {
-        const int rp = rev_path(p);
-        for (int a = 0; a < cout; ++a) {
-            // g = W[p][a][b]^+ D_a, then transported by T_{rev p}: transport first (it
-            // acts on colour only), then the spin matrix
-            float2 t[12];
-            transport(t, D + (int64_t)a * V * 12, U, nbr, V, x, rp);
-            const float2* w = W + (((int64_t)p * cout + a) * cin + b) * 16;
+            for (int f = 0; f < 12; ++f) v[f] = h[n * 12 + f];
+            transport_vals(w, v, U, V, x, n, q);
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    float re = acc[s * 3 + c].x, im = acc[s * 3 + c].y;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const float2 m = w[q * 4 + s], v = t[q * 3 + c];   // conj(W[q][s]) * t[q]
-                        re += m.x * v.x + m.y * v.y;
-                        im += m.x * v.y - m.y * v.x;
-                    }
-                    acc[s * 3 + c] = make_float2(re, im);
-                }
+            for (int f = 0; f < 12; ++f) tp[sl][p][f] = w[f];
         }
-    }
-#pragma unroll
-    for (int f = 0; f < 12; ++f) Dh[((int64_t)b * V + x) * 12 + f] = acc[f];
-}
-
-// partial[blk][combo][16] of 2 sum_x sum_c D_a(x)[s][c] conj(T_p h_b(x)[t][c]); grid (blocks, 9*cout*cin)
-__global__ __launch_bounds__(256) void k_ptc_wgrad(double* __restrict__ part, const float2* __restrict__ D,
-                                                   const float2* __restrict__ h, const float2* __restrict__ U,
-                                                   const int* __restrict__ nbr, int64_t V, int cin, int cout) {
-    __shared__ double red[4][32];
-    const int combo = blockIdx.y;
-    const int p = combo / (cout * cin), a = (combo / cin) % cout, b = combo % cin;
-    double acc[32];
-#pragma unroll
-    for (int i = 0; i < 32; ++i) acc[i] = 0;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < V; x += (int64_t)gridDim.x * blockDim.x) {
-        float2 t[12];
-        transport(t, h + (int64_t)b * V * 12, U, nbr, V, x, p);
-        const float2* d = D + ((int64_t)a * V + x) * 12;
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    const float2 dv = d[s * 3 + c], tv = t[q * 3 + c];
-                    acc[2 * (s * 4 + q)] += (double)dv.x * tv.x + (double)dv.y * tv.y;
-                    acc[2 * (s * 4 + q) + 1] += (double)dv.y * tv.x - (double)dv.x * tv.y;
-                }
-    }
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-#pragma unroll
-    for (int i = 0; i < 32; ++i) {
-        double v = acc[i];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-        if (l == 0) red[w][i] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 32) {
-        const double v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
-        part[((int64_t)blockIdx.x * gridDim.y + combo) * 32 + threadIdx.x] = 2.0 * v;
+    for (int idx = t; idx < kPtcSites * C; idx += kPtcFanThreads) {
+        const int sl = idx % kPtcSites, a = idx / kPtcSites;
+        const int64_t x = x0 + sl;
+        if (x >= V) continue;
+        float2 acc[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) acc[f] = make_float2(0, 0);
+        for (int p = 0; p < 9; ++p) {
+            const float2* w = W + ((int64_t)p * C + a) * 16;
+#pragma unroll
+            for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    float re = acc[sp * 3 + c].x, im = acc[sp * 3 + c].y;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const float2 v = tp[sl][p][q * 3 + c];
+                        if (ADJ) {   // conj(W[q][sp]) v
+                            const float2 m = w[q * 4 + sp];
+                            re += m.x * v.x + m.y * v.y;
+                            im += m.x * v.y - m.y * v.x;
+                        } else {
+                            const float2 m = w[sp * 4 + q];
+                            re += m.x * v.x - m.y * v.y;
+                            im += m.x * v.y + m.y * v.x;
+                        }
+                    }
+                    acc[sp * 3 + c] = make_float2(re, im);
+                }
+        }
+#pragma unroll
+        for (int f = 0; f < 12; ++f) out[((int64_t)a * V + x) * 12 + f] = acc[f];
+    }
+}
+
+// C input channels h [C][V][12], one output: out = sum_p T_p (sum_b W2[p][0][b] h_b)
+__global__ __launch_bounds__(kPtcFanThreads) void k_ptc_fan_in(float2* __restrict__ out, const float2* __restrict__ h,
+                                                               const float2* __restrict__ W,
+                                                               const float2* __restrict__ U,
+                                                               const int* __restrict__ nbr, int64_t V, int C) {
+    __shared__ float2 cp[kPtcSites][9][12];
+    const int64_t x0 = (int64_t)blockIdx.x * kPtcSites;
+    const int t = threadIdx.x;
+    {
+        const int sl = t / 9, p = t - (t / 9) * 9;
+        const int64_t x = x0 + sl;
+        if (x < V) {
+            const int64_t n = path_site(nbr, x, p);
+            float2 g[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) g[f] = make_float2(0, 0);
+            for (int b = 0; b < C; ++b) {
+                const float2* w = W + ((int64_t)p * C + b) * 16;
+                float2 v[12];
+#pragma unroll
+                for (int f = 0; f < 12; ++f) v[f] = h[((int64_t)b * V + n) * 12 + f];
+#pragma unroll
+                for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float re = g[sp * 3 + c].x, im = g[sp * 3 + c].y;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const float2 m = w[sp * 4 + q], vv = v[q * 3 + c];
+                            re += m.x * vv.x - m.y * vv.y;
+                            im += m.x * vv.y + m.y * vv.x;
+                        }
+                        g[sp * 3 + c] = make_float2(re, im);
+                    }
+            }
+            float2 w2[12];
+            transport_vals(w2, g, U, V, x, n, p);
+#pragma unroll
+            for (int f = 0; f < 12; ++f) cp[sl][p][f] = w2[f];
+        }
+    }
+    __syncthreads();
+    for (int idx = t; idx < kPtcSites * 12; idx += kPtcFanThreads) {
+        const int sl = idx / 12, f = idx - (idx / 12) * 12;
+        const int64_t x = x0 + sl;
+        if (x >= V) continue;
+        float re = 0, im = 0;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            re += cp[sl][p][f].x;
+            im += cp[sl][p][f].y;
+        }
+        out[x * 12 + f] = make_float2(re, im);
+    }
+}
+
+// Weight gradient against one transported field (tr, 1 channel) and one
+// C-channel field (mc), G[p][k](s,t) = 2 sum_{x,c} L(x)[s][c] conj(R(x)[t][c]):
+//   TR_LEFT (second layer, G2[p][0][k]): L = T_{rev p} tr (tr = D), R = mc_k (h1);
+//   else    (first layer,  G1[p][k][0]): L = mc_k (D1), R = T_p tr (tr = r).
+// Each work-group walks chunks of kPtcSites sites: per chunk the nine
+// transports per site and the C channels of the chunk's sites go to LDS, and
+// each thread accumulates its fixed set of (p, k, s, t) entries in FP64;
+// per-work-group partials part[blk][9*C][32] are summed in a fixed order.
+template <bool TR_LEFT>
+__global__ __launch_bounds__(kPtcFanThreads) void k_ptc_wgrad_fan(double* __restrict__ part,
+                                                                  const float2* __restrict__ tr,
+                                                                  const float2* __restrict__ mc,
+                                                                  const float2* __restrict__ U,
+                                                                  const int* __restrict__ nbr, int64_t V, int C) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float2 (*tp)[9][12] = reinterpret_cast<float2 (*)[9][12]>(smem);
+    float2* ms = reinterpret_cast<float2*>(smem + sizeof(float2) * kPtcSites * 9 * 12);   // [C][kPtcSites][12]
+    const int t = threadIdx.x;
+    const int ncombo = 9 * C * 16;
+    constexpr int kMaxPer = 8;   // combos per thread (C <= 16)
+    double acc[kMaxPer][2];
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) acc[j][0] = acc[j][1] = 0;
+    const int64_t nchunks = (V + kPtcSites - 1) / kPtcSites;
+    for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
+        const int64_t x0 = ch * kPtcSites;
+        __syncthreads();   // the previous chunk's LDS reads are done
+        {
+            const int sl = t / 9, p = t - (t / 9) * 9;
+            const int64_t x = x0 + sl;
+            float2 w[12];
+            if (x < V) {
+                const int q = TR_LEFT ? rev_path(p) : p;
+                const int64_t n = path_site(nbr, x, q);
+                float2 v[12];
+#pragma unroll
+                for (int f = 0; f < 12; ++f) v[f] = tr[n * 12 + f];
+                transport_vals(w, v, U, V, x, n, q);
+            } else {
+#pragma unroll
+                for (int f = 0; f < 12; ++f) w[f] = make_float2(0, 0);
+            }
+#pragma unroll
+            for (int f = 0; f < 12; ++f) tp[sl][p][f] = w[f];
+        }
+        for (int idx = t; idx < C * kPtcSites * 12; idx += kPtcFanThreads) {
+            const int f = idx % 12, sl = (idx / 12) % kPtcSites, k = idx / (12 * kPtcSites);
+            const int64_t x = x0 + sl;
+            ms[idx] = x < V ? mc[((int64_t)k * V + x) * 12 + f] : make_float2(0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMaxPer; ++j) {
+            const int cidx = t + j * kPtcFanThreads;
+            if (cidx >= ncombo) break;
+            const int p = cidx / (C * 16), k = (cidx / 16) % C, sp = (cidx / 4) % 4, tt = cidx % 4;
+            double re = 0, im = 0;
+            for (int sl = 0; sl < kPtcSites; ++sl) {
+                const float2* m = ms + ((int64_t)k * kPtcSites + sl) * 12;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float2 l = TR_LEFT ? tp[sl][p][sp * 3 + c] : m[sp * 3 + c];
+                    const float2 r = TR_LEFT ? m[tt * 3 + c] : tp[sl][p][tt * 3 + c];
+                    re += (double)l.x * r.x + (double)l.y * r.y;
+                    im += (double)l.y * r.x - (double)l.x * r.y;
+                }
+            }
+            acc[j][0] += re;
+            acc[j][1] += im;
+        }
+    }
+    // part[blk][combo/16][32]: (p, k) block of 16 complex entries
+#pragma unroll
+    for (int j = 0; j < kMaxPer; ++j) {
+        const int cidx = t + j * kPtcFanThreads;
+        if (cidx >= ncombo) break;
+        part[((int64_t)blockIdx.x * (9 * C) + cidx / 16) * 32 + 2 * (cidx % 16)] = 2.0 * acc[j][0];
+        part[((int64_t)blockIdx.x * (9 * C) + cidx / 16) * 32 + 2 * (cidx % 16) + 1] = 2.0 * acc[j][1];
     }
 }
 
@@ -263,11 +365,12 @@ static int ptc_blocks(int64_t V) {
 
 qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s) {
     const int64_t V = t->V;
-    const dim3 blk(kPtcThreads);
-    const unsigned gx = (unsigned)((V + kPtcThreads - 1) / kPtcThreads);
+    const unsigned gx = (unsigned)((V + kPtcSites - 1) / kPtcSites);
     const float2* U = (const float2*)t->op->U;
-    hipLaunchKernelGGL(k_ptc_layer, dim3(gx, t->C), blk, 0, s, t->h1, (const float2*)r, t->W1, U, t->op->nbr, V, 1, t->C);
-    hipLaunchKernelGGL(k_ptc_layer, dim3(gx, 1), blk, 0, s, (float2*)y, t->h1, t->W2, U, t->op->nbr, V, t->C, 1);
+    hipLaunchKernelGGL(k_ptc_fan_out<false>, dim3(gx), dim3(kPtcFanThreads), 0, s, t->h1, (const float2*)r, t->W1, U,
+                       t->op->nbr, V, t->C);
+    hipLaunchKernelGGL(k_ptc_fan_in, dim3(gx), dim3(kPtcFanThreads), 0, s, (float2*)y, t->h1, t->W2, U, t->op->nbr, V,
+                       t->C);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -395,13 +498,20 @@ qmg_status ptc_backward(qmg_ptc t, const void* r, hipStream_t s) {
     const int* nbr = t->op->nbr;
     const int C = t->C;
     const int gb = ptc_blocks(V);
-    // layer 2 (C -> 1): weight gradient, then D1 = dL/dh1*
-    hipLaunchKernelGGL(k_ptc_wgrad, dim3(gb, 9 * C), dim3(256), 0, s, t->part, t->D2, t->h1, U, nbr, V, C, 1);
+    const size_t lds = sizeof(float2) * kPtcSites * 12 * (9 + C);
+    if (lds > 65536) {
+        QMG_HIP(hipFuncSetAttribute((const void*)k_ptc_wgrad_fan<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        QMG_HIP(hipFuncSetAttribute((const void*)k_ptc_wgrad_fan<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    // second layer (C -> 1): weight gradient, then D1 = dL/dh1*
+    hipLaunchKernelGGL(k_ptc_wgrad_fan<true>, dim3(gb), dim3(kPtcFanThreads), lds, s, t->part, t->D2, t->h1, U, nbr, V,
+                       C);
     hipLaunchKernelGGL(k_ptc_wgrad_final, dim3((9 * C * 16 + 255) / 256), dim3(256), 0, s, t->G2, t->part, gb, 9 * C);
-    const unsigned gx = (unsigned)((V + kPtcThreads - 1) / kPtcThreads);
-    hipLaunchKernelGGL(k_ptc_back_data, dim3(gx, C), dim3(kPtcThreads), 0, s, t->D1, t->D2, t->W2, U, nbr, V, C, 1);
-    // layer 1 (1 -> C): weight gradient against the input r
-    hipLaunchKernelGGL(k_ptc_wgrad, dim3(gb, 9 * C), dim3(256), 0, s, t->part, t->D1, (const float2*)r, U, nbr, V, 1, C);
+    const unsigned gx = (unsigned)((V + kPtcSites - 1) / kPtcSites);
+    hipLaunchKernelGGL(k_ptc_fan_out<true>, dim3(gx), dim3(kPtcFanThreads), 0, s, t->D1, t->D2, t->W2, U, nbr, V, C);
+    // first layer (1 -> C): weight gradient against the input r
+    hipLaunchKernelGGL(k_ptc_wgrad_fan<false>, dim3(gb), dim3(kPtcFanThreads), lds, s, t->part, (const float2*)r,
+                       t->D1, U, nbr, V, C);
     hipLaunchKernelGGL(k_ptc_wgrad_final, dim3((9 * C * 16 + 255) / 256), dim3(256), 0, s, t->G1, t->part, gb, 9 * C);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
