@@ -34,6 +34,19 @@ def test_gauge_links_are_special_unitary():
     assert not np.allclose(synth.gauge_field((2, 2, 2, 2), 0.4, 0), synth.gauge_field((2, 2, 2, 2), 0.4, 1))
 
 
+def test_special_unitary_rows_are_conjugate_cross_products():
+    """The property 12-real link compression rests on: for U in SU(3) each row
+    is the complex conjugate of the cross product of the other two (from
+    U^+ U = 1 and det U = 1); it holds to rounding for the synthetic links and
+    fails for a unitary matrix with det = -1 (the time-boundary sign)."""
+    U = synth.gauge_field((4, 4, 2, 2), 0.4, 7).reshape(-1, 3, 3)
+    c = np.conj(np.cross(U[:, 0], U[:, 1]))
+    assert np.abs(c - U[:, 2]).max() < 1e-14
+    assert np.abs(np.conj(np.cross(U[:, 1], U[:, 2])) - U[:, 0]).max() < 1e-14
+    W = -U   # det = -1
+    assert np.abs(np.conj(np.cross(W[:, 0], W[:, 1])) + W[:, 2]).max() < 1e-14
+
+
 def test_gamma_clifford_algebra_and_chiral_basis():
     g = lattice.gammas()
     for mu in range(4):
