@@ -309,6 +309,20 @@ qmg_status qmg_wilson_clover_schur_source(qmg_fine_op op, const void* b, void* b
 qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const void* x_e, const void* b, void* x, int nrhs,
                                                qmg_prec prec, void* stream);
 
+/* qmg_wilson_clover_schur for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels, with the odd half-lattice intermediate in a
+ * fixed 16 MiB device array the library holds on every device it runs on
+ * until the process ends, instead of the operator's grown scratch.  The call
+ * allocates and frees nothing.  QMG_ERR_ARG if nrhs * V/2 * 12 complex
+ * entries (16 bytes each for QMG_C128, 8 otherwise) exceed 16 MiB (e.g. up to
+ * 16^3x32 in complex128 with one right-hand side).  Every call on a device
+ * shares that device's array: calls that overlap in time on one device (on
+ * different streams or host threads) race and must be serialised by the
+ * caller.  Arguments and other errors as for qmg_wilson_clover_schur. */
+qmg_status qmg_wilson_clover_schur_noalloc(qmg_fine_op op, const void* in_e, void* out_e, int nrhs, qmg_prec prec,
+                                           void* stream);
+
 
 /* ---------------------------------------------------------------------------
  * Transfer operators (Sec. 3.4 step 3, Sec. 6.6).  The near-null vectors are

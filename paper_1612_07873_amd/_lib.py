@@ -57,6 +57,7 @@ SIGNATURES = {
     'qmg_wilson_clover_schur': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_wilson_clover_schur_source': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_wilson_clover_schur_reconstruct': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
+    'qmg_wilson_clover_schur_noalloc': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_coarse_op_prepare_schur': (c_int, [c_void_p, c_void_p]),
     'qmg_coarse_dslash_schur': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_coarse_schur_source': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),

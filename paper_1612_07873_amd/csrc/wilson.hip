@@ -29,6 +29,7 @@
 #include "codes16.h"
 #include "handles.h"
 
+#include <mutex>
 #include <vector>
 
 namespace qmg {
@@ -1120,4 +1121,47 @@ extern "C" qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const 
     if (!x_e || !b || !x) return fail(QMG_ERR_ARG, "wilson_clover_schur_reconstruct: NULL field");
     if (x == b || x == x_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_reconstruct: x aliases an input");
     return fine_schur_reconstruct(op, x_e, b, x, prec, nrhs, as_stream(stream));
+}
+// ------------------------------------------------------ allocation-free Schur
+// For callers that cannot allocate (code under graph capture, tight serving
+// loops): the odd half-lattice scratch of the Schur operator lives in a
+// fixed device array instead of the operator's grown buffer.  Each device
+// the library runs on holds its own copy for the life of the process; host
+// code only ever uses its device address, looked up once per device.
+namespace {
+constexpr size_t kNoAllocScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device
+
+qmg_status scratch_address(void** out) {
+    int dev = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(QMG_ERR_HIP, "wilson_clover_schur_noalloc: scratch address on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return QMG_OK;
+}
+}  // namespace
+
+extern "C" qmg_status qmg_wilson_clover_schur_noalloc(qmg_fine_op op, const void* in_e, void* out_e, int nrhs,
+                                                      qmg_prec prec, void* stream) {
+    QMG_TRY(schur_checks(op, nrhs, prec, "wilson_clover_schur_noalloc"));
+    if (!in_e || !out_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_noalloc: NULL field");
+    if (in_e == out_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_noalloc: in and out alias");
+    const size_t need = (size_t)nrhs * (op->V / 2) * 12 * (prec == QMG_C128 ? 16 : 8);
+    if (need > kNoAllocScratchBytes)
+        return fail(QMG_ERR_ARG, "wilson_clover_schur_noalloc: %zu bytes of scratch needed, the fixed scratch holds %zu",
+                    need, kNoAllocScratchBytes);
+    void* tmp = nullptr;
+    QMG_TRY(scratch_address(&tmp));
+    return fine_schur_apply(op, in_e, out_e, tmp, prec, nrhs, as_stream(stream));
 }
