@@ -425,6 +425,9 @@ def learned(npairs, epochs, loss, source='smoother'):
     t_train = time.perf_counter() - t0
     mg.set_smoother(net)
     withnet = timed_solves(mg, 12, 1000)
+    # the network step followed by two MR steps on the residual it leaves
+    mg.set_smoother(net, mr_steps=2)
+    hybrid = timed_solves(mg, 12, 1000)
     mg.set_smoother(None)
     del mg
     # the comparison the method is judged by: 16-bit fine and coarse storage,
@@ -442,7 +445,9 @@ def learned(npairs, epochs, loss, source='smoother'):
             'pair_seconds': round(t_pairs, 2),
             'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
             'train_seconds': round(t_train, 2), 'mg_with_MR': plain, 'mg_with_learned': withnet,
+            'mg_with_learned_then_MR2': hybrid,
             'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3),
+            'speedup_time_learned_then_MR2': round(plain['time_to_1e-10_s'] / hybrid['time_to_1e-10_s'], 3),
             'north_star': {'plain': 'FP32 inner, FP64 outer, single right-hand side, MR(4) smoother',
                            'mixed': 'FP16 fine and coarse storage (FP32 scales, FP32 arithmetic), 16 right-hand '
                                     'sides per solve, matrix-core coarse stencils, learned level-0 smoother',
@@ -467,10 +472,13 @@ def fine_and_transfer(steps=200):
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
     psi = [torch.from_numpy(synth.gaussian((V, 4, 3), 10 + k, 2)).to(dev).to(torch.complex64) for k in range(4)]
     out = {}
-    site_bytes = {'c64': 768, 'h16_fp32_vectors': 144 + 152 + 192, 'h16_16bit_vectors': 144 + 152 + 2 * (48 + 4)}
-    for name, storage in (('c64', 'c64'), ('h16_fp32_vectors', 'h16'), ('h16_16bit_vectors', 'h16')):
+    # bytes per site: links (4 x 18 or 12 reals), clover (72 reals + 2 scales), spinor in and out
+    site_bytes = {'c64': 768, 'h16_fp32_vectors': 144 + 152 + 192, 'h16_16bit_vectors': 144 + 152 + 2 * (48 + 4),
+                  'c64_12real_links': 192 + 288 + 192, 'h16_12real_links_fp32_vectors': 96 + 152 + 192}
+    for name, storage, reals in (('c64', 'c64', 18), ('h16_fp32_vectors', 'h16', 18), ('h16_16bit_vectors', 'h16', 18),
+                                 ('c64_12real_links', 'c64', 12), ('h16_12real_links_fp32_vectors', 'h16', 12)):
         R = 4 if storage == 'c64' else 8
-        ops = [FineOp(dims, U, -0.18, 1.0, True, storage) for _ in range(R)]
+        ops = [FineOp(dims, U, -0.18, 1.0, True, storage, link_reals=reals) for _ in range(R)]
         if name == 'h16_16bit_vectors':
             qs = [quantize_sites(p.reshape(V, 12), 'h16') for p in psi]
             o16, osc = torch.empty_like(qs[0][0]), torch.empty_like(qs[0][1])
@@ -561,6 +569,8 @@ def bicgstab(U, m0, nsolves=3, dims=(16, 16, 16, 32)):
 
 
 def mg_gcr(nsolves=12, nrhs=16):
+    import torch
+    import synth
     mg, U, m0, m0_src, setup = build_mg_16x32()
     out = {'lattice': [16, 16, 16, 32], 'm0': m0, 'm0_source': m0_src,
            'levels': '16^3x32 -(4^4,Nvec24)-> 4^3x8 N48 -(2^4,Nvec32)-> 2^3x4 N64', 'inner': 'fp32',
@@ -574,6 +584,27 @@ def mg_gcr(nsolves=12, nrhs=16):
     rb.update(timed_solves(mg, nsolves, 0))
     rb['speedup_vs_whole_lattice'] = round(out['time_to_1e-10_s'] / rb['time_to_1e-10_s'], 3)
     out['red_black'] = rb
+    # where the time goes, level by level (device time from events around the
+    # coarse-grid solves; one solve each, whole lattice and red-black)
+    out['level_seconds'] = {}
+    for name, eo in (('whole_lattice', False), ('red_black', True)):
+        mg.set_evenodd(eo)
+        mg.set_level_timing(True)
+        mg.solve(torch.from_numpy(synth.gaussian((mg.V, 4, 3), 0, 2)).to('cuda'), tol=1e-10)
+        _, info = mg.solve(torch.from_numpy(synth.gaussian((mg.V, 4, 3), 1, 2)).to('cuda'), tol=1e-10)
+        mg.set_level_timing(False)
+        out['level_seconds'][name] = {'total_s': round(info['seconds'], 5),
+                                      'per_level_s': [round(t, 5) for t in info['level_seconds']],
+                                      'level_iters': info['level_iters']}
+    # the Schwarz (SAP) level-0 smoother: 4^4 blocks, 4 MR steps per block
+    mg.set_evenodd(False)
+    mg.set_sap((4, 4, 4, 4), 4)
+    sap = timed_solves(mg, nsolves, 0)
+    mg.set_evenodd(True)
+    sap['with_red_black'] = timed_solves(mg, nsolves, 0)
+    mg.set_sap(iters=0)
+    mg.set_evenodd(False)
+    out['sap_smoother'] = sap
     del mg
     out['bicgstab'] = bicgstab(U, m0)
     for k, v in out['bicgstab'].items():
@@ -647,8 +678,14 @@ def precision_form(nsolves=12, dims=(32, 32, 32, 64)):
         if name == 'fp16':   # with red-black preconditioning on every level as well (the paper's set-up)
             mg.set_evenodd(True)
             r['red_black'] = timed_solves(mg, nsolves, 0)
-            mg.set_evenodd(False)
             print('precision form: fp16 red-black %s' % r['red_black'], file=sys.stderr, flush=True)
+            # and the fine links compressed to 12 reals
+            mg.set_fine_links(12)
+            r['red_black_12real_links'] = timed_solves(mg, nsolves, 0)
+            mg.set_fine_links(18)
+            mg.set_evenodd(False)
+            print('precision form: fp16 red-black 12-real %s' % r['red_black_12real_links'], file=sys.stderr,
+                  flush=True)
         runs[name] = (mg, r)
     # FP64 operators from the same block bases, and each stored operator's error against them
     mg16 = runs['fp16'][0]
@@ -707,7 +744,7 @@ def main():
     ap.add_argument('--quick', action='store_true',
                     help='leave out the learned-smoother and 32^3x64 precision-form records')
     ap.add_argument('--pairs', type=int, default=4096)
-    ap.add_argument('--epochs', type=int, default=4)
+    ap.add_argument('--epochs', type=int, default=2)
     ap.add_argument('--loss', choices=['error', 'residual'], default='residual')
     ap.add_argument('--pairs-from', choices=['smoother', 'iterates'], default='smoother')
     args = ap.parse_args()
@@ -757,6 +794,14 @@ def main():
     copy_ms = timed(lambda i: dst.copy_(calib), 10, 2)      # achievable copy bandwidth on this machine
     copy_gbs = 2 * calib.numel() * 8 / (copy_ms * 1e-3) / 1e9
     del calib, dst
+    # achievable read bandwidth: the library's read-stream kernel over 1 GiB
+    from paper_1612_07873_amd import stream_read
+    rbuf = torch.ones(1 << 27, dtype=torch.complex64, device=dev)
+    sink = torch.empty(1 << 14, dtype=torch.int32, device=dev)
+    stream_read(rbuf, sink)
+    read_ms = timed(lambda i: stream_read(rbuf, sink), 10, 2)
+    read_gbs = rbuf.numel() * 8 / (read_ms * 1e-3) / 1e9
+    del rbuf, sink
     cd, N = (4, 4, 4, 8), 48
     V = int(np.prod(cd))
     X = synth.gaussian((V, N, N), 0, 2)
@@ -792,7 +837,9 @@ def main():
                      'traffic': measured_traffic([ops[0].launch()[0], ops[0].launch()[1], ops[0].prefetch()]),
                      'algorithmic_bytes_per_launch': byts, 'kernel': 'qmg::k_coarse_dslash (FP32 links)',
                      'achievable_copy_GB/s': round(copy_gbs, 1),
-                     'frac_of_achievable_copy': round(achieved / copy_gbs, 4)},
+                     'frac_of_achievable_copy': round(achieved / copy_gbs, 4),
+                     'achievable_read_GB/s': round(read_gbs, 1),
+                     'frac_of_achievable_read': round(achieved / read_gbs, 4)},
     }
     warm_ms = timed(lambda i: ops[0].apply(ud, out), 500, 50)
     rec['warm_cache'] = {'ms_per_step': round(warm_ms, 6), 'GFLOP/s': round(flops / (warm_ms * 1e-3) / 1e9, 2),

@@ -70,6 +70,14 @@ int qmg_version(void);
 /* Wait for all work on `stream`; returns QMG_ERR_HIP if an enqueued kernel failed. */
 qmg_status qmg_sync(void* stream);
 
+/* Measurement reference: read `bytes` (a multiple of 16) of the DEVICE buffer
+ * once with a plain read-stream kernel (8 work-groups of 256 threads per
+ * compute unit, four 16-byte loads in flight per thread), writing one word
+ * per work-group to the DEVICE `sink` (sink_words >= 8 x compute units).
+ * Timed by the caller, it gives the achievable HBM read bandwidth that the
+ * read-dominated stencils are compared with. */
+qmg_status qmg_stream_read(const void* buf, long long bytes, void* sink, int sink_words, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Coarse operator, Eq. (3) (Sec. 3.4):
  *     y(x) = X(x) u(x) + sum_{d=0..7} Y_d(x) u(x + hop_d),   periodic wrap,
@@ -254,6 +262,16 @@ qmg_status qmg_coarse_schur_reconstruct(qmg_coarse_op op, const void* x_e, const
 qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, double m0, double csw,
                               int antiperiodic_t, qmg_prec storage, void* stream, qmg_fine_op* out);
 
+/* As qmg_fine_op_create, with the links stored as link_reals real numbers
+ * each: 18 (all nine entries), or 12 (rows 0 and 1 only; the kernels rebuild
+ * row 2 as the complex conjugate of the cross product of the other two, which
+ * holds for SU(3) links -- the gauge compression of Sec. 4 and 7.1, here to 12
+ * reals; 8-real compression is not provided).  12 needs QMG_C64, QMG_H16 or
+ * QMG_B16 storage and cuts the link bytes by a third; the links must be
+ * special unitary (det = 1) for the rebuilt row to be right. */
+qmg_status qmg_fine_op_create_ex(const int dims[4], const void* gauge, double m0, double csw, int antiperiodic_t,
+                                 qmg_prec storage, int link_reals, void* stream, qmg_fine_op* out);
+
 /* out = M in for nrhs fields; in/out DEVICE [nrhs][V][4][3] in the operator's
  * storage precision (complex64 for the 16-bit storages); one launch covers
  * every field; 1 <= nrhs <= 1024; in and out must not overlap. */
@@ -279,6 +297,20 @@ qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* stream);
 qmg_status qmg_fine_op_export_links(qmg_fine_op op, void* gauge, void* stream);
 
 void qmg_fine_op_destroy(qmg_fine_op op);
+
+/* Schwarz alternating procedure (the domain-decomposition smoother whose
+ * blocks relax independently, with no global reduction): x = one sweep from
+ * x = 0 for M x = r.  The lattice is cut into blocks of extent block[4]
+ * (each dimension an even number >= 2 of blocks; at most 256 sites per
+ * block) coloured by the parity of their block coordinates; for colour 0,
+ * then 1, every block B of that colour takes `iters` (1..64) minimal-residual
+ * steps on M_BB d = (r - M x)_B from d = 0 (M_BB: Eq. (2) with the hops
+ * leaving B dropped; each block its own step lengths) and x += d on B.  One
+ * launch per colour; the block's links and residual stay in LDS.  r, x DEVICE
+ * complex64 [nrhs][V][4][3]; operator storage QMG_C64, QMG_H16 or QMG_B16
+ * (FP32 arithmetic).  Blocks (it builds the block tables). */
+qmg_status qmg_wilson_clover_sap(qmg_fine_op op, const int block[4], int iters, const void* r, void* x, int nrhs,
+                                 void* stream);
 
 /* ---------------------------------------------------------------------------
  * Red-black (even-odd) form of Eq. (2) (Sec. 3.3; the solver of Sec. 7.1
@@ -322,7 +354,6 @@ qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const void* x_e, 
  * caller.  Arguments and other errors as for qmg_wilson_clover_schur. */
 qmg_status qmg_wilson_clover_schur_noalloc(qmg_fine_op op, const void* in_e, void* out_e, int nrhs, qmg_prec prec,
                                            void* stream);
-
 
 /* ---------------------------------------------------------------------------
  * Transfer operators (Sec. 3.4 step 3, Sec. 6.6).  The near-null vectors are
@@ -415,6 +446,10 @@ typedef struct {
     double true_rel_residual; /* |b - M x| / |b| from the FP64 operator */
     double seconds;           /* host wall time of the solve */
     int smoother_fallbacks;   /* learned-smoother applications replaced by MR */
+    double level_seconds[4];  /* with qmg_mg_set_level_timing on: device time spent on each level,
+                                 exclusive of the coarser ones ([0]: the rest of the solve: outer
+                                 GCR, fine-level smoothing, transfers); -1 in [0] if some coarse
+                                 solves were not timed; 0 otherwise */
 } qmg_solve_info;
 
 /* Build the hierarchy on DEVICE gauge [4][V][3][3] complex128 (as in
@@ -458,6 +493,28 @@ qmg_status qmg_mg_gcr_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_p
  * QMG_ERR_NOCONV unless every member converged. */
 qmg_status qmg_mg_gcr_solve_multi(qmg_mg mg, const void* b, void* x, int nrhs, const qmg_solve_params* p,
                                   qmg_solve_info* info, void* stream);
+
+/* Store the links of the fine operator the K-cycle uses (the smoother's and
+ * the residual's, in the inner or 16-bit precision) with link_reals reals
+ * each, 18 or 12 (qmg_fine_op_create_ex), rebuilding it from the hierarchy's
+ * FP64 links; the FP64 operator of the outer solve keeps all 18.  Needs a
+ * complex64 inner precision (QMG_ERR_PREC).  Blocks. */
+qmg_status qmg_mg_set_fine_links(qmg_mg mg, int link_reals, void* stream);
+
+/* Level-0 smoother: one sweep of the Schwarz alternating procedure (as
+ * qmg_wilson_clover_sap, `iters` MR steps per block) in place of MR, followed
+ * by the residual r - A x the K-cycle continues with; iters = 0 returns to MR.
+ * The learned smoother, when attached, takes precedence.  Needs complex64
+ * inner precision (QMG_ERR_PREC) and a block that fits the lattice
+ * (QMG_ERR_SHAPE, as qmg_wilson_clover_sap). */
+qmg_status qmg_mg_set_sap(qmg_mg mg, const int block[4], int iters, void* stream);
+
+/* Time every coarse-grid solve of the following solves with HIP events on
+ * the solve's stream (on != 0) and report each level's share in
+ * info.level_seconds: the time-per-level picture of the paper's strong-scaling
+ * study (Sec. 7.2), on one GPU.  Adds two event records per coarse solve;
+ * off by default. */
+qmg_status qmg_mg_set_level_timing(qmg_mg mg, int on);
 
 /* Red-black preconditioning on every level (Sec. 7.1, with the Schur
  * complements of Sec. 3.3), on != 0; 0 switches it off.  With it on: the
@@ -564,6 +621,12 @@ void qmg_ptc_destroy(qmg_ptc net);
  * application uses MR instead (counted in smoother_fallbacks).  The network
  * is borrowed and must outlive its use. */
 qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net);
+
+/* MR steps (0..16, default 0) the learned smoother takes after an accepted
+ * network step, on the residual the network left: x = alpha N(r) + MR_k(r -
+ * alpha M N(r)).  Its kr2/kt workspace is the post-smoothing scratch of
+ * level 0, which is free while the smoother runs. */
+qmg_status qmg_mg_set_smoother_mr_steps(qmg_mg mg, int steps);
 
 /* As qmg_mg_gcr_solve, and also copy the iterate x_k after each of the first
  * maxrec outer steps into xhist (DEVICE complex128 [maxrec][V][4][3]);

@@ -11,10 +11,17 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['BiCGStab', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['BiCGStab', 'stream_read', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
+
+
+def stream_read(buf, sink):
+    """Read the device tensor `buf` once with the library's read-stream kernel (qmg_stream_read);
+    sink: int32 device tensor of at least 8 x (compute units) words."""
+    _lib.call('qmg_stream_read', ctypes.c_void_p(buf.data_ptr()), int(buf.numel() * buf.element_size()),
+              ctypes.c_void_p(sink.data_ptr()), int(sink.numel()), stream_ptr())
 
 
 def stream_ptr(stream=None):
@@ -218,18 +225,30 @@ class FineOp:
     storage 'h16' / 'b16' keeps links and clover in 16 bits; apply() then takes
     complex64 vectors and apply_scaled() 16-bit vectors with per-site scales."""
 
-    def __init__(self, dims, gauge, m0, csw=1.0, antiperiodic_t=True, storage='c128'):
+    def __init__(self, dims, gauge, m0, csw=1.0, antiperiodic_t=True, storage='c128', link_reals=18):
         self.dims = tuple(int(d) for d in dims)
         self.V = _vol(self.dims)
         self.storage = storage
         self.dtype = _VECDTYPE[storage]
         self.m0, self.csw = float(m0), float(csw)
+        self.link_reals = int(link_reals)
         h = ctypes.c_void_p()
-        _lib.call('qmg_fine_op_create', _lib.c_dims(*self.dims),
+        _lib.call('qmg_fine_op_create_ex', _lib.c_dims(*self.dims),
                   _dev_ptr(gauge, torch.complex128, (4, self.V, 3, 3), 'gauge'),
-                  self.m0, self.csw, int(bool(antiperiodic_t)), PREC[storage], stream_ptr(),
+                  self.m0, self.csw, int(bool(antiperiodic_t)), PREC[storage], self.link_reals, stream_ptr(),
                   ctypes.byref(h))
         self._h = h
+
+    def sap(self, r, block, iters, out=None):
+        """One Schwarz alternating procedure sweep x = SAP(r) (qmg_wilson_clover_sap);
+        r complex64 [V][4][3] or [nrhs][V][4][3]."""
+        if out is None:
+            out = torch.empty_like(r)
+        m, shape = _nrhs(r, (self.V, 4, 3), 'r')
+        _lib.call('qmg_wilson_clover_sap', self._h, _lib.c_dims(*block), int(iters),
+                  _dev_ptr(r, torch.complex64, shape, 'r'), _dev_ptr(out, torch.complex64, shape, 'x'), m,
+                  stream_ptr())
+        return out
 
     def apply(self, psi, out=None):
         """Eq. (2) on psi [V][4][3] or, for several fields, [nrhs][V][4][3]."""
@@ -495,7 +514,8 @@ class Multigrid:
         return {'outer_iters': info.outer_iters, 'level_iters': list(info.level_iters)[:self.nlevels],
                 'restarts': info.restarts, 'converged': bool(info.converged),
                 'true_rel_residual': info.true_rel_residual, 'seconds': info.seconds,
-                'smoother_fallbacks': info.smoother_fallbacks, 'status': st}
+                'smoother_fallbacks': info.smoother_fallbacks, 'level_seconds': list(info.level_seconds)[:self.nlevels],
+                'status': st}
 
     def solve_record(self, b, maxrec, tol=1e-10, maxit=500):
         """Solve and keep the outer iterates x_1..x_n (complex128 [n][V][4][3])."""
@@ -536,13 +556,27 @@ class Multigrid:
                   ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(e.data_ptr()), stream_ptr())
         return r, e
 
-    def set_smoother(self, net):
+    def set_smoother(self, net, mr_steps=0):
+        """Learned level-0 smoother (None: MR); mr_steps MR steps follow each accepted network step."""
         _lib.call('qmg_mg_set_smoother', self._h, net._h if net is not None else None)
+        _lib.call('qmg_mg_set_smoother_mr_steps', self._h, int(mr_steps))
         self._smoother = net
 
     def set_evenodd(self, on=True):
         """Red-black preconditioning on every level (qmg_mg_set_evenodd)."""
         _lib.call('qmg_mg_set_evenodd', self._h, int(bool(on)), stream_ptr())
+
+    def set_fine_links(self, link_reals):
+        """Links of the K-cycle's fine operator stored with 18 or 12 reals (qmg_mg_set_fine_links)."""
+        _lib.call('qmg_mg_set_fine_links', self._h, int(link_reals), stream_ptr())
+
+    def set_level_timing(self, on=True):
+        """Per-level device time in the solve info's level_seconds (qmg_mg_set_level_timing)."""
+        _lib.call('qmg_mg_set_level_timing', self._h, int(bool(on)))
+
+    def set_sap(self, block=(4, 4, 4, 4), iters=4):
+        """Level-0 Schwarz (SAP) smoother with `iters` MR steps per block; iters=0 returns to MR."""
+        _lib.call('qmg_mg_set_sap', self._h, _lib.c_dims(*block), int(iters), stream_ptr())
 
     def level(self, l):
         d = _lib.c_dims()

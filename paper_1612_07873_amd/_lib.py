@@ -19,6 +19,7 @@ SIGNATURES = {
     'qmg_last_error': (c_char_p, []),
     'qmg_version': (c_int, []),
     'qmg_sync': (c_int, [c_void_p]),
+    'qmg_stream_read': (c_int, [c_void_p, ctypes.c_longlong, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_create': (c_int, [c_dims, c_int, c_void_p, c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_coarse_op_export': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_coarse_dslash': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
@@ -59,6 +60,9 @@ SIGNATURES = {
     'qmg_wilson_clover_schur_reconstruct': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_wilson_clover_schur_noalloc': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_coarse_op_prepare_schur': (c_int, [c_void_p, c_void_p]),
+    'qmg_fine_op_create_ex': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, c_int, c_void_p,
+                                      ctypes.POINTER(c_void_p)]),
+    'qmg_wilson_clover_sap': (c_int, [c_void_p, c_dims, c_int, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_dslash_schur': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_coarse_schur_source': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_coarse_schur_reconstruct': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
@@ -78,7 +82,8 @@ class SolveParams(ctypes.Structure):
 
 class SolveInfo(ctypes.Structure):
     _fields_ = [('outer_iters', c_int), ('level_iters', c_int * 4), ('restarts', c_int), ('converged', c_int),
-                ('true_rel_residual', c_double), ('seconds', c_double), ('smoother_fallbacks', c_int)]
+                ('true_rel_residual', c_double), ('seconds', c_double), ('smoother_fallbacks', c_int),
+                ('level_seconds', c_double * 4)]
 
 
 class BicgstabParams(ctypes.Structure):
@@ -103,6 +108,10 @@ SIGNATURES.update({
     'qmg_mg_destroy': (None, [c_void_p]),
     'qmg_mg_set_smoother': (c_int, [c_void_p, c_void_p]),
     'qmg_mg_set_evenodd': (c_int, [c_void_p, c_int, c_void_p]),
+    'qmg_mg_set_fine_links': (c_int, [c_void_p, c_int, c_void_p]),
+    'qmg_mg_set_level_timing': (c_int, [c_void_p, c_int]),
+    'qmg_mg_set_sap': (c_int, [c_void_p, c_dims, c_int, c_void_p]),
+    'qmg_mg_set_smoother_mr_steps': (c_int, [c_void_p, c_int]),
     'qmg_mg_gcr_solve_record': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
                                         ctypes.POINTER(SolveInfo), c_void_p, c_int, c_int_p, c_void_p]),
     'qmg_mg_make_pairs': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, c_void_p, c_void_p]),

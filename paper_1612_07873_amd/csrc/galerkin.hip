@@ -232,6 +232,8 @@ extern "C" qmg_status qmg_build_coarse_op(qmg_transfer t, qmg_fine_op fine, qmg_
     const qmg_prec from = fine ? fine->storage : parent->storage;
     if (from != QMG_C128 && from != QMG_C64)
         return fail(QMG_ERR_PREC, "build_coarse_op: the parent operator must use complex128 or complex64 storage");
+    if (fine && fine->link_reals != 18)
+        return fail(QMG_ERR_PREC, "build_coarse_op: the fine operator must store all 18 link reals");
     hipStream_t s = as_stream(stream);
     const int64_t Vc = t->Vc;
     const size_t blk = (size_t)Vc * N * N;

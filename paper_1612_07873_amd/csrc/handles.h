@@ -48,6 +48,8 @@ struct qmg_fine_op_s {
     int* hsite = nullptr;
     void* eo_tmp = nullptr;    // half-lattice scratch of the Schur entry points (grown on demand)
     size_t eo_tmp_bytes = 0;
+    int link_reals = 18;       // 18, or 12: links stored as rows 0 and 1, [4][6][V], row 2 rebuilt
+    int64_t last = 0;          // first lattice index of the last time slice
 };
 
 struct qmg_transfer_s {
@@ -76,6 +78,12 @@ struct qmg_ptc_s {
     double* part;     // partial sums for reductions
     double* loss;     // [2]: accumulated loss, scratch
     int adam_t;
+    // inference: the network collapsed to K[p][q] = sum_b W2[p][0][b] W1[q][b][0]
+    // (81 spin matrices, rebuilt when the weights change) and the mixed fields
+    // g_p = sum_q K[p][q] T_q r, [9][V][12]
+    float2* K = nullptr;
+    float2* g = nullptr;
+    bool k_stale = true;
 };
 
 namespace qmg {

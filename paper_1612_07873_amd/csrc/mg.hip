@@ -65,6 +65,11 @@ qmg_status eo_gather(const int* hsite, int64_t Vh, int dof, const void* full, vo
                      int m, hipStream_t s);
 qmg_status eo_scatter(const int* hsite_p, const int* hsite_q, int64_t Vh, int dof, const void* half, void* full,
                       qmg_prec vprec, int m, hipStream_t s);
+struct SapPlan;
+qmg_status sap_plan_create(const qmg_fine_op_s* op, const int block[4], SapPlan** out, hipStream_t s);
+void sap_plan_destroy(SapPlan* P);
+qmg_status sap_sweep(const qmg_fine_op_s* op, const SapPlan& P, const void* r, void* x, int iters, int m,
+                     hipStream_t s);
 }
 
 using namespace qmg;
@@ -114,6 +119,7 @@ struct qmg_mg_s {
     hipStream_t s = nullptr;
     int level_iters[8] = {0};
     qmg_ptc ptc = nullptr;      // learned level-0 smoother (NULL: MR)
+    int ptc_mr = 0;             // MR steps after an accepted network step
     int fallbacks = 0;          // smoother applications that fell back to MR
     void* rec = nullptr;        // recording of outer iterates (complex128 [maxrec][V][12])
     int rec_max = 0, rec_n = 0;
@@ -121,6 +127,14 @@ struct qmg_mg_s {
     int srec_max = 0, srec_n = 0;
     bool eo = false;            // red-black form on every level
     void *eb64 = nullptr, *ex64 = nullptr, *etmp64 = nullptr;   // outer FP64 Schur source, iterate, scratch
+    // per-level timing (qmg_mg_set_level_timing): HIP events around every
+    // coarse-grid solve, read after the solve
+    SapPlan* sap = nullptr;     // level-0 Schwarz smoother (NULL: MR)
+    int sap_iters = 0;
+    bool timing = false;
+    std::vector<hipEvent_t> ev;           // pool, created on first use
+    std::vector<int> span_level;          // level of span k: events 2k, 2k+1
+    bool spans_overflow = false;
 };
 
 namespace {
@@ -262,6 +276,44 @@ template <typename R> qmg_status mr(qmg_mg_s* mg, int l, const void* r, void* x)
         QMG_HIP(hipMemcpyAsync(L.mr_r, r, nb * n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
     }
     return QMG_OK;
+}
+
+// Per-level timing: span k brackets one coarse-grid solve on level l (which
+// includes every coarser level's work) with events 2k and 2k+1 on the solve's
+// stream.  A pool of kTimingEvents events; spans beyond it are not recorded.
+constexpr int kTimingEvents = 8192;
+int timing_begin(qmg_mg_s* mg, int l) {
+    if (!mg->timing) return -1;
+    const int k = (int)mg->span_level.size();
+    if (2 * k + 2 > kTimingEvents) {
+        mg->spans_overflow = true;
+        return -1;
+    }
+    while ((int)mg->ev.size() < 2 * k + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        mg->ev.push_back(e);
+    }
+    if (hipEventRecord(mg->ev[2 * k], mg->s) != hipSuccess) return -1;
+    mg->span_level.push_back(l);
+    return k;
+}
+void timing_end(qmg_mg_s* mg, int k) {
+    if (k >= 0) (void)hipEventRecord(mg->ev[2 * k + 1], mg->s);
+}
+// seconds spent on each level, exclusive of the coarser levels; level 0 is
+// the rest of the solve (outer FGCR, fine-level smoothing and transfers)
+void timing_collect(qmg_mg_s* mg, double total_s, double out[4]) {
+    double incl[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    incl[0] = total_s;
+    for (size_t k = 0; k < mg->span_level.size(); ++k) {
+        float ms = 0;
+        if (hipEventElapsedTime(&ms, mg->ev[2 * k], mg->ev[2 * k + 1]) == hipSuccess)
+            incl[mg->span_level[k]] += ms * 1e-3;
+    }
+    const int nl = (int)mg->lv.size();
+    for (int l = 0; l < 4; ++l) out[l] = l < nl ? incl[l] - (l + 1 < nl ? incl[l + 1] : 0.0) : 0.0;
+    mg->span_level.clear();
 }
 
 // K-cycle preconditioner of a system: K_l(r) on the whole lattice, or for
@@ -440,8 +492,25 @@ template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void
             const bool ok = den > 0 && std::isfinite(den) && std::isfinite(re) && std::isfinite(im) && den - 2 * re < 0;
             if (!ok) ++bad;
         }
-        if (bad == 0) return mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n);
+        if (bad == 0) {
+            QMG_TRY(mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n));
+            if (mg->ptc_mr <= 0) return QMG_OK;
+            // then MR steps on the residual the network left: x += MR_k(r - A x)
+            const int keep = L.p.smoother_steps;
+            L.p.smoother_steps = mg->ptc_mr;
+            QMG_HIP(hipMemcpyAsync(L.kr2, L.mr_r, mg->nb * L.n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
+            const qmg_status st = mr<R>(mg, l, L.kr2, L.kt);
+            L.p.smoother_steps = keep;
+            QMG_TRY(st);
+            return mg->blas.axpy<R>(1.0, L.kt, x, L.n);
+        }
         mg->fallbacks += bad;
+    }
+    if (l == 0 && mg->sap && sizeof(R) == 4) {
+        // one SAP sweep, then the residual r - A x the K-cycle goes on with
+        QMG_TRY(sap_sweep(mg->fine_in, *mg->sap, r, x, mg->sap_iters, mg->nb, mg->s));
+        QMG_TRY(apply_op<R>(mg, 0, x, L.mr_Ar));
+        return mg->blas.xmy<R>(r, L.mr_Ar, L.mr_r, L.n);
     }
     if (mg->eo) return mr_schur<R>(mg, l, r, x);
     return mr<R>(mg, l, r, x);
@@ -468,6 +537,7 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     QMG_TRY(transfer_restrict(L.T, L.mr_r, C.b, p, mg->nb, mg->s));
     const bool coarsest = (l + 1 == nl - 1);
     int it = 0;
+    const int span = timing_begin(mg, l + 1);
     if (mg->eo && !C.Ainv) {
         // red-black: GCR on the next level's Schur system, odd sites back-substituted
         QMG_TRY(schur_source<R>(mg, l + 1, C.b, C.eb));
@@ -476,6 +546,7 @@ template <typename R> qmg_status kcycle(qmg_mg_s* mg, int l, const void* rin, vo
     } else {
         QMG_TRY(gcr<R>(mg, full_sys(mg, l + 1), C.b, C.x, false, L.p.coarse_tol, L.p.coarse_maxit, !coarsest, &it));
     }
+    timing_end(mg, span);
     mg->level_iters[l + 1] += it;
     QMG_TRY(transfer_prolong(L.T, C.x, L.kt, p, mg->nb, mg->s));
     QMG_TRY(mg->blas.axpy<R>(1.0, L.kt, zout, n));
@@ -601,6 +672,8 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
         return wilson_apply(mg->fine64, in, out, QMG_C128, nb, mg->s);
     };
     for (int i = 0; i < 8; ++i) mg->level_iters[i] = 0;
+    mg->span_level.clear();
+    mg->spans_overflow = false;
     mg->fallbacks = 0;
     mg->rec_n = 0;
     mg->srec_n = 0;
@@ -706,6 +779,12 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
     auto t1 = std::chrono::steady_clock::now();
     double worst = 0;
     for (int k = 0; k < nb; ++k) worst = true_rel[k] > worst ? true_rel[k] : worst;
+    double lsec[4] = {0, 0, 0, 0};
+    if (mg->timing) {
+        QMG_HIP(hipStreamSynchronize(mg->s));
+        timing_collect(mg, std::chrono::duration<double>(t1 - t0).count(), lsec);
+        if (mg->spans_overflow) lsec[0] = -1.0;   // incomplete: too many coarse solves to time
+    }
     if (info) {
         for (int k = 0; k < nb; ++k) {
             qmg_solve_info& I = info[k];
@@ -717,6 +796,7 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
             I.seconds = std::chrono::duration<double>(t1 - t0).count();
             I.converged = conv[k] ? 1 : 0;
             I.smoother_fallbacks = mg->fallbacks;
+            for (int l = 0; l < 4; ++l) I.level_seconds[l] = lsec[l];
         }
     }
     if (!all_conv) return fail(QMG_ERR_NOCONV, "mg_gcr_solve: %d steps, relative residual %.3e", iters, worst);
@@ -736,6 +816,8 @@ extern "C" void qmg_mg_destroy(qmg_mg mg) {
     for (void* p : mg->allocs) (void)hipFree(p);
     for (void* p : mg->sallocs) (void)hipFree(p);
     if (mg->hsc) (void)hipHostFree(mg->hsc);
+    for (hipEvent_t e : mg->ev) (void)hipEventDestroy(e);
+    sap_plan_destroy(mg->sap);
     mg->blas.release();
     delete mg;
 }
@@ -926,6 +1008,61 @@ extern "C" qmg_status qmg_mg_set_smoother(qmg_mg mg, qmg_ptc net) {
         if (mg->lv.size() < 2) return fail(QMG_ERR_STATE, "mg_set_smoother: a single-level solver has no smoother");
     }
     mg->ptc = net;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_set_fine_links(qmg_mg mg, int link_reals, void* stream) {
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_fine_links: NULL mg");
+    if (link_reals != 18 && link_reals != 12) return fail(QMG_ERR_ARG, "mg_set_fine_links: link_reals %d", link_reals);
+    if (mg->fine_in == mg->fine64)
+        return fail(QMG_ERR_PREC, "mg_set_fine_links: needs a complex64 or 16-bit fine operator in the K-cycle");
+    if (mg->fine_in->link_reals == link_reals) return QMG_OK;
+    hipStream_t s = as_stream(stream);
+    const qmg_fine_op_s* f = mg->fine64;
+    void* G = nullptr;
+    QMG_HIP(hipMalloc(&G, (size_t)f->V * 36 * 16));
+    qmg_fine_op nf = nullptr;
+    qmg_status st = qmg_fine_op_export_links(mg->fine64, G, stream);
+    if (st == QMG_OK)
+        st = qmg_fine_op_create_ex(f->dims, G, f->m0, f->csw, f->antiperiodic_t, mg->fine_in->storage, link_reals,
+                                   stream, &nf);
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(G);
+    if (st != QMG_OK) return st;
+    qmg_fine_op_destroy(mg->fine_in);
+    mg->fine_in = nf;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_set_smoother_mr_steps(qmg_mg mg, int steps) {
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_smoother_mr_steps: NULL mg");
+    if (steps < 0 || steps > 16) return fail(QMG_ERR_ARG, "mg_set_smoother_mr_steps: steps %d outside [0, 16]", steps);
+    mg->ptc_mr = steps;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_set_sap(qmg_mg mg, const int block[4], int iters, void* stream) {
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_sap: NULL mg");
+    if (iters == 0) {
+        sap_plan_destroy(mg->sap);
+        mg->sap = nullptr;
+        mg->sap_iters = 0;
+        return QMG_OK;
+    }
+    if (!block || iters < 1 || iters > 64) return fail(QMG_ERR_ARG, "mg_set_sap: block NULL or iters %d", iters);
+    if (mg->inner != QMG_C64) return fail(QMG_ERR_PREC, "mg_set_sap: the Schwarz smoother runs in FP32 (complex64 inner)");
+    if (mg->lv.size() < 2) return fail(QMG_ERR_STATE, "mg_set_sap: a single-level solver has no smoother");
+    SapPlan* P = nullptr;
+    QMG_TRY(sap_plan_create(mg->fine_in, block, &P, as_stream(stream)));
+    sap_plan_destroy(mg->sap);
+    mg->sap = P;
+    mg->sap_iters = iters;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_set_level_timing(qmg_mg mg, int on) {
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_level_timing: NULL mg");
+    mg->timing = on != 0;
     return QMG_OK;
 }
 

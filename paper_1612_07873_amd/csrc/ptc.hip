@@ -195,7 +195,8 @@ __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_fan_in(float2* __restric
 //   else    (first layer,  G1[p][k][0]): L = mc_k (D1), R = T_p tr (tr = r).
 // Each work-group walks chunks of kPtcSites sites: per chunk the nine
 // transports per site and the C channels of the chunk's sites go to LDS, and
-// each thread accumulates its fixed set of (p, k, s, t) entries in FP64;
+// each thread sums its fixed set of (p, k, s, t) entries over the chunk in
+// FP32 and accumulates the chunk sums in FP64;
 // per-work-group partials part[blk][9*C][32] are summed in a fixed order.
 template <bool TR_LEFT>
 __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_wgrad_fan(double* __restrict__ part,
@@ -245,19 +246,20 @@ __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_wgrad_fan(double* __rest
             const int cidx = t + j * kPtcFanThreads;
             if (cidx >= ncombo) break;
             const int p = cidx / (C * 16), k = (cidx / 16) % C, sp = (cidx / 4) % 4, tt = cidx % 4;
-            double re = 0, im = 0;
+            // the chunk's 32 sites x 3 colours in FP32, added to the FP64 total
+            float re = 0, im = 0;
             for (int sl = 0; sl < kPtcSites; ++sl) {
                 const float2* m = ms + ((int64_t)k * kPtcSites + sl) * 12;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const float2 l = TR_LEFT ? tp[sl][p][sp * 3 + c] : m[sp * 3 + c];
                     const float2 r = TR_LEFT ? m[tt * 3 + c] : tp[sl][p][tt * 3 + c];
-                    re += (double)l.x * r.x + (double)l.y * r.y;
-                    im += (double)l.y * r.x - (double)l.x * r.y;
+                    re += l.x * r.x + l.y * r.y;
+                    im += l.y * r.x - l.x * r.y;
                 }
             }
-            acc[j][0] += re;
-            acc[j][1] += im;
+            acc[j][0] += (double)re;
+            acc[j][1] += (double)im;
         }
     }
     // part[blk][combo/16][32]: (p, k) block of 16 complex entries
@@ -358,12 +360,122 @@ __global__ void k_gamma5_scale(float2* __restrict__ out, const float2* __restric
     out[i] = make_float2(in[i].x * sc, in[i].y * sc);
 }
 
+// Inference.  The two layers are linear, so N(r) = sum_p T_p sum_q K[p][q] T_q r
+// with K[p][q] = sum_b W2[p][0][b] W1[q][b][0] (the spin weights commute with
+// the transports).  First the 81 spin matrices K are formed, then
+//   k_ptc_mix:  per site, the nine transports T_q r (once each, in LDS) and the
+//               nine mixtures g_p = sum_q K[p][q] T_q r;
+//   k_ptc_gather: N(r)(x) = sum_p (T_p g_p)(x).
+// The hidden channels are never stored: per site 96 bytes in, 864 bytes of g
+// out and back, instead of the hidden layer's 8 channels read nine times.
+__global__ void k_ptc_collapse(float2* __restrict__ K, const float2* __restrict__ W1, const float2* __restrict__ W2,
+                               int C) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // (p, q, s, t)
+    if (i >= 81 * 16) return;
+    const int p = i / (9 * 16), q = (i / 16) % 9, sp = (i / 4) % 4, tt = i % 4;
+    float re = 0, im = 0;
+    for (int b = 0; b < C; ++b) {
+        const float2* w2 = W2 + ((int64_t)p * C + b) * 16;   // W2[p][0][b]
+        const float2* w1 = W1 + ((int64_t)q * C + b) * 16;   // W1[q][b][0]
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const float2 a = w2[sp * 4 + u], c = w1[u * 4 + tt];
+            re += a.x * c.x - a.y * c.y;
+            im += a.x * c.y + a.y * c.x;
+        }
+    }
+    K[i] = make_float2(re, im);
+}
+
+__global__ __launch_bounds__(kPtcFanThreads) void k_ptc_mix(float2* __restrict__ g, const float2* __restrict__ r,
+                                                            const float2* __restrict__ K,
+                                                            const float2* __restrict__ U,
+                                                            const int* __restrict__ nbr, int64_t V) {
+    __shared__ float2 tp[kPtcSites][9][12];
+    __shared__ float2 ks[81 * 16];
+    const int64_t x0 = (int64_t)blockIdx.x * kPtcSites;
+    const int t = threadIdx.x;
+    for (int i = t; i < 81 * 16; i += kPtcFanThreads) ks[i] = K[i];
+    const int sl = t / 9, pq = t - (t / 9) * 9;
+    const int64_t x = x0 + sl;
+    if (x < V) {
+        const int64_t n = path_site(nbr, x, pq);
+        float2 v[12], w[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) v[f] = r[n * 12 + f];
+        transport_vals(w, v, U, V, x, n, pq);
+#pragma unroll
+        for (int f = 0; f < 12; ++f) tp[sl][pq][f] = w[f];
+    }
+    __syncthreads();
+    if (x >= V) return;
+    // thread (site, p): g_p = sum_q K[p][q] T_q r
+    const int p = pq;
+    float2 acc[12];
+#pragma unroll
+    for (int f = 0; f < 12; ++f) acc[f] = make_float2(0, 0);
+    for (int q = 0; q < 9; ++q) {
+        const float2* k = ks + (p * 9 + q) * 16;
+#pragma unroll
+        for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float re = acc[sp * 3 + c].x, im = acc[sp * 3 + c].y;
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float2 m = k[sp * 4 + u], v = tp[sl][q][u * 3 + c];
+                    re += m.x * v.x - m.y * v.y;
+                    im += m.x * v.y + m.y * v.x;
+                }
+                acc[sp * 3 + c] = make_float2(re, im);
+            }
+    }
+#pragma unroll
+    for (int f = 0; f < 12; ++f) g[((int64_t)p * V + x) * 12 + f] = acc[f];
+}
+
+__global__ __launch_bounds__(kPtcFanThreads) void k_ptc_gather(float2* __restrict__ out, const float2* __restrict__ g,
+                                                               const float2* __restrict__ U,
+                                                               const int* __restrict__ nbr, int64_t V) {
+    __shared__ float2 cp[kPtcSites][9][12];
+    const int64_t x0 = (int64_t)blockIdx.x * kPtcSites;
+    const int t = threadIdx.x;
+    {
+        const int sl = t / 9, p = t - (t / 9) * 9;
+        const int64_t x = x0 + sl;
+        if (x < V) {
+            const int64_t n = path_site(nbr, x, p);
+            float2 v[12], w[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) v[f] = g[((int64_t)p * V + n) * 12 + f];
+            transport_vals(w, v, U, V, x, n, p);
+#pragma unroll
+            for (int f = 0; f < 12; ++f) cp[sl][p][f] = w[f];
+        }
+    }
+    __syncthreads();
+    for (int idx = t; idx < kPtcSites * 12; idx += kPtcFanThreads) {
+        const int sl = idx / 12, f = idx - (idx / 12) * 12;
+        const int64_t x = x0 + sl;
+        if (x >= V) continue;
+        float re = 0, im = 0;
+#pragma unroll
+        for (int p = 0; p < 9; ++p) {
+            re += cp[sl][p][f].x;
+            im += cp[sl][p][f].y;
+        }
+        out[x * 12 + f] = make_float2(re, im);
+    }
+}
+
 static int ptc_blocks(int64_t V) {
     int64_t b = (V + kPtcThreads - 1) / kPtcThreads;
     return (int)(b > kPtcMaxBlocks ? kPtcMaxBlocks : b);
 }
 
-qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s) {
+// Layer by layer, keeping the hidden channels h1 (the training path: the
+// gradients need them).
+static qmg_status ptc_forward_layers(qmg_ptc t, const void* r, void* y, hipStream_t s) {
     const int64_t V = t->V;
     const unsigned gx = (unsigned)((V + kPtcSites - 1) / kPtcSites);
     const float2* U = (const float2*)t->op->U;
@@ -371,6 +483,21 @@ qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s) {
                        t->op->nbr, V, t->C);
     hipLaunchKernelGGL(k_ptc_fan_in, dim3(gx), dim3(kPtcFanThreads), 0, s, (float2*)y, t->h1, t->W2, U, t->op->nbr, V,
                        t->C);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+// y = N(r) through the collapsed form (inference: the smoother and the forward entry point).
+qmg_status ptc_forward(qmg_ptc t, const void* r, void* y, hipStream_t s) {
+    const int64_t V = t->V;
+    const unsigned gx = (unsigned)((V + kPtcSites - 1) / kPtcSites);
+    const float2* U = (const float2*)t->op->U;
+    if (t->k_stale) {
+        hipLaunchKernelGGL(k_ptc_collapse, dim3((81 * 16 + 255) / 256), dim3(256), 0, s, t->K, t->W1, t->W2, t->C);
+        t->k_stale = false;
+    }
+    hipLaunchKernelGGL(k_ptc_mix, dim3(gx), dim3(kPtcFanThreads), 0, s, t->g, (const float2*)r, t->K, U, t->op->nbr, V);
+    hipLaunchKernelGGL(k_ptc_gather, dim3(gx), dim3(kPtcFanThreads), 0, s, (float2*)y, t->g, U, t->op->nbr, V);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -383,7 +510,8 @@ using namespace qmg;
 
 extern "C" void qmg_ptc_destroy(qmg_ptc t) {
     if (!t) return;
-    float2* bufs[] = {t->W1, t->W2, t->G1, t->G2, t->m1, t->v1, t->m2, t->v2, t->h1, t->D1, t->y, t->D2, t->t1, t->t2};
+    float2* bufs[] = {t->W1, t->W2, t->G1, t->G2, t->m1, t->v1, t->m2, t->v2, t->h1, t->D1, t->y, t->D2, t->t1, t->t2,
+                      t->K, t->g};
     for (float2* b : bufs)
         if (b) (void)hipFree(b);
     if (t->part) (void)hipFree(t->part);
@@ -395,7 +523,8 @@ extern "C" qmg_status qmg_ptc_create(qmg_fine_op links, int hidden, void* stream
     if (!out) return fail(QMG_ERR_ARG, "ptc_create: out is NULL");
     *out = nullptr;
     if (!links) return fail(QMG_ERR_ARG, "ptc_create: links is NULL");
-    if (links->storage != QMG_C64) return fail(QMG_ERR_PREC, "ptc_create: the operator must use complex64 storage");
+    if (links->storage != QMG_C64 || links->link_reals != 18)
+        return fail(QMG_ERR_PREC, "ptc_create: the operator must use complex64 storage of all 18 link reals");
     if (hidden < 1 || hidden > 16) return fail(QMG_ERR_ARG, "ptc_create: hidden channels %d outside [1,16]", hidden);
     hipStream_t s = as_stream(stream);
     auto* t = new qmg_ptc_s();
@@ -414,6 +543,8 @@ extern "C" qmg_status qmg_ptc_create(qmg_fine_op links, int hidden, void* stream
     if (e == hipSuccess) e = hipMalloc(&t->D2, sizeof(float2) * fv);
     if (e == hipSuccess) e = hipMalloc(&t->t1, sizeof(float2) * fv);
     if (e == hipSuccess) e = hipMalloc(&t->t2, sizeof(float2) * fv);
+    if (e == hipSuccess) e = hipMalloc(&t->K, sizeof(float2) * 81 * 16);
+    if (e == hipSuccess) e = hipMalloc(&t->g, sizeof(float2) * fv * 9);
     if (e == hipSuccess) e = hipMalloc(&t->part, sizeof(double) * kPtcMaxBlocks * 9 * hidden * 32);
     if (e == hipSuccess) e = hipMalloc(&t->loss, sizeof(double) * 2);
     for (float2** p : wb)
@@ -438,6 +569,7 @@ extern "C" qmg_status qmg_ptc_set_weights(qmg_ptc t, const void* W1, const void*
     QMG_HIP(hipMemsetAsync(t->m2, 0, nb, s));
     QMG_HIP(hipMemsetAsync(t->v2, 0, nb, s));
     t->adam_t = 0;
+    t->k_stale = true;
     return QMG_OK;
 }
 
@@ -460,7 +592,7 @@ extern "C" qmg_status qmg_ptc_accumulate_grad(qmg_ptc t, const void* r, const vo
     if (!t || !r || !e) return fail(QMG_ERR_ARG, "ptc_accumulate_grad: NULL argument");
     hipStream_t s = as_stream(stream);
     const int64_t V = t->V, n = V * 12;
-    QMG_TRY(ptc_forward(t, r, t->y, s));
+    QMG_TRY(ptc_forward_layers(t, r, t->y, s));
     const int nb = ptc_blocks(n);
     hipLaunchKernelGGL(k_ptc_loss_part, dim3(nb), dim3(256), 0, s, t->part, t->y, (const float2*)e, n);
     hipLaunchKernelGGL(k_ptc_loss_final, dim3(1), dim3(64), 0, s, t->loss, t->part, nb);
@@ -473,7 +605,7 @@ extern "C" qmg_status qmg_ptc_accumulate_grad_residual(qmg_ptc t, const void* r,
     if (!t || !r) return fail(QMG_ERR_ARG, "ptc_accumulate_grad_residual: NULL argument");
     hipStream_t s = as_stream(stream);
     const int64_t n = t->V * 12;
-    QMG_TRY(ptc_forward(t, r, t->y, s));
+    QMG_TRY(ptc_forward_layers(t, r, t->y, s));
     // t1 = M y ; loss += |M y - r|^2/|r|^2 ; t2 = (M y - r)/|r|^2 = dL/d(My)*
     QMG_TRY(qmg_wilson_clover_dslash(t->op, t->y, t->t1, 1, QMG_C64, stream));
     const int nb = ptc_blocks(n);
@@ -545,6 +677,7 @@ extern "C" qmg_status qmg_ptc_adam_step(qmg_ptc t, float lr, float beta1, float 
         return fail(QMG_ERR_ARG, "ptc_adam_step: bad hyper-parameters");
     hipStream_t s = as_stream(stream);
     t->adam_t += 1;
+    t->k_stale = true;
     const float c1 = 1.0f - powf(beta1, (float)t->adam_t), c2 = 1.0f - powf(beta2, (float)t->adam_t);
     const int n = 9 * t->C * 16;
     hipLaunchKernelGGL(k_ptc_adam, dim3((n + 255) / 256), dim3(256), 0, s, t->W1, t->G1, t->m1, t->v1, n, lr, beta1, beta2, eps, c1, c2);

@@ -1,0 +1,48 @@
+// Read-stream reference kernel: the achievable HBM read bandwidth the
+// read-dominated stencils are measured against (the coarse operator of Eq. (3)
+// reads its links once and writes a vector a ninth of their size).  Every
+// thread walks the buffer grid-strided with four independent 16-byte loads in
+// flight per step, folds what it reads into one word, and one word per
+// work-group is written so the loads cannot be dropped.  The launch fills the
+// device: 8 work-groups of 256 threads per compute unit.
+#include "qmg_internal.h"
+
+namespace {
+
+__global__ __launch_bounds__(256) void k_read_stream(const uint4* __restrict__ p, int64_t n, uint32_t* __restrict__ sink) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+    }
+    for (; i < n; i += stride) {
+        const uint4 a = p[i];
+        acc ^= a.x ^ a.y ^ a.z ^ a.w;
+    }
+    __shared__ uint32_t red[4];
+    for (int o = 32; o > 0; o >>= 1) acc ^= __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) sink[blockIdx.x] = red[0] ^ red[1] ^ red[2] ^ red[3];
+}
+
+}  // namespace
+
+using namespace qmg;
+
+extern "C" qmg_status qmg_stream_read(const void* buf, long long bytes, void* sink, int sink_words, void* stream) {
+    if (!buf || !sink) return fail(QMG_ERR_ARG, "stream_read: NULL argument");
+    if (bytes < 16 || bytes % 16) return fail(QMG_ERR_ARG, "stream_read: %lld bytes (a multiple of 16)", bytes);
+    int dev = 0, cus = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    QMG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const unsigned grid = (unsigned)(cus > 0 ? 8 * cus : 2048);
+    if ((long long)sink_words < (long long)grid)
+        return fail(QMG_ERR_ARG, "stream_read: the sink needs %u words, has %d", grid, sink_words);
+    hipLaunchKernelGGL(k_read_stream, dim3(grid), dim3(256), 0, as_stream(stream), static_cast<const uint4*>(buf),
+                       (int64_t)(bytes / 16), static_cast<uint32_t*>(sink));
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}

@@ -26,228 +26,12 @@
 // FP32 scale per (chirality, site), value = scale * stored.  Vectors are then
 // either complex64 or 16-bit pairs [V][12] words with one FP32 scale per site
 // (the largest |re| or |im| of its 12 components).
-#include "codes16.h"
-#include "handles.h"
+#include "wilson_dev.h"
 
 #include <mutex>
 #include <vector>
 
 namespace qmg {
-
-// ------------------------------------------------------------------ helpers
-template <typename R> struct c3 { cpx<R> v[3]; };
-
-template <typename R>
-__device__ __forceinline__ cpx<R> cadd(cpx<R> a, cpx<R> b) { return {a.re + b.re, a.im + b.im}; }
-template <typename R>
-__device__ __forceinline__ cpx<R> csub(cpx<R> a, cpx<R> b) { return {a.re - b.re, a.im - b.im}; }
-template <typename R>
-__device__ __forceinline__ cpx<R> cmul(cpx<R> a, cpx<R> b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-template <typename R>
-__device__ __forceinline__ cpx<R> cmulc(cpx<R> a, cpx<R> b) {  // conj(a) * b
-    return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
-}
-template <typename R> __device__ __forceinline__ cpx<R> ci(cpx<R> a) { return {-a.im, a.re}; }   // i a
-template <typename R> __device__ __forceinline__ cpx<R> cmi(cpx<R> a) { return {a.im, -a.re}; }  // -i a
-template <typename R> __device__ __forceinline__ cpx<R> cneg(cpx<R> a) { return {-a.re, -a.im}; }
-
-// g_mu * (p, q) for the 2x2 off-diagonal block of gamma_mu
-template <int MU, typename R>
-__device__ __forceinline__ void gmul(cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q) {
-    if (MU == 0) { o0 = cmi(q); o1 = cmi(p); }          // -i sigma_1
-    else if (MU == 1) { o0 = cneg(q); o1 = p; }         // -i sigma_2 = [[0,-1],[1,0]]
-    else if (MU == 2) { o0 = cmi(p); o1 = ci(q); }      // -i sigma_3 = diag(-i, i)
-    else { o0 = p; o1 = q; }                            // 1
-}
-// g_mu^+ * (p, q)
-template <int MU, typename R>
-__device__ __forceinline__ void gdmul(cpx<R>& o0, cpx<R>& o1, cpx<R> p, cpx<R> q) {
-    if (MU == 0) { o0 = ci(q); o1 = ci(p); }            // i sigma_1
-    else if (MU == 1) { o0 = q; o1 = cneg(p); }         // i sigma_2 = [[0,1],[-1,0]]
-    else if (MU == 2) { o0 = ci(p); o1 = cmi(q); }      // i sigma_3 = diag(i, -i)
-    else { o0 = p; o1 = q; }
-}
-
-template <int LF> struct FineT { using R = float; };
-template <> struct FineT<FMT_F64> { using R = double; };
-template <int F> constexpr bool is16f() { return F == FMT_H16 || F == FMT_B16; }
-
-template <int LF, typename R>
-__device__ __forceinline__ void load_link(cpx<R> u[9], const void* __restrict__ U, int mu, int64_t site,
-                                          int64_t V) {
-    if constexpr (is16f<LF>()) {
-        const uint32_t* W = static_cast<const uint32_t*>(U);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = dec_pair<LF>(W[((int64_t)mu * 9 + e) * V + site]);
-    } else {
-        const cpx<R>* P = static_cast<const cpx<R>*>(U);
-#pragma unroll
-        for (int e = 0; e < 9; ++e) u[e] = P[((int64_t)mu * 9 + e) * V + site];
-    }
-}
-
-// One chirality block of the clover term: 6 diagonal reals, 15 upper entries.
-template <int LF, typename R>
-__device__ __forceinline__ void load_clover(R d[6], cpx<R> o[15], const void* __restrict__ clov,
-                                            const float* __restrict__ cscale, int chi, int64_t site, int64_t V) {
-    if constexpr (is16f<LF>()) {
-        const uint32_t* W = static_cast<const uint32_t*>(clov) + (int64_t)chi * 18 * V + site;
-        const float k = cscale[(int64_t)chi * V + site];
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-            const cpx<float> v = dec_pair<LF>(W[q * V]);
-            d[2 * q] = k * v.re;
-            d[2 * q + 1] = k * v.im;
-        }
-#pragma unroll
-        for (int q = 0; q < 15; ++q) {
-            const cpx<float> v = dec_pair<LF>(W[(3 + q) * V]);
-            o[q] = {k * v.re, k * v.im};
-        }
-    } else {
-        const R* A = static_cast<const R*>(clov) + (int64_t)chi * 36 * V + site;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) d[i] = A[i * V];
-#pragma unroll
-        for (int q = 0; q < 15; ++q) o[q] = {A[(6 + 2 * q) * V], A[(7 + 2 * q) * V]};
-    }
-}
-
-// acc += H x for a site-local matrix H stored as two packed Hermitian 6x6
-// chirality blocks (the clover term, or the inverse of the site-local block).
-template <int LF, typename R>
-__device__ __forceinline__ void herm_mul_add(cpx<R> acc[12], const cpx<R> x12[12], const void* __restrict__ H,
-                                             const float* __restrict__ hscale, int64_t site, int64_t V) {
-#pragma unroll
-    for (int chi = 0; chi < 2; ++chi) {
-        R d[6];
-        cpx<R> o[15];
-        load_clover<LF>(d, o, H, hscale, chi, site, V);
-        const cpx<R>* x = x12 + 6 * chi;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            cpx<R> t = {d[i] * x[i].re, d[i] * x[i].im};
-            int k = 0;
-#pragma unroll
-            for (int r = 0; r < 6; ++r)
-#pragma unroll
-                for (int c = r + 1; c < 6; ++c, ++k) {
-                    if (r == i) t = cadd(t, cmul(o[k], x[c]));
-                    if (c == i) t = cadd(t, cmulc(o[k], x[r]));
-                }
-            acc[6 * chi + i] = cadd(acc[6 * chi + i], t);
-        }
-    }
-}
-
-// A site's 12 spinor components, with 16-byte loads (3 for 16-bit pairs, 6 in
-// FP32, 12 in FP64).
-template <int VF, typename R>
-__device__ __forceinline__ void load_spinor(cpx<R> p[12], const void* __restrict__ src,
-                                            const float* __restrict__ scale, int64_t site) {
-    if constexpr (is16f<VF>()) {
-        const uint4* s4 = static_cast<const uint4*>(src) + site * 3;
-        const float k = scale[site];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const uint4 w = s4[i];
-            const uint32_t q[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const cpx<float> v = dec_pair<VF>(q[j]);
-                p[4 * i + j] = cpx<R>{k * v.re, k * v.im};
-            }
-        }
-    } else if constexpr (VF == FMT_F32) {
-        const float4* s4 = static_cast<const float4*>(src) + site * 6;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) {
-            const float4 v = s4[i];
-            p[2 * i] = cpx<R>{v.x, v.y};
-            p[2 * i + 1] = cpx<R>{v.z, v.w};
-        }
-    } else {
-        const cpx<R>* s = static_cast<const cpx<R>*>(src) + site * 12;
-#pragma unroll
-        for (int f = 0; f < 12; ++f) p[f] = s[f];
-    }
-}
-
-template <int VF, typename R>
-__device__ __forceinline__ void store_spinor(void* __restrict__ dst, float* __restrict__ scale, int64_t site,
-                                             const cpx<R> p[12]) {
-    if constexpr (is16f<VF>()) {
-        float m = 0.0f;
-#pragma unroll
-        for (int f = 0; f < 12; ++f) m = fmaxf(m, fmaxf(fabsf(p[f].re), fabsf(p[f].im)));
-        const float inv = m > 0.0f ? 1.0f / m : 0.0f;
-        uint4* d4 = static_cast<uint4*>(dst) + site * 3;
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            uint32_t q[4];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) q[j] = enc_pair<VF>(p[4 * i + j].re * inv, p[4 * i + j].im * inv);
-            d4[i] = make_uint4(q[0], q[1], q[2], q[3]);
-        }
-        scale[site] = m;
-    } else if constexpr (VF == FMT_F32) {
-        float4* d4 = static_cast<float4*>(dst) + site * 6;
-#pragma unroll
-        for (int i = 0; i < 6; ++i) d4[i] = make_float4(p[2 * i].re, p[2 * i].im, p[2 * i + 1].re, p[2 * i + 1].im);
-    } else {
-        cpx<R>* d = static_cast<cpx<R>*>(dst) + site * 12;
-#pragma unroll
-        for (int f = 0; f < 12; ++f) d[f] = p[f];
-    }
-}
-
-// One hop in direction MU; BACK selects the backward hop: the operands of
-// acc += -1/2 * P (x) W psi(n).  vo: offset (in sites) of the batch member's vectors
-template <int MU, bool BACK, int LF, int VF, typename R>
-__device__ __forceinline__ void hop_load(cpx<R> p[12], cpx<R> u[9], const void* __restrict__ in,
-                                         const float* __restrict__ in_scale, const void* __restrict__ U, int64_t V,
-                                         int64_t site, int64_t n, int64_t vo) {
-    load_spinor<VF>(p, in, in_scale, n + vo);
-    load_link<LF>(u, U, MU, BACK ? n : site, V);
-}
-
-// acc += h * P (x) W psi(n): h = -1/2 is the hop term of Eq. (2)
-template <int MU, bool BACK, typename R>
-__device__ __forceinline__ void hop_apply(cpx<R> acc[12], const cpx<R> p[12], const cpx<R> u[9], const R h = R(-0.5)) {
-    cpx<R> a[2][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        cpx<R> g0, g1;
-        gmul<MU>(g0, g1, p[6 + c], p[9 + c]);
-        if (!BACK) { a[0][c] = csub(p[c], g0); a[1][c] = csub(p[3 + c], g1); }
-        else { a[0][c] = cadd(p[c], g0); a[1][c] = cadd(p[3 + c], g1); }
-    }
-    cpx<R> w[2][3];
-#pragma unroll
-    for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-            cpx<R> t = {0, 0};
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                if (!BACK) t = cadd(t, cmul(u[r * 3 + c], a[s][c]));
-                else t = cadd(t, cmulc(u[c * 3 + r], a[s][c]));
-            }
-            w[s][r] = t;
-        }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        cpx<R> l0, l1;
-        gdmul<MU>(l0, l1, w[0][c], w[1][c]);
-        acc[c].re += h * w[0][c].re; acc[c].im += h * w[0][c].im;
-        acc[3 + c].re += h * w[1][c].re; acc[3 + c].im += h * w[1][c].im;
-        if (!BACK) { l0 = cneg(l0); l1 = cneg(l1); }
-        acc[6 + c].re += h * l0.re; acc[6 + c].im += h * l0.im;
-        acc[9 + c].re += h * l1.re; acc[9 + c].im += h * l1.im;
-    }
-}
 
 // LF: storage of links and clover; VF: storage of the vectors (the same as LF
 // for complex128 / complex64, complex64 or 16-bit pairs for 16-bit links).
@@ -256,14 +40,16 @@ __device__ __forceinline__ void hop_apply(cpx<R> acc[12], const cpx<R> p[12], co
 // DOT: also the minimal-residual step's inner products of the result with
 // the input, <out,out> and <out,in> (re, im), summed over the work-group in
 // FP64 (fixed order) into part[member*pmember + value*pvalue + blockIdx.x].
-template <int LF, int VF, bool DOT = false>
+// LR: stored reals per link (18, or 12 with the third row rebuilt).
+template <int LF, int VF, bool DOT = false, int LR = 18>
 __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ U, const void* __restrict__ clov,
                                                        const float* __restrict__ cscale,
                                                        const int* __restrict__ nbr, const void* __restrict__ in,
                                                        const float* __restrict__ in_scale, void* __restrict__ out,
                                                        float* __restrict__ out_scale, int64_t V,
                                                        typename FineT<LF>::R diag, int use_clover,
-                                                       double* __restrict__ part, int64_t pmember, int pvalue) {
+                                                       double* __restrict__ part, int64_t pmember, int pvalue,
+                                                       int64_t last) {
     using R = typename FineT<LF>::R;
     // Work-groups are dealt to the 8 XCDs round-robin; renumber them so that
     // each XCD sweeps one contiguous range of sites and the neighbours one
@@ -281,8 +67,8 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
     // FP32: the first two hops' operands are requested before the local terms
     cpx<R> pa[12], ua[9], pb[12], ub[9];
     if constexpr (sizeof(R) == 4) {
-        hop_load<0, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[0], vo);
-        hop_load<0, true, LF, VF>(pb, ub, in, in_scale, U, V, site, nb[1], vo);
+        hop_load<0, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[0], vo, last);
+        hop_load<0, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[1], vo, last);
     }
     cpx<R> acc[12];
     cpx<R> p[12];
@@ -294,36 +80,36 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
         // FP32 arithmetic: the next two hops' operands are loaded while the
         // current two are applied (measured 7-10% faster than one hop at a time)
         hop_apply<0, false>(acc, pa, ua);
-        hop_load<1, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[2], vo);
+        hop_load<1, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[2], vo, last);
         hop_apply<0, true>(acc, pb, ub);
-        hop_load<1, true, LF, VF>(pb, ub, in, in_scale, U, V, site, nb[3], vo);
+        hop_load<1, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[3], vo, last);
         hop_apply<1, false>(acc, pa, ua);
-        hop_load<2, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[4], vo);
+        hop_load<2, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[4], vo, last);
         hop_apply<1, true>(acc, pb, ub);
-        hop_load<2, true, LF, VF>(pb, ub, in, in_scale, U, V, site, nb[5], vo);
+        hop_load<2, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[5], vo, last);
         hop_apply<2, false>(acc, pa, ua);
-        hop_load<3, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[6], vo);
+        hop_load<3, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[6], vo, last);
         hop_apply<2, true>(acc, pb, ub);
-        hop_load<3, true, LF, VF>(pb, ub, in, in_scale, U, V, site, nb[7], vo);
+        hop_load<3, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[7], vo, last);
         hop_apply<3, false>(acc, pa, ua);
         hop_apply<3, true>(acc, pb, ub);
     } else {
         // FP64: two hops in flight would need all 256 registers (one wave per SIMD)
-        hop_load<0, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[0], vo);
+        hop_load<0, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[0], vo, last);
         hop_apply<0, false>(acc, pa, ua);
-        hop_load<0, true, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[1], vo);
+        hop_load<0, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[1], vo, last);
         hop_apply<0, true>(acc, pa, ua);
-        hop_load<1, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[2], vo);
+        hop_load<1, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[2], vo, last);
         hop_apply<1, false>(acc, pa, ua);
-        hop_load<1, true, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[3], vo);
+        hop_load<1, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[3], vo, last);
         hop_apply<1, true>(acc, pa, ua);
-        hop_load<2, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[4], vo);
+        hop_load<2, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[4], vo, last);
         hop_apply<2, false>(acc, pa, ua);
-        hop_load<2, true, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[5], vo);
+        hop_load<2, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[5], vo, last);
         hop_apply<2, true>(acc, pa, ua);
-        hop_load<3, false, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[6], vo);
+        hop_load<3, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[6], vo, last);
         hop_apply<3, false>(acc, pa, ua);
-        hop_load<3, true, LF, VF>(pa, ua, in, in_scale, U, V, site, nb[7], vo);
+        hop_load<3, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[7], vo, last);
         hop_apply<3, true>(acc, pa, ua);
     }
     if (live) store_spinor<VF>(out, out_scale, site + vo, acc);
@@ -374,14 +160,14 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
 // fields, or whole-lattice ones indexed by x (self_full, out_full).
 // Member b of a batch (grid dimension y) finds its fields at b*V/2 (half) or
 // b*V (whole) sites.
-template <int LF, int VF, int SELF, bool HOPS, bool INV>
+template <int LF, int VF, int SELF, bool HOPS, bool INV, int LR = 18>
 __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, const void* __restrict__ clov,
                                                    const float* __restrict__ cscale, const void* __restrict__ cinv,
                                                    const float* __restrict__ ciscale, const int* __restrict__ nbr,
                                                    const int* __restrict__ hsite, const void* __restrict__ self,
                                                    const void* __restrict__ hin, void* __restrict__ out, int64_t Vh,
                                                    int64_t V, typename FineT<LF>::R diag, typename FineT<LF>::R coef,
-                                                   int use_clover, int self_full, int out_full) {
+                                                   int use_clover, int self_full, int out_full, int64_t last) {
     using R = typename FineT<LF>::R;
     // XCD-contiguous work-group numbering, as in k_wilson_clover (grid a multiple of 8)
     const int64_t per = gridDim.x >> 3;
@@ -412,7 +198,7 @@ __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, c
         cpx<R> p[12], u[9];
 #define QMG_EO_HOP(MU, BACK, D)                                              \
         load_spinor<VF>(p, hin, nullptr, (int64_t)(nb[D] >> 1) + vh);         \
-        load_link<LF>(u, U, MU, BACK ? (int64_t)nb[D] : site, V);            \
+        load_link<LF, LR>(u, U, MU, BACK ? (int64_t)nb[D] : site, V, last);  \
         hop_apply<MU, BACK>(acc, p, u, c);
         QMG_EO_HOP(0, false, 0)
         QMG_EO_HOP(0, true, 1)
@@ -622,25 +408,20 @@ __global__ void k_clover_export(double2* __restrict__ out, const void* __restric
 }
 
 // The links as the operator holds them -> canonical [4][V][3][3] complex128,
-// with the antiperiodic time sign taken back out.  One thread per entry.
-template <int LF>
-__global__ void k_links_export(double2* __restrict__ G, const void* __restrict__ U, int64_t V,
-                               int64_t last_slice_start, int anti) {
+// with the antiperiodic time sign taken back out (the third row rebuilt for
+// compressed storage).  One thread per link.
+template <int LF, int LR>
+__global__ void k_links_export(double2* __restrict__ G, const void* __restrict__ U, int64_t V, int64_t last,
+                               int anti) {
     using R = typename FineT<LF>::R;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 4 * 9 * V) return;
+    if (g >= 4 * V) return;
     const int64_t site = g % V;
-    const int e = (int)((g / V) % 9);
-    const int mu = (int)(g / (9 * V));
-    cpx<R> v;
-    if constexpr (is16f<LF>()) {
-        const cpx<float> d = dec_pair<LF>(static_cast<const uint32_t*>(U)[g]);
-        v = cpx<R>{d.re, d.im};
-    } else {
-        v = static_cast<const cpx<R>*>(U)[g];
-    }
-    const double sgn = (anti && mu == 3 && site >= last_slice_start) ? -1.0 : 1.0;
-    G[((int64_t)mu * V + site) * 9 + e] = make_double2(sgn * (double)v.re, sgn * (double)v.im);
+    const int mu = (int)(g / V);
+    cpx<R> u[9];
+    load_link<LF, LR>(u, U, mu, site, V, last);
+    const double sgn = (anti && mu == 3 && site >= last) ? -1.0 : 1.0;
+    for (int e = 0; e < 9; ++e) G[((int64_t)mu * V + site) * 9 + e] = make_double2(sgn * (double)u[e].re, sgn * (double)u[e].im);
 }
 
 // FP64 clover [2][36][V] -> 16-bit pairs [2][18][V] with one scale per (chirality, site).
@@ -660,29 +441,31 @@ __global__ void k_clover_pack16(uint32_t* __restrict__ W, float* __restrict__ cs
     }
 }
 
-// Canonical gauge -> 16-bit pairs [4][9][V], time sign folded.
+// Canonical gauge -> 16-bit pairs [4][ne][V] (ne = 9, or 6: rows 0 and 1 of a
+// compressed link), time sign folded.
 template <int LF>
 __global__ void k_pack_gauge16(uint32_t* __restrict__ U, const double2* __restrict__ G, int64_t V,
-                               int64_t last_slice_start, int anti) {
+                               int64_t last_slice_start, int anti, int ne) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 4 * 9 * V) return;
+    if (g >= 4 * ne * V) return;
     const int64_t site = g % V;
-    const int e = (int)((g / V) % 9);
-    const int mu = (int)(g / (9 * V));
+    const int e = (int)((g / V) % ne);
+    const int mu = (int)(g / (ne * V));
     const double2 v = G[((int64_t)mu * V + site) * 9 + e];
     const double sgn = (anti && mu == 3 && site >= last_slice_start) ? -1.0 : 1.0;
     U[g] = enc_pair<LF>((float)(sgn * v.x), (float)(sgn * v.y));
 }
 
-// Canonical gauge [4][V][3][3] complex128 -> SoA [4][9][V] in R, time sign folded.
+// Canonical gauge [4][V][3][3] complex128 -> SoA [4][ne][V] in R (ne = 9, or 6
+// for compressed links), time sign folded.
 template <typename R>
 __global__ void k_pack_gauge(cpx<R>* __restrict__ U, const double2* __restrict__ G, int64_t V,
-                             int64_t last_slice_start, int anti) {
+                             int64_t last_slice_start, int anti, int ne) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 4 * 9 * V) return;
+    if (g >= 4 * ne * V) return;
     const int64_t site = g % V;
-    const int e = (int)((g / V) % 9);
-    const int mu = (int)(g / (9 * V));
+    const int e = (int)((g / V) % ne);
+    const int mu = (int)(g / (ne * V));
     const double2 v = G[((int64_t)mu * V + site) * 9 + e];
     const double sgn = (anti && mu == 3 && site >= last_slice_start) ? -1.0 : 1.0;
     U[g] = cpx<R>{(R)(sgn * v.x), (R)(sgn * v.y)};
@@ -733,9 +516,17 @@ static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const f
                                 int64_t pmember = 0, int pvalue = 0) {
     using R = typename FineT<LF>::R;
     const unsigned nb = (unsigned)wilson_groups(op);
-    hipLaunchKernelGGL((k_wilson_clover<LF, VF, DOT>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov, op->cscale,
-                       op->nbr, in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0), op->csw != 0.0 ? 1 : 0, part,
-                       pmember, pvalue);
+#define QMG_WC_LAUNCH(LR)                                                                                          \
+    hipLaunchKernelGGL((k_wilson_clover<LF, VF, DOT, LR>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov,   \
+                       op->cscale, op->nbr, in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0),              \
+                       op->csw != 0.0 ? 1 : 0, part, pmember, pvalue, op->last)
+    if constexpr (LF != FMT_F64) {
+        if (op->link_reals == 12) QMG_WC_LAUNCH(12);
+        else QMG_WC_LAUNCH(18);
+    } else {
+        QMG_WC_LAUNCH(18);
+    }
+#undef QMG_WC_LAUNCH
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -807,10 +598,19 @@ static qmg_status launch_eo(const qmg_fine_op_s* op, int piece, int parity, cons
     const R diag = (R)(4.0 + op->m0);
     const int uc = op->csw != 0.0 ? 1 : 0;
     const dim3 grid(nb, (unsigned)m), block(256);
+#define QMG_EO_LAUNCH_LR(SELF, HOPS, INV, COEF, LR)                                                              \
+    hipLaunchKernelGGL((k_wilson_eo<LF, VF, SELF, HOPS, INV, LR>), grid, block, 0, s, op->U, op->clov,          \
+                       op->cscale, op->cinv, op->ciscale, op->nbr, hs, self, hin, out, Vh, op->V, diag, (R)(COEF), \
+                       uc, self_full, out_full, op->last)
 #define QMG_EO_LAUNCH(SELF, HOPS, INV, COEF)                                                                    \
-    hipLaunchKernelGGL((k_wilson_eo<LF, VF, SELF, HOPS, INV>), grid, block, 0, s, op->U, op->clov, op->cscale,  \
-                       op->cinv, op->ciscale, op->nbr, hs, self, hin, out, Vh, op->V, diag, (R)(COEF), uc,        \
-                       self_full, out_full)
+    do {                                                                                                        \
+        if constexpr (LF != FMT_F64 && HOPS) {                                                                  \
+            if (op->link_reals == 12) QMG_EO_LAUNCH_LR(SELF, HOPS, INV, COEF, 12);                               \
+            else QMG_EO_LAUNCH_LR(SELF, HOPS, INV, COEF, 18);                                                    \
+        } else {                                                                                                \
+            QMG_EO_LAUNCH_LR(SELF, HOPS, INV, COEF, 18);                                                         \
+        }                                                                                                       \
+    } while (0)
     switch (piece) {
         case EO_HOP_INV: QMG_EO_LAUNCH(0, true, true, 1.0); break;
         case EO_DIAG_HOP: QMG_EO_LAUNCH(2, true, false, -1.0); break;
@@ -820,6 +620,7 @@ static qmg_status launch_eo(const qmg_fine_op_s* op, int piece, int parity, cons
         default: QMG_EO_LAUNCH(1, false, false, 0.0);
     }
 #undef QMG_EO_LAUNCH
+#undef QMG_EO_LAUNCH_LR
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -898,15 +699,19 @@ extern "C" void qmg_fine_op_destroy(qmg_fine_op op) {
     delete op;
 }
 
-extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, double m0, double csw,
-                                         int antiperiodic_t, qmg_prec storage, void* stream,
-                                         qmg_fine_op* out) {
+extern "C" qmg_status qmg_fine_op_create_ex(const int dims[4], const void* gauge, double m0, double csw,
+                                            int antiperiodic_t, qmg_prec storage, int link_reals, void* stream,
+                                            qmg_fine_op* out) {
     if (!out) return fail(QMG_ERR_ARG, "fine_op_create: out is NULL");
     *out = nullptr;
     QMG_TRY(check_dims(dims, 2, "fine_op_create"));
     if (!gauge) return fail(QMG_ERR_ARG, "fine_op_create: gauge is NULL");
     if (storage != QMG_C128 && storage != QMG_C64 && !is16p(storage))
         return fail(QMG_ERR_PREC, "fine_op_create: storage %d not supported", (int)storage);
+    if (link_reals != 18 && link_reals != 12)
+        return fail(QMG_ERR_ARG, "fine_op_create: link_reals %d (18 or 12)", link_reals);
+    if (link_reals == 12 && storage == QMG_C128)
+        return fail(QMG_ERR_PREC, "fine_op_create: compressed links are for the complex64 and 16-bit storages");
     hipStream_t s = as_stream(stream);
     auto* op = new qmg_fine_op_s();
     for (int m = 0; m < 4; ++m) op->dims[m] = dims[m];
@@ -915,8 +720,11 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
     op->csw = csw;
     op->antiperiodic_t = antiperiodic_t ? 1 : 0;
     op->storage = storage;
+    op->link_reals = link_reals;
+    op->last = op->V - op->V / dims[3];
+    const int ne = link_reals == 12 ? 6 : 9;   // stored entries per link
     const size_t rb = real_bytes(storage);
-    hipError_t e = hipMalloc(&op->U, 2 * rb * 36 * op->V);
+    hipError_t e = hipMalloc(&op->U, 2 * rb * 4 * ne * op->V);
     if (e == hipSuccess) e = hipMalloc(&op->clov, rb * 72 * op->V);
     if (e == hipSuccess && is16p(storage)) e = hipMalloc(&op->cscale, sizeof(float) * 2 * op->V);
     if (e != hipSuccess) {
@@ -928,8 +736,8 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
         qmg_fine_op_destroy(op);
         return st;
     }
-    const int64_t last = op->V - op->V / dims[3];
-    const unsigned nbU = (unsigned)((36 * op->V + 255) / 256), nbS = (unsigned)((op->V + 127) / 128);
+    const int64_t last = op->last;
+    const unsigned nbU = (unsigned)((4 * ne * op->V + 255) / 256), nbS = (unsigned)((op->V + 127) / 128);
     const SigmaBlocks sb = sigma_blocks(csw);
     // red-black form when every extent is even: the half-site table and the
     // inverse of the site-local block, built from the FP64 clover term
@@ -956,7 +764,7 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
     const double diag = 4.0 + m0;
     if (storage == QMG_C128) {
         hipLaunchKernelGGL(k_pack_gauge<double>, dim3(nbU), dim3(256), 0, s, (cpx<double>*)op->U,
-                           (const double2*)gauge, op->V, last, op->antiperiodic_t);
+                           (const double2*)gauge, op->V, last, op->antiperiodic_t, ne);
         hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)op->clov,
                            (const double2*)gauge, op->nbr, op->V, sb);
         if (eo)
@@ -964,7 +772,7 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
                                (const double*)op->clov, op->V, diag);
     } else if (storage == QMG_C64) {
         hipLaunchKernelGGL(k_pack_gauge<float>, dim3(nbU), dim3(256), 0, s, (cpx<float>*)op->U,
-                           (const double2*)gauge, op->V, last, op->antiperiodic_t);
+                           (const double2*)gauge, op->V, last, op->antiperiodic_t, ne);
         hipLaunchKernelGGL(k_clover_build<float>, dim3(nbS), dim3(128), 0, s, (float*)op->clov,
                            (const double2*)gauge, op->nbr, op->V, sb);
         if (eo) {
@@ -985,7 +793,7 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
                                op->V, diag);
         if (storage == QMG_H16) {
             hipLaunchKernelGGL(k_pack_gauge16<FMT_H16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
-                               (const double2*)gauge, op->V, last, op->antiperiodic_t);
+                               (const double2*)gauge, op->V, last, op->antiperiodic_t, ne);
             hipLaunchKernelGGL(k_clover_pack16<FMT_H16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
                                op->cscale, (const double*)c64, op->V);
             if (eo)
@@ -993,7 +801,7 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
                                    op->ciscale, (const double*)i64, op->V);
         } else {
             hipLaunchKernelGGL(k_pack_gauge16<FMT_B16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
-                               (const double2*)gauge, op->V, last, op->antiperiodic_t);
+                               (const double2*)gauge, op->V, last, op->antiperiodic_t, ne);
             hipLaunchKernelGGL(k_clover_pack16<FMT_B16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
                                op->cscale, (const double*)c64, op->V);
             if (eo)
@@ -1015,6 +823,11 @@ extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, d
     return QMG_OK;
 }
 
+extern "C" qmg_status qmg_fine_op_create(const int dims[4], const void* gauge, double m0, double csw,
+                                         int antiperiodic_t, qmg_prec storage, void* stream, qmg_fine_op* out) {
+    return qmg_fine_op_create_ex(dims, gauge, m0, csw, antiperiodic_t, storage, 18, stream, out);
+}
+
 extern "C" qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* stream) {
     if (!op || !A) return fail(QMG_ERR_ARG, "fine_op_export_clover: NULL argument");
     hipStream_t s = as_stream(stream);
@@ -1032,15 +845,24 @@ extern "C" qmg_status qmg_fine_op_export_clover(qmg_fine_op op, void* A, void* s
 extern "C" qmg_status qmg_fine_op_export_links(qmg_fine_op op, void* gauge, void* stream) {
     if (!op || !gauge) return fail(QMG_ERR_ARG, "fine_op_export_links: NULL argument");
     hipStream_t s = as_stream(stream);
-    const unsigned nb = (unsigned)((36 * op->V + 255) / 256);
-    const int64_t last = op->V - op->V / op->dims[3];
+    const unsigned nb = (unsigned)((4 * op->V + 255) / 256);
+    const int64_t last = op->last;
     double2* G = static_cast<double2*>(gauge);
+    const bool c12 = op->link_reals == 12;
+#define QMG_LX(F)                                                                                                  \
+    do {                                                                                                           \
+        if (c12) hipLaunchKernelGGL((k_links_export<F, 12>), dim3(nb), dim3(256), 0, s, G, op->U, op->V, last,     \
+                                    op->antiperiodic_t);                                                           \
+        else hipLaunchKernelGGL((k_links_export<F, 18>), dim3(nb), dim3(256), 0, s, G, op->U, op->V, last,         \
+                                op->antiperiodic_t);                                                               \
+    } while (0)
     switch (op->storage) {
-        case QMG_C128: hipLaunchKernelGGL(k_links_export<FMT_F64>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
-        case QMG_C64: hipLaunchKernelGGL(k_links_export<FMT_F32>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
-        case QMG_H16: hipLaunchKernelGGL(k_links_export<FMT_H16>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
-        default: hipLaunchKernelGGL(k_links_export<FMT_B16>, dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t);
+        case QMG_C128: hipLaunchKernelGGL((k_links_export<FMT_F64, 18>), dim3(nb), dim3(256), 0, s, G, op->U, op->V, last, op->antiperiodic_t); break;
+        case QMG_C64: QMG_LX(FMT_F32); break;
+        case QMG_H16: QMG_LX(FMT_H16); break;
+        default: QMG_LX(FMT_B16);
     }
+#undef QMG_LX
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -1122,6 +944,7 @@ extern "C" qmg_status qmg_wilson_clover_schur_reconstruct(qmg_fine_op op, const 
     if (x == b || x == x_e) return fail(QMG_ERR_ARG, "wilson_clover_schur_reconstruct: x aliases an input");
     return fine_schur_reconstruct(op, x_e, b, x, prec, nrhs, as_stream(stream));
 }
+
 // ------------------------------------------------------ allocation-free Schur
 // For callers that cannot allocate (code under graph capture, tight serving
 // loops): the odd half-lattice scratch of the Schur operator lives in a
