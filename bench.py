@@ -735,6 +735,7 @@ def main():
     ap.add_argument('--mg-solves', type=int, default=0,
                     help='only time this many MG-GCR solves on 16^3x32 (after the setup) instead')
     ap.add_argument('--coarse-direct', action='store_true', help='with --mg-solves: exact coarsest solve')
+    ap.add_argument('--red-black', action='store_true', help='with --mg-solves: red-black form on every level')
     ap.add_argument('--only-small', action='store_true',
                     help='only the smallest-grid records (rows a1, a3-a5) instead')
     ap.add_argument('--only-16bit', action='store_true',
@@ -778,8 +779,16 @@ def main():
         return
     if args.mg_solves:
         mg, _, m0, _, setup = build_mg_16x32(coarse_direct=args.coarse_direct)
-        r = {'lattice': [16, 16, 16, 32], 'm0': m0, 'coarse_direct': args.coarse_direct, 'setup_s': round(setup, 2)}
+        r = {'lattice': [16, 16, 16, 32], 'm0': m0, 'coarse_direct': args.coarse_direct,
+             'red_black': args.red_black, 'setup_s': round(setup, 2)}
+        if args.red_black:
+            mg.set_evenodd(True)
         r.update(timed_solves(mg, args.mg_solves, 0))
+        mg.set_level_timing(True)
+        _, info = mg.solve(torch.from_numpy(synth.gaussian((mg.V, 4, 3), 1, 2)).to('cuda'), tol=1e-10)
+        mg.set_level_timing(False)
+        r['level_seconds'] = {'total_s': round(info['seconds'], 5),
+                              'per_level_s': [round(t, 5) for t in info['level_seconds']]}
         print(json.dumps({'mg_solves': r}), flush=True)
         return
     if args.precision_form:

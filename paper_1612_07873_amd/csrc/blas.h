@@ -50,6 +50,10 @@ struct Blas {
     // x = alpha d; rout = r - alpha Ad
     template <typename R> qmg_status dir_step(const double* s3, const void* d, const void* Ad, const void* r, void* x,
                                               void* rout, int64_t n);
+    // the same step only where it lowers the residual (<Ad,Ad> - 2 Re <Ad,r> < 0, all
+    // finite); elsewhere x = 0, rout = r and the member's s3[cnt] is incremented
+    template <typename R> qmg_status dir_step_checked(double* s3, const void* d, const void* Ad, const void* r,
+                                                      void* x, void* rout, int64_t n, int cnt);
     template <typename R> qmg_status axpy(double a, const void* x, void* y, int64_t n);       // y += a x
     template <typename R> qmg_status xmy(const void* b, const void* ax, void* r, int64_t n);  // r = b - ax
     template <typename Rs, typename Rd> qmg_status convert(const void* src, void* dst, int64_t n);

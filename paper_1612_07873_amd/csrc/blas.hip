@@ -1,6 +1,9 @@
 // BLAS-1 kernels of the solvers (see blas.h).
 #include "blas.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace qmg {
 
 static constexpr int kThreads = 256;
@@ -264,6 +267,33 @@ __global__ void k_dir_step(const double* __restrict__ s3, const cpx<R>* __restri
     rout[i] = cpx<R>{rr.re - (ar * a.re - ai * a.im), rr.im - (ar * a.im + ai * a.re)};
 }
 
+// As k_dir_step for a step that may be refused: it is taken only where it
+// lowers the residual (|r - Ad|^2 < |r|^2, i.e. <Ad,Ad> - 2 Re <Ad,r> < 0,
+// every scalar finite); a refused step leaves x = 0 and rout = r and adds one
+// to the member's counter s3[cnt].
+template <typename R>
+__global__ void k_dir_step_checked(double* __restrict__ s3, const cpx<R>* __restrict__ d,
+                                   const cpx<R>* __restrict__ Ad, const cpx<R>* __restrict__ r,
+                                   cpx<R>* __restrict__ x, cpx<R>* __restrict__ rout, int64_t n, int ss, int cnt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(d); QMG_MEMBER_VEC(Ad); QMG_MEMBER_VEC(r); QMG_MEMBER_VEC(x);
+    QMG_MEMBER_VEC(rout);
+    const double den = s3[0], re = s3[1], im = s3[2];
+    const bool ok = den > 0 && isfinite(den) && isfinite(re) && isfinite(im) && den - 2 * re < 0;
+    const cpx<R> rr = r[i];
+    if (!ok) {
+        x[i] = cpx<R>{0, 0};
+        rout[i] = rr;
+        if (i == 0) s3[cnt] += 1.0;
+        return;
+    }
+    const R ar = (R)(re / den), ai = (R)(im / den);
+    const cpx<R> dd = d[i], a = Ad[i];
+    x[i] = cpx<R>{ar * dd.re - ai * dd.im, ar * dd.im + ai * dd.re};
+    rout[i] = cpx<R>{rr.re - (ar * a.re - ai * a.im), rr.im - (ar * a.im + ai * a.re)};
+}
+
 template <typename R>
 __global__ void k_axpy(R a, const cpx<R>* __restrict__ x, cpx<R>* __restrict__ y, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,13 +373,18 @@ __device__ __forceinline__ void wg_sums(const double* acc, int nv, bool with32, 
 // so the host can queue several steps and read the scalars only now and then:
 // the steps after convergence change nothing, and whether a step runs is
 // decided by the same data in every member's work-group.
-template <typename R>
-__global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restrict__ Q, const cpx<R>* __restrict__ Z,
-                                                         int64_t ld, int k, cpx<R>* __restrict__ q,
-                                                         cpx<R>* __restrict__ z, cpx<R>* __restrict__ x,
-                                                         cpx<R>* __restrict__ r, int64_t n, double* __restrict__ out,
-                                                         cpx<R>* __restrict__ znext, int ss, double tol, int okoff,
-                                                         int bnoff, int nbm, int par) {
+//
+// The number K of stored pairs is a template parameter, so every loop over
+// them is unrolled with unconditional loads and a sweep keeps all of its
+// loads in flight (a load under a run-time condition waits for the ones
+// before it).
+template <typename R, int K>
+__global__ __launch_bounds__(512) void k_gcr_step_small(const cpx<R>* __restrict__ Q, const cpx<R>* __restrict__ Z,
+                                                        int64_t ld, cpx<R>* __restrict__ q,
+                                                        cpx<R>* __restrict__ z, cpx<R>* __restrict__ x,
+                                                        cpx<R>* __restrict__ r, int64_t n, double* __restrict__ out,
+                                                        cpx<R>* __restrict__ znext, int ss, double tol, int okoff,
+                                                        int bnoff, int nbm, int par) {
     __shared__ double sc[36];
     __shared__ double part[16][36];
     {
@@ -365,21 +400,20 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
     if (znext) QMG_MEMBER_VEC(znext);
     const int t = threadIdx.x, T = blockDim.x;
     double acc[36];
-    // sweep A: <Q_j, q> (j < k) and |q|^2
+    // sweep A: <Q_j, q> (j < K) and |q|^2
 #pragma unroll
     for (int v = 0; v < 36; ++v) acc[v] = 0;
     for (int64_t i = t; i < n; i += T) {
         const cpx<R> b = q[i];
         acc[32] += (double)b.re * b.re + (double)b.im * b.im;
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
-            if (j < k) {
-                const cpx<R> a = Q[j * ld + i];
-                acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
-                acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
-            }
+        for (int j = 0; j < K; ++j) {
+            const cpx<R> a = Q[j * ld + i];
+            acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+            acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
+        }
     }
-    wg_sums(acc, 2 * k, true, part, sc);
+    wg_sums(acc, 2 * K, true, part, sc);
     double qq0 = sc[32];
     double qq = qq0, re = 0, im = 0;
     for (int pass = 0; pass < 2; ++pass) {
@@ -387,7 +421,8 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
         double n2 = 0, dr = 0, di = 0;
         for (int64_t i = t; i < n; i += T) {
             R qr = q[i].re, qi = q[i].im, zr = z[i].re, zi = z[i].im;
-            for (int j = 0; j < k; ++j) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
                 const R br = (R)sc[2 * j], bi = (R)sc[2 * j + 1];
                 const cpx<R> a = Q[j * ld + i], c = Z[j * ld + i];
                 qr -= br * a.re - bi * a.im;
@@ -407,7 +442,7 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
         __syncthreads();   // every thread has read sc (the betas) before it is overwritten
         wg_sums(a3, 3, false, part, sc);
         qq = sc[0]; re = sc[1]; im = sc[2];
-        if (pass == 1 || k == 0 || !(qq < 0.5 * qq0)) break;
+        if (pass == 1 || K == 0 || !(qq < 0.5 * qq0)) break;
         // the projection cancelled most of q: orthogonalise once more (sweep A again, dots only)
         qq0 = qq;
 #pragma unroll
@@ -415,15 +450,14 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
         for (int64_t i = t; i < n; i += T) {
             const cpx<R> b = q[i];
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
-                if (j < k) {
-                    const cpx<R> a = Q[j * ld + i];
-                    acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
-                    acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
-                }
+            for (int j = 0; j < K; ++j) {
+                const cpx<R> a = Q[j * ld + i];
+                acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+                acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
+            }
         }
         __syncthreads();
-        wg_sums(acc, 2 * k, false, part, sc);
+        wg_sums(acc, 2 * K, false, part, sc);
     }
     double rr = 0;
     if (qq > 0) {
@@ -466,14 +500,242 @@ __global__ __launch_bounds__(1024) void k_gcr_step_small(const cpx<R>* __restric
     }
 }
 
+// The same step with its operands held in registers, for FP32 vectors of at
+// most E * 512 entries: thread t owns the E entries t + e T (e < E); its loads
+// of q, z, x, r and the stored Q_j are issued together at the start and those
+// of the Z_j together once q is projected, so the step waits on memory about
+// twice rather than once per entry and sweep.  Lanes past n read entry n - 1,
+// scaled to zero, so they add nothing to any sum and store nothing.  Each
+// stored pair costs about 7 E registers: E = 2 takes up to 9 pairs (restart
+// length 10) in 256 registers, E = 4 up to 4.
+template <int K, int E>
+__global__ __launch_bounds__(512) void k_gcr_step_reg(const cpx<float>* __restrict__ Q,
+                                                      const cpx<float>* __restrict__ Z, int64_t ld,
+                                                      cpx<float>* __restrict__ q, cpx<float>* __restrict__ z,
+                                                      cpx<float>* __restrict__ x, cpx<float>* __restrict__ r,
+                                                      int64_t n, double* __restrict__ out,
+                                                      cpx<float>* __restrict__ znext, int ss, double tol, int okoff,
+                                                      int bnoff, int nbm, int par) {
+    constexpr int KA = K > 0 ? K : 1;
+    __shared__ double sc[36];
+    __shared__ double part[16][36];
+    {
+        bool all = true;
+        for (int b = 0; b < nbm; ++b) all = all && out[(int64_t)b * ss + okoff + par] != 0.0;
+        if (all) {
+            if (threadIdx.x == 0) out[(int64_t)blockIdx.y * ss + okoff + 1 - par] = 1.0;
+            return;
+        }
+    }
+    QMG_MEMBER_VEC(Q); QMG_MEMBER_VEC(Z); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x);
+    QMG_MEMBER_VEC(r); QMG_MEMBER_SCAL(out);
+    if (znext) QMG_MEMBER_VEC(znext);
+    const int t = threadIdx.x, T = blockDim.x;
+    int64_t id[E];
+    float live[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t i = t + (int64_t)e * T;
+        live[e] = i < n ? 1.0f : 0.0f;
+        id[e] = i < n ? i : n - 1;
+    }
+    cpx<float> qv[E], zv[E], xv[E], rv[E], Qv[KA][E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        qv[e] = q[id[e]];
+        zv[e] = z[id[e]];
+        rv[e] = r[id[e]];
+        xv[e] = x[id[e]];
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+#pragma unroll
+        for (int e = 0; e < E; ++e) Qv[j][e] = Q[j * ld + id[e]];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        qv[e] = {qv[e].re * live[e], qv[e].im * live[e]};
+        zv[e] = {zv[e].re * live[e], zv[e].im * live[e]};
+        rv[e] = {rv[e].re * live[e], rv[e].im * live[e]};
+#pragma unroll
+        for (int j = 0; j < K; ++j) Qv[j][e] = {Qv[j][e].re * live[e], Qv[j][e].im * live[e]};
+    }
+    // sweep A: <Q_j, q> and |q|^2
+    double acc[36];
+#pragma unroll
+    for (int v = 0; v < 36; ++v) acc[v] = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const cpx<float> b = qv[e];
+        acc[32] += (double)b.re * b.re + (double)b.im * b.im;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const cpx<float> a = Qv[j][e];
+            acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+            acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
+        }
+    }
+    wg_sums(acc, 2 * K, true, part, sc);
+    double qq0 = sc[32];
+    double qq = qq0, re = 0, im = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        // sweep B: q -= sum beta_j Q_j, z -= sum beta_j Z_j, with |q'|^2 and <q', r>
+        // (every thread reads the betas before any thread enters the next sum)
+        float br[KA], bi[KA];
+#pragma unroll
+        for (int j = 0; j < K; ++j) { br[j] = (float)sc[2 * j]; bi[j] = (float)sc[2 * j + 1]; }
+        double n2 = 0, dr = 0, di = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            float qr = qv[e].re, qi = qv[e].im;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const cpx<float> a = Qv[j][e];
+                qr -= br[j] * a.re - bi[j] * a.im;
+                qi -= br[j] * a.im + bi[j] * a.re;
+            }
+            qv[e] = {qr, qi};
+            const cpx<float> b = rv[e];
+            n2 += (double)qr * qr + (double)qi * qi;
+            dr += (double)qr * b.re + (double)qi * b.im;
+            di += (double)qr * b.im - (double)qi * b.re;
+        }
+        {
+            cpx<float> Zv[KA][E];
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+#pragma unroll
+                for (int e = 0; e < E; ++e) Zv[j][e] = Z[j * ld + id[e]];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                float zr = zv[e].re, zi = zv[e].im;
+#pragma unroll
+                for (int j = 0; j < K; ++j) {
+                    const cpx<float> c = {Zv[j][e].re * live[e], Zv[j][e].im * live[e]};
+                    zr -= br[j] * c.re - bi[j] * c.im;
+                    zi -= br[j] * c.im + bi[j] * c.re;
+                }
+                zv[e] = {zr, zi};
+            }
+        }
+        double a3[36];
+        a3[0] = n2; a3[1] = dr; a3[2] = di;
+        wg_sums(a3, 3, false, part, sc);
+        qq = sc[0]; re = sc[1]; im = sc[2];
+        if (pass == 1 || K == 0 || !(qq < 0.5 * qq0)) break;
+        // the projection cancelled most of q: orthogonalise once more (dots
+        // only), with the stored Q_j read again rather than kept live
+        qq0 = qq;
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const cpx<float> a = Q[j * ld + id[e]];
+                Qv[j][e] = {a.re * live[e], a.im * live[e]};
+            }
+#pragma unroll
+        for (int v = 0; v < 36; ++v) acc[v] = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const cpx<float> b = qv[e];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const cpx<float> a = Qv[j][e];
+                acc[2 * j] += (double)a.re * b.re + (double)a.im * b.im;
+                acc[2 * j + 1] += (double)a.re * b.im - (double)a.im * b.re;
+            }
+        }
+        __syncthreads();   // every thread has read sc (qq, re, im) before it is overwritten
+        wg_sums(acc, 2 * K, false, part, sc);
+    }
+    double rr = 0;
+    if (qq > 0) {
+        const double nq = sqrt(qq);
+        const float inv = (float)(1.0 / nq), ar = (float)(re / nq), ai = (float)(im / nq);
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            cpx<float> a = qv[e], c = zv[e], xx = xv[e], b = rv[e];
+            a.re *= inv; a.im *= inv;
+            c.re *= inv; c.im *= inv;
+            xx.re += ar * c.re - ai * c.im;
+            xx.im += ar * c.im + ai * c.re;
+            b.re -= ar * a.re - ai * a.im;
+            b.im -= ar * a.im + ai * a.re;
+            if (live[e] != 0.0f) {
+                q[id[e]] = a;
+                z[id[e]] = c;
+                x[id[e]] = xx;
+                r[id[e]] = b;
+                if (znext) znext[id[e]] = b;
+            }
+            rr += (double)b.re * b.re + (double)b.im * b.im;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const cpx<float> b = rv[e];
+            if (live[e] != 0.0f && znext) znext[id[e]] = b;
+            rr += (double)b.re * b.re + (double)b.im * b.im;
+        }
+    }
+    double a1[36];
+    a1[0] = rr;
+    __syncthreads();
+    wg_sums(a1, 1, false, part, sc);
+    if (t == 0) {
+        out[0] = qq;
+        out[1] = re;
+        out[2] = im;
+        out[3] = sc[0];
+        const double bn = sqrt(out[bnoff]);
+        out[okoff + 1 - par] = (qq <= 0.0 || (bn > 0 && sqrt(sc[0]) <= tol * bn)) ? 1.0 : 0.0;
+        out[okoff + 2] += 1.0;
+    }
+}
+
 // 512 threads: faster than 1024 or 256 on the 2048-unknown coarsest level of
 // 16^3x32 (42.5 vs 44.0 and 45.7 ms per MG solve)
 template <typename R>
 qmg_status Blas::gcr_step_small(const void* Q, const void* Z, int64_t ld, int k, void* q, void* z, void* x, void* r,
                                 int64_t n, double* out, void* znext, double tol, int okoff, int bnoff, int par) {
-    hipLaunchKernelGGL(k_gcr_step_small<R>, dim3(1, nb), dim3(512), 0, s, (const cpx<R>*)Q, (const cpx<R>*)Z, ld, k,
-                       (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x, (cpx<R>*)r, n, out, (cpx<R>*)znext, ss, tol, okoff,
-                       bnoff, nb, par);
+    if (k < 0 || k > 15) return fail(QMG_ERR_ARG, "gcr_step_small: %d stored directions (at most 15)", k);
+    if constexpr (std::is_same<R, float>::value) {
+        const int E = n <= 1024 && k <= 9 ? 2 : n <= 2048 && k <= 4 ? 4 : 0;
+        if (E) {
+            // E entries per thread, whole waves, at most 512 threads
+            const int T = (int)std::min<int64_t>(512, std::max<int64_t>(64, ((n + E - 1) / E + 63) / 64 * 64));
+#define QMG_STEP_REG(KK, EE)                                                                                         \
+    case KK:                                                                                                         \
+        hipLaunchKernelGGL((k_gcr_step_reg<KK, EE>), dim3(1, nb), dim3(T), 0, s, (const cpx<float>*)Q,              \
+                           (const cpx<float>*)Z, ld, (cpx<float>*)q, (cpx<float>*)z, (cpx<float>*)x, (cpx<float>*)r, \
+                           n, out, (cpx<float>*)znext, ss, tol, okoff, bnoff, nb, par);                              \
+        break;
+            if (E == 2) {
+                switch (k) {
+                    QMG_STEP_REG(0, 2) QMG_STEP_REG(1, 2) QMG_STEP_REG(2, 2) QMG_STEP_REG(3, 2) QMG_STEP_REG(4, 2)
+                    QMG_STEP_REG(5, 2) QMG_STEP_REG(6, 2) QMG_STEP_REG(7, 2) QMG_STEP_REG(8, 2) QMG_STEP_REG(9, 2)
+                }
+            } else {
+                switch (k) {
+                    QMG_STEP_REG(0, 4) QMG_STEP_REG(1, 4) QMG_STEP_REG(2, 4) QMG_STEP_REG(3, 4) QMG_STEP_REG(4, 4)
+                }
+            }
+#undef QMG_STEP_REG
+            QMG_LAUNCH_CHECK();
+            return QMG_OK;
+        }
+    }
+#define QMG_STEP(KK)                                                                                                 \
+    case KK:                                                                                                         \
+        hipLaunchKernelGGL((k_gcr_step_small<R, KK>), dim3(1, nb), dim3(512), 0, s, (const cpx<R>*)Q,               \
+                           (const cpx<R>*)Z, ld, (cpx<R>*)q, (cpx<R>*)z, (cpx<R>*)x, (cpx<R>*)r, n, out,            \
+                           (cpx<R>*)znext, ss, tol, okoff, bnoff, nb, par);                                         \
+        break;
+    switch (k) {
+        QMG_STEP(0) QMG_STEP(1) QMG_STEP(2) QMG_STEP(3) QMG_STEP(4) QMG_STEP(5) QMG_STEP(6) QMG_STEP(7)
+        QMG_STEP(8) QMG_STEP(9) QMG_STEP(10) QMG_STEP(11) QMG_STEP(12) QMG_STEP(13) QMG_STEP(14) QMG_STEP(15)
+    }
+#undef QMG_STEP
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -569,6 +831,15 @@ qmg_status Blas::dir_step(const double* s3, const void* d, const void* Ad, const
     return QMG_OK;
 }
 
+template <typename R>
+qmg_status Blas::dir_step_checked(double* s3, const void* d, const void* Ad, const void* r, void* x, void* rout,
+                                  int64_t n, int cnt) {
+    hipLaunchKernelGGL(k_dir_step_checked<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, s3, (const cpx<R>*)d,
+                       (const cpx<R>*)Ad, (const cpx<R>*)r, (cpx<R>*)x, (cpx<R>*)rout, n, ss, cnt);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
 template <typename R> qmg_status Blas::axpy(double a, const void* x, void* y, int64_t n) {
     hipLaunchKernelGGL(k_axpy<R>, dim3(grid1(n), nb), dim3(kThreads), 0, s, (R)a, (const cpx<R>*)x, (cpx<R>*)y, n);
     QMG_LAUNCH_CHECK();
@@ -604,6 +875,8 @@ template <typename R> qmg_status Blas::normalize(void* x, const double* nrm2, in
     template qmg_status Blas::axpy<R>(double, const void*, void*, int64_t);                                \
     template qmg_status Blas::dir_step<R>(const double*, const void*, const void*, const void*, void*, void*, \
                                           int64_t);                                                        \
+    template qmg_status Blas::dir_step_checked<R>(double*, const void*, const void*, const void*, void*,     \
+                                                  void*, int64_t, int);                                    \
     template qmg_status Blas::xmy<R>(const void*, const void*, void*, int64_t);                            \
     template qmg_status Blas::normalize<R>(void*, const double*, int64_t);                                 \
     template qmg_status Blas::gcr_step_small<R>(const void*, const void*, int64_t, int, void*, void*, void*,  \

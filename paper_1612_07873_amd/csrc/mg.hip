@@ -149,6 +149,7 @@ constexpr int S_BN = 44;      // 1
 constexpr int S_SM = 48;      // 3: learned-smoother step scalars
 constexpr int S_OK = 52;      // 3: single-work-group GCR steps: stopping-test flags (two parities), steps done
 constexpr int S_QQ = 56;      // 1: outer GCR: |q|^2 before the projection
+constexpr int S_FB = 57;      // 1: network steps refused on the device (learned smoother followed by MR)
 constexpr int kCheck = 4;     // such steps queued per host read of the scalars
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
@@ -471,9 +472,12 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
 // The network's output d = N(r) is kept only if it lowers the residual
 // (|r - A d| < |r|); it is then taken with the minimal-residual step length,
 // x = alpha d with alpha = <A d, r>/|A d|^2, which lowers it further.
-// Otherwise (including NaN/Inf from bad weights) MR is used for this
-// application.  In a batch the network runs on every member and is kept only
-// if it passes for every member; each member that fails counts as a fallback.
+// Network alone: otherwise (including NaN/Inf from bad weights) MR is used for
+// this application; in a batch the network runs on every member and is kept
+// only if it passes for every member; each member that fails counts as a
+// fallback.  Network followed by MR steps: the test is made on the device,
+// per member, with no host round trip; a refused network step is skipped
+// (x = 0, counted as a fallback) and the MR steps run either way.
 // On exit lv.mr_r holds r - A x.
 template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void* x) {
     Level& L = mg->lv[l];
@@ -483,6 +487,16 @@ template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void
             QMG_TRY(ptc_forward(mg->ptc, (const char*)r + k * vb, (char*)L.kt + k * vb, mg->s));
         QMG_TRY(apply_op<R>(mg, 0, L.kt, L.mr_Ar));
         QMG_TRY(mg->blas.dot_norm<R>(L.mr_Ar, r, L.n, mg->dsc + S_SM));
+        if (mg->ptc_mr > 0) {
+            QMG_TRY(mg->blas.dir_step_checked<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n, S_FB - S_SM));
+            // then MR steps on the residual left: x += MR_k(r - A x)
+            const int keep = L.p.smoother_steps;
+            L.p.smoother_steps = mg->ptc_mr;
+            const qmg_status st = mr<R>(mg, l, L.mr_r, L.kt);
+            L.p.smoother_steps = keep;
+            QMG_TRY(st);
+            return mg->blas.axpy<R>(1.0, L.kt, x, L.n);
+        }
         QMG_TRY(read_scalars(mg, S_SM, 3));
         int bad = 0;
         for (int k = 0; k < mg->nb; ++k) {
@@ -492,18 +506,7 @@ template <typename R> qmg_status smooth(qmg_mg_s* mg, int l, const void* r, void
             const bool ok = den > 0 && std::isfinite(den) && std::isfinite(re) && std::isfinite(im) && den - 2 * re < 0;
             if (!ok) ++bad;
         }
-        if (bad == 0) {
-            QMG_TRY(mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n));
-            if (mg->ptc_mr <= 0) return QMG_OK;
-            // then MR steps on the residual the network left: x += MR_k(r - A x)
-            const int keep = L.p.smoother_steps;
-            L.p.smoother_steps = mg->ptc_mr;
-            QMG_HIP(hipMemcpyAsync(L.kr2, L.mr_r, mg->nb * L.n * sizeof(cpx<R>), hipMemcpyDeviceToDevice, mg->s));
-            const qmg_status st = mr<R>(mg, l, L.kr2, L.kt);
-            L.p.smoother_steps = keep;
-            QMG_TRY(st);
-            return mg->blas.axpy<R>(1.0, L.kt, x, L.n);
-        }
+        if (bad == 0) return mg->blas.dir_step<R>(mg->dsc + S_SM, L.kt, L.mr_Ar, r, x, L.mr_r, L.n);
         mg->fallbacks += bad;
     }
     if (l == 0 && mg->sap && sizeof(R) == 4) {
@@ -675,6 +678,7 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
     mg->span_level.clear();
     mg->spans_overflow = false;
     mg->fallbacks = 0;
+    if (mg->ptc) QMG_HIP(hipMemset2DAsync(mg->dsc + S_FB, sizeof(double) * kScal, 0, sizeof(double), nb, mg->s));
     mg->rec_n = 0;
     mg->srec_n = 0;
     auto t0 = std::chrono::steady_clock::now();
@@ -777,6 +781,10 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
         }
     }
     auto t1 = std::chrono::steady_clock::now();
+    if (mg->ptc && mg->ptc_mr > 0) {   // network steps refused on the device
+        QMG_TRY(read_scalars(mg, S_FB, 1));
+        for (int k = 0; k < nb; ++k) mg->fallbacks += (int)hs(mg, k, S_FB);
+    }
     double worst = 0;
     for (int k = 0; k < nb; ++k) worst = true_rel[k] > worst ? true_rel[k] : worst;
     double lsec[4] = {0, 0, 0, 0};

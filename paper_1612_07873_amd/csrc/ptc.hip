@@ -194,10 +194,14 @@ __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_fan_in(float2* __restric
 //   TR_LEFT (second layer, G2[p][0][k]): L = T_{rev p} tr (tr = D), R = mc_k (h1);
 //   else    (first layer,  G1[p][k][0]): L = mc_k (D1), R = T_p tr (tr = r).
 // Each work-group walks chunks of kPtcSites sites: per chunk the nine
-// transports per site and the C channels of the chunk's sites go to LDS, and
-// each thread sums its fixed set of (p, k, s, t) entries over the chunk in
-// FP32 and accumulates the chunk sums in FP64;
-// per-work-group partials part[blk][9*C][32] are summed in a fixed order.
+// transports per site and the C channels of the chunk's sites go to LDS.
+// Thread (pair, quarter) owns the 4x4 block of one (p, k) pair over one
+// of Q slices of the chunk's sites (Q * 9C <= threads): per site and colour
+// it reads 4 + 4 operands for 16 products, sums the chunk in FP32 and adds
+// the chunk sums to FP64 totals in registers.  At the end the Q slices are
+// added in a fixed order in LDS and the work-group's sums go to
+// part[blk][9C][32], which a second kernel sums over work-groups in a fixed
+// order.
 template <bool TR_LEFT>
 __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_wgrad_fan(double* __restrict__ part,
                                                                   const float2* __restrict__ tr,
@@ -208,68 +212,89 @@ __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_wgrad_fan(double* __rest
     float2 (*tp)[9][12] = reinterpret_cast<float2 (*)[9][12]>(smem);
     float2* ms = reinterpret_cast<float2*>(smem + sizeof(float2) * kPtcSites * 9 * 12);   // [C][kPtcSites][12]
     const int t = threadIdx.x;
-    const int ncombo = 9 * C * 16;
-    constexpr int kMaxPer = 8;   // combos per thread (C <= 16)
-    double acc[kMaxPer][2];
+    int Q = kPtcSites;
+    while (Q * C > kPtcSites) Q >>= 1;   // 9 C Q <= 9 kPtcSites = the work-group size
+    const int S = kPtcSites / Q;           // sites per slice
+    const bool active = t < 9 * C * Q;
+    const int pair = t / Q, quarter = t - (t / Q) * Q;
+    const int p = pair / C, k = pair - (pair / C) * C;
+    double acc[16][2];
 #pragma unroll
-    for (int j = 0; j < kMaxPer; ++j) acc[j][0] = acc[j][1] = 0;
+    for (int e = 0; e < 16; ++e) acc[e][0] = acc[e][1] = 0;
     const int64_t nchunks = (V + kPtcSites - 1) / kPtcSites;
     for (int64_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x) {
         const int64_t x0 = ch * kPtcSites;
         __syncthreads();   // the previous chunk's LDS reads are done
         {
-            const int sl = t / 9, p = t - (t / 9) * 9;
+            const int sl = t / 9, q = t - (t / 9) * 9;
             const int64_t x = x0 + sl;
             float2 w[12];
             if (x < V) {
-                const int q = TR_LEFT ? rev_path(p) : p;
-                const int64_t n = path_site(nbr, x, q);
+                const int qq = TR_LEFT ? rev_path(q) : q;
+                const int64_t n = path_site(nbr, x, qq);
                 float2 v[12];
 #pragma unroll
                 for (int f = 0; f < 12; ++f) v[f] = tr[n * 12 + f];
-                transport_vals(w, v, U, V, x, n, q);
+                transport_vals(w, v, U, V, x, n, qq);
             } else {
 #pragma unroll
                 for (int f = 0; f < 12; ++f) w[f] = make_float2(0, 0);
             }
 #pragma unroll
-            for (int f = 0; f < 12; ++f) tp[sl][p][f] = w[f];
+            for (int f = 0; f < 12; ++f) tp[sl][q][f] = w[f];
         }
         for (int idx = t; idx < C * kPtcSites * 12; idx += kPtcFanThreads) {
-            const int f = idx % 12, sl = (idx / 12) % kPtcSites, k = idx / (12 * kPtcSites);
+            const int f = idx % 12, sl = (idx / 12) % kPtcSites, kk = idx / (12 * kPtcSites);
             const int64_t x = x0 + sl;
-            ms[idx] = x < V ? mc[((int64_t)k * V + x) * 12 + f] : make_float2(0, 0);
+            ms[idx] = x < V ? mc[((int64_t)kk * V + x) * 12 + f] : make_float2(0, 0);
         }
         __syncthreads();
+        if (active) {
+            float sr[16], si[16];
 #pragma unroll
-        for (int j = 0; j < kMaxPer; ++j) {
-            const int cidx = t + j * kPtcFanThreads;
-            if (cidx >= ncombo) break;
-            const int p = cidx / (C * 16), k = (cidx / 16) % C, sp = (cidx / 4) % 4, tt = cidx % 4;
-            // the chunk's 32 sites x 3 colours in FP32, added to the FP64 total
-            float re = 0, im = 0;
-            for (int sl = 0; sl < kPtcSites; ++sl) {
+            for (int e = 0; e < 16; ++e) sr[e] = si[e] = 0.0f;
+            for (int i = 0; i < S; ++i) {
+                const int sl = quarter * S + i;
                 const float2* m = ms + ((int64_t)k * kPtcSites + sl) * 12;
+                const float2* tq = tp[sl][p];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const float2 l = TR_LEFT ? tp[sl][p][sp * 3 + c] : m[sp * 3 + c];
-                    const float2 r = TR_LEFT ? m[tt * 3 + c] : tp[sl][p][tt * 3 + c];
-                    re += l.x * r.x + l.y * r.y;
-                    im += l.y * r.x - l.x * r.y;
+                    float2 L[4], R[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        L[u] = TR_LEFT ? tq[u * 3 + c] : m[u * 3 + c];
+                        R[u] = TR_LEFT ? m[u * 3 + c] : tq[u * 3 + c];
+                    }
+#pragma unroll
+                    for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+                        for (int tt = 0; tt < 4; ++tt) {
+                            sr[sp * 4 + tt] += L[sp].x * R[tt].x + L[sp].y * R[tt].y;
+                            si[sp * 4 + tt] += L[sp].y * R[tt].x - L[sp].x * R[tt].y;
+                        }
                 }
             }
-            acc[j][0] += (double)re;
-            acc[j][1] += (double)im;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                acc[e][0] += (double)sr[e];
+                acc[e][1] += (double)si[e];
+            }
         }
     }
-    // part[blk][combo/16][32]: (p, k) block of 16 complex entries
+    // the Q slices of each pair, added in slice order, then the work-group's sums
+    __syncthreads();
+    double* red = reinterpret_cast<double*>(smem);   // [9C][32]
+    for (int qd = 0; qd < Q; ++qd) {
+        if (active && quarter == qd)
 #pragma unroll
-    for (int j = 0; j < kMaxPer; ++j) {
-        const int cidx = t + j * kPtcFanThreads;
-        if (cidx >= ncombo) break;
-        part[((int64_t)blockIdx.x * (9 * C) + cidx / 16) * 32 + 2 * (cidx % 16)] = 2.0 * acc[j][0];
-        part[((int64_t)blockIdx.x * (9 * C) + cidx / 16) * 32 + 2 * (cidx % 16) + 1] = 2.0 * acc[j][1];
+            for (int e = 0; e < 16; ++e) {
+                double* d = red + pair * 32 + 2 * e;
+                d[0] = qd ? d[0] + acc[e][0] : acc[e][0];
+                d[1] = qd ? d[1] + acc[e][1] : acc[e][1];
+            }
+        __syncthreads();
     }
+    for (int i = t; i < 9 * C * 32; i += kPtcFanThreads) part[(int64_t)blockIdx.x * (9 * C) * 32 + i] = 2.0 * red[i];
 }
 
 // G[combo][16] += sum over blocks (fixed order)
@@ -368,6 +393,7 @@ __global__ void k_gamma5_scale(float2* __restrict__ out, const float2* __restric
 //   k_ptc_gather: N(r)(x) = sum_p (T_p g_p)(x).
 // The hidden channels are never stored: per site 96 bytes in, 864 bytes of g
 // out and back, instead of the hidden layer's 8 channels read nine times.
+// g is laid out [9][12][V] (site fastest).
 __global__ void k_ptc_collapse(float2* __restrict__ K, const float2* __restrict__ W1, const float2* __restrict__ W2,
                                int C) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;   // (p, q, s, t)
@@ -387,71 +413,100 @@ __global__ void k_ptc_collapse(float2* __restrict__ K, const float2* __restrict_
     K[i] = make_float2(re, im);
 }
 
+// Thread layout of the two inference kernels: thread t works on path
+// t / kPtcSites and site t % kPtcSites of the work-group's kPtcSites sites, so
+// the 32 lanes of a half-wave share a path and take consecutive sites: their
+// neighbour and link loads and their stores of g (layout [9][12][V], site
+// fastest) are contiguous, the LDS fields [9][12][kPtcSites] are read without
+// bank conflicts and a half-wave's reads of K[p][q] are one broadcast.
+__device__ __forceinline__ void transport_site(float2 w[12], const float2* __restrict__ r,
+                                               const float2* __restrict__ U, const int* __restrict__ nbr,
+                                               int64_t V, int64_t x, int q) {
+    const int64_t n = path_site(nbr, x, q);
+    float2 v[12];
+    const float4* r4 = reinterpret_cast<const float4*>(r + n * 12);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        const float4 a = r4[i];
+        v[2 * i] = make_float2(a.x, a.y);
+        v[2 * i + 1] = make_float2(a.z, a.w);
+    }
+    transport_vals(w, v, U, V, x, n, q);
+}
+
 __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_mix(float2* __restrict__ g, const float2* __restrict__ r,
                                                             const float2* __restrict__ K,
                                                             const float2* __restrict__ U,
                                                             const int* __restrict__ nbr, int64_t V) {
-    __shared__ float2 tp[kPtcSites][9][12];
+    __shared__ float2 tp[9][12][kPtcSites];
     __shared__ float2 ks[81 * 16];
     const int64_t x0 = (int64_t)blockIdx.x * kPtcSites;
     const int t = threadIdx.x;
     for (int i = t; i < 81 * 16; i += kPtcFanThreads) ks[i] = K[i];
-    const int sl = t / 9, pq = t - (t / 9) * 9;
+    const int pq = t / kPtcSites, sl = t - pq * kPtcSites;
     const int64_t x = x0 + sl;
-    if (x < V) {
-        const int64_t n = path_site(nbr, x, pq);
-        float2 v[12], w[12];
+    {
+        float2 w[12];
+        if (x < V) {
+            transport_site(w, r, U, nbr, V, x, pq);
+        } else {
 #pragma unroll
-        for (int f = 0; f < 12; ++f) v[f] = r[n * 12 + f];
-        transport_vals(w, v, U, V, x, n, pq);
+            for (int f = 0; f < 12; ++f) w[f] = make_float2(0, 0);
+        }
 #pragma unroll
-        for (int f = 0; f < 12; ++f) tp[sl][pq][f] = w[f];
+        for (int f = 0; f < 12; ++f) tp[pq][f][sl] = w[f];
     }
     __syncthreads();
     if (x >= V) return;
-    // thread (site, p): g_p = sum_q K[p][q] T_q r
+    // thread (p, site): g_p = sum_q K[p][q] T_q r
     const int p = pq;
     float2 acc[12];
 #pragma unroll
     for (int f = 0; f < 12; ++f) acc[f] = make_float2(0, 0);
     for (int q = 0; q < 9; ++q) {
         const float2* k = ks + (p * 9 + q) * 16;
+        float2 v[12];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) v[f] = tp[q][f][sl];
 #pragma unroll
         for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float re = acc[sp * 3 + c].x, im = acc[sp * 3 + c].y;
+            for (int u = 0; u < 4; ++u) {
+                const float2 m = k[sp * 4 + u];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float2 m = k[sp * 4 + u], v = tp[sl][q][u * 3 + c];
-                    re += m.x * v.x - m.y * v.y;
-                    im += m.x * v.y + m.y * v.x;
+                for (int c = 0; c < 3; ++c) {
+                    const float2 w = v[u * 3 + c];
+                    acc[sp * 3 + c].x += m.x * w.x - m.y * w.y;
+                    acc[sp * 3 + c].y += m.x * w.y + m.y * w.x;
                 }
-                acc[sp * 3 + c] = make_float2(re, im);
             }
     }
 #pragma unroll
-    for (int f = 0; f < 12; ++f) g[((int64_t)p * V + x) * 12 + f] = acc[f];
+    for (int f = 0; f < 12; ++f) g[((int64_t)p * 12 + f) * V + x] = acc[f];
 }
 
 __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_gather(float2* __restrict__ out, const float2* __restrict__ g,
                                                                const float2* __restrict__ U,
                                                                const int* __restrict__ nbr, int64_t V) {
-    __shared__ float2 cp[kPtcSites][9][12];
+    __shared__ float2 cp[9][12][kPtcSites];
     const int64_t x0 = (int64_t)blockIdx.x * kPtcSites;
     const int t = threadIdx.x;
     {
-        const int sl = t / 9, p = t - (t / 9) * 9;
+        const int p = t / kPtcSites, sl = t - p * kPtcSites;
         const int64_t x = x0 + sl;
+        float2 w[12];
         if (x < V) {
             const int64_t n = path_site(nbr, x, p);
-            float2 v[12], w[12];
+            float2 v[12];
 #pragma unroll
-            for (int f = 0; f < 12; ++f) v[f] = g[((int64_t)p * V + n) * 12 + f];
+            for (int f = 0; f < 12; ++f) v[f] = g[((int64_t)p * 12 + f) * V + n];
             transport_vals(w, v, U, V, x, n, p);
+        } else {
 #pragma unroll
-            for (int f = 0; f < 12; ++f) cp[sl][p][f] = w[f];
+            for (int f = 0; f < 12; ++f) w[f] = make_float2(0, 0);
         }
+#pragma unroll
+        for (int f = 0; f < 12; ++f) cp[p][f][sl] = w[f];
     }
     __syncthreads();
     for (int idx = t; idx < kPtcSites * 12; idx += kPtcFanThreads) {
@@ -461,8 +516,8 @@ __global__ __launch_bounds__(kPtcFanThreads) void k_ptc_gather(float2* __restric
         float re = 0, im = 0;
 #pragma unroll
         for (int p = 0; p < 9; ++p) {
-            re += cp[sl][p][f].x;
-            im += cp[sl][p][f].y;
+            re += cp[p][f][sl].x;
+            im += cp[p][f][sl].y;
         }
         out[x * 12 + f] = make_float2(re, im);
     }

@@ -136,12 +136,16 @@ def test_training_on_solver_pairs_and_mg_with_learned_smoother():
     print('residual-form training loss %.4f -> %.4f' % (Lr0, Lr1))
     assert Lr1 < Lr0
     b = synth.gaussian((V, 4, 3), 7, 2)
-    _, base = mg.solve(dev(b))
+    x, base = mg.solve(dev(b))
+    tr0 = np.linalg.norm(b - wilson.apply_wilson_clover_c(host(x), U, A, m0, dims)) / np.linalg.norm(b)
     mg.set_smoother(net)
     x, info = mg.solve(dev(b))
     tr = np.linalg.norm(b - wilson.apply_wilson_clover_c(host(x), U, A, m0, dims)) / np.linalg.norm(b)
     print('MR smoother', base, '\nlearned smoother', info, 'oracle-M residual %.2e' % tr)
-    assert info['converged'] and tr <= 1e-10
+    assert info['converged'] and tr <= 1e-10 and tr0 <= 1e-10
+    # what the network gains over MR(4) on the same solve, both checked under
+    # the oracle's operator (outer steps to 1e-10)
+    cmp = {'MR(4)': base['outer_iters'], 'learned': info['outer_iters']}
     # poisoned weights: every application falls back to MR and the solve still converges
     bad = torch.full((9, 8, 1, 4, 4), float('nan'), dtype=torch.complex64, device='cuda')
     net.set_weights(bad, dev(W2, torch.complex64))
@@ -153,7 +157,26 @@ def test_training_on_solver_pairs_and_mg_with_learned_smoother():
     tr = np.linalg.norm(b - wilson.apply_wilson_clover_c(host(x), U, A, m0, dims)) / np.linalg.norm(b)
     print('residual-trained smoother', info3, 'oracle-M residual %.2e' % tr)
     assert info3['converged'] and tr <= 1e-10
+    cmp['learned (residual loss)'] = info3['outer_iters']
+    # the network followed by two MR steps on what it leaves
+    mg.set_smoother(net_r, mr_steps=2)
+    x, info4 = mg.solve(dev(b))
+    tr = np.linalg.norm(b - wilson.apply_wilson_clover_c(host(x), U, A, m0, dims)) / np.linalg.norm(b)
+    assert info4['converged'] and tr <= 1e-10
+    cmp['learned (residual loss) + MR(2)'] = info4['outer_iters']
+    # the same with the poisoned network: every network step is refused on the
+    # device and counted, the MR steps still run and the solve converges
+    mg.set_smoother(net, mr_steps=2)
+    x, info5 = mg.solve(dev(b))
+    tr = np.linalg.norm(b - wilson.apply_wilson_clover_c(host(x), U, A, m0, dims)) / np.linalg.norm(b)
+    print('poisoned network + MR(2)', info5, 'oracle-M residual %.2e' % tr)
+    assert info5['converged'] and tr <= 1e-10 and info5['smoother_fallbacks'] >= info5['outer_iters'] > 0
     mg.set_smoother(None)
+    print('outer steps to 1e-10 by level-0 smoother:', cmp)
+    # measured so far on this problem: the output-trained network ties MR(4)
+    # and the residual-trained one needs about a sixth more outer steps; every
+    # learned form is held to at most half again as many as MR(4)
+    assert max(v for k, v in cmp.items() if k != 'MR(4)') <= 1.5 * cmp['MR(4)']
 
 
 def test_recorded_smoother_inputs_match_the_oracle_kcycle():
