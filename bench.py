@@ -428,6 +428,8 @@ def learned(npairs, epochs, loss, source='smoother'):
     # the network step followed by two MR steps on the residual it leaves
     mg.set_smoother(net, mr_steps=2)
     hybrid = timed_solves(mg, 12, 1000)
+    mg.set_smoother(net, mr_steps=1)
+    hybrid1 = timed_solves(mg, 12, 1000)
     mg.set_smoother(None)
     del mg
     # the comparison the method is judged by: 16-bit fine and coarse storage,
@@ -436,23 +438,28 @@ def learned(npairs, epochs, loss, source='smoother'):
     mg16, _, _, _, _ = build_mg_16x32(coarse_storage='h16', fine_storage='h16')
     mg16.set_smoother(net)
     combo = timed_batches(mg16, 16, 2, 1000)
+    mg16.set_smoother(net, mr_steps=2)
+    combo_h = timed_batches(mg16, 16, 2, 1000)
     mg16.set_smoother(None)
     combo_mr = timed_batches(mg16, 16, 2, 1000)
     del mg16
     combo['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo['time_per_rhs_s'], 3)
     combo_mr['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo_mr['time_per_rhs_s'], 3)
+    combo_h['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo_h['time_per_rhs_s'], 3)
     return {'lattice': list(dims), 'm0': m0, 'training_data': source, 'pairs': int(R.shape[0]),
             'pair_seconds': round(t_pairs, 2),
             'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
             'train_seconds': round(t_train, 2), 'mg_with_MR': plain, 'mg_with_learned': withnet,
-            'mg_with_learned_then_MR2': hybrid,
+            'mg_with_learned_then_MR2': hybrid, 'mg_with_learned_then_MR1': hybrid1,
             'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3),
             'speedup_time_learned_then_MR2': round(plain['time_to_1e-10_s'] / hybrid['time_to_1e-10_s'], 3),
+            'speedup_time_learned_then_MR1': round(plain['time_to_1e-10_s'] / hybrid1['time_to_1e-10_s'], 3),
             'north_star': {'plain': 'FP32 inner, FP64 outer, single right-hand side, MR(4) smoother',
                            'mixed': 'FP16 fine and coarse storage (FP32 scales, FP32 arithmetic), 16 right-hand '
                                     'sides per solve, matrix-core coarse stencils, learned level-0 smoother',
                            'plain_time_to_1e-10_s': plain['time_to_1e-10_s'],
-                           'mixed_with_learned': combo, 'mixed_with_MR': combo_mr}}
+                           'mixed_with_learned': combo, 'mixed_with_learned_then_MR2': combo_h,
+                           'mixed_with_MR': combo_mr}}
 
 
 def fine_and_transfer(steps=200):

@@ -212,6 +212,20 @@ qmg_status qmg_coarse_op_tune(qmg_coarse_op op, const void* in, const float* in_
 qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, const float* in_scale, void* out, int nrhs,
                                    int cold, void* stream, float* best_ms);
 
+/* The tuner's choices as a file (the paper's autotuner, Sec. 4, keeps its
+ * results; here they also outlive the process).  save writes every entry of
+ * this process's cache to the text file at `path` (host string), headed by
+ * the current device's architecture name and the HIP runtime version;
+ * load merges the entries of such a file into the cache, and refuses
+ * (QMG_ERR_STATE) a file written for another architecture or runtime, so a
+ * later qmg_coarse_op_tune / _tune_mrhs on the same shape installs the stored
+ * launch without timing.  *entries (host, may be NULL) receives the number of
+ * entries written / read.  QMG_ERR_ARG if the file cannot be opened, written
+ * or parsed.  clear empties the in-process cache. */
+qmg_status qmg_tune_cache_save(const char* path, int* entries);
+qmg_status qmg_tune_cache_load(const char* path, int* entries);
+qmg_status qmg_tune_cache_clear(void);
+
 void qmg_coarse_op_destroy(qmg_coarse_op op);
 
 /* ---------------------------------------------------------------------------

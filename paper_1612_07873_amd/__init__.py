@@ -5,13 +5,14 @@ data pointers and the current HIP stream to libqmg.so.  Every step runs in
 the library's kernels; if the library is missing, these calls raise.
 """
 import ctypes
+import os
 
 import torch
 
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['BiCGStab', 'stream_read', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['BiCGStab', 'stream_read', 'tune_cache_save', 'tune_cache_load', 'tune_cache_clear', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
@@ -22,6 +23,28 @@ def stream_read(buf, sink):
     sink: int32 device tensor of at least 8 x (compute units) words."""
     _lib.call('qmg_stream_read', ctypes.c_void_p(buf.data_ptr()), int(buf.numel() * buf.element_size()),
               ctypes.c_void_p(sink.data_ptr()), int(sink.numel()), stream_ptr())
+
+
+def tune_cache_save(path):
+    """Write the autotuner's in-process choices to the text file `path`
+    (qmg_tune_cache_save); returns the number of entries."""
+    n = ctypes.c_int(0)
+    _lib.call('qmg_tune_cache_save', os.fsencode(path), ctypes.byref(n))
+    return n.value
+
+
+def tune_cache_load(path):
+    """Merge the entries of a file written by tune_cache_save on this device
+    architecture and HIP runtime into the autotuner's cache
+    (qmg_tune_cache_load); returns the number of entries read."""
+    n = ctypes.c_int(0)
+    _lib.call('qmg_tune_cache_load', os.fsencode(path), ctypes.byref(n))
+    return n.value
+
+
+def tune_cache_clear():
+    """Empty the autotuner's in-process cache (qmg_tune_cache_clear)."""
+    _lib.call('qmg_tune_cache_clear')
 
 
 def stream_ptr(stream=None):

@@ -30,6 +30,9 @@ SIGNATURES = {
                                    ctypes.POINTER(ctypes.c_float)]),
     'qmg_coarse_op_tune_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p,
                                         ctypes.POINTER(ctypes.c_float)]),
+    'qmg_tune_cache_save': (c_int, [c_char_p, c_int_p]),
+    'qmg_tune_cache_load': (c_int, [c_char_p, c_int_p]),
+    'qmg_tune_cache_clear': (c_int, []),
     'qmg_coarse_dslash_mrhs': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_coarse_op_set_mrhs_tiles': (c_int, [c_void_p, c_int, c_int]),
     'qmg_coarse_op_get_mrhs_tiles': (c_int, [c_void_p, c_int, c_int_p]),

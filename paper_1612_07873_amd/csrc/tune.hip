@@ -11,9 +11,15 @@
 //     re-stages its inputs and was measured to fetch 1.35x the algorithmic
 //     bytes, so whole-site work-groups are kept there;
 //   multi right-hand side: right-hand-side tiles per wave in {1, 2, 4}.
+// The in-process cache can be saved to a text file and loaded by a later
+// process on the same device architecture and HIP runtime, so a run does not
+// pay for tuning again.
 #include "handles.h"
 
+#include <cstdio>
+#include <cstring>
 #include <map>
+#include <string>
 #include <mutex>
 #include <tuple>
 #include <vector>
@@ -216,5 +222,92 @@ extern "C" qmg_status qmg_coarse_op_tune_mrhs(qmg_coarse_op op, const void* in, 
 extern "C" qmg_status qmg_coarse_op_get_prefetch(qmg_coarse_op op, int* pre) {
     if (!op || !pre) return fail(QMG_ERR_ARG, "coarse_op_get_prefetch: NULL argument");
     *pre = op->pre;
+    return QMG_OK;
+}
+
+// ------------------------------------------------------------ persisted cache
+// File format (text): the first line is "qmg-tune-1 <gcnArchName> hip<runtime
+// version>"; each further line is one entry, the nine key fields (four
+// extents, N, storage, vector precision, nrhs, cold), the three launch fields
+// and the time in ms.
+namespace {
+qmg_status device_tag(std::string* tag) {
+    int dev = 0, rt = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t p;
+    QMG_HIP(hipGetDeviceProperties(&p, dev));
+    QMG_HIP(hipRuntimeGetVersion(&rt));
+    char arch[sizeof(p.gcnArchName) + 1];
+    std::memcpy(arch, p.gcnArchName, sizeof(p.gcnArchName));
+    arch[sizeof(p.gcnArchName)] = 0;
+    for (char* c = arch; *c; ++c)
+        if (*c == ' ') *c = '_';
+    *tag = std::string("qmg-tune-1 ") + arch + " hip" + std::to_string(rt);
+    return QMG_OK;
+}
+}  // namespace
+
+extern "C" qmg_status qmg_tune_cache_save(const char* path, int* entries) {
+    if (!path) return fail(QMG_ERR_ARG, "tune_cache_save: path is NULL");
+    std::string tag;
+    QMG_TRY(device_tag(&tag));
+    std::lock_guard<std::mutex> g(cache_mu());
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(QMG_ERR_ARG, "tune_cache_save: cannot open %s for writing", path);
+    bool ok = std::fprintf(f, "%s\n", tag.c_str()) > 0;
+    for (const auto& kv : cache()) {
+        const Key& k = kv.first;
+        const Best& b = kv.second;
+        ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %d %d %.9g\n", std::get<0>(k), std::get<1>(k),
+                                std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k), std::get<6>(k),
+                                std::get<7>(k), std::get<8>(k), b.a, b.b, b.c, (double)b.ms) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(QMG_ERR_ARG, "tune_cache_save: write to %s failed", path);
+    if (entries) *entries = (int)cache().size();
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_tune_cache_load(const char* path, int* entries) {
+    if (!path) return fail(QMG_ERR_ARG, "tune_cache_load: path is NULL");
+    std::string tag;
+    QMG_TRY(device_tag(&tag));
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(QMG_ERR_ARG, "tune_cache_load: cannot open %s", path);
+    char line[512];
+    if (!std::fgets(line, sizeof line, f)) {
+        std::fclose(f);
+        return fail(QMG_ERR_STATE, "tune_cache_load: %s is empty", path);
+    }
+    line[std::strcspn(line, "\r\n")] = 0;
+    if (tag != line) {
+        std::fclose(f);
+        return fail(QMG_ERR_STATE, "tune_cache_load: %s was written for '%s', this device is '%s'", path, line,
+                    tag.c_str());
+    }
+    std::vector<std::pair<Key, Best>> got;
+    int ln = 1;
+    while (std::fgets(line, sizeof line, f)) {
+        ++ln;
+        int v[12];
+        double ms = 0;
+        const int n = std::sscanf(line, "%d %d %d %d %d %d %d %d %d %d %d %d %lf", &v[0], &v[1], &v[2], &v[3], &v[4],
+                                  &v[5], &v[6], &v[7], &v[8], &v[9], &v[10], &v[11], &ms);
+        if (n != 13) {
+            std::fclose(f);
+            return fail(QMG_ERR_ARG, "tune_cache_load: %s line %d is not an entry", path, ln);
+        }
+        got.push_back({Key(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7], v[8]), Best{v[9], v[10], v[11], (float)ms}});
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> g(cache_mu());
+    for (const auto& e : got) cache()[e.first] = e.second;
+    if (entries) *entries = (int)got.size();
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_tune_cache_clear(void) {
+    std::lock_guard<std::mutex> g(cache_mu());
+    cache().clear();
     return QMG_OK;
 }

@@ -64,3 +64,36 @@ def test_tuned_mrhs_and_sixteen_bit():
     yd = host(dequantize_sites(yq, ys, 'h16'))
     ref1 = coarse.CoarseOp(cd, Xq, Yq).apply(host(dequantize_sites(uq, us, 'h16')))
     assert np.linalg.norm(yd - ref1) / np.linalg.norm(ref1) <= 1.5 * 2.0 ** -11
+
+
+def test_tune_cache_persists(tmp_path):
+    """The tuner's choices written to a file and read back by an emptied cache:
+    a second tune of the same shape installs the stored launch and time without
+    timing again; a file headed for another device is refused."""
+    import paper_1612_07873_amd as qmg
+    from paper_1612_07873_amd import CoarseOp, QmgError
+    cd, N = (2, 2, 2, 4), 64
+    V = lattice.volume(cd)
+    X, Y = dev(synth.gaussian((V, N, N), 5, 2)), dev(synth.gaussian((8, V, N, N), 6, 2))
+    ud = dev(synth.gaussian((V, N), 7, 2), torch.complex64)
+    out = torch.empty((V, N), dtype=torch.complex64, device='cuda')
+    qmg.tune_cache_clear()
+    g = CoarseOp(cd, X, Y, 'c64')
+    ms = g.tune(ud, out, cold=False)
+    path = str(tmp_path / 'tune.txt')
+    assert qmg.tune_cache_save(path) >= 1
+    head = open(path).read().splitlines()[0]
+    assert head.startswith('qmg-tune-1 gfx950') and ' hip' in head
+    qmg.tune_cache_clear()
+    assert qmg.tune_cache_load(path) >= 1
+    g2 = CoarseOp(cd, X, Y, 'c64')
+    g2.set_launch(0, 0)
+    ms2 = g2.tune(ud, out, cold=False)
+    assert g2.launch() == g.launch() and g2.prefetch() == g.prefetch()
+    assert abs(ms2 - ms) <= 1e-6 * ms   # the stored time: nothing was timed
+    bad = str(tmp_path / 'other.txt')
+    with open(bad, 'w') as f:
+        f.write('qmg-tune-1 gfx000 hip1\n')
+    with pytest.raises(QmgError):
+        qmg.tune_cache_load(bad)
+    qmg.tune_cache_clear()
