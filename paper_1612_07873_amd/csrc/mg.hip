@@ -90,6 +90,7 @@ struct Level {
     void *mr_r = nullptr, *mr_Ar = nullptr, *kt = nullptr, *kr2 = nullptr, *kx2 = nullptr;
     void *kin = nullptr, *kout = nullptr;  // level 0 only: inner-precision copies
     void* Ainv = nullptr;           // coarsest level solved exactly: dense inverse [n][n] (inner precision)
+    void* Sdense = nullptr;         // coarsest level, red-black: its Schur operator as a dense [n/2][n/2] matrix
     void* q16 = nullptr;            // batched 16-bit stencil input [V][nb][N] (multi-RHS matrix-core path)
     float* qsc = nullptr;           // its scales [V][nb]
     // red-black form: half-lattice fields (n/2 entries per member)
@@ -140,6 +141,19 @@ struct qmg_mg_s {
 namespace {
 
 constexpr int kScal = 64;  // device scalar slots per batch member (member b at b*kScal)
+
+// the n x n identity, [n][n]
+template <typename R> __global__ void k_identity(cpx<R>* __restrict__ m, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n) return;
+    m[i] = cpx<R>{(i / n == i % n) ? R(1) : R(0), R(0)};
+}
+// out[i][j] = in[j][i], n x n
+template <typename R> __global__ void k_transpose(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ in, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * n) return;
+    out[i] = in[(i % n) * n + i / n];
+}
 // slot map
 constexpr int S_BETA = 0;     // 32 doubles (16 complex)
 constexpr int S_GCR = 32;     // 3
@@ -188,6 +202,7 @@ template <typename R> qmg_status schur_apply(qmg_mg_s* mg, int l, const void* in
     const qmg_prec p = sizeof(R) == 8 ? QMG_C128 : QMG_C64;
     Level& L = mg->lv[l];
     if (l == 0) return fine_schur_apply(mg->fine_in, in_e, out_e, L.etmp, p, mg->nb, mg->s);
+    if (L.Sdense) return dense_apply(L.Sdense, in_e, out_e, L.n / 2, mg->nb, p, mg->s);
     return coarse_schur_apply(L.op, in_e, out_e, L.etmp, p, mg->nb, mg->s);
 }
 template <typename R> qmg_status schur_source(qmg_mg_s* mg, int l, const void* b, void* bhat_e) {
@@ -1074,6 +1089,54 @@ extern "C" qmg_status qmg_mg_set_level_timing(qmg_mg mg, int on) {
     return QMG_OK;
 }
 
+// The coarsest level's Schur operator as a dense matrix, when it is small
+// (at most kDenseSchur even-site entries): its columns are the Schur stencil
+// applied to the unit vectors (one batched application, all columns as batch
+// members), transposed to rows.  A coarsest GCR step then applies it with one
+// matrix-vector launch instead of the two stencil launches of the Schur form,
+// whose tiny grids leave the launches latency-bound.  Same operator, same
+// precision; the summation order differs.
+constexpr int64_t kDenseSchur = 2048;
+qmg_status dense_schur_coarsest(qmg_mg_s* mg) {
+    const int nl = (int)mg->lv.size();
+    if (nl < 2) return QMG_OK;
+    Level& L = mg->lv[nl - 1];
+    const int64_t ne = L.n / 2;
+    if (L.Ainv || L.Sdense || ne > kDenseSchur || !L.op->eo_even) return QMG_OK;
+    const size_t cb = cbytes(mg->inner);
+    void *I = nullptr, *C = nullptr, *T = nullptr, *S = nullptr;
+    hipError_t e = hipMalloc(&I, cb * ne * ne);
+    if (e == hipSuccess) e = hipMalloc(&C, cb * ne * ne);
+    if (e == hipSuccess) e = hipMalloc(&T, cb * (L.n - ne) * ne);
+    if (e == hipSuccess) e = hipMalloc(&S, cb * ne * ne);
+    qmg_status st = e == hipSuccess ? QMG_OK : fail(QMG_ERR_NOMEM, "mg: dense coarsest Schur matrix: %s",
+                                                     hipGetErrorString(e));
+    const unsigned g = (unsigned)((ne * ne + 255) / 256);
+    if (st == QMG_OK) {
+        if (mg->inner == QMG_C128) hipLaunchKernelGGL(k_identity<double>, dim3(g), dim3(256), 0, mg->s, (cpx<double>*)I, ne);
+        else hipLaunchKernelGGL(k_identity<float>, dim3(g), dim3(256), 0, mg->s, (cpx<float>*)I, ne);
+        st = coarse_schur_apply(L.op, I, C, T, mg->inner, (int)ne, mg->s);
+    }
+    if (st == QMG_OK) {
+        if (mg->inner == QMG_C128)
+            hipLaunchKernelGGL(k_transpose<double>, dim3(g), dim3(256), 0, mg->s, (cpx<double>*)S, (const cpx<double>*)C, ne);
+        else
+            hipLaunchKernelGGL(k_transpose<float>, dim3(g), dim3(256), 0, mg->s, (cpx<float>*)S, (const cpx<float>*)C, ne);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(mg->s);
+        if (e != hipSuccess) st = fail(QMG_ERR_HIP, "mg: dense coarsest Schur matrix: %s", hipGetErrorString(e));
+    }
+    for (void* p : {I, C, T})
+        if (p) (void)hipFree(p);
+    if (st != QMG_OK) {
+        if (S) (void)hipFree(S);
+        return st;
+    }
+    L.Sdense = S;
+    mg->allocs.push_back(S);
+    return QMG_OK;
+}
+
 extern "C" qmg_status qmg_mg_set_evenodd(qmg_mg mg, int on, void* stream) {
     if (!mg) return fail(QMG_ERR_ARG, "mg_set_evenodd: NULL mg");
     if (!on) {
@@ -1089,6 +1152,7 @@ extern "C" qmg_status qmg_mg_set_evenodd(qmg_mg mg, int on, void* stream) {
         if (L.Ainv || L.op->eo_even) continue;
         QMG_TRY(qmg_coarse_op_prepare_schur(L.op, stream));
     }
+    QMG_TRY(dense_schur_coarsest(mg));
     mg->eo = true;
     const qmg_status st = workspace(mg, mg->cap > 0 ? mg->cap : 1);
     if (st != QMG_OK) mg->eo = false;

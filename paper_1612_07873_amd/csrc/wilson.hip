@@ -41,7 +41,48 @@ namespace qmg {
 // the input, <out,out> and <out,in> (re, im), summed over the work-group in
 // FP64 (fixed order) into part[member*pmember + value*pvalue + blockIdx.x].
 // LR: stored reals per link (18, or 12 with the third row rebuilt).
-template <int LF, int VF, bool DOT = false, int LR = 18>
+//
+// Order of the work and reuse of the input.  A work-group covers 256
+// consecutive sites.  When they are whole x-y planes (NEAR = 2) it first reads
+// their input spinors (decoded) into LDS, then takes the t and z hops, whose
+// neighbours belong to other work-groups that read them as their own sites at
+// the same time, so the second request finds them in L2; then the clover
+// term; then the x and y hops, whose neighbours come from LDS.  Taken in
+// lattice order, the z and t neighbours were fetched again once the clover
+// and link streams had pushed them out of L2: on 16^3x32 the order above
+// reads 829 instead of 942 bytes per site (1.20x instead of 1.35x the
+// algorithmic bytes, counters), at the same time per launch (the kernel is
+// one wave of work-groups there, bound by its memory latency).  Without
+// whole planes the hops are taken in lattice order, two in flight (taking t
+// and z first without the LDS copy was measured slower: 154 vs 136 us on
+// 24^3x48).
+constexpr int kWilsonSites = 256;
+
+template <typename R>
+__device__ __forceinline__ void lds_put(cpx<R>* sh, int t, const cpx<R> p[12]) {
+#pragma unroll
+    for (int f = 0; f < 12; ++f) sh[f * kWilsonSites + t] = p[f];
+}
+// The x and y hops of site n.  NEAR = 2: the work-group's range
+// [base, base + kWilsonSites) holds whole x-y planes (L0 L1 divides
+// kWilsonSites), so the x and y neighbours lie in it and their spinors are
+// read from the LDS copy; otherwise from memory.
+template <int NEAR, int MU, bool BACK, int LF, int VF, int LR, typename R>
+__device__ __forceinline__ void hop_load_near(cpx<R> p[12], cpx<R> u[9], const cpx<R>* sh,
+                                              const void* __restrict__ in, const float* __restrict__ in_scale,
+                                              const void* __restrict__ U, int64_t V, int64_t site, int64_t n,
+                                              int64_t base, int64_t vo, int64_t last) {
+    if constexpr (NEAR > MU) {
+        const int j = (int)(n - base);
+#pragma unroll
+        for (int f = 0; f < 12; ++f) p[f] = sh[f * kWilsonSites + j];
+    } else {
+        load_spinor<VF>(p, in, in_scale, n + vo);
+    }
+    load_link<LF, LR>(u, U, MU, BACK ? n : site, V, last);
+}
+
+template <int LF, int VF, bool DOT = false, int LR = 18, int NEAR = 0>
 __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ U, const void* __restrict__ clov,
                                                        const float* __restrict__ cscale,
                                                        const int* __restrict__ nbr, const void* __restrict__ in,
@@ -51,34 +92,38 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
                                                        double* __restrict__ part, int64_t pmember, int pvalue,
                                                        int64_t last) {
     using R = typename FineT<LF>::R;
+    __shared__ cpx<R> sh[12 * kWilsonSites];
     // Work-groups are dealt to the 8 XCDs round-robin; renumber them so that
     // each XCD sweeps one contiguous range of sites and the neighbours one
     // x2-plane away stay in that XCD's L2.  The grid is a multiple of 8.
     const int64_t per = gridDim.x >> 3;
     const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int64_t site0 = wg * blockDim.x + threadIdx.x;
-    if (!DOT && site0 >= V) return;
-    // with DOT every thread reaches the work-group sum: one past the last
-    // site computes the last site again, stores nothing and adds zero
+    const int t = threadIdx.x;
+    const int64_t base = wg * kWilsonSites;
+    const int64_t site0 = base + t;
+    // every thread reaches the barrier: one past the last site computes the
+    // last site again, stores nothing (and adds zero to the sums)
     const bool live = site0 < V;
     const int64_t site = live ? site0 : V - 1;
     const int64_t vo = (int64_t)blockIdx.y * V;
     const int* nb = nbr + site * 8;
-    // FP32: the first two hops' operands are requested before the local terms
-    cpx<R> pa[12], ua[9], pb[12], ub[9];
-    if constexpr (sizeof(R) == 4) {
+    cpx<R> acc[12];
+    if constexpr (NEAR < 2 && sizeof(R) == 4) {
+        // x-y neighbours in memory: the site-local terms first, then the hops
+        // in lattice order, two in flight, no LDS copy (where the work-group's
+        // range does not hold whole x-y planes, taking t and z first was
+        // measured slower: 154 vs 136 us on 24^3x48)
+        if (!DOT && !live) return;   // no barrier on this path
+        cpx<R> pa[12], ua[9], pb[12], ub[9];
         hop_load<0, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[0], vo, last);
         hop_load<0, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[1], vo, last);
-    }
-    cpx<R> acc[12];
-    cpx<R> p[12];
-    load_spinor<VF>(p, in, in_scale, site + vo);
+        {
+            cpx<R> p[12];
+            load_spinor<VF>(p, in, in_scale, site + vo);
 #pragma unroll
-    for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
-    if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, site, V);
-    if constexpr (sizeof(R) == 4) {
-        // FP32 arithmetic: the next two hops' operands are loaded while the
-        // current two are applied (measured 7-10% faster than one hop at a time)
+            for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
+            if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, site, V);
+        }
         hop_apply<0, false>(acc, pa, ua);
         hop_load<1, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[2], vo, last);
         hop_apply<0, true>(acc, pb, ub);
@@ -93,8 +138,16 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
         hop_load<3, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[7], vo, last);
         hop_apply<3, false>(acc, pa, ua);
         hop_apply<3, true>(acc, pb, ub);
-    } else {
-        // FP64: two hops in flight would need all 256 registers (one wave per SIMD)
+    } else if constexpr (NEAR < 2) {
+        // FP64 with the x-y neighbours in memory: the site-local terms first,
+        // then the hops one at a time in lattice order, no LDS copy (this
+        // order needs the fewest registers: two waves per SIMD)
+        if (!DOT && !live) return;   // no barrier on this path
+        cpx<R> pa[12], ua[9];
+        load_spinor<VF>(pa, in, in_scale, site + vo);
+#pragma unroll
+        for (int f = 0; f < 12; ++f) acc[f] = {diag * pa[f].re, diag * pa[f].im};
+        if (use_clover) herm_mul_add<LF>(acc, pa, clov, cscale, site, V);
         hop_load<0, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[0], vo, last);
         hop_apply<0, false>(acc, pa, ua);
         hop_load<0, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[1], vo, last);
@@ -111,14 +164,81 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
         hop_apply<3, false>(acc, pa, ua);
         hop_load<3, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[7], vo, last);
         hop_apply<3, true>(acc, pa, ua);
+    } else {
+#pragma unroll
+    for (int f = 0; f < 12; ++f) acc[f] = {0, 0};
+    {
+        cpx<R> p[12];
+        load_spinor<VF>(p, in, in_scale, site + vo);
+        lds_put(sh, t, p);
+    }
+    if constexpr (sizeof(R) == 4) {
+        // FP32 arithmetic: two hops' operands in flight while two are applied
+        cpx<R> pa[12], ua[9], pb[12], ub[9];
+        hop_load<3, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[6], vo, last);
+        hop_load<3, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[7], vo, last);
+        hop_apply<3, false>(acc, pa, ua);
+        hop_load<2, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[4], vo, last);
+        hop_apply<3, true>(acc, pb, ub);
+        hop_load<2, true, LF, VF, LR>(pb, ub, in, in_scale, U, V, site, nb[5], vo, last);
+        hop_apply<2, false>(acc, pa, ua);
+        hop_apply<2, true>(acc, pb, ub);
+        __syncthreads();   // the work-group's spinors are in LDS
+        hop_load_near<NEAR, 1, false, LF, VF, LR>(pa, ua, sh, in, in_scale, U, V, site, nb[2], base, vo, last);
+        hop_load_near<NEAR, 1, true, LF, VF, LR>(pb, ub, sh, in, in_scale, U, V, site, nb[3], base, vo, last);
+        {
+            cpx<R> p[12];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) p[f] = sh[f * kWilsonSites + t];
+#pragma unroll
+            for (int f = 0; f < 12; ++f) acc[f] = {acc[f].re + diag * p[f].re, acc[f].im + diag * p[f].im};
+            if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, site, V);
+        }
+        hop_apply<1, false>(acc, pa, ua);
+        hop_load_near<NEAR, 0, false, LF, VF, LR>(pa, ua, sh, in, in_scale, U, V, site, nb[0], base, vo, last);
+        hop_apply<1, true>(acc, pb, ub);
+        hop_load_near<NEAR, 0, true, LF, VF, LR>(pb, ub, sh, in, in_scale, U, V, site, nb[1], base, vo, last);
+        hop_apply<0, false>(acc, pa, ua);
+        hop_apply<0, true>(acc, pb, ub);
+    } else {
+        // FP64: two hops in flight would need all 256 registers (one wave per SIMD)
+        cpx<R> pa[12], ua[9];
+        hop_load<3, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[6], vo, last);
+        hop_apply<3, false>(acc, pa, ua);
+        hop_load<3, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[7], vo, last);
+        hop_apply<3, true>(acc, pa, ua);
+        hop_load<2, false, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[4], vo, last);
+        hop_apply<2, false>(acc, pa, ua);
+        hop_load<2, true, LF, VF, LR>(pa, ua, in, in_scale, U, V, site, nb[5], vo, last);
+        hop_apply<2, true>(acc, pa, ua);
+        __syncthreads();   // the work-group's spinors are in LDS
+#pragma unroll
+        for (int f = 0; f < 12; ++f) pa[f] = sh[f * kWilsonSites + t];
+#pragma unroll
+        for (int f = 0; f < 12; ++f) acc[f] = {acc[f].re + diag * pa[f].re, acc[f].im + diag * pa[f].im};
+        if (use_clover) herm_mul_add<LF>(acc, pa, clov, cscale, site, V);
+        hop_load_near<NEAR, 1, false, LF, VF, LR>(pa, ua, sh, in, in_scale, U, V, site, nb[2], base, vo, last);
+        hop_apply<1, false>(acc, pa, ua);
+        hop_load_near<NEAR, 1, true, LF, VF, LR>(pa, ua, sh, in, in_scale, U, V, site, nb[3], base, vo, last);
+        hop_apply<1, true>(acc, pa, ua);
+        hop_load_near<NEAR, 0, false, LF, VF, LR>(pa, ua, sh, in, in_scale, U, V, site, nb[0], base, vo, last);
+        hop_apply<0, false>(acc, pa, ua);
+        hop_load_near<NEAR, 0, true, LF, VF, LR>(pa, ua, sh, in, in_scale, U, V, site, nb[1], base, vo, last);
+        hop_apply<0, true>(acc, pa, ua);
+    }
     }
     if (live) store_spinor<VF>(out, out_scale, site + vo, acc);
     if constexpr (DOT) {
-        // the site's input is read again (a cache hit, normally) rather than
-        // kept live across the hops, which would cost half the occupancy; the
-        // empty asm keeps the compiler from reusing the first load instead
-        asm volatile("" ::: "memory");
-        load_spinor<VF>(p, in, in_scale, site + vo);
+        // the site's input from the LDS copy (read again from memory, a cache
+        // hit normally, on the paths that keep none)
+        cpx<R> p[12];
+        if constexpr (NEAR < 2) {
+            asm volatile("" ::: "memory");
+            load_spinor<VF>(p, in, in_scale, site + vo);
+        } else {
+#pragma unroll
+            for (int f = 0; f < 12; ++f) p[f] = sh[f * kWilsonSites + t];
+        }
         double s3[3] = {0, 0, 0};
         if (live)
 #pragma unroll
@@ -131,14 +251,14 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
 #pragma unroll
         for (int i = 0; i < 3; ++i)
             for (int o = 32; o > 0; o >>= 1) s3[i] += __shfl_down(s3[i], o, 64);
-        if ((threadIdx.x & 63) == 0)
+        if ((t & 63) == 0)
 #pragma unroll
-            for (int i = 0; i < 3; ++i) red[i][threadIdx.x >> 6] = s3[i];
+            for (int i = 0; i < 3; ++i) red[i][t >> 6] = s3[i];
         __syncthreads();
-        if (threadIdx.x < 3) {
-            double t = 0;
-            for (int j = 0; j < 4; ++j) t += red[threadIdx.x][j];
-            part[(int64_t)blockIdx.y * pmember + threadIdx.x * pvalue + blockIdx.x] = t;
+        if (t < 3) {
+            double r = 0;
+            for (int j = 0; j < 4; ++j) r += red[t][j];
+            part[(int64_t)blockIdx.y * pmember + t * pvalue + blockIdx.x] = r;
         }
     }
 }
@@ -516,16 +636,29 @@ static qmg_status launch_wilson(const qmg_fine_op_s* op, const void* in, const f
                                 int64_t pmember = 0, int pvalue = 0) {
     using R = typename FineT<LF>::R;
     const unsigned nb = (unsigned)wilson_groups(op);
-#define QMG_WC_LAUNCH(LR)                                                                                          \
-    hipLaunchKernelGGL((k_wilson_clover<LF, VF, DOT, LR>), dim3(nb, members), dim3(256), 0, s, op->U, op->clov,   \
-                       op->cscale, op->nbr, in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0),              \
+    // x and y neighbours from LDS when a work-group's 256 sites are whole x-y
+    // planes; not for 16-bit links with FP32 spinors, which were measured
+    // slower that way (21.8 vs 20.6 us on 16^3x32; FP32 25.6 vs 25.7, all
+    // 16-bit 18.6 vs 19.6)
+    const bool mixed = is16f<LF>() && !is16f<VF>();
+    const int near = !mixed && kWilsonSites % ((int64_t)op->dims[0] * op->dims[1]) == 0 ? 2 : 0;
+#define QMG_WC_LAUNCH(LR, NEAR)                                                                                    \
+    hipLaunchKernelGGL((k_wilson_clover<LF, VF, DOT, LR, NEAR>), dim3(nb, members), dim3(256), 0, s, op->U,       \
+                       op->clov, op->cscale, op->nbr, in, in_scale, out, out_scale, op->V, (R)(4.0 + op->m0),    \
                        op->csw != 0.0 ? 1 : 0, part, pmember, pvalue, op->last)
+#define QMG_WC_NEAR(LR)                                                                                            \
+    if (near == 2) QMG_WC_LAUNCH(LR, 2);                                                                           \
+    else QMG_WC_LAUNCH(LR, 0);
     if constexpr (LF != FMT_F64) {
-        if (op->link_reals == 12) QMG_WC_LAUNCH(12);
-        else QMG_WC_LAUNCH(18);
+        if (op->link_reals == 12) {
+            QMG_WC_NEAR(12)
+        } else {
+            QMG_WC_NEAR(18)
+        }
     } else {
-        QMG_WC_LAUNCH(18);
+        QMG_WC_NEAR(18)
     }
+#undef QMG_WC_NEAR
 #undef QMG_WC_LAUNCH
     QMG_LAUNCH_CHECK();
     return QMG_OK;
