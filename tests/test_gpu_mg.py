@@ -57,10 +57,47 @@ def test_two_level_matches_oracle_iterations(inner):
     tr = solvers.norm(b.reshape(-1) - fine.apply(xh.reshape(-1))) / solvers.norm(b.reshape(-1))
     print('inner', inner, 'gpu', info, 'oracle iters', io.iters, io.inner_iters, 'oracle-M residual %.2e' % tr)
     assert info['converged'] and tr <= 1e-10
+    # the coarsest GCR (single-work-group steps: 192 entries) takes the
+    # oracle's number of steps over the whole solve
     if inner == 'c128':
         assert abs(info['outer_iters'] - io.iters) <= 1
+        assert abs(info['level_iters'][1] - io.inner_iters[1]) <= 1
     else:
         assert info['outer_iters'] <= io.iters + 2
+        assert abs(info['level_iters'][1] - io.inner_iters[1]) <= 2
+
+
+@pytest.mark.parametrize('inner', ['c128', 'c64'])
+def test_coarsest_gcr_on_1536_entries_matches_oracle(inner):
+    """A coarsest level of 4^4 sites x 6 (1536 entries per vector), solved to
+    1e-6 so that a solve takes about six steps: in FP32 the single-work-group
+    GCR step keeps its operands in registers for up to four stored directions
+    and takes the loop form beyond; FP64 always the loop form.  Outer and
+    coarsest step counts against the oracle's K-cycle (FP64: +-1; FP32: +-2
+    outer, 5 % coarsest), true residual under the oracle's M."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2)], [3]
+    U, A, fine = problem(dims, 0.4, 5, m0)
+    st = starts_for(dims, blocks, nvecs, 3)
+    h = omg.Hierarchy(fine, blocks, nvecs, [s.reshape(nvecs[0], -1) for s in st], setup_iters=0)
+    b = synth.gaussian((fine.V, 4, 3), 1, 2)
+    _, io = omg.solve(h, b.reshape(-1), tol=1e-10, coarsest_tol=1e-6, coarsest_maxit=100)
+    levels = level_list(blocks, nvecs, 0, [100])
+    levels[0]['coarse_tol'] = 1e-6
+    mg = Multigrid(dims, dev(U), m0, 1.0, levels, [dev(s) for s in st], inner=inner)
+    d1, N1 = mg.level(1)[:2]
+    assert lattice.volume(d1) * N1 == 1536
+    x, info = mg.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('inner', inner, 'gpu', info, 'oracle iters', io.iters, io.inner_iters, 'oracle-M residual %.2e' % tr)
+    assert info['converged'] and tr <= 1e-10
+    if inner == 'c128':
+        assert abs(info['outer_iters'] - io.iters) <= 1
+        assert abs(info['level_iters'][1] - io.inner_iters[1]) <= 1
+    else:
+        assert abs(info['outer_iters'] - io.iters) <= 2
+        assert abs(info['level_iters'][1] - io.inner_iters[1]) <= max(2, 0.05 * io.inner_iters[1])
 
 
 def test_three_level_with_relaxed_null_vectors():
