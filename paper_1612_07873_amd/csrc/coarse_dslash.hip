@@ -162,6 +162,18 @@ __global__ __launch_bounds__(256) void k_link_scales(float* __restrict__ lscale,
 // oidx[site] (or site; member stride vout), so a piece can read and write
 // whole-lattice fields.
 
+// A link chunk, read once per application: a non-temporal load, so the
+// link stream does not push the input vector's blocks (each read by nine
+// sites) out of the caches.
+template <typename C> __device__ __forceinline__ C ld_link(const C* p) {
+    static_assert(sizeof(C) == 16, "16-byte link chunks");
+    typedef int i4 __attribute__((ext_vector_type(4)));
+    const i4 v = __builtin_nontemporal_load(reinterpret_cast<const i4*>(p));
+    C r;
+    __builtin_memcpy(&r, &v, sizeof(C));
+    return r;
+}
+
 // VF: 0 = vectors in the accumulation precision, else 16-bit pairs (format VF) + per-site scale.
 template <int F, int VF, int PRE, bool EO = false>
 __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C* __restrict__ L,
@@ -194,7 +206,7 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
     C a[PRE];
 #pragma unroll
     for (int q = 0; q < PRE; ++q)
-        if (q < K) a[q] = Ls[(int64_t)(s + split * q) * N];
+        if (q < K) a[q] = ld_link(Ls + (int64_t)(s + split * q) * N);
 
     for (int idx = t; idx < nd * N; idx += T) {
         const int dd = idx / N;
@@ -233,11 +245,11 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
     for (; k + 4 <= K; k += 4) {
         C b[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) b[q] = Ls[(int64_t)(s + split * (k + q)) * N];
+        for (int q = 0; q < 4; ++q) b[q] = ld_link(Ls + (int64_t)(s + split * (k + q)) * N);
 #pragma unroll
         for (int q = 0; q < 4; ++q) mac<F>(b[q], ul + (s + split * (k + q)) * cpc, ar[q], ai[q]);
     }
-    for (; k < K; ++k) mac<F>(Ls[(int64_t)(s + split * k) * N], ul + (s + split * k) * cpc, ar[0], ai[0]);
+    for (; k < K; ++k) mac<F>(ld_link(Ls + (int64_t)(s + split * k) * N), ul + (s + split * k) * cpc, ar[0], ai[0]);
     R sr = (ar[0] + ar[1]) + (ar[2] + ar[3]);
     R si = (ai[0] + ai[1]) + (ai[2] + ai[3]);
     if (split > 1) {

@@ -66,6 +66,15 @@ __global__ void k_pack_mfma(uint4* __restrict__ M, const uint4* __restrict__ L, 
     M[g] = L[(site * J + e / 4) * N + row];
 }
 
+// A link operand chunk, read once per application: a non-temporal load, so
+// the link stream does not push the input blocks -- each read by nine sites --
+// out of L2 before their neighbours ask for them.
+__device__ __forceinline__ uint4 ld_stream(const uint4* p) {
+    typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+    const u4v v = __builtin_nontemporal_load(reinterpret_cast<const u4v*>(p));
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
 // Work of one coarse site; the work-group has `nthreads` threads, of which the
 // first NW waves compute (all of them stage).  The nine input blocks pass
 // through two LDS buffers: while direction d is multiplied, every thread
@@ -95,7 +104,7 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
     uint4 Acur[T], Anext[T];
     if (computes) {
 #pragma unroll
-        for (int ks = 0; ks < T; ++ks) Acur[ks] = Ms[(int64_t)ks * 64];
+        for (int ks = 0; ks < T; ++ks) Acur[ks] = ld_stream(Ms + (int64_t)ks * 64);
     }
     // block 0 and all scales
     {
@@ -130,7 +139,7 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
             }
             if (computes) {
 #pragma unroll
-                for (int ks = 0; ks < T; ++ks) Anext[ks] = Ms[((int64_t)(d + 1) * T * T + ks) * 64];
+                for (int ks = 0; ks < T; ++ks) Anext[ks] = ld_stream(Ms + ((int64_t)(d + 1) * T * T + ks) * 64);
             }
         }
         if (computes) {
@@ -190,12 +199,26 @@ __device__ __forceinline__ void mrhs_site(int site, int nthreads, const uint4* _
     }
 }
 
+// Site of this work-group.  Work-groups are dealt to the 8 XCDs round-robin;
+// numbering the sites so that each XCD takes one contiguous range of ceil(V/8)
+// sites keeps most of a site's neighbours -- whose input blocks it reads --
+// in the same XCD's L2.  The grid is 8 ceil(V/8); -1 past the last site.
+__device__ __forceinline__ int xcd_site(int64_t V) {
+    const int64_t per = (V + 7) / 8;
+    const int64_t s = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    return s < V ? (int)s : -1;
+}
+static unsigned xcd_grid(int64_t V) { return (unsigned)(8 * ((V + 7) / 8)); }
+
 template <int F, int N, int NRHS, int RPW>
 __global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 64) void k_coarse_mrhs(
     const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
-    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y, int64_t oss, int64_t ors) {
+    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y, int64_t oss, int64_t ors,
+    int64_t V) {
     extern __shared__ __align__(16) unsigned char smem[];
-    mrhs_site<F, N, NRHS, RPW>(blockIdx.x, blockDim.x, M, lscale, nbr, u, uscale, y, oss, ors, smem);
+    const int site = xcd_site(V);
+    if (site < 0) return;   // the whole work-group
+    mrhs_site<F, N, NRHS, RPW>(site, blockDim.x, M, lscale, nbr, u, uscale, y, oss, ors, smem);
 }
 
 // Whole-site form: one wave per row tile, each owning every right-hand-side
@@ -209,7 +232,8 @@ __global__ __launch_bounds__((N / 16) * ((NRHS >= 16 ? NRHS / 16 : 1) / RPW) * 6
 template <int F, int N, int NRHS>
 __global__ __launch_bounds__((N / 16) * 64) void k_coarse_mrhs_all(
     const uint4* __restrict__ M, const float* __restrict__ lscale, const int* __restrict__ nbr,
-    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y, int64_t oss, int64_t ors) {
+    const uint32_t* __restrict__ u, const float* __restrict__ uscale, float2* __restrict__ y, int64_t oss, int64_t ors,
+    int64_t V) {
     constexpr int T = N / 16;                       // row tiles = waves = k steps per direction
     constexpr int NT = NRHS >= 16 ? NRHS / 16 : 1;  // right-hand-side tiles
     constexpr int UW = NRHS * N;                    // dwords per input block in HBM
@@ -220,7 +244,8 @@ __global__ __launch_bounds__((N / 16) * 64) void k_coarse_mrhs_all(
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t* Us = reinterpret_cast<uint32_t*>(smem);   // [9][NRHS][LD]
     float* Sc = reinterpret_cast<float*>(Us + 9 * US);   // [9][NRHS]
-    const int site = blockIdx.x;
+    const int site = xcd_site(V);
+    if (site < 0) return;   // the whole work-group
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int rt = w;
 
@@ -230,7 +255,7 @@ __global__ __launch_bounds__((N / 16) * 64) void k_coarse_mrhs_all(
 #pragma unroll
         for (int d = 0; d < 9; ++d)
 #pragma unroll
-            for (int ks = 0; ks < T; ++ks) A[d][ks] = Ms[((int64_t)d * T * T + ks) * 64];
+            for (int ks = 0; ks < T; ++ks) A[d][ks] = ld_stream(Ms + ((int64_t)d * T * T + ks) * 64);
     }
 #pragma unroll
     for (int d = 0; d < 9; ++d) {
@@ -341,8 +366,9 @@ static qmg_status launch_mrhs_t(const qmg_coarse_op_s* op, const void* in, const
     const size_t lds = 2 * (size_t)NRHS * (N + 4) * 4 + 9 * NRHS * 4;
     auto kern = k_coarse_mrhs<F, N, NRHS, RPW>;
     if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3((unsigned)op->V), dim3(NW * 64), lds, s, (const uint4*)op->mlinks, op->lscale, op->nbr,
-                       (const uint32_t*)in, sc, (float2*)out, ors ? (int64_t)N : (int64_t)NRHS * N, ors ? ors : (int64_t)N);
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(op->V)), dim3(NW * 64), lds, s, (const uint4*)op->mlinks, op->lscale,
+                       op->nbr, (const uint32_t*)in, sc, (float2*)out, ors ? (int64_t)N : (int64_t)NRHS * N,
+                       ors ? ors : (int64_t)N, op->V);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -353,9 +379,9 @@ static qmg_status launch_all_t(const qmg_coarse_op_s* op, const void* in, const 
     const size_t lds = 9 * (size_t)NRHS * (N + 4) * 4 + 9 * NRHS * 4;
     auto kern = k_coarse_mrhs_all<F, N, NRHS>;
     if (lds > 65536) QMG_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL(kern, dim3((unsigned)op->V), dim3((N / 16) * 64), lds, s, (const uint4*)op->mlinks, op->lscale,
-                       op->nbr, (const uint32_t*)in, sc, (float2*)out, ors ? (int64_t)N : (int64_t)NRHS * N,
-                       ors ? ors : (int64_t)N);
+    hipLaunchKernelGGL(kern, dim3(xcd_grid(op->V)), dim3((N / 16) * 64), lds, s, (const uint4*)op->mlinks,
+                       op->lscale, op->nbr, (const uint32_t*)in, sc, (float2*)out, ors ? (int64_t)N : (int64_t)NRHS * N,
+                       ors ? ors : (int64_t)N, op->V);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }

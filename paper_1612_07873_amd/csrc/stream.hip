@@ -3,22 +3,27 @@
 // reads its links once and writes a vector a ninth of their size).  Every
 // thread walks the buffer grid-strided with four independent 16-byte loads in
 // flight per step, folds what it reads into one word, and one word per
-// work-group is written so the loads cannot be dropped.  The launch fills the
+// work-group is written so the loads cannot be dropped.  The loads are
+// non-temporal, as the stencils' link loads are.  The launch fills the
 // device: 8 work-groups of 256 threads per compute unit.
 #include "qmg_internal.h"
 
 namespace {
 
-__global__ __launch_bounds__(256) void k_read_stream(const uint4* __restrict__ p, int64_t n, uint32_t* __restrict__ sink) {
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_read_stream(const u4v* __restrict__ p, int64_t n, uint32_t* __restrict__ sink) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t acc = 0;
     for (; i + 3 * stride < n; i += 4 * stride) {
-        const uint4 a = p[i], b = p[i + stride], c = p[i + 2 * stride], d = p[i + 3 * stride];
-        acc ^= a.x ^ a.y ^ a.z ^ a.w ^ b.x ^ b.y ^ b.z ^ b.w ^ c.x ^ c.y ^ c.z ^ c.w ^ d.x ^ d.y ^ d.z ^ d.w;
+        const u4v a = __builtin_nontemporal_load(p + i), b = __builtin_nontemporal_load(p + i + stride),
+                  c = __builtin_nontemporal_load(p + i + 2 * stride), d = __builtin_nontemporal_load(p + i + 3 * stride);
+        const u4v e = a ^ b ^ c ^ d;
+        acc ^= e.x ^ e.y ^ e.z ^ e.w;
     }
     for (; i < n; i += stride) {
-        const uint4 a = p[i];
+        const u4v a = __builtin_nontemporal_load(p + i);
         acc ^= a.x ^ a.y ^ a.z ^ a.w;
     }
     __shared__ uint32_t red[4];
@@ -41,7 +46,7 @@ extern "C" qmg_status qmg_stream_read(const void* buf, long long bytes, void* si
     const unsigned grid = (unsigned)(cus > 0 ? 8 * cus : 2048);
     if ((long long)sink_words < (long long)grid)
         return fail(QMG_ERR_ARG, "stream_read: the sink needs %u words, has %d", grid, sink_words);
-    hipLaunchKernelGGL(k_read_stream, dim3(grid), dim3(256), 0, as_stream(stream), static_cast<const uint4*>(buf),
+    hipLaunchKernelGGL(k_read_stream, dim3(grid), dim3(256), 0, as_stream(stream), static_cast<const u4v*>(buf),
                        (int64_t)(bytes / 16), static_cast<uint32_t*>(sink));
     QMG_LAUNCH_CHECK();
     return QMG_OK;
