@@ -82,6 +82,9 @@ __device__ __forceinline__ void load_link(cpx<R> u[9], const void* __restrict__ 
 }
 
 // One chirality block of the clover term: 6 diagonal reals, 15 upper entries.
+// Each site's block is read once per application: non-temporal loads, so it
+// does not push the spinors and links that neighbouring sites share out of
+// the caches.
 template <int LF, typename R>
 __device__ __forceinline__ void load_clover(R d[6], cpx<R> o[15], const void* __restrict__ clov,
                                             const float* __restrict__ cscale, int chi, int64_t site, int64_t V) {
@@ -90,21 +93,22 @@ __device__ __forceinline__ void load_clover(R d[6], cpx<R> o[15], const void* __
         const float k = cscale[(int64_t)chi * V + site];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-            const cpx<float> v = dec_pair<LF>(W[q * V]);
+            const cpx<float> v = dec_pair<LF>(__builtin_nontemporal_load(W + q * V));
             d[2 * q] = k * v.re;
             d[2 * q + 1] = k * v.im;
         }
 #pragma unroll
         for (int q = 0; q < 15; ++q) {
-            const cpx<float> v = dec_pair<LF>(W[(3 + q) * V]);
+            const cpx<float> v = dec_pair<LF>(__builtin_nontemporal_load(W + (3 + q) * V));
             o[q] = {k * v.re, k * v.im};
         }
     } else {
         const R* A = static_cast<const R*>(clov) + (int64_t)chi * 36 * V + site;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) d[i] = A[i * V];
+        for (int i = 0; i < 6; ++i) d[i] = __builtin_nontemporal_load(A + i * V);
 #pragma unroll
-        for (int q = 0; q < 15; ++q) o[q] = {A[(6 + 2 * q) * V], A[(7 + 2 * q) * V]};
+        for (int q = 0; q < 15; ++q)
+            o[q] = {__builtin_nontemporal_load(A + (6 + 2 * q) * V), __builtin_nontemporal_load(A + (7 + 2 * q) * V)};
     }
 }
 
