@@ -71,9 +71,10 @@ int qmg_version(void);
 qmg_status qmg_sync(void* stream);
 
 /* Measurement reference: read `bytes` (a multiple of 16) of the DEVICE buffer
- * once with a plain read-stream kernel (8 work-groups of 256 threads per
- * compute unit, four 16-byte loads in flight per thread), writing one word
- * per work-group to the DEVICE `sink` (sink_words >= 8 x compute units).
+ * once with a plain read-stream kernel (16 work-groups of 256 threads per
+ * compute unit, eight 16-byte non-temporal loads in flight per thread),
+ * writing one word per work-group to the DEVICE `sink` (sink_words >= 16 x
+ * compute units; fewer returns QMG_ERR_ARG).
  * Timed by the caller, it gives the achievable HBM read bandwidth that the
  * read-dominated stencils are compared with. */
 qmg_status qmg_stream_read(const void* buf, long long bytes, void* sink, int sink_words, void* stream);
@@ -394,6 +395,17 @@ qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, const int b
                                const void* nullvecs, qmg_prec storage, void* stream,
                                qmg_transfer* out);
 
+/* Rebuild a transfer from a basis that is already block-orthonormal, as
+ * qmg_transfer_export writes it (DEVICE complex128 [V][fine_dof][nvec]):
+ * no orthonormalisation, the FP64 basis is copied as given, so a transfer
+ * exported and imported again prolongs and restricts bit for bit as the
+ * original.  Checkpoint/resume of a hierarchy (setup amortised over solves,
+ * Sec. 3.4).  Same shape checks and errors as qmg_transfer_create; a basis
+ * that is not block-orthonormal is not detected (R P then differs from 1).
+ * Blocks until the copy is done. */
+qmg_status qmg_transfer_import(const int fine_dims[4], int fine_dof, const int block[4], int nvec,
+                               const void* basis, qmg_prec storage, void* stream, qmg_transfer* out);
+
 /* Coarse lattice extents and N = 2*nvec of the transfer (host outputs). */
 qmg_status qmg_transfer_coarse_dims(qmg_transfer t, int cdims[4], int* N);
 
@@ -482,6 +494,21 @@ typedef struct {
 qmg_status qmg_mg_create(const int dims[4], const void* gauge, double m0, double csw, int antiperiodic_t,
                          int nlevels, const qmg_level_params* lp, const void* const* starts,
                          qmg_prec inner, qmg_prec fine_storage, void* stream, qmg_mg* out);
+
+/* Resume a hierarchy from a checkpoint: as qmg_mg_create, with bases[l] =
+ * the FP64 transfer basis of level l as qmg_transfer_export writes it (DEVICE
+ * complex128 [V_l][dof_l][nvec_l], from the transfer that qmg_mg_level
+ * returns) in place of the start vectors.  The near-null relaxation is
+ * skipped (setup_iters unused) and the Galerkin build, the 16-bit
+ * conversions and the autotuning run as in qmg_mg_create, so the coarse
+ * operators come out bit for bit as in the hierarchy the bases were taken
+ * from (same gauge field, m0, csw, level parameters and precisions).  The
+ * solver settings changed after creation (qmg_mg_set_*) are not part of the
+ * hierarchy and are set again by the caller.  Blocks. */
+qmg_status qmg_mg_create_from_bases(const int dims[4], const void* gauge, double m0, double csw,
+                                    int antiperiodic_t, int nlevels, const qmg_level_params* lp,
+                                    const void* const* bases, qmg_prec inner, qmg_prec fine_storage,
+                                    void* stream, qmg_mg* out);
 
 /* Solve M x = b: b, x DEVICE complex128 [V][4][3] (x is overwritten, start
  * x = 0).  Blocks; returns QMG_ERR_NOCONV if maxit is reached and
@@ -610,6 +637,14 @@ qmg_status qmg_ptc_create(qmg_fine_op links, int hidden, void* stream, qmg_ptc* 
 /* Copy weights in (resets the Adam state) or out. */
 qmg_status qmg_ptc_set_weights(qmg_ptc net, const void* W1, const void* W2, void* stream);
 qmg_status qmg_ptc_get_weights(qmg_ptc net, void* W1, void* W2, void* stream);
+/* Adam state for checkpointing training: first and second moments m1, v1
+ * (layer 1) and m2, v2 (layer 2), DEVICE float32 pairs shaped like the
+ * weights (real and imaginary parts are independent parameters), and the
+ * number of Adam steps taken (its bias corrections).  Restore after
+ * qmg_ptc_set_weights, which clears the state. */
+qmg_status qmg_ptc_get_adam(qmg_ptc net, void* m1, void* v1, void* m2, void* v2, int* steps, void* stream);
+qmg_status qmg_ptc_set_adam(qmg_ptc net, const void* m1, const void* v1, const void* m2, const void* v2, int steps,
+                            void* stream);
 /* y = N(r); r and y must not overlap. */
 qmg_status qmg_ptc_forward(qmg_ptc net, const void* r, void* y, void* stream);
 /* Add the loss |N(r) - e|^2/|e|^2 of one pair and its gradients

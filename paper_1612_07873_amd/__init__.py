@@ -5,8 +5,10 @@ data pointers and the current HIP stream to libqmg.so.  Every step runs in
 the library's kernels; if the library is missing, these calls raise.
 """
 import ctypes
+import json
 import os
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -20,7 +22,7 @@ _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.comp
 
 def stream_read(buf, sink):
     """Read the device tensor `buf` once with the library's read-stream kernel (qmg_stream_read);
-    sink: int32 device tensor of at least 8 x (compute units) words."""
+    sink: int32 device tensor of at least 16 x (compute units) words."""
     _lib.call('qmg_stream_read', ctypes.c_void_p(buf.data_ptr()), int(buf.numel() * buf.element_size()),
               ctypes.c_void_p(sink.data_ptr()), int(sink.numel()), stream_ptr())
 
@@ -371,6 +373,30 @@ class Transfer:
         self.Vc = _vol(self.coarse_dims)
         self.N = n.value
 
+    @classmethod
+    def from_basis(cls, fine_dims, fine_dof, block, basis, storage='c128'):
+        """Transfer from a finished block-orthonormal basis, complex128 [V][fine_dof][nvec] as
+        basis() returns it (qmg_transfer_import: no orthonormalisation)."""
+        t = cls.__new__(cls)
+        t.fine_dims = tuple(int(d) for d in fine_dims)
+        t.V = _vol(t.fine_dims)
+        t.dof = int(fine_dof)
+        t.block = tuple(int(b) for b in block)
+        t.nvec = int(basis.shape[-1])
+        t.storage = storage
+        h = ctypes.c_void_p()
+        _lib.call('qmg_transfer_import', _lib.c_dims(*t.fine_dims), t.dof, _lib.c_dims(*t.block), t.nvec,
+                  _dev_ptr(basis, torch.complex128, (t.V, t.dof, t.nvec), 'basis'), PREC[storage], stream_ptr(),
+                  ctypes.byref(h))
+        t._h = h
+        cd = _lib.c_dims()
+        n = ctypes.c_int()
+        _lib.call('qmg_transfer_coarse_dims', h, cd, ctypes.byref(n))
+        t.coarse_dims = tuple(cd)
+        t.Vc = _vol(t.coarse_dims)
+        t.N = n.value
+        return t
+
     def basis(self):
         B = torch.empty((self.V, self.dof, self.nvec), dtype=torch.complex128, device='cuda')
         _lib.call('qmg_transfer_export', self._h, ctypes.c_void_p(B.data_ptr()), stream_ptr())
@@ -475,11 +501,19 @@ class Multigrid:
     [nvec_l][V_l][dof_l]; fine_storage: None or 'h16' / 'b16' for the fine
     operator inside the K-cycle."""
 
-    def __init__(self, dims, gauge, m0, csw, levels, starts, antiperiodic_t=True, inner='c64', fine_storage=None):
+    def __init__(self, dims, gauge, m0, csw, levels, starts, antiperiodic_t=True, inner='c64', fine_storage=None,
+                 bases=None):
+        """bases (instead of starts): the levels' FP64 transfer bases, complex128
+        [V_l][dof_l][nvec_l], as a checkpoint holds them (qmg_mg_create_from_bases)."""
         self.dims = tuple(int(d) for d in dims)
         self.V = _vol(self.dims)
         self.inner = inner
         self.nlevels = len(levels) + 1
+        self._cfg = dict(dims=list(self.dims), m0=float(m0), csw=float(csw), antiperiodic_t=bool(antiperiodic_t),
+                         inner=inner, fine_storage=fine_storage,
+                         levels=[{k: (list(v) if isinstance(v, (tuple, list)) else v) for k, v in L.items()}
+                                 for L in levels])
+        self._gauge = gauge
         lp = (_lib.LevelParams * max(1, len(levels)))()
         for i, L in enumerate(levels):
             lp[i].block = (ctypes.c_int * 4)(*L['block'])
@@ -490,14 +524,15 @@ class Multigrid:
             lp[i].coarse_maxit = int(L.get('coarse_maxit', 10))
             lp[i].coarse_storage = PREC[L['coarse_storage']] if L.get('coarse_storage') else 0
             lp[i].coarse_direct = int(bool(L.get('coarse_direct', False)))
-        ptrs = (ctypes.c_void_p * max(1, len(starts)))()
-        for i, t in enumerate(starts):
+        vecs, what = (starts, 'starts') if bases is None else (bases, 'bases')
+        ptrs = (ctypes.c_void_p * max(1, len(vecs)))()
+        for i, t in enumerate(vecs):
             if not (t.is_cuda and t.dtype == torch.complex128 and t.is_contiguous()):
-                raise TypeError('starts[%d] must be a contiguous complex128 device tensor' % i)
+                raise TypeError('%s[%d] must be a contiguous complex128 device tensor' % (what, i))
             ptrs[i] = t.data_ptr()
-        self._starts = starts
+        self._starts = vecs
         h = ctypes.c_void_p()
-        _lib.call('qmg_mg_create', _lib.c_dims(*self.dims),
+        _lib.call('qmg_mg_create' if bases is None else 'qmg_mg_create_from_bases', _lib.c_dims(*self.dims),
                   _dev_ptr(gauge, torch.complex128, (4, self.V, 3, 3), 'gauge'),
                   float(m0), float(csw), int(bool(antiperiodic_t)), self.nlevels, lp, ptrs, PREC[inner],
                   PREC[fine_storage] if fine_storage else 0, stream_ptr(), ctypes.byref(h))
@@ -616,6 +651,48 @@ class Multigrid:
             tr = _BorrowedTransfer(T, dims, dof.value, int(self._levels[l]['nvec']), self.inner)
         return dims, dof.value, cop, tr
 
+    def save(self, path):
+        """Checkpoint the hierarchy to an .npz file: the gauge field, the operator and
+        level parameters, and every level's FP64 transfer basis (qmg_transfer_export).
+        Multigrid.load rebuilds it without the near-null relaxation, with coarse
+        operators bit for bit equal; solver settings made with set_* are not saved."""
+        arrays = {'meta': np.frombuffer(json.dumps(self._cfg).encode(), dtype=np.uint8),
+                  'gauge': self._gauge.detach().cpu().numpy()}
+        for l in range(self.nlevels - 1):
+            arrays['basis%d' % l] = self.level(l)[3].basis().cpu().numpy()
+        # the autotuner's launch choices fix the stencils' summation order: keep them
+        # so that a resumed hierarchy in another process solves bit for bit alike
+        import tempfile
+        with tempfile.TemporaryDirectory() as d:
+            f = os.path.join(d, 'tune.txt')
+            tune_cache_save(f)
+            with open(f, 'rb') as fh:
+                arrays['tune'] = np.frombuffer(fh.read(), dtype=np.uint8)
+        np.savez(path, **arrays)
+
+    @classmethod
+    def load(cls, path):
+        """Resume a hierarchy written by save() (qmg_mg_create_from_bases).  The saved
+        launch choices enter the autotuner's cache first when the file was written on
+        this device architecture and runtime; otherwise the stencils are tuned anew."""
+        with np.load(path, allow_pickle=False) as z:
+            c = json.loads(bytes(z['meta']).decode())
+            gauge = torch.from_numpy(z['gauge']).to('cuda')
+            bases = [torch.from_numpy(z['basis%d' % l]).to('cuda') for l in range(len(c['levels']))]
+            tune = bytes(z['tune']) if 'tune' in z.files else b''
+        if tune:
+            import tempfile
+            with tempfile.TemporaryDirectory() as d:
+                f = os.path.join(d, 'tune.txt')
+                with open(f, 'wb') as fh:
+                    fh.write(tune)
+                try:
+                    tune_cache_load(f)
+                except QmgError:
+                    pass  # written on another device or runtime: the stencils are tuned anew
+        return cls(c['dims'], gauge, c['m0'], c['csw'], c['levels'], None, antiperiodic_t=c['antiperiodic_t'],
+                   inner=c['inner'], fine_storage=c['fine_storage'], bases=bases)
+
     def __del__(self):
         h = getattr(self, '_h', None)
         if h is not None and h.value and _lib._lib is not None:
@@ -701,6 +778,39 @@ class PTC:
 
     def adam_step(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
         _lib.call('qmg_ptc_adam_step', self._h, float(lr), float(beta1), float(beta2), float(eps), stream_ptr())
+
+    def adam_state(self):
+        """(m1, v1, m2, v2, steps) (qmg_ptc_get_adam): the Adam moments as complex64 tensors
+        shaped like the weights (real and imaginary parts: the moments of the two real
+        parameters) and the number of Adam steps taken."""
+        s1, s2 = self.wshapes()
+        m1, v1 = (torch.empty(s1, dtype=torch.complex64, device='cuda') for _ in range(2))
+        m2, v2 = (torch.empty(s2, dtype=torch.complex64, device='cuda') for _ in range(2))
+        n = ctypes.c_int()
+        _lib.call('qmg_ptc_get_adam', self._h, *(ctypes.c_void_p(t.data_ptr()) for t in (m1, v1, m2, v2)),
+                  ctypes.byref(n), stream_ptr())
+        return m1, v1, m2, v2, n.value
+
+    def set_adam_state(self, m1, v1, m2, v2, steps):
+        s1, s2 = self.wshapes()
+        _lib.call('qmg_ptc_set_adam', self._h, _dev_ptr(m1, torch.complex64, s1, 'm1'),
+                  _dev_ptr(v1, torch.complex64, s1, 'v1'), _dev_ptr(m2, torch.complex64, s2, 'm2'),
+                  _dev_ptr(v2, torch.complex64, s2, 'v2'), int(steps), stream_ptr())
+
+    def save(self, path):
+        """Checkpoint the weights and the Adam state to an .npz file."""
+        W1, W2 = self.weights()
+        m1, v1, m2, v2, n = self.adam_state()
+        np.savez(path, W1=W1.cpu().numpy(), W2=W2.cpu().numpy(), m1=m1.cpu().numpy(), v1=v1.cpu().numpy(),
+                 m2=m2.cpu().numpy(), v2=v2.cpu().numpy(), steps=np.array(n, dtype=np.int64))
+
+    def load(self, path):
+        """Restore weights and Adam state written by save(); training resumes where it stopped."""
+        with np.load(path, allow_pickle=False) as z:
+            t = {k: torch.from_numpy(z[k]).to('cuda') for k in ('W1', 'W2', 'm1', 'v1', 'm2', 'v2')}
+            n = int(z['steps'])
+        self.set_weights(t['W1'], t['W2'])
+        self.set_adam_state(t['m1'], t['v1'], t['m2'], t['v2'], n)
 
     def __del__(self):
         h = getattr(self, '_h', None)

@@ -54,6 +54,8 @@ SIGNATURES = {
                                     ctypes.POINTER(c_void_p)]),
     'qmg_transfer_coarse_dims': (c_int, [c_void_p, c_int_p, c_int_p]),
     'qmg_transfer_export': (c_int, [c_void_p, c_void_p, c_void_p]),
+    'qmg_transfer_import': (c_int, [c_dims, c_int, c_dims, c_int, c_void_p, c_int, c_void_p,
+                                    ctypes.POINTER(c_void_p)]),
     'qmg_prolong': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_restrict': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),
     'qmg_transfer_destroy': (None, [c_void_p]),
@@ -100,6 +102,9 @@ SIGNATURES.update({
     'qmg_bicgstab_destroy': (None, [c_void_p]),
     'qmg_mg_create': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int, ctypes.POINTER(LevelParams),
                               ctypes.POINTER(c_void_p), c_int, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    'qmg_mg_create_from_bases': (c_int, [c_dims, c_void_p, c_double, c_double, c_int, c_int,
+                                         ctypes.POINTER(LevelParams), ctypes.POINTER(c_void_p), c_int, c_int,
+                                         c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_mg_gcr_solve': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
                                  ctypes.POINTER(SolveInfo), c_void_p]),
     'qmg_mg_gcr_solve_record_smoother': (c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(SolveParams),
@@ -121,6 +126,8 @@ SIGNATURES.update({
     'qmg_ptc_create': (c_int, [c_void_p, c_int, c_void_p, ctypes.POINTER(c_void_p)]),
     'qmg_ptc_set_weights': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_ptc_get_weights': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
+    'qmg_ptc_get_adam': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int_p, c_void_p]),
+    'qmg_ptc_set_adam': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
     'qmg_ptc_forward': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_ptc_accumulate_grad': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p]),
     'qmg_ptc_zero_grad': (c_int, [c_void_p, c_void_p]),

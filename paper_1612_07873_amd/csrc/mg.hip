@@ -664,6 +664,18 @@ qmg_status setup_level(qmg_mg_s* mg, int l, const void* starts, int setup_iters)
     return st;
 }
 
+// transfer of level l from a finished FP64 basis (checkpoint resume), then the
+// next coarse operator exactly as setup_level builds it
+qmg_status import_level(qmg_mg_s* mg, int l, const void* basis) {
+    Level& L = mg->lv[l];
+    QMG_TRY(qmg_transfer_import(L.dims, L.dof, L.p.block, L.p.nvec, basis, mg->inner, mg->s, &L.T));
+    Level& C = mg->lv[l + 1];
+    const qmg_status st = l == 0 ? qmg_build_coarse_op(L.T, mg->fine64, nullptr, mg->inner, mg->s, &C.op)
+                                 : qmg_build_coarse_op(L.T, nullptr, L.op, mg->inner, mg->s, &C.op);
+    (void)hipStreamSynchronize(mg->s);
+    return st;
+}
+
 // b, x: nb members of [V][12] complex128; info: nb entries (or NULL)
 template <typename R>
 qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_params* sp, qmg_solve_info* info) {
@@ -845,16 +857,18 @@ extern "C" void qmg_mg_destroy(qmg_mg mg) {
     delete mg;
 }
 
-extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double m0, double csw,
-                                    int antiperiodic_t, int nlevels, const qmg_level_params* lp,
-                                    const void* const* starts, qmg_prec inner, qmg_prec fine_storage,
-                                    void* stream, qmg_mg* out) {
+// qmg_mg_create (vecs = start vectors of the relaxation) and
+// qmg_mg_create_from_bases (vecs = finished transfer bases, no relaxation)
+static qmg_status mg_make(const int dims[4], const void* gauge, double m0, double csw, int antiperiodic_t,
+                          int nlevels, const qmg_level_params* lp, const void* const* starts,
+                          bool from_bases, qmg_prec inner, qmg_prec fine_storage, void* stream, qmg_mg* out) {
     if (!out) return fail(QMG_ERR_ARG, "mg_create: out is NULL");
     *out = nullptr;
     QMG_TRY(check_dims(dims, 2, "mg_create"));
     if (!gauge) return fail(QMG_ERR_ARG, "mg_create: gauge is NULL");
     if (nlevels < 1 || nlevels > 4) return fail(QMG_ERR_ARG, "mg_create: nlevels %d outside [1,4]", nlevels);
-    if (nlevels > 1 && (!lp || !starts)) return fail(QMG_ERR_ARG, "mg_create: level params / starts missing");
+    if (nlevels > 1 && (!lp || !starts))
+        return fail(QMG_ERR_ARG, "mg_create: level params / %s missing", from_bases ? "bases" : "starts");
     if (inner != QMG_C128 && inner != QMG_C64) return fail(QMG_ERR_PREC, "mg_create: inner precision %d", (int)inner);
     const bool fine16 = fine_storage == QMG_H16 || fine_storage == QMG_B16;
     if (fine_storage != 0 && fine_storage != inner && !fine16)
@@ -862,7 +876,7 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
     if (fine16 && inner != QMG_C64)
         return fail(QMG_ERR_PREC, "mg_create: 16-bit fine storage needs complex64 inner precision");
     for (int l = 0; l + 1 < nlevels; ++l) {
-        if (!starts[l]) return fail(QMG_ERR_ARG, "mg_create: starts[%d] is NULL", l);
+        if (!starts[l]) return fail(QMG_ERR_ARG, "mg_create: %s[%d] is NULL", from_bases ? "bases" : "starts", l);
         if (lp[l].nvec < 1 || lp[l].nvec > 64) return fail(QMG_ERR_ARG, "mg_create: nvec %d", lp[l].nvec);
         if (lp[l].smoother_steps < 0 || lp[l].coarse_maxit < 1 || lp[l].setup_iters < 0)
             return fail(QMG_ERR_ARG, "mg_create: bad level %d parameters", l);
@@ -913,8 +927,9 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
     }
     if (st == QMG_OK) st = workspace(mg, 1);
     for (int l = 0; l + 1 < nlevels && st == QMG_OK; ++l)
-        st = inner == QMG_C128 ? setup_level<double>(mg, l, starts[l], lp[l].setup_iters)
-                               : setup_level<float>(mg, l, starts[l], lp[l].setup_iters);
+        st = from_bases ? import_level(mg, l, starts[l])
+             : inner == QMG_C128 ? setup_level<double>(mg, l, starts[l], lp[l].setup_iters)
+                                 : setup_level<float>(mg, l, starts[l], lp[l].setup_iters);
     // exact coarsest solve: the dense inverse of the full-precision operator
     if (st == QMG_OK && nlevels > 1 && lp[nlevels - 2].coarse_direct) {
         Level& C = mg->lv[nlevels - 1];
@@ -963,6 +978,21 @@ extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double
     }
     *out = mg;
     return QMG_OK;
+}
+
+extern "C" qmg_status qmg_mg_create(const int dims[4], const void* gauge, double m0, double csw,
+                                    int antiperiodic_t, int nlevels, const qmg_level_params* lp,
+                                    const void* const* starts, qmg_prec inner, qmg_prec fine_storage,
+                                    void* stream, qmg_mg* out) {
+    return mg_make(dims, gauge, m0, csw, antiperiodic_t, nlevels, lp, starts, false, inner, fine_storage, stream,
+                   out);
+}
+
+extern "C" qmg_status qmg_mg_create_from_bases(const int dims[4], const void* gauge, double m0, double csw,
+                                               int antiperiodic_t, int nlevels, const qmg_level_params* lp,
+                                               const void* const* bases, qmg_prec inner, qmg_prec fine_storage,
+                                               void* stream, qmg_mg* out) {
+    return mg_make(dims, gauge, m0, csw, antiperiodic_t, nlevels, lp, bases, true, inner, fine_storage, stream, out);
 }
 
 static qmg_status check_solve(qmg_mg mg, const void* b, void* x, const qmg_solve_params* p, const char* what) {

@@ -637,6 +637,32 @@ extern "C" qmg_status qmg_ptc_get_weights(qmg_ptc t, void* W1, void* W2, void* s
     return QMG_OK;
 }
 
+extern "C" qmg_status qmg_ptc_get_adam(qmg_ptc t, void* m1, void* v1, void* m2, void* v2, int* steps, void* stream) {
+    if (!t || !m1 || !v1 || !m2 || !v2 || !steps) return fail(QMG_ERR_ARG, "ptc_get_adam: NULL argument");
+    const size_t nb = sizeof(float2) * 9 * t->C * 16;
+    hipStream_t s = as_stream(stream);
+    QMG_HIP(hipMemcpyAsync(m1, t->m1, nb, hipMemcpyDeviceToDevice, s));
+    QMG_HIP(hipMemcpyAsync(v1, t->v1, nb, hipMemcpyDeviceToDevice, s));
+    QMG_HIP(hipMemcpyAsync(m2, t->m2, nb, hipMemcpyDeviceToDevice, s));
+    QMG_HIP(hipMemcpyAsync(v2, t->v2, nb, hipMemcpyDeviceToDevice, s));
+    *steps = t->adam_t;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_ptc_set_adam(qmg_ptc t, const void* m1, const void* v1, const void* m2, const void* v2,
+                                       int steps, void* stream) {
+    if (!t || !m1 || !v1 || !m2 || !v2) return fail(QMG_ERR_ARG, "ptc_set_adam: NULL argument");
+    if (steps < 0) return fail(QMG_ERR_ARG, "ptc_set_adam: steps %d < 0", steps);
+    const size_t nb = sizeof(float2) * 9 * t->C * 16;
+    hipStream_t s = as_stream(stream);
+    QMG_HIP(hipMemcpyAsync(t->m1, m1, nb, hipMemcpyDeviceToDevice, s));
+    QMG_HIP(hipMemcpyAsync(t->v1, v1, nb, hipMemcpyDeviceToDevice, s));
+    QMG_HIP(hipMemcpyAsync(t->m2, m2, nb, hipMemcpyDeviceToDevice, s));
+    QMG_HIP(hipMemcpyAsync(t->v2, v2, nb, hipMemcpyDeviceToDevice, s));
+    t->adam_t = steps;
+    return QMG_OK;
+}
+
 extern "C" qmg_status qmg_ptc_forward(qmg_ptc t, const void* r, void* y, void* stream) {
     if (!t || !r || !y) return fail(QMG_ERR_ARG, "ptc_forward: NULL argument");
     if (r == y) return fail(QMG_ERR_ARG, "ptc_forward: r and y alias");

@@ -288,32 +288,32 @@ extern "C" void qmg_transfer_destroy(qmg_transfer t) {
     delete t;
 }
 
-extern "C" qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, const int block[4],
-                                          int nvec, const void* nullvecs, qmg_prec storage,
-                                          void* stream, qmg_transfer* out) {
-    if (!out) return fail(QMG_ERR_ARG, "transfer_create: out is NULL");
-    *out = nullptr;
-    QMG_TRY(check_dims(fine_dims, 2, "transfer_create"));
-    if (!block || !nullvecs) return fail(QMG_ERR_ARG, "transfer_create: NULL argument");
+namespace {
+
+// Validation, aggregate tables and the FP64 basis buffer shared by
+// qmg_transfer_create and qmg_transfer_import; `what` prefixes the messages.
+qmg_status transfer_shell(const char* what, const int fine_dims[4], int fine_dof, const int block[4], int nvec,
+                          const void* vecs, qmg_prec storage, hipStream_t s, qmg_transfer_s** out) {
+    QMG_TRY(check_dims(fine_dims, 2, what));
+    if (!block || !vecs) return fail(QMG_ERR_ARG, "%s: NULL argument", what);
     if (fine_dof < 2 || (fine_dof & 1) || fine_dof > 128)
-        return fail(QMG_ERR_SHAPE, "transfer_create: fine_dof %d must be even in [2,128]", fine_dof);
-    if (nvec < 1 || 2 * nvec > 128) return fail(QMG_ERR_SHAPE, "transfer_create: nvec %d outside [1,64]", nvec);
+        return fail(QMG_ERR_SHAPE, "%s: fine_dof %d must be even in [2,128]", what, fine_dof);
+    if (nvec < 1 || 2 * nvec > 128) return fail(QMG_ERR_SHAPE, "%s: nvec %d outside [1,64]", what, nvec);
     if (storage != QMG_C128 && storage != QMG_C64)
-        return fail(QMG_ERR_PREC, "transfer_create: storage %d not supported", (int)storage);
+        return fail(QMG_ERR_PREC, "%s: storage %d not supported", what, (int)storage);
     int cd[4];
     int64_t bs = 1;
     for (int m = 0; m < 4; ++m) {
         if (block[m] < 1 || fine_dims[m] % block[m])
-            return fail(QMG_ERR_SHAPE, "transfer_create: block %d does not divide extent %d (dim %d)",
-                        block[m], fine_dims[m], m);
+            return fail(QMG_ERR_SHAPE, "%s: block %d does not divide extent %d (dim %d)", what, block[m],
+                        fine_dims[m], m);
         cd[m] = fine_dims[m] / block[m];
-        if (cd[m] < 2) return fail(QMG_ERR_SHAPE, "transfer_create: coarse extent %d < 2 in dim %d", cd[m], m);
+        if (cd[m] < 2) return fail(QMG_ERR_SHAPE, "%s: coarse extent %d < 2 in dim %d", what, cd[m], m);
         bs *= block[m];
     }
     if ((int64_t)nvec > bs * (fine_dof / 2))
-        return fail(QMG_ERR_SHAPE, "transfer_create: nvec %d exceeds aggregate dimension %lld", nvec,
+        return fail(QMG_ERR_SHAPE, "%s: nvec %d exceeds aggregate dimension %lld", what, nvec,
                     (long long)(bs * (fine_dof / 2)));
-    hipStream_t s = as_stream(stream);
     auto* t = new qmg_transfer_s();
     for (int m = 0; m < 4; ++m) { t->fdims[m] = fine_dims[m]; t->block[m] = block[m]; t->cdims[m] = cd[m]; }
     t->V = volume(fine_dims);
@@ -334,17 +334,52 @@ extern "C" qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, 
         members[xc * bs + fill[xc]++] = (int)i;
     }
     const size_t nb = (size_t)t->V * fine_dof * nvec;
-    const int64_t Lb = bs * (fine_dof / 2);
-    const size_t wbytes = sizeof(double2) * (size_t)t->Vc * 2 * nvec * Lb;
-    double2* W = nullptr;
-    int* flag = nullptr;
     hipError_t e = hipMalloc(&t->members, sizeof(int) * t->V);
     if (e == hipSuccess) e = hipMalloc(&t->owner, sizeof(int) * t->V);
     if (e == hipSuccess) e = hipMalloc(&t->basis64, sizeof(double2) * nb);
-    if (e == hipSuccess) e = hipMalloc(&W, wbytes);
-    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int));
     if (e == hipSuccess) e = hipMemcpyAsync(t->members, members.data(), sizeof(int) * t->V, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(t->owner, owner.data(), sizeof(int) * t->V, hipMemcpyHostToDevice, s);
+    // the host tables are released on return: the copies must have landed
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        qmg_transfer_destroy(t);
+        return fail(e == hipErrorOutOfMemory ? QMG_ERR_NOMEM : QMG_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    }
+    *out = t;
+    return QMG_OK;
+}
+
+// The storage-precision copy of the FP64 basis (the same buffer for QMG_C128).
+qmg_status transfer_finish(const char* what, qmg_transfer_s* t, hipStream_t s) {
+    const size_t nb = (size_t)t->V * t->dof * t->nvec;
+    if (t->storage == QMG_C128) {
+        t->basis = t->basis64;
+        return QMG_OK;
+    }
+    const hipError_t e = hipMalloc(&t->basis, sizeof(float2) * nb);
+    if (e != hipSuccess) return fail(QMG_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
+    hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (float2*)t->basis, t->basis64,
+                       (int64_t)nb);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+}  // namespace
+
+extern "C" qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, const int block[4],
+                                          int nvec, const void* nullvecs, qmg_prec storage,
+                                          void* stream, qmg_transfer* out) {
+    if (!out) return fail(QMG_ERR_ARG, "transfer_create: out is NULL");
+    *out = nullptr;
+    hipStream_t s = as_stream(stream);
+    qmg_transfer_s* t = nullptr;
+    QMG_TRY(transfer_shell("transfer_create", fine_dims, fine_dof, block, nvec, nullvecs, storage, s, &t));
+    const int64_t Lb = (int64_t)t->bsites * (fine_dof / 2);
+    const size_t wbytes = sizeof(double2) * (size_t)t->Vc * 2 * nvec * Lb;
+    double2* W = nullptr;
+    int* flag = nullptr;
+    hipError_t e = hipMalloc(&W, wbytes);
+    if (e == hipSuccess) e = hipMalloc(&flag, sizeof(int));
     if (e == hipSuccess) e = hipMemsetAsync(flag, 0, sizeof(int), s);
     if (e != hipSuccess) {
         if (W) (void)hipFree(W);
@@ -373,17 +408,31 @@ extern "C" qmg_status qmg_transfer_create(const int fine_dims[4], int fine_dof, 
         qmg_transfer_destroy(t);
         return fail(QMG_ERR_ARG, "transfer_create: near-null vectors are linearly dependent within an aggregate");
     }
-    if (storage == QMG_C128) {
-        t->basis = t->basis64;
-    } else {
-        e = hipMalloc(&t->basis, sizeof(float2) * nb);
-        if (e != hipSuccess) {
-            qmg_transfer_destroy(t);
-            return fail(QMG_ERR_NOMEM, "transfer_create: %s", hipGetErrorString(e));
-        }
-        hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (float2*)t->basis,
-                           t->basis64, (int64_t)nb);
-        QMG_LAUNCH_CHECK();
+    const qmg_status st = transfer_finish("transfer_create", t, s);
+    if (st != QMG_OK) {
+        qmg_transfer_destroy(t);
+        return st;
+    }
+    *out = t;
+    return QMG_OK;
+}
+
+extern "C" qmg_status qmg_transfer_import(const int fine_dims[4], int fine_dof, const int block[4], int nvec,
+                                          const void* basis, qmg_prec storage, void* stream, qmg_transfer* out) {
+    if (!out) return fail(QMG_ERR_ARG, "transfer_import: out is NULL");
+    *out = nullptr;
+    hipStream_t s = as_stream(stream);
+    qmg_transfer_s* t = nullptr;
+    QMG_TRY(transfer_shell("transfer_import", fine_dims, fine_dof, block, nvec, basis, storage, s, &t));
+    qmg_status st = QMG_OK;
+    if (hipMemcpyAsync(t->basis64, basis, sizeof(double2) * (size_t)t->V * fine_dof * nvec, hipMemcpyDeviceToDevice,
+                       s) != hipSuccess)
+        st = fail(QMG_ERR_HIP, "transfer_import: basis copy failed");
+    if (st == QMG_OK) st = transfer_finish("transfer_import", t, s);
+    if (st == QMG_OK && hipStreamSynchronize(s) != hipSuccess) st = fail(QMG_ERR_HIP, "transfer_import: sync");
+    if (st != QMG_OK) {
+        qmg_transfer_destroy(t);
+        return st;
     }
     *out = t;
     return QMG_OK;
