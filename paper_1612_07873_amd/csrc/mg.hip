@@ -99,6 +99,7 @@ struct Level {
     void *sb = nullptr, *sx = nullptr, *sr = nullptr, *sAr = nullptr;  // Schur MR smoother
     void *etmp = nullptr;   // odd half-lattice scratch of the Schur operator
     void *ekin = nullptr;   // level 0: inner-precision half field of the outer solve
+    int small_steps[2] = {0, 0};   // steps of the last single-work-group GCR solve (whole, Schur system)
 };
 
 }  // namespace
@@ -159,12 +160,13 @@ constexpr int S_BETA = 0;     // 32 doubles (16 complex)
 constexpr int S_GCR = 32;     // 3
 constexpr int S_NRM = 36;     // 1
 constexpr int S_MR = 40;      // 3
-constexpr int S_BN = 44;      // 1
+constexpr int S_BN = 44;      // 4: |b|^2 of the GCR on level l in slot S_BN + l (nested solves keep theirs)
 constexpr int S_SM = 48;      // 3: learned-smoother step scalars
 constexpr int S_OK = 52;      // 3: single-work-group GCR steps: stopping-test flags (two parities), steps done
 constexpr int S_QQ = 56;      // 1: outer GCR: |q|^2 before the projection
 constexpr int S_FB = 57;      // 1: network steps refused on the device (learned smoother followed by MR)
-constexpr int kCheck = 4;     // such steps queued per host read of the scalars
+constexpr int kCheck = 4;     // such steps queued before the first host read of the scalars (at least)
+constexpr int kRecheck = 2;   // and between later reads
 
 size_t cbytes(qmg_prec p) { return p == QMG_C128 ? 16 : 8; }
 
@@ -390,10 +392,11 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
     const int nb = mg->nb;
     const size_t vb = n * sizeof(cpx<R>);   // one member's field
     const size_t bb = nb * vb;              // the batch's field (one Krylov direction of all members)
+    // |b|^2 stays on the device (the single-work-group step takes its stopping
+    // test from it); the host reads it with the first step's scalars
     double bnorm[Blas::kMaxBatch];
-    QMG_TRY(mg->blas.norm2<R>(b, n, mg->dsc + S_BN));
-    QMG_TRY(read_scalars(mg, S_BN, 1));
-    for (int k = 0; k < nb; ++k) bnorm[k] = std::sqrt(hs(mg, k, S_BN));
+    const int sbn = S_BN + l;
+    QMG_TRY(mg->blas.norm2<R>(b, n, mg->dsc + sbn));
     if (x0) {
         QMG_TRY(apply_sys<R>(mg, sy, x, sy.t));
         QMG_TRY(mg->blas.xmy<R>(b, sy.t, sy.r, n));
@@ -430,6 +433,13 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
     if (small)   // stopping-test flags and step counters of every member
         QMG_HIP(hipMemset2DAsync(mg->dsc + S_OK, sizeof(double) * kScal, 0, 3 * sizeof(double), nb, mg->s));
     int launches = 0;   // single-work-group steps queued: the flags of the last one are in slot S_OK + (launches & 1)
+    // Single-work-group steps: a step queued after every member has passed its
+    // test does nothing, so steps are queued ahead of the host's reads of the
+    // scalars, across restarts: the first read comes a few steps before the
+    // step count of this level's previous solve, then one every kRecheck steps
+    // (with tol = 0, only at maxit).  Reads never change the iterates.
+    int& expect = L.small_steps[sy.schur ? 1 : 0];
+    int next_read = defer ? maxit : std::max(kCheck, expect - 3);
     while (!done && iters < maxit) {
         int j = 0;
         if (small) QMG_HIP(hipMemcpyAsync(sy.Z, sy.r, bb, hipMemcpyDeviceToDevice, mg->s));
@@ -440,15 +450,15 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
             if (small) {
                 // the step evaluates the stopping test itself (a step queued
                 // after every member has passed it does nothing), so the
-                // scalars are read every kCheck steps and at the end of a cycle
+                // scalars are read only when next_read is reached
                 QMG_TRY(apply_sys<R>(mg, sy, z, q));
                 void* znext = j + 1 < m ? (char*)sy.Z + (j + 1) * bb : nullptr;
                 QMG_TRY(mg->blas.gcr_step_small<R>(sy.Q, sy.Z, ld, j, q, z, x, sy.r, n, mg->dsc + S_GCR, znext,
-                                                   tol > 0.0 ? tol : 0.0, S_OK - S_GCR, S_BN - S_GCR,
+                                                   tol > 0.0 ? tol : 0.0, S_OK - S_GCR, sbn - S_GCR,
                                                    launches & 1));
                 ++launches;
                 ++iters;
-                if ((defer || iters % kCheck) && j + 1 < m && iters < maxit) continue;
+                if (iters < next_read && iters < maxit) continue;
                 QMG_TRY(read_scalars(mg, S_GCR, S_OK + 3 - S_GCR));
                 iters = (int)hs(mg, 0, S_OK + 2);   // steps that ran (the same for every member)
                 done = true;
@@ -458,6 +468,7 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
                 }
                 if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
                 if (done) { ++j; break; }
+                next_read = iters + kRecheck;
                 continue;
             }
             if (precond) QMG_TRY(precond_sys<R>(mg, sy, sy.r, z));
@@ -469,7 +480,8 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
             ++iters;
             if (defer && j + 1 < m && iters < maxit) continue;
             QMG_TRY(mg->blas.norm2<R>(sy.r, n, mg->dsc + S_NRM));
-            QMG_TRY(read_scalars(mg, S_GCR, 5));
+            QMG_TRY(read_scalars(mg, S_GCR, sbn + 1 - S_GCR));
+            for (int k = 0; k < nb; ++k) bnorm[k] = std::sqrt(hs(mg, k, sbn));
             done = all_done(S_NRM, &fault);
             if (fault) return fail(QMG_ERR_NONFINITE, "gcr on level %d: non-finite residual after %d steps", l, iters);
             if (done) { ++j; break; }
@@ -479,6 +491,7 @@ qmg_status gcr(qmg_mg_s* mg, const Sys& sy, const void* b, void* x, bool x0, dou
         QMG_TRY(apply_sys<R>(mg, sy, x, sy.t));
         QMG_TRY(mg->blas.xmy<R>(b, sy.t, sy.r, n));
     }
+    if (small && !defer) expect = iters;
     if (iters_out) *iters_out += iters;
     return QMG_OK;
 }
