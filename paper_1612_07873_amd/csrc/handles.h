@@ -40,12 +40,21 @@ struct qmg_fine_op_s {
                  // (16-bit storages: [2][18][V] pairs of those reals)
     float* cscale;  // [2][V] clover scales of the 16-bit storages, else NULL
     int* nbr;    // [V][8]
-    // red-black form (every extent even): inverse of the site-local block
-    // (4 + m0 + A(x))^-1 in the clover's packed layout and storage, and the
-    // lattice index of every half-lattice site of each parity [2][V/2]
+    // red-black form (every extent even): the lattice index of every
+    // half-lattice site of each parity, hsite [2][V/2] ("parity order":
+    // index p*V/2 + h is site hsite[p*V/2 + h]); the inverse of the site-local
+    // block (4 + m0 + A(x))^-1 in the clover's packed layout and storage, in
+    // parity order; parity-order copies of the links, the clover term and its
+    // scales, and the neighbour table hnb [V][8] in parity order (lattice
+    // indices of the neighbours), so that a red-black kernel over the sites of
+    // one parity reads each of them contiguously
     void* cinv = nullptr;
     float* ciscale = nullptr;
     int* hsite = nullptr;
+    void* U_eo = nullptr;
+    void* clov_eo = nullptr;
+    float* cscale_eo = nullptr;
+    int* hnb = nullptr;
     void* eo_tmp = nullptr;    // half-lattice scratch of the Schur entry points (grown on demand)
     size_t eo_tmp_bytes = 0;
     int link_reals = 18;       // 18, or 12: links stored as rows 0 and 1, [4][6][V], row 2 rebuilt

@@ -279,62 +279,112 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
 // because x0 runs fastest and L0 is even.  self and out are half-lattice
 // fields, or whole-lattice ones indexed by x (self_full, out_full).
 // Member b of a batch (grid dimension y) finds its fields at b*V/2 (half) or
-// b*V (whole) sites.
-template <int LF, int VF, int SELF, bool HOPS, bool INV, int LR = 18>
-__global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, const void* __restrict__ clov,
-                                                   const float* __restrict__ cscale, const void* __restrict__ cinv,
-                                                   const float* __restrict__ ciscale, const int* __restrict__ nbr,
-                                                   const int* __restrict__ hsite, const void* __restrict__ self,
-                                                   const void* __restrict__ hin, void* __restrict__ out, int64_t Vh,
-                                                   int64_t V, typename FineT<LF>::R diag, typename FineT<LF>::R coef,
-                                                   int use_clover, int self_full, int out_full, int64_t last) {
-    using R = typename FineT<LF>::R;
-    // XCD-contiguous work-group numbering, as in k_wilson_clover (grid a multiple of 8)
-    const int64_t per = gridDim.x >> 3;
-    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int64_t h = wg * blockDim.x + threadIdx.x;
-    if (h >= Vh) return;
-    const int64_t site = hsite[h];
-    const int64_t vh = (int64_t)blockIdx.y * Vh, vf = (int64_t)blockIdx.y * V;
-    cpx<R> acc[12];
+// b*V (whole) sites.  Links, clover, inverse and neighbour table are read in
+// their parity-order copies: the thread of site x (parity p, half index h)
+// finds its own entries at p*V/2 + h and a neighbour y's link at
+// (1-p)*V/2 + (y >> 1), so every wave reads them contiguously, and each link
+// is read once per launch (non-temporal: forward links of this parity,
+// backward links of the other).
+// The site-local part of a red-black piece: acc = 0 (SELF 0), self (1) or
+// C(x) self (2); the clover term in parity order at index ie.
+template <int LF, int VF, int SELF, typename R>
+__device__ __forceinline__ void eo_self_terms(cpx<R> acc[12], const void* __restrict__ self, int64_t si, R diag,
+                                              int use_clover, const void* __restrict__ clov,
+                                              const float* __restrict__ cscale, int64_t ie, int64_t V) {
     if constexpr (SELF == 0) {
 #pragma unroll
         for (int f = 0; f < 12; ++f) acc[f] = {R(0), R(0)};
     } else {
         cpx<R> p[12];
-        load_spinor<VF>(p, self, nullptr, self_full ? site + vf : h + vh);
+        load_spinor<VF>(p, self, nullptr, si);
         if constexpr (SELF == 1) {
 #pragma unroll
             for (int f = 0; f < 12; ++f) acc[f] = p[f];
         } else {
 #pragma unroll
             for (int f = 0; f < 12; ++f) acc[f] = {diag * p[f].re, diag * p[f].im};
-            if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, site, V);
+            if (use_clover) herm_mul_add<LF>(acc, p, clov, cscale, ie, V);
         }
     }
+}
+
+template <int LF, int VF, int SELF, bool HOPS, bool INV, int LR = 18>
+__global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, const void* __restrict__ clov,
+                                                   const float* __restrict__ cscale, const void* __restrict__ cinv,
+                                                   const float* __restrict__ ciscale, const int* __restrict__ hnb,
+                                                   const int* __restrict__ hsite, const void* __restrict__ self,
+                                                   const void* __restrict__ hin, void* __restrict__ out, int64_t Vh,
+                                                   int64_t V, typename FineT<LF>::R diag, typename FineT<LF>::R coef,
+                                                   int use_clover, int self_full, int out_full, int64_t last,
+                                                   int parity) {
+    using R = typename FineT<LF>::R;
+    // XCD-contiguous work-group numbering, as in k_wilson_clover (grid a multiple of 8)
+    const int64_t per = gridDim.x >> 3;
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t h = wg * blockDim.x + threadIdx.x;
+    if (h >= Vh) return;
+    const int64_t ie = (int64_t)parity * Vh + h;       // this site in parity order
+    const int64_t io = (int64_t)(1 - parity) * Vh;     // start of the other parity
+    const int64_t site = hsite[ie];
+    const int64_t vh = (int64_t)blockIdx.y * Vh, vf = (int64_t)blockIdx.y * V;
+    cpx<R> acc[12];
     if constexpr (HOPS) {
-        const int* nb = nbr + site * 8;
+        const int4* nb4 = reinterpret_cast<const int4*>(hnb + ie * 8);
+        const int4 na = nb4[0], nc = nb4[1];
+        const int nb[8] = {na.x, na.y, na.z, na.w, nc.x, nc.y, nc.z, nc.w};
         const R c = R(-0.5) * coef;
-        cpx<R> p[12], u[9];
-#define QMG_EO_HOP(MU, BACK, D)                                              \
-        load_spinor<VF>(p, hin, nullptr, (int64_t)(nb[D] >> 1) + vh);         \
-        load_link<LF, LR>(u, U, MU, BACK ? (int64_t)nb[D] : site, V, last);  \
-        hop_apply<MU, BACK>(acc, p, u, c);
-        QMG_EO_HOP(0, false, 0)
-        QMG_EO_HOP(0, true, 1)
-        QMG_EO_HOP(1, false, 2)
-        QMG_EO_HOP(1, true, 3)
-        QMG_EO_HOP(2, false, 4)
-        QMG_EO_HOP(2, true, 5)
-        QMG_EO_HOP(3, false, 6)
-        QMG_EO_HOP(3, true, 7)
+#define QMG_EO_LOAD(P, UU, MU, BACK, D)                                                               \
+        load_spinor<VF>(P, hin, nullptr, (int64_t)(nb[D] >> 1) + vh);                                  \
+        load_link_at<LF, LR, true>(UU, U, MU, BACK ? io + (nb[D] >> 1) : ie, V,                        \
+                                   MU == 3 && (BACK ? (int64_t)nb[D] : site) >= last);
+        if constexpr (sizeof(R) == 4) {
+            // FP32 arithmetic: the next two hops' operands are in flight while
+            // two are applied; the site-local part runs under the first loads
+            // (9-10 % faster than one hop at a time on 16^3x32 and 32^3x64
+            // with 18-real links, 1-2 % with 12-real ones; with a register cap
+            // of four waves per SIMD both forms spill and are slower)
+            cpx<R> pa[12], ua[9], pb[12], ub[9];
+            QMG_EO_LOAD(pa, ua, 0, false, 0)
+            QMG_EO_LOAD(pb, ub, 0, true, 1)
+            eo_self_terms<LF, VF, SELF>(acc, self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale, ie, V);
+            hop_apply<0, false>(acc, pa, ua, c);
+            QMG_EO_LOAD(pa, ua, 1, false, 2)
+            hop_apply<0, true>(acc, pb, ub, c);
+            QMG_EO_LOAD(pb, ub, 1, true, 3)
+            hop_apply<1, false>(acc, pa, ua, c);
+            QMG_EO_LOAD(pa, ua, 2, false, 4)
+            hop_apply<1, true>(acc, pb, ub, c);
+            QMG_EO_LOAD(pb, ub, 2, true, 5)
+            hop_apply<2, false>(acc, pa, ua, c);
+            QMG_EO_LOAD(pa, ua, 3, false, 6)
+            hop_apply<2, true>(acc, pb, ub, c);
+            QMG_EO_LOAD(pb, ub, 3, true, 7)
+            hop_apply<3, false>(acc, pa, ua, c);
+            hop_apply<3, true>(acc, pb, ub, c);
+        } else {
+            // FP64: one hop at a time (registers)
+            eo_self_terms<LF, VF, SELF>(acc, self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale, ie, V);
+            cpx<R> p[12], u[9];
+#define QMG_EO_HOP(MU, BACK, D) QMG_EO_LOAD(p, u, MU, BACK, D) hop_apply<MU, BACK>(acc, p, u, c);
+            QMG_EO_HOP(0, false, 0)
+            QMG_EO_HOP(0, true, 1)
+            QMG_EO_HOP(1, false, 2)
+            QMG_EO_HOP(1, true, 3)
+            QMG_EO_HOP(2, false, 4)
+            QMG_EO_HOP(2, true, 5)
+            QMG_EO_HOP(3, false, 6)
+            QMG_EO_HOP(3, true, 7)
 #undef QMG_EO_HOP
+        }
+#undef QMG_EO_LOAD
+    } else {
+        eo_self_terms<LF, VF, SELF>(acc, self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale, ie, V);
     }
     if constexpr (INV) {
         cpx<R> t[12];
 #pragma unroll
         for (int f = 0; f < 12; ++f) t[f] = {R(0), R(0)};
-        herm_mul_add<LF>(t, acc, cinv, ciscale, site, V);
+        herm_mul_add<LF>(t, acc, cinv, ciscale, ie, V);
         store_spinor<VF>(out, nullptr, out_full ? site + vf : h + vh, t);
     } else {
         store_spinor<VF>(out, nullptr, out_full ? site + vf : h + vh, acc);
@@ -503,6 +553,24 @@ __global__ void k_clover_invert(double* __restrict__ cinv, const double* __restr
 __global__ void k_real_to_f32(float* __restrict__ out, const double* __restrict__ in, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) out[i] = (float)in[i];
+}
+
+// Parity-order copy of a [K][V] array of W-sized elements: dst[k][j] =
+// src[k][hsite[j]], hsite [V] holding the lattice index of parity-order index j.
+template <typename W>
+__global__ void k_to_parity_order(W* __restrict__ dst, const W* __restrict__ src, const int* __restrict__ hsite,
+                                  int64_t K, int64_t V) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= K * V) return;
+    const int64_t k = i / V, j = i - k * V;
+    dst[i] = src[k * V + hsite[j]];
+}
+// hnb[j][d] = nbr[hsite[j]][d]: the neighbour table in parity order
+__global__ void k_nbr_parity_order(int* __restrict__ hnb, const int* __restrict__ nbr, const int* __restrict__ hsite,
+                                   int64_t V) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= V * 8) return;
+    hnb[i] = nbr[(int64_t)hsite[i >> 3] * 8 + (i & 7)];
 }
 
 template <int LF>
@@ -727,14 +795,13 @@ static qmg_status launch_eo(const qmg_fine_op_s* op, int piece, int parity, cons
     using R = typename FineT<LF>::R;
     const int64_t Vh = op->V / 2;
     const unsigned nb = (unsigned)(((Vh + 255) / 256 + 7) / 8 * 8);
-    const int* hs = op->hsite + parity * Vh;
     const R diag = (R)(4.0 + op->m0);
     const int uc = op->csw != 0.0 ? 1 : 0;
     const dim3 grid(nb, (unsigned)m), block(256);
 #define QMG_EO_LAUNCH_LR(SELF, HOPS, INV, COEF, LR)                                                              \
-    hipLaunchKernelGGL((k_wilson_eo<LF, VF, SELF, HOPS, INV, LR>), grid, block, 0, s, op->U, op->clov,          \
-                       op->cscale, op->cinv, op->ciscale, op->nbr, hs, self, hin, out, Vh, op->V, diag, (R)(COEF), \
-                       uc, self_full, out_full, op->last)
+    hipLaunchKernelGGL((k_wilson_eo<LF, VF, SELF, HOPS, INV, LR>), grid, block, 0, s, op->U_eo, op->clov_eo,    \
+                       op->cscale_eo, op->cinv, op->ciscale, op->hnb, op->hsite, self, hin, out, Vh, op->V, diag,  \
+                       (R)(COEF), uc, self_full, out_full, op->last, parity)
 #define QMG_EO_LAUNCH(SELF, HOPS, INV, COEF)                                                                    \
     do {                                                                                                        \
         if constexpr (LF != FMT_F64 && HOPS) {                                                                  \
@@ -828,6 +895,10 @@ extern "C" void qmg_fine_op_destroy(qmg_fine_op op) {
     if (op->cinv) (void)hipFree(op->cinv);
     if (op->ciscale) (void)hipFree(op->ciscale);
     if (op->hsite) (void)hipFree(op->hsite);
+    if (op->U_eo) (void)hipFree(op->U_eo);
+    if (op->clov_eo) (void)hipFree(op->clov_eo);
+    if (op->cscale_eo) (void)hipFree(op->cscale_eo);
+    if (op->hnb) (void)hipFree(op->hnb);
     if (op->eo_tmp) (void)hipFree(op->eo_tmp);
     delete op;
 }
@@ -947,7 +1018,58 @@ extern "C" qmg_status qmg_fine_op_create_ex(const int dims[4], const void* gauge
         if (c64) (void)hipFree(c64);
         if (i64) (void)hipFree(i64);
     }
-    e = hipGetLastError();
+    const hipError_t le = hipGetLastError();
+    if (eo && le == hipSuccess) {
+        // parity-order copies for the red-black kernels; the inverse of the
+        // site-local block is kept in parity order only
+        const int64_t V = op->V;
+        const int lb = storage == QMG_C128 ? 16 : storage == QMG_C64 ? 8 : 4;   // bytes per stored link entry
+        const int64_t lk = 4 * ne;                                              // link entries per site
+        const int cb = is16p(storage) ? 4 : (int)rb;                            // bytes per clover element
+        const int64_t ck = is16p(storage) ? 36 : 72;                            // clover elements per site
+        void *ci = nullptr, *cis = nullptr;
+        e = hipMalloc(&op->U_eo, (size_t)lb * lk * V);
+        if (e == hipSuccess) e = hipMalloc(&op->clov_eo, (size_t)cb * ck * V);
+        if (e == hipSuccess) e = hipMalloc(&op->hnb, sizeof(int) * 8 * V);
+        if (e == hipSuccess) e = hipMalloc(&ci, (size_t)cb * ck * V);
+        if (e == hipSuccess && is16p(storage)) e = hipMalloc(&op->cscale_eo, sizeof(float) * 2 * V);
+        if (e == hipSuccess && is16p(storage)) e = hipMalloc(&cis, sizeof(float) * 2 * V);
+        if (e != hipSuccess) {
+            if (ci) (void)hipFree(ci);
+            if (cis) (void)hipFree(cis);
+            qmg_fine_op_destroy(op);
+            return fail(QMG_ERR_NOMEM, "fine_op_create: red-black copies: %s", hipGetErrorString(e));
+        }
+        auto permute = [&](void* dst, const void* src, int64_t K, int eb) {
+            const unsigned g = (unsigned)((K * V + 255) / 256);
+            if (eb == 16)
+                hipLaunchKernelGGL(k_to_parity_order<uint4>, dim3(g), dim3(256), 0, s, (uint4*)dst, (const uint4*)src,
+                                   op->hsite, K, V);
+            else if (eb == 8)
+                hipLaunchKernelGGL(k_to_parity_order<uint2>, dim3(g), dim3(256), 0, s, (uint2*)dst, (const uint2*)src,
+                                   op->hsite, K, V);
+            else
+                hipLaunchKernelGGL(k_to_parity_order<uint32_t>, dim3(g), dim3(256), 0, s, (uint32_t*)dst,
+                                   (const uint32_t*)src, op->hsite, K, V);
+        };
+        permute(op->U_eo, op->U, lk, lb);
+        permute(op->clov_eo, op->clov, ck, cb);
+        permute(ci, op->cinv, ck, cb);
+        if (is16p(storage)) {
+            permute(op->cscale_eo, op->cscale, 2, 4);
+            permute(cis, op->ciscale, 2, 4);
+        }
+        hipLaunchKernelGGL(k_nbr_parity_order, dim3((unsigned)((8 * V + 255) / 256)), dim3(256), 0, s, op->hnb,
+                           op->nbr, op->hsite, V);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(op->cinv);
+        op->cinv = ci;
+        if (is16p(storage)) {
+            (void)hipFree(op->ciscale);
+            op->ciscale = (float*)cis;
+        }
+    }
+    e = le != hipSuccess ? le : hipGetLastError();
     if (e != hipSuccess) {
         qmg_fine_op_destroy(op);
         return fail(QMG_ERR_HIP, "fine_op_create: launch: %s", hipGetErrorString(e));

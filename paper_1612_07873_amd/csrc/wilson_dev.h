@@ -55,21 +55,36 @@ template <int F> constexpr bool is16f() { return F == FMT_H16 || F == FMT_B16; }
 // cross product of the other two: c = conj(a x b).  The antiperiodic time
 // sign is folded into the stored rows, and the rebuilt row takes it from the
 // link's position (mu = 3 on the last time slice, ls >= last).
-template <int LF, int LR = 18, typename R>
-__device__ __forceinline__ void load_link(cpx<R> u[9], const void* __restrict__ U, int mu, int64_t ls, int64_t V,
-                                          int64_t last = 0) {
+// load_link_at reads the link stored at index `idx` of a [4][ne][V] array
+// (lattice order, or the red-black copy in parity order) and takes the time
+// sign of a rebuilt row from `neg`; NT marks a once-per-application read.
+template <int LF, int LR = 18, bool NT = false, typename R>
+__device__ __forceinline__ void load_link_at(cpx<R> u[9], const void* __restrict__ U, int mu, int64_t idx, int64_t V,
+                                             bool neg) {
     constexpr int ne = LR == 12 ? 6 : 9;
     if constexpr (is16f<LF>()) {
         const uint32_t* W = static_cast<const uint32_t*>(U);
 #pragma unroll
-        for (int e = 0; e < ne; ++e) u[e] = dec_pair<LF>(W[((int64_t)mu * ne + e) * V + ls]);
+        for (int e = 0; e < ne; ++e) {
+            const uint32_t* a = W + ((int64_t)mu * ne + e) * V + idx;
+            u[e] = dec_pair<LF>(NT ? __builtin_nontemporal_load(a) : *a);
+        }
     } else {
         const cpx<R>* P = static_cast<const cpx<R>*>(U);
 #pragma unroll
-        for (int e = 0; e < ne; ++e) u[e] = P[((int64_t)mu * ne + e) * V + ls];
+        for (int e = 0; e < ne; ++e) {
+            const cpx<R>* a = P + ((int64_t)mu * ne + e) * V + idx;
+            if constexpr (NT) {
+                typedef R v2 __attribute__((ext_vector_type(2)));   // one 8- or 16-byte load (elements are so aligned)
+                const v2 v = __builtin_nontemporal_load(reinterpret_cast<const v2*>(a));
+                u[e] = cpx<R>{v.x, v.y};
+            } else {
+                u[e] = *a;
+            }
+        }
     }
     if constexpr (LR == 12) {
-        const R sg = (mu == 3 && ls >= last) ? R(-1) : R(1);
+        const R sg = neg ? R(-1) : R(1);
 #pragma unroll
         for (int j = 0; j < 3; ++j) {
             const int k = (j + 1) % 3, l = (j + 2) % 3;
@@ -79,6 +94,12 @@ __device__ __forceinline__ void load_link(cpx<R> u[9], const void* __restrict__ 
             u[6 + j] = cpx<R>{sg * re, -sg * im};
         }
     }
+}
+
+template <int LF, int LR = 18, typename R>
+__device__ __forceinline__ void load_link(cpx<R> u[9], const void* __restrict__ U, int mu, int64_t ls, int64_t V,
+                                          int64_t last = 0) {
+    load_link_at<LF, LR, false>(u, U, mu, ls, V, mu == 3 && ls >= last);
 }
 
 // One chirality block of the clover term: 6 diagonal reals, 15 upper entries.
