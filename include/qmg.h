@@ -386,8 +386,10 @@ qmg_status qmg_wilson_clover_schur_noalloc(qmg_fine_op op, const void* in_e, voi
 /* Build P from DEVICE near-null vectors nullvecs [nvec][V][fine_dof]
  * complex128 (fine_dof = 12 on the fine lattice, the parent's N on a coarse
  * one).  block must divide fine_dims with every coarse extent >= 2.  The
- * orthonormalisation runs in FP64; storage (QMG_C128 or QMG_C64) is the
- * precision prolong/restrict use for complex64 fields.  Blocks this call
+ * orthonormalisation runs in FP64; storage (QMG_C128, QMG_C64, or QMG_H16:
+ * FP16 pairs with no scale, the entries being at most 1 in modulus) is the
+ * basis prolong/restrict use for complex64 fields (complex128 fields always
+ * use the FP64 basis).  Blocks this call
  * until the basis is built (it checks the rank on the host): returns
  * QMG_ERR_ARG if a vector is linearly dependent (relative residual norm
  * < 1e-10) on some aggregate. */
@@ -456,6 +458,11 @@ typedef struct {
                             in FP64 (at most 4096 coarsest unknowns) and applied in the inner
                             precision, instead of the paper's GCR (coarse_tol/coarse_maxit are
                             then unused); 0 = GCR */
+    int transfer_storage; /* storage of this level's transfer basis for the solve's prolongation and
+                            restriction: 0 = the inner precision, QMG_H16 = FP16 pairs with no
+                            scale (entries of a block-orthonormal basis are at most 1 in modulus;
+                            inner precision must be QMG_C64); the Galerkin build always uses the
+                            FP64 basis */
 } qmg_level_params;
 
 typedef struct {

@@ -495,7 +495,8 @@ class Multigrid:
 
     levels: list of dicts with keys block, nvec, setup_iters, smoother_steps,
     coarse_tol, coarse_maxit and optionally coarse_storage ('h16' / 'b16': the
-    next level's operator in 16-bit storage during the solve) and, on the last
+    next level's operator in 16-bit storage during the solve), transfer_storage
+    ('h16': the level's transfer basis as FP16 pairs in the solve) and, on the last
     entry, coarse_direct (exact coarsest solve by a dense inverse), one per
     coarsened level; starts: list of device complex128 tensors
     [nvec_l][V_l][dof_l]; fine_storage: None or 'h16' / 'b16' for the fine
@@ -524,6 +525,7 @@ class Multigrid:
             lp[i].coarse_maxit = int(L.get('coarse_maxit', 10))
             lp[i].coarse_storage = PREC[L['coarse_storage']] if L.get('coarse_storage') else 0
             lp[i].coarse_direct = int(bool(L.get('coarse_direct', False)))
+            lp[i].transfer_storage = PREC[L['transfer_storage']] if L.get('transfer_storage') else 0
         vecs, what = (starts, 'starts') if bases is None else (bases, 'bases')
         ptrs = (ctypes.c_void_p * max(1, len(vecs)))()
         for i, t in enumerate(vecs):

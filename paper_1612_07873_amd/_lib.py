@@ -78,7 +78,7 @@ SIGNATURES = {
 class LevelParams(ctypes.Structure):
     _fields_ = [('block', c_int * 4), ('nvec', c_int), ('setup_iters', c_int), ('smoother_steps', c_int),
                 ('coarse_tol', c_double), ('coarse_maxit', c_int), ('coarse_storage', c_int),
-                ('coarse_direct', c_int)]
+                ('coarse_direct', c_int), ('transfer_storage', c_int)]
 
 
 class SolveParams(ctypes.Structure):

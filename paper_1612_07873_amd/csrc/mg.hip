@@ -634,6 +634,11 @@ qmg_status workspace(qmg_mg_s* mg, int cap) {
     return QMG_OK;
 }
 
+// storage of level L's transfer basis in the solve
+qmg_prec transfer_prec(const qmg_mg_s* mg, const Level& L) {
+    return L.p.transfer_storage ? (qmg_prec)L.p.transfer_storage : mg->inner;
+}
+
 // near-null vectors of level l -> transfer and next coarse operator
 template <typename R>
 qmg_status setup_level(qmg_mg_s* mg, int l, const void* starts, int setup_iters) {
@@ -665,7 +670,7 @@ qmg_status setup_level(qmg_mg_s* mg, int l, const void* starts, int setup_iters)
     }
     if (st == QMG_OK) st = mg->blas.convert<R, double>(NV, NV64, n * nvec);
     if (st == QMG_OK)
-        st = qmg_transfer_create(L.dims, L.dof, L.p.block, nvec, NV64, mg->inner, mg->s, &L.T);
+        st = qmg_transfer_create(L.dims, L.dof, L.p.block, nvec, NV64, transfer_prec(mg, L), mg->s, &L.T);
     if (st == QMG_OK) {
         Level& C = mg->lv[l + 1];
         if (l == 0) st = qmg_build_coarse_op(L.T, mg->fine64, nullptr, mg->inner, mg->s, &C.op);
@@ -681,7 +686,7 @@ qmg_status setup_level(qmg_mg_s* mg, int l, const void* starts, int setup_iters)
 // next coarse operator exactly as setup_level builds it
 qmg_status import_level(qmg_mg_s* mg, int l, const void* basis) {
     Level& L = mg->lv[l];
-    QMG_TRY(qmg_transfer_import(L.dims, L.dof, L.p.block, L.p.nvec, basis, mg->inner, mg->s, &L.T));
+    QMG_TRY(qmg_transfer_import(L.dims, L.dof, L.p.block, L.p.nvec, basis, transfer_prec(mg, L), mg->s, &L.T));
     Level& C = mg->lv[l + 1];
     const qmg_status st = l == 0 ? qmg_build_coarse_op(L.T, mg->fine64, nullptr, mg->inner, mg->s, &C.op)
                                  : qmg_build_coarse_op(L.T, nullptr, L.op, mg->inner, mg->s, &C.op);
@@ -900,6 +905,11 @@ static qmg_status mg_make(const int dims[4], const void* gauge, double m0, doubl
             return fail(QMG_ERR_PREC, "mg_create: 16-bit coarse storage needs complex64 inner precision and N %% 4 == 0");
         if (lp[l].coarse_direct && l + 2 != nlevels)
             return fail(QMG_ERR_ARG, "mg_create: coarse_direct is for the last level entry only (level %d)", l);
+        const int ts = lp[l].transfer_storage;
+        if (ts != 0 && ts != QMG_H16)
+            return fail(QMG_ERR_PREC, "mg_create: transfer_storage %d of level %d", ts, l);
+        if (ts != 0 && inner != QMG_C64)
+            return fail(QMG_ERR_PREC, "mg_create: a 16-bit transfer basis needs complex64 inner precision");
     }
     auto* mg = new qmg_mg_s();
     mg->s = as_stream(stream);

@@ -17,7 +17,10 @@
 //            LDS in a fixed order: no atomics, bitwise repeatable.
 // The basis is kept as [V][dof][Nvec] (row f of site x holds the Nvec
 // coefficients of its chirality) in the storage precision, plus an FP64 copy
-// for the Galerkin build.
+// for the Galerkin build.  The 16-bit storage keeps each complex entry as an
+// FP16 pair with no scale: the columns are orthonormal within an aggregate,
+// so no entry exceeds 1 in modulus.
+#include "codes16.h"
 #include "handles.h"
 
 #include <vector>
@@ -122,21 +125,35 @@ __global__ void k_to_c64(float2* __restrict__ o, const double2* __restrict__ i, 
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < n) o[g] = make_float2((float)i[g].x, (float)i[g].y);
 }
+__global__ void k_to_h16(uint32_t* __restrict__ o, const double2* __restrict__ i, int64_t n) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n) o[g] = enc_pair<FMT_H16>((float)i[g].x, (float)i[g].y);
+}
+
+// A stored basis entry as a complex number of the arithmetic precision R:
+// BT = cpx<R> (complex128 or complex64 storage) or a 32-bit FP16 pair.
+template <typename R> __device__ __forceinline__ cpx<R> bval(const cpx<R>& b) { return b; }
+template <typename R> __device__ __forceinline__ cpx<R> bval(const uint32_t& w) {
+    const cpx<float> v = dec_pair<FMT_H16>(w);
+    return cpx<R>{(R)v.re, (R)v.im};
+}
 
 // CPC consecutive basis entries, read once per application: non-temporal
 // loads, so the basis stream does not push the fine vector being restricted
 // out of the caches (restriction 52.6 -> 51.1 us on 16^3x32, Nvec 24; the
 // prolongation, which reads the small coarse vector, was slower with them,
 // 61.2 -> 62.8 us, and keeps plain loads).
-template <typename R, int CPC>
-__device__ __forceinline__ void ld_basis(cpx<R> (&b)[CPC], const cpx<R>* p) {
-    constexpr int bytes = (int)sizeof(cpx<R>) * CPC;
-    if constexpr (bytes == 8) {
+template <typename BT, int CPC>
+__device__ __forceinline__ void ld_basis(BT (&b)[CPC], const BT* p) {
+    constexpr int bytes = (int)sizeof(BT) * CPC;
+    if constexpr (bytes == 4) {
+        b[0] = __builtin_nontemporal_load(reinterpret_cast<const BT*>(p));
+    } else if constexpr (bytes == 8) {
         typedef int i2 __attribute__((ext_vector_type(2)));
         const i2 v = __builtin_nontemporal_load(reinterpret_cast<const i2*>(p));
         __builtin_memcpy(b, &v, 8);
     } else {
-        static_assert(bytes % 16 == 0, "basis chunks of 8 or a multiple of 16 bytes");
+        static_assert(bytes % 16 == 0, "basis chunks of 4, 8 or a multiple of 16 bytes");
         typedef int i4 __attribute__((ext_vector_type(4)));
         i4 v[bytes / 16];
 #pragma unroll
@@ -151,8 +168,8 @@ __device__ __forceinline__ void ld_basis(cpx<R> (&b)[CPC], const cpx<R>* p) {
 // loads before any arithmetic so that enough bytes are in flight to cover
 // HBM latency.  The `cpr` chunks of a row (x, f) are then summed in LDS in a
 // fixed order, one thread per row.
-template <typename R, int CPC, int RPT>
-__global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
+template <typename R, typename BT, int CPC, int RPT>
+__global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const BT* __restrict__ B,
                                                  const cpx<R>* __restrict__ uc, const int* __restrict__ owner,
                                                  int64_t V, int dof, int nvec, int rows_per_wg, int64_t cstride) {
     constexpr int cpc = CPC;
@@ -164,7 +181,7 @@ __global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const
     const int lr = t / cpr, kc = t - (t / cpr) * cpr;
     const int64_t rows = V * dof;
     const int64_t base = (int64_t)blockIdx.x * rows_per_wg * RPT;
-    cpx<R> b[RPT][cpc];
+    BT b[RPT][cpc];
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
         const int64_t row = base + (int64_t)j * rows_per_wg + lr;
@@ -183,7 +200,10 @@ __global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const
             const int chi = f / (dof / 2);
             const cpx<R>* u = uc + (int64_t)owner[x] * 2 * nvec + chi * nvec + kc * cpc;
 #pragma unroll
-            for (int q = 0; q < cpc; ++q) cmac(ar, ai, b[j][q].re, b[j][q].im, u[q].re, u[q].im);
+            for (int q = 0; q < cpc; ++q) {
+                const cpx<R> bq = bval<R>(b[j][q]);
+                cmac(ar, ai, bq.re, bq.im, u[q].re, u[q].im);
+            }
         }
         part[j][t] = cpx<R>{ar, ai};
     }
@@ -208,8 +228,8 @@ __global__ __launch_bounds__(256) void k_prolong(cpx<R>* __restrict__ out, const
 // and then the dof/2 rows of each chirality are summed in LDS in a fixed
 // order.  No atomics; bitwise repeatable.  With S = 1 the threads stride over
 // the chunks instead (blocks with more chunks than threads).
-template <typename R, int CPC>
-__global__ __launch_bounds__(1024) void k_restrict(cpx<R>* __restrict__ out, const cpx<R>* __restrict__ B,
+template <typename R, typename BT, int CPC>
+__global__ __launch_bounds__(1024) void k_restrict(cpx<R>* __restrict__ out, const BT* __restrict__ B,
                                                    const cpx<R>* __restrict__ in, const int* __restrict__ members,
                                                    int dof, int nvec, int bsites, int64_t fstride, int S) {
     constexpr int cpc = CPC;
@@ -234,26 +254,32 @@ __global__ __launch_bounds__(1024) void k_restrict(cpx<R>* __restrict__ out, con
             int b = slice;
             for (; b + 3 * S < bsites; b += 4 * S) {
                 int64_t x[4];
-                cpx<R> v[4], bb[4][cpc];
+                cpx<R> v[4];
+                BT bb[4][cpc];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     x[j] = mem[b + j * S];
                     v[j] = in[x[j] * dof + f];
-                    ld_basis<R, cpc>(bb[j], B + (x[j] * dof + f) * nvec + kc * cpc);
+                    ld_basis<BT, cpc>(bb[j], B + (x[j] * dof + f) * nvec + kc * cpc);
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int c = 0; c < cpc; ++c)
-                        cmac_conj(ar[c], ai[c], bb[j][c].re, bb[j][c].im, v[j].re, v[j].im);
+                    for (int c = 0; c < cpc; ++c) {
+                        const cpx<R> bq = bval<R>(bb[j][c]);
+                        cmac_conj(ar[c], ai[c], bq.re, bq.im, v[j].re, v[j].im);
+                    }
             }
             for (; b < bsites; b += S) {
                 const int64_t x = mem[b];
                 const cpx<R> v = in[x * dof + f];
-                cpx<R> bv[cpc];
-                ld_basis<R, cpc>(bv, B + (x * dof + f) * nvec + kc * cpc);
+                BT bv[cpc];
+                ld_basis<BT, cpc>(bv, B + (x * dof + f) * nvec + kc * cpc);
 #pragma unroll
-                for (int c = 0; c < cpc; ++c) cmac_conj(ar[c], ai[c], bv[c].re, bv[c].im, v.re, v.im);
+                for (int c = 0; c < cpc; ++c) {
+                    const cpx<R> bq = bval<R>(bv[c]);
+                    cmac_conj(ar[c], ai[c], bq.re, bq.im, v.re, v.im);
+                }
             }
 #pragma unroll
             for (int c = 0; c < cpc; ++c) acc_s[f * nvec + kc * cpc + c] = cpx<R>{ar[c], ai[c]};
@@ -299,7 +325,7 @@ qmg_status transfer_shell(const char* what, const int fine_dims[4], int fine_dof
     if (fine_dof < 2 || (fine_dof & 1) || fine_dof > 128)
         return fail(QMG_ERR_SHAPE, "%s: fine_dof %d must be even in [2,128]", what, fine_dof);
     if (nvec < 1 || 2 * nvec > 128) return fail(QMG_ERR_SHAPE, "%s: nvec %d outside [1,64]", what, nvec);
-    if (storage != QMG_C128 && storage != QMG_C64)
+    if (storage != QMG_C128 && storage != QMG_C64 && storage != QMG_H16)
         return fail(QMG_ERR_PREC, "%s: storage %d not supported", what, (int)storage);
     int cd[4];
     int64_t bs = 1;
@@ -356,10 +382,15 @@ qmg_status transfer_finish(const char* what, qmg_transfer_s* t, hipStream_t s) {
         t->basis = t->basis64;
         return QMG_OK;
     }
-    const hipError_t e = hipMalloc(&t->basis, sizeof(float2) * nb);
+    const bool h16 = t->storage == QMG_H16;
+    const hipError_t e = hipMalloc(&t->basis, (h16 ? sizeof(uint32_t) : sizeof(float2)) * nb);
     if (e != hipSuccess) return fail(QMG_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
-    hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (float2*)t->basis, t->basis64,
-                       (int64_t)nb);
+    if (h16)
+        hipLaunchKernelGGL(k_to_h16, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (uint32_t*)t->basis,
+                           t->basis64, (int64_t)nb);
+    else
+        hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (float2*)t->basis,
+                           t->basis64, (int64_t)nb);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
@@ -453,7 +484,7 @@ extern "C" qmg_status qmg_transfer_export(qmg_transfer t, void* basis, void* str
 }
 
 namespace qmg {
-template <typename R, int CPC>
+template <typename R, typename BT, int CPC>
 static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void* out, int nb, hipStream_t s) {
     constexpr int RPT = 4;
     const int cpr = t->nvec / CPC;
@@ -461,13 +492,13 @@ static qmg_status prolong_t(qmg_transfer t, const void* B, const void* in, void*
     const int64_t rows = t->V * t->dof;
     const int64_t per_wg = (int64_t)rows_per_wg * RPT;
     const unsigned nblk = (unsigned)((rows + per_wg - 1) / per_wg);
-    hipLaunchKernelGGL((k_prolong<R, CPC, RPT>), dim3(nblk, nb), dim3(256), 0, s, (cpx<R>*)out, (const cpx<R>*)B,
+    hipLaunchKernelGGL((k_prolong<R, BT, CPC, RPT>), dim3(nblk, nb), dim3(256), 0, s, (cpx<R>*)out, (const BT*)B,
                        (const cpx<R>*)in, t->owner, t->V, t->dof, t->nvec, rows_per_wg, t->Vc * 2 * t->nvec);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
-template <typename R, int CPC>
+template <typename R, typename BT, int CPC>
 static qmg_status restrict_t(qmg_transfer t, const void* B, const void* in, void* out, int nb, hipStream_t s) {
     const int nchunk = t->dof * (t->nvec / CPC);
     const size_t lds1 = sizeof(cpx<R>) * t->dof * t->nvec;
@@ -483,30 +514,45 @@ static qmg_status restrict_t(qmg_transfer t, const void* B, const void* in, void
     if (threads > 1024) threads = 1024;
     const size_t lds = lds1 * S;
     if (lds > 65536)
-        QMG_HIP(hipFuncSetAttribute((const void*)k_restrict<R, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    hipLaunchKernelGGL((k_restrict<R, CPC>), dim3((unsigned)t->Vc, nb), dim3(threads), lds, s, (cpx<R>*)out,
-                       (const cpx<R>*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites, t->V * t->dof, S);
+        QMG_HIP(hipFuncSetAttribute((const void*)k_restrict<R, BT, CPC>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    hipLaunchKernelGGL((k_restrict<R, BT, CPC>), dim3((unsigned)t->Vc, nb), dim3(threads), lds, s, (cpx<R>*)out,
+                       (const BT*)B, (const cpx<R>*)in, t->members, t->dof, t->nvec, t->bsites, t->V * t->dof, S);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
 
+// complex64 fields with a 16-bit basis: 16-byte chunks of four FP16 pairs
+// where nvec allows, else 8 or 4 bytes
 qmg_status transfer_prolong(qmg_transfer t, const void* in, void* out, qmg_prec p, int nb, hipStream_t s) {
-    if (p == QMG_C128) return prolong_t<double, 1>(t, t->basis64, in, out, nb, s);
-    if (t->nvec % 2) return prolong_t<float, 1>(t, t->basis, in, out, nb, s);
-    return prolong_t<float, 2>(t, t->basis, in, out, nb, s);
+    using C64 = cpx<float>;
+    if (p == QMG_C128) return prolong_t<double, cpx<double>, 1>(t, t->basis64, in, out, nb, s);
+    if (t->storage == QMG_H16) {
+        if (t->nvec % 4 == 0) return prolong_t<float, uint32_t, 4>(t, t->basis, in, out, nb, s);
+        if (t->nvec % 2 == 0) return prolong_t<float, uint32_t, 2>(t, t->basis, in, out, nb, s);
+        return prolong_t<float, uint32_t, 1>(t, t->basis, in, out, nb, s);
+    }
+    if (t->nvec % 2) return prolong_t<float, C64, 1>(t, t->basis, in, out, nb, s);
+    return prolong_t<float, C64, 2>(t, t->basis, in, out, nb, s);
 }
 
 qmg_status transfer_restrict(qmg_transfer t, const void* in, void* out, qmg_prec p, int nb, hipStream_t s) {
-    if (p == QMG_C128) return restrict_t<double, 1>(t, t->basis64, in, out, nb, s);
-    if (t->nvec % 2) return restrict_t<float, 1>(t, t->basis, in, out, nb, s);
-    return restrict_t<float, 2>(t, t->basis, in, out, nb, s);
+    using C64 = cpx<float>;
+    if (p == QMG_C128) return restrict_t<double, cpx<double>, 1>(t, t->basis64, in, out, nb, s);
+    if (t->storage == QMG_H16) {
+        if (t->nvec % 4 == 0) return restrict_t<float, uint32_t, 4>(t, t->basis, in, out, nb, s);
+        if (t->nvec % 2 == 0) return restrict_t<float, uint32_t, 2>(t, t->basis, in, out, nb, s);
+        return restrict_t<float, uint32_t, 1>(t, t->basis, in, out, nb, s);
+    }
+    if (t->nvec % 2) return restrict_t<float, C64, 1>(t, t->basis, in, out, nb, s);
+    return restrict_t<float, C64, 2>(t, t->basis, in, out, nb, s);
 }
 }  // namespace qmg
 
 static qmg_status check_transfer_prec(qmg_transfer t, qmg_prec p, const char* what) {
     if (p != QMG_C128 && p != QMG_C64) return fail(QMG_ERR_PREC, "%s: precision %d not supported", what, (int)p);
-    if (p == QMG_C64 && t->storage != QMG_C64)
-        return fail(QMG_ERR_PREC, "%s: complex64 fields need a transfer created with complex64 storage", what);
+    if (p == QMG_C64 && t->storage != QMG_C64 && t->storage != QMG_H16)
+        return fail(QMG_ERR_PREC, "%s: complex64 fields need a transfer created with complex64 or FP16 storage", what);
     return QMG_OK;
 }
 

@@ -293,3 +293,35 @@ def test_direct_coarsest_solve_matches_oracle():
         assert solvers.norm(r) <= 1e-10 * solvers.norm(B[k].reshape(-1))
     with pytest.raises(QmgError):
         Multigrid(dims, dev(U), m0, 1.0, [dict(base[0], coarse_direct=True), base[1]], st, inner='c64')
+
+
+def test_three_level_fp16_transfer_bases():
+    """Both levels' transfer bases stored as FP16 pairs for the solve (the
+    Galerkin build keeps the FP64 bases, so the coarse operators are unchanged):
+    the FP64 outer GCR reaches 1e-10 under the oracle's M in about the step
+    count of the complex64-basis solve, whole lattice and red-black, and a
+    16-bit basis is refused with complex128 inner precision."""
+    from paper_1612_07873_amd import Multigrid, QmgError
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U, A, fine = problem(dims, 0.3, 2, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 5)]
+    ref_levels = level_list(blocks, nvecs, 30, [10, 100])
+    mg32 = Multigrid(dims, dev(U), m0, 1.0, ref_levels, st, inner='c64')
+    mg16 = Multigrid(dims, dev(U), m0, 1.0, [dict(L, transfer_storage='h16') for L in ref_levels], st, inner='c64')
+    for l in (1, 2):
+        X32, Y32 = mg32.level(l)[2].export()
+        X16, Y16 = mg16.level(l)[2].export()
+        assert torch.equal(X32, X16) and torch.equal(Y32, Y16)
+    b = synth.gaussian((fine.V, 4, 3), 1, 2)
+    for rb in (False, True):
+        mg32.set_evenodd(rb)
+        mg16.set_evenodd(rb)
+        _, i32 = mg32.solve(dev(b), tol=1e-10)
+        x16, i16 = mg16.solve(dev(b), tol=1e-10)
+        tr = solvers.norm(b.reshape(-1) - fine.apply(host(x16).reshape(-1))) / solvers.norm(b.reshape(-1))
+        print('red-black' if rb else 'whole lattice', 'c64 bases', i32, 'fp16 bases', i16, 'oracle-M residual %.2e' % tr)
+        assert i16['converged'] and tr <= 1e-10
+        assert i16['outer_iters'] <= i32['outer_iters'] + 1
+    with pytest.raises(QmgError):
+        Multigrid(dims, dev(U), m0, 1.0, [dict(L, transfer_storage='h16') for L in ref_levels], st, inner='c128')

@@ -64,3 +64,40 @@ def test_restrict_is_repeatable_and_rank_failure_reported():
         Transfer(dims, 12, (3, 4, 4, 4), dev(vecs))      # block does not divide the lattice
     with pytest.raises(QmgError):
         Transfer(dims, 12, (8, 4, 4, 4), dev(vecs))      # coarse extent 1
+
+
+def _fp16_basis(Vb):
+    """The basis as the 16-bit storage holds it: FP64 -> FP32 -> FP16 (round to
+    nearest even each time), per real and imaginary part."""
+    q = lambda a: a.astype(np.float32).astype(np.float16).astype(np.float64)
+    return q(Vb.real) + 1j * q(Vb.imag)
+
+
+@pytest.mark.parametrize('dims,dof,block,nvec', [CASES[1], CASES[2], CASES[3], CASES[4]])
+def test_fp16_basis_prolong_restrict(dims, dof, block, nvec):
+    """FP16 basis storage (complex64 fields): the arithmetic against the oracle
+    applied to the rounded basis (1e-5), and the storage error against the
+    oracle's FP64 transfer within 4u, u = 2^-11 the FP16 unit roundoff."""
+    from paper_1612_07873_amd import Transfer
+    V = lattice.volume(dims)
+    vecs = synth.gaussian((nvec, V, dof), 7, 1)
+    Vb = transfer.block_orthonormalize(vecs, dims, block)
+    assert np.abs(Vb).max() <= 1.0
+    Vq = _fp16_basis(Vb)
+    cd = transfer.coarse_dims(dims, block)
+    uc = synth.gaussian((lattice.volume(cd), 2 * nvec), 8, 2)
+    f = synth.gaussian((V, dof), 9, 2)
+    t = Transfer(dims, dof, block, dev(vecs), 'h16')
+    assert rel_err(host(t.basis()), Vb) <= 1e-12          # the FP64 basis is kept for the Galerkin build
+    yp = host(t.prolong(dev(uc, torch.complex64)))
+    yr = host(t.restrict(dev(f, torch.complex64)))
+    e_pq = rel_err(yp, transfer.prolong(Vq, uc, dims, block))
+    e_rq = rel_err(yr, transfer.restrict(Vq, f, dims, block))
+    assert e_pq <= 1e-5 and e_rq <= 1e-5, (e_pq, e_rq)
+    u = 2.0 ** -11
+    e_p = rel_err(yp, transfer.prolong(Vb, uc, dims, block))
+    e_r = rel_err(yr, transfer.restrict(Vb, f, dims, block))
+    assert e_p <= 4 * u and e_r <= 4 * u, (e_p, e_r)
+    print(dims, dof, block, nvec, 'fp16 basis: arithmetic %.1e %.1e, storage %.1e %.1e' % (e_pq, e_rq, e_p, e_r))
+    # complex128 fields use the FP64 basis whatever the storage
+    assert rel_err(host(t.prolong(dev(uc))), transfer.prolong(Vb, uc, dims, block)) <= 1e-12
