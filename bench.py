@@ -309,7 +309,7 @@ def precision_form_levels(dims):
     return levels, starts
 
 
-def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
+def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False, transfer_storage=None):
     import numpy as np
     import torch
     import synth
@@ -320,9 +320,9 @@ def build_mg_16x32(coarse_storage=None, fine_storage=None, coarse_direct=False):
     V = int(np.prod(dims))
     U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to(dev)
     levels = [dict(block=(4, 4, 4, 4), nvec=24, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=10,
-                   coarse_storage=coarse_storage),
+                   coarse_storage=coarse_storage, transfer_storage=transfer_storage),
               dict(block=(2, 2, 2, 2), nvec=32, setup_iters=100, smoother_steps=4, coarse_tol=0.25, coarse_maxit=100,
-                   coarse_storage=coarse_storage, coarse_direct=coarse_direct)]
+                   coarse_storage=coarse_storage, coarse_direct=coarse_direct, transfer_storage=transfer_storage)]
     starts = [torch.from_numpy(synth.gaussian((24, V, 12), 0, 1)).to(dev),
               torch.from_numpy(synth.gaussian((32, 512, 48), 1, 1)).to(dev)]
     t0 = time.perf_counter()
@@ -443,9 +443,20 @@ def learned(npairs, epochs, loss, source='smoother'):
     mg16.set_smoother(None)
     combo_mr = timed_batches(mg16, 16, 2, 1000)
     del mg16
-    combo['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo['time_per_rhs_s'], 3)
-    combo_mr['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo_mr['time_per_rhs_s'], 3)
-    combo_h['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / combo_h['time_per_rhs_s'], 3)
+    # and with every 16-bit storage the build has (transfer bases too) and
+    # red-black preconditioning on every level (the network acts on the whole
+    # fine lattice, the MR steps after it too)
+    mgb, _, _, _, _ = build_mg_16x32(coarse_storage='h16', fine_storage='h16', transfer_storage='h16')
+    mgb.set_evenodd(True)
+    mgb.set_smoother(net)
+    rb_l = timed_batches(mgb, 16, 2, 1000)
+    mgb.set_smoother(net, mr_steps=2)
+    rb_h = timed_batches(mgb, 16, 2, 1000)
+    mgb.set_smoother(None)
+    rb_mr = timed_batches(mgb, 16, 2, 1000)
+    del mgb
+    for c in (combo, combo_mr, combo_h, rb_l, rb_h, rb_mr):
+        c['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / c['time_per_rhs_s'], 3)
     return {'lattice': list(dims), 'm0': m0, 'training_data': source, 'pairs': int(R.shape[0]),
             'pair_seconds': round(t_pairs, 2),
             'loss': loss, 'epochs': epochs, 'loss_history': [round(h, 5) for h in hist],
@@ -459,7 +470,11 @@ def learned(npairs, epochs, loss, source='smoother'):
                                     'sides per solve, matrix-core coarse stencils, learned level-0 smoother',
                            'plain_time_to_1e-10_s': plain['time_to_1e-10_s'],
                            'mixed_with_learned': combo, 'mixed_with_learned_then_MR2': combo_h,
-                           'mixed_with_MR': combo_mr}}
+                           'mixed_with_MR': combo_mr,
+                           'mixed_red_black': 'the same with FP16 transfer bases and red-black preconditioning on '
+                                              'every level',
+                           'mixed_red_black_with_learned': rb_l, 'mixed_red_black_with_learned_then_MR2': rb_h,
+                           'mixed_red_black_with_MR': rb_mr}}
 
 
 def fine_and_transfer(steps=200):

@@ -325,3 +325,13 @@ def test_three_level_fp16_transfer_bases():
         assert i16['outer_iters'] <= i32['outer_iters'] + 1
     with pytest.raises(QmgError):
         Multigrid(dims, dev(U), m0, 1.0, [dict(L, transfer_storage='h16') for L in ref_levels], st, inner='c128')
+    # every 16-bit storage at once (fine, coarse, transfer bases), red-black, a batch of 8
+    lv = [dict(L, transfer_storage='h16', coarse_storage='h16') for L in ref_levels]
+    mga = Multigrid(dims, dev(U), m0, 1.0, lv, st, inner='c64', fine_storage='h16')
+    mga.set_evenodd(True)
+    B = np.stack([synth.gaussian((fine.V, 4, 3), 60 + k, 2) for k in range(8)])
+    X, infos = mga.solve_multi(dev(B), tol=1e-10)
+    Xh = host(X)
+    for k in range(8):
+        r = solvers.norm(B[k].reshape(-1) - fine.apply(Xh[k].reshape(-1))) / solvers.norm(B[k].reshape(-1))
+        assert infos[k]['converged'] and r <= 1e-10, (k, r)
