@@ -762,6 +762,28 @@ def precision_form(nsolves=12, dims=(32, 32, 32, 64)):
     return out
 
 
+def pf_solves(nsolves, dims=(32, 32, 32, 64)):
+    """The 32^3x64 precision form at its fastest (FP16 fine links with 12 reals and
+    clover, FP16 coarse operators and transfer bases, red-black on every level),
+    built as precision_form() builds it; one read-stream launch marks the end of
+    the setup for a kernel trace, then `nsolves` solves."""
+    import torch
+    import synth
+    from paper_1612_07873_amd import Multigrid, stream_read
+    m0, _ = golden_m0(True)
+    U = torch.from_numpy(synth.gauge_field(dims, 0.3, 0)).to('cuda')
+    levels, starts = precision_form_levels(dims)
+    mg = Multigrid(dims, U, m0, 1.0, [dict(L, coarse_storage='h16', transfer_storage='h16') for L in levels], starts,
+                   inner='c64', fine_storage='h16')
+    mg.set_evenodd(True)
+    mg.set_fine_links(12)
+    buf = torch.ones(1 << 20, dtype=torch.float32, device='cuda')
+    sink = torch.empty(1 << 14, dtype=torch.int32, device='cuda')
+    stream_read(buf, sink)
+    torch.cuda.synchronize()
+    return timed_solves(mg, nsolves, 0)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument('--gpus', type=int, default=1)
@@ -782,6 +804,9 @@ def main():
                     help='only the 16-bit single-RHS and multi-RHS matrix-core records (rows a6, a7) instead')
     ap.add_argument('--precision-form', action='store_true',
                     help='16-bit precision form vs FP32 inner precision on 32^3x64 instead')
+    ap.add_argument('--pf-solves', type=int, default=0,
+                    help='only N solves of the 32^3x64 precision form with every storage 16-bit and red-black '
+                         '(a profiling driver: the end of the setup is marked by one read-stream launch)')
     ap.add_argument('--quick', action='store_true',
                     help='leave out the learned-smoother and 32^3x64 precision-form records')
     ap.add_argument('--pairs', type=int, default=4096)
@@ -833,6 +858,9 @@ def main():
         return
     if args.precision_form:
         print(json.dumps({'precision_form': precision_form()}), flush=True)
+        return
+    if args.pf_solves > 0:
+        print(json.dumps({'precision_form_all_16bit_red_black': pf_solves(args.pf_solves)}), flush=True)
         return
     dev = torch.device('cuda')
     # a plain device copy of known size (512 MiB read, 512 MiB written), outside
