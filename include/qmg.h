@@ -43,7 +43,7 @@ typedef enum {
     QMG_ERR_HIP = 4,        /* a HIP runtime call failed                    */
     QMG_ERR_NOMEM = 5,      /* device allocation failed                     */
     QMG_ERR_NOCONV = 6,     /* solver hit its iteration limit               */
-    QMG_ERR_NONFINITE = 7,  /* NaN/Inf met in a solver                      */
+    QMG_ERR_NONFINITE = 7,  /* NaN/Inf met in a solver, or by a 16-bit encoder */
     QMG_ERR_STATE = 8       /* handle used in a state that does not allow it */
 } qmg_status;
 
@@ -67,7 +67,15 @@ const char* qmg_last_error(void);
 /* ABI version (major*100 + minor). */
 int qmg_version(void);
 
-/* Wait for all work on `stream`; returns QMG_ERR_HIP if an enqueued kernel failed. */
+/* Wait for all work on `stream`; returns QMG_ERR_HIP if an enqueued kernel
+ * failed, and QMG_ERR_NONFINITE if a 16-bit encoder (qmg_quantize_sites, the
+ * 16-bit storages of qmg_coarse_op_create, or the batched solve's rounding of
+ * stencil inputs) met a NaN or Inf input, or a block whose largest entry does
+ * not fit FP32, since the last such report: those inputs are never encoded
+ * silently.  The record is one word per device, shared by every stream and
+ * handle on it, and is cleared when reported.  Blocking calls that encode
+ * (qmg_fine_op_create with a 16-bit storage, qmg_transfer_create/import with
+ * QMG_H16, qmg_mg_create, the MG solves) report it themselves. */
 qmg_status qmg_sync(void* stream);
 
 /* Measurement reference: read `bytes` (a multiple of 16) of the DEVICE buffer

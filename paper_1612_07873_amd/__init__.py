@@ -14,7 +14,7 @@ import torch
 from . import _lib
 from ._lib import PREC, QmgError, lib
 
-__all__ = ['BiCGStab', 'stream_read', 'tune_cache_save', 'tune_cache_load', 'tune_cache_clear', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
+__all__ = ['BiCGStab', 'sync', 'stream_read', 'tune_cache_save', 'tune_cache_load', 'tune_cache_clear', 'apply_mrhs_multi', 'PTC', 'quantize_sites', 'dequantize_sites', 'CoarseOp', 'FineOp', 'Transfer', 'build_coarse_op', 'Multigrid', 'QmgError', 'lib', 'stream_ptr', 'PREC']
 
 _CDTYPE = {'c128': torch.complex128, 'c64': torch.complex64}
 _VECDTYPE = {'c128': torch.complex128, 'c64': torch.complex64, 'h16': torch.complex64, 'b16': torch.complex64}
@@ -25,6 +25,12 @@ def stream_read(buf, sink):
     sink: int32 device tensor of at least 16 x (compute units) words."""
     _lib.call('qmg_stream_read', ctypes.c_void_p(buf.data_ptr()), int(buf.numel() * buf.element_size()),
               ctypes.c_void_p(sink.data_ptr()), int(sink.numel()), stream_ptr())
+
+
+def sync():
+    """Wait for the current stream (qmg_sync); raises QmgError with QMG_ERR_NONFINITE if a
+    16-bit encoder met a NaN or Inf input since the last report."""
+    _lib.call('qmg_sync', stream_ptr())
 
 
 def tune_cache_save(path):

@@ -139,17 +139,27 @@ __global__ void k_unpack(const typename Fmt<F>::C* __restrict__ L, const float* 
 
 // Per (site, direction block) scale: largest |re| or |im| of the N x N block.
 __global__ __launch_bounds__(256) void k_link_scales(float* __restrict__ lscale, const double2* __restrict__ X,
-                                                     const double2* __restrict__ Y, int64_t V, int N) {
+                                                     const double2* __restrict__ Y, int64_t V, int N,
+                                                     unsigned* __restrict__ nf) {
     __shared__ double red[4];
     const int64_t site = blockIdx.x / 9;
     const int d = blockIdx.x % 9;
     const double2* B = d == 0 ? X + site * N * N : Y + (((int64_t)(d - 1)) * V + site) * N * N;
     double m = 0;
-    for (int i = threadIdx.x; i < N * N; i += blockDim.x) m = fmax(m, fmax(fabs(B[i].x), fabs(B[i].y)));
+    bool bad = false;
+    for (int i = threadIdx.x; i < N * N; i += blockDim.x) {
+        bad = bad || !(isfinite(B[i].x) && isfinite(B[i].y));
+        m = fmax(m, fmax(fabs(B[i].x), fabs(B[i].y)));
+    }
+    note_nonfinite(nf, bad);
     for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) lscale[blockIdx.x] = (float)fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (threadIdx.x == 0) {
+        const float sc = (float)fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+        note_nonfinite(nf, !isfinite(sc));
+        lscale[blockIdx.x] = sc;
+    }
 }
 
 // ------------------------------------------------------------------ stencil
@@ -290,13 +300,16 @@ __global__ __launch_bounds__(1024) void k_coarse_dslash(const typename Fmt<F>::C
 // -------------------------------------------------------- vector (de)quantise
 template <int VF>
 __global__ __launch_bounds__(64) void k_quantize(const float2* __restrict__ in, uint32_t* __restrict__ out,
-                                                 float* __restrict__ scale, int N) {
+                                                 float* __restrict__ scale, int N, unsigned* __restrict__ nf) {
     const int64_t site = blockIdx.x;
     float m = 0.f;
+    bool bad = false;
     for (int c = threadIdx.x; c < N; c += 64) {
         const float2 v = in[site * N + c];
+        bad = bad || !(isfinite(v.x) && isfinite(v.y));
         m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
+    note_nonfinite(nf, bad);
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
     const float inv = m > 0 ? 1.0f / m : 0.0f;
     for (int c = threadIdx.x; c < N; c += 64) {
@@ -309,15 +322,19 @@ __global__ __launch_bounds__(64) void k_quantize(const float2* __restrict__ in, 
 // [m][V][N] complex64 -> 16-bit [V][m][N] with one scale per (site, member) [V][m]
 template <int VF>
 __global__ __launch_bounds__(64) void k_quantize_perm(const float2* __restrict__ in, uint32_t* __restrict__ out,
-                                                      float* __restrict__ scale, int64_t V, int m, int N) {
+                                                      float* __restrict__ scale, int64_t V, int m, int N,
+                                                      unsigned* __restrict__ nf) {
     const int64_t g = blockIdx.x;           // input row: member g / V, site g % V
     const int64_t site = g % V, j = g / V;
     const int64_t o = site * m + j;         // output row
     float mx = 0.f;
+    bool bad = false;
     for (int c = threadIdx.x; c < N; c += 64) {
         const float2 v = in[g * N + c];
+        bad = bad || !(isfinite(v.x) && isfinite(v.y));
         mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
     }
+    note_nonfinite(nf, bad);
     for (int k = 32; k > 0; k >>= 1) mx = fmaxf(mx, __shfl_xor(mx, k, 64));
     const float inv = mx > 0 ? 1.0f / mx : 0.0f;
     for (int c = threadIdx.x; c < N; c += 64) {
@@ -504,12 +521,14 @@ bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m) {
 qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec vprec, int m, void* q16,
                         float* qsc, hipStream_t s) {
     if (m > 1 && vprec == QMG_C64 && q16 && coarse_batch_uses_mfma(op, m)) {
+        unsigned* nf = nullptr;
+        QMG_TRY(nonfinite_flag(&nf));
         if (op->storage == QMG_H16)
             hipLaunchKernelGGL(k_quantize_perm<FMT_H16>, dim3((unsigned)(op->V * m)), dim3(64), 0, s, (const float2*)in,
-                               (uint32_t*)q16, qsc, op->V, m, op->N);
+                               (uint32_t*)q16, qsc, op->V, m, op->N, nf);
         else
             hipLaunchKernelGGL(k_quantize_perm<FMT_B16>, dim3((unsigned)(op->V * m)), dim3(64), 0, s, (const float2*)in,
-                               (uint32_t*)q16, qsc, op->V, m, op->N);
+                               (uint32_t*)q16, qsc, op->V, m, op->N, nf);
         QMG_LAUNCH_CHECK();
         return coarse_mrhs(op, q16, qsc, out, m, 0, s, op->V * op->N);
     }
@@ -549,15 +568,21 @@ qmg_status coarse_op_build(const int dims[4], int64_t V, int N, const void* X, c
     const int64_t total = op->V * op->J * N;
     const unsigned nb = (unsigned)((total + 255) / 256);
     const double2 *x = (const double2*)X, *y = (const double2*)Y;
+    unsigned* nf = nullptr;
+    if (is16(storage)) st = nonfinite_flag(&nf);
+    if (st != QMG_OK) {
+        qmg_coarse_op_destroy(op);
+        return st;
+    }
     switch (fmt_of(storage)) {
         case FMT_F64: hipLaunchKernelGGL(k_pack<FMT_F64>, dim3(nb), dim3(256), 0, s, (double2*)op->links, nullptr, x, y, op->V, N, op->J); break;
         case FMT_F32: hipLaunchKernelGGL(k_pack<FMT_F32>, dim3(nb), dim3(256), 0, s, (float4*)op->links, nullptr, x, y, op->V, N, op->J); break;
         case FMT_H16:
-            hipLaunchKernelGGL(k_link_scales, dim3((unsigned)(op->V * 9)), dim3(256), 0, s, op->lscale, x, y, op->V, N);
+            hipLaunchKernelGGL(k_link_scales, dim3((unsigned)(op->V * 9)), dim3(256), 0, s, op->lscale, x, y, op->V, N, nf);
             hipLaunchKernelGGL(k_pack<FMT_H16>, dim3(nb), dim3(256), 0, s, (uint4*)op->links, op->lscale, x, y, op->V, N, op->J);
             break;
         default:
-            hipLaunchKernelGGL(k_link_scales, dim3((unsigned)(op->V * 9)), dim3(256), 0, s, op->lscale, x, y, op->V, N);
+            hipLaunchKernelGGL(k_link_scales, dim3((unsigned)(op->V * 9)), dim3(256), 0, s, op->lscale, x, y, op->V, N, nf);
             hipLaunchKernelGGL(k_pack<FMT_B16>, dim3(nb), dim3(256), 0, s, (uint4*)op->links, op->lscale, x, y, op->V, N, op->J);
     }
     e = hipGetLastError();
@@ -662,10 +687,14 @@ extern "C" qmg_status qmg_quantize_sites(const void* in, void* out, float* scale
     if (V < 1 || N < 1) return fail(QMG_ERR_SHAPE, "quantize_sites: V=%lld N=%d", V, N);
     if (!is16(prec)) return fail(QMG_ERR_PREC, "quantize_sites: precision must be QMG_H16 or QMG_B16");
     hipStream_t s = as_stream(stream);
+    unsigned* nf = nullptr;
+    QMG_TRY(nonfinite_flag(&nf));
     if (prec == QMG_H16)
-        hipLaunchKernelGGL(k_quantize<FMT_H16>, dim3((unsigned)V), dim3(64), 0, s, (const float2*)in, (uint32_t*)out, scale, N);
+        hipLaunchKernelGGL(k_quantize<FMT_H16>, dim3((unsigned)V), dim3(64), 0, s, (const float2*)in, (uint32_t*)out, scale, N,
+                           nf);
     else
-        hipLaunchKernelGGL(k_quantize<FMT_B16>, dim3((unsigned)V), dim3(64), 0, s, (const float2*)in, (uint32_t*)out, scale, N);
+        hipLaunchKernelGGL(k_quantize<FMT_B16>, dim3((unsigned)V), dim3(64), 0, s, (const float2*)in, (uint32_t*)out, scale, N,
+                           nf);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }

@@ -48,4 +48,11 @@ template <int F> __device__ __forceinline__ uint32_t enc_pair(float re, float im
     return (uint32_t)enc16<F>(re) | ((uint32_t)enc16<F>(im) << 16);
 }
 
+// An encoder that met a NaN or Inf input (or a scale beyond FP32) records it
+// in the per-device word nf (a vector atomic OR), which the next blocking
+// call or qmg_sync turns into QMG_ERR_NONFINITE.
+__device__ __forceinline__ void note_nonfinite(unsigned* nf, bool bad) {
+    if (bad) atomicOr(nf, 1u);
+}
+
 }  // namespace qmg

@@ -1,6 +1,7 @@
 // Error state, argument checks and lattice helpers shared by the entry points.
 #include "qmg_internal.h"
 
+#include <mutex>
 #include <vector>
 
 namespace qmg {
@@ -82,6 +83,41 @@ qmg_status make_half_site_table(const int dims[4], int** dev_out, hipStream_t s)
     return QMG_OK;
 }
 
+namespace {
+__device__ unsigned g_nonfinite = 0;   // one word per device: see nonfinite_flag()
+std::mutex g_nf_mu;
+std::vector<unsigned*> g_nf_ptr;
+}  // namespace
+
+qmg_status nonfinite_flag(unsigned** out) {
+    int dev = 0;
+    QMG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(g_nf_mu);
+    if ((int)g_nf_ptr.size() <= dev) g_nf_ptr.resize(dev + 1, nullptr);
+    if (!g_nf_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_nonfinite));
+        if (e != hipSuccess || !p)
+            return fail(QMG_ERR_HIP, "non-finite flag address on device %d: %s", dev, hipGetErrorString(e));
+        g_nf_ptr[dev] = static_cast<unsigned*>(p);
+    }
+    *out = g_nf_ptr[dev];
+    return QMG_OK;
+}
+
+qmg_status take_nonfinite(hipStream_t s, const char* what) {
+    unsigned* f = nullptr;
+    QMG_TRY(nonfinite_flag(&f));
+    unsigned h = 0;
+    QMG_HIP(hipMemcpyAsync(&h, f, sizeof h, hipMemcpyDeviceToHost, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    if (!h) return QMG_OK;
+    const unsigned zero = 0;
+    QMG_HIP(hipMemcpyAsync(f, &zero, sizeof zero, hipMemcpyHostToDevice, s));
+    QMG_HIP(hipStreamSynchronize(s));
+    return fail(QMG_ERR_NONFINITE, "%s: a 16-bit encoder met a NaN or Inf input (or a scale beyond FP32)", what);
+}
+
 const char* last_error() { return g_err; }
 
 }  // namespace qmg
@@ -92,5 +128,5 @@ extern "C" int qmg_version(void) { return 100; }
 
 extern "C" qmg_status qmg_sync(void* stream) {
     QMG_HIP(hipStreamSynchronize(qmg::as_stream(stream)));
-    return QMG_OK;
+    return qmg::take_nonfinite(qmg::as_stream(stream), "sync");
 }

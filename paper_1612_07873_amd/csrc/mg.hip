@@ -995,6 +995,7 @@ static qmg_status mg_make(const int dims[4], const void* gauge, double m0, doubl
         const qmg_prec vp = inner == QMG_C128 ? QMG_C128 : QMG_C64;
         st = qmg_coarse_op_tune(L.op, L.x, nullptr, L.t, nullptr, vp, 0, mg->s, nullptr);
     }
+    if (st == QMG_OK) st = take_nonfinite(mg->s, "mg_create");   // the 16-bit conversions above
     if (st != QMG_OK) {
         qmg_mg_destroy(mg);
         return st;
@@ -1036,10 +1037,19 @@ static qmg_status run_solve(qmg_mg mg, const void* b, void* x, int nrhs, const q
     if (nrhs > mg->cap) QMG_TRY(workspace(mg, nrhs));
     mg->nb = nrhs;
     mg->blas.nb = nrhs;
-    const qmg_status st = mg->inner == QMG_C128 ? solve_impl<double>(mg, b, x, p, info)
-                                                : solve_impl<float>(mg, b, x, p, info);
+    qmg_status st = mg->inner == QMG_C128 ? solve_impl<double>(mg, b, x, p, info)
+                                          : solve_impl<float>(mg, b, x, p, info);
     mg->nb = 1;
     mg->blas.nb = 1;
+    // a NaN or Inf met by the batched path's 16-bit rounding of stencil inputs
+    if (st == QMG_OK) {
+        st = take_nonfinite(mg->s, "mg_gcr_solve");
+    } else {   // the solve's own failure is the one reported; the flag is cleared all the same
+        char msg[1024];
+        snprintf(msg, sizeof msg, "%s", last_error());
+        (void)take_nonfinite(mg->s, "mg_gcr_solve");
+        st = fail(st, "%s", msg);
+    }
     return st;
 }
 

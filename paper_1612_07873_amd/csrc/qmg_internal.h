@@ -14,6 +14,7 @@ namespace qmg {
 
 qmg_status fail(qmg_status st, const char* fmt, ...);
 void clear_error();
+const char* last_error();
 
 #define QMG_HIP(call)                                                                   \
     do {                                                                                \
@@ -45,6 +46,14 @@ qmg_status make_neighbour_table(const int dims[4], int** dev_out, hipStream_t s)
 // Red-black numbering [2][V/2]: lattice index of each half-lattice site of
 // parity 0, then parity 1 (QMG_ERR_SHAPE unless every extent is even).
 qmg_status make_half_site_table(const int dims[4], int** dev_out, hipStream_t s);
+
+// Non-finite inputs of the 16-bit encoders: a per-device word that an encoder
+// kernel sets (vector atomic OR) when it meets a NaN or Inf input, or a scale
+// that does not fit FP32.  nonfinite_flag() is its device address on the
+// current device (looked up once per device); take_nonfinite() waits for
+// `s`, and if the word is set clears it and returns QMG_ERR_NONFINITE.
+qmg_status nonfinite_flag(unsigned** out);
+qmg_status take_nonfinite(hipStream_t s, const char* what);
 
 // Launch error check right after a kernel launch.
 #define QMG_LAUNCH_CHECK() QMG_HIP(hipGetLastError())

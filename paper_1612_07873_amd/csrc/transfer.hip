@@ -125,9 +125,11 @@ __global__ void k_to_c64(float2* __restrict__ o, const double2* __restrict__ i, 
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < n) o[g] = make_float2((float)i[g].x, (float)i[g].y);
 }
-__global__ void k_to_h16(uint32_t* __restrict__ o, const double2* __restrict__ i, int64_t n) {
+__global__ void k_to_h16(uint32_t* __restrict__ o, const double2* __restrict__ i, int64_t n, unsigned* __restrict__ nf) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < n) o[g] = enc_pair<FMT_H16>((float)i[g].x, (float)i[g].y);
+    if (g >= n) return;
+    note_nonfinite(nf, !(isfinite(i[g].x) && isfinite(i[g].y)));
+    o[g] = enc_pair<FMT_H16>((float)i[g].x, (float)i[g].y);
 }
 
 // A stored basis entry as a complex number of the arithmetic precision R:
@@ -385,10 +387,14 @@ qmg_status transfer_finish(const char* what, qmg_transfer_s* t, hipStream_t s) {
     const bool h16 = t->storage == QMG_H16;
     const hipError_t e = hipMalloc(&t->basis, (h16 ? sizeof(uint32_t) : sizeof(float2)) * nb);
     if (e != hipSuccess) return fail(QMG_ERR_NOMEM, "%s: %s", what, hipGetErrorString(e));
-    if (h16)
+    if (h16) {
+        unsigned* nf = nullptr;
+        QMG_TRY(nonfinite_flag(&nf));
         hipLaunchKernelGGL(k_to_h16, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (uint32_t*)t->basis,
-                           t->basis64, (int64_t)nb);
-    else
+                           t->basis64, (int64_t)nb, nf);
+        QMG_LAUNCH_CHECK();
+        return take_nonfinite(s, what);
+    } else
         hipLaunchKernelGGL(k_to_c64, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, (float2*)t->basis,
                            t->basis64, (int64_t)nb);
     QMG_LAUNCH_CHECK();

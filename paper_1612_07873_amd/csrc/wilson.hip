@@ -615,13 +615,19 @@ __global__ void k_links_export(double2* __restrict__ G, const void* __restrict__
 // FP64 clover [2][36][V] -> 16-bit pairs [2][18][V] with one scale per (chirality, site).
 template <int LF>
 __global__ void k_clover_pack16(uint32_t* __restrict__ W, float* __restrict__ cscale,
-                                const double* __restrict__ clov, int64_t V) {
+                                const double* __restrict__ clov, int64_t V, unsigned* __restrict__ nf) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= V) return;
     for (int chi = 0; chi < 2; ++chi) {
         const double* A = clov + (int64_t)chi * 36 * V + x;
         float m = 0.0f;
-        for (int i = 0; i < 36; ++i) m = fmaxf(m, fabsf((float)A[i * V]));
+        bool bad = false;
+        for (int i = 0; i < 36; ++i) {
+            const float a = (float)A[i * V];
+            bad = bad || !isfinite(a);
+            m = fmaxf(m, fabsf(a));
+        }
+        note_nonfinite(nf, bad);
         const float inv = m > 0.0f ? 1.0f / m : 0.0f;
         for (int q = 0; q < 18; ++q)
             W[((int64_t)chi * 18 + q) * V + x] = enc_pair<LF>((float)A[2 * q * V] * inv, (float)A[(2 * q + 1) * V] * inv);
@@ -633,13 +639,14 @@ __global__ void k_clover_pack16(uint32_t* __restrict__ W, float* __restrict__ cs
 // compressed link), time sign folded.
 template <int LF>
 __global__ void k_pack_gauge16(uint32_t* __restrict__ U, const double2* __restrict__ G, int64_t V,
-                               int64_t last_slice_start, int anti, int ne) {
+                               int64_t last_slice_start, int anti, int ne, unsigned* __restrict__ nf) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= 4 * ne * V) return;
     const int64_t site = g % V;
     const int e = (int)((g / V) % ne);
     const int mu = (int)(g / (ne * V));
     const double2 v = G[((int64_t)mu * V + site) * 9 + e];
+    note_nonfinite(nf, !(isfinite((float)v.x) && isfinite((float)v.y)));
     const double sgn = (anti && mu == 3 && site >= last_slice_start) ? -1.0 : 1.0;
     U[g] = enc_pair<LF>((float)(sgn * v.x), (float)(sgn * v.y));
 }
@@ -989,7 +996,16 @@ extern "C" qmg_status qmg_fine_op_create_ex(const int dims[4], const void* gauge
         }
     } else {
         // the clover term is built in FP64 in a temporary, then scaled per
-        // (chirality, site) and rounded to 16 bits (its inverse likewise)
+        // (chirality, site) and rounded to 16 bits (its inverse likewise);
+        // a NaN or Inf met on the way is reported below
+        unsigned* nf = nullptr;
+        st = nonfinite_flag(&nf);
+        if (st != QMG_OK) {
+            if (c64) (void)hipFree(c64);
+            if (i64) (void)hipFree(i64);
+            qmg_fine_op_destroy(op);
+            return st;
+        }
         hipLaunchKernelGGL(k_clover_build<double>, dim3(nbS), dim3(128), 0, s, (double*)c64,
                            (const double2*)gauge, op->nbr, op->V, sb);
         if (eo)
@@ -997,20 +1013,20 @@ extern "C" qmg_status qmg_fine_op_create_ex(const int dims[4], const void* gauge
                                op->V, diag);
         if (storage == QMG_H16) {
             hipLaunchKernelGGL(k_pack_gauge16<FMT_H16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
-                               (const double2*)gauge, op->V, last, op->antiperiodic_t, ne);
+                               (const double2*)gauge, op->V, last, op->antiperiodic_t, ne, nf);
             hipLaunchKernelGGL(k_clover_pack16<FMT_H16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
-                               op->cscale, (const double*)c64, op->V);
+                               op->cscale, (const double*)c64, op->V, nf);
             if (eo)
                 hipLaunchKernelGGL(k_clover_pack16<FMT_H16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->cinv,
-                                   op->ciscale, (const double*)i64, op->V);
+                                   op->ciscale, (const double*)i64, op->V, nf);
         } else {
             hipLaunchKernelGGL(k_pack_gauge16<FMT_B16>, dim3(nbU), dim3(256), 0, s, (uint32_t*)op->U,
-                               (const double2*)gauge, op->V, last, op->antiperiodic_t, ne);
+                               (const double2*)gauge, op->V, last, op->antiperiodic_t, ne, nf);
             hipLaunchKernelGGL(k_clover_pack16<FMT_B16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->clov,
-                               op->cscale, (const double*)c64, op->V);
+                               op->cscale, (const double*)c64, op->V, nf);
             if (eo)
                 hipLaunchKernelGGL(k_clover_pack16<FMT_B16>, dim3(nbS), dim3(128), 0, s, (uint32_t*)op->cinv,
-                                   op->ciscale, (const double*)i64, op->V);
+                                   op->ciscale, (const double*)i64, op->V, nf);
         }
     }
     if (c64 || i64) {
@@ -1073,6 +1089,13 @@ extern "C" qmg_status qmg_fine_op_create_ex(const int dims[4], const void* gauge
     if (e != hipSuccess) {
         qmg_fine_op_destroy(op);
         return fail(QMG_ERR_HIP, "fine_op_create: launch: %s", hipGetErrorString(e));
+    }
+    if (is16p(storage)) {
+        st = take_nonfinite(s, "fine_op_create");
+        if (st != QMG_OK) {
+            qmg_fine_op_destroy(op);
+            return st;
+        }
     }
     *out = op;
     return QMG_OK;
