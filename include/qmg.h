@@ -357,6 +357,15 @@ qmg_status qmg_wilson_clover_sap(qmg_fine_op op, const int block[4], int iters, 
 /* out_e = S in_e. */
 qmg_status qmg_wilson_clover_schur(qmg_fine_op op, const void* in_e, void* out_e, int nrhs, qmg_prec prec,
                                    void* stream);
+
+/* out_e = S in_e on 16-bit half-lattice vectors (Sec. 7.1: the fine-level
+ * smoother in half precision): in_e, out_e DEVICE [nrhs][V/2][12] FP16
+ * (re, im) pairs with one FP32 scale per site (in_scale, out_scale
+ * [nrhs][V/2], the layout of qmg_quantize_sites); FP32 arithmetic, the odd
+ * intermediate also rounded to 16 bits.  Needs an operator with 16-bit
+ * storage (QMG_ERR_PREC otherwise). */
+qmg_status qmg_wilson_clover_schur_scaled(qmg_fine_op op, const void* in_e, const float* in_scale, void* out_e,
+                                          float* out_scale, int nrhs, void* stream);
 /* bhat_e = b_e - D_eo C_oo^-1 b_o for whole-lattice b. */
 qmg_status qmg_wilson_clover_schur_source(qmg_fine_op op, const void* b, void* bhat_e, int nrhs, qmg_prec prec,
                                           void* stream);
@@ -564,6 +573,15 @@ qmg_status qmg_mg_set_fine_links(qmg_mg mg, int link_reals, void* stream);
  * inner precision (QMG_ERR_PREC) and a block that fits the lattice
  * (QMG_ERR_SHAPE, as qmg_wilson_clover_sap). */
 qmg_status qmg_mg_set_sap(qmg_mg mg, const int block[4], int iters, void* stream);
+
+/* Level-0 MR smoother vectors in the red-black form: 0 = the inner precision,
+ * QMG_H16 = the Schur system's source, residual and intermediates as FP16
+ * pairs with one FP32 scale per site (the paper's half-precision fine-level
+ * smoother, Sec. 7.1), the correction kept in complex64.  Needs a 16-bit fine
+ * operator in the K-cycle (QMG_ERR_PREC); takes effect while the red-black
+ * form is on (the whole-lattice MR is unchanged); regrows the solve
+ * workspace. */
+qmg_status qmg_mg_set_smoother_vectors(qmg_mg mg, int storage, void* stream);
 
 /* Time every coarse-grid solve of the following solves with HIP events on
  * the solve's stream (on != 0) and report each level's share in

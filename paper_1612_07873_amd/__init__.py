@@ -309,6 +309,19 @@ class FineOp:
     def _vp(self):
         return self.storage if self.storage in ('c128', 'c64') else 'c64'
 
+    def schur_scaled(self, u16, uscale, out16=None, oscale=None):
+        """S on 16-bit half-lattice spinors: u16 int32 [V/2][12] (or [nrhs][V/2][12]) FP16
+        pairs, uscale float32 [V/2] (or [nrhs][V/2]) (qmg_wilson_clover_schur_scaled)."""
+        if out16 is None:
+            out16 = torch.empty_like(u16)
+        if oscale is None:
+            oscale = torch.empty_like(uscale)
+        m, shape = _nrhs(u16, (self.V // 2, 12), 'in_e')
+        _lib.call('qmg_wilson_clover_schur_scaled', self._h, _dev_ptr(u16, torch.int32, shape, 'in_e'),
+                  _dev_ptr(uscale, torch.float32, shape[:-1], 'in_scale'), _dev_ptr(out16, torch.int32, shape, 'out_e'),
+                  _dev_ptr(oscale, torch.float32, shape[:-1], 'out_scale'), m, stream_ptr())
+        return out16, oscale
+
     def schur(self, pe, out=None):
         """S p_e = (C_ee - D_eo C_oo^-1 D_oe) p_e, C = 4 + m0 + A, D the hops of Eq. (2)."""
         if out is None:
@@ -639,6 +652,11 @@ class Multigrid:
     def set_level_timing(self, on=True):
         """Per-level device time in the solve info's level_seconds (qmg_mg_set_level_timing)."""
         _lib.call('qmg_mg_set_level_timing', self._h, int(bool(on)))
+
+    def set_smoother_vectors(self, storage=None):
+        """Level-0 MR smoother vectors in the red-black form: None (inner precision) or 'h16'
+        (qmg_mg_set_smoother_vectors)."""
+        _lib.call('qmg_mg_set_smoother_vectors', self._h, PREC[storage] if storage else 0, stream_ptr())
 
     def set_sap(self, block=(4, 4, 4, 4), iters=4):
         """Level-0 Schwarz (SAP) smoother with `iters` MR steps per block; iters=0 returns to MR."""

@@ -54,6 +54,8 @@ SIGNATURES = {
                                     ctypes.POINTER(c_void_p)]),
     'qmg_transfer_coarse_dims': (c_int, [c_void_p, c_int_p, c_int_p]),
     'qmg_transfer_export': (c_int, [c_void_p, c_void_p, c_void_p]),
+    'qmg_wilson_clover_schur_scaled': (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+    'qmg_mg_set_smoother_vectors': (c_int, [c_void_p, c_int, c_void_p]),
     'qmg_transfer_import': (c_int, [c_dims, c_int, c_dims, c_int, c_void_p, c_int, c_void_p,
                                     ctypes.POINTER(c_void_p)]),
     'qmg_prolong': (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_int, c_void_p]),

@@ -46,6 +46,16 @@ struct Blas {
     // (r may equal rin; the result residual goes to r)
     template <typename R> qmg_status mr_update(const double* s3, const void* rin, void* r, const void* Ar, void* x,
                                                int first, int64_t n);
+    // the same two on 16-bit spinor fields (FP16 pairs [site][12], one FP32 scale per
+    // site; x stays complex64): q, r and Ar of nsites sites per member
+    qmg_status dot_norm_h16(const void* q, const float* qs, const void* r, const float* rs, int64_t nsites,
+                            double* out);
+    qmg_status mr_update_h16(const double* s3, const void* rin, const float* rins, void* r, float* rs, const void* Ar,
+                             const float* Ars, void* x, int first, int64_t nsites);
+    // complex64 spinors [nsites][12] <-> FP16 pairs with one scale per site (all
+    // members' sites at once; a NaN or Inf input is recorded for qmg_sync)
+    qmg_status quantize_spinors(const void* in, void* out, float* scale, int64_t nsites);
+    qmg_status dequantize_spinors(const void* in, const float* scale, void* out, int64_t nsites);
     // minimal-residual step along d with Ad = A d, s3 = dot_norm(Ad, r): alpha = <Ad,r>/<Ad,Ad>;
     // x = alpha d; rout = r - alpha Ad
     template <typename R> qmg_status dir_step(const double* s3, const void* d, const void* Ad, const void* r, void* x,

@@ -1,5 +1,6 @@
 // BLAS-1 kernels of the solvers (see blas.h).
 #include "blas.h"
+#include "codes16.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -247,6 +248,124 @@ __global__ void k_mr_update(const double* __restrict__ s3, const cpx<R>* rin, cp
     rr.im -= ar * a.im + ai * a.re;
     x[i] = xx;
     r[i] = rr;
+}
+
+// MR on 16-bit spinor fields (FP16 pairs [site][12], one FP32 scale per site).
+// Four consecutive lanes share a site; lane j of the four takes components j,
+// j + 4 and j + 8, so each load or store instruction of a wave covers 64
+// consecutive words (16 sites), and the new residual's per-site scale is the
+// maximum over the four lanes (two lane exchanges).  Member b's fields start
+// at b * nsites sites.
+__global__ __launch_bounds__(1024) void k_dot_norm_h16(const uint32_t* __restrict__ q, const float* __restrict__ qs,
+                                                       const uint32_t* __restrict__ r, const float* __restrict__ rs,
+                                                       int64_t nsites, double* __restrict__ part,
+                                                       double* __restrict__ out, int ss) {
+    __shared__ double lds[16];
+    const int64_t mo = (int64_t)blockIdx.y * nsites;
+    q += mo * 12;
+    r += mo * 12;
+    qs += mo;
+    rs += mo;
+    QMG_MEMBER_SCAL(out); QMG_MEMBER_PART(part);
+    double qq = 0, re = 0, im = 0;
+    const int64_t nq = nsites * 4;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t site = i >> 2;
+        const float ka = qs[site], kb = rs[site];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int64_t w = (i & ~int64_t(3)) * 3 + (i & 3) + 4 * c;
+            const cpx<float> a = dec_pair<FMT_H16>(q[w]), b = dec_pair<FMT_H16>(r[w]);
+            const double xr = ka * a.re, xi = ka * a.im, yr = kb * b.re, yi = kb * b.im;
+            qq += xr * xr + xi * xi;
+            re += xr * yr + xi * yi;
+            im += xr * yi - xi * yr;
+        }
+    }
+    qq = wg_sum(qq, lds);
+    re = wg_sum(re, lds);
+    im = wg_sum(im, lds);
+    if (threadIdx.x == 0) {
+        put(part, out, 0, qq);
+        put(part, out, 1, re);
+        put(part, out, 2, im);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_mr_update_h16(const double* __restrict__ s3, const uint32_t* rin,
+                                                       const float* rins, uint32_t* r, float* rs,
+                                                       const uint32_t* __restrict__ Ar, const float* __restrict__ Ars,
+                                                       float2* __restrict__ x, int first, int64_t nsites, int ss) {
+    const int64_t per = gridDim.x >> 3;   // XCD-contiguous ranges, as in k_mr_update
+    const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    const int64_t i = wg * blockDim.x + threadIdx.x;   // quarter of a site: whole groups of four lanes
+    if (i >= nsites * 4) return;
+    const int64_t mo = (int64_t)blockIdx.y * nsites;
+    s3 += (int64_t)blockIdx.y * ss;
+    const double den = s3[0];
+    const float ar = den > 0 ? (float)(s3[1] / den) : 0.f, ai = den > 0 ? (float)(s3[2] / den) : 0.f;
+    const int64_t site = mo + (i >> 2), w0 = site * 12 + (i & 3);   // component c at w0 + 4 c
+    const float kr = rins[site], ka = Ars[site];
+    float2 nr[3];
+    float m = 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<float> u = dec_pair<FMT_H16>(rin[w0 + 4 * c]), v = dec_pair<FMT_H16>(Ar[w0 + 4 * c]);
+        const float ur = kr * u.re, ui = kr * u.im, vr = ka * v.re, vi = ka * v.im;
+        float2 xx = first ? make_float2(0.f, 0.f) : x[w0 + 4 * c];
+        xx.x += ar * ur - ai * ui;
+        xx.y += ar * ui + ai * ur;
+        x[w0 + 4 * c] = xx;
+        nr[c] = make_float2(ur - (ar * vr - ai * vi), ui - (ar * vi + ai * vr));
+        m = fmaxf(m, fmaxf(fabsf(nr[c].x), fabsf(nr[c].y)));
+    }
+    m = fmaxf(m, __shfl_xor(m, 1, 64));
+    m = fmaxf(m, __shfl_xor(m, 2, 64));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) r[w0 + 4 * c] = enc_pair<FMT_H16>(nr[c].x * inv, nr[c].y * inv);
+    if ((i & 3) == 0) rs[site] = m;
+}
+
+// complex64 spinors [site][12] -> FP16 pairs with one scale per site, four lanes per
+// site in the interleaved order above (a NaN or Inf input is recorded in nf)
+__global__ __launch_bounds__(256) void k_quantize_spinor(const float2* __restrict__ in, uint32_t* __restrict__ out,
+                                                         float* __restrict__ scale, int64_t nsites,
+                                                         unsigned* __restrict__ nf) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsites * 4) return;
+    const int64_t w0 = (i >> 2) * 12 + (i & 3);   // component c at w0 + 4 c
+    float2 v[3];
+    float m = 0.f;
+    bool bad = false;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        v[c] = in[w0 + 4 * c];
+        bad = bad || !(isfinite(v[c].x) && isfinite(v[c].y));
+        m = fmaxf(m, fmaxf(fabsf(v[c].x), fabsf(v[c].y)));
+    }
+    note_nonfinite(nf, bad);
+    m = fmaxf(m, __shfl_xor(m, 1, 64));
+    m = fmaxf(m, __shfl_xor(m, 2, 64));
+    const float inv = m > 0.f ? 1.0f / m : 0.f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) out[w0 + 4 * c] = enc_pair<FMT_H16>(v[c].x * inv, v[c].y * inv);
+    if ((i & 3) == 0) scale[i >> 2] = m;
+}
+
+// FP16 pairs with per-site scales -> complex64 spinors
+__global__ __launch_bounds__(256) void k_dequantize_spinor(const uint32_t* __restrict__ in,
+                                                           const float* __restrict__ scale, float2* __restrict__ out,
+                                                           int64_t nsites) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsites * 4) return;
+    const float k = scale[i >> 2];
+    const int64_t w0 = (i >> 2) * 12 + (i & 3);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const cpx<float> v = dec_pair<FMT_H16>(in[w0 + 4 * c]);
+        out[w0 + 4 * c] = make_float2(k * v.re, k * v.im);
+    }
 }
 
 // Minimal-residual step along a given direction d with Ad = A d, from
@@ -822,6 +941,39 @@ qmg_status Blas::mr_update(const double* s3, const void* rin, void* r, const voi
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
+qmg_status Blas::dot_norm_h16(const void* q, const float* qs, const void* r, const float* rs, int64_t nsites,
+                              double* out) {
+    const int nblk = nblocks(nsites * 4);
+    hipLaunchKernelGGL(k_dot_norm_h16, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const uint32_t*)q, qs,
+                       (const uint32_t*)r, rs, nsites, partials, out, ss);
+    finish(s, partials, nblk, 3, out, nb, ss);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+qmg_status Blas::mr_update_h16(const double* s3, const void* rin, const float* rins, void* r, float* rs, const void* Ar,
+                               const float* Ars, void* x, int first, int64_t nsites) {
+    hipLaunchKernelGGL(k_mr_update_h16, dim3((grid1(nsites * 4) + 7) / 8 * 8, nb), dim3(kThreads), 0, s, s3,
+                       (const uint32_t*)rin, rins, (uint32_t*)r, rs, (const uint32_t*)Ar, Ars, (float2*)x, first, nsites,
+                       ss);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
+qmg_status Blas::quantize_spinors(const void* in, void* out, float* scale, int64_t nsites) {
+    unsigned* nf = nullptr;
+    QMG_TRY(nonfinite_flag(&nf));
+    hipLaunchKernelGGL(k_quantize_spinor, dim3(grid1(nsites * 4)), dim3(kThreads), 0, s, (const float2*)in,
+                       (uint32_t*)out, scale, nsites, nf);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+qmg_status Blas::dequantize_spinors(const void* in, const float* scale, void* out, int64_t nsites) {
+    hipLaunchKernelGGL(k_dequantize_spinor, dim3(grid1(nsites * 4)), dim3(kThreads), 0, s, (const uint32_t*)in, scale,
+                       (float2*)out, nsites);
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
+}
+
 template <typename R>
 qmg_status Blas::dir_step(const double* s3, const void* d, const void* Ad, const void* r, void* x, void* rout,
                           int64_t n) {

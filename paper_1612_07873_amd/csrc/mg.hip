@@ -48,6 +48,8 @@ qmg_status coarse_apply(qmg_coarse_op_s* op, const void* in, void* out, qmg_prec
 bool coarse_batch_uses_mfma(const qmg_coarse_op_s* op, int m);
 qmg_status dense_inverse(qmg_coarse_op_s* op, qmg_prec prec, void** out, hipStream_t s);
 qmg_status dense_apply(const void* Ainv, const void* b, void* y, int64_t n, int nb, qmg_prec prec, hipStream_t s);
+qmg_status fine_schur_apply16(const qmg_fine_op_s* op, const void* in_e, const float* in_s, void* out_e, float* out_s,
+                              void* tmp_o, float* tmp_s, int m, hipStream_t s);
 qmg_status fine_schur_apply(const qmg_fine_op_s* op, const void* in_e, void* out_e, void* tmp_o, qmg_prec vprec,
                             int m, hipStream_t s);
 qmg_status fine_schur_source(const qmg_fine_op_s* op, const void* b, void* bhat_e, void* tmp_o, qmg_prec vprec,
@@ -100,6 +102,10 @@ struct Level {
     void *etmp = nullptr;   // odd half-lattice scratch of the Schur operator
     void *ekin = nullptr;   // level 0: inner-precision half field of the outer solve
     int small_steps[2] = {0, 0};   // steps of the last single-work-group GCR solve (whole, Schur system)
+    // level 0, red-black, 16-bit smoother vectors: the Schur system's source,
+    // residual, odd intermediate and A r as FP16 pairs [site][12] with scales
+    void *hb = nullptr, *hr = nullptr, *ht = nullptr, *hAr = nullptr;
+    float *hbs = nullptr, *hrs = nullptr, *hts = nullptr, *hArs = nullptr;
 };
 
 }  // namespace
@@ -128,6 +134,7 @@ struct qmg_mg_s {
     void* srec = nullptr;       // recording of level-0 smoother inputs (complex64 [maxrec][V][12])
     int srec_max = 0, srec_n = 0;
     bool eo = false;            // red-black form on every level
+    bool smooth16 = false;      // level-0 MR on the Schur system with 16-bit vectors (red-black form)
     void *eb64 = nullptr, *ex64 = nullptr, *etmp64 = nullptr;   // outer FP64 Schur source, iterate, scratch
     // per-level timing (qmg_mg_set_level_timing): HIP events around every
     // coarse-grid solve, read after the solve
@@ -352,7 +359,37 @@ template <typename R> qmg_status precond_sys(qmg_mg_s* mg, const Sys& sy, const 
 // of level l, then x_o = M_oo^-1 (r_o - M_oe x_e).  The residual r - A x it
 // leaves is zero on the odd sites (up to rounding) and the MR residual on the
 // even ones; that is what lv.mr_r receives.
+// Level 0: the same MR steps on the Schur system with 16-bit vectors (FP16
+// pairs with a scale per site; FP32 arithmetic; the iterate x in complex64),
+// the paper's half-precision fine-level smoother.
+qmg_status mr_schur16(qmg_mg_s* mg, const void* r, void* x) {
+    Level& L = mg->lv[0];
+    const int64_t Vh = L.V / 2;
+    const int nb = mg->nb;
+    hipStream_t s = mg->s;
+    QMG_TRY(schur_source<float>(mg, 0, r, L.sb));
+    QMG_TRY(mg->blas.quantize_spinors(L.sb, L.hb, L.hbs, Vh * nb));
+    for (int it = 0; it < L.p.smoother_steps; ++it) {
+        const void* cur = it == 0 ? L.hb : L.hr;
+        const float* curs = it == 0 ? L.hbs : L.hrs;
+        QMG_TRY(fine_schur_apply16(mg->fine_in, cur, curs, L.hAr, L.hArs, L.ht, L.hts, nb, s));
+        QMG_TRY(mg->blas.dot_norm_h16(L.hAr, L.hArs, cur, curs, Vh, mg->dsc + S_MR));
+        QMG_TRY(mg->blas.mr_update_h16(mg->dsc + S_MR, cur, curs, L.hr, L.hrs, L.hAr, L.hArs, L.sx, it == 0, Vh));
+    }
+    if (L.p.smoother_steps <= 0) {
+        QMG_HIP(hipMemsetAsync(L.sx, 0, nb * Vh * 12 * sizeof(cpx<float>), s));
+        QMG_HIP(hipMemcpyAsync(L.hr, L.hb, nb * Vh * 48, hipMemcpyDeviceToDevice, s));
+        QMG_HIP(hipMemcpyAsync(L.hrs, L.hbs, nb * Vh * sizeof(float), hipMemcpyDeviceToDevice, s));
+    }
+    QMG_TRY(mg->blas.dequantize_spinors(L.hr, L.hrs, L.sr, Vh * nb));
+    QMG_TRY(schur_reconstruct<float>(mg, 0, L.sx, r, x));
+    const int* hs = level_hsite(mg, 0);
+    return eo_scatter(hs, hs + Vh, Vh, L.dof, L.sr, L.mr_r, QMG_C64, nb, s);
+}
+
 template <typename R> qmg_status mr_schur(qmg_mg_s* mg, int l, const void* r, void* x) {
+    if constexpr (sizeof(R) == 4)
+        if (l == 0 && mg->smooth16) return mr_schur16(mg, r, x);
     Level& L = mg->lv[l];
     const int64_t ne = L.n / 2;
     const int nb = mg->nb;
@@ -617,6 +654,15 @@ qmg_status workspace(qmg_mg_s* mg, int cap) {
             for (void** p : half) QMG_TRY(salloc(mg, p, vb / 2));
             QMG_TRY(salloc(mg, &L.eQ, vb / 2 * mg->restart));
             QMG_TRY(salloc(mg, &L.eZ, vb / 2 * mg->restart));
+        }
+        void** h16[] = {&L.hb, &L.hr, &L.ht, &L.hAr};
+        float** h16s[] = {&L.hbs, &L.hrs, &L.hts, &L.hArs};
+        for (void** p : h16) *p = nullptr;
+        for (float** p : h16s) *p = nullptr;
+        if (l == 0 && mg->eo && mg->smooth16) {
+            const size_t sites = (size_t)(L.V / 2) * cap;
+            for (void** p : h16) QMG_TRY(salloc(mg, p, sites * 48));
+            for (float** p : h16s) QMG_TRY(salloc(mg, (void**)p, sites * 4));
         }
     }
     const size_t vb64 = mg->lv[0].n * 16 * cap;
@@ -1219,6 +1265,21 @@ extern "C" qmg_status qmg_mg_set_evenodd(qmg_mg mg, int on, void* stream) {
     mg->eo = true;
     const qmg_status st = workspace(mg, mg->cap > 0 ? mg->cap : 1);
     if (st != QMG_OK) mg->eo = false;
+    return st;
+}
+
+extern "C" qmg_status qmg_mg_set_smoother_vectors(qmg_mg mg, int storage, void* stream) {
+    (void)stream;
+    if (!mg) return fail(QMG_ERR_ARG, "mg_set_smoother_vectors: NULL mg");
+    if (storage != 0 && storage != QMG_H16)
+        return fail(QMG_ERR_PREC, "mg_set_smoother_vectors: storage %d (0 or QMG_H16)", storage);
+    if (storage && mg->fine_in->storage != QMG_H16 && mg->fine_in->storage != QMG_B16)
+        return fail(QMG_ERR_PREC, "mg_set_smoother_vectors: 16-bit vectors need a 16-bit fine operator in the K-cycle");
+    const bool on = storage != 0;
+    if (on == mg->smooth16) return QMG_OK;
+    mg->smooth16 = on;
+    const qmg_status st = workspace(mg, mg->cap > 0 ? mg->cap : 1);
+    if (st != QMG_OK) mg->smooth16 = false;
     return st;
 }
 

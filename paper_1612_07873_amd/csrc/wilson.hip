@@ -288,7 +288,8 @@ __global__ __launch_bounds__(256) void k_wilson_clover(const void* __restrict__ 
 // The site-local part of a red-black piece: acc = 0 (SELF 0), self (1) or
 // C(x) self (2); the clover term in parity order at index ie.
 template <int LF, int VF, int SELF, typename R>
-__device__ __forceinline__ void eo_self_terms(cpx<R> acc[12], const void* __restrict__ self, int64_t si, R diag,
+__device__ __forceinline__ void eo_self_terms(cpx<R> acc[12], const void* __restrict__ self,
+                                              const float* __restrict__ self_sc, int64_t si, R diag,
                                               int use_clover, const void* __restrict__ clov,
                                               const float* __restrict__ cscale, int64_t ie, int64_t V) {
     if constexpr (SELF == 0) {
@@ -296,7 +297,7 @@ __device__ __forceinline__ void eo_self_terms(cpx<R> acc[12], const void* __rest
         for (int f = 0; f < 12; ++f) acc[f] = {R(0), R(0)};
     } else {
         cpx<R> p[12];
-        load_spinor<VF>(p, self, nullptr, si);
+        load_spinor<VF>(p, self, self_sc, si);
         if constexpr (SELF == 1) {
 #pragma unroll
             for (int f = 0; f < 12; ++f) acc[f] = p[f];
@@ -308,6 +309,14 @@ __device__ __forceinline__ void eo_self_terms(cpx<R> acc[12], const void* __rest
     }
 }
 
+// Per-site scales of 16-bit vector fields (VF = FMT_H16 / FMT_B16), indexed
+// like the fields; unused for complex vectors.
+struct EoScales {
+    const float* self = nullptr;
+    const float* hin = nullptr;
+    float* out = nullptr;
+};
+
 template <int LF, int VF, int SELF, bool HOPS, bool INV, int LR = 18>
 __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, const void* __restrict__ clov,
                                                    const float* __restrict__ cscale, const void* __restrict__ cinv,
@@ -316,7 +325,7 @@ __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, c
                                                    const void* __restrict__ hin, void* __restrict__ out, int64_t Vh,
                                                    int64_t V, typename FineT<LF>::R diag, typename FineT<LF>::R coef,
                                                    int use_clover, int self_full, int out_full, int64_t last,
-                                                   int parity) {
+                                                   int parity, EoScales sc) {
     using R = typename FineT<LF>::R;
     // XCD-contiguous work-group numbering, as in k_wilson_clover (grid a multiple of 8)
     const int64_t per = gridDim.x >> 3;
@@ -334,7 +343,7 @@ __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, c
         const int nb[8] = {na.x, na.y, na.z, na.w, nc.x, nc.y, nc.z, nc.w};
         const R c = R(-0.5) * coef;
 #define QMG_EO_LOAD(P, UU, MU, BACK, D)                                                               \
-        load_spinor<VF>(P, hin, nullptr, (int64_t)(nb[D] >> 1) + vh);                                  \
+        load_spinor<VF>(P, hin, sc.hin, (int64_t)(nb[D] >> 1) + vh);                                   \
         load_link_at<LF, LR, true>(UU, U, MU, BACK ? io + (nb[D] >> 1) : ie, V,                        \
                                    MU == 3 && (BACK ? (int64_t)nb[D] : site) >= last);
         if constexpr (sizeof(R) == 4) {
@@ -346,7 +355,8 @@ __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, c
             cpx<R> pa[12], ua[9], pb[12], ub[9];
             QMG_EO_LOAD(pa, ua, 0, false, 0)
             QMG_EO_LOAD(pb, ub, 0, true, 1)
-            eo_self_terms<LF, VF, SELF>(acc, self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale, ie, V);
+            eo_self_terms<LF, VF, SELF>(acc, self, sc.self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale,
+                                        ie, V);
             hop_apply<0, false>(acc, pa, ua, c);
             QMG_EO_LOAD(pa, ua, 1, false, 2)
             hop_apply<0, true>(acc, pb, ub, c);
@@ -363,7 +373,8 @@ __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, c
             hop_apply<3, true>(acc, pb, ub, c);
         } else {
             // FP64: one hop at a time (registers)
-            eo_self_terms<LF, VF, SELF>(acc, self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale, ie, V);
+            eo_self_terms<LF, VF, SELF>(acc, self, sc.self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale,
+                                        ie, V);
             cpx<R> p[12], u[9];
 #define QMG_EO_HOP(MU, BACK, D) QMG_EO_LOAD(p, u, MU, BACK, D) hop_apply<MU, BACK>(acc, p, u, c);
             QMG_EO_HOP(0, false, 0)
@@ -378,16 +389,17 @@ __global__ __launch_bounds__(256) void k_wilson_eo(const void* __restrict__ U, c
         }
 #undef QMG_EO_LOAD
     } else {
-        eo_self_terms<LF, VF, SELF>(acc, self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale, ie, V);
+        eo_self_terms<LF, VF, SELF>(acc, self, sc.self, self_full ? site + vf : h + vh, diag, use_clover, clov, cscale,
+                                        ie, V);
     }
     if constexpr (INV) {
         cpx<R> t[12];
 #pragma unroll
         for (int f = 0; f < 12; ++f) t[f] = {R(0), R(0)};
         herm_mul_add<LF>(t, acc, cinv, ciscale, ie, V);
-        store_spinor<VF>(out, nullptr, out_full ? site + vf : h + vh, t);
+        store_spinor<VF>(out, sc.out, out_full ? site + vf : h + vh, t);
     } else {
-        store_spinor<VF>(out, nullptr, out_full ? site + vf : h + vh, acc);
+        store_spinor<VF>(out, sc.out, out_full ? site + vf : h + vh, acc);
     }
 }
 
@@ -808,7 +820,7 @@ static qmg_status launch_eo(const qmg_fine_op_s* op, int piece, int parity, cons
 #define QMG_EO_LAUNCH_LR(SELF, HOPS, INV, COEF, LR)                                                              \
     hipLaunchKernelGGL((k_wilson_eo<LF, VF, SELF, HOPS, INV, LR>), grid, block, 0, s, op->U_eo, op->clov_eo,    \
                        op->cscale_eo, op->cinv, op->ciscale, op->hnb, op->hsite, self, hin, out, Vh, op->V, diag,  \
-                       (R)(COEF), uc, self_full, out_full, op->last, parity)
+                       (R)(COEF), uc, self_full, out_full, op->last, parity, EoScales{})
 #define QMG_EO_LAUNCH(SELF, HOPS, INV, COEF)                                                                    \
     do {                                                                                                        \
         if constexpr (LF != FMT_F64 && HOPS) {                                                                  \
@@ -852,6 +864,48 @@ qmg_status fine_schur_apply(const qmg_fine_op_s* op, const void* in_e, void* out
                             int m, hipStream_t s) {
     QMG_TRY(fine_eo(op, EO_HOP_INV, 1, nullptr, 0, in_e, tmp_o, 0, vprec, m, s));
     return fine_eo(op, EO_DIAG_HOP, 0, in_e, 0, tmp_o, out_e, 0, vprec, m, s);
+}
+
+// The Schur operator on 16-bit half-lattice vectors (FP16 pairs with one FP32
+// scale per site, FP32 arithmetic), for an operator with 16-bit storage:
+// tmp_o = C_oo^-1 D_oe in_e, then out_e = C_ee in_e - D_eo tmp_o, every
+// intermediate rounded to 16 bits with its own per-site scale.
+template <int LF>
+static void launch_schur16(const qmg_fine_op_s* op, const void* in_e, const float* in_s, void* out_e, float* out_s,
+                           void* tmp_o, float* tmp_s, int m, hipStream_t s) {
+    const int64_t Vh = op->V / 2;
+    const unsigned nb = (unsigned)(((Vh + 255) / 256 + 7) / 8 * 8);
+    const float diag = (float)(4.0 + op->m0);
+    const int uc = op->csw != 0.0 ? 1 : 0;
+    const dim3 grid(nb, (unsigned)m), block(256);
+    EoScales a, b;
+    a.hin = in_s;
+    a.out = tmp_s;
+    b.self = in_s;
+    b.hin = tmp_s;
+    b.out = out_s;
+#define QMG_S16(LR)                                                                                                 \
+    do {                                                                                                            \
+        hipLaunchKernelGGL((k_wilson_eo<LF, FMT_H16, 0, true, true, LR>), grid, block, 0, s, op->U_eo, op->clov_eo,  \
+                           op->cscale_eo, op->cinv, op->ciscale, op->hnb, op->hsite, nullptr, in_e, tmp_o, Vh, op->V, \
+                           diag, 1.0f, uc, 0, 0, op->last, 1, a);                                                   \
+        hipLaunchKernelGGL((k_wilson_eo<LF, FMT_H16, 2, true, false, LR>), grid, block, 0, s, op->U_eo,             \
+                           op->clov_eo, op->cscale_eo, op->cinv, op->ciscale, op->hnb, op->hsite, in_e, tmp_o, out_e, \
+                           Vh, op->V, diag, -1.0f, uc, 0, 0, op->last, 0, b);                                        \
+    } while (0)
+    if (op->link_reals == 12) QMG_S16(12);
+    else QMG_S16(18);
+#undef QMG_S16
+}
+
+qmg_status fine_schur_apply16(const qmg_fine_op_s* op, const void* in_e, const float* in_s, void* out_e, float* out_s,
+                              void* tmp_o, float* tmp_s, int m, hipStream_t s) {
+    if (!op->hsite) return fail(QMG_ERR_SHAPE, "red-black form needs every lattice extent even");
+    if (op->storage == QMG_H16) launch_schur16<FMT_H16>(op, in_e, in_s, out_e, out_s, tmp_o, tmp_s, m, s);
+    else if (op->storage == QMG_B16) launch_schur16<FMT_B16>(op, in_e, in_s, out_e, out_s, tmp_o, tmp_s, m, s);
+    else return fail(QMG_ERR_PREC, "Schur operator on 16-bit vectors: the operator needs 16-bit storage");
+    QMG_LAUNCH_CHECK();
+    return QMG_OK;
 }
 
 // bhat_e = b_e - D_eo C_oo^-1 b_o for whole-lattice b.
@@ -1203,6 +1257,24 @@ extern "C" qmg_status qmg_wilson_clover_schur(qmg_fine_op op, const void* in_e, 
     hipStream_t s = as_stream(stream);
     QMG_TRY(schur_tmp(op, nrhs, prec, s));
     return fine_schur_apply(op, in_e, out_e, op->eo_tmp, prec, nrhs, s);
+}
+
+extern "C" qmg_status qmg_wilson_clover_schur_scaled(qmg_fine_op op, const void* in_e, const float* in_scale,
+                                                     void* out_e, float* out_scale, int nrhs, void* stream) {
+    if (!op) return fail(QMG_ERR_ARG, "wilson_clover_schur_scaled: NULL operator");
+    if (op->storage != QMG_H16 && op->storage != QMG_B16)
+        return fail(QMG_ERR_PREC, "wilson_clover_schur_scaled: needs an operator with 16-bit storage");
+    QMG_TRY(schur_checks(op, nrhs, QMG_C64, "wilson_clover_schur_scaled"));
+    if (!in_e || !in_scale || !out_e || !out_scale) return fail(QMG_ERR_ARG, "wilson_clover_schur_scaled: NULL field");
+    if (in_e == out_e || in_scale == out_scale)
+        return fail(QMG_ERR_ARG, "wilson_clover_schur_scaled: in and out alias");
+    hipStream_t s = as_stream(stream);
+    // the odd intermediate (48 bytes and a scale per site) in the operator's
+    // scratch, which holds 96 bytes per site and member
+    QMG_TRY(schur_tmp(op, nrhs, QMG_C64, s));
+    const int64_t n16 = (int64_t)nrhs * (op->V / 2) * 48;
+    float* ts = reinterpret_cast<float*>(static_cast<char*>(op->eo_tmp) + n16);
+    return fine_schur_apply16(op, in_e, in_scale, out_e, out_scale, op->eo_tmp, ts, nrhs, s);
 }
 
 extern "C" qmg_status qmg_wilson_clover_schur_source(qmg_fine_op op, const void* b, void* bhat_e, int nrhs,

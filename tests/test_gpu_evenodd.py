@@ -87,6 +87,36 @@ def test_fine_schur_16bit_storage(storage):
     assert err <= 8 * U_ROUND[storage]
 
 
+@pytest.mark.parametrize('storage', ['h16', 'b16'])
+@pytest.mark.parametrize('link_reals', [18, 12])
+def test_fine_schur_16bit_vectors(storage, link_reals):
+    """The Schur operator on 16-bit vectors (FP16 pairs with a scale per site,
+    the odd intermediate rounded as well; qmg_wilson_clover_schur_scaled):
+    against the same operator on complex64 vectors given the same rounded
+    input, within 4 units of FP16 rounding, and against the FP64 oracle within
+    the storage bound plus those; a batch of two gives each member's result."""
+    from paper_1612_07873_amd import FineOp, dequantize_sites, quantize_sites
+    dims, m0 = (4, 4, 4, 8), -0.2
+    U, A, S = fine_case(dims, 0.4, 2, m0, 1.0)
+    Vh = lattice.volume(dims) // 2
+    xe = synth.gaussian((2, Vh, 12), 8, 2)
+    op = FineOp(dims, dev(U), m0, 1.0, True, storage, link_reals=link_reals)
+    q, sc = quantize_sites(dev(xe.reshape(2 * Vh, 12), torch.complex64), 'h16')
+    xq = host(dequantize_sites(q, sc, 'h16')).reshape(2, Vh, 12)
+    y16, ys = op.schur_scaled(q.reshape(2, Vh, 12), sc.reshape(2, Vh))
+    y = host(dequantize_sites(y16.reshape(2 * Vh, 12), ys.reshape(2 * Vh), 'h16')).reshape(2, Vh, 12)
+    y32 = host(op.schur(dev(xq.reshape(2, Vh, 4, 3), torch.complex64))).reshape(2, Vh, 12)
+    u = 2.0 ** -11
+    for k in range(2):
+        ref = S.apply(xq[k])
+        e32 = np.linalg.norm(y[k] - y32[k]) / np.linalg.norm(y32[k])
+        e64 = np.linalg.norm(y[k] - ref) / np.linalg.norm(ref)
+        print(storage, link_reals, 'member', k, '16-bit vectors vs complex64 vectors %.2e, vs oracle %.2e' % (e32, e64))
+        assert e32 <= 4 * u and e64 <= 8 * U_ROUND[storage] + 4 * u
+    y1, ys1 = op.schur_scaled(q.reshape(2, Vh, 12)[1].contiguous(), sc.reshape(2, Vh)[1].contiguous())
+    assert torch.equal(y1, y16[1]) and torch.equal(ys1, ys[1])
+
+
 def test_fine_schur_refuses_odd_extent():
     from paper_1612_07873_amd import FineOp, QmgError
     dims = (3, 4, 2, 2)

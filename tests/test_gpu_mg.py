@@ -335,3 +335,39 @@ def test_three_level_fp16_transfer_bases():
     for k in range(8):
         r = solvers.norm(B[k].reshape(-1) - fine.apply(Xh[k].reshape(-1))) / solvers.norm(B[k].reshape(-1))
         assert infos[k]['converged'] and r <= 1e-10, (k, r)
+
+
+def test_fp16_smoother_vectors_red_black():
+    """The level-0 MR smoother on the Schur system with 16-bit vectors (the
+    paper's half-precision fine smoother), with 16-bit fine and coarse
+    operators: the FP64 outer GCR reaches 1e-10 under the oracle's M in about
+    the step count of the complex64-vector smoother, also for a batch; a
+    complex64 fine operator refuses it."""
+    from paper_1612_07873_amd import Multigrid, QmgError
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2), (2, 2, 2, 2)], [8, 12]
+    U, A, fine = problem(dims, 0.3, 2, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 5)]
+    lv = [dict(L, coarse_storage='h16', transfer_storage='h16') for L in level_list(blocks, nvecs, 30, [10, 100])]
+    mg = Multigrid(dims, dev(U), m0, 1.0, lv, st, inner='c64', fine_storage='h16')
+    mg.set_evenodd(True)
+    b = synth.gaussian((fine.V, 4, 3), 1, 2)
+    _, i32 = mg.solve(dev(b), tol=1e-10)
+    mg.set_smoother_vectors('h16')
+    x, i16 = mg.solve(dev(b), tol=1e-10)
+    tr = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+    print('complex64 smoother vectors', i32, '16-bit smoother vectors', i16, 'oracle-M residual %.2e' % tr)
+    assert i16['converged'] and tr <= 1e-10
+    assert i16['outer_iters'] <= i32['outer_iters'] + 2
+    B = np.stack([synth.gaussian((fine.V, 4, 3), 70 + k, 2) for k in range(3)])
+    X, infos = mg.solve_multi(dev(B), tol=1e-10)
+    Xh = host(X)
+    for k in range(3):
+        r = solvers.norm(B[k].reshape(-1) - fine.apply(Xh[k].reshape(-1))) / solvers.norm(B[k].reshape(-1))
+        assert infos[k]['converged'] and r <= 1e-10, (k, r)
+    mg.set_smoother_vectors(None)
+    _, i32b = mg.solve(dev(b), tol=1e-10)
+    assert i32b['outer_iters'] == i32['outer_iters']
+    mgc = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 0, [10, 100]), st, inner='c64')
+    with pytest.raises(QmgError):
+        mgc.set_smoother_vectors('h16')
