@@ -454,8 +454,11 @@ def learned(npairs, epochs, loss, source='smoother'):
     rb_h = timed_batches(mgb, 16, 2, 1000)
     mgb.set_smoother(None)
     rb_mr = timed_batches(mgb, 16, 2, 1000)
+    # the MR smoother of the Schur system on 16-bit vectors (half-precision fine smoother)
+    mgb.set_smoother_vectors('h16')
+    rb_mr16 = timed_batches(mgb, 16, 2, 1000)
     del mgb
-    for c in (combo, combo_mr, combo_h, rb_l, rb_h, rb_mr):
+    for c in (combo, combo_mr, combo_h, rb_l, rb_h, rb_mr, rb_mr16):
         c['speedup_per_rhs_vs_single_fp32_MR'] = round(plain['time_to_1e-10_s'] / c['time_per_rhs_s'], 3)
     return {'lattice': list(dims), 'm0': m0, 'training_data': source, 'pairs': int(R.shape[0]),
             'pair_seconds': round(t_pairs, 2),
@@ -474,7 +477,8 @@ def learned(npairs, epochs, loss, source='smoother'):
                            'mixed_red_black': 'the same with FP16 transfer bases and red-black preconditioning on '
                                               'every level',
                            'mixed_red_black_with_learned': rb_l, 'mixed_red_black_with_learned_then_MR2': rb_h,
-                           'mixed_red_black_with_MR': rb_mr}}
+                           'mixed_red_black_with_MR': rb_mr,
+                           'mixed_red_black_with_MR_fp16_smoother_vectors': rb_mr16}}
 
 
 def fine_and_transfer(steps=200):
