@@ -250,12 +250,11 @@ __global__ void k_mr_update(const double* __restrict__ s3, const cpx<R>* rin, cp
     r[i] = rr;
 }
 
-// MR on 16-bit spinor fields (FP16 pairs [site][12], one FP32 scale per site).
-// Four consecutive lanes share a site; lane j of the four takes components j,
-// j + 4 and j + 8, so each load or store instruction of a wave covers 64
-// consecutive words (16 sites), and the new residual's per-site scale is the
-// maximum over the four lanes (two lane exchanges).  Member b's fields start
-// at b * nsites sites.
+// MR on 16-bit spinor fields (FP16 pairs [site][12], one FP32 scale per site);
+// member b's fields start at b * nsites sites.  The inner products give four
+// consecutive lanes a site, lane j of the four taking components j, j + 4 and
+// j + 8 (measured faster here than consecutive words per lane, which need a
+// scale load per word).
 __global__ __launch_bounds__(1024) void k_dot_norm_h16(const uint32_t* __restrict__ q, const float* __restrict__ qs,
                                                        const uint32_t* __restrict__ r, const float* __restrict__ rs,
                                                        int64_t nsites, double* __restrict__ part,
@@ -292,39 +291,64 @@ __global__ __launch_bounds__(1024) void k_dot_norm_h16(const uint32_t* __restric
     }
 }
 
+// The update: a work-group of 256 lanes takes 64 whole sites (768 words, three
+// per lane at stride 256, so every load and store instruction of a wave covers
+// 64 consecutive words); the new residual's per-site maximum goes through LDS
+// (one lane per site reduces its 12 words).
+constexpr int kMrSites = 64;
 __global__ __launch_bounds__(256) void k_mr_update_h16(const double* __restrict__ s3, const uint32_t* rin,
                                                        const float* rins, uint32_t* r, float* rs,
                                                        const uint32_t* __restrict__ Ar, const float* __restrict__ Ars,
                                                        float2* __restrict__ x, int first, int64_t nsites, int ss) {
+    __shared__ float wmax[kMrSites * 12];
+    __shared__ float smax[kMrSites];
     const int64_t per = gridDim.x >> 3;   // XCD-contiguous ranges, as in k_mr_update
     const int64_t wg = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-    const int64_t i = wg * blockDim.x + threadIdx.x;   // quarter of a site: whole groups of four lanes
-    if (i >= nsites * 4) return;
+    const int64_t s0 = wg * kMrSites;     // first site of the work-group (grid padded to whole groups of 8)
     const int64_t mo = (int64_t)blockIdx.y * nsites;
     s3 += (int64_t)blockIdx.y * ss;
     const double den = s3[0];
     const float ar = den > 0 ? (float)(s3[1] / den) : 0.f, ai = den > 0 ? (float)(s3[2] / den) : 0.f;
-    const int64_t site = mo + (i >> 2), w0 = site * 12 + (i & 3);   // component c at w0 + 4 c
-    const float kr = rins[site], ka = Ars[site];
+    const int64_t nw = (nsites - s0) * 12;   // words of this group's sites left in the member (may be <= 0)
+    const int64_t base = (mo + s0) * 12;
     float2 nr[3];
-    float m = 0.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const cpx<float> u = dec_pair<FMT_H16>(rin[w0 + 4 * c]), v = dec_pair<FMT_H16>(Ar[w0 + 4 * c]);
-        const float ur = kr * u.re, ui = kr * u.im, vr = ka * v.re, vi = ka * v.im;
-        float2 xx = first ? make_float2(0.f, 0.f) : x[w0 + 4 * c];
-        xx.x += ar * ur - ai * ui;
-        xx.y += ar * ui + ai * ur;
-        x[w0 + 4 * c] = xx;
-        nr[c] = make_float2(ur - (ar * vr - ai * vi), ui - (ar * vi + ai * vr));
-        m = fmaxf(m, fmaxf(fabsf(nr[c].x), fabsf(nr[c].y)));
+        const int lw = c * 256 + threadIdx.x;   // word within the group
+        float m = 0.f;
+        nr[c] = make_float2(0.f, 0.f);
+        if (lw < nw) {
+            const int64_t site = mo + s0 + lw / 12, w = base + lw;
+            const float kr = rins[site], ka = Ars[site];
+            const cpx<float> u = dec_pair<FMT_H16>(rin[w]), v = dec_pair<FMT_H16>(Ar[w]);
+            const float ur = kr * u.re, ui = kr * u.im, vr = ka * v.re, vi = ka * v.im;
+            float2 xx = first ? make_float2(0.f, 0.f) : x[w];
+            xx.x += ar * ur - ai * ui;
+            xx.y += ar * ui + ai * ur;
+            x[w] = xx;
+            nr[c] = make_float2(ur - (ar * vr - ai * vi), ui - (ar * vi + ai * vr));
+            m = fmaxf(fabsf(nr[c].x), fabsf(nr[c].y));
+        }
+        wmax[lw] = m;
     }
-    m = fmaxf(m, __shfl_xor(m, 1, 64));
-    m = fmaxf(m, __shfl_xor(m, 2, 64));
-    const float inv = m > 0.f ? 1.0f / m : 0.f;
+    __syncthreads();
+    if (threadIdx.x < kMrSites) {
+        float m = 0.f;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) r[w0 + 4 * c] = enc_pair<FMT_H16>(nr[c].x * inv, nr[c].y * inv);
-    if ((i & 3) == 0) rs[site] = m;
+        for (int k = 0; k < 12; ++k) m = fmaxf(m, wmax[threadIdx.x * 12 + k]);
+        smax[threadIdx.x] = m;
+        if (s0 + threadIdx.x < nsites) rs[mo + s0 + threadIdx.x] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const int lw = c * 256 + threadIdx.x;
+        if (lw < nw) {
+            const float m = smax[lw / 12];
+            const float inv = m > 0.f ? 1.0f / m : 0.f;
+            r[base + lw] = enc_pair<FMT_H16>(nr[c].x * inv, nr[c].y * inv);
+        }
+    }
 }
 
 // complex64 spinors [site][12] -> FP16 pairs with one scale per site, four lanes per
@@ -943,7 +967,7 @@ qmg_status Blas::mr_update(const double* s3, const void* rin, void* r, const voi
 }
 qmg_status Blas::dot_norm_h16(const void* q, const float* qs, const void* r, const float* rs, int64_t nsites,
                               double* out) {
-    const int nblk = nblocks(nsites * 4);
+    const int nblk = nblocks(nsites * 4);   // four lanes per site
     hipLaunchKernelGGL(k_dot_norm_h16, dim3(nblk, nb), dim3(rthreads(nblk)), 0, s, (const uint32_t*)q, qs,
                        (const uint32_t*)r, rs, nsites, partials, out, ss);
     finish(s, partials, nblk, 3, out, nb, ss);
@@ -952,7 +976,9 @@ qmg_status Blas::dot_norm_h16(const void* q, const float* qs, const void* r, con
 }
 qmg_status Blas::mr_update_h16(const double* s3, const void* rin, const float* rins, void* r, float* rs, const void* Ar,
                                const float* Ars, void* x, int first, int64_t nsites) {
-    hipLaunchKernelGGL(k_mr_update_h16, dim3((grid1(nsites * 4) + 7) / 8 * 8, nb), dim3(kThreads), 0, s, s3,
+    static_assert(kThreads == 256, "k_mr_update_h16 takes 64 sites per 256-lane work-group");
+    const int64_t groups = (nsites + kMrSites - 1) / kMrSites;
+    hipLaunchKernelGGL(k_mr_update_h16, dim3((unsigned)((groups + 7) / 8 * 8), nb), dim3(kThreads), 0, s, s3,
                        (const uint32_t*)rin, rins, (uint32_t*)r, rs, (const uint32_t*)Ar, Ars, (float2*)x, first, nsites,
                        ss);
     QMG_LAUNCH_CHECK();

@@ -371,3 +371,29 @@ def test_fp16_smoother_vectors_red_black():
     mgc = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 0, [10, 100]), st, inner='c64')
     with pytest.raises(QmgError):
         mgc.set_smoother_vectors('h16')
+
+
+@pytest.mark.parametrize('nb', [1, 3])
+def test_fp16_smoother_vectors_ragged_half_lattice(nb):
+    """16-bit smoother vectors on 6x6x4x4 (288 half-lattice sites: four whole
+    work-groups of the MR update and a partial fifth) with odd aggregates
+    (3x3x2x2): the solve reaches 1e-10 under the oracle's M for every member,
+    in about the step count of complex64 smoother vectors."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (6, 6, 4, 4), -0.3
+    blocks, nvecs = [(3, 3, 2, 2)], [6]
+    U, A, fine = problem(dims, 0.3, 4, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 9)]
+    lv = [dict(L, coarse_storage='h16') for L in level_list(blocks, nvecs, 10, [100])]
+    mg = Multigrid(dims, dev(U), m0, 1.0, lv, st, inner='c64', fine_storage='h16')
+    mg.set_evenodd(True)
+    B = np.stack([synth.gaussian((fine.V, 4, 3), 90 + k, 2) for k in range(nb)])
+    _, i32 = mg.solve_multi(dev(B), tol=1e-10)
+    mg.set_smoother_vectors('h16')
+    X, i16 = mg.solve_multi(dev(B), tol=1e-10)
+    Xh = host(X)
+    for k in range(nb):
+        r = solvers.norm(B[k].reshape(-1) - fine.apply(Xh[k].reshape(-1))) / solvers.norm(B[k].reshape(-1))
+        print(k, i32[k]['outer_iters'], i16[k]['outer_iters'], '%.2e' % r)
+        assert i16[k]['converged'] and r <= 1e-10, (k, r)
+        assert i16[k]['outer_iters'] <= i32[k]['outer_iters'] + 2
