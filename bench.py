@@ -564,16 +564,18 @@ def plain_gcr(maxit=40000):
 def bicgstab(U, m0, nsolves=3, dims=(16, 16, 16, 32)):
     """The paper's comparison solver on the same system: BiCGStab with FP64
     reliable updates (delta 0.1) on the red-black (Schur) system, iterating
-    with 16-bit links and clover (the paper's half precision) and with FP32
-    storage; the first solve discarded."""
+    with 16-bit links and clover (the paper's half precision), the same with
+    12-real gauge compression, and with FP32 storage; the first solve
+    discarded."""
     import numpy as np
     import torch
     import synth
     from paper_1612_07873_amd import BiCGStab, FineOp
     hi = FineOp(dims, U, m0, 1.0, True, 'c128')
     out = {}
-    for name, lo_storage in (('fp16_red_black', 'h16'), ('fp32_red_black', 'c64')):
-        lo = FineOp(dims, U, m0, 1.0, True, lo_storage)
+    for name, lo_storage, reals in (('fp16_red_black', 'h16', 18), ('fp16_12real_red_black', 'h16', 12),
+                                    ('fp32_red_black', 'c64', 18)):
+        lo = FineOp(dims, U, m0, 1.0, True, lo_storage, link_reals=reals)
         solver = BiCGStab(hi, lo, evenodd=True)
         times, iters, upd, res = [], [], [], []
         for i in range(nsolves):

@@ -45,8 +45,10 @@ def test_fp64_bicgstab_step_count_matches_oracle(evenodd_form):
     assert abs(info['iters'] - io.iters) <= max(2, io.iters // 10)
 
 
-@pytest.mark.parametrize('lo', ['c64', 'h16'])
-def test_mixed_precision_reliable_updates_reach_1e10(lo):
+@pytest.mark.parametrize('lo,link_reals', [('c64', 18), ('h16', 18), ('h16', 12)])
+def test_mixed_precision_reliable_updates_reach_1e10(lo, link_reals):
+    """Low-precision iteration (FP32, or the paper's half precision, with or
+    without 12-real gauge compression) with FP64 reliable updates."""
     from paper_1612_07873_amd import BiCGStab, FineOp
     dims, m0 = (8, 8, 8, 8), -0.2
     U = synth.gauge_field(dims, 0.3, 1)
@@ -54,13 +56,13 @@ def test_mixed_precision_reliable_updates_reach_1e10(lo):
     V = lattice.volume(dims)
     b = synth.gaussian((V, 4, 3), 3, 2)
     hi = FineOp(dims, dev(U), m0, 1.0, True, 'c128')
-    low = FineOp(dims, dev(U), m0, 1.0, True, lo)
+    low = FineOp(dims, dev(U), m0, 1.0, True, lo, link_reals=link_reals)
     steps = {}
     for eo in (False, True):
         solver = BiCGStab(hi, low, evenodd=eo)
         x, info = solver.solve(dev(b), tol=1e-10, delta=0.1)
         tr = oracle_residual(U, A, m0, dims, b, host(x))
-        print(lo, 'red-black' if eo else 'whole', info, 'oracle-M %.2e' % tr)
+        print(lo, link_reals, 'red-black' if eo else 'whole', info, 'oracle-M %.2e' % tr)
         assert info['converged'] and tr <= 1e-10
         assert info['reliable_updates'] >= 2      # the low-precision recursion alone stalls near its rounding
         steps[eo] = info['iters']
