@@ -207,23 +207,30 @@ __global__ void k_multi_axpy(const double* __restrict__ beta, const cpx<R>* __re
 template <typename R>
 __global__ void k_gcr_update(const double* __restrict__ s3, cpx<R>* __restrict__ q, cpx<R>* __restrict__ z,
                              cpx<R>* __restrict__ x, cpx<R>* __restrict__ r, int64_t n, int ss) {
-    QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x); QMG_MEMBER_VEC(r);
+    // z and x null: the deferred form (q normalised, r updated; the caller
+    // forms x from the unnormalised directions at the end of the cycle)
+    QMG_MEMBER_SCAL(s3); QMG_MEMBER_VEC(q); QMG_MEMBER_VEC(r);
+    if (z) { QMG_MEMBER_VEC(z); QMG_MEMBER_VEC(x); }
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !(s3[0] > 0)) return;  // q = 0: no update (breakdown is reported by the caller)
     const double nq = sqrt(s3[0]);
     const R inv = (R)(1.0 / nq);
     const R ar = (R)(s3[1] / nq), ai = (R)(s3[2] / nq);
-    cpx<R> qq = q[i], zz = z[i];
+    cpx<R> qq = q[i];
     qq.re *= inv; qq.im *= inv;
-    zz.re *= inv; zz.im *= inv;
     q[i] = qq;
-    z[i] = zz;
-    cpx<R> xx = x[i], rr = r[i];
-    xx.re += ar * zz.re - ai * zz.im;
-    xx.im += ar * zz.im + ai * zz.re;
+    if (z) {
+        cpx<R> zz = z[i];
+        zz.re *= inv; zz.im *= inv;
+        z[i] = zz;
+        cpx<R> xx = x[i];
+        xx.re += ar * zz.re - ai * zz.im;
+        xx.im += ar * zz.im + ai * zz.re;
+        x[i] = xx;
+    }
+    cpx<R> rr = r[i];
     rr.re -= ar * qq.re - ai * qq.im;
     rr.im -= ar * qq.im + ai * qq.re;
-    x[i] = xx;
     r[i] = rr;
 }
 

@@ -30,6 +30,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <vector>
 
 struct qmg_mg_s;
@@ -794,8 +795,30 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
         QMG_HIP(hipMemsetAsync(xs, 0, bbs, mg->s));
     }
     QMG_HIP(hipMemcpyAsync(mg->r64, bs, bbs, hipMemcpyDeviceToDevice, mg->s));
+    // Deferred solution update (unless iterates are recorded every step): the
+    // preconditioned directions w_j stay as the K-cycle returned them and only
+    // q_j is orthogonalised and normalised; with Z_j = (w_j - sum_i beta_ij Z_i)
+    // / nu_j the cycle's correction sum_j alpha_j Z_j = sum_j gamma_j w_j, gamma
+    // by back substitution, is added to x once at the end of the cycle.  The
+    // residual recursion is the same as in the eager form.
+    const bool deferred = !mg->rec && m <= 16;
+    std::vector<std::complex<double>> cbeta, calpha;
+    std::vector<double> cnu;
+    if (deferred) {
+        cbeta.assign((size_t)nb * m * m, 0.0);
+        calpha.assign((size_t)nb * m, 0.0);
+        cnu.assign((size_t)nb * m, 0.0);
+    }
+    auto add_beta = [&](int j) {   // the projection coefficients of q_j now in the mirror's S_BETA slots
+        for (int b = 0; b < nb; ++b)
+            for (int i = 0; i < j; ++i)
+                cbeta[((size_t)b * m + i) * m + j] += std::complex<double>(hs(mg, b, S_BETA + 2 * i),
+                                                                           hs(mg, b, S_BETA + 2 * i + 1));
+    };
     int iters = 0, restarts = 0;
     while (!all_conv && iters < sp->maxit) {
+        int kc = 0;   // steps of this cycle
+        if (deferred) std::fill(cbeta.begin(), cbeta.end(), 0.0);
         for (int j = 0; j < m && iters < sp->maxit; ++j) {
             void* z = (char*)mg->Z64 + j * bbs;
             void* q = (char*)mg->Q64 + j * bbs;
@@ -821,19 +844,38 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
                 // Stewart test; the preconditioned directions are nearly
                 // orthogonal already, so the second pass is rarely needed)
                 QMG_TRY(mg->blas.norm2<double>(q, ns, mg->dsc + S_QQ));
-                QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, ns, 1));
+                const void* Zs = deferred ? nullptr : mg->Z64;
+                void* zs = deferred ? nullptr : z;
+                QMG_TRY(orthogonalize<double>(mg, mg->Q64, Zs, ld, j, q, zs, ns, 1));
                 QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, ns, mg->dsc + S_GCR));
-                QMG_TRY(read_scalars(mg, S_GCR, S_QQ + 1 - S_GCR));
+                const int first = deferred ? S_BETA : S_GCR;
+                QMG_TRY(read_scalars(mg, first, S_QQ + 1 - first));
+                if (deferred) add_beta(j);
                 bool again = false;
                 for (int b = 0; b < nb; ++b) again = again || !(hs(mg, b, S_GCR) >= 0.5 * hs(mg, b, S_QQ));
                 if (again) {
-                    QMG_TRY(orthogonalize<double>(mg, mg->Q64, mg->Z64, ld, j, q, z, ns, 1));
+                    QMG_TRY(orthogonalize<double>(mg, mg->Q64, Zs, ld, j, q, zs, ns, 1));
                     QMG_TRY(mg->blas.dot_norm<double>(q, mg->r64, ns, mg->dsc + S_GCR));
+                    if (deferred) {   // the second pass's coefficients add to the first's
+                        QMG_TRY(read_scalars(mg, S_BETA, 2 * j));
+                        add_beta(j);
+                    }
                 }
             }
-            QMG_TRY(mg->blas.gcr_update<double>(mg->dsc + S_GCR, q, z, xs, mg->r64, ns));
+            QMG_TRY(mg->blas.gcr_update<double>(mg->dsc + S_GCR, q, deferred ? nullptr : z, deferred ? nullptr : xs,
+                                                mg->r64, ns));
             QMG_TRY(mg->blas.norm2<double>(mg->r64, ns, mg->dsc + S_NRM));
             QMG_TRY(read_scalars(mg, S_GCR, 5));
+            if (deferred) {
+                for (int b = 0; b < nb; ++b) {
+                    const double qq = hs(mg, b, S_GCR);
+                    const double nu = qq > 0 ? std::sqrt(qq) : 0.0;
+                    cnu[(size_t)b * m + j] = nu;
+                    calpha[(size_t)b * m + j] =
+                        nu > 0 ? std::complex<double>(hs(mg, b, S_GCR + 1), hs(mg, b, S_GCR + 2)) / nu : 0.0;
+                }
+            }
+            ++kc;
             ++iters;
             if (mg->rec && mg->rec_n < mg->rec_max) {
                 QMG_HIP(hipMemcpyAsync((char*)mg->rec + (size_t)mg->rec_n * vb64, x, vb64, hipMemcpyDeviceToDevice, mg->s));
@@ -846,6 +888,29 @@ qmg_status solve_impl(qmg_mg_s* mg, const void* b, void* x, const qmg_solve_para
                 stop = stop && (rn <= sp->tol * bnorm[k] || hs(mg, k, S_GCR) <= 0.0);
             }
             if (stop) break;
+        }
+        if (deferred && kc > 0) {
+            // x += sum_j gamma_j w_j: back substitution through Z_j = (w_j - sum_i beta_ij Z_i) / nu_j
+            // (a broken-down step, nu_j = 0, contributes nothing and projected nothing away)
+            for (int b = 0; b < nb; ++b) {
+                std::complex<double> c[16];
+                for (int j = 0; j < kc; ++j) c[j] = calpha[(size_t)b * m + j];
+                for (int j = kc - 1; j >= 0; --j) {
+                    const double nu = cnu[(size_t)b * m + j];
+                    const std::complex<double> g = nu > 0 ? c[j] / nu : 0.0;
+                    for (int i = 0; i < j; ++i) c[i] -= cbeta[((size_t)b * m + i) * m + j] * g;
+                    hs(mg, b, S_BETA + 2 * j) = -g.real();   // multi_axpy subtracts
+                    hs(mg, b, S_BETA + 2 * j + 1) = -g.imag();
+                }
+            }
+            if (nb == 1)
+                QMG_HIP(hipMemcpyAsync(mg->dsc + S_BETA, mg->hsc + S_BETA, sizeof(double) * 2 * kc,
+                                       hipMemcpyHostToDevice, mg->s));
+            else
+                QMG_HIP(hipMemcpy2DAsync(mg->dsc + S_BETA, sizeof(double) * kScal, mg->hsc + S_BETA,
+                                         sizeof(double) * kScal, sizeof(double) * 2 * kc, nb, hipMemcpyHostToDevice,
+                                         mg->s));
+            QMG_TRY(mg->blas.multi_axpy<double>(mg->dsc + S_BETA, mg->Z64, nullptr, ld, kc, xs, nullptr, ns));
         }
         // reliable update: true residual in FP64 (of the whole system, after
         // the odd sites are back-substituted in the red-black form)
