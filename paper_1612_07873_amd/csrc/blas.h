@@ -52,10 +52,14 @@ struct Blas {
                             double* out);
     qmg_status mr_update_h16(const double* s3, const void* rin, const float* rins, void* r, float* rs, const void* Ar,
                              const float* Ars, void* x, int first, int64_t nsites);
-    // complex64 spinors [nsites][12] <-> FP16 pairs with one scale per site (all
+    // complex64 spinors [nsites][12] -> FP16 pairs with one scale per site (all
     // members' sites at once; a NaN or Inf input is recorded for qmg_sync)
     qmg_status quantize_spinors(const void* in, void* out, float* scale, int64_t nsites);
-    qmg_status dequantize_spinors(const void* in, const float* scale, void* out, int64_t nsites);
+    // 16-bit half-lattice spinors of every member (nsites each) decoded into
+    // whole-lattice complex64 fields [member][2 nsites][12]: site hp[h] takes
+    // half-site h, site hq[h] is set to zero
+    qmg_status scatter_dequantize(const void* in, const float* scale, const int* hp, const int* hq, void* full,
+                                  int64_t nsites);
     // minimal-residual step along d with Ad = A d, s3 = dot_norm(Ad, r): alpha = <Ad,r>/<Ad,Ad>;
     // x = alpha d; rout = r - alpha Ad
     template <typename R> qmg_status dir_step(const double* s3, const void* d, const void* Ad, const void* r, void* x,

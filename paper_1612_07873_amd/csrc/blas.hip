@@ -384,18 +384,24 @@ __global__ __launch_bounds__(256) void k_quantize_spinor(const float2* __restric
     if ((i & 3) == 0) scale[i >> 2] = m;
 }
 
-// FP16 pairs with per-site scales -> complex64 spinors
-__global__ __launch_bounds__(256) void k_dequantize_spinor(const uint32_t* __restrict__ in,
-                                                           const float* __restrict__ scale, float2* __restrict__ out,
-                                                           int64_t nsites) {
+// FP16 pairs with per-site scales on the half lattice -> complex64 whole-lattice
+// fields: full[b][hp[h]] = decoded half[b][h], full[b][hq[h]] = 0 (the
+// other parity); four lanes per site in the interleaved order above
+__global__ __launch_bounds__(256) void k_scatter_dequantize(const uint32_t* __restrict__ in,
+                                                            const float* __restrict__ scale,
+                                                            const int* __restrict__ hp, const int* __restrict__ hq,
+                                                            float2* __restrict__ full, int64_t nsites) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nsites * 4) return;
-    const float k = scale[i >> 2];
-    const int64_t w0 = (i >> 2) * 12 + (i & 3);
+    const int64_t b = blockIdx.y, h = i >> 2, hb = b * nsites + h;
+    const float k = scale[hb];
+    const int64_t wi = hb * 12 + (i & 3);
+    const int64_t wp = (b * 2 * nsites + hp[h]) * 12 + (i & 3), wq = (b * 2 * nsites + hq[h]) * 12 + (i & 3);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const cpx<float> v = dec_pair<FMT_H16>(in[w0 + 4 * c]);
-        out[w0 + 4 * c] = make_float2(k * v.re, k * v.im);
+        const cpx<float> v = dec_pair<FMT_H16>(in[wi + 4 * c]);
+        full[wp + 4 * c] = make_float2(k * v.re, k * v.im);
+        full[wq + 4 * c] = make_float2(0.f, 0.f);
     }
 }
 
@@ -1000,9 +1006,10 @@ qmg_status Blas::quantize_spinors(const void* in, void* out, float* scale, int64
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }
-qmg_status Blas::dequantize_spinors(const void* in, const float* scale, void* out, int64_t nsites) {
-    hipLaunchKernelGGL(k_dequantize_spinor, dim3(grid1(nsites * 4)), dim3(kThreads), 0, s, (const uint32_t*)in, scale,
-                       (float2*)out, nsites);
+qmg_status Blas::scatter_dequantize(const void* in, const float* scale, const int* hp, const int* hq, void* full,
+                                    int64_t nsites) {
+    hipLaunchKernelGGL(k_scatter_dequantize, dim3(grid1(nsites * 4), nb), dim3(kThreads), 0, s, (const uint32_t*)in,
+                       scale, hp, hq, (float2*)full, nsites);
     QMG_LAUNCH_CHECK();
     return QMG_OK;
 }

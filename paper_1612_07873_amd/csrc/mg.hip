@@ -382,10 +382,10 @@ qmg_status mr_schur16(qmg_mg_s* mg, const void* r, void* x) {
         QMG_HIP(hipMemcpyAsync(L.hr, L.hb, nb * Vh * 48, hipMemcpyDeviceToDevice, s));
         QMG_HIP(hipMemcpyAsync(L.hrs, L.hbs, nb * Vh * sizeof(float), hipMemcpyDeviceToDevice, s));
     }
-    QMG_TRY(mg->blas.dequantize_spinors(L.hr, L.hrs, L.sr, Vh * nb));
     QMG_TRY(schur_reconstruct<float>(mg, 0, L.sx, r, x));
+    // the whole residual: the even sites' 16-bit residual decoded, zero on the odd sites
     const int* hs = level_hsite(mg, 0);
-    return eo_scatter(hs, hs + Vh, Vh, L.dof, L.sr, L.mr_r, QMG_C64, nb, s);
+    return mg->blas.scatter_dequantize(L.hr, L.hrs, hs, hs + Vh, L.mr_r, Vh);
 }
 
 template <typename R> qmg_status mr_schur(qmg_mg_s* mg, int l, const void* r, void* x) {
