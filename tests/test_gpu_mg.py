@@ -397,3 +397,29 @@ def test_fp16_smoother_vectors_ragged_half_lattice(nb):
         print(k, i32[k]['outer_iters'], i16[k]['outer_iters'], '%.2e' % r)
         assert i16[k]['converged'] and r <= 1e-10, (k, r)
         assert i16[k]['outer_iters'] <= i32[k]['outer_iters'] + 2
+
+
+def test_outer_deferred_update_matches_eager():
+    """The outer FGCR forms x once per cycle from the unprojected directions
+    (deferred update); the recording solve, which needs x after every step,
+    updates it eagerly.  Both run the same residual recursion, so after one
+    cycle of ten steps their iterates agree to FP64 rounding, and the full
+    solves take the same steps and meet 1e-10 under the oracle's M."""
+    from paper_1612_07873_amd import Multigrid
+    dims, m0 = (8, 8, 8, 8), -0.3
+    blocks, nvecs = [(2, 2, 2, 2)], [8]
+    U, A, fine = problem(dims, 0.3, 3, m0)
+    st = [dev(s) for s in starts_for(dims, blocks, nvecs, 11)]
+    mg = Multigrid(dims, dev(U), m0, 1.0, level_list(blocks, nvecs, 20, [50]), st, inner='c64')
+    b = synth.gaussian((fine.V, 4, 3), 12, 2)
+    xr, hist, ir = mg.solve_record(dev(b), 64)
+    x1, i1 = mg.solve(dev(b), tol=1e-10, maxit=10, check=False)
+    assert ir['outer_iters'] > 10 and not i1['converged']
+    err = rel_err(host(x1), host(hist[9]))
+    xd, idf = mg.solve(dev(b), tol=1e-10)
+    print('after one cycle: deferred vs eager %.2e;' % err, 'steps', idf['outer_iters'], ir['outer_iters'])
+    assert err <= 1e-11
+    assert idf['outer_iters'] == ir['outer_iters']
+    for x in (xr, xd):
+        r = solvers.norm(b.reshape(-1) - fine.apply(host(x).reshape(-1))) / solvers.norm(b.reshape(-1))
+        assert r <= 1e-10
