@@ -468,7 +468,7 @@ def learned(npairs, epochs, loss, source='smoother'):
             'speedup_time': round(plain['time_to_1e-10_s'] / withnet['time_to_1e-10_s'], 3),
             'speedup_time_learned_then_MR2': round(plain['time_to_1e-10_s'] / hybrid['time_to_1e-10_s'], 3),
             'speedup_time_learned_then_MR1': round(plain['time_to_1e-10_s'] / hybrid1['time_to_1e-10_s'], 3),
-            'north_star': {'plain': 'FP32 inner, FP64 outer, single right-hand side, MR(4) smoother',
+            'mixed_vs_plain': {'plain': 'FP32 inner, FP64 outer, single right-hand side, MR(4) smoother',
                            'mixed': 'FP16 fine and coarse storage (FP32 scales, FP32 arithmetic), 16 right-hand '
                                     'sides per solve, matrix-core coarse stencils, learned level-0 smoother',
                            'plain_time_to_1e-10_s': plain['time_to_1e-10_s'],
